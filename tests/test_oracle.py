@@ -1,0 +1,311 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test names the passage it checks.  None of them re-types the oracle's own
+formulas: they compare with closed forms, exact integrals, manufactured
+solutions (Sec. 4.1), exact discrete invariants (Sec. 2.2 reduction consistency,
+mass conservation of the Cahn-Hilliard split) and special cases (3D with
+z-independent data equals 2D)."""
+import math
+import os
+
+import numpy as np
+import pytest
+import sympy as s
+
+from oracle.sem import gll, diff_matrix, Mesh2D, BOTTOM, TOP, LEFT, RIGHT
+from oracle.scheme import Scheme, Params, BCs, WALL, OPEN
+from cases import mms_setup, mms_run_oracle, mms_errors, mms_params
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- GLL tables
+def test_gll_closed_forms():
+    """GLL points/weights against the closed forms of A&S 25.4.32 (golden file)."""
+    rows = {}
+    for line in open(os.path.join(GOLD, "gll_lobatto.txt")):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        K, xn, wn = line.split()
+        ev = lambda e: float(eval(e, {"sqrt": math.sqrt}))
+        rows.setdefault(int(K), []).append((ev(xn), ev(wn)))
+    for K, vals in rows.items():
+        x, w = gll(K)
+        xe = np.array([v[0] for v in vals])
+        we = np.array([v[1] for v in vals])
+        np.testing.assert_allclose(x, xe, atol=1e-15)
+        np.testing.assert_allclose(w, we, rtol=1e-14)
+
+
+@pytest.mark.parametrize("K", [2, 5, 8, 12, 16])
+def test_gll_quadrature_degree(K):
+    """GLL with K+1 points integrates polynomials of degree <= 2K-1 exactly."""
+    x, w = gll(K)
+    for p in range(2 * K):
+        exact = 0.0 if p % 2 else 2.0 / (p + 1)
+        assert abs(np.dot(w, x ** p) - exact) < 1e-13
+    # and fails at degree 2K (it is a Lobatto rule, not Gauss)
+    assert abs(np.dot(w, x ** (2 * K)) - 2.0 / (2 * K + 1)) > 1e-10
+
+
+@pytest.mark.parametrize("K", [1, 3, 6, 10, 14])
+def test_diff_matrix_exact(K):
+    """D maps nodal values of x^p (p <= K) to p x^(p-1) exactly."""
+    x, _ = gll(K)
+    D = diff_matrix(K)
+    for p in range(K + 1):
+        d = p * x ** (p - 1) if p > 0 else np.zeros_like(x)
+        np.testing.assert_allclose(D @ x ** p, d, atol=1e-11 * max(1, K * K))
+
+
+def _poly_mesh():
+    return Mesh2D([0.0, 0.3, 1.1], [-0.5, 0.2, 0.4, 1.0], 4, periodic_x=False)
+
+
+def test_mass_stiffness_exact_integrals():
+    """q^T M p = int q p and q^T K p = int grad q . grad p for polynomials whose
+    per-variable degree stays within the GLL rule's exactness (Sec. 3.2.1 spaces)."""
+    m = _poly_mesh()
+    X, Y = s.symbols("x y")
+    polys = [X ** 2 * Y, X * Y ** 3 + 1, (X - 0.2) ** 3 - Y ** 2, X ** 4 * Y]
+    xs, ys = m.X.ravel(), m.Y.ravel()
+    nod = [s.lambdify((X, Y), p, "numpy")(xs, ys) * np.ones_like(xs) for p in polys]
+    for i, p in enumerate(polys):
+        for j, q in enumerate(polys):
+            mass = float(s.integrate(s.integrate(p * q, (X, 0, 1.1)), (Y, -0.5, 1.0)))
+            stiff = float(s.integrate(s.integrate(
+                s.diff(p, X) * s.diff(q, X) + s.diff(p, Y) * s.diff(q, Y), (X, 0, 1.1)),
+                (Y, -0.5, 1.0)))
+            degx = s.degree(p, X) + s.degree(q, X)
+            degy = s.degree(p, Y) + s.degree(q, Y)
+            if degx <= 7 and degy <= 7:
+                assert abs(nod[i] @ (m.M @ nod[j]) - mass) < 1e-12 * max(1, abs(mass))
+            if degx <= 7 and degy <= 7:
+                assert abs(nod[i] @ (m.Kst @ nod[j]) - stiff) < 1e-11 * max(1, abs(stiff))
+
+
+def test_periodic_mesh_identifies_ends():
+    m = Mesh2D([0.0, 1.0, 2.0], [0.0, 1.0], 3, periodic_x=True)
+    assert m.Nx == 6 and m.Ny == 4
+    # the stiffness of a constant vanishes (no boundary in x, Neumann in y)
+    np.testing.assert_allclose(m.Kst @ np.ones(m.Ng), 0.0, atol=1e-13)
+    assert abs(m.Mdiag.sum() - 2.0) < 1e-14
+
+
+# ------------------------------------------------------ manufactured solutions
+def test_mms_2d_spatial_exponential():
+    """Sec. 4.1, eq. (80): errors fall exponentially with the element order
+    (dt = 1e-3, t_f = 0.2)."""
+    dt, n = 1e-3, 200
+    prev = None
+    for K in (4, 6, 8, 10):
+        case = mms_setup("eq80", K, dt)
+        e = mms_errors(case, mms_run_oracle(case, n, dt), n * dt)
+        if prev is not None:
+            for k in e:
+                assert e[k] < prev[k] / 5.0, (K, k, e[k], prev[k])
+        prev = e
+    assert max(prev.values()) < 2e-4
+
+
+def test_mms_2d_temporal_second_order():
+    """Sec. 4.1, eq. (80): second-order convergence in dt at a high element order.
+    S is held fixed (at the lower bound of the smallest dt) so that the
+    stabilisation term is O(dt^2) for every dt."""
+    K, tf = 14, 0.2
+    dts = (0.01, 0.005, 0.0025)
+    Sfix = 0.1 ** 2 * math.sqrt(4 * 1.5 / (0.01 * 0.01 * dts[-1]))
+    errs = []
+    for dt in dts:
+        case = mms_setup("eq80", K, dt, S=Sfix)
+        n = int(round(tf / dt))
+        errs.append(mms_errors(case, mms_run_oracle(case, n, dt), n * dt))
+    for k in errs[0]:
+        r = errs[-2][k] / errs[-1][k]
+        assert 3.0 < r < 5.0, (k, r)
+
+
+def test_mms_box_spatial():
+    """Closed box with walls on every side (the C1/C2 boundary family): the
+    manufactured errors fall with the element order."""
+    dt, n = 5e-4, 100
+    prev = None
+    for K in (4, 6, 8):
+        case = mms_setup("box", K, dt)
+        e = mms_errors(case, mms_run_oracle(case, n, dt), n * dt)
+        if prev is not None:
+            for k in e:
+                assert e[k] < prev[k] / 4.0, (K, k, e[k], prev[k])
+        prev = e
+    assert max(prev.values()) < 1e-3
+
+
+def test_mms_3d_spatial():
+    """Sec. 4.1, eq. (81): 3D hybrid Fourier/SEM errors fall with the element
+    order (Nz = 8, dt = 1e-3)."""
+    dt, n = 1e-3, 50
+    prev = None
+    for K in (6, 8, 10):
+        case = mms_setup("eq81", K, dt, Nz=8)
+        e = mms_errors(case, mms_run_oracle(case, n, dt), n * dt)
+        if prev is not None:
+            for k in e:
+                assert e[k] < prev[k] / 2.5, (K, k, e[k], prev[k])
+        prev = e
+    assert max(prev.values()) < 1e-2
+
+
+# --------------------------------------------------------------- invariants
+def _box(K=5, n=3, periodic=False):
+    xb = np.linspace(0, 1, n + 1)
+    m = Mesh2D(xb, xb, K, periodic_x=periodic)
+    side = {BOTTOM: WALL, TOP: WALL} if periodic else {BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}
+    return m, BCs(side=side, pot_sides=(BOTTOM, TOP))
+
+
+def _drop_params(dt=1e-4):
+    return Params(rho1=1.0, rho2=2.0, mu1=0.01, mu2=0.02, eps1=2.0, eps2=8.0,
+                  lam=3 * 0.05 / (2 * math.sqrt(2)), eta=0.05, gamma1=1e-2,
+                  theta_s_deg=70.0, dt=dt)
+
+
+def _vd_top(m, v=1.0):
+    return np.where(np.isclose(m.Y.ravel(), 1.0), v, 0.0)
+
+
+@pytest.mark.parametrize("phival", [1.0, -1.0])
+def test_reduction_consistency(phival):
+    """Sec. 2.2 (eq. a12): phi = +-1 is an exact solution; the discrete CH split
+    keeps phi = +-1 and psi = alpha (grad^2 phi + alpha phi = psi) to roundoff,
+    with a non-trivial velocity field and imposed voltage present."""
+    m, bc = _box()
+    par = _drop_params()
+    sch = Scheme(m, par, bc)
+    X, Y = m.X.ravel(), m.Y.ravel()
+    u0 = (np.sin(np.pi * X) * np.sin(2 * np.pi * Y), -np.sin(2 * np.pi * X) * np.sin(np.pi * Y))
+    sch.set_state(np.full(m.Ng, phival), u0)
+    src = dict(Vd=_vd_top(m))
+    sch.init_potential(src)
+    for _ in range(4):
+        out = sch.step(src)
+        np.testing.assert_allclose(out["phi"], phival, atol=1e-11)
+        np.testing.assert_allclose(out["psi"], phival * sch.c["alpha"],
+                                   atol=1e-11 * abs(sch.c["alpha"]))
+
+
+def test_potential_linear_closed_form():
+    """With phi = -1 (constant permittivity) and V = 0 / 1 on the bottom / top
+    electrodes, Neumann on the sides: V = y and E = (0, 1) exactly (eqs. 54, 55)."""
+    m, bc = _box(K=4, n=2)
+    par = _drop_params()
+    sch = Scheme(m, par, bc)
+    sch.set_state(np.full(m.Ng, -1.0))
+    src = dict(Vd=_vd_top(m))
+    sch.init_potential(src)
+    out = sch.step(src)
+    np.testing.assert_allclose(out["V"][0], m.Y.ravel(), atol=1e-13)
+    np.testing.assert_allclose(out["Ex"][0], 0.0, atol=1e-12)
+    np.testing.assert_allclose(out["Ey"][0], 1.0, atol=1e-12)
+
+
+def _drop(m, r=0.25, c=(0.5, 0.5), eta=0.05):
+    d = np.sqrt((m.X.ravel() - c[0]) ** 2 + (m.Y.ravel() - c[1]) ** 2) - r
+    return np.tanh(d / (math.sqrt(2) * eta))
+
+
+def test_mass_conservation_equilibrium_system():
+    """Testing eqs. (56)/(57) with w = 1 and c_phi c_psi = gamma0/(lambda gamma1 dt):
+    with u = 0 and no sources, int_h phi is conserved exactly (equilibrium system,
+    eqs. 15c-d, 16), also with a wall contact angle and an imposed voltage."""
+    m, bc = _box(K=6, n=3)
+    par = _drop_params(dt=1e-5)
+    sch = Scheme(m, par, bc)
+    sch.set_state(_drop(m, c=(0.4, 0.0)))
+    src = dict(Vd=_vd_top(m, 2.0))
+    sch.init_potential(src)
+    m0 = sch.mass()
+    for _ in range(5):
+        sch.step(src, equilibrium=True)
+    assert abs(sch.mass() - m0) < 1e-12 * abs(m0)
+
+
+def test_mass_identity_full_model():
+    """Same identity with flow: int_h phi^{n+1} = (dt/gamma0) int_h(phi_hat/dt - u*.grad phi*)."""
+    m, bc = _box(K=6, n=3)
+    par = _drop_params(dt=1e-4)
+    sch = Scheme(m, par, bc)
+    X, Y = m.X.ravel(), m.Y.ravel()
+    u0 = (np.sin(np.pi * X) * np.sin(2 * np.pi * Y), -np.sin(2 * np.pi * X) * np.sin(np.pi * Y))
+    sch.set_state(_drop(m), u0)
+    src = dict(Vd=_vd_top(m))
+    sch.init_potential(src)
+    for _ in range(3):
+        cur, old = sch.state["cur"], sch.state["old"]
+        phis = 2 * cur["phi"][0] - old["phi"][0]
+        phih = 2 * cur["phi"][0] - 0.5 * old["phi"][0]
+        us = [2 * cur["u"][i][0] - old["u"][i][0] for i in range(2)]
+        adv = m.loc(us[0]) * m.dx(phis) + m.loc(us[1]) * m.dy(phis)
+        expect = (par.dt / 1.5) * (np.sum(m.Mdiag * phih) / par.dt - np.sum(m.wq * adv))
+        out = sch.step(src)
+        assert abs(np.sum(m.Mdiag * out["phi"][0]) - expect) < 1e-12 * abs(expect)
+
+
+def test_pressure_closed_box_gauge_and_compatibility():
+    """Closed box (no open boundary): the pressure right side of eq. (58a) is
+    orthogonal to constants (q = 1 has zero gradient, w = 0), and the gauge
+    int_h P = 0 holds (reading R-gauge)."""
+    m, bc = _box(K=6, n=3)
+    par = _drop_params()
+    sch = Scheme(m, par, bc)
+    X, Y = m.X.ravel(), m.Y.ravel()
+    u0 = (np.sin(np.pi * X) * np.sin(2 * np.pi * Y), -np.sin(2 * np.pi * X) * np.sin(np.pi * Y))
+    sch.set_state(_drop(m), u0)
+    src = dict(Vd=_vd_top(m))
+    sch.init_potential(src)
+    for _ in range(2):
+        out = sch.step(src)
+        b = sch.rhs_P[0]
+        assert abs(b.sum()) < 1e-12 * np.abs(b).sum()
+        assert abs(np.sum(m.Mdiag * out["P"][0])) < 1e-12 * np.sum(m.Mdiag * np.abs(out["P"][0]))
+
+
+def test_3d_with_z_independent_data_equals_2d():
+    """Algorithm 2 with z-independent data keeps every k != 0 mode at zero and
+    reproduces Algorithm 1 plane by plane (Sec. 3.2.2 reduces to Sec. 3.2.1)."""
+    m, bc = _box(K=5, n=2, periodic=True)
+    par = _drop_params()
+    s2 = Scheme(m, par, bc)
+    s3 = Scheme(m, par, bc, Nz=4, Lz=1.0)
+    X, Y = m.X.ravel(), m.Y.ravel()
+    phi0 = _drop(m, c=(0.5, 0.3))
+    u0 = (np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y), np.cos(2 * np.pi * X) * np.sin(np.pi * Y))
+    s2.set_state(phi0, u0)
+    s3.set_state(np.tile(phi0, (4, 1)), (np.tile(u0[0], (4, 1)), np.tile(u0[1], (4, 1)), None))
+    src2 = dict(Vd=_vd_top(m))
+    src3 = dict(Vd=np.tile(_vd_top(m), (4, 1)))
+    s2.init_potential(src2)
+    s3.state["cur"]["V"] = np.tile(s2.state["cur"]["V"], (4, 1))
+    s3.state["old"]["V"] = s3.state["cur"]["V"].copy()
+    for _ in range(3):
+        o2 = s2.step(src2)
+        o3 = s3.step(src3)
+    for k in ("phi", "V", "P", "ux", "uy", "psi", "Ex", "Ey"):
+        for j in range(4):
+            np.testing.assert_allclose(o3[k][j], o2[k][0], atol=1e-11 * max(1, np.abs(o2[k]).max()))
+    np.testing.assert_allclose(o3["uz"], 0.0, atol=1e-13)
+    np.testing.assert_allclose(o3["Ez"], 0.0, atol=1e-13)
+
+
+def test_fixed_point_potential_converges_to_direct_solve():
+    """Remark 3.1: the fixed point eps0 K V^{k+1} = -K_{eps-eps0} V^k - M f_V converges
+    to the variable-coefficient solve used by the oracle (reading R-V0)."""
+    m, bc = _box(K=4, n=3)
+    par = _drop_params()
+    sch = Scheme(m, par, bc)
+    sch.set_state(_drop(m))
+    src = dict(Vd=_vd_top(m))
+    Vdir = sch.init_potential(src)
+    Vit, its = sch.iterate_potential(sch.zeros(), sch._src(src, "Vd"), tol=1e-14, maxit=2000)
+    assert its < 2000
+    np.testing.assert_allclose(Vit, Vdir, atol=1e-12)
