@@ -1,0 +1,219 @@
+/*
+ * pfd -- one time step of the decoupled phase-field scheme for two immiscible
+ * dielectric fluids (Yang, Christov & Dong, arXiv 2305.09020) on an AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library advances (u, P, phi, V) by Algorithm 1 (2D: C0 spectral elements,
+ * Sec. 3.2.1, eqs. 54-59) or Algorithm 2 (3D: spectral elements in x-y times a
+ * Fourier expansion in z, Sec. 3.2.2, eqs. 74-78).  Each step solves, in order,
+ * V, E, psi, phi, P and u, every one with a constant coefficient matrix
+ * (remark after Algorithm 2).
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ *  - Floating point is IEEE binary64 (double) at the boundary.
+ *  - Nodal arrays use the layout  value[(p * Ny + iy) * Nx + ix],
+ *      Nx = nx*K + 1 - periodic_x,  Ny = ny*K + 1,
+ *    p = plane: the z index j (z_j = j*Lz/Nz) in 3D, the instance index of a
+ *    2D batch, 0 for a single 2D problem.  Node coordinates come from
+ *    pfd_get_coords.
+ *  - Memory: the caller owns every buffer.  Device memory for the whole
+ *    context is ONE caller-allocated workspace (size from pfd_workspace_query);
+ *    the library does not allocate device memory after pfd_create.  Host
+ *    memory of the context (small tables) is allocated in pfd_create and freed
+ *    by pfd_destroy.
+ *  - Streams: every device operation is ordered on the hipStream_t given to
+ *    pfd_create.  Entry points taking host buffers synchronise that stream
+ *    before returning; entry points taking device buffers do not.
+ *  - Errors: every call returns a pfd_status; pfd_last_error gives a message.
+ *    A non-finite value detected in a step makes the context sticky-failed:
+ *    further steps return PFD_ESTATE until a field is set again.
+ *  - Threads: one context must not be used from two threads at once.
+ */
+#ifndef PFD_H
+#define PFD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PFD_OK = 0,
+  PFD_EINVAL = 1,      /* bad argument or unsupported configuration            */
+  PFD_ENOMEM = 2,      /* workspace too small                                  */
+  PFD_EHIP = 3,        /* HIP runtime error                                    */
+  PFD_ENONFINITE = 4,  /* a NaN/Inf appeared in the state during a step        */
+  PFD_ENOCONV = 5,     /* iterative refinement / fixed point did not converge  */
+  PFD_ESTATE = 6,      /* context failed earlier or is not initialised         */
+  PFD_ENOTIMPL = 7
+} pfd_status;
+
+/* fields readable/writable with pfd_get_field / pfd_set_field */
+typedef enum {
+  PFD_UX = 0, PFD_UY = 1, PFD_UZ = 2,   /* velocity u (eqs. 59, 78)            */
+  PFD_P = 3,                            /* pressure P (eqs. 58, 77)            */
+  PFD_PHI = 4,                          /* phase field phi (eqs. 57, 76)       */
+  PFD_PSI = 5,                          /* auxiliary psi of eq. (44)           */
+  PFD_V = 6,                            /* electric potential V (eqs. 54, 74)  */
+  PFD_EX = 7, PFD_EY = 8, PFD_EZ = 9,   /* electric field E (eqs. 55, 78)      */
+  PFD_NFIELDS = 10
+} pfd_field;
+
+/* source terms of the source-augmented system (Sec. 3.1, eqs. 27-33), nodal
+ * values at t^{n+1}.  Volume sources: G (phase field), FX..FZ (momentum f),
+ * FV (potential f_V).  Boundary sources (only values on the relevant boundary
+ * nodes are read): G1 (n.grad of the chemical-potential bracket of eq. phia,
+ * open and wall), G2 (n.grad phi, open), G3 (eq. phic, wall), F1X..F1Z
+ * (du/dn, open), F2 (P, open), WX..WZ (u, wall), VD (V on the Dirichlet
+ * electrode nodes).  Sources persist until replaced; a NULL pointer resets a
+ * source to zero. */
+typedef enum {
+  PFD_SRC_G = 0, PFD_SRC_FX, PFD_SRC_FY, PFD_SRC_FZ, PFD_SRC_FV,
+  PFD_SRC_G1, PFD_SRC_G2, PFD_SRC_G3, PFD_SRC_F1X, PFD_SRC_F1Y, PFD_SRC_F1Z,
+  PFD_SRC_F2, PFD_SRC_WX, PFD_SRC_WY, PFD_SRC_WZ, PFD_SRC_VD,
+  PFD_NSRC
+} pfd_source;
+
+/* precision of the constant-coefficient solves */
+typedef enum {
+  PFD_PLAIN_FP64 = 0,   /* FP64 fast-diagonalisation solve                     */
+  PFD_REFINED_FP32 = 1  /* FP32 solve + FP64 residual iterative refinement     */
+} pfd_precision;
+
+enum { PFD_WALL = 0, PFD_OPEN = 1, PFD_PERIODIC = 2 };
+enum { PFD_BOTTOM = 0, PFD_TOP = 1, PFD_LEFT = 2, PFD_RIGHT = 3 };
+
+/* solve families: the five constant operators (K + c M) of the step */
+enum { PFD_FAM_V = 0, PFD_FAM_PSI = 1, PFD_FAM_PHI = 2, PFD_FAM_P = 3, PFD_FAM_U = 4 };
+
+typedef struct {
+  int nx, ny;            /* elements along x and y (tensor-product mesh)        */
+  int K;                 /* element order, 2 <= K <= 16                         */
+  const double* xb;      /* nx+1 increasing x breakpoints (host)                */
+  const double* yb;      /* ny+1 increasing y breakpoints (host)                */
+  int periodic_x;        /* 1: x = xb[0] and x = xb[nx] identified              */
+  int nz;                /* 0: 2D; even >= 2: number of Fourier planes (3D)    */
+  double lz;             /* period in z (3D)                                    */
+  int nbatch;            /* 2D only: independent instances on this mesh (>=1)  */
+} pfd_mesh;
+
+typedef struct {
+  double rho1, rho2;     /* densities (eq. interpolation)                       */
+  double mu1, mu2;       /* dynamic viscosities                                 */
+  double eps1, eps2;     /* permittivities                                      */
+  double lambda;         /* mixing energy density (eq. double_well)             */
+  double eta;            /* interface thickness                                 */
+  double gamma1;         /* mobility                                            */
+  double theta_s_deg;    /* static contact angle of eq. (theta_def), degrees    */
+  double dt;             /* time step                                           */
+  int bdf_order;         /* J = 1 or 2 (Sec. 3.1)                               */
+  double S;              /* stabiliser; 0 -> eta^2 sqrt(4 gamma0/(lambda gamma1 dt)) */
+  double nu_m;           /* 0 -> max(mu1,mu2)/min(rho1,rho2)                    */
+} pfd_params;
+
+typedef struct {
+  int side_type[4];        /* PFD_WALL / PFD_OPEN per side (x sides ignored if periodic) */
+  int pot_dirichlet[4];    /* 1: V Dirichlet on the whole side                   */
+  int n_electrodes;        /* V Dirichlet segments [x0,x1] on the bottom wall    */
+  const double* electrode_x0;  /* host; segment ends must lie on element edges   */
+  const double* electrode_x1;
+} pfd_bcs;
+
+typedef struct {
+  pfd_mesh mesh;
+  pfd_params par;
+  pfd_bcs bc;
+  int precision;         /* pfd_precision                                        */
+  int refine_iters;      /* corrections per solve in PFD_REFINED_FP32 (0 -> 2)   */
+} pfd_problem;
+
+typedef struct pfd_ctx pfd_ctx;
+
+typedef struct {
+  double derived[10];    /* gamma0, S, alpha, c_psi, c_phi, eps0, rho0, nu_m, c_u, -  */
+  double last_residual;  /* max over the last step's solves of ||b-Ax||_2/||b||_2 (if checked) */
+  int nonfinite;         /* 1 if a non-finite value was seen                     */
+  long steps;            /* steps taken since the last pfd_set_field             */
+} pfd_diag;
+
+/* Human-readable name of a status code.  Never NULL. */
+const char* pfd_status_string(pfd_status s);
+
+/* Message describing the last error on ctx (or on the most recent failed
+ * pfd_create when ctx is NULL).  Valid until the next call on ctx. */
+const char* pfd_last_error(const pfd_ctx* ctx);
+
+/* Device bytes the context for *prob needs.  Host-only; validates prob
+ * (PFD_EINVAL for: K outside [2,16], nx or ny < 1, non-increasing breakpoints,
+ * dt <= 0, eta <= 0, odd or < 2 nz, nbatch < 1 or nbatch > 1 in 3D, an
+ * electrode segment not on element edges, no V Dirichlet node at all). */
+pfd_status pfd_workspace_query(const pfd_problem* prob, size_t* dev_bytes);
+
+/* Build the context: GLL tables, 1D operators and their FP64 generalised
+ * eigen-decompositions (Lynch-Rice-Thomas fast diagonalisation of the constant
+ * matrices), electrode capacitance matrices, and device copies.  dev_ws is a
+ * device buffer of at least dev_bytes from pfd_workspace_query, 256-byte
+ * aligned, owned by the caller and kept alive until pfd_destroy.  stream is a
+ * hipStream_t (NULL = default stream).  All fields start at zero. */
+pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t dev_bytes,
+                      void* stream, pfd_ctx** out);
+
+/* Free host memory of ctx (the workspace stays the caller's).  NULL is a no-op. */
+void pfd_destroy(pfd_ctx* ctx);
+
+/* Nx, Ny and the number of planes (nz in 3D, nbatch in 2D). */
+pfd_status pfd_get_dims(const pfd_ctx* ctx, int* Nx, int* Ny, int* planes);
+
+/* Host copies of the 1D node coordinates: x[Nx], y[Ny], z[planes] (z may be
+ * NULL; in 2D z is filled with zeros). */
+pfd_status pfd_get_coords(const pfd_ctx* ctx, double* x, double* y, double* z);
+
+/* Derived constants and diagnostics. */
+pfd_status pfd_get_diag(pfd_ctx* ctx, pfd_diag* d);
+
+/* Copy a field in or out.  level 0 = time level n, -1 = level n-1 (u, P, phi,
+ * V, psi have two levels; E only level 0).  src/dst hold planes*Ny*Nx doubles,
+ * on the device when on_device != 0 (stream-ordered, no sync) else on the
+ * host (synchronous).  Setting level 0 of u, P, phi or V without setting
+ * level -1 afterwards also copies it to level -1 (BDF start, Sec. 3.1). */
+pfd_status pfd_set_field(pfd_ctx* ctx, int field, int level, const double* src, int on_device);
+pfd_status pfd_get_field(pfd_ctx* ctx, int field, int level, double* dst, int on_device);
+
+/* Set one source array (see pfd_source); NULL resets it to zero. */
+pfd_status pfd_set_source(pfd_ctx* ctx, int source, const double* src, int on_device);
+
+/* Initial potential by the fixed point of Remark 3.1: iterate eq. (54)/(74)
+ * with phi* = phi^0 and V* = previous iterate until
+ * max|dV| <= tol * max(1, max|V|) or max_iter iterations.  Stores the result
+ * at levels n and n-1 of V and updates E.  Synchronises.  PFD_ENOCONV if the
+ * tolerance is not met. */
+pfd_status pfd_init_potential(pfd_ctx* ctx, double tol, int max_iter, int* iters);
+
+/* Advance nsteps time steps (Algorithm 1 or 2).  equilibrium != 0 runs the
+ * simpler system of Sec. 2.4 (eqs. 15c-d and 16: V, E, psi, phi with u = 0)
+ * instead of the full step.  Sources are held fixed over the nsteps steps.
+ * Stream-ordered; synchronises once at the end to read the status word.
+ * Returns PFD_ENONFINITE if a non-finite value appeared. */
+pfd_status pfd_step(pfd_ctx* ctx, int nsteps, int equilibrium);
+
+/* Same as pfd_step without the final synchronisation or status read: for
+ * timing loops and graph capture.  Check pfd_get_diag afterwards. */
+pfd_status pfd_step_async(pfd_ctx* ctx, int nsteps, int equilibrium);
+
+/* Solve (K + (c_f + beta_p^2) M) x = b for solve family fam on every plane,
+ * with x = x_in on the family's Dirichlet nodes (eqs. 54-59 operators).  b and
+ * x are device arrays of planes*Ny*Nx doubles; x holds the initial guess and
+ * the Dirichlet values on entry and the solution on exit.  For a singular
+ * family (no Dirichlet node and zero shift) b is projected onto the range and
+ * the solution has int_h x = 0.  Uses the context's precision setting. */
+pfd_status pfd_solve(pfd_ctx* ctx, int fam, const double* b, double* x);
+
+/* y = (K + (c_f + beta_p^2) M) x on every plane (device arrays). */
+pfd_status pfd_apply(pfd_ctx* ctx, int fam, const double* x, double* y);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFD_H */

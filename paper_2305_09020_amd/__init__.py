@@ -1,0 +1,228 @@
+"""Python binding of the pfd C-ABI library (libpfd.so, HIP for gfx950).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch provides the device workspace and the stream.  Importing this
+module loads the in-tree libpfd.so and raises if it is missing; build it with
+``python -m paper_2305_09020_amd.build`` (or ``__graft_entry__.build()``).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libpfd.so")
+
+if not os.path.exists(LIBPATH):
+    raise ImportError("libpfd.so is not built (run paper_2305_09020_amd/build.py)")
+_lib = ctypes.CDLL(LIBPATH)
+
+# ---- enums (mirror include/pfd.h) -------------------------------------------------
+OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ENOCONV, ESTATE, ENOTIMPL = range(8)
+UX, UY, UZ, P, PHI, PSI, V, EX, EY, EZ = range(10)
+FIELDS = dict(ux=UX, uy=UY, uz=UZ, P=P, phi=PHI, psi=PSI, V=V, Ex=EX, Ey=EY, Ez=EZ)
+SOURCES = dict(g=0, fx=1, fy=2, fz=3, fV=4, g1=5, g2=6, g3=7, f1x=8, f1y=9, f1z=10, f2=11,
+               wx=12, wy=13, wz=14, Vd=15)
+PLAIN_FP64, REFINED_FP32 = 0, 1
+WALL, OPEN, PERIODIC = 0, 1, 2
+BOTTOM, TOP, LEFT, RIGHT = 0, 1, 2, 3
+FAM_V, FAM_PSI, FAM_PHI, FAM_P, FAM_U = range(5)
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("K", ctypes.c_int),
+                ("xb", _dp), ("yb", _dp), ("periodic_x", ctypes.c_int), ("nz", ctypes.c_int),
+                ("lz", ctypes.c_double), ("nbatch", ctypes.c_int)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("rho1", "rho2", "mu1", "mu2", "eps1", "eps2", "lam", "eta", "gamma1",
+                 "theta_s_deg", "dt")] + [("bdf_order", ctypes.c_int), ("S", ctypes.c_double),
+                                          ("nu_m", ctypes.c_double)]
+
+
+class BCs(ctypes.Structure):
+    _fields_ = [("side_type", ctypes.c_int * 4), ("pot_dirichlet", ctypes.c_int * 4),
+                ("n_electrodes", ctypes.c_int), ("electrode_x0", _dp), ("electrode_x1", _dp)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("mesh", Mesh), ("par", Params), ("bc", BCs), ("precision", ctypes.c_int),
+                ("refine_iters", ctypes.c_int)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("derived", ctypes.c_double * 10), ("last_residual", ctypes.c_double),
+                ("nonfinite", ctypes.c_int), ("steps", ctypes.c_long)]
+
+
+_vp = ctypes.c_void_p
+_sig = {
+    "pfd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "pfd_last_error": (ctypes.c_char_p, [_vp]),
+    "pfd_workspace_query": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)]),
+    "pfd_create": (ctypes.c_int, [ctypes.POINTER(Problem), _vp, ctypes.c_size_t, _vp,
+                                  ctypes.POINTER(_vp)]),
+    "pfd_destroy": (None, [_vp]),
+    "pfd_get_dims": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int)]),
+    "pfd_get_coords": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "pfd_get_diag": (ctypes.c_int, [_vp, ctypes.POINTER(Diag)]),
+    "pfd_set_field": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int]),
+    "pfd_get_field": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int]),
+    "pfd_set_source": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
+    "pfd_init_potential": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int)]),
+    "pfd_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "pfd_step_async": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "pfd_solve": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
+    "pfd_apply": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
+}
+EXPORTS = tuple(_sig)
+for _n, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _n)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class PfdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_lib.pfd_status_string(code).decode(), msg))
+        self.code = code
+
+
+def _check(code, ctx=None):
+    if code != OK:
+        raise PfdError(code, _lib.pfd_last_error(ctx).decode())
+
+
+def make_problem(xb, yb, K, params, side_type, pot_dirichlet, periodic_x=False, nbatch=1,
+                 nz=0, lz=0.0, precision=PLAIN_FP64, refine_iters=0, electrodes=()):
+    """Build the C problem struct.  params: mapping with rho1, rho2, mu1, mu2, eps1, eps2,
+    lam, eta, gamma1, theta_s_deg, dt and optional bdf (2), S (0), nu_m (0)."""
+    xb = np.ascontiguousarray(xb, dtype=np.float64)
+    yb = np.ascontiguousarray(yb, dtype=np.float64)
+    pr = Problem()
+    pr.mesh = Mesh(len(xb) - 1, len(yb) - 1, K, xb.ctypes.data_as(_dp), yb.ctypes.data_as(_dp),
+                   int(periodic_x), int(nz), float(lz), int(nbatch))
+    g = params.get
+    pr.par = Params(g("rho1"), g("rho2"), g("mu1"), g("mu2"), g("eps1"), g("eps2"), g("lam"),
+                    g("eta"), g("gamma1"), g("theta_s_deg"), g("dt"), int(g("bdf", 2)),
+                    float(g("S", 0.0)), float(g("nu_m", 0.0)))
+    st = (ctypes.c_int * 4)(*side_type)
+    pd = (ctypes.c_int * 4)(*pot_dirichlet)
+    e0 = np.ascontiguousarray([e[0] for e in electrodes], dtype=np.float64)
+    e1 = np.ascontiguousarray([e[1] for e in electrodes], dtype=np.float64)
+    pr.bc = BCs(st, pd, len(electrodes), e0.ctypes.data_as(_dp), e1.ctypes.data_as(_dp))
+    pr.precision = precision
+    pr.refine_iters = refine_iters
+    pr._keep = (xb, yb, e0, e1)   # keep host arrays alive while pr is used
+    return pr
+
+
+def workspace_bytes(problem):
+    n = ctypes.c_size_t(0)
+    _check(_lib.pfd_workspace_query(ctypes.byref(problem), ctypes.byref(n)))
+    return n.value
+
+
+class Context:
+    """A pfd context on the current torch device and stream.  Device memory is one
+    torch uint8 tensor (the workspace) owned by this object."""
+
+    def __init__(self, problem, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        nbytes = workspace_bytes(problem)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        h = _vp()
+        _check(_lib.pfd_create(ctypes.byref(problem), _vp(base + off), nbytes,
+                               _vp(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        nx, ny, npl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.pfd_get_dims(h, ctypes.byref(nx), ctypes.byref(ny), ctypes.byref(npl)), h)
+        self.Nx, self.Ny, self.planes = nx.value, ny.value, npl.value
+        self.shape = (self.planes, self.Ny, self.Nx)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.pfd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # -- host / device transfers -------------------------------------------------
+    def coords(self):
+        x = np.zeros(self.Nx)
+        y = np.zeros(self.Ny)
+        z = np.zeros(self.planes)
+        _check(_lib.pfd_get_coords(self.h, x.ctypes.data_as(_dp), y.ctypes.data_as(_dp),
+                                   z.ctypes.data_as(_dp)), self.h)
+        return x, y, z
+
+    def _arr(self, a):
+        """(pointer, on_device, keepalive) for a numpy array or torch tensor of the field shape."""
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            if a.dtype != t.float64 or not a.is_contiguous() or a.numel() != self.planes * self.Ny * self.Nx:
+                raise ValueError("need a contiguous float64 tensor of %d values" % (self.planes * self.Ny * self.Nx))
+            return _vp(a.data_ptr()), int(a.is_cuda), a
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if a.size != self.planes * self.Ny * self.Nx:
+            raise ValueError("field has %d values, expected %d" % (a.size, self.planes * self.Ny * self.Nx))
+        return _vp(a.ctypes.data), 0, a
+
+    def set_field(self, name, value, level=0):
+        p, dev, keep = self._arr(value)
+        _check(_lib.pfd_set_field(self.h, FIELDS[name], level, p, dev), self.h)
+
+    def get_field(self, name, level=0, out=None):
+        if out is None:
+            out = np.zeros(self.shape)
+        p, dev, keep = self._arr(out)
+        _check(_lib.pfd_get_field(self.h, FIELDS[name], level, p, dev), self.h)
+        return out
+
+    def set_source(self, name, value):
+        if value is None:
+            _check(_lib.pfd_set_source(self.h, SOURCES[name], None, 0), self.h)
+            return
+        p, dev, keep = self._arr(value)
+        _check(_lib.pfd_set_source(self.h, SOURCES[name], p, dev), self.h)
+
+    def set_sources(self, src):
+        for k, v in src.items():
+            if k in SOURCES:
+                self.set_source(k, v)
+
+    # -- the method ------------------------------------------------------------------
+    def init_potential(self, tol=1e-13, max_iter=20000):
+        it = ctypes.c_int(0)
+        _check(_lib.pfd_init_potential(self.h, tol, max_iter, ctypes.byref(it)), self.h)
+        return it.value
+
+    def step(self, nsteps=1, equilibrium=False):
+        _check(_lib.pfd_step(self.h, int(nsteps), int(bool(equilibrium))), self.h)
+
+    def step_async(self, nsteps=1, equilibrium=False):
+        _check(_lib.pfd_step_async(self.h, int(nsteps), int(bool(equilibrium))), self.h)
+
+    def solve(self, fam, b, x):
+        """Device tensors b, x (float64, planes*Ny*Nx); x: guess + Dirichlet values in, solution out."""
+        _check(_lib.pfd_solve(self.h, fam, _vp(b.data_ptr()), _vp(x.data_ptr())), self.h)
+
+    def apply(self, fam, x, y):
+        _check(_lib.pfd_apply(self.h, fam, _vp(x.data_ptr()), _vp(y.data_ptr())), self.h)
+
+    def diag(self):
+        d = Diag()
+        _check(_lib.pfd_get_diag(self.h, ctypes.byref(d)), self.h)
+        return dict(derived=list(d.derived), last_residual=d.last_residual,
+                    nonfinite=d.nonfinite, steps=d.steps)

@@ -1,0 +1,475 @@
+// C-ABI of the pfd library: context set-up, field I/O and the step driver.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "pfd_internal.h"
+
+using namespace pfd;
+
+static std::string g_create_err;
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess) {                                                       \
+      c->err = std::string("HIP error: ") + hipGetErrorString(_e) + " at " #expr; \
+      return PFD_EHIP;                                                            \
+    }                                                                             \
+  } while (0)
+
+extern "C" const char* pfd_status_string(pfd_status s) {
+  switch (s) {
+    case PFD_OK: return "PFD_OK";
+    case PFD_EINVAL: return "PFD_EINVAL";
+    case PFD_ENOMEM: return "PFD_ENOMEM";
+    case PFD_EHIP: return "PFD_EHIP";
+    case PFD_ENONFINITE: return "PFD_ENONFINITE";
+    case PFD_ENOCONV: return "PFD_ENOCONV";
+    case PFD_ESTATE: return "PFD_ESTATE";
+    case PFD_ENOTIMPL: return "PFD_ENOTIMPL";
+  }
+  return "PFD_UNKNOWN";
+}
+
+extern "C" const char* pfd_last_error(const pfd_ctx* c) {
+  return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+namespace {
+
+struct Layout {
+  int Nx, Ny, planes, is3d;
+  long Ng, Nl;
+  size_t bytes;
+};
+
+pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
+  if (!p) { *err = "null problem"; return PFD_EINVAL; }
+  const pfd_mesh& m = p->mesh;
+  if (m.K < 2 || m.K > PFD_KMAX) { *err = "K must be in [2,16]"; return PFD_EINVAL; }
+  if (m.nx < 1 || m.ny < 1 || !m.xb || !m.yb) { *err = "bad element counts or breakpoints"; return PFD_EINVAL; }
+  if (m.periodic_x && m.nx < 2) { *err = "periodic x needs nx >= 2"; return PFD_EINVAL; }
+  for (int i = 0; i < m.nx; ++i)
+    if (!(m.xb[i + 1] > m.xb[i])) { *err = "x breakpoints must increase"; return PFD_EINVAL; }
+  for (int i = 0; i < m.ny; ++i)
+    if (!(m.yb[i + 1] > m.yb[i])) { *err = "y breakpoints must increase"; return PFD_EINVAL; }
+  const pfd_params& q = p->par;
+  if (!(q.dt > 0) || !(q.eta > 0) || !(q.lambda > 0) || !(q.gamma1 > 0)) {
+    *err = "dt, eta, lambda, gamma1 must be positive"; return PFD_EINVAL;
+  }
+  if (!(q.rho1 > 0) || !(q.rho2 > 0) || !(q.mu1 > 0) || !(q.mu2 > 0) || !(q.eps1 > 0) || !(q.eps2 > 0)) {
+    *err = "material properties must be positive"; return PFD_EINVAL;
+  }
+  if (q.bdf_order != 1 && q.bdf_order != 2) { *err = "bdf_order must be 1 or 2"; return PFD_EINVAL; }
+  if (p->precision != PFD_PLAIN_FP64 && p->precision != PFD_REFINED_FP32) { *err = "bad precision"; return PFD_EINVAL; }
+  if (m.nz != 0) { *err = "3D (nz > 0) is not available in this build"; return PFD_ENOTIMPL; }
+  if (m.nbatch < 1) { *err = "nbatch must be >= 1"; return PFD_EINVAL; }
+  if (p->bc.n_electrodes > 0) { *err = "partial electrode segments are not available in this build"; return PFD_ENOTIMPL; }
+  for (int s = 0; s < 4; ++s) {
+    if (m.periodic_x && s >= PFD_LEFT) continue;
+    if (p->bc.side_type[s] != PFD_WALL && p->bc.side_type[s] != PFD_OPEN) { *err = "side type must be WALL or OPEN"; return PFD_EINVAL; }
+  }
+  bool anyV = false;
+  for (int s = 0; s < 4; ++s)
+    if (p->bc.pot_dirichlet[s] && !(m.periodic_x && s >= PFD_LEFT)) anyV = true;
+  if (!anyV) { *err = "the potential needs a Dirichlet side"; return PFD_EINVAL; }
+  L->Nx = m.nx * m.K + 1 - (m.periodic_x ? 1 : 0);
+  L->Ny = m.ny * m.K + 1;
+  if (L->Nx > PFD_NMAX || L->Ny > PFD_NMAX) { *err = "more than 320 nodes along a direction"; return PFD_EINVAL; }
+  L->is3d = 0;
+  L->planes = m.nbatch;
+  L->Ng = (long)L->Nx * L->Ny;
+  L->Nl = (long)m.nx * m.ny * (m.K + 1) * (m.K + 1);
+  const long Pg = L->planes * L->Ng, Pl = L->planes * L->Nl;
+  size_t dbl = 0;
+  dbl += (size_t)F_NSTATE * 2 * Pg;      // state
+  dbl += (size_t)PFD_NSRC * Pg;          // sources
+  dbl += 3 * (size_t)Pl;                 // element-local buffers
+  dbl += 3 * (size_t)Pg;                 // right sides
+  dbl += 5 * (size_t)Pg;                 // r, U, Q2, tmp, zero
+  dbl += 7 * (size_t)L->Ng;              // boundary masses, mass
+  const int NN = std::max(L->Nx, L->Ny);
+  dbl += 8 * (3 * (size_t)NN * NN + 3 * NN + 8);  // up to 8 distinct 1D operators
+  dbl += 8 * (size_t)NN * NN;            // float copies (as doubles, generous)
+  dbl += 2 * (size_t)(m.nx + m.ny + 2) + (PFD_KMAX + 1) * (PFD_KMAX + 2);
+  dbl += 16 * (size_t)L->planes + 256;   // shifts, norms, reductions
+  L->bytes = dbl * sizeof(double) + 256 * 128;  // alignment slack
+  return PFD_OK;
+}
+
+void* carve(pfd_ctx* c, size_t bytes) {
+  size_t off = (c->ws_used + 255) & ~(size_t)255;
+  if (off + bytes > c->ws_bytes) return nullptr;
+  c->ws_used = off + bytes;
+  return c->ws + off;
+}
+
+}  // namespace
+
+extern "C" pfd_status pfd_workspace_query(const pfd_problem* prob, size_t* dev_bytes) {
+  Layout L;
+  pfd_status s = validate(prob, &L, &g_create_err);
+  if (s != PFD_OK) return s;
+  if (dev_bytes) *dev_bytes = L.bytes;
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t dev_bytes, void* stream,
+                                 pfd_ctx** out) {
+  if (!out) { g_create_err = "null output pointer"; return PFD_EINVAL; }
+  *out = nullptr;
+  Layout L;
+  pfd_status st = validate(prob, &L, &g_create_err);
+  if (st != PFD_OK) return st;
+  if (!dev_ws || dev_bytes < L.bytes) { g_create_err = "workspace too small"; return PFD_ENOMEM; }
+  if (((uintptr_t)dev_ws) & 255) { g_create_err = "workspace must be 256-byte aligned"; return PFD_EINVAL; }
+  pfd_ctx* c = new pfd_ctx();
+  c->prob = *prob;
+  c->prob.mesh.xb = nullptr;  // host pointers are not kept
+  c->prob.mesh.yb = nullptr;
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)dev_ws;
+  c->ws_bytes = dev_bytes;
+  c->Nx = L.Nx; c->Ny = L.Ny; c->planes = L.planes; c->is3d = L.is3d;
+  c->Ng = L.Ng; c->Nl = L.Nl;
+  const pfd_mesh& m = prob->mesh;
+  const int K = m.K;
+  c->K = K; c->n = K + 1; c->nq = (K + 1) * (K + 1);
+  gll_rule(K, c->xi, c->w, c->D);
+
+  // ---- derived constants (Sec. 3.1, eq. 44)
+  const pfd_params& q = prob->par;
+  Par& P = c->par;
+  P.rho1 = q.rho1; P.rho2 = q.rho2; P.mu1 = q.mu1; P.mu2 = q.mu2; P.eps1 = q.eps1; P.eps2 = q.eps2;
+  P.lam = q.lambda; P.eta = q.eta; P.gamma1 = q.gamma1; P.dt = q.dt;
+  P.gamma0 = (q.bdf_order == 2) ? 1.5 : 1.0;
+  const double lg = q.lambda * q.gamma1;
+  const double Slow = q.eta * q.eta * std::sqrt(4.0 * P.gamma0 / (lg * q.dt));
+  P.S = q.S > 0 ? q.S : Slow;
+  double rad = 1.0 - 4.0 * P.gamma0 / (lg * q.dt) * std::pow(q.eta, 4) / (P.S * P.S);
+  if (rad < 0.0) rad = 0.0;
+  P.alpha = -P.S / (2.0 * q.eta * q.eta) * (1.0 + std::sqrt(rad));
+  P.c_psi = P.alpha + P.S / (q.eta * q.eta);
+  P.c_phi = -P.alpha;
+  P.eps0 = std::max(q.eps1, q.eps2);
+  P.rho0 = std::min(q.rho1, q.rho2);
+  P.nu_m = q.nu_m > 0 ? q.nu_m : std::max(q.mu1, q.mu2) / std::min(q.rho1, q.rho2);
+  P.c_u = P.gamma0 / (P.nu_m * q.dt);
+  P.cos_theta = std::cos(q.theta_s_deg * M_PI / 180.0);
+  if (q.bdf_order == 2) { P.cs_n = 2.0; P.cs_o = -1.0; P.ch_n = 2.0; P.ch_o = -0.5; }
+  else { P.cs_n = 1.0; P.cs_o = 0.0; P.ch_n = 1.0; P.ch_o = 0.0; }
+
+  // ---- 1D operators per family and direction (deduplicated)
+  const pfd_bcs& bc = prob->bc;
+  const bool per = m.periodic_x != 0;
+  auto side_dir = [&](int fam, int s) -> bool {
+    if (per && s >= PFD_LEFT) return false;
+    switch (fam) {
+      case PFD_FAM_V: return bc.pot_dirichlet[s] != 0;
+      case PFD_FAM_P: return bc.side_type[s] == PFD_OPEN;
+      case PFD_FAM_U: return bc.side_type[s] == PFD_WALL;
+      default: return false;
+    }
+  };
+  std::map<std::tuple<int, int, int>, int> xkey, ykey;
+  for (int f = 0; f < 5; ++f) {
+    auto kx = std::make_tuple(per ? 2 : 0, (int)side_dir(f, PFD_LEFT), (int)side_dir(f, PFD_RIGHT));
+    auto ky = std::make_tuple(0, (int)side_dir(f, PFD_BOTTOM), (int)side_dir(f, PFD_TOP));
+    if (!xkey.count(kx)) {
+      Dir1D d;
+      build_dir1d(d, m.nx, m.xb, K, per, std::get<1>(kx), std::get<2>(kx), c->xi, c->w, c->D);
+      xkey[kx] = (int)c->dirs.size();
+      c->dirs.push_back(std::move(d));
+    }
+    if (!ykey.count(ky)) {
+      Dir1D d;
+      build_dir1d(d, m.ny, m.yb, K, false, std::get<1>(ky), std::get<2>(ky), c->xi, c->w, c->D);
+      ykey[ky] = (int)c->dirs.size();
+      c->dirs.push_back(std::move(d));
+    }
+    c->fam[f].ix = xkey[kx];
+    c->fam[f].iy = ykey[ky];
+  }
+  const double shifts[5] = {0.0, P.c_psi, P.c_phi, 0.0, P.c_u};
+  c->beta2.assign(c->planes, 0.0);
+  c->betad.assign(c->planes, 0.0);
+
+  // ---- carve the workspace
+  const long Pg = (long)c->planes * c->Ng, Pl = (long)c->planes * c->Nl;
+  auto D = [&](long n) { return (double*)carve(c, sizeof(double) * n); };
+  for (int f = 0; f < F_NSTATE; ++f)
+    for (int l = 0; l < 2; ++l) c->fld[f][l] = D(Pg);
+  for (int s = 0; s < PFD_NSRC; ++s) c->src[s] = D(Pg);
+  for (int i = 0; i < 3; ++i) c->Lb[i] = D(Pl);
+  for (int i = 0; i < 3; ++i) c->b[i] = D(Pg);
+  c->r = D(Pg); c->U = D(Pg); c->Q2 = D(Pg); c->tmp = D(Pg);
+  double* zero = D(Pg);
+  for (int s = 0; s < 4; ++s) c->bm_side[s] = D(c->Ng);
+  c->bm_open = D(c->Ng); c->bm_wall = D(c->Ng); c->Mdiag = D(c->Ng);
+  c->d_hx = D(m.nx); c->d_hy = D(m.ny);
+  c->d_w = D(K + 1); c->d_D = D((long)(K + 1) * (K + 1));
+  c->d_status = (int*)carve(c, 64);
+  c->d_norms = D(2 * c->planes + 2);
+  c->d_red = D(2 * 64);
+  c->d_beta2 = D(c->planes); c->d_betad = D(c->planes);
+  for (int f = 0; f < 5; ++f) c->fam[f].dshift = D(c->planes);
+  for (auto& d : c->dirs) {
+    const long NN = (long)d.N * d.N;
+    d.dS = D(NN); d.dST = D(NN); d.dK1 = D(NN); d.dlam = D(d.N); d.dM1 = D(d.N);
+    d.fS = (float*)carve(c, sizeof(float) * NN);
+    d.fST = (float*)carve(c, sizeof(float) * NN);
+    d.ddir = (unsigned char*)carve(c, d.N);
+  }
+  bool ok = c->fld[0][0] && zero && c->fam[4].dshift;
+  for (auto& d : c->dirs) ok = ok && d.ddir;
+  if (!ok) { g_create_err = "workspace too small (layout)"; delete c; return PFD_ENOMEM; }
+  (void)zero;
+
+  // ---- host tables -> device (synchronous copies: set-up only)
+  hipError_t e = hipStreamSynchronize(c->stream);
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  for (auto& d : c->dirs) {
+    if (e) break;
+    const int N = d.N;
+    std::vector<double> ST((size_t)N * N);
+    std::vector<float> f1((size_t)N * N), f2((size_t)N * N);
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        ST[(size_t)j * N + i] = d.S[(size_t)i * N + j];
+        f1[(size_t)i * N + j] = (float)d.S[(size_t)i * N + j];
+        f2[(size_t)j * N + i] = (float)d.S[(size_t)i * N + j];
+      }
+    std::vector<unsigned char> dd(N);
+    for (int i = 0; i < N; ++i) dd[i] = d.dir[i] ? 1 : 0;
+    e = up(d.dS, d.S.data(), 8 * N * N); if (e) break;
+    e = up(d.dST, ST.data(), 8 * N * N); if (e) break;
+    e = up(d.dK1, d.K1.data(), 8 * N * N); if (e) break;
+    e = up(d.dlam, d.lam.data(), 8 * N); if (e) break;
+    e = up(d.dM1, d.M1.data(), 8 * N); if (e) break;
+    e = up(d.fS, f1.data(), 4 * N * N); if (e) break;
+    e = up(d.fST, f2.data(), 4 * N * N); if (e) break;
+    e = up(d.ddir, dd.data(), N); if (e) break;
+  }
+  // boundary and volume masses from the x/y 1D masses (any family's dirs share M1)
+  const Dir1D& DX = c->dirs[c->fam[0].ix];
+  const Dir1D& DY = c->dirs[c->fam[0].iy];
+  std::vector<double> Md(c->Ng), bs[4], bo(c->Ng, 0.0), bw(c->Ng, 0.0);
+  for (int s = 0; s < 4; ++s) bs[s].assign(c->Ng, 0.0);
+  for (int iy = 0; iy < c->Ny; ++iy)
+    for (int ix = 0; ix < c->Nx; ++ix) Md[(long)iy * c->Nx + ix] = DX.M1[ix] * DY.M1[iy];
+  for (int ix = 0; ix < c->Nx; ++ix) {
+    bs[PFD_BOTTOM][ix] = DX.M1[ix];
+    bs[PFD_TOP][(long)(c->Ny - 1) * c->Nx + ix] = DX.M1[ix];
+  }
+  if (!per)
+    for (int iy = 0; iy < c->Ny; ++iy) {
+      bs[PFD_LEFT][(long)iy * c->Nx] = DY.M1[iy];
+      bs[PFD_RIGHT][(long)iy * c->Nx + c->Nx - 1] = DY.M1[iy];
+    }
+  for (int s = 0; s < 4; ++s) {
+    if (per && s >= PFD_LEFT) continue;
+    for (long i = 0; i < c->Ng; ++i) {
+      if (bc.side_type[s] == PFD_OPEN) bo[i] += bs[s][i];
+      else bw[i] += bs[s][i];
+    }
+  }
+  std::vector<double> hx(m.nx), hy(m.ny);
+  for (int i = 0; i < m.nx; ++i) hx[i] = m.xb[i + 1] - m.xb[i];
+  for (int i = 0; i < m.ny; ++i) hy[i] = m.yb[i + 1] - m.yb[i];
+  std::vector<double> shp[5];
+  for (int f = 0; f < 5; ++f) {
+    Family& F = c->fam[f];
+    F.shift = shifts[f];
+    F.hshift.assign(c->planes, 0.0);
+    bool sing = c->dirs[F.ix].singular && c->dirs[F.iy].singular;
+    F.any_singular = false;
+    for (int p = 0; p < c->planes; ++p) {
+      F.hshift[p] = F.shift + c->beta2[p];
+      if (sing && F.hshift[p] == 0.0) F.any_singular = true;
+    }
+  }
+  if (!e) for (int s = 0; s < 4; ++s) { e = up(c->bm_side[s], bs[s].data(), 8 * c->Ng); if (e) break; }
+  if (!e) e = up(c->bm_open, bo.data(), 8 * c->Ng);
+  if (!e) e = up(c->bm_wall, bw.data(), 8 * c->Ng);
+  if (!e) e = up(c->Mdiag, Md.data(), 8 * c->Ng);
+  if (!e) e = up(c->d_hx, hx.data(), 8 * m.nx);
+  if (!e) e = up(c->d_hy, hy.data(), 8 * m.ny);
+  if (!e) e = up(c->d_w, c->w.data(), 8 * (K + 1));
+  if (!e) e = up(c->d_D, c->D.data(), 8 * (K + 1) * (K + 1));
+  if (!e) e = up(c->d_beta2, c->beta2.data(), 8 * c->planes);
+  if (!e) e = up(c->d_betad, c->betad.data(), 8 * c->planes);
+  for (int f = 0; f < 5 && !e; ++f) e = up(c->fam[f].dshift, c->fam[f].hshift.data(), 8 * c->planes);
+  // zero every field and source
+  for (int f = 0; f < F_NSTATE && !e; ++f)
+    for (int l = 0; l < 2 && !e; ++l) e = hipMemsetAsync(c->fld[f][l], 0, 8 * Pg, c->stream);
+  for (int s = 0; s < PFD_NSRC && !e; ++s) e = hipMemsetAsync(c->src[s], 0, 8 * Pg, c->stream);
+  if (!e) e = hipMemsetAsync(zero, 0, 8 * Pg, c->stream);
+  if (!e) e = hipMemsetAsync(c->d_status, 0, 64, c->stream);
+  if (!e) e = hipStreamSynchronize(c->stream);
+  if (e) { g_create_err = std::string("HIP error in create: ") + hipGetErrorString(e); delete c; return PFD_EHIP; }
+
+  Geo& g = c->geo;
+  g.K = K; g.n = K + 1; g.nq = c->nq; g.nx = m.nx; g.ny = m.ny; g.Nx = c->Nx; g.Ny = c->Ny;
+  g.periodic = per ? 1 : 0; g.planes = c->planes; g.Ng = c->Ng; g.Nl = c->Nl;
+  g.hx = c->d_hx; g.hy = c->d_hy; g.w = c->d_w; g.D = c->d_D;
+  for (int s = 0; s < 4; ++s) {
+    g.bm_side[s] = c->bm_side[s];
+    g.side_type[s] = (per && s >= PFD_LEFT) ? -1 : bc.side_type[s];
+  }
+  c->zero_buf = zero;
+  *out = c;
+  return PFD_OK;
+}
+
+extern "C" void pfd_destroy(pfd_ctx* c) { delete c; }
+
+extern "C" pfd_status pfd_get_dims(const pfd_ctx* c, int* Nx, int* Ny, int* planes) {
+  if (!c) return PFD_EINVAL;
+  if (Nx) *Nx = c->Nx;
+  if (Ny) *Ny = c->Ny;
+  if (planes) *planes = c->planes;
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_get_coords(const pfd_ctx* c, double* x, double* y, double* z) {
+  if (!c) return PFD_EINVAL;
+  const Dir1D& DX = c->dirs[c->fam[0].ix];
+  const Dir1D& DY = c->dirs[c->fam[0].iy];
+  if (x) std::memcpy(x, DX.coord.data(), sizeof(double) * c->Nx);
+  if (y) std::memcpy(y, DY.coord.data(), sizeof(double) * c->Ny);
+  if (z)
+    for (int p = 0; p < c->planes; ++p)
+      z[p] = c->is3d ? p * c->prob.mesh.lz / c->prob.mesh.nz : 0.0;
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_get_diag(pfd_ctx* c, pfd_diag* d) {
+  if (!c || !d) return PFD_EINVAL;
+  const Par& P = c->par;
+  double v[10] = {P.gamma0, P.S, P.alpha, P.c_psi, P.c_phi, P.eps0, P.rho0, P.nu_m, P.c_u, 0.0};
+  std::memcpy(d->derived, v, sizeof(v));
+  int st = 0;
+  hipError_t e = hipMemcpyAsync(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (!e) e = hipStreamSynchronize(c->stream);
+  if (e) { c->err = hipGetErrorString(e); return PFD_EHIP; }
+  d->nonfinite = st & 1;
+  d->last_residual = c->last_residual;
+  d->steps = c->steps;
+  return PFD_OK;
+}
+
+static double* field_ptr(pfd_ctx* c, int f, int level) {
+  if (f < 0 || f >= PFD_NFIELDS) return nullptr;
+  const bool two = (f <= PFD_V);
+  if (level != 0 && !(two && level == -1)) return nullptr;
+  if (f >= PFD_EX) return c->fld[f][0];
+  return c->fld[f][level == 0 ? c->cur : 1 - c->cur];
+}
+
+extern "C" pfd_status pfd_set_field(pfd_ctx* c, int f, int level, const double* src, int on_device) {
+  if (!c || !src) return PFD_EINVAL;
+  double* dst = field_ptr(c, f, level);
+  if (!dst) { c->err = "bad field or level"; return PFD_EINVAL; }
+  const size_t bytes = sizeof(double) * c->planes * c->Ng;
+  hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, k, c->stream));
+  if (level == 0 && f <= PFD_V) {
+    double* old = field_ptr(c, f, -1);
+    HIPCHK(hipMemcpyAsync(old, src, bytes, k, c->stream));
+  }
+  if (!on_device) HIPCHK(hipStreamSynchronize(c->stream));
+  c->failed = 0;
+  c->steps = 0;
+  HIPCHK(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_get_field(pfd_ctx* c, int f, int level, double* dst, int on_device) {
+  if (!c || !dst) return PFD_EINVAL;
+  double* src = field_ptr(c, f, level);
+  if (!src) { c->err = "bad field or level"; return PFD_EINVAL; }
+  const size_t bytes = sizeof(double) * c->planes * c->Ng;
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  if (!on_device) HIPCHK(hipStreamSynchronize(c->stream));
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_set_source(pfd_ctx* c, int s, const double* src, int on_device) {
+  if (!c || s < 0 || s >= PFD_NSRC) return PFD_EINVAL;
+  const size_t bytes = sizeof(double) * c->planes * c->Ng;
+  if (!src) {
+    HIPCHK(hipMemsetAsync(c->src[s], 0, bytes, c->stream));
+  } else {
+    HIPCHK(hipMemcpyAsync(c->src[s], src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          c->stream));
+    if (!on_device) HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_init_potential(pfd_ctx* c, double tol, int max_iter, int* iters) {
+  if (!c) return PFD_EINVAL;
+  if (max_iter < 1) { c->err = "max_iter must be >= 1"; return PFD_EINVAL; }
+  double* A = c->fld[F_V][c->cur];
+  double* B = c->fld[F_V][1 - c->cur];
+  int it = 0;
+  bool conv = false;
+  for (it = 1; it <= max_iter; ++it) {
+    HIPCHK(potential_iteration(c, A, B));
+    double h[2];
+    HIPCHK(max_abs_diff(c, A, B, h));
+    std::swap(A, B);  // A = newest
+    if (!std::isfinite(h[0])) { c->err = "non-finite potential"; return PFD_ENONFINITE; }
+    if (h[0] <= tol * std::max(1.0, h[1])) { conv = true; break; }
+  }
+  if (it > max_iter) it = max_iter;
+  const size_t bytes = sizeof(double) * c->planes * c->Ng;
+  double* cur = c->fld[F_V][c->cur];
+  if (A != cur) HIPCHK(hipMemcpyAsync(cur, A, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->fld[F_V][1 - c->cur], cur, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(update_E(c));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (iters) *iters = it;
+  if (!conv) { c->err = "potential fixed point did not converge"; return PFD_ENOCONV; }
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_step_async(pfd_ctx* c, int nsteps, int equilibrium) {
+  if (!c || nsteps < 0) return PFD_EINVAL;
+  if (c->failed) { c->err = "context failed earlier; set the fields again"; return PFD_ESTATE; }
+  for (int i = 0; i < nsteps; ++i) HIPCHK(step_once(c, equilibrium));
+  c->steps += nsteps;
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_step(pfd_ctx* c, int nsteps, int equilibrium) {
+  pfd_status s = pfd_step_async(c, nsteps, equilibrium);
+  if (s != PFD_OK) return s;
+  int st = 0;
+  HIPCHK(hipMemcpyAsync(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (st & 1) {
+    c->failed = 1;
+    c->err = "non-finite value in the state";
+    return PFD_ENONFINITE;
+  }
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_solve(pfd_ctx* c, int fam, const double* b, double* x) {
+  if (!c || !b || !x || fam < 0 || fam > 4) return PFD_EINVAL;
+  HIPCHK(solve(c, fam, b, x, 1));
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_apply(pfd_ctx* c, int fam, const double* x, double* y) {
+  if (!c || !x || !y || fam < 0 || fam > 4) return PFD_EINVAL;
+  HIPCHK(apply(c, fam, x, y, 1));
+  return PFD_OK;
+}

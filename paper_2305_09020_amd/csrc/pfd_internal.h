@@ -1,0 +1,110 @@
+// Internal layout of a pfd context (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/pfd.h"
+
+#define PFD_KMAX 16
+#define PFD_NMAX 320  // max nodes per direction handled by the solve kernels
+
+namespace pfd {
+
+// One direction x one boundary-condition combination of the 1D operators.
+struct Dir1D {
+  int N = 0, nfree = 0;
+  bool periodic = false;
+  bool singular = false;            // no Dirichlet end: constants in the kernel
+  std::vector<double> K1, M1, S, lam, coord;
+  std::vector<char> dir;            // Dirichlet flag per node
+  // device copies
+  double *dS = nullptr, *dST = nullptr, *dlam = nullptr, *dK1 = nullptr, *dM1 = nullptr;
+  float *fS = nullptr, *fST = nullptr;
+  unsigned char* ddir = nullptr;
+};
+
+struct Family {
+  int ix = 0, iy = 0;               // indices into ctx dirs (x and y)
+  double shift = 0.0;               // c_f (plus beta_p^2 per plane)
+  double* dshift = nullptr;         // per-plane total shift (device)
+  std::vector<double> hshift;       // per-plane total shift (host)
+  bool any_singular = false;        // some plane has a singular operator
+};
+
+// geometry passed to element / nodal kernels by value
+struct Geo {
+  int K, n, nq, nx, ny, Nx, Ny, periodic, planes;
+  long Ng, Nl;
+  const double *hx, *hy, *w, *D;    // device
+  const double *bm_side[4];         // per-side boundary mass (device, Ng)
+  int side_type[4];                 // WALL/OPEN/-1 (absent, periodic)
+};
+
+// scalar parameters passed to kernels by value
+struct Par {
+  double rho1, rho2, mu1, mu2, eps1, eps2, lam, eta, gamma1, dt;
+  double gamma0, S, alpha, c_psi, c_phi, eps0, rho0, nu_m, c_u;
+  double cos_theta;
+  double cs_n, cs_o, ch_n, ch_o;    // xi* = cs_n xi^n + cs_o xi^{n-1}; xi^ likewise
+};
+
+enum { F_UX = 0, F_UY, F_UZ, F_P, F_PHI, F_PSI, F_V, F_EX, F_EY, F_EZ, F_E2, F_NSTATE };
+
+}  // namespace pfd
+
+struct pfd_ctx {
+  pfd_problem prob;
+  std::string err;
+  hipStream_t stream = nullptr;
+  int Nx = 0, Ny = 0, planes = 0, is3d = 0;
+  long Ng = 0, Nl = 0;
+  int K = 0, n = 0, nq = 0;
+  pfd::Par par{};
+  pfd::Geo geo{};
+  std::vector<double> xi, w, D;            // GLL rule
+  std::vector<pfd::Dir1D> dirs;            // distinct 1D operators
+  pfd::Family fam[5];
+  std::vector<double> beta2, betad;        // per plane (spectral packing in 3D)
+  double *d_beta2 = nullptr, *d_betad = nullptr;
+  // device buffers
+  char* ws = nullptr;
+  size_t ws_bytes = 0, ws_used = 0;
+  double* fld[pfd::F_NSTATE][2] = {};     // state fields, two time levels
+  int cur = 0;                             // index of level n
+  int set_old[pfd::F_NSTATE] = {};         // level n-1 explicitly set
+  double* src[PFD_NSRC] = {};
+  double *Lb[3] = {}, *b[3] = {}, *r = nullptr, *U = nullptr, *Q2 = nullptr;
+  double* tmp = nullptr;                   // solve intermediate (double or float)
+  double* zero_buf = nullptr;              // planes*Ng zeros (u = 0 of the equilibrium system)
+  double *bm_side[4] = {}, *bm_open = nullptr, *bm_wall = nullptr, *Mdiag = nullptr;
+  double *d_hx = nullptr, *d_hy = nullptr, *d_w = nullptr, *d_D = nullptr;
+  int* d_status = nullptr;                 // [0] nonfinite flag
+  double* d_norms = nullptr;               // per plane: ||r||^2, ||b||^2 (diagnostics)
+  double* d_red = nullptr;                 // reduction scratch (planes)
+  long steps = 0;
+  int failed = 0;
+  int check_residual = 0;
+  double last_residual = 0.0;
+};
+
+namespace pfd {
+// set-up (pfd_setup.cpp)
+void sym_eig(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V);
+void gll_rule(int K, std::vector<double>& x, std::vector<double>& w, std::vector<double>& D);
+void build_dir1d(Dir1D& d, int ne, const double* bp, int K, bool periodic, bool dir_lo, bool dir_hi,
+                 const std::vector<double>& xi, const std::vector<double>& w,
+                 const std::vector<double>& D);
+
+// kernels (pfd_kernels.hip); all enqueue on ctx->stream
+hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp);
+hipError_t apply(pfd_ctx* c, int fam, const double* x, double* y, int ncomp);
+hipError_t step_once(pfd_ctx* c, int equilibrium);
+hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout);
+hipError_t update_E(pfd_ctx* c);
+hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* out_host2);
+}  // namespace pfd

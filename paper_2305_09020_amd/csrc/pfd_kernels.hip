@@ -1,0 +1,840 @@
+// HIP kernels for one time step of the decoupled scheme (Algorithm 1 / 2) on gfx950.
+//
+// Data layout (HBM): every nodal field is FP64, value[(p*Ny + iy)*Nx + ix];
+// element-local work buffers are value[(p*ne + e)*nq + b*(K+1) + a] with
+// e = ey*nx + ex.
+//
+// Kernel families
+//  * element kernels (one work-group per (element, plane)): gather nodal
+//    values into LDS, tensor-product (sum-factorised) derivatives with the GLL
+//    differentiation matrix, pointwise terms at the GLL quadrature points,
+//    and the transposed ("weak divergence") contraction, written to an
+//    element-local buffer;
+//  * nodal kernels (one thread per node): direct-stiffness summation of the
+//    element-local buffers in a fixed order (deterministic, no atomics), plus
+//    nodal source and boundary terms;
+//  * solve kernels: FP64 residual with the assembled 1D operators, and the two
+//    fast-diagonalisation passes  T = (Sy^T R Sx) ./ (ly_i + lx_j + c_p)  and
+//    X += Sy T Sx^T, each a chain of two LDS-staged GEMMs per (plane, column
+//    block), templated on the compute type (double / float).
+#include <cmath>
+#include <vector>
+
+#include "pfd_internal.h"
+
+namespace pfd {
+
+#define WG 256
+
+__device__ __forceinline__ int gidx(const Geo& g, int ex, int ey, int a, int b) {
+  int ix = ex * g.K + a;
+  if (g.periodic && ix == g.Nx) ix = 0;
+  return (ey * g.K + b) * g.Nx + ix;
+}
+
+// ------------------------------------------------------------------ mixture laws
+__device__ __forceinline__ double eps_of(const Par& P, double p) {
+  return 0.5 * (P.eps1 + P.eps2) + 0.25 * (P.eps1 - P.eps2) * p * (3.0 - p * p);
+}
+__device__ __forceinline__ double deps_of(const Par& P, double p) {
+  return 0.75 * (P.eps2 - P.eps1) * (p * p - 1.0);
+}
+__device__ __forceinline__ double h_of(const Par& P, double p) {
+  return p * (p * p - 1.0) / (P.eta * P.eta);
+}
+// Theta'(phi)/lambda with lambda = 3 sigma eta / (2 sqrt 2)
+__device__ __forceinline__ double thp_of(const Par& P, double p) {
+  return P.cos_theta * (p * p - 1.0) * (0.70710678118654752440 / P.eta);
+}
+
+// ---------------------------------------------------------------- element helpers
+// shared element context: D and w in LDS, geometry of this element
+struct ElemLDS {
+  double D[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  double w[PFD_KMAX + 1];
+};
+
+__device__ __forceinline__ void load_gll(const Geo& g, ElemLDS& s) {
+  for (int i = threadIdx.x; i < g.nq; i += blockDim.x) s.D[i] = g.D[i];
+  for (int i = threadIdx.x; i < g.n; i += blockDim.x) s.w[i] = g.w[i];
+}
+
+// d/dx at local (a,b) of an LDS element array f[b*n + p]
+__device__ __forceinline__ double ddx(const ElemLDS& s, int n, int a, int b, const double* f, double sx) {
+  double acc = 0.0;
+  for (int p = 0; p < n; ++p) acc += s.D[a * n + p] * f[b * n + p];
+  return sx * acc;
+}
+__device__ __forceinline__ double ddy(const ElemLDS& s, int n, int a, int b, const double* f, double sy) {
+  double acc = 0.0;
+  for (int p = 0; p < n; ++p) acc += s.D[b * n + p] * f[p * n + a];
+  return sy * acc;
+}
+// x-part of the weak divergence: sum_p D[p][a] gx[b*n+p]  (gx pre-multiplied by w_p)
+__device__ __forceinline__ double wdx(const ElemLDS& s, int n, int a, int b, const double* gx) {
+  double acc = 0.0;
+  for (int p = 0; p < n; ++p) acc += s.D[p * n + a] * gx[b * n + p];
+  return acc;
+}
+__device__ __forceinline__ double wdy(const ElemLDS& s, int n, int a, int b, const double* gy) {
+  double acc = 0.0;
+  for (int p = 0; p < n; ++p) acc += s.D[p * n + b] * gy[p * n + a];
+  return acc;
+}
+
+#define ELEM_PROLOGUE                                                    \
+  const int e = blockIdx.x, pl = blockIdx.y;                             \
+  const int ex = e % g.nx, ey = e / g.nx;                                \
+  const int n = g.n, t = threadIdx.x;                                    \
+  const bool act = t < g.nq;                                             \
+  const int a = act ? t % n : 0, b = act ? t / n : 0;                    \
+  const double hx = g.hx[ex], hy = g.hy[ey];                             \
+  const double sx = 2.0 / hx, sy = 2.0 / hy;                             \
+  const long pofs = (long)pl * g.Ng;                                     \
+  const int gi = gidx(g, ex, ey, a, b);                                  \
+  const long lofs = ((long)pl * g.nx * g.ny + e) * g.nq + t;             \
+  __shared__ ElemLDS s;                                                  \
+  load_gll(g, s);
+
+// ------------------------------------------------------------------ DSS (gather-sum)
+// sum of the element-local contributions at global node (ix, iy) of plane pl
+__device__ __forceinline__ double dss(const Geo& g, const double* L, int pl, int ix, int iy) {
+  int exs[2], as[2], nxe = 0;
+  int eys[2], bs[2], nye = 0;
+  const int K = g.K;
+  if (g.periodic) {
+    if (ix % K == 0) {
+      int ex = ix / K;
+      exs[nxe] = (ex == 0) ? g.nx - 1 : ex - 1; as[nxe++] = K;
+      exs[nxe] = ex; as[nxe++] = 0;
+    } else {
+      exs[nxe] = ix / K; as[nxe++] = ix % K;
+    }
+  } else {
+    if (ix % K == 0) {
+      int ex = ix / K;
+      if (ex > 0) { exs[nxe] = ex - 1; as[nxe++] = K; }
+      if (ex < g.nx) { exs[nxe] = ex; as[nxe++] = 0; }
+    } else {
+      exs[nxe] = ix / K; as[nxe++] = ix % K;
+    }
+  }
+  if (iy % K == 0) {
+    int ey = iy / K;
+    if (ey > 0) { eys[nye] = ey - 1; bs[nye++] = K; }
+    if (ey < g.ny) { eys[nye] = ey; bs[nye++] = 0; }
+  } else {
+    eys[nye] = iy / K; bs[nye++] = iy % K;
+  }
+  double acc = 0.0;
+  const long base = (long)pl * g.nx * g.ny;
+  for (int j = 0; j < nye; ++j)
+    for (int i = 0; i < nxe; ++i) {
+      long e = base + eys[j] * g.nx + exs[i];
+      acc += L[e * g.nq + bs[j] * g.n + as[i]];
+    }
+  return acc;
+}
+
+#define NODAL_PROLOGUE                                                   \
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;           \
+  if (id >= (long)g.planes * g.Ng) return;                               \
+  const int pl = (int)(id / g.Ng);                                       \
+  const int node = (int)(id - (long)pl * g.Ng);                          \
+  const int iy = node / g.Nx, ix = node - iy * g.Nx;                     \
+  (void)pl;
+
+// =================================================================== stage V (eq. 54)
+// L0 = -int (eps(phi*) - eps0) grad V* . grad e   (element-local)
+__global__ void __launch_bounds__(WG) k_V_elem(Geo g, Par P, const double* phn, const double* pho,
+                                               const double* Vn, const double* Vo, double* L0) {
+  ELEM_PROLOGUE
+  __shared__ double sV[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sgx[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sgy[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  double phs = 0.0;
+  if (act) {
+    sV[t] = P.cs_n * Vn[pofs + gi] + P.cs_o * Vo[pofs + gi];
+    phs = P.cs_n * phn[pofs + gi] + P.cs_o * pho[pofs + gi];
+  }
+  __syncthreads();
+  if (act) {
+    double r = eps_of(P, phs) - P.eps0;
+    sgx[t] = s.w[a] * r * ddx(s, n, a, b, sV, sx);
+    sgy[t] = s.w[b] * r * ddy(s, n, a, b, sV, sy);
+  }
+  __syncthreads();
+  if (act) L0[lofs] = -(0.5 * hy * s.w[b] * wdx(s, n, a, b, sgx) + 0.5 * hx * s.w[a] * wdy(s, n, a, b, sgy));
+}
+
+// b = (DSS(L0) - M f_V)/eps0 ; x0 = V* with Dirichlet values from VD
+__global__ void k_V_rhs(Geo g, Par P, const double* L0, const double* Mdiag, const double* fV,
+                        const double* Vn, const double* Vo, const double* Vd,
+                        const unsigned char* dirx, const unsigned char* diry, double* bb, double* x0) {
+  NODAL_PROLOGUE
+  double v = dss(g, L0, pl, ix, iy) - Mdiag[node] * fV[id];
+  bb[id] = v / P.eps0;
+  bool d = dirx[ix] || diry[iy];
+  x0[id] = d ? Vd[id] : P.cs_n * Vn[id] + P.cs_o * Vo[id];
+}
+
+// =================================================================== stage E (eq. 55)
+__global__ void __launch_bounds__(WG) k_E_elem(Geo g, const double* V, double* L0, double* L1) {
+  ELEM_PROLOGUE
+  __shared__ double sV[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  if (act) sV[t] = V[pofs + gi];
+  __syncthreads();
+  if (act) {
+    double wq = 0.25 * hx * hy * s.w[a] * s.w[b];
+    L0[lofs] = wq * ddx(s, n, a, b, sV, sx);
+    L1[lofs] = wq * ddy(s, n, a, b, sV, sy);
+  }
+}
+
+__global__ void k_E_nodal(Geo g, const double* L0, const double* L1, const double* Mdiag,
+                          const double* Ez, double* Ex, double* Ey, double* E2) {
+  NODAL_PROLOGUE
+  double m = Mdiag[node];
+  double ex = dss(g, L0, pl, ix, iy) / m, ey = dss(g, L1, pl, ix, iy) / m;
+  Ex[id] = ex;
+  Ey[id] = ey;
+  double ez = Ez ? Ez[id] : 0.0;
+  E2[id] = ex * ex + ey * ey + ez * ez;
+}
+
+// =================================================================== stage psi (eq. 56)
+// L0 = -int Q1 w + int grad Q2 . grad w ;  Q2 also written (nodal, same at shared nodes)
+__global__ void __launch_bounds__(WG) k_psi_elem(Geo g, Par P, const double* phn, const double* pho,
+                                                 const double* uxn, const double* uxo, const double* uyn,
+                                                 const double* uyo, const double* E2, const double* gsrc,
+                                                 double* L0) {
+  ELEM_PROLOGUE
+  __shared__ double sph[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sQ2[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sgx[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sgy[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  double phh = 0.0, uxs = 0.0, uys = 0.0, gg = 0.0;
+  if (act) {
+    double pn = phn[pofs + gi], po = pho[pofs + gi];
+    double phs = P.cs_n * pn + P.cs_o * po;
+    phh = P.ch_n * pn + P.ch_o * po;
+    sph[t] = phs;
+    sQ2[t] = h_of(P, phs) - P.S / (P.eta * P.eta) * phs - deps_of(P, phs) * E2[pofs + gi] / (2.0 * P.lam);
+    uxs = P.cs_n * uxn[pofs + gi] + P.cs_o * uxo[pofs + gi];
+    uys = P.cs_n * uyn[pofs + gi] + P.cs_o * uyo[pofs + gi];
+    gg = gsrc[pofs + gi];
+  }
+  __syncthreads();
+  double q1 = 0.0;
+  if (act) {
+    double adv = uxs * ddx(s, n, a, b, sph, sx) + uys * ddy(s, n, a, b, sph, sy);
+    q1 = (gg - adv + phh / P.dt) / (P.lam * P.gamma1);
+    sgx[t] = s.w[a] * ddx(s, n, a, b, sQ2, sx);
+    sgy[t] = s.w[b] * ddy(s, n, a, b, sQ2, sy);
+  }
+  __syncthreads();
+  if (act) {
+    double wq = 0.25 * hx * hy * s.w[a] * s.w[b];
+    L0[lofs] = -wq * q1 + 0.5 * hy * s.w[b] * wdx(s, n, a, b, sgx) + 0.5 * hx * s.w[a] * wdy(s, n, a, b, sgy);
+  }
+}
+
+// b_psi = DSS(L0) + Bo (g1 + c_psi g2) + Bs (g1 + c_psi U);  U = -g3 - Theta'(phi*)/lambda
+// also stores U (reused by the phi stage) and x0 = psi*
+__global__ void k_psi_rhs(Geo g, Par P, const double* L0, const double* bmo, const double* bmw,
+                          const double* g1, const double* g2, const double* g3, const double* phn,
+                          const double* pho, const double* psn, const double* pso, const double* E2,
+                          double* bb, double* U, double* Q2, double* x0) {
+  NODAL_PROLOGUE
+  double phs = P.cs_n * phn[id] + P.cs_o * pho[id];
+  double u = -g3[id] - thp_of(P, phs);
+  U[id] = u;
+  Q2[id] = h_of(P, phs) - P.S / (P.eta * P.eta) * phs - deps_of(P, phs) * E2[id] / (2.0 * P.lam);
+  bb[id] = dss(g, L0, pl, ix, iy) + bmo[node] * (g1[id] + P.c_psi * g2[id]) +
+           bmw[node] * (g1[id] + P.c_psi * u);
+  x0[id] = P.cs_n * psn[id] + P.cs_o * pso[id];
+}
+
+// =================================================================== stage phi (eq. 57)
+__global__ void k_phi_rhs(Geo g, Par P, const double* Mdiag, const double* psi, const double* bmo,
+                          const double* bmw, const double* g2, const double* U, const double* phn,
+                          const double* pho, double* bb, double* x0) {
+  NODAL_PROLOGUE
+  bb[id] = -Mdiag[node] * psi[id] + bmo[node] * g2[id] + bmw[node] * U[id];
+  x0[id] = P.cs_n * phn[id] + P.cs_o * pho[id];
+}
+
+// =================================================================== momentum terms (eq. 49)
+// L0 = rho0 int G.grad q - rho0 int_dOmega (mu/rho) (n x w*).grad q   (pressure, eq. 58a)
+// L1, L2 = (1/nu_m)[int G v -+ int K x grad v] - (1/nu_m) int_open L v (velocity, eq. 59a;
+//          the -grad P^{n+1}/rho0 part is added after the pressure solve)
+__global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi, const double* psi,
+                                                 const double* E2, const double* Q2,
+                                                 const double* uxn, const double* uxo, const double* uyn,
+                                                 const double* uyo, const double* Pn, const double* Po,
+                                                 const double* fx, const double* fy, double* L0,
+                                                 double* L1, double* L2) {
+  ELEM_PROLOGUE
+  __shared__ double sph[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sPhi[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sux[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double suy[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sP[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sgx[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sgy[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sK[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sf[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  double ph = 0.0, ps = 0.0, e2 = 0.0, uhx = 0.0, uhy = 0.0, ffx = 0.0, ffy = 0.0;
+  if (act) {
+    const long id = pofs + gi;
+    ph = phi[id];
+    ps = psi[id];
+    e2 = E2[id];
+    sph[t] = ph;
+    sPhi[t] = ps - P.c_psi * ph - Q2[id];
+    double un = uxn[id], uo = uxo[id];
+    sux[t] = P.cs_n * un + P.cs_o * uo;
+    uhx = P.ch_n * un + P.ch_o * uo;
+    un = uyn[id]; uo = uyo[id];
+    suy[t] = P.cs_n * un + P.cs_o * uo;
+    uhy = P.ch_n * un + P.ch_o * uo;
+    sP[t] = P.cs_n * Pn[id] + P.cs_o * Po[id];
+    ffx = fx[id];
+    ffy = fy[id];
+  }
+  __syncthreads();
+  double Gx = 0.0, Gy = 0.0, Kv = 0.0;
+  if (act) {
+    const double pc = fmin(1.0, fmax(-1.0, ph));
+    const double rho = 0.5 * (P.rho1 + P.rho2) + 0.5 * (P.rho1 - P.rho2) * pc;
+    const double mu = 0.5 * (P.mu1 + P.mu2) + 0.5 * (P.mu1 - P.mu2) * pc;
+    const double dpx = ddx(s, n, a, b, sph, sx), dpy = ddy(s, n, a, b, sph, sy);
+    const double drr = 0.5 * (P.rho1 - P.rho2), dmm = 0.5 * (P.mu1 - P.mu2);
+    const double irho = 1.0 / rho;
+    const double gnx = (rho * dmm - mu * drr) * dpx * irho * irho;
+    const double gny = (rho * dmm - mu * drr) * dpy * irho * irho;
+    const double jc = 0.5 * (P.rho1 - P.rho2) * P.lam * P.gamma1;
+    const double Jx = jc * ddx(s, n, a, b, sPhi, sx), Jy = jc * ddy(s, n, a, b, sPhi, sy);
+    const double ux = sux[t], uy = suy[t];
+    const double uxx = ddx(s, n, a, b, sux, sx), uxy = ddy(s, n, a, b, sux, sy);  // d_x ux, d_y ux
+    const double uyx = ddx(s, n, a, b, suy, sx), uyy = ddy(s, n, a, b, suy, sy);  // d_x uy, d_y uy
+    const double om = uyx - uxy;
+    const double dmx = dmm * dpx, dmy = dmm * dpy;
+    const double gmDx = dmx * 2.0 * uxx + dmy * (uxy + uyx);
+    const double gmDy = dmx * (uyx + uxy) + dmy * 2.0 * uyy;
+    const double Nx_ = ux * uxx + uy * uxy, Ny_ = ux * uyx + uy * uyy;
+    const double JUx = Jx * uxx + Jy * uxy, JUy = Jx * uyx + Jy * uyy;
+    const double lap = ps - P.alpha * ph;
+    const double dep = deps_of(P, ph);
+    const double gPx = ddx(s, n, a, b, sP, sx), gPy = ddy(s, n, a, b, sP, sy);
+    const double cP = 1.0 / P.rho0 - irho;
+    const double Tx = (ffx - P.lam * lap * dpx - 0.5 * dep * e2 * dpx + gmDx - JUx) * irho + uhx / P.dt - Nx_ + cP * gPx;
+    const double Ty = (ffy - P.lam * lap * dpy - 0.5 * dep * e2 * dpy + gmDy - JUy) * irho + uhy / P.dt - Ny_ + cP * gPy;
+    Gx = Tx + gny * om;
+    Gy = Ty - gnx * om;
+    const double mr = mu * irho;
+    Kv = (mr - P.nu_m) * om;
+    sgx[t] = s.w[a] * Gx;
+    sgy[t] = s.w[b] * Gy;
+    sK[t] = Kv;
+    sf[t] = mr * om;
+  }
+  __syncthreads();
+  if (act) {
+    const double wq = 0.25 * hx * hy * s.w[a] * s.w[b];
+    double l0 = P.rho0 * (0.5 * hy * s.w[b] * wdx(s, n, a, b, sgx) + 0.5 * hx * s.w[a] * wdy(s, n, a, b, sgy));
+    // weak-div pieces of K: y-part (for u_x) and x-part (for u_y), K pre-multiplied by w_p
+    double kyp = 0.0, kxp = 0.0;
+    for (int p = 0; p < n; ++p) {
+      kyp += s.D[p * n + b] * s.w[p] * sK[p * n + a];
+      kxp += s.D[p * n + a] * s.w[p] * sK[b * n + p];
+    }
+    double l1 = wq * Gx + 0.5 * hx * s.w[a] * kyp;
+    double l2 = wq * Gy - 0.5 * hy * s.w[b] * kxp;
+    // boundary edges: tangential term of eq. (58a) on every side; L term of eq. (59a) on open sides
+    const int K = g.K;
+    if (ey == 0 && b == 0) {  // bottom, n = (0,-1)
+      double acc = 0.0;
+      for (int p = 0; p < n; ++p) acc += s.w[p] * sf[p] * s.D[p * n + a];
+      l0 += P.rho0 * acc;
+      if (g.side_type[PFD_BOTTOM] == PFD_OPEN) l1 += 0.5 * hx * s.w[a] * Kv;
+    }
+    if (ey == g.ny - 1 && b == K) {  // top, n = (0,1)
+      double acc = 0.0;
+      for (int p = 0; p < n; ++p) acc += s.w[p] * sf[K * n + p] * s.D[p * n + a];
+      l0 -= P.rho0 * acc;
+      if (g.side_type[PFD_TOP] == PFD_OPEN) l1 -= 0.5 * hx * s.w[a] * Kv;
+    }
+    if (!g.periodic && ex == 0 && a == 0) {  // left, n = (-1,0)
+      double acc = 0.0;
+      for (int p = 0; p < n; ++p) acc += s.w[p] * sf[p * n] * s.D[p * n + b];
+      l0 -= P.rho0 * acc;
+      if (g.side_type[PFD_LEFT] == PFD_OPEN) l2 -= 0.5 * hy * s.w[b] * Kv;
+    }
+    if (!g.periodic && ex == g.nx - 1 && a == K) {  // right, n = (1,0)
+      double acc = 0.0;
+      for (int p = 0; p < n; ++p) acc += s.w[p] * sf[p * n + K] * s.D[p * n + b];
+      l0 += P.rho0 * acc;
+      if (g.side_type[PFD_RIGHT] == PFD_OPEN) l2 += 0.5 * hy * s.w[b] * Kv;
+    }
+    L0[lofs] = l0;
+    L1[lofs] = l1 / P.nu_m;
+    L2[lofs] = l2 / P.nu_m;
+  }
+}
+
+// b_P = DSS(L0) - rho0 gamma0/dt sum_walls int (n.w) q ;  x0 = P* (f2 on open sides)
+__global__ void k_P_rhs(Geo g, Par P, const double* L0, const double* wx, const double* wy,
+                        const double* Pn, const double* Po, const double* f2,
+                        const unsigned char* dirx, const unsigned char* diry, double* bb, double* x0) {
+  NODAL_PROLOGUE
+  double v = dss(g, L0, pl, ix, iy);
+  const double c = P.rho0 * P.gamma0 / P.dt;
+  const double nw[4] = {-wy[id], wy[id], -wx[id], wx[id]};  // n.w for bottom, top, left, right
+  for (int sd = 0; sd < 4; ++sd)
+    if (g.side_type[sd] == PFD_WALL) v -= c * g.bm_side[sd][node] * nw[sd];
+  bb[id] = v;
+  bool d = dirx[ix] || diry[iy];
+  x0[id] = d ? f2[id] : P.cs_n * Pn[id] + P.cs_o * Po[id];
+}
+
+// u right side: add -(1/(nu_m rho0)) int grad P^{n+1} v to L1, L2
+__global__ void __launch_bounds__(WG) k_gradP_elem(Geo g, Par P, const double* Pnew, double* L1, double* L2) {
+  ELEM_PROLOGUE
+  __shared__ double sP[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  if (act) sP[t] = Pnew[pofs + gi];
+  __syncthreads();
+  if (act) {
+    const double c = -0.25 * hx * hy * s.w[a] * s.w[b] / (P.nu_m * P.rho0);
+    L1[lofs] += c * ddx(s, n, a, b, sP, sx);
+    L2[lofs] += c * ddy(s, n, a, b, sP, sy);
+  }
+}
+
+// b_u = DSS(L) + Bo f1 ; x0 = u* with w on walls (two components)
+__global__ void k_u_rhs(Geo g, Par P, const double* L1, const double* L2, const double* bmo,
+                        const double* f1x, const double* f1y, const double* uxn, const double* uxo,
+                        const double* uyn, const double* uyo, const double* wx, const double* wy,
+                        const unsigned char* dirx, const unsigned char* diry, double* bx, double* by,
+                        double* x0x, double* x0y) {
+  NODAL_PROLOGUE
+  bx[id] = dss(g, L1, pl, ix, iy) + bmo[node] * f1x[id];
+  by[id] = dss(g, L2, pl, ix, iy) + bmo[node] * f1y[id];
+  bool d = dirx[ix] || diry[iy];
+  x0x[id] = d ? wx[id] : P.cs_n * uxn[id] + P.cs_o * uxo[id];
+  x0y[id] = d ? wy[id] : P.cs_n * uyn[id] + P.cs_o * uyo[id];
+}
+
+// non-finite guard on a field: sets status[0]
+__global__ void k_check_finite(long N, const double* f, int* status) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  for (; i < N; i += (long)gridDim.x * blockDim.x)
+    if (!isfinite(f[i])) bad = true;
+  if (bad) atomicOr(status, 1);
+}
+
+// =================================================================== solves
+// r = b - (Kx (x) My + Mx (x) Ky + c_p Mx (x) My) x on free nodes, 0 on Dirichlet nodes.
+// With b == nullptr and sign = -1 it computes y = A x on every node (apply).
+__global__ void k_residual(int Nx, int Ny, int planes, int K, int perx, const double* Kx, const double* Mx,
+                           const unsigned char* dirx, const double* Ky, const double* My,
+                           const unsigned char* diry, const double* shift, const double* bb,
+                           const double* x, double* r, int apply_only, double* norms) {
+  const long Ng = (long)Nx * Ny;
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double rr = 0.0, b2 = 0.0;
+  int pl = 0;
+  if (id < planes * Ng) {
+    pl = (int)(id / Ng);
+    const int node = (int)(id - pl * Ng);
+    const int iy = node / Nx, ix = node - iy * Nx;
+    const double* xp = x + pl * Ng;
+    double ax = 0.0, ay = 0.0;
+    // with periodic x and two elements (Nx = 2K) the offsets -K and +K reach the same node
+    const int dhi = (perx && Nx == 2 * K) ? K - 1 : K;
+    for (int d = -K; d <= dhi; ++d) {
+      int j = ix + d;
+      if (perx) { j = (j + Nx) % Nx; } else if (j < 0 || j >= Nx) continue;
+      ax += Kx[(long)ix * Nx + j] * xp[(long)iy * Nx + j];
+    }
+    for (int d = -K; d <= K; ++d) {
+      int j = iy + d;
+      if (j < 0 || j >= Ny) continue;
+      ay += Ky[(long)iy * Ny + j] * xp[(long)j * Nx + ix];
+    }
+    const double xv = xp[node];
+    const double Av = ax * My[iy] + Mx[ix] * ay + shift[pl] * Mx[ix] * My[iy] * xv;
+    if (apply_only) {
+      r[id] = Av;
+    } else {
+      const bool d = dirx[ix] || diry[iy];
+      const double v = d ? 0.0 : bb[id] - Av;
+      r[id] = v;
+      rr = v * v;
+      b2 = d ? 0.0 : bb[id] * bb[id];
+    }
+  }
+  if (norms && id < planes * Ng) {  // diagnostics only
+    atomicAdd(&norms[2 * pl], rr);
+    atomicAdd(&norms[2 * pl + 1], b2);
+  }
+}
+
+// Two chained GEMMs per (plane, column block), intermediate kept in LDS.
+//   MODE 0:  T[:, jb]  = (Lm * (In * Rm[:, jb])) ./ (ly_i + lx_j + c_p)   (0 where the denominator is 0)
+//   MODE 1:  X[:, jb] += (Lm * (In * Rm[:, jb]))
+// In: planes of Ny x Nx (TIN), Rm: Nx x Nx, Lm: Ny x Ny (compute type T, row-major).
+#define FD_NB 32
+#define FD_KC 16
+template <typename T, typename TIN, int MODE, int MR>
+__global__ void __launch_bounds__(WG) k_fdm(const TIN* __restrict__ in, const T* __restrict__ Rm,
+                                            const T* __restrict__ Lm, int Nx, int Ny,
+                                            T* __restrict__ tout, const double* __restrict__ lamx,
+                                            const double* __restrict__ lamy, const double* __restrict__ shift,
+                                            double* __restrict__ X) {
+  constexpr int ROWS = MR * 8;
+  __shared__ T sA[ROWS][FD_KC + 1];
+  __shared__ T sB[FD_KC][FD_NB + 1];
+  __shared__ T sT[ROWS][FD_NB + 1];
+  const int t = threadIdx.x;
+  const int j = t % FD_NB, rg = t / FD_NB;
+  const int j0 = blockIdx.x * FD_NB;
+  const int pl = blockIdx.y;
+  const long Ng = (long)Nx * Ny;
+  const TIN* inp = in + pl * Ng;
+  T acc[MR];
+#pragma unroll
+  for (int m = 0; m < MR; ++m) acc[m] = T(0);
+  // phase 1: T1 = In * Rm[:, j0:j0+NB]
+  for (int kc = 0; kc < Nx; kc += FD_KC) {
+    for (int i = t; i < ROWS * FD_KC; i += WG) {
+      int r = i / FD_KC, k = i % FD_KC;
+      sA[r][k] = (r < Ny && kc + k < Nx) ? T(inp[(long)r * Nx + kc + k]) : T(0);
+    }
+    for (int i = t; i < FD_KC * FD_NB; i += WG) {
+      int k = i / FD_NB, jj = i % FD_NB;
+      sB[k][jj] = (kc + k < Nx && j0 + jj < Nx) ? Rm[(long)(kc + k) * Nx + j0 + jj] : T(0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < FD_KC; ++k) {
+      const T bv = sB[k][j];
+#pragma unroll
+      for (int m = 0; m < MR; ++m) acc[m] += sA[rg + 8 * m][k] * bv;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    sT[rg + 8 * m][j] = acc[m];
+    acc[m] = T(0);
+  }
+  __syncthreads();
+  // phase 2: Out = Lm * T1
+  for (int kc = 0; kc < Ny; kc += FD_KC) {
+    for (int i = t; i < ROWS * FD_KC; i += WG) {
+      int r = i / FD_KC, k = i % FD_KC;
+      sA[r][k] = (r < Ny && kc + k < Ny) ? Lm[(long)r * Ny + kc + k] : T(0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < FD_KC; ++k) {
+      const T bv = (kc + k < ROWS) ? sT[kc + k][j] : T(0);
+#pragma unroll
+      for (int m = 0; m < MR; ++m) acc[m] += sA[rg + 8 * m][k] * bv;
+    }
+    __syncthreads();
+  }
+  const int jj = j0 + j;
+  if (jj >= Nx) return;
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    const int i = rg + 8 * m;
+    if (i >= Ny) continue;
+    if (MODE == 0) {
+      const double den = lamy[i] + lamx[jj] + shift[pl];
+      tout[pl * Ng + (long)i * Nx + jj] = (den != 0.0) ? T(double(acc[m]) / den) : T(0);
+    } else {
+      X[pl * Ng + (long)i * Nx + jj] += double(acc[m]);
+    }
+  }
+}
+
+template <typename T, typename TIN, int MODE>
+static void launch_fdm(int MRneed, dim3 grid, hipStream_t st, const TIN* in, const T* Rm, const T* Lm,
+                       int Nx, int Ny, T* tout, const double* lamx, const double* lamy,
+                       const double* shift, double* X) {
+#define FD_CASE(MRV)                                                                              \
+  if (MRneed <= MRV) {                                                                            \
+    hipLaunchKernelGGL((k_fdm<T, TIN, MODE, MRV>), grid, dim3(WG), 0, st, in, Rm, Lm, Nx, Ny,     \
+                       tout, lamx, lamy, shift, X);                                               \
+    return;                                                                                       \
+  }
+  FD_CASE(4) FD_CASE(8) FD_CASE(12) FD_CASE(16) FD_CASE(20) FD_CASE(24) FD_CASE(32) FD_CASE(40)
+#undef FD_CASE
+}
+
+// range projection of a right side for singular planes: r -= (sum r / sum M) M
+__global__ void k_project(long Ng, const double* Mdiag, const double* shift, double* r) {
+  const int pl = blockIdx.x;
+  if (shift[pl] != 0.0) return;
+  __shared__ double sm[WG], sw[WG];
+  double a = 0.0, m = 0.0;
+  double* rp = r + pl * Ng;
+  for (long i = threadIdx.x; i < Ng; i += WG) {
+    a += rp[i];
+    m += Mdiag[i];
+  }
+  sm[threadIdx.x] = a;
+  sw[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = WG / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sm[threadIdx.x] += sm[threadIdx.x + o];
+      sw[threadIdx.x] += sw[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  const double c = sm[0] / sw[0];
+  for (long i = threadIdx.x; i < Ng; i += WG) rp[i] -= c * Mdiag[i];
+}
+
+// mean removal for singular planes: x -= (sum M x / sum M)
+__global__ void k_mean_remove(long Ng, const double* Mdiag, const double* shift, double* x) {
+  const int pl = blockIdx.x;
+  if (shift[pl] != 0.0) return;
+  __shared__ double sm[WG], sw[WG];
+  double a = 0.0, m = 0.0;
+  double* xp = x + pl * Ng;
+  for (long i = threadIdx.x; i < Ng; i += WG) {
+    a += Mdiag[i] * xp[i];
+    m += Mdiag[i];
+  }
+  sm[threadIdx.x] = a;
+  sw[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = WG / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sm[threadIdx.x] += sm[threadIdx.x + o];
+      sw[threadIdx.x] += sw[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  const double mean = sm[0] / sw[0];
+  for (long i = threadIdx.x; i < Ng; i += WG) xp[i] -= mean;
+}
+
+static inline unsigned nblk(long n) { return (unsigned)((n + WG - 1) / WG); }
+
+hipError_t apply(pfd_ctx* c, int fam, const double* x, double* y, int ncomp) {
+  Family& F = c->fam[fam];
+  Dir1D& dx = c->dirs[F.ix];
+  Dir1D& dy = c->dirs[F.iy];
+  for (int comp = 0; comp < ncomp; ++comp) {
+    long off = (long)comp * c->planes * c->Ng;
+    hipLaunchKernelGGL(k_residual, dim3(nblk((long)c->planes * c->Ng)), dim3(WG), 0, c->stream, c->Nx,
+                       c->Ny, c->planes, c->K, (int)dx.periodic, dx.dK1, dx.dM1, dx.ddir, dy.dK1, dy.dM1,
+                       dy.ddir, F.dshift, nullptr, x + off, y + off, 1, nullptr);
+  }
+  return hipGetLastError();
+}
+
+// Solve (K + c M) x = b for ncomp stacked right sides (each planes*Ng), x holding
+// the initial guess and Dirichlet values.
+hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp) {
+  Family& F = c->fam[fam];
+  Dir1D& dx = c->dirs[F.ix];
+  Dir1D& dy = c->dirs[F.iy];
+  const int Nx = c->Nx, Ny = c->Ny;
+  const long tot = (long)c->planes * c->Ng;
+  const bool fp32 = c->prob.precision == PFD_REFINED_FP32;
+  const int iters = fp32 ? (c->prob.refine_iters > 0 ? c->prob.refine_iters : 2) : 1;
+  const int MRneed = (Ny + 7) / 8;
+  dim3 grid((Nx + FD_NB - 1) / FD_NB, c->planes);
+  for (int comp = 0; comp < ncomp; ++comp) {
+    const double* bc = b + comp * tot;
+    double* xc = x + comp * tot;
+    for (int it = 0; it < iters; ++it) {
+      hipLaunchKernelGGL(k_residual, dim3(nblk(tot)), dim3(WG), 0, c->stream, Nx, Ny, c->planes, c->K,
+                         (int)dx.periodic, dx.dK1, dx.dM1, dx.ddir, dy.dK1, dy.dM1, dy.ddir, F.dshift, bc,
+                         xc, c->r, 0, nullptr);
+      // singular planes: keep only the compatible part of the residual (in FP64), so the
+      // low-precision null column cannot leak the incompatible part into other modes
+      if (F.any_singular)
+        hipLaunchKernelGGL(k_project, dim3(c->planes), dim3(WG), 0, c->stream, c->Ng, c->Mdiag, F.dshift, c->r);
+      if (fp32) {
+        float* tf = reinterpret_cast<float*>(c->tmp);
+        launch_fdm<float, double, 0>(MRneed, grid, c->stream, c->r, dx.fS, dy.fST, Nx, Ny, tf, dx.dlam,
+                                     dy.dlam, F.dshift, nullptr);
+        launch_fdm<float, float, 1>(MRneed, grid, c->stream, tf, dx.fST, dy.fS, Nx, Ny, nullptr, nullptr,
+                                    nullptr, nullptr, xc);
+      } else {
+        launch_fdm<double, double, 0>(MRneed, grid, c->stream, c->r, dx.dS, dy.dST, Nx, Ny, c->tmp, dx.dlam,
+                                      dy.dlam, F.dshift, nullptr);
+        launch_fdm<double, double, 1>(MRneed, grid, c->stream, c->tmp, dx.dST, dy.dS, Nx, Ny, nullptr,
+                                      nullptr, nullptr, nullptr, xc);
+      }
+    }
+    if (F.any_singular)
+      hipLaunchKernelGGL(k_mean_remove, dim3(c->planes), dim3(WG), 0, c->stream, c->Ng, c->Mdiag, F.dshift, xc);
+    if (c->check_residual) {
+      hipMemsetAsync(c->d_norms, 0, sizeof(double) * 2 * c->planes, c->stream);
+      hipLaunchKernelGGL(k_residual, dim3(nblk(tot)), dim3(WG), 0, c->stream, Nx, Ny, c->planes, c->K,
+                         (int)dx.periodic, dx.dK1, dx.dM1, dx.ddir, dy.dK1, dy.dM1, dy.ddir, F.dshift, bc,
+                         xc, c->r, 0, c->d_norms);
+      std::vector<double> h(2 * c->planes);
+      hipMemcpyAsync(h.data(), c->d_norms, sizeof(double) * 2 * c->planes, hipMemcpyDeviceToHost, c->stream);
+      hipStreamSynchronize(c->stream);
+      for (int p = 0; p < c->planes; ++p) {
+        double rel = std::sqrt(h[2 * p]) / std::max(1e-300, std::sqrt(h[2 * p + 1]));
+        if (h[2 * p + 1] > 0 && rel > c->last_residual) c->last_residual = rel;
+      }
+    }
+  }
+  return hipGetLastError();
+}
+
+// ================================================================== step orchestration
+#define FLD(f, lv) c->fld[f][(lv) == 0 ? c->cur : 1 - c->cur]
+
+hipError_t update_E(pfd_ctx* c) {
+  const Geo& g = c->geo;
+  dim3 eg(c->geo.nx * c->geo.ny, c->planes), eb(((c->nq + 63) / 64) * 64);
+  const long tot = (long)c->planes * c->Ng;
+  hipLaunchKernelGGL(k_E_elem, eg, eb, 0, c->stream, g, FLD(F_V, 0), c->Lb[0], c->Lb[1]);
+  hipLaunchKernelGGL(k_E_nodal, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, c->Lb[0], c->Lb[1], c->Mdiag,
+                     (const double*)nullptr, c->fld[F_EX][0], c->fld[F_EY][0], c->fld[F_E2][0]);
+  return hipGetLastError();
+}
+
+// one fixed-point iteration of Remark 3.1 with phi* = phi^n (level 0)
+hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout) {
+  Geo g = c->geo;
+  Par P = c->par;
+  P.cs_n = 1.0;
+  P.cs_o = 0.0;
+  dim3 eg(g.nx * g.ny, c->planes), eb(((c->nq + 63) / 64) * 64);
+  const long tot = (long)c->planes * c->Ng;
+  const double* ph = FLD(F_PHI, 0);
+  Dir1D& dx = c->dirs[c->fam[PFD_FAM_V].ix];
+  Dir1D& dy = c->dirs[c->fam[PFD_FAM_V].iy];
+  hipLaunchKernelGGL(k_V_elem, eg, eb, 0, c->stream, g, P, ph, ph, Vin, Vin, c->Lb[0]);
+  hipLaunchKernelGGL(k_V_rhs, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, P, c->Lb[0], c->Mdiag,
+                     c->src[PFD_SRC_FV], Vin, Vin, c->src[PFD_SRC_VD], dx.ddir, dy.ddir, c->b[0], Vout);
+  return solve(c, PFD_FAM_V, c->b[0], Vout, 1);
+}
+
+hipError_t step_once(pfd_ctx* c, int equilibrium) {
+  const Geo& g = c->geo;
+  const Par& P = c->par;
+  dim3 eg(g.nx * g.ny, c->planes), eb(((c->nq + 63) / 64) * 64);
+  const long tot = (long)c->planes * c->Ng;
+  const dim3 ng(nblk(tot)), nb(WG);
+  hipStream_t st = c->stream;
+  const int nw = 1 - c->cur;  // level n+1 overwrites level n-1
+  double* const* S = c->src;
+  // ---- V (eq. 54)
+  {
+    Dir1D& dx = c->dirs[c->fam[PFD_FAM_V].ix];
+    Dir1D& dy = c->dirs[c->fam[PFD_FAM_V].iy];
+    hipLaunchKernelGGL(k_V_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), FLD(F_V, 0), FLD(F_V, -1),
+                       c->Lb[0]);
+    hipLaunchKernelGGL(k_V_rhs, ng, nb, 0, st, g, P, c->Lb[0], c->Mdiag, S[PFD_SRC_FV], FLD(F_V, 0),
+                       FLD(F_V, -1), S[PFD_SRC_VD], dx.ddir, dy.ddir, c->b[0], c->fld[F_V][nw]);
+    solve(c, PFD_FAM_V, c->b[0], c->fld[F_V][nw], 1);
+  }
+  // ---- E (eq. 55)
+  hipLaunchKernelGGL(k_E_elem, eg, eb, 0, st, g, c->fld[F_V][nw], c->Lb[0], c->Lb[1]);
+  hipLaunchKernelGGL(k_E_nodal, ng, nb, 0, st, g, c->Lb[0], c->Lb[1], c->Mdiag, (const double*)nullptr,
+                     c->fld[F_EX][0], c->fld[F_EY][0], c->fld[F_E2][0]);
+  // ---- psi (eq. 56)
+  const double* E2 = c->fld[F_E2][0];
+  // the equilibrium system (Sec. 2.4) has u = 0: read zeros instead of the velocity
+  const double* uxn = equilibrium ? c->zero_buf : FLD(F_UX, 0);
+  const double* uxo = equilibrium ? c->zero_buf : FLD(F_UX, -1);
+  const double* uyn = equilibrium ? c->zero_buf : FLD(F_UY, 0);
+  const double* uyo = equilibrium ? c->zero_buf : FLD(F_UY, -1);
+  hipLaunchKernelGGL(k_psi_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), uxn, uxo, uyn, uyo, E2,
+                     S[PFD_SRC_G], c->Lb[0]);
+  hipLaunchKernelGGL(k_psi_rhs, ng, nb, 0, st, g, P, c->Lb[0], c->bm_open, c->bm_wall, S[PFD_SRC_G1],
+                     S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), FLD(F_PSI, 0), FLD(F_PSI, -1),
+                     E2, c->b[0], c->U, c->Q2, c->fld[F_PSI][nw]);
+  solve(c, PFD_FAM_PSI, c->b[0], c->fld[F_PSI][nw], 1);
+  // ---- phi (eq. 57)
+  hipLaunchKernelGGL(k_phi_rhs, ng, nb, 0, st, g, P, c->Mdiag, c->fld[F_PSI][nw], c->bm_open, c->bm_wall,
+                     S[PFD_SRC_G2], c->U, FLD(F_PHI, 0), FLD(F_PHI, -1), c->b[0], c->fld[F_PHI][nw]);
+  solve(c, PFD_FAM_PHI, c->b[0], c->fld[F_PHI][nw], 1);
+  if (equilibrium) {
+    hipMemsetAsync(c->fld[F_UX][nw], 0, sizeof(double) * tot, st);
+    hipMemsetAsync(c->fld[F_UY][nw], 0, sizeof(double) * tot, st);
+    hipMemsetAsync(c->fld[F_P][nw], 0, sizeof(double) * tot, st);
+  } else {
+    // ---- momentum terms, P (eq. 58)
+    // phi^{n-1} now holds phi^{n+1}: the momentum kernel takes Q2 (built from phi*) from the psi stage
+    hipLaunchKernelGGL(k_mom_elem, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
+                       FLD(F_UX, 0), FLD(F_UX, -1), FLD(F_UY, 0), FLD(F_UY, -1), FLD(F_P, 0),
+                       FLD(F_P, -1), S[PFD_SRC_FX], S[PFD_SRC_FY], c->Lb[0], c->Lb[1], c->Lb[2]);
+    Dir1D& px = c->dirs[c->fam[PFD_FAM_P].ix];
+    Dir1D& py = c->dirs[c->fam[PFD_FAM_P].iy];
+    hipLaunchKernelGGL(k_P_rhs, ng, nb, 0, st, g, P, c->Lb[0], S[PFD_SRC_WX], S[PFD_SRC_WY], FLD(F_P, 0),
+                       FLD(F_P, -1), S[PFD_SRC_F2], px.ddir, py.ddir, c->b[0], c->fld[F_P][nw]);
+    solve(c, PFD_FAM_P, c->b[0], c->fld[F_P][nw], 1);
+    // ---- u (eq. 59)
+    hipLaunchKernelGGL(k_gradP_elem, eg, eb, 0, st, g, P, c->fld[F_P][nw], c->Lb[1], c->Lb[2]);
+    Dir1D& ux = c->dirs[c->fam[PFD_FAM_U].ix];
+    Dir1D& uy = c->dirs[c->fam[PFD_FAM_U].iy];
+    // the two components are solved as one stacked right side: b[0..1], x in fld UX/UY
+    hipLaunchKernelGGL(k_u_rhs, ng, nb, 0, st, g, P, c->Lb[1], c->Lb[2], c->bm_open, S[PFD_SRC_F1X],
+                       S[PFD_SRC_F1Y], FLD(F_UX, 0), FLD(F_UX, -1), FLD(F_UY, 0), FLD(F_UY, -1), S[PFD_SRC_WX],
+                       S[PFD_SRC_WY], ux.ddir, uy.ddir, c->b[1], c->b[2], c->fld[F_UX][nw], c->fld[F_UY][nw]);
+    solve(c, PFD_FAM_U, c->b[1], c->fld[F_UX][nw], 1);
+    solve(c, PFD_FAM_U, c->b[2], c->fld[F_UY][nw], 1);
+  }
+  hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
+  if (!equilibrium)
+    hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_UX][nw], c->d_status);
+  c->cur = nw;
+  return hipGetLastError();
+}
+
+// max |a - b| and max |b| over all planes (host result), for the potential fixed point
+__global__ void k_maxdiff(long N, const double* a, const double* b, double* out) {
+  __shared__ double s1[WG], s2[WG];
+  double m1 = 0.0, m2 = 0.0;
+  for (long i = (long)blockIdx.x * WG + threadIdx.x; i < N; i += (long)gridDim.x * WG) {
+    m1 = fmax(m1, fabs(a[i] - b[i]));
+    m2 = fmax(m2, fabs(b[i]));
+  }
+  s1[threadIdx.x] = m1;
+  s2[threadIdx.x] = m2;
+  __syncthreads();
+  for (int o = WG / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + o]);
+      s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = s1[0];
+    out[2 * blockIdx.x + 1] = s2[0];
+  }
+}
+
+hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* out_host2) {
+  const long N = (long)c->planes * c->Ng;
+  const int nb = 64;
+  hipLaunchKernelGGL(k_maxdiff, dim3(nb), dim3(WG), 0, c->stream, N, a, b, c->d_red);
+  double h[2 * 64];
+  hipMemcpyAsync(h, c->d_red, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, c->stream);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  out_host2[0] = out_host2[1] = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    out_host2[0] = fmax(out_host2[0], h[2 * i]);
+    out_host2[1] = fmax(out_host2[1], h[2 * i + 1]);
+  }
+  return e;
+}
+
+}  // namespace pfd

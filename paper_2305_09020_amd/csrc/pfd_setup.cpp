@@ -1,0 +1,202 @@
+// One-time FP64 host set-up of the constant operators (remark after Algorithm 2:
+// every coefficient matrix of the step is time-independent and is prepared once).
+//
+//  * GLL rule of order K: interior nodes are the eigenvalues of the Jacobi matrix
+//    of the (1,1) Gauss-Jacobi polynomials (P_K' is proportional to P_{K-1}^{(1,1)}),
+//    weights 2/(K(K+1) P_K(x)^2); Lagrange derivative matrix from barycentric
+//    weights.
+//  * 1D assembled stiffness and (diagonal, GLL-collocated) mass along x and y.
+//    On a tensor-product mesh with collocated GLL quadrature the 2D operator
+//    int grad u . grad v + c int u v is exactly  Kx (x) My + Mx (x) Ky + c Mx (x) My.
+//  * Generalised eigen-decompositions Kd S = Md S Lambda, S^T Md S = I, per
+//    direction and boundary-condition combination (fast diagonalisation,
+//    Lynch, Rice & Thomas 1964), by cyclic Jacobi rotations.
+#include "pfd_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace pfd {
+
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix A (row-major,
+// destroyed).  On return lam holds the eigenvalues, V (row-major) the
+// eigenvectors as columns, sorted by ascending eigenvalue.
+void sym_eig(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double v = a(i, j) * a(i, j);
+        tot += v;
+        if (i != j) off += v;
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        double apq = a(p, q);
+        if (std::fabs(apq) < 1e-300) continue;
+        double app = a(p, p), aqq = a(q, q);
+        double theta = (aqq - app) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // rows/cols p, q
+          double akp = a(k, p), akq = a(k, q);
+          a(k, p) = c * akp - s * akq;
+          a(k, q) = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          double apk = a(p, k), aqk = a(q, k);
+          a(p, k) = c * apk - s * aqk;
+          a(q, k) = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = c * vkp - s * vkq;
+          V[(size_t)k * n + q] = s * vkp + c * vkq;
+        }
+      }
+    }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return a(x, x) < a(y, y); });
+  lam.resize(n);
+  std::vector<double> W((size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    lam[j] = a(idx[j], idx[j]);
+    for (int k = 0; k < n; ++k) W[(size_t)k * n + j] = V[(size_t)k * n + idx[j]];
+  }
+  V.swap(W);
+}
+
+static double legendre_val(int K, double x) {
+  double p0 = 1.0, p1 = x;
+  if (K == 0) return 1.0;
+  for (int n = 1; n < K; ++n) {
+    double p2 = ((2 * n + 1) * x * p1 - n * p0) / (n + 1);
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+void gll_rule(int K, std::vector<double>& x, std::vector<double>& w, std::vector<double>& D) {
+  const int n = K + 1;
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  x[0] = -1.0;
+  x[K] = 1.0;
+  if (K >= 2) {
+    int m = K - 1;  // interior nodes: roots of P_{K-1}^{(1,1)}
+    std::vector<double> J((size_t)m * m, 0.0), lam, V;
+    for (int i = 1; i < m; ++i) {  // off-diagonal b_i = sqrt(i(i+2)/((2i+1)(2i+3)))
+      double b = std::sqrt((double)i * (i + 2) / ((2.0 * i + 1) * (2.0 * i + 3)));
+      J[(size_t)(i - 1) * m + i] = b;
+      J[(size_t)i * m + (i - 1)] = b;
+    }
+    sym_eig(m, J, lam, V);
+    for (int i = 0; i < m; ++i) x[i + 1] = lam[i];
+    // symmetrise to remove rounding asymmetry of the eigen-solver
+    for (int i = 0; i <= K / 2; ++i) {
+      double s = 0.5 * (x[K - i] - x[i]);
+      x[i] = -s;
+      x[K - i] = s;
+    }
+    if (K % 2 == 0) x[K / 2] = 0.0;
+  }
+  for (int j = 0; j < n; ++j) {
+    double p = legendre_val(K, x[j]);
+    w[j] = 2.0 / (K * (K + 1.0) * p * p);
+  }
+  // barycentric weights bw_j = 1 / prod_{k != j} (x_j - x_k)
+  std::vector<double> bw(n, 1.0);
+  for (int j = 0; j < n; ++j)
+    for (int k = 0; k < n; ++k)
+      if (k != j) bw[j] /= (x[j] - x[k]);
+  D.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double diag = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (i == j) continue;
+      double v = (bw[j] / bw[i]) / (x[i] - x[j]);
+      D[(size_t)i * n + j] = v;
+      diag -= v;
+    }
+    D[(size_t)i * n + i] = diag;
+  }
+}
+
+// Assembled 1D stiffness (dense) and lumped mass along one direction.
+void assemble_1d(int ne, const double* bp, int K, bool periodic, const std::vector<double>& w,
+                 const std::vector<double>& D, std::vector<double>& Kd, std::vector<double>& Md,
+                 std::vector<double>& coord, const std::vector<double>& xi) {
+  int N = ne * K + 1 - (periodic ? 1 : 0);
+  Kd.assign((size_t)N * N, 0.0);
+  Md.assign(N, 0.0);
+  coord.assign(N, 0.0);
+  const int n = K + 1;
+  for (int e = 0; e < ne; ++e) {
+    double h = bp[e + 1] - bp[e];
+    for (int a = 0; a < n; ++a) {
+      const int gi = e * K + a;
+      const bool wrap = periodic && gi == N;   // last node identified with node 0
+      const int i = wrap ? 0 : gi;
+      if (!wrap) coord[i] = bp[e] + 0.5 * h * (xi[a] + 1.0);
+      Md[i] += 0.5 * h * w[a];
+      for (int b = 0; b < n; ++b) {
+        const int gj = e * K + b;
+        const int j = (periodic && gj == N) ? 0 : gj;
+        double s = 0.0;
+        for (int q = 0; q < n; ++q) s += w[q] * D[(size_t)q * n + a] * D[(size_t)q * n + b];
+        Kd[(size_t)i * N + j] += 2.0 / h * s;
+      }
+    }
+  }
+}
+
+// Fast-diagonalisation factors for one direction with Dirichlet flags at the
+// two ends (ignored when periodic).  Dirichlet rows of S are zero.
+void build_dir1d(Dir1D& d, int ne, const double* bp, int K, bool periodic, bool dir_lo, bool dir_hi,
+                 const std::vector<double>& xi, const std::vector<double>& w,
+                 const std::vector<double>& D) {
+  assemble_1d(ne, bp, K, periodic, w, D, d.K1, d.M1, d.coord, xi);
+  const int N = (int)d.M1.size();
+  d.N = N;
+  d.periodic = periodic;
+  d.dir.assign(N, 0);
+  if (!periodic) {
+    if (dir_lo) d.dir[0] = 1;
+    if (dir_hi) d.dir[N - 1] = 1;
+  }
+  std::vector<int> fr;
+  for (int i = 0; i < N; ++i)
+    if (!d.dir[i]) fr.push_back(i);
+  const int m = (int)fr.size();
+  std::vector<double> B((size_t)m * m), lam, Q;
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b < m; ++b)
+      B[(size_t)a * m + b] = d.K1[(size_t)fr[a] * N + fr[b]] /
+                             std::sqrt(d.M1[fr[a]] * d.M1[fr[b]]);
+  sym_eig(m, B, lam, Q);
+  d.singular = (m == N);  // no Dirichlet node: constants are in the kernel
+  d.S.assign((size_t)N * N, 0.0);
+  d.lam.assign(N, 1.0);
+  for (int j = 0; j < m; ++j) {
+    d.lam[j] = lam[j];
+    for (int a = 0; a < m; ++a) d.S[(size_t)fr[a] * N + j] = Q[(size_t)a * m + j] / std::sqrt(d.M1[fr[a]]);
+  }
+  if (d.singular) {
+    // the lowest pair is exactly (0, 1/sqrt(sum M))
+    double tot = 0.0;
+    for (int i = 0; i < N; ++i) tot += d.M1[i];
+    d.lam[0] = 0.0;
+    for (int i = 0; i < N; ++i) d.S[(size_t)i * N + 0] = 1.0 / std::sqrt(tot);
+  }
+  d.nfree = m;
+}
+
+}  // namespace pfd

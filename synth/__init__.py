@@ -1,0 +1,49 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the
+benchmark.  This module holds workload descriptions (mesh sizes, material
+parameters, boundary sides) and initial-condition generators only -- none of the
+method's arithmetic.  Fields are evaluated on coordinates supplied by the caller.
+
+Workloads follow the paper's setups (tanh interface profiles of a drop in an
+ambient fluid, Sec. 4.2-4.4) at the sizes of the benchmark configurations:
+  C1  [0,1]^2, 4x4 elements, K = 6, dt = 1e-4, 100 steps, drop r = 0.25 at the
+      centre, eta = 0.01, rho 1:2, mu 0.01:0.02, eps 2:8, walls, V = 0 / 1 on the
+      bottom / top.
+  C2  [0,1]^2, 20x20 elements, K = 8, dt = 5e-5, 2000 steps, sessile half-disc
+      r = 0.25 at (0.5, 0), theta_s = 90 deg, eta = 0.01, rho 1:1000,
+      mu 0.01:1, eps 1:40, V_top in {0, 0.5, 1, 2} (four instances).
+Fluid 1 (phi = +1) is the ambient fluid, fluid 2 (phi = -1) the drop.
+"""
+import math
+
+import numpy as np
+
+
+def lam_from_sigma(sigma, eta):
+    """lambda = 3 sigma eta / (2 sqrt 2), the relation quoted in Sec. 2.1."""
+    return 3.0 * sigma * eta / (2.0 * math.sqrt(2.0))
+
+
+def drop_field(X, Y, center, r, eta, Z=None, zc=None, rfun=None):
+    """phi = tanh((|x - c| - r)/(sqrt(2) eta)): -1 inside the drop, +1 outside."""
+    d2 = (np.asarray(X) - center[0]) ** 2 + (np.asarray(Y) - center[1]) ** 2
+    if Z is not None:
+        d2 = d2 + (np.asarray(Z) - zc) ** 2
+    rr = r if rfun is None else rfun
+    return np.tanh((np.sqrt(d2) - rr) / (math.sqrt(2.0) * eta))
+
+
+def c1_param_dict(dt=1e-4):
+    eta = 0.01
+    return dict(rho1=1.0, rho2=2.0, mu1=0.01, mu2=0.02, eps1=2.0, eps2=8.0,
+                lam=lam_from_sigma(1.0, eta), eta=eta, gamma1=1e-4, theta_s_deg=90.0, dt=dt)
+
+
+def c2_param_dict(dt=5e-5):
+    eta = 0.01
+    return dict(rho1=1.0, rho2=1000.0, mu1=0.01, mu2=1.0, eps1=1.0, eps2=40.0,
+                lam=lam_from_sigma(1.0, eta), eta=eta, gamma1=1e-4, theta_s_deg=90.0, dt=dt)
+
+
+C1 = dict(name="C1", nx=4, ny=4, K=6, steps=100, center=(0.5, 0.5), r=0.25, vtop=(1.0,))
+C2 = dict(name="C2", nx=20, ny=20, K=8, steps=2000, center=(0.5, 0.0), r=0.25,
+          vtop=(0.0, 0.5, 1.0, 2.0))

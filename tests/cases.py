@@ -6,6 +6,15 @@ import numpy as np
 from oracle.sem import Mesh2D, BOTTOM, TOP, LEFT, RIGHT, NORMALS
 from oracle.scheme import Scheme, Params, BCs, WALL, OPEN
 from oracle.manufactured import Manufactured
+from synth import c1_param_dict, c2_param_dict
+
+
+def c1_params(dt=1e-4):
+    return Params(**c1_param_dict(dt))
+
+
+def c2_params(dt=5e-5):
+    return Params(**c2_param_dict(dt))
 
 
 def mms_params(dt=1e-3, S=0.0):

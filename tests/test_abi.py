@@ -1,0 +1,51 @@
+"""The C-ABI library loads and exports every entry point that include/pfd.h declares
+(no GPU needed: nothing is called)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2305_09020_amd", "libpfd.so")
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "pfd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pfd_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    for s in ("pfd_create", "pfd_step", "pfd_get_field", "pfd_set_field", "pfd_destroy",
+              "pfd_solve", "pfd_init_potential"):
+        assert s in syms
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_host_only_validation():
+    """pfd_workspace_query validates a problem on the host (no device calls)."""
+    import numpy as np
+    import paper_2305_09020_amd as pfd
+    par = dict(rho1=1, rho2=2, mu1=0.01, mu2=0.02, eps1=2, eps2=8, lam=0.05, eta=0.02,
+               gamma1=1e-3, theta_s_deg=90, dt=1e-4)
+    xb = np.linspace(0, 1, 5)
+    good = pfd.make_problem(xb, xb, 6, par, [0, 0, 0, 0], [1, 1, 0, 0])
+    assert pfd.workspace_bytes(good) > 0
+    bad = pfd.make_problem(xb, xb, 1, par, [0, 0, 0, 0], [1, 1, 0, 0])
+    with pytest.raises(pfd.PfdError):
+        pfd.workspace_bytes(bad)
+    nov = pfd.make_problem(xb, xb, 6, par, [0, 0, 0, 0], [0, 0, 0, 0])
+    with pytest.raises(pfd.PfdError):
+        pfd.workspace_bytes(nov)
+    par2 = dict(par, dt=-1.0)
+    with pytest.raises(pfd.PfdError):
+        pfd.workspace_bytes(pfd.make_problem(xb, xb, 6, par2, [0, 0, 0, 0], [1, 1, 0, 0]))

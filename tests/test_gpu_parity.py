@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle, element by
+element on the same seeded inputs.  Tolerances: plain FP64 path 1e-10 relative
+per field (the oracle uses sparse LU, the library fast diagonalisation: both are
+direct FP64 solves, differing by rounding); FP32-refined path 1e-8 (the
+spec bound)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.sem import Mesh2D, BOTTOM, TOP, LEFT, RIGHT
+from oracle.scheme import Scheme, Params, BCs, WALL, OPEN
+from cases import mms_setup, mms_initial, mms_errors, c1_params
+from gpu_cases import gpu_context, rel_err
+from synth import drop_field
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("phi", "psi", "V", "P", "ux", "uy", "Ex", "Ey")
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def box_case(n=4, K=6, periodic=False, top=WALL, par=None):
+    xb = np.linspace(0.0, 1.0, n + 1)
+    m = Mesh2D(xb, xb, K, periodic_x=periodic)
+    side = {BOTTOM: WALL, TOP: top}
+    if not periodic:
+        side.update({LEFT: WALL, RIGHT: WALL})
+    bc = BCs(side=side, pot_sides=(BOTTOM, TOP))
+    return m, bc, par or c1_params()
+
+
+# ------------------------------------------------------------------ solver (P8)
+@pytest.mark.parametrize("periodic,top", [(False, WALL), (True, OPEN)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_matches_sparse_lu(periodic, top, precision):
+    """Each constant operator K + c M (families V, psi, phi, P, u) solved by the
+    library matches SciPy's sparse LU of the assembled matrix on random data,
+    with random Dirichlet values (remark after Algorithm 2)."""
+    torch = _torch()
+    m, bc, par = box_case(n=3, K=7, periodic=periodic, top=top)
+    sch = Scheme(m, par, bc)
+    ctx = gpu_context(m, par, bc, precision=precision, refine_iters=3)
+    rng = np.random.default_rng(230509020)
+    tol = 1e-11 if precision == 0 else 1e-9
+    for fam, name in enumerate(("V", "psi", "phi", "P", "u")):
+        b = rng.standard_normal(m.Ng)
+        g = rng.standard_normal(m.Ng)
+        xr = sch.solve(name, 0, b, g)
+        bt = torch.tensor(b, device="cuda")
+        xt = torch.tensor(g, device="cuda")       # Dirichlet values + initial guess
+        ctx.solve(fam, bt, xt)
+        torch.cuda.synchronize()
+        e = rel_err(xt.cpu().numpy(), xr)
+        assert e < tol, (name, e)
+
+
+# ------------------------------------------------------------- full-step parity
+def run_pair(m, par, bc, phi0, u0, src, nsteps, nbatch=1, precision=0, equilibrium=False,
+             per_step_src=None, init_V=True, V0=None, prev=None, P0=None):
+    """Run the oracle and the library side by side; returns list of (oracle, gpu) field dicts."""
+    _torch()
+    ctx = gpu_context(m, par, bc, nbatch=nbatch, precision=precision, refine_iters=3)
+    schs = []
+    for ib in range(nbatch):
+        s = Scheme(m, par, bc)
+        sl = (lambda a: None if a is None else np.asarray(a).reshape(nbatch, -1)[ib])
+        s.set_state(sl(phi0), None if u0 is None else tuple(sl(x) for x in u0), sl(P0), sl(V0),
+                    prev=None if prev is None else {k: (tuple(sl(x) for x in v) if k == "u" else sl(v))
+                                                    for k, v in prev.items()})
+        schs.append(s)
+    shape = (nbatch, m.Ny, m.Nx)
+    ctx.set_field("phi", np.reshape(phi0, shape))
+    if u0 is not None:
+        ctx.set_field("ux", np.reshape(u0[0], shape))
+        ctx.set_field("uy", np.reshape(u0[1], shape))
+    if P0 is not None:
+        ctx.set_field("P", np.reshape(P0, shape))
+    if V0 is not None:
+        ctx.set_field("V", np.reshape(V0, shape))
+    if prev is not None:
+        for k in ("phi", "P", "V"):
+            if k in prev:
+                ctx.set_field(k, np.reshape(prev[k], shape), level=-1)
+        if "u" in prev:
+            ctx.set_field("ux", np.reshape(prev["u"][0], shape), level=-1)
+            ctx.set_field("uy", np.reshape(prev["u"][1], shape), level=-1)
+    ctx.set_sources({k: np.reshape(v, shape) for k, v in src.items()})
+    if init_V:
+        for ib, s in enumerate(schs):
+            s.init_potential({k: np.reshape(v, (nbatch, -1))[ib] for k, v in src.items()})
+        ctx.init_potential(tol=1e-14, max_iter=20000)
+    out = []
+    for n in range(nsteps):
+        if per_step_src is not None:
+            srcn = per_step_src(n)
+            ctx.set_sources({k: np.reshape(v, shape) for k, v in srcn.items()})
+        else:
+            srcn = src
+        o = [s.step({k: np.reshape(v, (nbatch, -1))[ib] for k, v in srcn.items()},
+                    equilibrium=equilibrium) for ib, s in enumerate(schs)]
+        ctx.step(1, equilibrium=equilibrium)
+        gf = {k: ctx.get_field(k) for k in FIELDS}
+        of = {k: np.stack([oo[k][0] for oo in o]).reshape(shape) for k in FIELDS}
+        out.append((of, gf))
+    return out, ctx
+
+
+def check_parity(out, tol, fields=FIELDS):
+    worst = {}
+    for (of, gf) in out:
+        for k in fields:
+            scale = max(np.linalg.norm(of[k]), 1e-12 * np.linalg.norm(of["phi"]))
+            e = np.linalg.norm(gf[k] - of[k]) / scale
+            worst[k] = max(worst.get(k, 0.0), e)
+    bad = {k: v for k, v in worst.items() if not v < tol}
+    assert not bad, (bad, worst)
+    return worst
+
+
+def test_c1_drop_step_parity_fp64():
+    """C1 workload (4x4 elements, K = 6, drop r = 0.25, eta = 0.01, V 0/1): every
+    field of Algorithm 1 after each of 10 steps."""
+    m, bc, par = box_case(n=4, K=6)
+    phi0 = drop_field(m.X, m.Y, (0.5, 0.5), 0.25, par.eta)
+    vd = np.where(np.isclose(m.Y, 1.0), 1.0, 0.0)
+    out, ctx = run_pair(m, par, bc, phi0, None, dict(Vd=vd), 10)
+    check_parity(out, 1e-10)
+
+
+def test_c1_drop_step_parity_refined_fp32():
+    """Same with FP32 solves + FP64 iterative refinement: 1e-8 per field."""
+    m, bc, par = box_case(n=4, K=6)
+    phi0 = drop_field(m.X, m.Y, (0.5, 0.5), 0.25, par.eta)
+    vd = np.where(np.isclose(m.Y, 1.0), 1.0, 0.0)
+    out, ctx = run_pair(m, par, bc, phi0, None, dict(Vd=vd), 10, precision=1)
+    check_parity(out, 1e-8)
+
+
+def test_batched_instances_equal_oracle_runs():
+    """Three instances in one context (one per plane) with different top
+    voltages: each matches its own oracle run."""
+    m, bc, par = box_case(n=3, K=5)
+    phi1 = drop_field(m.X, m.Y, (0.5, 0.0), 0.3, 0.04)
+    phi0 = np.stack([phi1] * 3)
+    vd = np.stack([np.where(np.isclose(m.Y, 1.0), v, 0.0) for v in (0.0, 1.0, 2.0)])
+    p2 = Params(**{**par.__dict__, "eta": 0.04, "lam": 3 * 0.04 / (2 * math.sqrt(2))})
+    out, ctx = run_pair(m, p2, bc, phi0, None, dict(Vd=vd), 5, nbatch=3)
+    check_parity(out, 1e-10)
+
+
+def test_equilibrium_system_parity():
+    """Simpler system of Sec. 2.4 (V, E, psi, phi with u = 0): parity and exact
+    conservation of int_h phi on the GPU."""
+    m, bc, par = box_case(n=3, K=6)
+    p2 = Params(**{**par.__dict__, "eta": 0.04, "lam": 3 * 0.04 / (2 * math.sqrt(2)),
+                   "theta_s_deg": 60.0, "dt": 1e-5})
+    phi0 = drop_field(m.X, m.Y, (0.5, 0.0), 0.3, 0.04)
+    vd = np.where(np.isclose(m.Y, 1.0), 2.0, 0.0)
+    out, ctx = run_pair(m, p2, bc, phi0, None, dict(Vd=vd), 8, equilibrium=True)
+    check_parity(out, 1e-10, fields=("phi", "psi", "V", "Ex", "Ey"))
+    M = m.Mdiag
+    m0 = np.sum(M * phi0.ravel())
+    m1 = np.sum(M * out[-1][1]["phi"].ravel())
+    assert abs(m1 - m0) < 1e-12 * abs(m0)
+
+
+@pytest.mark.parametrize("kind", ["eq80", "box"])
+def test_manufactured_parity_and_accuracy(kind):
+    """Manufactured solutions (Sec. 4.1 eq. 80; closed box): the GPU path matches
+    the oracle step by step with time-dependent sources, and its error against
+    the exact solution is the oracle's."""
+    K, dt, n = 8, 1e-3, 20
+    case = mms_setup(kind, K, dt)
+    m, par, bc = case["mesh"], case["par"], case["bc"]
+    f0, fm = mms_initial(case, dt)
+    x, y, z = case["x"], case["y"], case["z"]
+    mf = case["mf"]
+    src_fn = lambda i: mf.sources(x, y, z, (i + 1) * dt, case["sides"])
+    out, ctx = run_pair(m, par, bc, f0["phi"], f0["u"][:2], src_fn(0), n, per_step_src=src_fn,
+                        init_V=False, V0=f0["V"], P0=f0["P"],
+                        prev=dict(phi=fm["phi"], u=fm["u"][:2], P=fm["P"], V=fm["V"]))
+    check_parity(out, 1e-10)
+    of, gf = out[-1]
+    fe = mf.fields(x, y, z, n * dt)
+    eg = max(np.max(np.abs(gf["phi"].ravel() - fe["phi"].ravel())),
+             np.max(np.abs(gf["ux"].ravel() - fe["u"][0].ravel())))
+    assert eg < 1e-3
+
+
+def test_init_potential_matches_direct_solve():
+    """Remark 3.1 fixed point on the GPU converges to the oracle's direct
+    variable-coefficient solve."""
+    m, bc, par = box_case(n=4, K=6)
+    phi0 = drop_field(m.X, m.Y, (0.5, 0.5), 0.25, par.eta)
+    vd = np.where(np.isclose(m.Y, 1.0), 1.0, 0.0)
+    sch = Scheme(m, par, bc)
+    sch.set_state(phi0.ravel())
+    Vo = sch.init_potential(dict(Vd=vd.ravel()))
+    ctx = gpu_context(m, par, bc)
+    ctx.set_field("phi", phi0.reshape(1, m.Ny, m.Nx))
+    ctx.set_source("Vd", vd.reshape(1, m.Ny, m.Nx))
+    its = ctx.init_potential(tol=1e-14, max_iter=5000)
+    assert its < 5000
+    Vg = ctx.get_field("V")
+    assert rel_err(Vg, Vo) < 1e-12
+
+
+def test_nonfinite_state_is_reported():
+    """A NaN written into the state is caught by the step's guard (sticky error)."""
+    import paper_2305_09020_amd as pfd
+    m, bc, par = box_case(n=2, K=4)
+    ctx = gpu_context(m, par, bc)
+    phi = drop_field(m.X, m.Y, (0.5, 0.5), 0.25, 0.05).reshape(1, m.Ny, m.Nx).copy()
+    phi[0, 3, 3] = np.nan
+    ctx.set_field("phi", phi)
+    with pytest.raises(pfd.PfdError) as ei:
+        ctx.step(1)
+    assert ei.value.code == pfd.ENONFINITE
+    with pytest.raises(pfd.PfdError) as ei:
+        ctx.step(1)
+    assert ei.value.code == pfd.ESTATE
