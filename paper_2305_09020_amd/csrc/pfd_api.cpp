@@ -90,13 +90,13 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   dbl += (size_t)PFD_NSRC * Pg;          // sources
   dbl += 3 * (size_t)Pl;                 // element-local buffers
   dbl += 3 * (size_t)Pg;                 // right sides
-  dbl += 5 * (size_t)Pg;                 // r, U, Q2, tmp, zero
+  dbl += 8 * (size_t)Pg;                 // r (3), U, Q2, tmp, tmp2, zero
   dbl += 7 * (size_t)L->Ng;              // boundary masses, mass
   const int NN = std::max(L->Nx, L->Ny);
   dbl += 8 * (3 * (size_t)NN * NN + 3 * NN + 8);  // up to 8 distinct 1D operators
   dbl += 8 * (size_t)NN * NN;            // float copies (as doubles, generous)
   dbl += 2 * (size_t)(m.nx + m.ny + 2) + (PFD_KMAX + 1) * (PFD_KMAX + 2);
-  dbl += 16 * (size_t)L->planes + 256;   // shifts, norms, reductions
+  dbl += 48 * (size_t)L->planes + 256;   // shifts, norms, reductions
   L->bytes = dbl * sizeof(double) + 256 * 128;  // alignment slack
   return PFD_OK;
 }
@@ -206,7 +206,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   for (int s = 0; s < PFD_NSRC; ++s) c->src[s] = D(Pg);
   for (int i = 0; i < 3; ++i) c->Lb[i] = D(Pl);
   for (int i = 0; i < 3; ++i) c->b[i] = D(Pg);
-  c->r = D(Pg); c->U = D(Pg); c->Q2 = D(Pg); c->tmp = D(Pg);
+  c->r = D(3 * Pg); c->U = D(Pg); c->Q2 = D(Pg); c->tmp = D(Pg); c->tmp2 = D(Pg);
   double* zero = D(Pg);
   for (int s = 0; s < 4; ++s) c->bm_side[s] = D(c->Ng);
   c->bm_open = D(c->Ng); c->bm_wall = D(c->Ng); c->Mdiag = D(c->Ng);
@@ -215,11 +215,13 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   c->d_status = (int*)carve(c, 64);
   c->d_norms = D(2 * c->planes + 2);
   c->d_red = D(2 * 64);
+  c->d_part = D(32 * (long)c->planes);
   c->d_beta2 = D(c->planes); c->d_betad = D(c->planes);
   for (int f = 0; f < 5; ++f) c->fam[f].dshift = D(c->planes);
   for (auto& d : c->dirs) {
     const long NN = (long)d.N * d.N;
-    d.dS = D(NN); d.dST = D(NN); d.dK1 = D(NN); d.dlam = D(d.N); d.dM1 = D(d.N);
+    d.dS = D(NN); d.dST = D(NN); d.dKb = D((long)(2 * K + 1) * d.N); d.dlam = D(d.N); d.dM1 = D(d.N);
+    d.dK0 = D(d.N); d.dKN = D(d.N);
     d.fS = (float*)carve(c, sizeof(float) * NN);
     d.fST = (float*)carve(c, sizeof(float) * NN);
     d.ddir = (unsigned char*)carve(c, d.N);
@@ -249,20 +251,31 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     for (int i = 0; i < N; ++i) dd[i] = d.dir[i] ? 1 : 0;
     e = up(d.dS, d.S.data(), 8 * N * N); if (e) break;
     e = up(d.dST, ST.data(), 8 * N * N); if (e) break;
-    e = up(d.dK1, d.K1.data(), 8 * N * N); if (e) break;
+    e = up(d.dKb, d.Kb.data(), 8 * (2 * K + 1) * N); if (e) break;
     e = up(d.dlam, d.lam.data(), 8 * N); if (e) break;
     e = up(d.dM1, d.M1.data(), 8 * N); if (e) break;
     e = up(d.fS, f1.data(), 4 * N * N); if (e) break;
     e = up(d.fST, f2.data(), 4 * N * N); if (e) break;
     e = up(d.ddir, dd.data(), N); if (e) break;
+    std::vector<double> k0(N), kn(N);
+    for (int i = 0; i < N; ++i) {
+      k0[i] = d.K1[(size_t)i * N];
+      kn[i] = d.K1[(size_t)i * N + N - 1];
+    }
+    e = up(d.dK0, k0.data(), 8 * N); if (e) break;
+    e = up(d.dKN, kn.data(), 8 * N); if (e) break;
   }
   // boundary and volume masses from the x/y 1D masses (any family's dirs share M1)
   const Dir1D& DX = c->dirs[c->fam[0].ix];
   const Dir1D& DY = c->dirs[c->fam[0].iy];
   std::vector<double> Md(c->Ng), bs[4], bo(c->Ng, 0.0), bw(c->Ng, 0.0);
   for (int s = 0; s < 4; ++s) bs[s].assign(c->Ng, 0.0);
+  c->Mtot = 0.0;
   for (int iy = 0; iy < c->Ny; ++iy)
-    for (int ix = 0; ix < c->Nx; ++ix) Md[(long)iy * c->Nx + ix] = DX.M1[ix] * DY.M1[iy];
+    for (int ix = 0; ix < c->Nx; ++ix) {
+      Md[(long)iy * c->Nx + ix] = DX.M1[ix] * DY.M1[iy];
+      c->Mtot += DX.M1[ix] * DY.M1[iy];
+    }
   for (int ix = 0; ix < c->Nx; ++ix) {
     bs[PFD_BOTTOM][ix] = DX.M1[ix];
     bs[PFD_TOP][(long)(c->Ny - 1) * c->Nx + ix] = DX.M1[ix];
@@ -323,6 +336,11 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     g.side_type[s] = (per && s >= PFD_LEFT) ? -1 : bc.side_type[s];
   }
   c->zero_buf = zero;
+  for (int f = 0; f < 5; ++f) {
+    const Dir1D& dx = c->dirs[c->fam[f].ix];
+    const Dir1D& dy = c->dirs[c->fam[f].iy];
+    c->lift[f] = Lift{dx.dK0, dx.dKN, dy.dK0, dy.dKN, dx.dM1, dy.dM1, dx.ddir, dy.ddir};
+  }
   *out = c;
   return PFD_OK;
 }
@@ -464,7 +482,7 @@ extern "C" pfd_status pfd_step(pfd_ctx* c, int nsteps, int equilibrium) {
 
 extern "C" pfd_status pfd_solve(pfd_ctx* c, int fam, const double* b, double* x) {
   if (!c || !b || !x || fam < 0 || fam > 4) return PFD_EINVAL;
-  HIPCHK(solve(c, fam, b, x, 1));
+  HIPCHK(solve(c, fam, b, x, 1, 1, nullptr));
   return PFD_OK;
 }
 

@@ -23,7 +23,9 @@ struct Dir1D {
   std::vector<double> K1, M1, S, lam, coord;
   std::vector<char> dir;            // Dirichlet flag per node
   // device copies
-  double *dS = nullptr, *dST = nullptr, *dlam = nullptr, *dK1 = nullptr, *dM1 = nullptr;
+  double *dS = nullptr, *dST = nullptr, *dlam = nullptr, *dKb = nullptr, *dM1 = nullptr;
+  double *dK0 = nullptr, *dKN = nullptr;  // first and last columns of K1 (Dirichlet lifting)
+  std::vector<double> Kb;            // banded transposed stiffness: Kb[(d+K)*N + i] = K1[i][i+d]
   float *fS = nullptr, *fST = nullptr;
   unsigned char* ddir = nullptr;
 };
@@ -55,6 +57,12 @@ struct Par {
 
 enum { F_UX = 0, F_UY, F_UZ, F_P, F_PHI, F_PSI, F_V, F_EX, F_EY, F_EZ, F_E2, F_NSTATE };
 
+// Dirichlet lifting data of one solve family (device pointers)
+struct Lift {
+  const double *Kx0, *KxN, *Ky0, *KyN, *Mx, *My;
+  const unsigned char *dirx, *diry;
+};
+
 }  // namespace pfd
 
 struct pfd_ctx {
@@ -69,6 +77,7 @@ struct pfd_ctx {
   std::vector<double> xi, w, D;            // GLL rule
   std::vector<pfd::Dir1D> dirs;            // distinct 1D operators
   pfd::Family fam[5];
+  pfd::Lift lift[5];
   std::vector<double> beta2, betad;        // per plane (spectral packing in 3D)
   double *d_beta2 = nullptr, *d_betad = nullptr;
   // device buffers
@@ -79,7 +88,9 @@ struct pfd_ctx {
   int set_old[pfd::F_NSTATE] = {};         // level n-1 explicitly set
   double* src[PFD_NSRC] = {};
   double *Lb[3] = {}, *b[3] = {}, *r = nullptr, *U = nullptr, *Q2 = nullptr;
-  double* tmp = nullptr;                   // solve intermediate (double or float)
+  double *tmp = nullptr, *tmp2 = nullptr;  // solve intermediates (double or float)
+  double* d_part = nullptr;                // per-plane partial sums
+  double Mtot = 0.0;                       // sum of the mass matrix (area)
   double* zero_buf = nullptr;              // planes*Ng zeros (u = 0 of the equilibrium system)
   double *bm_side[4] = {}, *bm_open = nullptr, *bm_wall = nullptr, *Mdiag = nullptr;
   double *d_hx = nullptr, *d_hy = nullptr, *d_w = nullptr, *d_D = nullptr;
@@ -101,7 +112,7 @@ void build_dir1d(Dir1D& d, int ne, const double* bp, int K, bool periodic, bool 
                  const std::vector<double>& D);
 
 // kernels (pfd_kernels.hip); all enqueue on ctx->stream
-hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp);
+hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp, int project, const double* r0);
 hipError_t apply(pfd_ctx* c, int fam, const double* x, double* y, int ncomp);
 hipError_t step_once(pfd_ctx* c, int equilibrium);
 hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout);

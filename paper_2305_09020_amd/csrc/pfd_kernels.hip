@@ -144,6 +144,37 @@ __device__ __forceinline__ double dss(const Geo& g, const double* L, int pl, int
   const int iy = node / g.Nx, ix = node - iy * g.Nx;                     \
   (void)pl;
 
+// Right side of a solve and its initial guess.
+//  * warm start (Fn != nullptr, FP32-refined path): x0 = extrapolated history
+//    cs_n Fn + cs_o Fo (Dirichlet data on Dirichlet nodes), so the low-precision
+//    corrections act on a small residual; the solve computes the first residual.
+//  * cold start (FP64 path): x0 = Dirichlet data x_D, zero elsewhere, and the first
+//    residual r = b - A x_D is folded in here: each family's Dirichlet set is a union of
+//    whole sides, so (A x_D) at a free node needs only the first and last columns of the
+//    1D stiffness matrices (Kx0 = Kx[:,0], KxN = Kx[:,Nx-1], likewise in y).
+__device__ __forceinline__ void rhs_out(const Geo& g, const Par& P, const Lift& L, const double* gD,
+                                        const double* Fn, const double* Fo, long id, long pofs, int ix, int iy,
+                                        double b, double* bb, double* r, double* x0) {
+  bb[id] = b;
+  const bool dn = L.dirx[ix] || L.diry[iy];
+  if (Fn) {
+    x0[id] = dn ? gD[id] : P.cs_n * Fn[id] + P.cs_o * Fo[id];
+    return;
+  }
+  if (dn) {
+    r[id] = 0.0;
+    x0[id] = gD[id];
+    return;
+  }
+  double ax = 0.0, ay = 0.0;
+  if (L.dirx[0]) ax += L.Kx0[ix] * gD[pofs + (long)iy * g.Nx];
+  if (L.dirx[g.Nx - 1]) ax += L.KxN[ix] * gD[pofs + (long)iy * g.Nx + g.Nx - 1];
+  if (L.diry[0]) ay += L.Ky0[iy] * gD[pofs + ix];
+  if (L.diry[g.Ny - 1]) ay += L.KyN[iy] * gD[pofs + (long)(g.Ny - 1) * g.Nx + ix];
+  r[id] = b - (ax * L.My[iy] + L.Mx[ix] * ay);
+  x0[id] = 0.0;
+}
+
 // =================================================================== stage V (eq. 54)
 // L0 = -int (eps(phi*) - eps0) grad V* . grad e   (element-local)
 __global__ void __launch_bounds__(WG) k_V_elem(Geo g, Par P, const double* phn, const double* pho,
@@ -167,15 +198,12 @@ __global__ void __launch_bounds__(WG) k_V_elem(Geo g, Par P, const double* phn, 
   if (act) L0[lofs] = -(0.5 * hy * s.w[b] * wdx(s, n, a, b, sgx) + 0.5 * hx * s.w[a] * wdy(s, n, a, b, sgy));
 }
 
-// b = (DSS(L0) - M f_V)/eps0 ; x0 = V* with Dirichlet values from VD
-__global__ void k_V_rhs(Geo g, Par P, const double* L0, const double* Mdiag, const double* fV,
-                        const double* Vn, const double* Vo, const double* Vd,
-                        const unsigned char* dirx, const unsigned char* diry, double* bb, double* x0) {
+// b = (DSS(L0) - M f_V)/eps0, Dirichlet values from VD
+__global__ void k_V_rhs(Geo g, Par P, Lift L, const double* L0, const double* Mdiag, const double* fV,
+                        const double* Vd, const double* Fn, const double* Fo, double* bb, double* r, double* x0) {
   NODAL_PROLOGUE
-  double v = dss(g, L0, pl, ix, iy) - Mdiag[node] * fV[id];
-  bb[id] = v / P.eps0;
-  bool d = dirx[ix] || diry[iy];
-  x0[id] = d ? Vd[id] : P.cs_n * Vn[id] + P.cs_o * Vo[id];
+  const double v = dss(g, L0, pl, ix, iy) - Mdiag[node] * fV[id];
+  rhs_out(g, P, L, Vd, Fn, Fo, id, (long)pl * g.Ng, ix, iy, v / P.eps0, bb, r, x0);
 }
 
 // =================================================================== stage E (eq. 55)
@@ -243,25 +271,37 @@ __global__ void __launch_bounds__(WG) k_psi_elem(Geo g, Par P, const double* phn
 // also stores U (reused by the phi stage) and x0 = psi*
 __global__ void k_psi_rhs(Geo g, Par P, const double* L0, const double* bmo, const double* bmw,
                           const double* g1, const double* g2, const double* g3, const double* phn,
-                          const double* pho, const double* psn, const double* pso, const double* E2,
-                          double* bb, double* U, double* Q2, double* x0) {
+                          const double* pho, const double* E2, const double* Fn, const double* Fo,
+                          double* bb, double* U, double* Q2, double* r, double* x0) {
   NODAL_PROLOGUE
   double phs = P.cs_n * phn[id] + P.cs_o * pho[id];
   double u = -g3[id] - thp_of(P, phs);
   U[id] = u;
   Q2[id] = h_of(P, phs) - P.S / (P.eta * P.eta) * phs - deps_of(P, phs) * E2[id] / (2.0 * P.lam);
-  bb[id] = dss(g, L0, pl, ix, iy) + bmo[node] * (g1[id] + P.c_psi * g2[id]) +
-           bmw[node] * (g1[id] + P.c_psi * u);
-  x0[id] = P.cs_n * psn[id] + P.cs_o * pso[id];
+  const double v = dss(g, L0, pl, ix, iy) + bmo[node] * (g1[id] + P.c_psi * g2[id]) +
+                   bmw[node] * (g1[id] + P.c_psi * u);
+  bb[id] = v;  // no Dirichlet node: cold start r = b, x0 = 0
+  if (Fn) {
+    x0[id] = P.cs_n * Fn[id] + P.cs_o * Fo[id];
+  } else {
+    r[id] = v;
+    x0[id] = 0.0;
+  }
 }
 
 // =================================================================== stage phi (eq. 57)
 __global__ void k_phi_rhs(Geo g, Par P, const double* Mdiag, const double* psi, const double* bmo,
-                          const double* bmw, const double* g2, const double* U, const double* phn,
-                          const double* pho, double* bb, double* x0) {
+                          const double* bmw, const double* g2, const double* U, const double* Fn,
+                          const double* Fo, double* bb, double* r, double* x0) {
   NODAL_PROLOGUE
-  bb[id] = -Mdiag[node] * psi[id] + bmo[node] * g2[id] + bmw[node] * U[id];
-  x0[id] = P.cs_n * phn[id] + P.cs_o * pho[id];
+  const double v = -Mdiag[node] * psi[id] + bmo[node] * g2[id] + bmw[node] * U[id];
+  bb[id] = v;  // no Dirichlet node
+  if (Fn) {
+    x0[id] = P.cs_n * Fn[id] + P.cs_o * Fo[id];
+  } else {
+    r[id] = v;
+    x0[id] = 0.0;
+  }
 }
 
 // =================================================================== momentum terms (eq. 49)
@@ -384,18 +424,15 @@ __global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi
 }
 
 // b_P = DSS(L0) - rho0 gamma0/dt sum_walls int (n.w) q ;  x0 = P* (f2 on open sides)
-__global__ void k_P_rhs(Geo g, Par P, const double* L0, const double* wx, const double* wy,
-                        const double* Pn, const double* Po, const double* f2,
-                        const unsigned char* dirx, const unsigned char* diry, double* bb, double* x0) {
+__global__ void k_P_rhs(Geo g, Par P, Lift L, const double* L0, const double* wx, const double* wy,
+                        const double* f2, const double* Fn, const double* Fo, double* bb, double* r, double* x0) {
   NODAL_PROLOGUE
   double v = dss(g, L0, pl, ix, iy);
   const double c = P.rho0 * P.gamma0 / P.dt;
   const double nw[4] = {-wy[id], wy[id], -wx[id], wx[id]};  // n.w for bottom, top, left, right
   for (int sd = 0; sd < 4; ++sd)
     if (g.side_type[sd] == PFD_WALL) v -= c * g.bm_side[sd][node] * nw[sd];
-  bb[id] = v;
-  bool d = dirx[ix] || diry[iy];
-  x0[id] = d ? f2[id] : P.cs_n * Pn[id] + P.cs_o * Po[id];
+  rhs_out(g, P, L, f2, Fn, Fo, id, (long)pl * g.Ng, ix, iy, v, bb, r, x0);
 }
 
 // u right side: add -(1/(nu_m rho0)) int grad P^{n+1} v to L1, L2
@@ -412,17 +449,14 @@ __global__ void __launch_bounds__(WG) k_gradP_elem(Geo g, Par P, const double* P
 }
 
 // b_u = DSS(L) + Bo f1 ; x0 = u* with w on walls (two components)
-__global__ void k_u_rhs(Geo g, Par P, const double* L1, const double* L2, const double* bmo,
-                        const double* f1x, const double* f1y, const double* uxn, const double* uxo,
-                        const double* uyn, const double* uyo, const double* wx, const double* wy,
-                        const unsigned char* dirx, const unsigned char* diry, double* bx, double* by,
-                        double* x0x, double* x0y) {
+__global__ void k_u_rhs(Geo g, Par P, Lift L, const double* L1, const double* L2, const double* bmo,
+                        const double* f1x, const double* f1y, const double* wx, const double* wy,
+                        const double* Fxn, const double* Fxo, const double* Fyn, const double* Fyo,
+                        double* bx, double* by, double* rx, double* ry, double* x0x, double* x0y) {
   NODAL_PROLOGUE
-  bx[id] = dss(g, L1, pl, ix, iy) + bmo[node] * f1x[id];
-  by[id] = dss(g, L2, pl, ix, iy) + bmo[node] * f1y[id];
-  bool d = dirx[ix] || diry[iy];
-  x0x[id] = d ? wx[id] : P.cs_n * uxn[id] + P.cs_o * uxo[id];
-  x0y[id] = d ? wy[id] : P.cs_n * uyn[id] + P.cs_o * uyo[id];
+  const long pofs = (long)pl * g.Ng;
+  rhs_out(g, P, L, wx, Fxn, Fxo, id, pofs, ix, iy, dss(g, L1, pl, ix, iy) + bmo[node] * f1x[id], bx, rx, x0x);
+  rhs_out(g, P, L, wy, Fyn, Fyo, id, pofs, ix, iy, dss(g, L2, pl, ix, iy) + bmo[node] * f1y[id], by, ry, x0y);
 }
 
 // non-finite guard on a field: sets status[0]
@@ -436,253 +470,277 @@ __global__ void k_check_finite(long N, const double* f, int* status) {
 
 // =================================================================== solves
 // r = b - (Kx (x) My + Mx (x) Ky + c_p Mx (x) My) x on free nodes, 0 on Dirichlet nodes.
-// With b == nullptr and sign = -1 it computes y = A x on every node (apply).
-__global__ void k_residual(int Nx, int Ny, int planes, int K, int perx, const double* Kx, const double* Mx,
-                           const unsigned char* dirx, const double* Ky, const double* My,
-                           const unsigned char* diry, const double* shift, const double* bb,
-                           const double* x, double* r, int apply_only, double* norms) {
+// The 1D stiffness matrices are stored banded and transposed: KxB[(d+K)*Nx + ix] =
+// Kx[ix][ix+d] (periodic wrap in x; zero outside the band), so consecutive threads read
+// consecutive coefficients.  apply_only = 1 computes y = A x on every node.
+template <int K>
+__global__ void k_residual(int Nx, int Ny, int planes, int perx, const double* __restrict__ KxB,
+                           const double* __restrict__ Mx, const unsigned char* __restrict__ dirx,
+                           const double* __restrict__ KyB, const double* __restrict__ My,
+                           const unsigned char* __restrict__ diry, const double* __restrict__ shift,
+                           const double* __restrict__ bb, const double* __restrict__ x, double* __restrict__ r,
+                           int apply_only, double* norms) {
   const long Ng = (long)Nx * Ny;
   const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double rr = 0.0, b2 = 0.0;
-  int pl = 0;
-  if (id < planes * Ng) {
-    pl = (int)(id / Ng);
-    const int node = (int)(id - pl * Ng);
-    const int iy = node / Nx, ix = node - iy * Nx;
-    const double* xp = x + pl * Ng;
-    double ax = 0.0, ay = 0.0;
-    // with periodic x and two elements (Nx = 2K) the offsets -K and +K reach the same node
-    const int dhi = (perx && Nx == 2 * K) ? K - 1 : K;
-    for (int d = -K; d <= dhi; ++d) {
-      int j = ix + d;
-      if (perx) { j = (j + Nx) % Nx; } else if (j < 0 || j >= Nx) continue;
-      ax += Kx[(long)ix * Nx + j] * xp[(long)iy * Nx + j];
-    }
-    for (int d = -K; d <= K; ++d) {
-      int j = iy + d;
-      if (j < 0 || j >= Ny) continue;
-      ay += Ky[(long)iy * Ny + j] * xp[(long)j * Nx + ix];
-    }
-    const double xv = xp[node];
-    const double Av = ax * My[iy] + Mx[ix] * ay + shift[pl] * Mx[ix] * My[iy] * xv;
-    if (apply_only) {
-      r[id] = Av;
-    } else {
-      const bool d = dirx[ix] || diry[iy];
-      const double v = d ? 0.0 : bb[id] - Av;
-      r[id] = v;
-      rr = v * v;
-      b2 = d ? 0.0 : bb[id] * bb[id];
-    }
+  if (id >= planes * Ng) return;
+  const int pl = (int)(id / Ng);
+  const int node = (int)(id - pl * Ng);
+  const int iy = node / Nx, ix = node - iy * Nx;
+  const double* xp = x + pl * Ng;
+  const double* xrow = xp + (long)iy * Nx;
+  double ax = 0.0, ay = 0.0;
+#pragma unroll
+  for (int d = -K; d <= K; ++d) {
+    int j = ix + d;
+    if (perx) { j = (j < 0) ? j + Nx : (j >= Nx ? j - Nx : j); } else if (j < 0 || j >= Nx) continue;
+    ax += KxB[(long)(d + K) * Nx + ix] * xrow[j];
   }
-  if (norms && id < planes * Ng) {  // diagnostics only
-    atomicAdd(&norms[2 * pl], rr);
-    atomicAdd(&norms[2 * pl + 1], b2);
+#pragma unroll
+  for (int d = -K; d <= K; ++d) {
+    const int j = iy + d;
+    if (j < 0 || j >= Ny) continue;
+    ay += KyB[(long)(d + K) * Ny + iy] * xp[(long)j * Nx + ix];
+  }
+  const double xv = xrow[ix];
+  const double Av = ax * My[iy] + Mx[ix] * ay + shift[pl] * Mx[ix] * My[iy] * xv;
+  if (apply_only) {
+    r[id] = Av;
+    return;
+  }
+  const bool dn = dirx[ix] || diry[iy];
+  const double v = dn ? 0.0 : bb[id] - Av;
+  r[id] = v;
+  if (norms) {  // diagnostics only
+    atomicAdd(&norms[2 * pl], v * v);
+    atomicAdd(&norms[2 * pl + 1], dn ? 0.0 : bb[id] * bb[id]);
   }
 }
 
-// Two chained GEMMs per (plane, column block), intermediate kept in LDS.
-//   MODE 0:  T[:, jb]  = (Lm * (In * Rm[:, jb])) ./ (ly_i + lx_j + c_p)   (0 where the denominator is 0)
-//   MODE 1:  X[:, jb] += (Lm * (In * Rm[:, jb]))
-// In: planes of Ny x Nx (TIN), Rm: Nx x Nx, Lm: Ny x Ny (compute type T, row-major).
-#define FD_NB 32
-#define FD_KC 16
-template <typename T, typename TIN, int MODE, int MR>
-__global__ void __launch_bounds__(WG) k_fdm(const TIN* __restrict__ in, const T* __restrict__ Rm,
-                                            const T* __restrict__ Lm, int Nx, int Ny,
-                                            T* __restrict__ tout, const double* __restrict__ lamx,
-                                            const double* __restrict__ lamy, const double* __restrict__ shift,
-                                            double* __restrict__ X) {
-  constexpr int ROWS = MR * 8;
-  __shared__ T sA[ROWS][FD_KC + 1];
-  __shared__ T sB[FD_KC][FD_NB + 1];
-  __shared__ T sT[ROWS][FD_NB + 1];
-  const int t = threadIdx.x;
-  const int j = t % FD_NB, rg = t / FD_NB;
-  const int j0 = blockIdx.x * FD_NB;
-  const int pl = blockIdx.y;
-  const long Ng = (long)Nx * Ny;
-  const TIN* inp = in + pl * Ng;
-  T acc[MR];
+// Batched GEMM on the matrix cores for the fast-diagonalisation passes:
+//   C[p] (M x N) = A[p] (M x K) * B[p] (K x N), row-major, plane strides sA, sB (0: shared).
+// One work-group (four waves) computes one 16x16 output tile with v_mfma_{f64,f32}_16x16x4
+// (operands straight from L2 into the MFMA register layout).  Within each 16-wide slice of K, lane
+// group g = lane/16 takes k = k0 + 4g + s at MFMA step s (s = 0..3): a permutation of the
+// contraction index applied to both operands, which makes each lane's A reads contiguous.
+// The next slice is loaded while the current one is multiplied.  Epilogues:
+//   EPI 0: C = acc
+//   EPI 1: C = acc / (lr[m] + lc[n] + shift[p])   (0 where the denominator vanishes: the
+//          constant null mode of a singular operator)
+//   EPI 2: X += acc   (FP64 accumulation of the correction)
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double V __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ V op(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator element j of lane group g holds row 4j + g (measured on gfx950)
+  static __device__ __forceinline__ int row(int g, int j) { return 4 * j + g; }
+};
+template <>
+struct Mfma<float> {
+  typedef float V __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ V op(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator element j of lane group g holds row 4g + j
+  static __device__ __forceinline__ int row(int g, int j) { return 4 * g + j; }
+};
+
+template <typename T, typename TA, typename TB, int EPI>
+__global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA, const TB* __restrict__ B, long sB,
+                                              int M, int N, int K, T* __restrict__ C, long sC,
+                                              const double* __restrict__ lr, const double* __restrict__ lc,
+                                              const double* __restrict__ shift, double* __restrict__ X) {
+  // four waves split K: wave w takes the 16-wide slices w, w+4, w+8, ... of the contraction,
+  // and the partial tiles are summed in LDS in a fixed order (deterministic)
+  __shared__ T red[4][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int n0 = blockIdx.x * 16, m0 = blockIdx.y * 16, pl = blockIdx.z;
+  const int m = m0 + r16, n = n0 + r16;
+  const bool mok = m < M, nok = n < N;
+  const TA* Arow = A + pl * sA + (long)(mok ? m : 0) * K;
+  const TB* Bcol = B + pl * sB + (nok ? n : 0);
+  typename Mfma<T>::V acc = {T(0), T(0), T(0), T(0)};
+  T a[4], b[4], an[4], bn[4];
+  const int kstart = 16 * w;
 #pragma unroll
-  for (int m = 0; m < MR; ++m) acc[m] = T(0);
-  // phase 1: T1 = In * Rm[:, j0:j0+NB]
-  for (int kc = 0; kc < Nx; kc += FD_KC) {
-    for (int i = t; i < ROWS * FD_KC; i += WG) {
-      int r = i / FD_KC, k = i % FD_KC;
-      sA[r][k] = (r < Ny && kc + k < Nx) ? T(inp[(long)r * Nx + kc + k]) : T(0);
-    }
-    for (int i = t; i < FD_KC * FD_NB; i += WG) {
-      int k = i / FD_NB, jj = i % FD_NB;
-      sB[k][jj] = (kc + k < Nx && j0 + jj < Nx) ? Rm[(long)(kc + k) * Nx + j0 + jj] : T(0);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < FD_KC; ++k) {
-      const T bv = sB[k][j];
+  for (int s = 0; s < 4; ++s) {
+    const int k = kstart + 4 * g + s;
+    a[s] = (mok && k < K) ? T(Arow[k]) : T(0);
+    b[s] = (nok && k < K) ? T(Bcol[(long)k * N]) : T(0);
+  }
+  for (int k0 = kstart; k0 < K; k0 += 64) {
+    const int k1 = k0 + 64;
 #pragma unroll
-      for (int m = 0; m < MR; ++m) acc[m] += sA[rg + 8 * m][k] * bv;
+    for (int s = 0; s < 4; ++s) {
+      const int k = k1 + 4 * g + s;
+      an[s] = (mok && k < K) ? T(Arow[k]) : T(0);
+      bn[s] = (nok && k < K) ? T(Bcol[(long)k * N]) : T(0);
     }
-    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = Mfma<T>::op(a[s], b[s], acc);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      a[s] = an[s];
+      b[s] = bn[s];
+    }
   }
 #pragma unroll
-  for (int m = 0; m < MR; ++m) {
-    sT[rg + 8 * m][j] = acc[m];
-    acc[m] = T(0);
-  }
+  for (int j = 0; j < 4; ++j) red[w][j][lane] = acc[j];
   __syncthreads();
-  // phase 2: Out = Lm * T1
-  for (int kc = 0; kc < Ny; kc += FD_KC) {
-    for (int i = t; i < ROWS * FD_KC; i += WG) {
-      int r = i / FD_KC, k = i % FD_KC;
-      sA[r][k] = (r < Ny && kc + k < Ny) ? Lm[(long)r * Ny + kc + k] : T(0);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < FD_KC; ++k) {
-      const T bv = (kc + k < ROWS) ? sT[kc + k][j] : T(0);
+  if (w != 0) return;
+  // accumulator layout: lane (g, r16) holds column r16 of four rows (Mfma<T>::row)
 #pragma unroll
-      for (int m = 0; m < MR; ++m) acc[m] += sA[rg + 8 * m][k] * bv;
-    }
-    __syncthreads();
-  }
-  const int jj = j0 + j;
-  if (jj >= Nx) return;
-#pragma unroll
-  for (int m = 0; m < MR; ++m) {
-    const int i = rg + 8 * m;
-    if (i >= Ny) continue;
-    if (MODE == 0) {
-      const double den = lamy[i] + lamx[jj] + shift[pl];
-      tout[pl * Ng + (long)i * Nx + jj] = (den != 0.0) ? T(double(acc[m]) / den) : T(0);
+  for (int j = 0; j < 4; ++j) {
+    const T v = ((red[0][j][lane] + red[1][j][lane]) + red[2][j][lane]) + red[3][j][lane];
+    const int mm = m0 + Mfma<T>::row(g, j);
+    if (mm >= M || !nok) continue;
+    const long o = pl * sC + (long)mm * N + n;
+    if (EPI == 0) {
+      C[o] = v;
+    } else if (EPI == 1) {
+      const double den = lr[mm] + lc[n] + shift[pl];
+      C[o] = (den != 0.0) ? T(double(v) / den) : T(0);
     } else {
-      X[pl * Ng + (long)i * Nx + jj] += double(acc[m]);
+      X[o] += double(v);
     }
   }
 }
 
-template <typename T, typename TIN, int MODE>
-static void launch_fdm(int MRneed, dim3 grid, hipStream_t st, const TIN* in, const T* Rm, const T* Lm,
-                       int Nx, int Ny, T* tout, const double* lamx, const double* lamy,
-                       const double* shift, double* X) {
-#define FD_CASE(MRV)                                                                              \
-  if (MRneed <= MRV) {                                                                            \
-    hipLaunchKernelGGL((k_fdm<T, TIN, MODE, MRV>), grid, dim3(WG), 0, st, in, Rm, Lm, Nx, Ny,     \
-                       tout, lamx, lamy, shift, X);                                               \
-    return;                                                                                       \
-  }
-  FD_CASE(4) FD_CASE(8) FD_CASE(12) FD_CASE(16) FD_CASE(20) FD_CASE(24) FD_CASE(32) FD_CASE(40)
-#undef FD_CASE
+template <typename T, typename TA, typename TB, int EPI>
+static void gemm(hipStream_t st, int planes, const TA* A, long sA, const TB* B, long sB, int M, int N, int K,
+                 T* C, long sC, const double* lr, const double* lc, const double* shift, double* X) {
+  dim3 grid((N + 15) / 16, (M + 15) / 16, planes);
+  hipLaunchKernelGGL((k_gemm<T, TA, TB, EPI>), grid, dim3(256), 0, st, A, sA, B, sB, M, N, K, C, sC, lr, lc,
+                     shift, X);
 }
 
-// range projection of a right side for singular planes: r -= (sum r / sum M) M
-__global__ void k_project(long Ng, const double* Mdiag, const double* shift, double* r) {
-  const int pl = blockIdx.x;
-  if (shift[pl] != 0.0) return;
-  __shared__ double sm[WG], sw[WG];
-  double a = 0.0, m = 0.0;
-  double* rp = r + pl * Ng;
-  for (long i = threadIdx.x; i < Ng; i += WG) {
-    a += rp[i];
-    m += Mdiag[i];
+// Deterministic per-plane sums: part[p*PCH + blk] = sum over chunk blk of w_i f_i
+// (w = M when weighted, else 1), for planes whose shift is 0 (singular operators).
+// k_plane_sub then subtracts, per plane:
+//   mode 0 (gauge int_h f = 0):    f -= (sum M f)/(sum M)
+//   mode 1 (range projection):     f -= (sum f)/(sum M) * M
+#define PCH 32
+__global__ void k_plane_sums(long Ng, const double* __restrict__ Mdiag, const double* __restrict__ shift,
+                             const double* __restrict__ f, int weighted, double* __restrict__ part) {
+  const int blk = blockIdx.x, pl = blockIdx.y;
+  __shared__ double sm[WG];
+  double a = 0.0;
+  if (shift[pl] == 0.0) {
+    const long chunk = (Ng + PCH - 1) / PCH;
+    const long i0 = blk * chunk, i1 = min(Ng, i0 + chunk);
+    const double* fp = f + pl * Ng;
+    for (long i = i0 + threadIdx.x; i < i1; i += WG) a += weighted ? Mdiag[i] * fp[i] : fp[i];
   }
   sm[threadIdx.x] = a;
-  sw[threadIdx.x] = m;
   __syncthreads();
   for (int o = WG / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      sm[threadIdx.x] += sm[threadIdx.x + o];
-      sw[threadIdx.x] += sw[threadIdx.x + o];
-    }
+    if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
     __syncthreads();
   }
-  const double c = sm[0] / sw[0];
-  for (long i = threadIdx.x; i < Ng; i += WG) rp[i] -= c * Mdiag[i];
+  if (threadIdx.x == 0) part[pl * PCH + blk] = sm[0];
 }
 
-// mean removal for singular planes: x -= (sum M x / sum M)
-__global__ void k_mean_remove(long Ng, const double* Mdiag, const double* shift, double* x) {
-  const int pl = blockIdx.x;
+__global__ void k_plane_sub(long Ng, int planes, const double* __restrict__ Mdiag, const double* __restrict__ shift,
+                            const double* __restrict__ part, double Mtot, int mode, double* __restrict__ f) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= planes * Ng) return;
+  const int pl = (int)(id / Ng);
   if (shift[pl] != 0.0) return;
-  __shared__ double sm[WG], sw[WG];
-  double a = 0.0, m = 0.0;
-  double* xp = x + pl * Ng;
-  for (long i = threadIdx.x; i < Ng; i += WG) {
-    a += Mdiag[i] * xp[i];
-    m += Mdiag[i];
-  }
-  sm[threadIdx.x] = a;
-  sw[threadIdx.x] = m;
-  __syncthreads();
-  for (int o = WG / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      sm[threadIdx.x] += sm[threadIdx.x + o];
-      sw[threadIdx.x] += sw[threadIdx.x + o];
-    }
-    __syncthreads();
-  }
-  const double mean = sm[0] / sw[0];
-  for (long i = threadIdx.x; i < Ng; i += WG) xp[i] -= mean;
+  double s = 0.0;
+  for (int b = 0; b < PCH; ++b) s += part[pl * PCH + b];
+  const long i = id - pl * Ng;
+  f[id] -= (mode == 0) ? s / Mtot : s / Mtot * Mdiag[i];
 }
 
 static inline unsigned nblk(long n) { return (unsigned)((n + WG - 1) / WG); }
 
-hipError_t apply(pfd_ctx* c, int fam, const double* x, double* y, int ncomp) {
+static void plane_fix(pfd_ctx* c, int fam, double* f, int mode) {
+  Family& F = c->fam[fam];
+  const long tot = (long)c->planes * c->Ng;
+  hipLaunchKernelGGL(k_plane_sums, dim3(PCH, c->planes), dim3(WG), 0, c->stream, c->Ng, c->Mdiag, F.dshift, f,
+                     mode == 0 ? 1 : 0, c->d_part);
+  hipLaunchKernelGGL(k_plane_sub, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Ng, c->planes, c->Mdiag, F.dshift,
+                     c->d_part, c->Mtot, mode, f);
+}
+
+static void residual(pfd_ctx* c, int fam, const double* b, const double* x, double* r, int apply_only,
+                     double* norms) {
   Family& F = c->fam[fam];
   Dir1D& dx = c->dirs[F.ix];
   Dir1D& dy = c->dirs[F.iy];
-  for (int comp = 0; comp < ncomp; ++comp) {
-    long off = (long)comp * c->planes * c->Ng;
-    hipLaunchKernelGGL(k_residual, dim3(nblk((long)c->planes * c->Ng)), dim3(WG), 0, c->stream, c->Nx,
-                       c->Ny, c->planes, c->K, (int)dx.periodic, dx.dK1, dx.dM1, dx.ddir, dy.dK1, dy.dM1,
-                       dy.ddir, F.dshift, nullptr, x + off, y + off, 1, nullptr);
+  const long tot = (long)c->planes * c->Ng;
+#define RES_CASE(KK)                                                                                      \
+  case KK:                                                                                                \
+    hipLaunchKernelGGL(k_residual<KK>, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->planes,   \
+                       (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, F.dshift, b, x, r, \
+                       apply_only, norms);                                                                \
+    break;
+  switch (c->K) {
+    RES_CASE(2) RES_CASE(3) RES_CASE(4) RES_CASE(5) RES_CASE(6) RES_CASE(7) RES_CASE(8) RES_CASE(9)
+    RES_CASE(10) RES_CASE(11) RES_CASE(12) RES_CASE(13) RES_CASE(14) RES_CASE(15) RES_CASE(16)
   }
+#undef RES_CASE
+}
+
+hipError_t apply(pfd_ctx* c, int fam, const double* x, double* y, int ncomp) {
+  const long tot = (long)c->planes * c->Ng;
+  for (int comp = 0; comp < ncomp; ++comp) residual(c, fam, nullptr, x + comp * tot, y + comp * tot, 1, nullptr);
   return hipGetLastError();
 }
 
-// Solve (K + c M) x = b for ncomp stacked right sides (each planes*Ng), x holding
-// the initial guess and Dirichlet values.
-hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp) {
+// Fast-diagonalisation correction  x += Sy [ (Sy^T r Sx) ./ (ly_i + lx_j + c_p) ] Sx^T
+// as four batched GEMMs over all planes (Sx, Sy shared by every plane).
+template <typename T>
+static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const double* shift, const T* Sx,
+                        const T* SxT, const T* Sy, const T* SyT, const double* r, double* x) {
+  const int Nx = c->Nx, Ny = c->Ny, P = c->planes;
+  const long Ng = c->Ng;
+  T* t1 = reinterpret_cast<T*>(c->tmp);
+  T* t2 = reinterpret_cast<T*>(c->tmp2);
+  hipStream_t st = c->stream;
+  gemm<T, double, T, 0>(st, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr, nullptr, nullptr);
+  gemm<T, T, T, 1>(st, P, SyT, 0, t1, Ng, Ny, Nx, Ny, t2, Ng, dy.dlam, dx.dlam, shift, nullptr);
+  gemm<T, T, T, 0>(st, P, Sy, 0, t2, Ng, Ny, Nx, Ny, t1, Ng, nullptr, nullptr, nullptr, nullptr);
+  gemm<T, T, T, 2>(st, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr, nullptr, nullptr, x);
+}
+
+// Solve (K + c M) x = b for ncomp stacked right sides (each planes*Ng), x holding the initial
+// guess and the Dirichlet values.  r0 != nullptr: the first residual b - A x is given
+// (stacked like b).  project != 0: the right side may be incompatible on singular planes
+// (general entry point) and the initial guess arbitrary, so the residual is projected and
+// the gauge int_h x = 0 imposed; the step's own right sides are compatible and start
+// from x0 = x_D, whose corrections keep int_h x = 0 up to rounding.
+hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp, int project, const double* r0) {
   Family& F = c->fam[fam];
   Dir1D& dx = c->dirs[F.ix];
   Dir1D& dy = c->dirs[F.iy];
-  const int Nx = c->Nx, Ny = c->Ny;
   const long tot = (long)c->planes * c->Ng;
   const bool fp32 = c->prob.precision == PFD_REFINED_FP32;
   const int iters = fp32 ? (c->prob.refine_iters > 0 ? c->prob.refine_iters : 2) : 1;
-  const int MRneed = (Ny + 7) / 8;
-  dim3 grid((Nx + FD_NB - 1) / FD_NB, c->planes);
   for (int comp = 0; comp < ncomp; ++comp) {
     const double* bc = b + comp * tot;
     double* xc = x + comp * tot;
     for (int it = 0; it < iters; ++it) {
-      hipLaunchKernelGGL(k_residual, dim3(nblk(tot)), dim3(WG), 0, c->stream, Nx, Ny, c->planes, c->K,
-                         (int)dx.periodic, dx.dK1, dx.dM1, dx.ddir, dy.dK1, dy.dM1, dy.ddir, F.dshift, bc,
-                         xc, c->r, 0, nullptr);
-      // singular planes: keep only the compatible part of the residual (in FP64), so the
-      // low-precision null column cannot leak the incompatible part into other modes
-      if (F.any_singular)
-        hipLaunchKernelGGL(k_project, dim3(c->planes), dim3(WG), 0, c->stream, c->Ng, c->Mdiag, F.dshift, c->r);
-      if (fp32) {
-        float* tf = reinterpret_cast<float*>(c->tmp);
-        launch_fdm<float, double, 0>(MRneed, grid, c->stream, c->r, dx.fS, dy.fST, Nx, Ny, tf, dx.dlam,
-                                     dy.dlam, F.dshift, nullptr);
-        launch_fdm<float, float, 1>(MRneed, grid, c->stream, tf, dx.fST, dy.fS, Nx, Ny, nullptr, nullptr,
-                                    nullptr, nullptr, xc);
+      const double* rin = c->r;
+      if (it == 0 && r0) {
+        rin = r0 + comp * tot;
       } else {
-        launch_fdm<double, double, 0>(MRneed, grid, c->stream, c->r, dx.dS, dy.dST, Nx, Ny, c->tmp, dx.dlam,
-                                      dy.dlam, F.dshift, nullptr);
-        launch_fdm<double, double, 1>(MRneed, grid, c->stream, c->tmp, dx.dST, dy.dS, Nx, Ny, nullptr,
-                                      nullptr, nullptr, nullptr, xc);
+        residual(c, fam, bc, xc, c->r, 0, nullptr);
+        if (F.any_singular && project) plane_fix(c, fam, c->r, 1);
       }
+      if (fp32)
+        fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, rin, xc);
+      else
+        fdm_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, rin, xc);
     }
-    if (F.any_singular)
-      hipLaunchKernelGGL(k_mean_remove, dim3(c->planes), dim3(WG), 0, c->stream, c->Ng, c->Mdiag, F.dshift, xc);
+    if (F.any_singular && (project || fp32)) plane_fix(c, fam, xc, 0);
     if (c->check_residual) {
       hipMemsetAsync(c->d_norms, 0, sizeof(double) * 2 * c->planes, c->stream);
-      hipLaunchKernelGGL(k_residual, dim3(nblk(tot)), dim3(WG), 0, c->stream, Nx, Ny, c->planes, c->K,
-                         (int)dx.periodic, dx.dK1, dx.dM1, dx.ddir, dy.dK1, dy.dM1, dy.ddir, F.dshift, bc,
-                         xc, c->r, 0, c->d_norms);
+      residual(c, fam, bc, xc, c->r, 0, c->d_norms);
       std::vector<double> h(2 * c->planes);
       hipMemcpyAsync(h.data(), c->d_norms, sizeof(double) * 2 * c->planes, hipMemcpyDeviceToHost, c->stream);
       hipStreamSynchronize(c->stream);
@@ -719,10 +777,14 @@ hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout) {
   const double* ph = FLD(F_PHI, 0);
   Dir1D& dx = c->dirs[c->fam[PFD_FAM_V].ix];
   Dir1D& dy = c->dirs[c->fam[PFD_FAM_V].iy];
+  (void)dx;
+  (void)dy;
   hipLaunchKernelGGL(k_V_elem, eg, eb, 0, c->stream, g, P, ph, ph, Vin, Vin, c->Lb[0]);
-  hipLaunchKernelGGL(k_V_rhs, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, P, c->Lb[0], c->Mdiag,
-                     c->src[PFD_SRC_FV], Vin, Vin, c->src[PFD_SRC_VD], dx.ddir, dy.ddir, c->b[0], Vout);
-  return solve(c, PFD_FAM_V, c->b[0], Vout, 1);
+  const bool warm = c->prob.precision == PFD_REFINED_FP32;
+  hipLaunchKernelGGL(k_V_rhs, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, P, c->lift[PFD_FAM_V], c->Lb[0],
+                     c->Mdiag, c->src[PFD_SRC_FV], c->src[PFD_SRC_VD], warm ? Vin : nullptr, Vin, c->b[0], c->r,
+                     Vout);
+  return solve(c, PFD_FAM_V, c->b[0], Vout, 1, 0, warm ? nullptr : c->r);
 }
 
 hipError_t step_once(pfd_ctx* c, int equilibrium) {
@@ -733,6 +795,11 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
   const dim3 ng(nblk(tot)), nb(WG);
   hipStream_t st = c->stream;
   const int nw = 1 - c->cur;  // level n+1 overwrites level n-1
+  // FP32-refined solves start from the extrapolated history (warm), FP64 ones from the
+  // Dirichlet data with the first residual folded into the right-side kernels (cold)
+  const bool warm = c->prob.precision == PFD_REFINED_FP32;
+  auto H = [&](int f, int lv) -> const double* { return warm ? FLD(f, lv) : nullptr; };
+  double* r0 = warm ? nullptr : c->r;
   double* const* S = c->src;
   // ---- V (eq. 54)
   {
@@ -740,9 +807,11 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
     Dir1D& dy = c->dirs[c->fam[PFD_FAM_V].iy];
     hipLaunchKernelGGL(k_V_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), FLD(F_V, 0), FLD(F_V, -1),
                        c->Lb[0]);
-    hipLaunchKernelGGL(k_V_rhs, ng, nb, 0, st, g, P, c->Lb[0], c->Mdiag, S[PFD_SRC_FV], FLD(F_V, 0),
-                       FLD(F_V, -1), S[PFD_SRC_VD], dx.ddir, dy.ddir, c->b[0], c->fld[F_V][nw]);
-    solve(c, PFD_FAM_V, c->b[0], c->fld[F_V][nw], 1);
+    (void)dx;
+    (void)dy;
+    hipLaunchKernelGGL(k_V_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_V], c->Lb[0], c->Mdiag, S[PFD_SRC_FV],
+                       S[PFD_SRC_VD], H(F_V, 0), H(F_V, -1), c->b[0], c->r, c->fld[F_V][nw]);
+    solve(c, PFD_FAM_V, c->b[0], c->fld[F_V][nw], 1, 0, r0);
   }
   // ---- E (eq. 55)
   hipLaunchKernelGGL(k_E_elem, eg, eb, 0, st, g, c->fld[F_V][nw], c->Lb[0], c->Lb[1]);
@@ -758,13 +827,13 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
   hipLaunchKernelGGL(k_psi_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), uxn, uxo, uyn, uyo, E2,
                      S[PFD_SRC_G], c->Lb[0]);
   hipLaunchKernelGGL(k_psi_rhs, ng, nb, 0, st, g, P, c->Lb[0], c->bm_open, c->bm_wall, S[PFD_SRC_G1],
-                     S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), FLD(F_PSI, 0), FLD(F_PSI, -1),
-                     E2, c->b[0], c->U, c->Q2, c->fld[F_PSI][nw]);
-  solve(c, PFD_FAM_PSI, c->b[0], c->fld[F_PSI][nw], 1);
+                     S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), E2, H(F_PSI, 0), H(F_PSI, -1),
+                     c->b[0], c->U, c->Q2, c->r, c->fld[F_PSI][nw]);
+  solve(c, PFD_FAM_PSI, c->b[0], c->fld[F_PSI][nw], 1, 0, r0);
   // ---- phi (eq. 57)
   hipLaunchKernelGGL(k_phi_rhs, ng, nb, 0, st, g, P, c->Mdiag, c->fld[F_PSI][nw], c->bm_open, c->bm_wall,
-                     S[PFD_SRC_G2], c->U, FLD(F_PHI, 0), FLD(F_PHI, -1), c->b[0], c->fld[F_PHI][nw]);
-  solve(c, PFD_FAM_PHI, c->b[0], c->fld[F_PHI][nw], 1);
+                     S[PFD_SRC_G2], c->U, H(F_PHI, 0), H(F_PHI, -1), c->b[0], c->r, c->fld[F_PHI][nw]);
+  solve(c, PFD_FAM_PHI, c->b[0], c->fld[F_PHI][nw], 1, 0, r0);
   if (equilibrium) {
     hipMemsetAsync(c->fld[F_UX][nw], 0, sizeof(double) * tot, st);
     hipMemsetAsync(c->fld[F_UY][nw], 0, sizeof(double) * tot, st);
@@ -775,21 +844,17 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
     hipLaunchKernelGGL(k_mom_elem, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
                        FLD(F_UX, 0), FLD(F_UX, -1), FLD(F_UY, 0), FLD(F_UY, -1), FLD(F_P, 0),
                        FLD(F_P, -1), S[PFD_SRC_FX], S[PFD_SRC_FY], c->Lb[0], c->Lb[1], c->Lb[2]);
-    Dir1D& px = c->dirs[c->fam[PFD_FAM_P].ix];
-    Dir1D& py = c->dirs[c->fam[PFD_FAM_P].iy];
-    hipLaunchKernelGGL(k_P_rhs, ng, nb, 0, st, g, P, c->Lb[0], S[PFD_SRC_WX], S[PFD_SRC_WY], FLD(F_P, 0),
-                       FLD(F_P, -1), S[PFD_SRC_F2], px.ddir, py.ddir, c->b[0], c->fld[F_P][nw]);
-    solve(c, PFD_FAM_P, c->b[0], c->fld[F_P][nw], 1);
+    hipLaunchKernelGGL(k_P_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_P], c->Lb[0], S[PFD_SRC_WX], S[PFD_SRC_WY],
+                       S[PFD_SRC_F2], H(F_P, 0), H(F_P, -1), c->b[0], c->r, c->fld[F_P][nw]);
+    solve(c, PFD_FAM_P, c->b[0], c->fld[F_P][nw], 1, 0, r0);
     // ---- u (eq. 59)
     hipLaunchKernelGGL(k_gradP_elem, eg, eb, 0, st, g, P, c->fld[F_P][nw], c->Lb[1], c->Lb[2]);
-    Dir1D& ux = c->dirs[c->fam[PFD_FAM_U].ix];
-    Dir1D& uy = c->dirs[c->fam[PFD_FAM_U].iy];
-    // the two components are solved as one stacked right side: b[0..1], x in fld UX/UY
-    hipLaunchKernelGGL(k_u_rhs, ng, nb, 0, st, g, P, c->Lb[1], c->Lb[2], c->bm_open, S[PFD_SRC_F1X],
-                       S[PFD_SRC_F1Y], FLD(F_UX, 0), FLD(F_UX, -1), FLD(F_UY, 0), FLD(F_UY, -1), S[PFD_SRC_WX],
-                       S[PFD_SRC_WY], ux.ddir, uy.ddir, c->b[1], c->b[2], c->fld[F_UX][nw], c->fld[F_UY][nw]);
-    solve(c, PFD_FAM_U, c->b[1], c->fld[F_UX][nw], 1);
-    solve(c, PFD_FAM_U, c->b[2], c->fld[F_UY][nw], 1);
+    hipLaunchKernelGGL(k_u_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_U], c->Lb[1], c->Lb[2], c->bm_open,
+                       S[PFD_SRC_F1X], S[PFD_SRC_F1Y], S[PFD_SRC_WX], S[PFD_SRC_WY], H(F_UX, 0), H(F_UX, -1),
+                       H(F_UY, 0), H(F_UY, -1), c->b[1], c->b[2], c->r, c->r + tot, c->fld[F_UX][nw],
+                       c->fld[F_UY][nw]);
+    solve(c, PFD_FAM_U, c->b[1], c->fld[F_UX][nw], 1, 0, r0);
+    solve(c, PFD_FAM_U, c->b[2], c->fld[F_UY][nw], 1, 0, warm ? nullptr : c->r + tot);
   }
   hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
   if (!equilibrium)

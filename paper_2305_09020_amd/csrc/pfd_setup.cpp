@@ -197,6 +197,17 @@ void build_dir1d(Dir1D& d, int ne, const double* bp, int K, bool periodic, bool 
     for (int i = 0; i < N; ++i) d.S[(size_t)i * N + 0] = 1.0 / std::sqrt(tot);
   }
   d.nfree = m;
+  // banded, transposed copy of the stiffness for the residual kernel
+  d.Kb.assign((size_t)(2 * K + 1) * N, 0.0);
+  for (int i = 0; i < N; ++i) {
+    const int dhi = (periodic && N == 2 * K) ? K - 1 : K;  // two periodic elements: -K and +K coincide
+    for (int dd = -K; dd <= dhi; ++dd) {
+      int j = i + dd;
+      if (periodic) j = (j + N) % N;
+      else if (j < 0 || j >= N) continue;
+      d.Kb[(size_t)(dd + K) * N + i] = d.K1[(size_t)i * N + j];
+    }
+  }
 }
 
 }  // namespace pfd

@@ -40,7 +40,7 @@ def c1_param_dict(dt=1e-4):
 
 def c2_param_dict(dt=5e-5):
     eta = 0.01
-    return dict(rho1=1.0, rho2=1000.0, mu1=0.01, mu2=1.0, eps1=1.0, eps2=40.0,
+    return dict(rho1=1.0, rho2=1000.0, mu1=0.01, mu2=1.0, eps1=0.025, eps2=1.0,
                 lam=lam_from_sigma(1.0, eta), eta=eta, gamma1=1e-4, theta_s_deg=90.0, dt=dt)
 
 

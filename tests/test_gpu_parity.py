@@ -62,10 +62,10 @@ def test_solve_matches_sparse_lu(periodic, top, precision):
 
 # ------------------------------------------------------------- full-step parity
 def run_pair(m, par, bc, phi0, u0, src, nsteps, nbatch=1, precision=0, equilibrium=False,
-             per_step_src=None, init_V=True, V0=None, prev=None, P0=None):
+             per_step_src=None, init_V=True, V0=None, prev=None, P0=None, refine_iters=2):
     """Run the oracle and the library side by side; returns list of (oracle, gpu) field dicts."""
     _torch()
-    ctx = gpu_context(m, par, bc, nbatch=nbatch, precision=precision, refine_iters=3)
+    ctx = gpu_context(m, par, bc, nbatch=nbatch, precision=precision, refine_iters=refine_iters)
     schs = []
     for ib in range(nbatch):
         s = Scheme(m, par, bc)
@@ -111,14 +111,17 @@ def run_pair(m, par, bc, phi0, u0, src, nsteps, nbatch=1, precision=0, equilibri
     return out, ctx
 
 
-def check_parity(out, tol, fields=FIELDS):
+def check_parity(out, tol, fields=FIELDS, field_tol=None):
+    """Relative 2-norm error per field, worst over the steps; field_tol overrides tol."""
     worst = {}
     for (of, gf) in out:
         for k in fields:
             scale = max(np.linalg.norm(of[k]), 1e-12 * np.linalg.norm(of["phi"]))
             e = np.linalg.norm(gf[k] - of[k]) / scale
             worst[k] = max(worst.get(k, 0.0), e)
-    bad = {k: v for k, v in worst.items() if not v < tol}
+    lim = {k: (field_tol or {}).get(k, tol) for k in worst}
+    print("parity", {k: "%.2e" % v for k, v in worst.items()})
+    bad = {k: v for k, v in worst.items() if not v < lim[k]}
     assert not bad, (bad, worst)
     return worst
 
@@ -133,13 +136,37 @@ def test_c1_drop_step_parity_fp64():
     check_parity(out, 1e-10)
 
 
-def test_c1_drop_step_parity_refined_fp32():
-    """Same with FP32 solves + FP64 iterative refinement: 1e-8 per field."""
+@pytest.mark.parametrize("iters", [2, 3])
+def test_c1_drop_step_parity_refined_fp32(iters):
+    """Same with FP32 solves + FP64 iterative refinement (warm start, 2 or 3
+    corrections per solve): 1e-8 per field."""
     m, bc, par = box_case(n=4, K=6)
     phi0 = drop_field(m.X, m.Y, (0.5, 0.5), 0.25, par.eta)
     vd = np.where(np.isclose(m.Y, 1.0), 1.0, 0.0)
-    out, ctx = run_pair(m, par, bc, phi0, None, dict(Vd=vd), 10, precision=1)
+    out, ctx = run_pair(m, par, bc, phi0, None, dict(Vd=vd), 10, precision=1, refine_iters=iters)
     check_parity(out, 1e-8)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-8)])
+def test_benchmark_workload_parity(precision, tol):
+    """The benchmark workload (20x20 elements, K = 8, sessile drop, rho 1:1000, mu 1:100,
+    eps 1:40) at full size: two of its instances (V_top = 0.5 and 2) in one context,
+    every field after each of 6 steps.  FP64 path 1e-9, FP32-refined path (the
+    benchmark's 2 corrections) 1e-8.  The velocity starts from rest and is ~1e-5 after a
+    few steps while the O(1-100) pressure and inertia terms of its equation nearly cancel,
+    so rounding differences between the two FP64 implementations appear ~1e-9 relative
+    to |u|: u is held to the 1e-8 bound on both paths."""
+    from cases import c2_params
+    from synth import C2
+    par = c2_params()
+    xb = np.linspace(0.0, 1.0, C2["nx"] + 1)
+    m = Mesh2D(xb, xb, C2["K"])
+    bc = BCs(side={BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}, pot_sides=(BOTTOM, TOP))
+    phi1 = drop_field(m.X, m.Y, C2["center"], C2["r"], par.eta)
+    vd = np.stack([np.where(np.isclose(m.Y, 1.0), v, 0.0) for v in (0.5, 2.0)])
+    out, ctx = run_pair(m, par, bc, np.stack([phi1] * 2), None, dict(Vd=vd), 6, nbatch=2,
+                        precision=precision, refine_iters=2)
+    check_parity(out, tol, field_tol=dict(ux=1e-8, uy=1e-8))
 
 
 def test_batched_instances_equal_oracle_runs():
