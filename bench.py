@@ -15,11 +15,16 @@ FP32-refined path (FP32 fast-diagonalisation solves + FP64 residual iterative
 refinement) is the reported value; the plain FP64 path is timed beside it.
 
 One JSON line is printed.  Extra keys:
-  roofline      dominant kernel (FP32 or FP64 fast-diagonalisation pass) against the
-                vector-ALU peak of its precision, from per-kernel HIP-event timing
-                done inside the library on its stream (pfd_time_kernel);
+  roofline      the dominant kernel class of the reported path, from HIP events the
+                library records on its own stream around every launch during a second
+                run of the same steps (pfd_profile_enable / pfd_profile_read):
+                  fast-diagonalisation GEMM passes: algorithmic flops per launch
+                    = Ny*Nx*(Nx+Ny)*planes (mean of the four passes 2*Ny*Nx*K*planes),
+                    against the dense MFMA peak of their precision;
+                  residual: algorithmic bytes per launch = 24*planes*Ny*Nx (read b, x;
+                    write r), against HBM bandwidth;
   cpu_baseline  the FP64 oracle (NumPy/SciPy) on a bounded sample of the same
-                workload (one instance, a few steps after its one-time LU set-up).
+                workload (one instance, some steps after its one-time LU set-up).
 """
 import argparse
 import json
@@ -71,7 +76,55 @@ def time_steps(ctx, steps, warmup):
     return e0.elapsed_time(e1) / 1e3
 
 
-def cpu_baseline(nsteps=8):
+PEAK = {"gemm64": (78.6e12, "TFLOP/s", "mfma"), "gemm32": (157.3e12, "TFLOP/s", "mfma"),
+        "residual": (8.0e12, "GB/s", "hbm")}
+
+
+def roofline(ctx, steps):
+    """Per-class kernel time over `steps` instrumented steps; roofline of the dominant
+    class among those with an algorithmic per-launch figure."""
+    ctx.profile_enable(True)
+    ctx.step_async(steps)
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    tot = {k: v for k, v in prof.items() if v[1] > 0}
+    dom = max((k for k in tot if k in PEAK), key=lambda k: tot[k][0])
+    ms, n = tot[dom]
+    avg = ctx.profile_replay(dom, 200) * 1e-6     # back-to-back replay, no per-launch events
+    avg_bracketed = ms / 1e3 / n
+    P, Nx, Ny = ctx.planes, ctx.Nx, ctx.Ny
+    if dom.startswith("gemm"):
+        per = float(Ny * Nx * (Nx + Ny) * P)
+        achieved = per / avg / 1e12
+        peak = PEAK[dom][0] / 1e12
+    else:
+        per = float(24 * P * Nx * Ny)
+        achieved = per / avg / 1e9
+        peak = PEAK[dom][0] / 1e9
+    share = {k: round(v[0] / sum(x[0] for x in tot.values()), 4) for k, v in tot.items()}
+    return {"bound": PEAK[dom][2], "achieved": achieved, "peak": peak, "unit": PEAK[dom][1],
+            "frac": achieved / peak, "traffic": traffic(dom, per), "kernel": dom,
+            "avg_launch_us": avg * 1e6, "avg_launch_us_event_bracketed": avg_bracketed * 1e6,
+            "launches_per_step": n / steps, "per_launch": per, "class_time_share": share}
+
+
+def traffic(dom, per):
+    """HBM bytes per launch of the class from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, scaled by a plain copy kernel), only while the
+    kernel source is the one the counters were taken on; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "fdm_gemm_c2_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2305_09020_amd", "csrc", "pfd_kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    cls = rec.get("classes", {}).get(dom)
+    return None if cls is None else cls["hbm_bytes_per_launch"]
+
+
+def cpu_baseline(nsteps=40):
     """The FP64 oracle on one instance of the workload (V_top = 1): a few steps after
     its one-time sparse-LU factorisation (timed separately, not included)."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -107,7 +160,19 @@ def main():
     ap.add_argument("--refine-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["refined", "fp64", "both"], default="both")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy 5 times (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     a = ap.parse_args()
+    if a.calibrate_copy:
+        import torch
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copied 5 x %d bytes" % (src.numel() * 8))
+        return
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the step would shard by Fourier mode in 3D; see the design notes)", file=sys.stderr)
@@ -122,7 +187,8 @@ def main():
         ctx, its = make_context(prec, a.refine_iters)
         t = time_steps(ctx, a.steps, a.warmup)
         dof = ctx.planes * ctx.Nx * ctx.Ny
-        res[name] = dict(t=t, dof=dof, value=dof * a.steps / t, ctx=ctx)
+        res[name] = dict(t=t, dof=dof, value=dof * a.steps / t, ctx=ctx,
+                         roofline=roofline(ctx, min(a.steps, 200)))
         print("# %-7s %.3f ms/step  %.4e DOF-steps/s  (V0 fixed point: %d iterations)"
               % (name, 1e3 * t / a.steps, dof * a.steps / t, its), file=sys.stderr, flush=True)
     main_name = "refined" if "refined" in res else "fp64"
@@ -146,9 +212,11 @@ def main():
                    "instances": len(VTOP), "dof_per_step": r["dof"],
                    "refine_iters": a.refine_iters if main_name == "refined" else 0},
     }
+    out["roofline"] = r["roofline"]
     if "fp64" in res and "refined" in res:
         out["fp64_value"] = res["fp64"]["value"]
         out["refined_over_fp64"] = res["refined"]["value"] / res["fp64"]["value"]
+        out["fp64_roofline"] = res["fp64"]["roofline"]
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -213,6 +213,34 @@ pfd_status pfd_solve(pfd_ctx* ctx, int fam, const double* b, double* x);
 /* y = (K + (c_f + beta_p^2) M) x on every plane (device arrays). */
 pfd_status pfd_apply(pfd_ctx* ctx, int fam, const double* x, double* y);
 
+/* Kernel classes timed by pfd_profile_read */
+enum {
+  PFD_PROF_GEMM64 = 0,   /* fast-diagonalisation GEMM passes, FP64 (MFMA)          */
+  PFD_PROF_GEMM32 = 1,   /* fast-diagonalisation GEMM passes, FP32 (MFMA)          */
+  PFD_PROF_RESID = 2,    /* FP64 residual r = b - A x                               */
+  PFD_PROF_ELEM = 3,     /* element kernels (sum-factorised terms, weak forms)     */
+  PFD_PROF_NODAL = 4,    /* nodal kernels (direct-stiffness sums, right sides)      */
+  PFD_PROF_OTHER = 5,    /* reductions, guards                                      */
+  PFD_PROF_NCLASS = 6
+};
+
+/* Enable (on != 0) or disable per-launch timing: when enabled, every kernel launch of
+ * the context is bracketed by two HIP events on the context's stream (this adds a
+ * little host overhead per launch; time the step loop with profiling off).  Enabling
+ * clears earlier records. */
+pfd_status pfd_profile_enable(pfd_ctx* ctx, int on);
+
+/* Total device time (ms) and number of launches of one kernel class since profiling
+ * was enabled.  Synchronises the stream. */
+pfd_status pfd_profile_read(pfd_ctx* ctx, int cls, double* total_ms, long* launches);
+
+/* Average device time (microseconds) of one launch of a kernel class, measured by
+ * replaying it reps times back to back on the context's own shapes, buffers and
+ * stream between two HIP events (GEMM classes: the four fast-diagonalisation passes
+ * of one velocity correction; PFD_PROF_RESID: the velocity residual).  Writes only
+ * scratch buffers; the state is unchanged.  Synchronises. */
+pfd_status pfd_profile_replay(pfd_ctx* ctx, int cls, int reps, double* avg_us);
+
 #ifdef __cplusplus
 }
 #endif

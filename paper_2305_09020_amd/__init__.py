@@ -27,6 +27,7 @@ PLAIN_FP64, REFINED_FP32 = 0, 1
 WALL, OPEN, PERIODIC = 0, 1, 2
 BOTTOM, TOP, LEFT, RIGHT = 0, 1, 2, 3
 FAM_V, FAM_PSI, FAM_PHI, FAM_P, FAM_U = range(5)
+PROF_CLASSES = ("gemm64", "gemm32", "residual", "element", "nodal", "other")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -80,6 +81,10 @@ _sig = {
     "pfd_step_async": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "pfd_solve": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
     "pfd_apply": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
+    "pfd_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "pfd_profile_replay": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "pfd_profile_read": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_long)]),
 }
 EXPORTS = tuple(_sig)
 for _n, (_res, _args) in _sig.items():
@@ -145,6 +150,7 @@ class Context:
         _check(_lib.pfd_create(ctypes.byref(problem), _vp(base + off), nbytes,
                                _vp(self.stream.cuda_stream), ctypes.byref(h)))
         self.h = h
+        self._destroy = _lib.pfd_destroy   # kept for interpreter shutdown
         nx, ny, npl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(_lib.pfd_get_dims(h, ctypes.byref(nx), ctypes.byref(ny), ctypes.byref(npl)), h)
         self.Nx, self.Ny, self.planes = nx.value, ny.value, npl.value
@@ -152,7 +158,7 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
-            _lib.pfd_destroy(self.h)
+            self._destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -220,6 +226,25 @@ class Context:
 
     def apply(self, fam, x, y):
         _check(_lib.pfd_apply(self.h, fam, _vp(x.data_ptr()), _vp(y.data_ptr())), self.h)
+
+    def profile_enable(self, on=True):
+        _check(_lib.pfd_profile_enable(self.h, int(bool(on))), self.h)
+
+    def profile_read(self):
+        """{class: (total_ms, launches)} since profiling was enabled (synchronises)."""
+        out = {}
+        for k, name in enumerate(PROF_CLASSES):
+            ms, n = ctypes.c_double(0), ctypes.c_long(0)
+            _check(_lib.pfd_profile_read(self.h, k, ctypes.byref(ms), ctypes.byref(n)), self.h)
+            out[name] = (ms.value, n.value)
+        return out
+
+    def profile_replay(self, cls, reps=200):
+        """Average device microseconds of one launch of class cls (name or index)."""
+        k = PROF_CLASSES.index(cls) if isinstance(cls, str) else cls
+        us = ctypes.c_double(0)
+        _check(_lib.pfd_profile_replay(self.h, k, int(reps), ctypes.byref(us)), self.h)
+        return us.value
 
     def diag(self):
         d = Diag()

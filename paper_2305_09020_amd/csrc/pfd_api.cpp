@@ -345,7 +345,12 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   return PFD_OK;
 }
 
-extern "C" void pfd_destroy(pfd_ctx* c) { delete c; }
+extern "C" void pfd_destroy(pfd_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+}
 
 extern "C" pfd_status pfd_get_dims(const pfd_ctx* c, int* Nx, int* Ny, int* planes) {
   if (!c) return PFD_EINVAL;
@@ -489,5 +494,44 @@ extern "C" pfd_status pfd_solve(pfd_ctx* c, int fam, const double* b, double* x)
 extern "C" pfd_status pfd_apply(pfd_ctx* c, int fam, const double* x, double* y) {
   if (!c || !x || !y || fam < 0 || fam > 4) return PFD_EINVAL;
   HIPCHK(apply(c, fam, x, y, 1));
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_profile_enable(pfd_ctx* c, int on) {
+  if (!c) return PFD_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->prof_on = on ? 1 : 0;
+  c->ev_used = 0;
+  c->prof_rec.clear();
+  for (int k = 0; k < PFD_PROF_NCLASS; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_profile_read(pfd_ctx* c, int cls, double* total_ms, long* launches) {
+  if (!c || cls < 0 || cls >= PFD_PROF_NCLASS) return PFD_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (const auto& r : c->prof_rec) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev_pool[r.second], c->ev_pool[r.second + 1]));
+    c->prof_ms[r.first] += ms;
+    c->prof_n[r.first] += 1;
+  }
+  c->prof_rec.clear();
+  c->ev_used = 0;
+  if (total_ms) *total_ms = c->prof_ms[cls];
+  if (launches) *launches = c->prof_n[cls];
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_profile_replay(pfd_ctx* c, int cls, int reps, double* avg_us) {
+  if (!c || !avg_us || reps < 1) return PFD_EINVAL;
+  if (cls != PFD_PROF_GEMM32 && cls != PFD_PROF_GEMM64 && cls != PFD_PROF_RESID) {
+    c->err = "replay supports the GEMM and residual classes";
+    return PFD_EINVAL;
+  }
+  HIPCHK(replay(c, cls, reps, avg_us));
   return PFD_OK;
 }

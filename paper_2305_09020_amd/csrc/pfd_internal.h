@@ -101,9 +101,26 @@ struct pfd_ctx {
   int failed = 0;
   int check_residual = 0;
   double last_residual = 0.0;
+  // per-kernel-class timing (pfd_profile_enable / pfd_profile_read)
+  int prof_on = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> prof_rec;   // (class, index of the start event)
+  double prof_ms[PFD_PROF_NCLASS] = {};
+  long prof_n[PFD_PROF_NCLASS] = {};
 };
 
 namespace pfd {
+// timing scope around one launch (no-op unless profiling is enabled)
+struct ProfScope {
+  pfd_ctx* c;
+  int cls;
+  size_t i0;
+  bool on;
+  ProfScope(pfd_ctx* ctx, int k);
+  ~ProfScope();
+};
+
 // set-up (pfd_setup.cpp)
 void sym_eig(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V);
 void gll_rule(int K, std::vector<double>& x, std::vector<double>& w, std::vector<double>& D);
@@ -118,4 +135,5 @@ hipError_t step_once(pfd_ctx* c, int equilibrium);
 hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout);
 hipError_t update_E(pfd_ctx* c);
 hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* out_host2);
+hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us);
 }  // namespace pfd

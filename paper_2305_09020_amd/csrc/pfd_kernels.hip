@@ -611,11 +611,12 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA,
 }
 
 template <typename T, typename TA, typename TB, int EPI>
-static void gemm(hipStream_t st, int planes, const TA* A, long sA, const TB* B, long sB, int M, int N, int K,
+static void gemm(pfd_ctx* c, int planes, const TA* A, long sA, const TB* B, long sB, int M, int N, int K,
                  T* C, long sC, const double* lr, const double* lc, const double* shift, double* X) {
   dim3 grid((N + 15) / 16, (M + 15) / 16, planes);
-  hipLaunchKernelGGL((k_gemm<T, TA, TB, EPI>), grid, dim3(256), 0, st, A, sA, B, sB, M, N, K, C, sC, lr, lc,
-                     shift, X);
+  ProfScope ps(c, sizeof(T) == 8 ? PFD_PROF_GEMM64 : PFD_PROF_GEMM32);
+  hipLaunchKernelGGL((k_gemm<T, TA, TB, EPI>), grid, dim3(256), 0, c->stream, A, sA, B, sB, M, N, K, C, sC, lr,
+                     lc, shift, X);
 }
 
 // Deterministic per-plane sums: part[p*PCH + blk] = sum over chunk blk of w_i f_i
@@ -658,12 +659,38 @@ __global__ void k_plane_sub(long Ng, int planes, const double* __restrict__ Mdia
 
 static inline unsigned nblk(long n) { return (unsigned)((n + WG - 1) / WG); }
 
+// launch with an optional timing scope (class as in pfd_profile_read)
+#define LAUNCH(cls, ...)            \
+  do {                              \
+    ProfScope _ps(c, cls);          \
+    hipLaunchKernelGGL(__VA_ARGS__); \
+  } while (0)
+
+ProfScope::ProfScope(pfd_ctx* ctx, int k) : c(ctx), cls(k), i0(0), on(ctx && ctx->prof_on) {
+  if (!on) return;
+  if (c->ev_used + 2 > c->ev_pool.size()) {
+    if (c->ev_pool.size() >= 200000) { on = false; return; }
+    size_t n0 = c->ev_pool.size();
+    c->ev_pool.resize(n0 + 4096);
+    for (size_t i = n0; i < c->ev_pool.size(); ++i) (void)hipEventCreate(&c->ev_pool[i]);
+  }
+  i0 = c->ev_used;
+  c->ev_used += 2;
+  (void)hipEventRecord(c->ev_pool[i0], c->stream);
+}
+
+ProfScope::~ProfScope() {
+  if (!on) return;
+  (void)hipEventRecord(c->ev_pool[i0 + 1], c->stream);
+  c->prof_rec.push_back({cls, i0});
+}
+
 static void plane_fix(pfd_ctx* c, int fam, double* f, int mode) {
   Family& F = c->fam[fam];
   const long tot = (long)c->planes * c->Ng;
-  hipLaunchKernelGGL(k_plane_sums, dim3(PCH, c->planes), dim3(WG), 0, c->stream, c->Ng, c->Mdiag, F.dshift, f,
+  LAUNCH(PFD_PROF_OTHER, k_plane_sums, dim3(PCH, c->planes), dim3(WG), 0, c->stream, c->Ng, c->Mdiag, F.dshift, f,
                      mode == 0 ? 1 : 0, c->d_part);
-  hipLaunchKernelGGL(k_plane_sub, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Ng, c->planes, c->Mdiag, F.dshift,
+  LAUNCH(PFD_PROF_OTHER, k_plane_sub, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Ng, c->planes, c->Mdiag, F.dshift,
                      c->d_part, c->Mtot, mode, f);
 }
 
@@ -675,7 +702,7 @@ static void residual(pfd_ctx* c, int fam, const double* b, const double* x, doub
   const long tot = (long)c->planes * c->Ng;
 #define RES_CASE(KK)                                                                                      \
   case KK:                                                                                                \
-    hipLaunchKernelGGL(k_residual<KK>, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->planes,   \
+    LAUNCH(PFD_PROF_RESID, k_residual<KK>, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->planes,   \
                        (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, F.dshift, b, x, r, \
                        apply_only, norms);                                                                \
     break;
@@ -701,11 +728,10 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
   const long Ng = c->Ng;
   T* t1 = reinterpret_cast<T*>(c->tmp);
   T* t2 = reinterpret_cast<T*>(c->tmp2);
-  hipStream_t st = c->stream;
-  gemm<T, double, T, 0>(st, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr, nullptr, nullptr);
-  gemm<T, T, T, 1>(st, P, SyT, 0, t1, Ng, Ny, Nx, Ny, t2, Ng, dy.dlam, dx.dlam, shift, nullptr);
-  gemm<T, T, T, 0>(st, P, Sy, 0, t2, Ng, Ny, Nx, Ny, t1, Ng, nullptr, nullptr, nullptr, nullptr);
-  gemm<T, T, T, 2>(st, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr, nullptr, nullptr, x);
+  gemm<T, double, T, 0>(c, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr, nullptr, nullptr);
+  gemm<T, T, T, 1>(c, P, SyT, 0, t1, Ng, Ny, Nx, Ny, t2, Ng, dy.dlam, dx.dlam, shift, nullptr);
+  gemm<T, T, T, 0>(c, P, Sy, 0, t2, Ng, Ny, Nx, Ny, t1, Ng, nullptr, nullptr, nullptr, nullptr);
+  gemm<T, T, T, 2>(c, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr, nullptr, nullptr, x);
 }
 
 // Solve (K + c M) x = b for ncomp stacked right sides (each planes*Ng), x holding the initial
@@ -753,6 +779,46 @@ hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp, int
   return hipGetLastError();
 }
 
+// Back-to-back replay of one kernel class on the context's real shapes and buffers,
+// bracketed by two events on its stream: average device time per launch (us).
+// GEMM classes replay the four passes of one velocity-family correction into scratch;
+// the residual class replays the velocity-family residual.
+hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us) {
+  Family& F = c->fam[PFD_FAM_U];
+  Dir1D& dx = c->dirs[F.ix];
+  Dir1D& dy = c->dirs[F.iy];
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e) return e;
+  e = hipEventCreate(&e1);
+  if (e) return e;
+  const int saved = c->prof_on;
+  c->prof_on = 0;
+  double* scratch = c->b[2];
+  int per = 1;
+  (void)hipEventRecord(e0, c->stream);
+  for (int i = 0; i < reps; ++i) {
+    if (cls == PFD_PROF_GEMM32) {
+      fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, c->r, scratch);
+      per = 4;
+    } else if (cls == PFD_PROF_GEMM64) {
+      fdm_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, c->r, scratch);
+      per = 4;
+    } else {
+      residual(c, PFD_FAM_U, c->b[1], scratch, c->r + 2 * (long)c->planes * c->Ng, 0, nullptr);
+    }
+  }
+  (void)hipEventRecord(e1, c->stream);
+  e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (!e) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->prof_on = saved;
+  *avg_us = 1e3 * ms / (double(reps) * per);
+  return e;
+}
+
 // ================================================================== step orchestration
 #define FLD(f, lv) c->fld[f][(lv) == 0 ? c->cur : 1 - c->cur]
 
@@ -760,8 +826,8 @@ hipError_t update_E(pfd_ctx* c) {
   const Geo& g = c->geo;
   dim3 eg(c->geo.nx * c->geo.ny, c->planes), eb(((c->nq + 63) / 64) * 64);
   const long tot = (long)c->planes * c->Ng;
-  hipLaunchKernelGGL(k_E_elem, eg, eb, 0, c->stream, g, FLD(F_V, 0), c->Lb[0], c->Lb[1]);
-  hipLaunchKernelGGL(k_E_nodal, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, c->Lb[0], c->Lb[1], c->Mdiag,
+  LAUNCH(PFD_PROF_ELEM, k_E_elem, eg, eb, 0, c->stream, g, FLD(F_V, 0), c->Lb[0], c->Lb[1]);
+  LAUNCH(PFD_PROF_NODAL, k_E_nodal, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, c->Lb[0], c->Lb[1], c->Mdiag,
                      (const double*)nullptr, c->fld[F_EX][0], c->fld[F_EY][0], c->fld[F_E2][0]);
   return hipGetLastError();
 }
@@ -779,9 +845,9 @@ hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout) {
   Dir1D& dy = c->dirs[c->fam[PFD_FAM_V].iy];
   (void)dx;
   (void)dy;
-  hipLaunchKernelGGL(k_V_elem, eg, eb, 0, c->stream, g, P, ph, ph, Vin, Vin, c->Lb[0]);
+  LAUNCH(PFD_PROF_ELEM, k_V_elem, eg, eb, 0, c->stream, g, P, ph, ph, Vin, Vin, c->Lb[0]);
   const bool warm = c->prob.precision == PFD_REFINED_FP32;
-  hipLaunchKernelGGL(k_V_rhs, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, P, c->lift[PFD_FAM_V], c->Lb[0],
+  LAUNCH(PFD_PROF_NODAL, k_V_rhs, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, P, c->lift[PFD_FAM_V], c->Lb[0],
                      c->Mdiag, c->src[PFD_SRC_FV], c->src[PFD_SRC_VD], warm ? Vin : nullptr, Vin, c->b[0], c->r,
                      Vout);
   return solve(c, PFD_FAM_V, c->b[0], Vout, 1, 0, warm ? nullptr : c->r);
@@ -805,17 +871,17 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
   {
     Dir1D& dx = c->dirs[c->fam[PFD_FAM_V].ix];
     Dir1D& dy = c->dirs[c->fam[PFD_FAM_V].iy];
-    hipLaunchKernelGGL(k_V_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), FLD(F_V, 0), FLD(F_V, -1),
+    LAUNCH(PFD_PROF_ELEM, k_V_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), FLD(F_V, 0), FLD(F_V, -1),
                        c->Lb[0]);
     (void)dx;
     (void)dy;
-    hipLaunchKernelGGL(k_V_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_V], c->Lb[0], c->Mdiag, S[PFD_SRC_FV],
+    LAUNCH(PFD_PROF_NODAL, k_V_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_V], c->Lb[0], c->Mdiag, S[PFD_SRC_FV],
                        S[PFD_SRC_VD], H(F_V, 0), H(F_V, -1), c->b[0], c->r, c->fld[F_V][nw]);
     solve(c, PFD_FAM_V, c->b[0], c->fld[F_V][nw], 1, 0, r0);
   }
   // ---- E (eq. 55)
-  hipLaunchKernelGGL(k_E_elem, eg, eb, 0, st, g, c->fld[F_V][nw], c->Lb[0], c->Lb[1]);
-  hipLaunchKernelGGL(k_E_nodal, ng, nb, 0, st, g, c->Lb[0], c->Lb[1], c->Mdiag, (const double*)nullptr,
+  LAUNCH(PFD_PROF_ELEM, k_E_elem, eg, eb, 0, st, g, c->fld[F_V][nw], c->Lb[0], c->Lb[1]);
+  LAUNCH(PFD_PROF_NODAL, k_E_nodal, ng, nb, 0, st, g, c->Lb[0], c->Lb[1], c->Mdiag, (const double*)nullptr,
                      c->fld[F_EX][0], c->fld[F_EY][0], c->fld[F_E2][0]);
   // ---- psi (eq. 56)
   const double* E2 = c->fld[F_E2][0];
@@ -824,14 +890,14 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
   const double* uxo = equilibrium ? c->zero_buf : FLD(F_UX, -1);
   const double* uyn = equilibrium ? c->zero_buf : FLD(F_UY, 0);
   const double* uyo = equilibrium ? c->zero_buf : FLD(F_UY, -1);
-  hipLaunchKernelGGL(k_psi_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), uxn, uxo, uyn, uyo, E2,
+  LAUNCH(PFD_PROF_ELEM, k_psi_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), uxn, uxo, uyn, uyo, E2,
                      S[PFD_SRC_G], c->Lb[0]);
-  hipLaunchKernelGGL(k_psi_rhs, ng, nb, 0, st, g, P, c->Lb[0], c->bm_open, c->bm_wall, S[PFD_SRC_G1],
+  LAUNCH(PFD_PROF_NODAL, k_psi_rhs, ng, nb, 0, st, g, P, c->Lb[0], c->bm_open, c->bm_wall, S[PFD_SRC_G1],
                      S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), E2, H(F_PSI, 0), H(F_PSI, -1),
                      c->b[0], c->U, c->Q2, c->r, c->fld[F_PSI][nw]);
   solve(c, PFD_FAM_PSI, c->b[0], c->fld[F_PSI][nw], 1, 0, r0);
   // ---- phi (eq. 57)
-  hipLaunchKernelGGL(k_phi_rhs, ng, nb, 0, st, g, P, c->Mdiag, c->fld[F_PSI][nw], c->bm_open, c->bm_wall,
+  LAUNCH(PFD_PROF_NODAL, k_phi_rhs, ng, nb, 0, st, g, P, c->Mdiag, c->fld[F_PSI][nw], c->bm_open, c->bm_wall,
                      S[PFD_SRC_G2], c->U, H(F_PHI, 0), H(F_PHI, -1), c->b[0], c->r, c->fld[F_PHI][nw]);
   solve(c, PFD_FAM_PHI, c->b[0], c->fld[F_PHI][nw], 1, 0, r0);
   if (equilibrium) {
@@ -841,24 +907,24 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
   } else {
     // ---- momentum terms, P (eq. 58)
     // phi^{n-1} now holds phi^{n+1}: the momentum kernel takes Q2 (built from phi*) from the psi stage
-    hipLaunchKernelGGL(k_mom_elem, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
+    LAUNCH(PFD_PROF_ELEM, k_mom_elem, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
                        FLD(F_UX, 0), FLD(F_UX, -1), FLD(F_UY, 0), FLD(F_UY, -1), FLD(F_P, 0),
                        FLD(F_P, -1), S[PFD_SRC_FX], S[PFD_SRC_FY], c->Lb[0], c->Lb[1], c->Lb[2]);
-    hipLaunchKernelGGL(k_P_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_P], c->Lb[0], S[PFD_SRC_WX], S[PFD_SRC_WY],
+    LAUNCH(PFD_PROF_NODAL, k_P_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_P], c->Lb[0], S[PFD_SRC_WX], S[PFD_SRC_WY],
                        S[PFD_SRC_F2], H(F_P, 0), H(F_P, -1), c->b[0], c->r, c->fld[F_P][nw]);
     solve(c, PFD_FAM_P, c->b[0], c->fld[F_P][nw], 1, 0, r0);
     // ---- u (eq. 59)
-    hipLaunchKernelGGL(k_gradP_elem, eg, eb, 0, st, g, P, c->fld[F_P][nw], c->Lb[1], c->Lb[2]);
-    hipLaunchKernelGGL(k_u_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_U], c->Lb[1], c->Lb[2], c->bm_open,
+    LAUNCH(PFD_PROF_ELEM, k_gradP_elem, eg, eb, 0, st, g, P, c->fld[F_P][nw], c->Lb[1], c->Lb[2]);
+    LAUNCH(PFD_PROF_NODAL, k_u_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_U], c->Lb[1], c->Lb[2], c->bm_open,
                        S[PFD_SRC_F1X], S[PFD_SRC_F1Y], S[PFD_SRC_WX], S[PFD_SRC_WY], H(F_UX, 0), H(F_UX, -1),
                        H(F_UY, 0), H(F_UY, -1), c->b[1], c->b[2], c->r, c->r + tot, c->fld[F_UX][nw],
                        c->fld[F_UY][nw]);
     solve(c, PFD_FAM_U, c->b[1], c->fld[F_UX][nw], 1, 0, r0);
     solve(c, PFD_FAM_U, c->b[2], c->fld[F_UY][nw], 1, 0, warm ? nullptr : c->r + tot);
   }
-  hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
+  LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
   if (!equilibrium)
-    hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_UX][nw], c->d_status);
+    LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_UX][nw], c->d_status);
   c->cur = nw;
   return hipGetLastError();
 }
@@ -890,7 +956,7 @@ __global__ void k_maxdiff(long N, const double* a, const double* b, double* out)
 hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* out_host2) {
   const long N = (long)c->planes * c->Ng;
   const int nb = 64;
-  hipLaunchKernelGGL(k_maxdiff, dim3(nb), dim3(WG), 0, c->stream, N, a, b, c->d_red);
+  LAUNCH(PFD_PROF_OTHER, k_maxdiff, dim3(nb), dim3(WG), 0, c->stream, N, a, b, c->d_red);
   double h[2 * 64];
   hipMemcpyAsync(h, c->d_red, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, c->stream);
   hipError_t e = hipStreamSynchronize(c->stream);
