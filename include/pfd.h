@@ -202,7 +202,9 @@ pfd_status pfd_step(pfd_ctx* ctx, int nsteps, int equilibrium);
  * timing loops and graph capture.  Check pfd_get_diag afterwards. */
 pfd_status pfd_step_async(pfd_ctx* ctx, int nsteps, int equilibrium);
 
-/* Solve (K + (c_f + beta_p^2) M) x = b for solve family fam on every plane,
+/* Solve (K + (c_f + beta_p^2) M) x = b for solve family fam on every plane (in 3D the
+ * planes are the packed spectral planes: 0 = Re k=0, 1 = Re k=Nz/2, 2k / 2k+1 = Re / Im of
+ * mode k, beta_p = 2 pi k / Lz),
  * with x = x_in on the family's Dirichlet nodes (eqs. 54-59 operators).  b and
  * x are device arrays of planes*Ny*Nx doubles; x holds the initial guess and
  * the Dirichlet values on entry and the solution on exit.  For a singular
@@ -221,7 +223,8 @@ enum {
   PFD_PROF_ELEM = 3,     /* element kernels (sum-factorised terms, weak forms)     */
   PFD_PROF_NODAL = 4,    /* nodal kernels (direct-stiffness sums, right sides)      */
   PFD_PROF_OTHER = 5,    /* reductions, guards                                      */
-  PFD_PROF_NCLASS = 6
+  PFD_PROF_ZFFT = 6,     /* z transforms (packed real DFT GEMMs, 3D)                */
+  PFD_PROF_NCLASS = 7
 };
 
 /* Enable (on != 0) or disable per-launch timing: when enabled, every kernel launch of

@@ -27,7 +27,7 @@ PLAIN_FP64, REFINED_FP32 = 0, 1
 WALL, OPEN, PERIODIC = 0, 1, 2
 BOTTOM, TOP, LEFT, RIGHT = 0, 1, 2, 3
 FAM_V, FAM_PSI, FAM_PHI, FAM_P, FAM_U = range(5)
-PROF_CLASSES = ("gemm64", "gemm32", "residual", "element", "nodal", "other")
+PROF_CLASSES = ("gemm64", "gemm32", "residual", "element", "nodal", "other", "zfft")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 

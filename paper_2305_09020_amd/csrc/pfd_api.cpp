@@ -66,8 +66,10 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   }
   if (q.bdf_order != 1 && q.bdf_order != 2) { *err = "bdf_order must be 1 or 2"; return PFD_EINVAL; }
   if (p->precision != PFD_PLAIN_FP64 && p->precision != PFD_REFINED_FP32) { *err = "bad precision"; return PFD_EINVAL; }
-  if (m.nz != 0) { *err = "3D (nz > 0) is not available in this build"; return PFD_ENOTIMPL; }
-  if (m.nbatch < 1) { *err = "nbatch must be >= 1"; return PFD_EINVAL; }
+  if (m.nz < 0 || m.nz == 1 || (m.nz > 0 && m.nz % 2)) { *err = "nz must be 0 (2D) or even >= 2"; return PFD_EINVAL; }
+  if (m.nz > 0 && !(m.lz > 0)) { *err = "lz must be positive in 3D"; return PFD_EINVAL; }
+  if (m.nz > 512) { *err = "nz above 512 is not supported"; return PFD_EINVAL; }
+  if (m.nbatch < 1 || (m.nz > 0 && m.nbatch != 1)) { *err = "nbatch must be >= 1 (and 1 in 3D)"; return PFD_EINVAL; }
   if (p->bc.n_electrodes > 0) { *err = "partial electrode segments are not available in this build"; return PFD_ENOTIMPL; }
   for (int s = 0; s < 4; ++s) {
     if (m.periodic_x && s >= PFD_LEFT) continue;
@@ -80,15 +82,21 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   L->Nx = m.nx * m.K + 1 - (m.periodic_x ? 1 : 0);
   L->Ny = m.ny * m.K + 1;
   if (L->Nx > PFD_NMAX || L->Ny > PFD_NMAX) { *err = "more than 320 nodes along a direction"; return PFD_EINVAL; }
-  L->is3d = 0;
-  L->planes = m.nbatch;
+  L->is3d = m.nz > 0;
+  L->planes = L->is3d ? m.nz : m.nbatch;
   L->Ng = (long)L->Nx * L->Ny;
   L->Nl = (long)m.nx * m.ny * (m.K + 1) * (m.K + 1);
   const long Pg = L->planes * L->Ng, Pl = L->planes * L->Nl;
   size_t dbl = 0;
   dbl += (size_t)F_NSTATE * 2 * Pg;      // state
   dbl += (size_t)PFD_NSRC * Pg;          // sources
-  dbl += 3 * (size_t)Pl;                 // element-local buffers
+  dbl += (L->is3d ? 7 : 3) * (size_t)Pl; // element-local buffers
+  if (L->is3d) {
+    dbl += 14 * (size_t)Pg;              // spectral state
+    dbl += 16 * (size_t)Pg;              // physical / spectral / z-derivative temporaries
+    dbl += 5 * (size_t)Pg;               // spectral Dirichlet data
+    dbl += 4 * (size_t)m.nz * m.nz + 64; // DFT matrices
+  }
   dbl += 3 * (size_t)Pg;                 // right sides
   dbl += 8 * (size_t)Pg;                 // r (3), U, Q2, tmp, tmp2, zero
   dbl += 7 * (size_t)L->Ng;              // boundary masses, mass
@@ -197,6 +205,42 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   const double shifts[5] = {0.0, P.c_psi, P.c_phi, 0.0, P.c_u};
   c->beta2.assign(c->planes, 0.0);
   c->betad.assign(c->planes, 0.0);
+  std::vector<double> Wf, Wi, Wd, Dz;
+  if (c->is3d) {
+    // packed spectral planes: 0 = k 0, 1 = Nyquist, 2k / 2k+1 = Re / Im of mode k
+    const int Nz = m.nz;
+    const double Lz = m.lz;
+    auto kof = [&](int p) { return p == 0 ? 0 : (p == 1 ? Nz / 2 : p / 2); };
+    for (int p = 0; p < Nz; ++p) {
+      const double beta = 2.0 * M_PI * kof(p) / Lz;
+      c->beta2[p] = beta * beta;
+      c->betad[p] = (p < 2) ? 0.0 : beta;   // Nyquist first derivative is 0 (reading R-nyq)
+    }
+    Wf.assign((size_t)Nz * Nz, 0.0); Wi = Wf; Wd = Wf; Dz = Wf;
+    for (int j = 0; j < Nz; ++j) {
+      const double sgn = (j % 2) ? -1.0 : 1.0;
+      Wf[(size_t)0 * Nz + j] = 1.0 / Nz;
+      Wf[(size_t)1 * Nz + j] = sgn / Nz;
+      Wi[(size_t)j * Nz + 0] = 1.0;
+      Wi[(size_t)j * Nz + 1] = sgn;
+      for (int k = 1; k < Nz / 2; ++k) {
+        const double th = 2.0 * M_PI * (double)((long)j * k % Nz) / Nz;
+        const double cs = std::cos(th), sn = std::sin(th), beta = 2.0 * M_PI * k / Lz;
+        Wf[(size_t)(2 * k) * Nz + j] = cs / Nz;
+        Wf[(size_t)(2 * k + 1) * Nz + j] = -sn / Nz;
+        Wi[(size_t)j * Nz + 2 * k] = 2.0 * cs;
+        Wi[(size_t)j * Nz + 2 * k + 1] = -2.0 * sn;
+        Wd[(size_t)j * Nz + 2 * k] = -2.0 * beta * sn;
+        Wd[(size_t)j * Nz + 2 * k + 1] = -2.0 * beta * cs;
+      }
+    }
+    for (int i = 0; i < Nz; ++i)
+      for (int j = 0; j < Nz; ++j) {
+        double acc = 0.0;
+        for (int p = 0; p < Nz; ++p) acc += Wd[(size_t)i * Nz + p] * Wf[(size_t)p * Nz + j];
+        Dz[(size_t)i * Nz + j] = acc;
+      }
+  }
 
   // ---- carve the workspace
   const long Pg = (long)c->planes * c->Ng, Pl = (long)c->planes * c->Nl;
@@ -204,7 +248,17 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   for (int f = 0; f < F_NSTATE; ++f)
     for (int l = 0; l < 2; ++l) c->fld[f][l] = D(Pg);
   for (int s = 0; s < PFD_NSRC; ++s) c->src[s] = D(Pg);
-  for (int i = 0; i < 3; ++i) c->Lb[i] = D(Pl);
+  for (int i = 0; i < (c->is3d ? 7 : 3); ++i) c->Lb[i] = D(Pl);
+  if (c->is3d) {
+    for (int f : {F_UX, F_UY, F_UZ, F_P, F_PHI, F_PSI, F_V})
+      for (int l = 0; l < 2; ++l) c->spec[f][l] = D(Pg);
+    for (int i = 0; i < 5; ++i) c->ph[i] = D(Pg);
+    for (int i = 0; i < 5; ++i) c->sp[i] = D(Pg);
+    for (int i = 0; i < 6; ++i) c->dz[i] = D(Pg);
+    for (int s : {PFD_SRC_VD, PFD_SRC_F2, PFD_SRC_WX, PFD_SRC_WY, PFD_SRC_WZ}) c->srcS[s] = D(Pg);
+    const long NZ2 = (long)m.nz * m.nz;
+    c->Wf = D(NZ2); c->Wi = D(NZ2); c->Wd = D(NZ2); c->Dz = D(NZ2);
+  }
   for (int i = 0; i < 3; ++i) c->b[i] = D(Pg);
   c->r = D(3 * Pg); c->U = D(Pg); c->Q2 = D(Pg); c->tmp = D(Pg); c->tmp2 = D(Pg);
   double* zero = D(Pg);
@@ -318,6 +372,17 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   if (!e) e = up(c->d_beta2, c->beta2.data(), 8 * c->planes);
   if (!e) e = up(c->d_betad, c->betad.data(), 8 * c->planes);
   for (int f = 0; f < 5 && !e; ++f) e = up(c->fam[f].dshift, c->fam[f].hshift.data(), 8 * c->planes);
+  if (c->is3d && !e) {
+    const size_t nz2 = 8 * (size_t)m.nz * m.nz;
+    e = up(c->Wf, Wf.data(), nz2);
+    if (!e) e = up(c->Wi, Wi.data(), nz2);
+    if (!e) e = up(c->Wd, Wd.data(), nz2);
+    if (!e) e = up(c->Dz, Dz.data(), nz2);
+    for (int f : {F_UX, F_UY, F_UZ, F_P, F_PHI, F_PSI, F_V})
+      for (int l = 0; l < 2 && !e; ++l) e = hipMemsetAsync(c->spec[f][l], 0, 8 * Pg, c->stream);
+    for (int s : {PFD_SRC_VD, PFD_SRC_F2, PFD_SRC_WX, PFD_SRC_WY, PFD_SRC_WZ})
+      if (!e) e = hipMemsetAsync(c->srcS[s], 0, 8 * Pg, c->stream);
+  }
   // zero every field and source
   for (int f = 0; f < F_NSTATE && !e; ++f)
     for (int l = 0; l < 2 && !e; ++l) e = hipMemsetAsync(c->fld[f][l], 0, 8 * Pg, c->stream);
@@ -406,6 +471,11 @@ extern "C" pfd_status pfd_set_field(pfd_ctx* c, int f, int level, const double* 
     double* old = field_ptr(c, f, -1);
     HIPCHK(hipMemcpyAsync(old, src, bytes, k, c->stream));
   }
+  if (c->is3d && f <= PFD_V) {  // spectral copies (both levels when level 0 was set)
+    const int lv = (level == 0) ? c->cur : 1 - c->cur;
+    HIPCHK(to_spectral(c, c->fld[f][lv], c->spec[f][lv]));
+    if (level == 0) HIPCHK(to_spectral(c, c->fld[f][lv], c->spec[f][1 - lv]));
+  }
   if (!on_device) HIPCHK(hipStreamSynchronize(c->stream));
   c->failed = 0;
   c->steps = 0;
@@ -426,6 +496,7 @@ extern "C" pfd_status pfd_get_field(pfd_ctx* c, int f, int level, double* dst, i
 extern "C" pfd_status pfd_set_source(pfd_ctx* c, int s, const double* src, int on_device) {
   if (!c || s < 0 || s >= PFD_NSRC) return PFD_EINVAL;
   const size_t bytes = sizeof(double) * c->planes * c->Ng;
+  c->src_dirty[s] = 1;
   if (!src) {
     HIPCHK(hipMemsetAsync(c->src[s], 0, bytes, c->stream));
   } else {
@@ -444,7 +515,7 @@ extern "C" pfd_status pfd_init_potential(pfd_ctx* c, double tol, int max_iter, i
   int it = 0;
   bool conv = false;
   for (it = 1; it <= max_iter; ++it) {
-    HIPCHK(potential_iteration(c, A, B));
+    HIPCHK(c->is3d ? potential_iteration_3d(c, A, B) : potential_iteration(c, A, B));
     double h[2];
     HIPCHK(max_abs_diff(c, A, B, h));
     std::swap(A, B);  // A = newest
@@ -456,6 +527,10 @@ extern "C" pfd_status pfd_init_potential(pfd_ctx* c, double tol, int max_iter, i
   double* cur = c->fld[F_V][c->cur];
   if (A != cur) HIPCHK(hipMemcpyAsync(cur, A, bytes, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->fld[F_V][1 - c->cur], cur, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (c->is3d) {
+    HIPCHK(to_spectral(c, cur, c->spec[F_V][c->cur]));
+    HIPCHK(to_spectral(c, cur, c->spec[F_V][1 - c->cur]));
+  }
   HIPCHK(update_E(c));
   HIPCHK(hipStreamSynchronize(c->stream));
   if (iters) *iters = it;
@@ -466,7 +541,7 @@ extern "C" pfd_status pfd_init_potential(pfd_ctx* c, double tol, int max_iter, i
 extern "C" pfd_status pfd_step_async(pfd_ctx* c, int nsteps, int equilibrium) {
   if (!c || nsteps < 0) return PFD_EINVAL;
   if (c->failed) { c->err = "context failed earlier; set the fields again"; return PFD_ESTATE; }
-  for (int i = 0; i < nsteps; ++i) HIPCHK(step_once(c, equilibrium));
+  for (int i = 0; i < nsteps; ++i) HIPCHK(c->is3d ? step_once_3d(c, equilibrium) : step_once(c, equilibrium));
   c->steps += nsteps;
   return PFD_OK;
 }

@@ -87,7 +87,13 @@ struct pfd_ctx {
   int cur = 0;                             // index of level n
   int set_old[pfd::F_NSTATE] = {};         // level n-1 explicitly set
   double* src[PFD_NSRC] = {};
-  double *Lb[3] = {}, *b[3] = {}, *r = nullptr, *U = nullptr, *Q2 = nullptr;
+  double *Lb[7] = {}, *b[3] = {}, *r = nullptr, *U = nullptr, *Q2 = nullptr;
+  // 3D (Fourier in z): packed DFT matrices, spectral state, temporaries
+  double *Wf = nullptr, *Wi = nullptr, *Wd = nullptr, *Dz = nullptr;
+  double* spec[pfd::F_NSTATE][2] = {};     // spectral copies of u, P, phi, psi, V (two levels)
+  double *ph[5] = {}, *sp[5] = {}, *dz[6] = {};
+  double* srcS[PFD_NSRC] = {};             // spectral Dirichlet data (VD, F2, WX, WY, WZ)
+  int src_dirty[PFD_NSRC] = {};
   double *tmp = nullptr, *tmp2 = nullptr;  // solve intermediates (double or float)
   double* d_part = nullptr;                // per-plane partial sums
   double Mtot = 0.0;                       // sum of the mass matrix (area)
@@ -136,4 +142,7 @@ hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout);
 hipError_t update_E(pfd_ctx* c);
 hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* out_host2);
 hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us);
+hipError_t step_once_3d(pfd_ctx* c, int equilibrium);
+hipError_t potential_iteration_3d(pfd_ctx* c, const double* Vin, double* Vout);
+hipError_t to_spectral(pfd_ctx* c, const double* phys, double* spec);
 }  // namespace pfd

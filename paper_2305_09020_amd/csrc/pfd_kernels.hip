@@ -235,6 +235,7 @@ __global__ void k_E_nodal(Geo g, const double* L0, const double* L1, const doubl
 __global__ void __launch_bounds__(WG) k_psi_elem(Geo g, Par P, const double* phn, const double* pho,
                                                  const double* uxn, const double* uxo, const double* uyn,
                                                  const double* uyo, const double* E2, const double* gsrc,
+                                                 const double* uzn, const double* uzo, const double* dzphs,
                                                  double* L0) {
   ELEM_PROLOGUE
   __shared__ double sph[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
@@ -256,6 +257,10 @@ __global__ void __launch_bounds__(WG) k_psi_elem(Geo g, Par P, const double* phn
   double q1 = 0.0;
   if (act) {
     double adv = uxs * ddx(s, n, a, b, sph, sx) + uys * ddy(s, n, a, b, sph, sy);
+    if (uzn) {  // 3D: + u*_z d(phi*)/dz, the z-derivative taken from the spectral phi
+      const long id = pofs + gi;
+      adv += (P.cs_n * uzn[id] + P.cs_o * uzo[id]) * dzphs[id];
+    }
     q1 = (gg - adv + phh / P.dt) / (P.lam * P.gamma1);
     sgx[t] = s.w[a] * ddx(s, n, a, b, sQ2, sx);
     sgy[t] = s.w[b] * ddy(s, n, a, b, sQ2, sy);
@@ -304,27 +309,40 @@ __global__ void k_phi_rhs(Geo g, Par P, const double* Mdiag, const double* psi, 
   }
 }
 
+// optional 3D inputs / outputs of the momentum element kernel (Algorithm 2):
+// z-derivatives come from the spectral representation (nodal values, one per node)
+struct Mom3 {
+  const double *uzn, *uzo, *dzphi, *dzPhi, *dzux, *dzuy, *dzuz, *dzP, *fz;
+  double *LBP, *LAz, *LBx, *LBy;
+};
+
 // =================================================================== momentum terms (eq. 49)
-// L0 = rho0 int G.grad q - rho0 int_dOmega (mu/rho) (n x w*).grad q   (pressure, eq. 58a)
-// L1, L2 = (1/nu_m)[int G v -+ int K x grad v] - (1/nu_m) int_open L v (velocity, eq. 59a;
+// L0 = rho0 int G.grad q - rho0 int_dOmega (mu/rho) (n x w*).grad q   (pressure, eqs. 58a / 77a)
+// L1, L2 = (1/nu_m)[int G v -+ int K x grad v] - (1/nu_m) int_open L v (velocity, eqs. 59a / 78a;
 //          the -grad P^{n+1}/rho0 part is added after the pressure solve)
+// 3D (Z3): the parts multiplied by i beta_k in the per-mode forms go to LBP, LBx, LBy, and the
+//          z velocity right side to LAz (G, omega*, K are full 3-vectors there).
+template <bool Z3>
 __global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi, const double* psi,
                                                  const double* E2, const double* Q2,
                                                  const double* uxn, const double* uxo, const double* uyn,
                                                  const double* uyo, const double* Pn, const double* Po,
                                                  const double* fx, const double* fy, double* L0,
-                                                 double* L1, double* L2) {
+                                                 double* L1, double* L2, Mom3 z) {
   ELEM_PROLOGUE
   __shared__ double sph[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
   __shared__ double sPhi[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
   __shared__ double sux[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
   __shared__ double suy[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double suz[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
   __shared__ double sP[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
   __shared__ double sgx[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
   __shared__ double sgy[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sK[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sf[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  double ph = 0.0, ps = 0.0, e2 = 0.0, uhx = 0.0, uhy = 0.0, ffx = 0.0, ffy = 0.0;
+  __shared__ double sKz[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sfz[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sfx[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  __shared__ double sfy[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  double ph = 0.0, ps = 0.0, e2 = 0.0, uh[3] = {0.0, 0.0, 0.0}, ff[3] = {0.0, 0.0, 0.0};
   if (act) {
     const long id = pofs + gi;
     ph = phi[id];
@@ -334,92 +352,162 @@ __global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi
     sPhi[t] = ps - P.c_psi * ph - Q2[id];
     double un = uxn[id], uo = uxo[id];
     sux[t] = P.cs_n * un + P.cs_o * uo;
-    uhx = P.ch_n * un + P.ch_o * uo;
-    un = uyn[id]; uo = uyo[id];
+    uh[0] = P.ch_n * un + P.ch_o * uo;
+    un = uyn[id];
+    uo = uyo[id];
     suy[t] = P.cs_n * un + P.cs_o * uo;
-    uhy = P.ch_n * un + P.ch_o * uo;
+    uh[1] = P.ch_n * un + P.ch_o * uo;
+    if (Z3) {
+      un = z.uzn[id];
+      uo = z.uzo[id];
+      suz[t] = P.cs_n * un + P.cs_o * uo;
+      uh[2] = P.ch_n * un + P.ch_o * uo;
+      ff[2] = z.fz[id];
+    } else {
+      suz[t] = 0.0;
+    }
     sP[t] = P.cs_n * Pn[id] + P.cs_o * Po[id];
-    ffx = fx[id];
-    ffy = fy[id];
+    ff[0] = fx[id];
+    ff[1] = fy[id];
   }
   __syncthreads();
-  double Gx = 0.0, Gy = 0.0, Kv = 0.0;
+  double G[3] = {0.0, 0.0, 0.0}, Kv[3] = {0.0, 0.0, 0.0}, om[3] = {0.0, 0.0, 0.0}, mr = 0.0;
   if (act) {
+    const long id = pofs + gi;
     const double pc = fmin(1.0, fmax(-1.0, ph));
     const double rho = 0.5 * (P.rho1 + P.rho2) + 0.5 * (P.rho1 - P.rho2) * pc;
     const double mu = 0.5 * (P.mu1 + P.mu2) + 0.5 * (P.mu1 - P.mu2) * pc;
-    const double dpx = ddx(s, n, a, b, sph, sx), dpy = ddy(s, n, a, b, sph, sy);
-    const double drr = 0.5 * (P.rho1 - P.rho2), dmm = 0.5 * (P.mu1 - P.mu2);
     const double irho = 1.0 / rho;
-    const double gnx = (rho * dmm - mu * drr) * dpx * irho * irho;
-    const double gny = (rho * dmm - mu * drr) * dpy * irho * irho;
+    const double drr = 0.5 * (P.rho1 - P.rho2), dmm = 0.5 * (P.mu1 - P.mu2);
+    const double gph[3] = {ddx(s, n, a, b, sph, sx), ddy(s, n, a, b, sph, sy), Z3 ? z.dzphi[id] : 0.0};
+    const double cnu = (rho * dmm - mu * drr) * irho * irho;  // grad(mu/rho) = cnu grad(phi)
     const double jc = 0.5 * (P.rho1 - P.rho2) * P.lam * P.gamma1;
-    const double Jx = jc * ddx(s, n, a, b, sPhi, sx), Jy = jc * ddy(s, n, a, b, sPhi, sy);
-    const double ux = sux[t], uy = suy[t];
-    const double uxx = ddx(s, n, a, b, sux, sx), uxy = ddy(s, n, a, b, sux, sy);  // d_x ux, d_y ux
-    const double uyx = ddx(s, n, a, b, suy, sx), uyy = ddy(s, n, a, b, suy, sy);  // d_x uy, d_y uy
-    const double om = uyx - uxy;
-    const double dmx = dmm * dpx, dmy = dmm * dpy;
-    const double gmDx = dmx * 2.0 * uxx + dmy * (uxy + uyx);
-    const double gmDy = dmx * (uyx + uxy) + dmy * 2.0 * uyy;
-    const double Nx_ = ux * uxx + uy * uxy, Ny_ = ux * uyx + uy * uyy;
-    const double JUx = Jx * uxx + Jy * uxy, JUy = Jx * uyx + Jy * uyy;
+    const double Jt[3] = {jc * ddx(s, n, a, b, sPhi, sx), jc * ddy(s, n, a, b, sPhi, sy),
+                          Z3 ? jc * z.dzPhi[id] : 0.0};
+    const double u[3] = {sux[t], suy[t], suz[t]};
+    // gu[i][k] = d_i u*_k
+    double gu[3][3];
+    gu[0][0] = ddx(s, n, a, b, sux, sx);
+    gu[0][1] = ddx(s, n, a, b, suy, sx);
+    gu[1][0] = ddy(s, n, a, b, sux, sy);
+    gu[1][1] = ddy(s, n, a, b, suy, sy);
+    if (Z3) {
+      gu[0][2] = ddx(s, n, a, b, suz, sx);
+      gu[1][2] = ddy(s, n, a, b, suz, sy);
+      gu[2][0] = z.dzux[id];
+      gu[2][1] = z.dzuy[id];
+      gu[2][2] = z.dzuz[id];
+    } else {
+      gu[0][2] = gu[1][2] = gu[2][0] = gu[2][1] = gu[2][2] = 0.0;
+    }
+    om[0] = gu[1][2] - gu[2][1];
+    om[1] = gu[2][0] - gu[0][2];
+    om[2] = gu[0][1] - gu[1][0];
     const double lap = ps - P.alpha * ph;
     const double dep = deps_of(P, ph);
-    const double gPx = ddx(s, n, a, b, sP, sx), gPy = ddy(s, n, a, b, sP, sy);
+    const double gP[3] = {ddx(s, n, a, b, sP, sx), ddy(s, n, a, b, sP, sy), Z3 ? z.dzP[id] : 0.0};
     const double cP = 1.0 / P.rho0 - irho;
-    const double Tx = (ffx - P.lam * lap * dpx - 0.5 * dep * e2 * dpx + gmDx - JUx) * irho + uhx / P.dt - Nx_ + cP * gPx;
-    const double Ty = (ffy - P.lam * lap * dpy - 0.5 * dep * e2 * dpy + gmDy - JUy) * irho + uhy / P.dt - Ny_ + cP * gPy;
-    Gx = Tx + gny * om;
-    Gy = Ty - gnx * om;
-    const double mr = mu * irho;
-    Kv = (mr - P.nu_m) * om;
-    sgx[t] = s.w[a] * Gx;
-    sgy[t] = s.w[b] * Gy;
-    sK[t] = Kv;
-    sf[t] = mr * om;
+    const double gnu[3] = {cnu * gph[0], cnu * gph[1], cnu * gph[2]};
+    const double cr[3] = {gnu[1] * om[2] - gnu[2] * om[1], gnu[2] * om[0] - gnu[0] * om[2],
+                          gnu[0] * om[1] - gnu[1] * om[0]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (!Z3 && k == 2) break;
+      double gmD = 0.0, Nk = 0.0, JU = 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        gmD += dmm * gph[i] * (gu[i][k] + gu[k][i]);
+        Nk += u[i] * gu[i][k];
+        JU += Jt[i] * gu[i][k];
+      }
+      const double T = (ff[k] - P.lam * lap * gph[k] - 0.5 * dep * e2 * gph[k] + gmD - JU) * irho +
+                       uh[k] / P.dt - Nk + cP * gP[k];
+      G[k] = T + cr[k];
+    }
+    mr = mu * irho;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Kv[k] = (mr - P.nu_m) * om[k];
+    sgx[t] = s.w[a] * G[0];
+    sgy[t] = s.w[b] * G[1];
+    sKz[t] = Kv[2];
+    sfz[t] = mr * om[2];
+    sfx[t] = Kv[0];
+    sfy[t] = Kv[1];
   }
   __syncthreads();
   if (act) {
     const double wq = 0.25 * hx * hy * s.w[a] * s.w[b];
-    double l0 = P.rho0 * (0.5 * hy * s.w[b] * wdx(s, n, a, b, sgx) + 0.5 * hx * s.w[a] * wdy(s, n, a, b, sgy));
-    // weak-div pieces of K: y-part (for u_x) and x-part (for u_y), K pre-multiplied by w_p
-    double kyp = 0.0, kxp = 0.0;
+    const double ewx = 0.5 * hx * s.w[a], ewy = 0.5 * hy * s.w[b];   // edge weights
+    double l0 = P.rho0 * (ewy * wdx(s, n, a, b, sgx) + ewx * wdy(s, n, a, b, sgy));
+    // x- and y-parts of the weak divergence of K components (K weighted by w_p inside)
+    double kz_y = 0.0, kz_x = 0.0, ky_x = 0.0, kx_y = 0.0;
     for (int p = 0; p < n; ++p) {
-      kyp += s.D[p * n + b] * s.w[p] * sK[p * n + a];
-      kxp += s.D[p * n + a] * s.w[p] * sK[b * n + p];
+      kz_y += s.D[p * n + b] * s.w[p] * sKz[p * n + a];
+      kz_x += s.D[p * n + a] * s.w[p] * sKz[b * n + p];
+      if (Z3) {
+        ky_x += s.D[p * n + a] * s.w[p] * sfy[b * n + p];
+        kx_y += s.D[p * n + b] * s.w[p] * sfx[p * n + a];
+      }
     }
-    double l1 = wq * Gx + 0.5 * hx * s.w[a] * kyp;
-    double l2 = wq * Gy - 0.5 * hy * s.w[b] * kxp;
-    // boundary edges: tangential term of eq. (58a) on every side; L term of eq. (59a) on open sides
+    double l1 = wq * G[0] + ewx * kz_y;
+    double l2 = wq * G[1] - ewy * kz_x;
+    double laz = 0.0, lbp = 0.0;
+    if (Z3) {
+      laz = wq * G[2] + ewy * ky_x - ewx * kx_y;
+      lbp = -P.rho0 * wq * G[2];
+    }
+    // boundary edges: tangential term of the pressure equation on every side (reading R-Pbnd),
+    // its z part (3D), and the L term of the velocity equation on open sides
     const int K = g.K;
     if (ey == 0 && b == 0) {  // bottom, n = (0,-1)
       double acc = 0.0;
-      for (int p = 0; p < n; ++p) acc += s.w[p] * sf[p] * s.D[p * n + a];
+      for (int p = 0; p < n; ++p) acc += s.w[p] * sfz[p] * s.D[p * n + a];
       l0 += P.rho0 * acc;
-      if (g.side_type[PFD_BOTTOM] == PFD_OPEN) l1 += 0.5 * hx * s.w[a] * Kv;
+      if (Z3) lbp += P.rho0 * ewx * mr * om[0];
+      if (g.side_type[PFD_BOTTOM] == PFD_OPEN) {
+        l1 += ewx * Kv[2];
+        if (Z3) laz -= ewx * Kv[0];
+      }
     }
     if (ey == g.ny - 1 && b == K) {  // top, n = (0,1)
       double acc = 0.0;
-      for (int p = 0; p < n; ++p) acc += s.w[p] * sf[K * n + p] * s.D[p * n + a];
+      for (int p = 0; p < n; ++p) acc += s.w[p] * sfz[K * n + p] * s.D[p * n + a];
       l0 -= P.rho0 * acc;
-      if (g.side_type[PFD_TOP] == PFD_OPEN) l1 -= 0.5 * hx * s.w[a] * Kv;
+      if (Z3) lbp -= P.rho0 * ewx * mr * om[0];
+      if (g.side_type[PFD_TOP] == PFD_OPEN) {
+        l1 -= ewx * Kv[2];
+        if (Z3) laz += ewx * Kv[0];
+      }
     }
     if (!g.periodic && ex == 0 && a == 0) {  // left, n = (-1,0)
       double acc = 0.0;
-      for (int p = 0; p < n; ++p) acc += s.w[p] * sf[p * n] * s.D[p * n + b];
+      for (int p = 0; p < n; ++p) acc += s.w[p] * sfz[p * n] * s.D[p * n + b];
       l0 -= P.rho0 * acc;
-      if (g.side_type[PFD_LEFT] == PFD_OPEN) l2 -= 0.5 * hy * s.w[b] * Kv;
+      if (Z3) lbp -= P.rho0 * ewy * mr * om[1];
+      if (g.side_type[PFD_LEFT] == PFD_OPEN) {
+        l2 -= ewy * Kv[2];
+        if (Z3) laz += ewy * Kv[1];
+      }
     }
     if (!g.periodic && ex == g.nx - 1 && a == K) {  // right, n = (1,0)
       double acc = 0.0;
-      for (int p = 0; p < n; ++p) acc += s.w[p] * sf[p * n + K] * s.D[p * n + b];
+      for (int p = 0; p < n; ++p) acc += s.w[p] * sfz[p * n + K] * s.D[p * n + b];
       l0 += P.rho0 * acc;
-      if (g.side_type[PFD_RIGHT] == PFD_OPEN) l2 += 0.5 * hy * s.w[b] * Kv;
+      if (Z3) lbp += P.rho0 * ewy * mr * om[1];
+      if (g.side_type[PFD_RIGHT] == PFD_OPEN) {
+        l2 += ewy * Kv[2];
+        if (Z3) laz -= ewy * Kv[1];
+      }
     }
     L0[lofs] = l0;
     L1[lofs] = l1 / P.nu_m;
     L2[lofs] = l2 / P.nu_m;
+    if (Z3) {
+      z.LBP[lofs] = lbp;
+      z.LAz[lofs] = laz / P.nu_m;
+      z.LBx[lofs] = wq * Kv[1] / P.nu_m;
+      z.LBy[lofs] = -wq * Kv[0] / P.nu_m;
+    }
   }
 }
 
@@ -435,8 +523,10 @@ __global__ void k_P_rhs(Geo g, Par P, Lift L, const double* L0, const double* wx
   rhs_out(g, P, L, f2, Fn, Fo, id, (long)pl * g.Ng, ix, iy, v, bb, r, x0);
 }
 
-// u right side: add -(1/(nu_m rho0)) int grad P^{n+1} v to L1, L2
-__global__ void __launch_bounds__(WG) k_gradP_elem(Geo g, Par P, const double* Pnew, double* L1, double* L2) {
+// u right side: add -(1/(nu_m rho0)) int grad P^{n+1} v to L1, L2 (and to LAz in 3D, with the
+// z-derivative dzP taken from the spectral pressure)
+__global__ void __launch_bounds__(WG) k_gradP_elem(Geo g, Par P, const double* Pnew, const double* dzP,
+                                                   double* L1, double* L2, double* LAz) {
   ELEM_PROLOGUE
   __shared__ double sP[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
   if (act) sP[t] = Pnew[pofs + gi];
@@ -445,6 +535,7 @@ __global__ void __launch_bounds__(WG) k_gradP_elem(Geo g, Par P, const double* P
     const double c = -0.25 * hx * hy * s.w[a] * s.w[b] / (P.nu_m * P.rho0);
     L1[lofs] += c * ddx(s, n, a, b, sP, sx);
     L2[lofs] += c * ddy(s, n, a, b, sP, sy);
+    if (dzP) LAz[lofs] += c * dzP[pofs + gi];
   }
 }
 
@@ -457,6 +548,11 @@ __global__ void k_u_rhs(Geo g, Par P, Lift L, const double* L1, const double* L2
   const long pofs = (long)pl * g.Ng;
   rhs_out(g, P, L, wx, Fxn, Fxo, id, pofs, ix, iy, dss(g, L1, pl, ix, iy) + bmo[node] * f1x[id], bx, rx, x0x);
   rhs_out(g, P, L, wy, Fyn, Fyo, id, pofs, ix, iy, dss(g, L2, pl, ix, iy) + bmo[node] * f1y[id], by, ry, x0y);
+}
+
+__global__ void k_fill(long N, double* f, double v) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) f[i] = v;
 }
 
 // non-finite guard on a field: sets status[0]
@@ -552,7 +648,9 @@ template <typename T, typename TA, typename TB, int EPI>
 __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA, const TB* __restrict__ B, long sB,
                                               int M, int N, int K, T* __restrict__ C, long sC,
                                               const double* __restrict__ lr, const double* __restrict__ lc,
-                                              const double* __restrict__ shift, double* __restrict__ X) {
+                                              const double* __restrict__ shift, double* __restrict__ X,
+                                              const TB* __restrict__ B2, double cb1, double cb2) {
+  // B2 != nullptr: the right operand is cb1 B + cb2 B2 (e.g. the BDF extrapolation of a field)
   // four waves split K: wave w takes the 16-wide slices w, w+4, w+8, ... of the contraction,
   // and the partial tiles are summed in LDS in a fixed order (deterministic)
   __shared__ T red[4][4][64];
@@ -563,6 +661,8 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA,
   const bool mok = m < M, nok = n < N;
   const TA* Arow = A + pl * sA + (long)(mok ? m : 0) * K;
   const TB* Bcol = B + pl * sB + (nok ? n : 0);
+  const TB* B2col = B2 ? B2 + pl * sB + (nok ? n : 0) : nullptr;
+  auto ldb = [&](long o) -> T { return B2col ? T(cb1 * double(Bcol[o]) + cb2 * double(B2col[o])) : T(Bcol[o]); };
   typename Mfma<T>::V acc = {T(0), T(0), T(0), T(0)};
   T a[4], b[4], an[4], bn[4];
   const int kstart = 16 * w;
@@ -570,7 +670,7 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA,
   for (int s = 0; s < 4; ++s) {
     const int k = kstart + 4 * g + s;
     a[s] = (mok && k < K) ? T(Arow[k]) : T(0);
-    b[s] = (nok && k < K) ? T(Bcol[(long)k * N]) : T(0);
+    b[s] = (nok && k < K) ? ldb((long)k * N) : T(0);
   }
   for (int k0 = kstart; k0 < K; k0 += 64) {
     const int k1 = k0 + 64;
@@ -578,7 +678,7 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA,
     for (int s = 0; s < 4; ++s) {
       const int k = k1 + 4 * g + s;
       an[s] = (mok && k < K) ? T(Arow[k]) : T(0);
-      bn[s] = (nok && k < K) ? T(Bcol[(long)k * N]) : T(0);
+      bn[s] = (nok && k < K) ? ldb((long)k * N) : T(0);
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc = Mfma<T>::op(a[s], b[s], acc);
@@ -616,7 +716,7 @@ static void gemm(pfd_ctx* c, int planes, const TA* A, long sA, const TB* B, long
   dim3 grid((N + 15) / 16, (M + 15) / 16, planes);
   ProfScope ps(c, sizeof(T) == 8 ? PFD_PROF_GEMM64 : PFD_PROF_GEMM32);
   hipLaunchKernelGGL((k_gemm<T, TA, TB, EPI>), grid, dim3(256), 0, c->stream, A, sA, B, sB, M, N, K, C, sC, lr,
-                     lc, shift, X);
+                     lc, shift, X, (const TB*)nullptr, 1.0, 0.0);
 }
 
 // Deterministic per-plane sums: part[p*PCH + blk] = sum over chunk blk of w_i f_i
@@ -822,13 +922,21 @@ hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us) {
 // ================================================================== step orchestration
 #define FLD(f, lv) c->fld[f][(lv) == 0 ? c->cur : 1 - c->cur]
 
+static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, const double* in2, double c1,
+                   double c2);
+
 hipError_t update_E(pfd_ctx* c) {
   const Geo& g = c->geo;
   dim3 eg(c->geo.nx * c->geo.ny, c->planes), eb(((c->nq + 63) / 64) * 64);
   const long tot = (long)c->planes * c->Ng;
+  const double* Ez = nullptr;
+  if (c->is3d) {
+    ztrans(c, c->Wd, c->spec[F_V][c->cur], c->fld[F_EZ][0], nullptr, 1.0, 0.0);
+    Ez = c->fld[F_EZ][0];
+  }
   LAUNCH(PFD_PROF_ELEM, k_E_elem, eg, eb, 0, c->stream, g, FLD(F_V, 0), c->Lb[0], c->Lb[1]);
   LAUNCH(PFD_PROF_NODAL, k_E_nodal, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, c->Lb[0], c->Lb[1], c->Mdiag,
-                     (const double*)nullptr, c->fld[F_EX][0], c->fld[F_EY][0], c->fld[F_E2][0]);
+                     Ez, c->fld[F_EX][0], c->fld[F_EY][0], c->fld[F_E2][0]);
   return hipGetLastError();
 }
 
@@ -891,7 +999,7 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
   const double* uyn = equilibrium ? c->zero_buf : FLD(F_UY, 0);
   const double* uyo = equilibrium ? c->zero_buf : FLD(F_UY, -1);
   LAUNCH(PFD_PROF_ELEM, k_psi_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), uxn, uxo, uyn, uyo, E2,
-                     S[PFD_SRC_G], c->Lb[0]);
+                     S[PFD_SRC_G], (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, c->Lb[0]);
   LAUNCH(PFD_PROF_NODAL, k_psi_rhs, ng, nb, 0, st, g, P, c->Lb[0], c->bm_open, c->bm_wall, S[PFD_SRC_G1],
                      S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), E2, H(F_PSI, 0), H(F_PSI, -1),
                      c->b[0], c->U, c->Q2, c->r, c->fld[F_PSI][nw]);
@@ -907,14 +1015,15 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
   } else {
     // ---- momentum terms, P (eq. 58)
     // phi^{n-1} now holds phi^{n+1}: the momentum kernel takes Q2 (built from phi*) from the psi stage
-    LAUNCH(PFD_PROF_ELEM, k_mom_elem, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
+    LAUNCH(PFD_PROF_ELEM, k_mom_elem<false>, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
                        FLD(F_UX, 0), FLD(F_UX, -1), FLD(F_UY, 0), FLD(F_UY, -1), FLD(F_P, 0),
-                       FLD(F_P, -1), S[PFD_SRC_FX], S[PFD_SRC_FY], c->Lb[0], c->Lb[1], c->Lb[2]);
+                       FLD(F_P, -1), S[PFD_SRC_FX], S[PFD_SRC_FY], c->Lb[0], c->Lb[1], c->Lb[2], Mom3{});
     LAUNCH(PFD_PROF_NODAL, k_P_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_P], c->Lb[0], S[PFD_SRC_WX], S[PFD_SRC_WY],
                        S[PFD_SRC_F2], H(F_P, 0), H(F_P, -1), c->b[0], c->r, c->fld[F_P][nw]);
     solve(c, PFD_FAM_P, c->b[0], c->fld[F_P][nw], 1, 0, r0);
     // ---- u (eq. 59)
-    LAUNCH(PFD_PROF_ELEM, k_gradP_elem, eg, eb, 0, st, g, P, c->fld[F_P][nw], c->Lb[1], c->Lb[2]);
+    LAUNCH(PFD_PROF_ELEM, k_gradP_elem, eg, eb, 0, st, g, P, c->fld[F_P][nw], (const double*)nullptr, c->Lb[1],
+           c->Lb[2], (double*)nullptr);
     LAUNCH(PFD_PROF_NODAL, k_u_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_U], c->Lb[1], c->Lb[2], c->bm_open,
                        S[PFD_SRC_F1X], S[PFD_SRC_F1Y], S[PFD_SRC_WX], S[PFD_SRC_WY], H(F_UX, 0), H(F_UX, -1),
                        H(F_UY, 0), H(F_UY, -1), c->b[1], c->b[2], c->r, c->r + tot, c->fld[F_UX][nw],
@@ -966,6 +1075,275 @@ hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* ou
     out_host2[1] = fmax(out_host2[1], h[2 * i + 1]);
   }
   return e;
+}
+
+// ============================================================ 3D: Fourier in z (Algorithm 2)
+// Physical fields are z planes; spectral fields use the packed real layout on the same
+// planes: plane 0 = Re k=0, plane 1 = Re k=Nz/2, planes 2k / 2k+1 = Re / Im of mode k.
+// The z transforms are the dense packed DFT matrices (Nz x Nz) applied with the batched MFMA
+// GEMM: Wf (forward, 1/Nz normalised), Wi (inverse), Wd (spectral -> physical d/dz, i beta_k;
+// the Nyquist derivative is 0), Dz = Wd Wf (physical d/dz).
+
+// right side of the per-mode weak forms from the transformed parts:
+//   b = scale * (A + i beta_k B)   (bmode 0)   or   scale * (A + beta_k^2 B)   (bmode 1)
+//       + mc * M * Cv   (optional spectral term),
+// then the initial guess / first residual as in rhs_out (gD, Fn, Fo spectral)
+__global__ void k_spec_rhs(Geo g, Par P, Lift L, const double* A, const double* B, int bmode, double scale,
+                           const double* Cv, double mc, const double* Mdiag, const double* beta2,
+                           const double* betad, const double* gD, const double* Fn, const double* Fo, double* bb,
+                           double* r, double* x0) {
+  NODAL_PROLOGUE
+  double v = A[id];
+  if (B) {
+    if (bmode == 0) {
+      const double bd = betad[pl];
+      if (bd != 0.0) v += ((pl & 1) == 0) ? -bd * B[id + g.Ng] : bd * B[id - g.Ng];
+    } else {
+      v += beta2[pl] * B[id];
+    }
+  }
+  v *= scale;
+  if (Cv) v += mc * Mdiag[node] * Cv[id];
+  rhs_out(g, P, L, gD, Fn, Fo, id, (long)pl * g.Ng, ix, iy, v, bb, r, x0);
+}
+
+// V: A = DSS(L0) - M f_V,  B = M (eps(phi*) - eps0) d(V*)/dz
+__global__ void k_V_rhs3(Geo g, Par P, const double* L0, const double* Mdiag, const double* fV, const double* phn,
+                         const double* pho, const double* dzV, double* A, double* B) {
+  NODAL_PROLOGUE
+  A[id] = dss(g, L0, pl, ix, iy) - Mdiag[node] * fV[id];
+  const double phs = P.cs_n * phn[id] + P.cs_o * pho[id];
+  B[id] = Mdiag[node] * (eps_of(P, phs) - P.eps0) * dzV[id];
+}
+
+// psi: A = DSS(L0) + Bo (g1 + c_psi g2) + Bs (g1 + c_psi U),  B = M Q2 ; U, Q2 kept
+__global__ void k_psi_rhs3(Geo g, Par P, const double* L0, const double* Mdiag, const double* bmo,
+                           const double* bmw, const double* g1, const double* g2, const double* g3,
+                           const double* phn, const double* pho, const double* E2, double* A, double* B,
+                           double* U, double* Q2) {
+  NODAL_PROLOGUE
+  const double phs = P.cs_n * phn[id] + P.cs_o * pho[id];
+  const double u = -g3[id] - thp_of(P, phs);
+  U[id] = u;
+  const double q2 = h_of(P, phs) - P.S / (P.eta * P.eta) * phs - deps_of(P, phs) * E2[id] / (2.0 * P.lam);
+  Q2[id] = q2;
+  A[id] = dss(g, L0, pl, ix, iy) + bmo[node] * (g1[id] + P.c_psi * g2[id]) + bmw[node] * (g1[id] + P.c_psi * u);
+  B[id] = Mdiag[node] * q2;
+}
+
+// phi: boundary part Bo g2 + Bs U (the -M psi part is added in spectral space)
+__global__ void k_phi_bnd3(Geo g, const double* bmo, const double* bmw, const double* g2, const double* U,
+                           double* A) {
+  NODAL_PROLOGUE
+  A[id] = bmo[node] * g2[id] + bmw[node] * U[id];
+}
+
+// Phi_hat = psi_hat - c_psi phi_hat - Q2_hat, with Q2_hat = (M Q2)_hat / M (reading R-J)
+__global__ void k_Phi_hat3(Geo g, Par P, const double* psh, const double* phh, const double* BQ,
+                           const double* Mdiag, double* out) {
+  NODAL_PROLOGUE
+  out[id] = psh[id] - P.c_psi * phh[id] - BQ[id] / Mdiag[node];
+}
+
+// P: A = DSS(L0) - rho0 gamma0/dt sum_walls int (n.w) q,  B = DSS(LBP)
+__global__ void k_P_rhs3(Geo g, Par P, const double* L0, const double* LBP, const double* wx, const double* wy,
+                         double* A, double* B) {
+  NODAL_PROLOGUE
+  double v = dss(g, L0, pl, ix, iy);
+  const double c = P.rho0 * P.gamma0 / P.dt;
+  const double nw[4] = {-wy[id], wy[id], -wx[id], wx[id]};
+  for (int sd = 0; sd < 4; ++sd)
+    if (g.side_type[sd] == PFD_WALL) v -= c * g.bm_side[sd][node] * nw[sd];
+  A[id] = v;
+  B[id] = dss(g, LBP, pl, ix, iy);
+}
+
+// u: A_x, B_x, A_y, B_y, A_z (open-side f1 added to the A parts)
+__global__ void k_u_rhs3(Geo g, const double* L1, const double* LBx, const double* L2, const double* LBy,
+                         const double* LAz, const double* bmo, const double* f1x, const double* f1y,
+                         const double* f1z, double* Ax, double* Bx, double* Ay, double* By, double* Az) {
+  NODAL_PROLOGUE
+  Ax[id] = dss(g, L1, pl, ix, iy) + bmo[node] * f1x[id];
+  Bx[id] = dss(g, LBx, pl, ix, iy);
+  Ay[id] = dss(g, L2, pl, ix, iy) + bmo[node] * f1y[id];
+  By[id] = dss(g, LBy, pl, ix, iy);
+  Az[id] = dss(g, LAz, pl, ix, iy) + bmo[node] * f1z[id];
+}
+
+// out = W in  (or W (c1 in + c2 in2)) along z for every node: one GEMM, M = K = Nz, N = Ng
+static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, const double* in2 = nullptr,
+                   double c1 = 1.0, double c2 = 0.0);
+static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, const double* in2, double c1,
+                   double c2) {
+  ProfScope ps(c, PFD_PROF_ZFFT);
+  dim3 grid(((int)c->Ng + 15) / 16, (c->planes + 15) / 16, 1);
+  hipLaunchKernelGGL((k_gemm<double, double, double, 0>), grid, dim3(256), 0, c->stream, W, 0L, in, 0L, c->planes,
+                     (int)c->Ng, c->planes, out, 0L, (const double*)nullptr, (const double*)nullptr,
+                     (const double*)nullptr, (double*)nullptr, in2, c1, c2);
+}
+
+// spectral copies of the Dirichlet sources that changed since the last step (reading R-dir3d)
+static void refresh_spectral_sources(pfd_ctx* c) {
+  const int ids[5] = {PFD_SRC_VD, PFD_SRC_F2, PFD_SRC_WX, PFD_SRC_WY, PFD_SRC_WZ};
+  for (int s : ids)
+    if (c->src_dirty[s]) {
+      ztrans(c, c->Wf, c->src[s], c->srcS[s]);
+      c->src_dirty[s] = 0;
+    }
+}
+
+#define SPEC(f, lv) c->spec[f][(lv) == 0 ? c->cur : 1 - c->cur]
+
+hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
+  const Geo& g = c->geo;
+  const Par& P = c->par;
+  dim3 eg(g.nx * g.ny, c->planes), eb(((c->nq + 63) / 64) * 64);
+  const long tot = (long)c->planes * c->Ng;
+  const dim3 ng(nblk(tot)), nb(WG);
+  hipStream_t st = c->stream;
+  const int nw = 1 - c->cur;
+  const bool warm = c->prob.precision == PFD_REFINED_FP32;
+  auto H = [&](int f, int lv) -> const double* { return warm ? SPEC(f, lv) : nullptr; };
+  double* r0 = warm ? nullptr : c->r;
+  double* const* S = c->src;
+  double **ph = c->ph, **sp = c->sp, **dz = c->dz, **Lb = c->Lb;
+  refresh_spectral_sources(c);
+  // ---- V (eq. 74)
+  ztrans(c, c->Wd, SPEC(F_V, 0), dz[0], SPEC(F_V, -1), P.cs_n, P.cs_o);
+  LAUNCH(PFD_PROF_ELEM, k_V_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), FLD(F_V, 0), FLD(F_V, -1),
+         Lb[0]);
+  LAUNCH(PFD_PROF_NODAL, k_V_rhs3, ng, nb, 0, st, g, P, Lb[0], c->Mdiag, S[PFD_SRC_FV], FLD(F_PHI, 0),
+         FLD(F_PHI, -1), dz[0], ph[0], ph[1]);
+  ztrans(c, c->Wf, ph[0], sp[0]);
+  ztrans(c, c->Wf, ph[1], sp[1]);
+  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_V], sp[0], sp[1], 0, 1.0 / P.eps0,
+         (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_VD], H(F_V, 0), H(F_V, -1),
+         c->b[0], c->r, c->spec[F_V][nw]);
+  solve(c, PFD_FAM_V, c->b[0], c->spec[F_V][nw], 1, 0, r0);
+  ztrans(c, c->Wi, c->spec[F_V][nw], c->fld[F_V][nw]);
+  // ---- E (eq. 78): E_x, E_y by plane-wise projection, E_z = i beta V (reading R-Ez)
+  ztrans(c, c->Wd, c->spec[F_V][nw], c->fld[F_EZ][0]);
+  LAUNCH(PFD_PROF_ELEM, k_E_elem, eg, eb, 0, st, g, c->fld[F_V][nw], Lb[0], Lb[1]);
+  LAUNCH(PFD_PROF_NODAL, k_E_nodal, ng, nb, 0, st, g, Lb[0], Lb[1], c->Mdiag, (const double*)c->fld[F_EZ][0],
+         c->fld[F_EX][0], c->fld[F_EY][0], c->fld[F_E2][0]);
+  const double* E2 = c->fld[F_E2][0];
+  // ---- psi (eq. 75)
+  ztrans(c, c->Wd, SPEC(F_PHI, 0), dz[1], SPEC(F_PHI, -1), P.cs_n, P.cs_o);
+  const double* uxn = equilibrium ? c->zero_buf : FLD(F_UX, 0);
+  const double* uxo = equilibrium ? c->zero_buf : FLD(F_UX, -1);
+  const double* uyn = equilibrium ? c->zero_buf : FLD(F_UY, 0);
+  const double* uyo = equilibrium ? c->zero_buf : FLD(F_UY, -1);
+  const double* uzn = equilibrium ? c->zero_buf : FLD(F_UZ, 0);
+  const double* uzo = equilibrium ? c->zero_buf : FLD(F_UZ, -1);
+  LAUNCH(PFD_PROF_ELEM, k_psi_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), uxn, uxo, uyn, uyo, E2,
+         S[PFD_SRC_G], uzn, uzo, (const double*)dz[1], Lb[0]);
+  LAUNCH(PFD_PROF_NODAL, k_psi_rhs3, ng, nb, 0, st, g, P, Lb[0], c->Mdiag, c->bm_open, c->bm_wall, S[PFD_SRC_G1],
+         S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), E2, ph[0], ph[1], c->U, c->Q2);
+  ztrans(c, c->Wf, ph[0], sp[0]);
+  ztrans(c, c->Wf, ph[1], sp[1]);  // (M Q2)_hat, kept for Phi_hat below
+  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_PSI], sp[0], sp[1], 1, 1.0,
+         (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, (const double*)nullptr, H(F_PSI, 0),
+         H(F_PSI, -1), c->b[0], c->r, c->spec[F_PSI][nw]);
+  solve(c, PFD_FAM_PSI, c->b[0], c->spec[F_PSI][nw], 1, 0, r0);
+  ztrans(c, c->Wi, c->spec[F_PSI][nw], c->fld[F_PSI][nw]);
+  // ---- phi (eq. 76, reading R-psi)
+  LAUNCH(PFD_PROF_NODAL, k_phi_bnd3, ng, nb, 0, st, g, c->bm_open, c->bm_wall, S[PFD_SRC_G2], c->U, ph[0]);
+  ztrans(c, c->Wf, ph[0], sp[0]);
+  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_PHI], sp[0], (const double*)nullptr, 0,
+         1.0, (const double*)c->spec[F_PSI][nw], -1.0, c->Mdiag, c->d_beta2, c->d_betad, (const double*)nullptr,
+         H(F_PHI, 0), H(F_PHI, -1), c->b[0], c->r, c->spec[F_PHI][nw]);
+  solve(c, PFD_FAM_PHI, c->b[0], c->spec[F_PHI][nw], 1, 0, r0);
+  ztrans(c, c->Wi, c->spec[F_PHI][nw], c->fld[F_PHI][nw]);
+  if (equilibrium) {
+    for (int f : {F_UX, F_UY, F_UZ, F_P}) {
+      LAUNCH(PFD_PROF_OTHER, k_fill, ng, nb, 0, st, tot, c->fld[f][nw], 0.0);
+      LAUNCH(PFD_PROF_OTHER, k_fill, ng, nb, 0, st, tot, c->spec[f][nw], 0.0);
+    }
+  } else {
+    // ---- momentum terms (eq. 49 and the G, Y, K, J, L of Sec. 3.2.2)
+    ztrans(c, c->Wd, c->spec[F_PHI][nw], dz[0]);
+    LAUNCH(PFD_PROF_NODAL, k_Phi_hat3, ng, nb, 0, st, g, P, c->spec[F_PSI][nw], c->spec[F_PHI][nw], sp[1],
+           c->Mdiag, sp[2]);
+    ztrans(c, c->Wd, sp[2], dz[1]);
+    ztrans(c, c->Wd, SPEC(F_UX, 0), dz[2], SPEC(F_UX, -1), P.cs_n, P.cs_o);
+    ztrans(c, c->Wd, SPEC(F_UY, 0), dz[3], SPEC(F_UY, -1), P.cs_n, P.cs_o);
+    ztrans(c, c->Wd, SPEC(F_UZ, 0), dz[4], SPEC(F_UZ, -1), P.cs_n, P.cs_o);
+    ztrans(c, c->Wd, SPEC(F_P, 0), dz[5], SPEC(F_P, -1), P.cs_n, P.cs_o);
+    Mom3 z{FLD(F_UZ, 0), FLD(F_UZ, -1), dz[0], dz[1], dz[2], dz[3], dz[4], dz[5], S[PFD_SRC_FZ],
+           Lb[3], Lb[4], Lb[5], Lb[6]};
+    LAUNCH(PFD_PROF_ELEM, k_mom_elem<true>, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
+           FLD(F_UX, 0), FLD(F_UX, -1), FLD(F_UY, 0), FLD(F_UY, -1), FLD(F_P, 0), FLD(F_P, -1), S[PFD_SRC_FX],
+           S[PFD_SRC_FY], Lb[0], Lb[1], Lb[2], z);
+    // ---- P (eq. 77)
+    LAUNCH(PFD_PROF_NODAL, k_P_rhs3, ng, nb, 0, st, g, P, Lb[0], Lb[3], S[PFD_SRC_WX], S[PFD_SRC_WY], ph[0],
+           ph[1]);
+    ztrans(c, c->Wf, ph[0], sp[0]);
+    ztrans(c, c->Wf, ph[1], sp[1]);
+    LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_P], sp[0], sp[1], 0, 1.0,
+           (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_F2], H(F_P, 0),
+           H(F_P, -1), c->b[0], c->r, c->spec[F_P][nw]);
+    solve(c, PFD_FAM_P, c->b[0], c->spec[F_P][nw], 1, 0, r0);
+    ztrans(c, c->Wi, c->spec[F_P][nw], c->fld[F_P][nw]);
+    // ---- u (eq. 78)
+    ztrans(c, c->Wd, c->spec[F_P][nw], dz[0]);
+    LAUNCH(PFD_PROF_ELEM, k_gradP_elem, eg, eb, 0, st, g, P, c->fld[F_P][nw], (const double*)dz[0], Lb[1], Lb[2],
+           Lb[4]);
+    LAUNCH(PFD_PROF_NODAL, k_u_rhs3, ng, nb, 0, st, g, Lb[1], Lb[5], Lb[2], Lb[6], Lb[4], c->bm_open,
+           S[PFD_SRC_F1X], S[PFD_SRC_F1Y], S[PFD_SRC_F1Z], ph[0], ph[1], ph[2], ph[3], ph[4]);
+    for (int i = 0; i < 5; ++i) ztrans(c, c->Wf, ph[i], sp[i]);
+    const int uf[3] = {F_UX, F_UY, F_UZ};
+    const int ws[3] = {PFD_SRC_WX, PFD_SRC_WY, PFD_SRC_WZ};
+    const double* Bs[3] = {sp[1], sp[3], nullptr};
+    const double* As[3] = {sp[0], sp[2], sp[4]};
+    for (int i = 0; i < 3; ++i)
+      LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_U], As[i], Bs[i], 0, 1.0,
+             (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[ws[i]], H(uf[i], 0),
+             H(uf[i], -1), c->b[i], c->r + i * tot, c->spec[uf[i]][nw]);
+    for (int i = 0; i < 3; ++i) {
+      solve(c, PFD_FAM_U, c->b[i], c->spec[uf[i]][nw], 1, 0, warm ? nullptr : c->r + i * tot);
+      ztrans(c, c->Wi, c->spec[uf[i]][nw], c->fld[uf[i]][nw]);
+    }
+  }
+  LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
+  if (!equilibrium) LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_UX][nw], c->d_status);
+  c->cur = nw;
+  return hipGetLastError();
+}
+
+// one fixed-point iteration of Remark 3.1 in 3D (phi* = phi^n), physical Vin -> Vout
+hipError_t potential_iteration_3d(pfd_ctx* c, const double* Vin, double* Vout) {
+  Geo g = c->geo;
+  Par P = c->par;
+  P.cs_n = 1.0;
+  P.cs_o = 0.0;
+  dim3 eg(g.nx * g.ny, c->planes), eb(((c->nq + 63) / 64) * 64);
+  const long tot = (long)c->planes * c->Ng;
+  const dim3 ng(nblk(tot)), nb(WG);
+  hipStream_t st = c->stream;
+  const bool warm = c->prob.precision == PFD_REFINED_FP32;
+  double **ph = c->ph, **sp = c->sp, **dz = c->dz;
+  refresh_spectral_sources(c);
+  const double* phn = FLD(F_PHI, 0);
+  ztrans(c, c->Dz, Vin, dz[0]);
+  LAUNCH(PFD_PROF_ELEM, k_V_elem, eg, eb, 0, st, g, P, phn, phn, Vin, Vin, c->Lb[0]);
+  LAUNCH(PFD_PROF_NODAL, k_V_rhs3, ng, nb, 0, st, g, P, c->Lb[0], c->Mdiag, c->src[PFD_SRC_FV], phn, phn, dz[0],
+         ph[0], ph[1]);
+  ztrans(c, c->Wf, ph[0], sp[0]);
+  ztrans(c, c->Wf, ph[1], sp[1]);
+  if (warm) ztrans(c, c->Wf, Vin, sp[2]);
+  double* Vh = c->spec[F_V][1 - c->cur];
+  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_V], sp[0], sp[1], 0, 1.0 / P.eps0,
+         (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_VD],
+         warm ? (const double*)sp[2] : nullptr, (const double*)sp[2], c->b[0], c->r, Vh);
+  hipError_t e = solve(c, PFD_FAM_V, c->b[0], Vh, 1, 0, warm ? nullptr : c->r);
+  ztrans(c, c->Wi, Vh, Vout);
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+// spectral copy of a physical field: spec = Wf phys
+hipError_t to_spectral(pfd_ctx* c, const double* phys, double* spec) {
+  ztrans(c, c->Wf, phys, spec);
+  return hipGetLastError();
 }
 
 }  // namespace pfd

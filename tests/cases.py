@@ -37,9 +37,12 @@ def mms_setup(kind, K, dt, Nz=8, S=0.0, par=None):
         m = Mesh2D([0.0, 1.0, 2.0], [0.0, 1.0], K, periodic_x=True)
         bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, pot_sides=(BOTTOM,))
         sch = Scheme(m, par, bc)
-    elif kind == "eq81":
+    elif kind in ("eq81", "eq81b"):
         m = Mesh2D([0.0, 1.0, 2.0], [-1.0, 1.0], K, periodic_x=True)
-        bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, electrodes=[(0.0, 1.0)])
+        if kind == "eq81":
+            bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, electrodes=[(0.0, 1.0)])
+        else:  # same solution with V Dirichlet on the whole bottom wall
+            bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, pot_sides=(BOTTOM,))
         sch = Scheme(m, par, bc, Nz=Nz, Lz=2.0)
     elif kind == "box":
         m = Mesh2D([0.0, 0.5, 1.0], [0.0, 0.5, 1.0], K, periodic_x=False)
@@ -59,7 +62,7 @@ def mms_setup(kind, K, dt, Nz=8, S=0.0, par=None):
         g[m.side_nodes(s)] = True
         mask = np.broadcast_to(g[None, :], (Nzz, m.Ng)).copy()
         sides.append((mask, NORMALS[s], bc.side[s]))
-    mf = Manufactured(kind, par)
+    mf = Manufactured("eq81" if kind == "eq81b" else kind, par)
     return dict(mesh=m, bc=bc, sch=sch, par=par, x=x, y=y, z=z, sides=sides, mf=mf)
 
 
