@@ -38,13 +38,30 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from synth import C2, c2_param_dict, drop_field  # noqa: E402
+from synth import C2, C3, c2_param_dict, c3_param_dict, c3_phi0, drop_field  # noqa: E402
 
 VTOP = (0.0, 0.5, 1.0, 2.0)
 
 
-def make_context(precision, refine_iters):
+def make_context_c3(precision, refine_iters):
+    """3D workload: 16x16 elements, K = 8, 128 Fourier planes, perturbed sphere."""
     import paper_2305_09020_amd as pfd
+    xb = np.linspace(0.0, 1.0, C3["nx"] + 1)
+    prob = pfd.make_problem(xb, xb, C3["K"], c3_param_dict(), [pfd.WALL] * 4, [1, 1, 0, 0],
+                            nz=C3["nz"], lz=C3["lz"], precision=precision, refine_iters=refine_iters)
+    ctx = pfd.Context(prob)
+    x, y, z = ctx.coords()
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    ctx.set_field("phi", c3_phi0(X, Y, Z))
+    ctx.set_source("Vd", np.where(np.isclose(Y, 1.0), 1.0, 0.0))
+    its = ctx.init_potential(tol=1e-12, max_iter=20000)
+    return ctx, its
+
+
+def make_context(precision, refine_iters, workload="c2"):
+    import paper_2305_09020_amd as pfd
+    if workload == "c3":
+        return make_context_c3(precision, refine_iters)
     xb = np.linspace(0.0, 1.0, C2["nx"] + 1)
     prob = pfd.make_problem(xb, xb, C2["K"], c2_param_dict(), [pfd.WALL] * 4, [1, 1, 0, 0],
                             nbatch=len(VTOP), precision=precision, refine_iters=refine_iters)
@@ -152,10 +169,44 @@ def cpu_baseline(nsteps=40):
                        % (nsteps, tset, os.cpu_count() or 0))
 
 
+def cpu_baseline_c3(nsteps=1):
+    """The FP64 oracle on the 3D workload at full size: one step after its first (the
+    first includes the per-mode sparse-LU set-up, timed separately)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from oracle.sem import Mesh2D, BOTTOM, TOP, LEFT, RIGHT
+    from oracle.scheme import Scheme, Params, BCs, WALL
+    par = Params(**c3_param_dict())
+    xb = np.linspace(0.0, 1.0, C3["nx"] + 1)
+    m = Mesh2D(xb, xb, C3["K"])
+    bc = BCs(side={BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}, pot_sides=(BOTTOM, TOP))
+    sch = Scheme(m, par, bc, Nz=C3["nz"], Lz=C3["lz"])
+    Z = np.broadcast_to(sch.z[:, None], (C3["nz"], m.Ng))
+    X = np.broadcast_to(m.X.ravel()[None, :], Z.shape)
+    Y = np.broadcast_to(m.Y.ravel()[None, :], Z.shape)
+    sch.set_state(c3_phi0(X, Y, Z))
+    src = dict(Vd=np.where(np.isclose(Y, 1.0), 1.0, 0.0))
+    sch.state["cur"]["V"] = np.array(Y)   # linear start V = y (the V0 fixed point is not timed)
+    sch.state["old"]["V"] = sch.state["cur"]["V"].copy()
+    t0 = time.perf_counter()
+    sch.step(src)
+    tset = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        sch.step(src)
+    t = time.perf_counter() - t0
+    dof = m.Ng * C3["nz"]
+    return dict(value=dof * nsteps / t, unit="DOF-steps/s", cores=1, kind="oracle",
+                sample="the 3D workload at full size, %d step(s) after the first; first step incl. "
+                       "per-mode sparse-LU set-up %.1f s excluded; single-threaded SciPy/NumPy "
+                       "(host has %d cores)" % (nsteps, tset, os.cpu_count() or 0))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
+                    help="c2: the 2D benchmark configuration (default); c3: the 3D configuration")
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--refine-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -180,15 +231,17 @@ def main():
     import torch
     import paper_2305_09020_amd as pfd
     torch.cuda.set_device(0)
+    if a.steps is None:
+        a.steps = C2["steps"] if a.workload == "c2" else C3["steps"]
     res = {}
     for name, prec in (("refined", pfd.REFINED_FP32), ("fp64", pfd.PLAIN_FP64)):
         if a.only not in (name, "both"):
             continue
-        ctx, its = make_context(prec, a.refine_iters)
+        ctx, its = make_context(prec, a.refine_iters, a.workload)
         t = time_steps(ctx, a.steps, a.warmup)
         dof = ctx.planes * ctx.Nx * ctx.Ny
         res[name] = dict(t=t, dof=dof, value=dof * a.steps / t, ctx=ctx,
-                         roofline=roofline(ctx, min(a.steps, 200)))
+                         roofline=roofline(ctx, min(a.steps, 200 if a.workload == "c2" else 20)))
         print("# %-7s %.3f ms/step  %.4e DOF-steps/s  (V0 fixed point: %d iterations)"
               % (name, 1e3 * t / a.steps, dof * a.steps / t, its), file=sys.stderr, flush=True)
     main_name = "refined" if "refined" in res else "fp64"
@@ -206,11 +259,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32" if main_name == "refined" else "f64",
         "data": "synthetic",
-        "config": {"workload": "2D sessile drop, 20x20 elements order 8 (25,921 points), "
-                               "rho 1:1000, mu 1:100, eps 1:40, V_top {0,0.5,1,2} as 4 instances, "
-                               "dt 5e-5, closed box; %s path" % main_name,
-                   "instances": len(VTOP), "dof_per_step": r["dof"],
-                   "refine_iters": a.refine_iters if main_name == "refined" else 0},
+        "config": ({"workload": "2D sessile drop, 20x20 elements order 8 (25,921 points), "
+                                "rho 1:1000, mu 1:100, eps 1:40, V_top {0,0.5,1,2} as 4 instances, "
+                                "dt 5e-5, closed box; %s path" % main_name,
+                    "instances": len(VTOP), "dof_per_step": r["dof"],
+                    "refine_iters": a.refine_iters if main_name == "refined" else 0}
+                   if a.workload == "c2" else
+                   {"workload": "3D drop, 16x16 elements order 8 x 128 Fourier planes (Lz = 2, "
+                                "2,130,048 points), perturbed sphere r = 0.3, rho 1:10, mu 1:2, "
+                                "eps 1:10, dt 1e-4, walls; %s path" % main_name,
+                    "instances": 1, "dof_per_step": r["dof"],
+                    "refine_iters": a.refine_iters if main_name == "refined" else 0}),
     }
     out["roofline"] = r["roofline"]
     if "fp64" in res and "refined" in res:
@@ -218,7 +277,7 @@ def main():
         out["refined_over_fp64"] = res["refined"]["value"] / res["fp64"]["value"]
         out["fp64_roofline"] = res["fp64"]["roofline"]
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline() if a.workload == "c2" else cpu_baseline_c3()
     print(json.dumps(out), flush=True)
 
 

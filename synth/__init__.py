@@ -11,6 +11,12 @@ ambient fluid, Sec. 4.2-4.4) at the sizes of the benchmark configurations:
   C2  [0,1]^2, 20x20 elements, K = 8, dt = 5e-5, 2000 steps, sessile half-disc
       r = 0.25 at (0.5, 0), theta_s = 90 deg, eta = 0.01, rho 1:1000,
       mu 0.01:1, eps 1:40, V_top in {0, 0.5, 1, 2} (four instances).
+  C3  [0,1]^2 x [0, 2) (z periodic), 16x16 elements, K = 8, Nz = 128, dt = 1e-4, 500
+      steps, sphere r = 0.3 at (0.5, 0.5, 1.0) with a 1% radius perturbation
+      r = 0.3 (1 + 0.01 xi(x)), xi = sum of 8 cosines with integer wave vectors and
+      amplitudes / phases drawn from numpy PCG64 (seed 230509020), amplitudes
+      normalised to sum 1 (so |xi| <= 1); eta = 0.02, rho 1:10, mu 0.01:0.02,
+      eps 0.1:1 (ratio 10), walls, V = 0 / 1 on the bottom / top.
 Fluid 1 (phi = +1) is the ambient fluid, fluid 2 (phi = -1) the drop.
 """
 import math
@@ -47,3 +53,39 @@ def c2_param_dict(dt=5e-5):
 C1 = dict(name="C1", nx=4, ny=4, K=6, steps=100, center=(0.5, 0.5), r=0.25, vtop=(1.0,))
 C2 = dict(name="C2", nx=20, ny=20, K=8, steps=2000, center=(0.5, 0.0), r=0.25,
           vtop=(0.0, 0.5, 1.0, 2.0))
+
+
+def c3_param_dict(dt=1e-4):
+    eta = 0.02
+    return dict(rho1=1.0, rho2=10.0, mu1=0.01, mu2=0.02, eps1=0.1, eps2=1.0,
+                lam=lam_from_sigma(1.0, eta), eta=eta, gamma1=1e-4, theta_s_deg=90.0, dt=dt)
+
+
+C3 = dict(name="C3", nx=16, ny=16, K=8, nz=128, lz=2.0, steps=500, center=(0.5, 0.5, 1.0), r=0.3,
+          seed=230509020)
+
+
+def perturbation(X, Y, Z, lz, seed, n=8, kmax=2):
+    """xi(x) = sum_i a_i cos(2 pi (kx x + ky y + kz z / lz) + p_i), integer wave vectors in
+    [-kmax, kmax]^3 (not all zero), a_i >= 0 with sum 1, phases uniform; PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ks = []
+    while len(ks) < n:
+        k = rng.integers(-kmax, kmax + 1, size=3)
+        if np.any(k != 0):
+            ks.append(k)
+    a = rng.random(n)
+    a = a / a.sum()
+    ph = rng.random(n) * 2.0 * np.pi
+    xi = np.zeros(np.broadcast(X, Y, Z).shape)
+    for i in range(n):
+        xi = xi + a[i] * np.cos(2.0 * np.pi * (ks[i][0] * X + ks[i][1] * Y + ks[i][2] * Z / lz) + ph[i])
+    return xi
+
+
+def c3_phi0(X, Y, Z):
+    """Initial phase field of C3 on node coordinates (arrays of one shape)."""
+    xi = perturbation(X, Y, Z, C3["lz"], C3["seed"])
+    r = C3["r"] * (1.0 + 0.01 * xi)
+    d = np.sqrt((X - C3["center"][0]) ** 2 + (Y - C3["center"][1]) ** 2 + (Z - C3["center"][2]) ** 2)
+    return np.tanh((d - r) / (math.sqrt(2.0) * c3_param_dict()["eta"]))
