@@ -116,8 +116,17 @@ typedef struct {
 typedef struct {
   int side_type[4];        /* PFD_WALL / PFD_OPEN per side (x sides ignored if periodic) */
   int pot_dirichlet[4];    /* 1: V Dirichlet on the whole side                   */
-  int n_electrodes;        /* V Dirichlet segments [x0,x1] on the bottom wall    */
-  const double* electrode_x0;  /* host; segment ends must lie on element edges   */
+  /* Electrode segments on the bottom wall (eq. 21, and the gap condition
+   * dV/dn = 0 between electrodes, Sec. 2): closed intervals [x0, x1] of x whose
+   * bottom-row nodes carry Dirichlet V (its values come from PFD_SRC_VD, so each
+   * electrode may hold its own voltage); the other bottom nodes are unknowns
+   * with the natural condition.  Ends must lie on element edges, x0 < x1; with
+   * periodic x a segment is taken in [xb[0], xb[nx]) (it covers the node at
+   * xb[0] only if it starts there).  Host arrays, read during pfd_create only.
+   * The gap nodes are eliminated through an FP64 capacitance (Schur complement)
+   * matrix per Fourier mode, of size (gap nodes)^2, built at create time. */
+  int n_electrodes;
+  const double* electrode_x0;
   const double* electrode_x1;
 } pfd_bcs;
 

@@ -70,12 +70,25 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   if (m.nz > 0 && !(m.lz > 0)) { *err = "lz must be positive in 3D"; return PFD_EINVAL; }
   if (m.nz > 512) { *err = "nz above 512 is not supported"; return PFD_EINVAL; }
   if (m.nbatch < 1 || (m.nz > 0 && m.nbatch != 1)) { *err = "nbatch must be >= 1 (and 1 in 3D)"; return PFD_EINVAL; }
-  if (p->bc.n_electrodes > 0) { *err = "partial electrode segments are not available in this build"; return PFD_ENOTIMPL; }
+  if (p->bc.n_electrodes < 0 || (p->bc.n_electrodes > 0 && (!p->bc.electrode_x0 || !p->bc.electrode_x1))) {
+    *err = "bad electrode list"; return PFD_EINVAL;
+  }
+  for (int i = 0; i < p->bc.n_electrodes; ++i) {
+    // segment ends must lie on element edges
+    const double e0 = p->bc.electrode_x0[i], e1 = p->bc.electrode_x1[i];
+    bool ok0 = false, ok1 = false;
+    const double tol = 1e-10 * (m.xb[m.nx] - m.xb[0]);
+    for (int k = 0; k <= m.nx; ++k) {
+      if (std::fabs(m.xb[k] - e0) <= tol) ok0 = true;
+      if (std::fabs(m.xb[k] - e1) <= tol) ok1 = true;
+    }
+    if (!ok0 || !ok1 || !(e1 > e0)) { *err = "electrode segments must span element edges"; return PFD_EINVAL; }
+  }
   for (int s = 0; s < 4; ++s) {
     if (m.periodic_x && s >= PFD_LEFT) continue;
     if (p->bc.side_type[s] != PFD_WALL && p->bc.side_type[s] != PFD_OPEN) { *err = "side type must be WALL or OPEN"; return PFD_EINVAL; }
   }
-  bool anyV = false;
+  bool anyV = p->bc.n_electrodes > 0;
   for (int s = 0; s < 4; ++s)
     if (p->bc.pot_dirichlet[s] && !(m.periodic_x && s >= PFD_LEFT)) anyV = true;
   if (!anyV) { *err = "the potential needs a Dirichlet side"; return PFD_EINVAL; }
@@ -98,7 +111,8 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
     dbl += 4 * (size_t)m.nz * m.nz + 64; // DFT matrices
   }
   dbl += 3 * (size_t)Pg;                 // right sides
-  dbl += 8 * (size_t)Pg;                 // r (3), U, Q2, tmp, tmp2, zero
+  dbl += 9 * (size_t)Pg;                 // r (3), U, Q2, tmp, tmp2, zero, Ybuf
+  if (p->bc.n_electrodes > 0) dbl += (size_t)L->planes * (L->Nx * (size_t)L->Nx + L->Nx) + 4 * (size_t)L->Nx;
   dbl += 7 * (size_t)L->Ng;              // boundary masses, mass
   const int NN = std::max(L->Nx, L->Ny);
   dbl += 8 * (3 * (size_t)NN * NN + 3 * NN + 8);  // up to 8 distinct 1D operators
@@ -177,7 +191,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   auto side_dir = [&](int fam, int s) -> bool {
     if (per && s >= PFD_LEFT) return false;
     switch (fam) {
-      case PFD_FAM_V: return bc.pot_dirichlet[s] != 0;
+      case PFD_FAM_V: return bc.pot_dirichlet[s] != 0 || (s == PFD_BOTTOM && bc.n_electrodes > 0);
       case PFD_FAM_P: return bc.side_type[s] == PFD_OPEN;
       case PFD_FAM_U: return bc.side_type[s] == PFD_WALL;
       default: return false;
@@ -262,6 +276,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   for (int i = 0; i < 3; ++i) c->b[i] = D(Pg);
   c->r = D(3 * Pg); c->U = D(Pg); c->Q2 = D(Pg); c->tmp = D(Pg); c->tmp2 = D(Pg);
   double* zero = D(Pg);
+  c->Ybuf = D(Pg);
   for (int s = 0; s < 4; ++s) c->bm_side[s] = D(c->Ng);
   c->bm_open = D(c->Ng); c->bm_wall = D(c->Ng); c->Mdiag = D(c->Ng);
   c->d_hx = D(m.nx); c->d_hy = D(m.ny);
@@ -401,10 +416,55 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     g.side_type[s] = (per && s >= PFD_LEFT) ? -1 : bc.side_type[s];
   }
   c->zero_buf = zero;
+  // ---- electrode gap nodes of the potential operator (Schur complement, FP64)
+  if (bc.n_electrodes > 0 && !bc.pot_dirichlet[PFD_BOTTOM]) {
+    const Dir1D& vx = c->dirs[c->fam[PFD_FAM_V].ix];
+    const Dir1D& vy = c->dirs[c->fam[PFD_FAM_V].iy];
+    Elec& E = c->elec;
+    E.ebot.assign(c->Nx, 0);
+    const double tol = 1e-10 * (m.xb[m.nx] - m.xb[0]);
+    for (int ix = 0; ix < c->Nx; ++ix) {
+      const double x = vx.coord[ix];
+      for (int i = 0; i < bc.n_electrodes; ++i)
+        if (x >= bc.electrode_x0[i] - tol && x <= bc.electrode_x1[i] + tol) E.ebot[ix] = 1;
+      if (vx.dir[ix]) E.ebot[ix] = 1;
+    }
+    std::vector<int> gapidx(c->Nx, -1);
+    for (int ix = 0; ix < c->Nx; ++ix)
+      if (!E.ebot[ix]) {
+        gapidx[ix] = (int)E.gap.size();
+        E.gap.push_back(ix);
+      }
+    E.ng = (int)E.gap.size();
+    if (E.ng > 0) {
+      E.d_gap = (int*)carve(c, sizeof(int) * E.ng);
+      E.d_gapidx = (int*)carve(c, sizeof(int) * c->Nx);
+      E.d_ebot = (unsigned char*)carve(c, c->Nx);
+      E.d_Sinv = D((long)c->planes * E.ng * E.ng);
+      E.d_dG = D((long)c->planes * E.ng);
+      if (!E.d_gap || !E.d_gapidx || !E.d_ebot || !E.d_Sinv || !E.d_dG) {
+        g_create_err = "workspace too small (electrodes)"; delete c; return PFD_ENOMEM;
+      }
+      std::vector<double> all((size_t)c->planes * E.ng * E.ng), Sinv;
+      double last_shift = -1.0;
+      for (int p = 0; p < c->planes; ++p) {
+        const double sh = c->fam[PFD_FAM_V].hshift[p];
+        if (p == 0 || sh != last_shift) electrode_schur_inverse(vx, vy, E.gap, K, sh, Sinv);
+        last_shift = sh;
+        std::copy(Sinv.begin(), Sinv.end(), all.begin() + (size_t)p * E.ng * E.ng);
+      }
+      e = hipMemcpy(E.d_gap, E.gap.data(), sizeof(int) * E.ng, hipMemcpyHostToDevice);
+      if (!e) e = hipMemcpy(E.d_gapidx, gapidx.data(), sizeof(int) * c->Nx, hipMemcpyHostToDevice);
+      if (!e) e = hipMemcpy(E.d_ebot, E.ebot.data(), c->Nx, hipMemcpyHostToDevice);
+      if (!e) e = hipMemcpy(E.d_Sinv, all.data(), 8 * all.size(), hipMemcpyHostToDevice);
+      if (e) { g_create_err = std::string("HIP error in create: ") + hipGetErrorString(e); delete c; return PFD_EHIP; }
+    }
+  }
   for (int f = 0; f < 5; ++f) {
     const Dir1D& dx = c->dirs[c->fam[f].ix];
     const Dir1D& dy = c->dirs[c->fam[f].iy];
-    c->lift[f] = Lift{dx.dK0, dx.dKN, dy.dK0, dy.dKN, dx.dM1, dy.dM1, dx.ddir, dy.ddir};
+    c->lift[f] = Lift{dx.dK0, dx.dKN, dy.dK0, dy.dKN, dx.dM1, dy.dM1, dx.dKb, dx.ddir, dy.ddir,
+                      (f == PFD_FAM_V && c->elec.ng > 0) ? c->elec.d_ebot : nullptr};
   }
   *out = c;
   return PFD_OK;

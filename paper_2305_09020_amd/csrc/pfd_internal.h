@@ -57,10 +57,23 @@ struct Par {
 
 enum { F_UX = 0, F_UY, F_UZ, F_P, F_PHI, F_PSI, F_V, F_EX, F_EY, F_EZ, F_E2, F_NSTATE };
 
-// Dirichlet lifting data of one solve family (device pointers)
+// Dirichlet lifting data of one solve family (device pointers).  ebot (potential family with
+// partial electrode segments only): 1 on bottom-row nodes that are Dirichlet (electrodes),
+// 0 on the gap nodes between them, which are unknowns although diry[0] marks the base
+// operator's bottom row as Dirichlet.
 struct Lift {
-  const double *Kx0, *KxN, *Ky0, *KyN, *Mx, *My;
-  const unsigned char *dirx, *diry;
+  const double *Kx0, *KxN, *Ky0, *KyN, *Mx, *My, *KxB;
+  const unsigned char *dirx, *diry, *ebot;
+};
+
+// gap-node Schur complement data of the potential family (electrode segments)
+struct Elec {
+  int ng = 0;                       // number of gap nodes on the bottom row
+  std::vector<int> gap;             // their x indices
+  std::vector<unsigned char> ebot;  // Nx flags: Dirichlet (electrode) bottom nodes
+  int *d_gap = nullptr, *d_gapidx = nullptr;
+  unsigned char* d_ebot = nullptr;
+  double *d_Sinv = nullptr, *d_dG = nullptr;  // planes x ng x ng, planes x ng
 };
 
 }  // namespace pfd
@@ -78,6 +91,8 @@ struct pfd_ctx {
   std::vector<pfd::Dir1D> dirs;            // distinct 1D operators
   pfd::Family fam[5];
   pfd::Lift lift[5];
+  pfd::Elec elec;
+  double* Ybuf = nullptr;                  // base-operator correction (electrode solves)
   std::vector<double> beta2, betad;        // per plane (spectral packing in 3D)
   double *d_beta2 = nullptr, *d_betad = nullptr;
   // device buffers
@@ -133,6 +148,8 @@ void gll_rule(int K, std::vector<double>& x, std::vector<double>& w, std::vector
 void build_dir1d(Dir1D& d, int ne, const double* bp, int K, bool periodic, bool dir_lo, bool dir_hi,
                  const std::vector<double>& xi, const std::vector<double>& w,
                  const std::vector<double>& D);
+void electrode_schur_inverse(const Dir1D& dx, const Dir1D& dy, const std::vector<int>& gap, int K, double c,
+                             std::vector<double>& Sinv);
 
 // kernels (pfd_kernels.hip); all enqueue on ctx->stream
 hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp, int project, const double* r0);

@@ -152,11 +152,19 @@ __device__ __forceinline__ double dss(const Geo& g, const double* L, int pl, int
 //    residual r = b - A x_D is folded in here: each family's Dirichlet set is a union of
 //    whole sides, so (A x_D) at a free node needs only the first and last columns of the
 //    1D stiffness matrices (Kx0 = Kx[:,0], KxN = Kx[:,Nx-1], likewise in y).
+// Dirichlet node of a family (gap nodes of a partial electrode row are unknowns)
+__device__ __forceinline__ bool is_dir(const unsigned char* dirx, const unsigned char* diry,
+                                       const unsigned char* ebot, int ix, int iy) {
+  if (dirx[ix]) return true;
+  if (!diry[iy]) return false;
+  return !(iy == 0 && ebot && !ebot[ix]);
+}
+
 __device__ __forceinline__ void rhs_out(const Geo& g, const Par& P, const Lift& L, const double* gD,
                                         const double* Fn, const double* Fo, long id, long pofs, int ix, int iy,
                                         double b, double* bb, double* r, double* x0) {
   bb[id] = b;
-  const bool dn = L.dirx[ix] || L.diry[iy];
+  const bool dn = is_dir(L.dirx, L.diry, L.ebot, ix, iy);
   if (Fn) {
     x0[id] = dn ? gD[id] : P.cs_n * Fn[id] + P.cs_o * Fo[id];
     return;
@@ -169,8 +177,16 @@ __device__ __forceinline__ void rhs_out(const Geo& g, const Par& P, const Lift& 
   double ax = 0.0, ay = 0.0;
   if (L.dirx[0]) ax += L.Kx0[ix] * gD[pofs + (long)iy * g.Nx];
   if (L.dirx[g.Nx - 1]) ax += L.KxN[ix] * gD[pofs + (long)iy * g.Nx + g.Nx - 1];
-  if (L.diry[0]) ay += L.Ky0[iy] * gD[pofs + ix];
+  if (L.diry[0] && iy > 0 && (!L.ebot || L.ebot[ix])) ay += L.Ky0[iy] * gD[pofs + ix];
   if (L.diry[g.Ny - 1]) ay += L.KyN[iy] * gD[pofs + (long)(g.Ny - 1) * g.Nx + ix];
+  if (L.ebot && iy == 0) {  // gap node: coupling along the bottom row to the electrode nodes
+    for (int d = -g.K; d <= g.K; ++d) {
+      int j = ix + d;
+      if (g.periodic) j = (j < 0) ? j + g.Nx : (j >= g.Nx ? j - g.Nx : j);
+      else if (j < 0 || j >= g.Nx) continue;
+      if (L.ebot[j] && !L.dirx[j]) ax += L.KxB[(long)(d + g.K) * g.Nx + ix] * gD[pofs + j];
+    }
+  }
   r[id] = b - (ax * L.My[iy] + L.Mx[ix] * ay);
   x0[id] = 0.0;
 }
@@ -575,7 +591,7 @@ __global__ void k_residual(int Nx, int Ny, int planes, int perx, const double* _
                            const double* __restrict__ KyB, const double* __restrict__ My,
                            const unsigned char* __restrict__ diry, const double* __restrict__ shift,
                            const double* __restrict__ bb, const double* __restrict__ x, double* __restrict__ r,
-                           int apply_only, double* norms) {
+                           int apply_only, double* norms, const unsigned char* __restrict__ ebot) {
   const long Ng = (long)Nx * Ny;
   const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= planes * Ng) return;
@@ -603,7 +619,7 @@ __global__ void k_residual(int Nx, int Ny, int planes, int perx, const double* _
     r[id] = Av;
     return;
   }
-  const bool dn = dirx[ix] || diry[iy];
+  const bool dn = is_dir(dirx, diry, ebot, ix, iy);
   const double v = dn ? 0.0 : bb[id] - Av;
   r[id] = v;
   if (norms) {  // diagnostics only
@@ -704,8 +720,10 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA,
     } else if (EPI == 1) {
       const double den = lr[mm] + lc[n] + shift[pl];
       C[o] = (den != 0.0) ? T(double(v) / den) : T(0);
-    } else {
+    } else if (EPI == 2) {
       X[o] += double(v);
+    } else {
+      X[o] = double(v);
     }
   }
 }
@@ -804,7 +822,7 @@ static void residual(pfd_ctx* c, int fam, const double* b, const double* x, doub
   case KK:                                                                                                \
     LAUNCH(PFD_PROF_RESID, k_residual<KK>, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->planes,   \
                        (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, F.dshift, b, x, r, \
-                       apply_only, norms);                                                                \
+                       apply_only, norms, c->lift[fam].ebot);                                             \
     break;
   switch (c->K) {
     RES_CASE(2) RES_CASE(3) RES_CASE(4) RES_CASE(5) RES_CASE(6) RES_CASE(7) RES_CASE(8) RES_CASE(9)
@@ -823,7 +841,8 @@ hipError_t apply(pfd_ctx* c, int fam, const double* x, double* y, int ncomp) {
 // as four batched GEMMs over all planes (Sx, Sy shared by every plane).
 template <typename T>
 static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const double* shift, const T* Sx,
-                        const T* SxT, const T* Sy, const T* SyT, const double* r, double* x) {
+                        const T* SxT, const T* Sy, const T* SyT, const double* r, double* x,
+                        bool overwrite = false) {
   const int Nx = c->Nx, Ny = c->Ny, P = c->planes;
   const long Ng = c->Ng;
   T* t1 = reinterpret_cast<T*>(c->tmp);
@@ -831,7 +850,74 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
   gemm<T, double, T, 0>(c, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr, nullptr, nullptr);
   gemm<T, T, T, 1>(c, P, SyT, 0, t1, Ng, Ny, Nx, Ny, t2, Ng, dy.dlam, dx.dlam, shift, nullptr);
   gemm<T, T, T, 0>(c, P, Sy, 0, t2, Ng, Ny, Nx, Ny, t1, Ng, nullptr, nullptr, nullptr, nullptr);
-  gemm<T, T, T, 2>(c, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr, nullptr, nullptr, x);
+  if (overwrite)
+    gemm<T, T, T, 3>(c, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr, nullptr, nullptr, x);
+  else
+    gemm<T, T, T, 2>(c, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr, nullptr, nullptr, x);
+}
+
+// Electrode gap nodes (potential family): with Y = A_FF^{-1} r_F from the base operator,
+//   t_G = r_G - A_GF Y,  dG = S_G^{-1} t_G  (S_G^{-1} per plane, FP64, from set-up)
+// where A_GF Y at gap node (g, 0) = Mx[g] sum_{iy=1..K} Ky[0][iy] Y(g, iy).
+__global__ void k_elec_gap(int Nx, int Ny, int K, long Ng, int ng, const int* __restrict__ gap,
+                           const double* __restrict__ Mx, const double* __restrict__ Ky0,
+                           const double* __restrict__ r, const double* __restrict__ Y,
+                           const double* __restrict__ Sinv, double* __restrict__ dG) {
+  __shared__ double t[PFD_NMAX];
+  const int pl = blockIdx.x;
+  const double* rp = r + pl * Ng;
+  const double* Yp = Y + pl * Ng;
+  const int kmax = min(K, Ny - 1);
+  for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    const int gx = gap[i];
+    double acc = 0.0;
+    for (int iy = 1; iy <= kmax; ++iy) acc += Ky0[iy] * Yp[(long)iy * Nx + gx];
+    t[i] = rp[gx] - Mx[gx] * acc;
+  }
+  __syncthreads();
+  const double* Sp = Sinv + (long)pl * ng * ng;
+  for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < ng; ++j) acc += Sp[(long)i * ng + j] * t[j];
+    dG[(long)pl * ng + i] = acc;
+  }
+}
+
+// z = -A_FG dG (nonzero in the gap columns, rows 1..K), and x += Y (+ dG on the gap nodes)
+__global__ void k_elec_z(int Nx, int Ny, int K, int planes, int ng, const int* __restrict__ gapidx,
+                         const double* __restrict__ Mx, const double* __restrict__ Ky0,
+                         const double* __restrict__ dG, const double* __restrict__ Y, double* __restrict__ z,
+                         double* __restrict__ x) {
+  const long Ng = (long)Nx * Ny;
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= planes * Ng) return;
+  const int pl = (int)(id / Ng);
+  const int node = (int)(id - pl * Ng);
+  const int iy = node / Nx, ix = node - iy * Nx;
+  const int i = gapidx[ix];
+  double zv = 0.0, add = Y[id];
+  if (i >= 0) {
+    const double d = dG[(long)pl * ng + i];
+    if (iy >= 1 && iy <= K) zv = -Mx[ix] * Ky0[iy] * d;
+    if (iy == 0) add += d;
+  }
+  z[id] = zv;
+  x[id] += add;
+}
+
+// one correction of the potential family with electrode gap nodes:
+//   x += A_FF^{-1}(r_F - A_FG dG) on F,  x += dG on G
+template <typename T>
+static void elec_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const double* shift, const T* Sx,
+                         const T* SxT, const T* Sy, const T* SyT, const double* r, double* x) {
+  const long tot = (long)c->planes * c->Ng;
+  double* z = c->r + tot;   // scratch block of r (the potential solve uses block 0)
+  fdm_correct<T>(c, dx, dy, shift, Sx, SxT, Sy, SyT, r, c->Ybuf, true);
+  LAUNCH(PFD_PROF_OTHER, k_elec_gap, dim3(c->planes), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->K, c->Ng,
+         c->elec.ng, c->elec.d_gap, dx.dM1, dy.dK0, r, c->Ybuf, c->elec.d_Sinv, c->elec.d_dG);
+  LAUNCH(PFD_PROF_OTHER, k_elec_z, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->K, c->planes,
+         c->elec.ng, c->elec.d_gapidx, dx.dM1, dy.dK0, c->elec.d_dG, c->Ybuf, z, x);
+  fdm_correct<T>(c, dx, dy, shift, Sx, SxT, Sy, SyT, z, x);
 }
 
 // Solve (K + c M) x = b for ncomp stacked right sides (each planes*Ng), x holding the initial
@@ -858,7 +944,12 @@ hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp, int
         residual(c, fam, bc, xc, c->r, 0, nullptr);
         if (F.any_singular && project) plane_fix(c, fam, c->r, 1);
       }
-      if (fp32)
+      const bool elec = fam == PFD_FAM_V && c->elec.ng > 0;
+      if (fp32 && elec)
+        elec_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, rin, xc);
+      else if (elec)
+        elec_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, rin, xc);
+      else if (fp32)
         fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, rin, xc);
       else
         fdm_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, rin, xc);

@@ -211,3 +211,84 @@ void build_dir1d(Dir1D& d, int ne, const double* bp, int K, bool periodic, bool 
 }
 
 }  // namespace pfd
+
+namespace pfd {
+
+// Gap-node Schur complement of the potential operator with partial electrode sets.
+// The fast-diagonalisation base operator A_D treats the whole bottom row as Dirichlet; the
+// true operator releases the gap nodes G of that row (bottom nodes outside the electrode
+// segments).  With F the free nodes of A_D:
+//   S_G = A_GG - A_GF A_FF^{-1} A_FG,
+// where A_FG couples a gap node (g, 0) only to (g, iy), iy = 1..K, through Mx[g] Ky[iy][0],
+// and A_GG = My[0] Kx[g_i][g_j] + delta_ij Mx[g_i] (Ky[0][0] + c My[0]).
+// Returns S_G^{-1} (row-major n_g x n_g) for the total shift c.
+void electrode_schur_inverse(const Dir1D& dx, const Dir1D& dy, const std::vector<int>& gap, int K, double c,
+                             std::vector<double>& Sinv) {
+  const int Nx = dx.N, Ny = dy.N, ng = (int)gap.size();
+  const int kmax = std::min(K, Ny - 1);
+  std::vector<double> S((size_t)ng * ng, 0.0);
+  std::vector<double> u(Ny), T((size_t)Ny * Nx);
+  for (int j = 0; j < ng; ++j) {
+    const int gj = gap[j];
+    // z = A_FG e_j: column gj, rows 1..K, value Mx[gj] Ky[iy][0]
+    // w = A_FF^{-1} z = Sy [ (Sy^T z Sx) ./ (ly + lx + c) ] Sx^T ; z has one column
+    for (int a = 0; a < Ny; ++a) {
+      double acc = 0.0;
+      for (int iy = 1; iy <= kmax; ++iy) acc += dy.S[(size_t)iy * Ny + a] * dx.M1[gj] * dy.K1[(size_t)iy * Ny];
+      u[a] = acc;
+    }
+    for (int a = 0; a < Ny; ++a)
+      for (int b = 0; b < Nx; ++b) {
+        const double den = dy.lam[a] + dx.lam[b] + c;
+        T[(size_t)a * Nx + b] = den != 0.0 ? u[a] * dx.S[(size_t)gj * Nx + b] / den : 0.0;
+      }
+    for (int i = 0; i < ng; ++i) {
+      const int gi = gap[i];
+      // (A_GF w)_i = Mx[gi] sum_{iy=1..K} Ky[0][iy] w(gi, iy),  w(gi, iy) = sum_a Sy[iy][a] ta[a]
+      for (int a = 0; a < Ny; ++a) {
+        double acc = 0.0;
+        for (int b = 0; b < Nx; ++b) acc += T[(size_t)a * Nx + b] * dx.S[(size_t)gi * Nx + b];
+        u[a] = acc;  // (reuses u as ta: u of column j is no longer needed)
+      }
+      double agw = 0.0;
+      for (int iy = 1; iy <= kmax; ++iy) {
+        double w = 0.0;
+        for (int a = 0; a < Ny; ++a) w += dy.S[(size_t)iy * Ny + a] * u[a];
+        agw += dy.K1[(size_t)iy] * w;
+      }
+      agw *= dx.M1[gi];
+      double agg = dy.M1[0] * dx.K1[(size_t)gi * Nx + gj];
+      if (i == j) agg += dx.M1[gi] * (dy.K1[0] + c * dy.M1[0]);
+      S[(size_t)i * ng + j] = agg - agw;
+    }
+  }
+  // Gauss-Jordan inverse with partial pivoting (S is symmetric positive definite)
+  Sinv.assign((size_t)ng * ng, 0.0);
+  for (int i = 0; i < ng; ++i) Sinv[(size_t)i * ng + i] = 1.0;
+  for (int col = 0; col < ng; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < ng; ++r)
+      if (std::fabs(S[(size_t)r * ng + col]) > std::fabs(S[(size_t)piv * ng + col])) piv = r;
+    if (piv != col)
+      for (int k = 0; k < ng; ++k) {
+        std::swap(S[(size_t)col * ng + k], S[(size_t)piv * ng + k]);
+        std::swap(Sinv[(size_t)col * ng + k], Sinv[(size_t)piv * ng + k]);
+      }
+    const double d = S[(size_t)col * ng + col];
+    for (int k = 0; k < ng; ++k) {
+      S[(size_t)col * ng + k] /= d;
+      Sinv[(size_t)col * ng + k] /= d;
+    }
+    for (int r = 0; r < ng; ++r) {
+      if (r == col) continue;
+      const double f = S[(size_t)r * ng + col];
+      if (f == 0.0) continue;
+      for (int k = 0; k < ng; ++k) {
+        S[(size_t)r * ng + k] -= f * S[(size_t)col * ng + k];
+        Sinv[(size_t)r * ng + k] -= f * Sinv[(size_t)col * ng + k];
+      }
+    }
+  }
+}
+
+}  // namespace pfd

@@ -49,3 +49,10 @@ def test_host_only_validation():
     par2 = dict(par, dt=-1.0)
     with pytest.raises(pfd.PfdError):
         pfd.workspace_bytes(pfd.make_problem(xb, xb, 6, par2, [0, 0, 0, 0], [1, 1, 0, 0]))
+    # electrode segments: ends on element edges accepted, others rejected
+    el = pfd.make_problem(xb, xb, 6, par, [0, 0, 0, 0], [0, 0, 0, 0], electrodes=[(0.25, 0.5)])
+    assert pfd.workspace_bytes(el) > pfd.workspace_bytes(good)
+    for segs in ([(0.3, 0.5)], [(0.5, 0.25)]):
+        with pytest.raises(pfd.PfdError):
+            pfd.workspace_bytes(pfd.make_problem(xb, xb, 6, par, [0, 0, 0, 0], [0, 0, 0, 0],
+                                                 electrodes=segs))

@@ -68,6 +68,34 @@ def test_3d_mode_solves_match_sparse_lu(precision):
         assert e < tol, (name, e)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_3d_potential_mode_solves_with_electrodes(precision):
+    """Per-mode potential operators K + beta_k^2 M with a partial electrode segment on the
+    bottom wall (gap nodes unknown in every mode) against SciPy LU."""
+    torch = _torch()
+    Nz, Lz = 8, 1.7
+    xb = np.linspace(0.0, 1.0, 4)
+    m = Mesh2D(xb, xb, 6, periodic_x=True)
+    bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, electrodes=[(1.0 / 3.0, 2.0 / 3.0)])
+    par = c1_params()
+    sch = Scheme(m, par, bc, Nz=Nz, Lz=Lz)
+    ctx = gpu_context(m, par, bc, nz=Nz, lz=Lz, precision=precision, refine_iters=3)
+    rng = np.random.default_rng(8)
+    tol = 1e-11 if precision == 0 else 1e-9
+    b = rng.standard_normal((Nz, m.Ng))
+    gd = rng.standard_normal((Nz, m.Ng))
+    ref = np.zeros((Nz, m.Ng))
+    for p in range(Nz):
+        k, part = packed_mode(p, Nz)
+        ref[p] = sch.solve("V", k, b[p], gd[p])
+    bt = torch.tensor(b, device="cuda")
+    xt = torch.tensor(gd, device="cuda")
+    ctx.solve(0, bt, xt)
+    torch.cuda.synchronize()
+    e = rel_err(xt.cpu().numpy(), ref)
+    assert e < tol, e
+
+
 def run3d(m, bc, par, Nz, Lz, phi0, u0, src, nsteps, precision=0, equilibrium=False,
           per_step_src=None, V0=None, P0=None, prev=None, init_V=True):
     _torch()
@@ -162,6 +190,23 @@ def test_3d_manufactured_parity():
     K, dt, n = 6, 1e-3, 6
     case = mms_setup("eq81b", K, dt, Nz=8)
     m, par, bc = case["mesh"], case["par"], case["bc"]
+    f0, fm = mms_initial(case, dt)
+    x, y, z = case["x"], case["y"], case["z"]
+    mf = case["mf"]
+    src_fn = lambda i: mf.sources(x, y, z, (i + 1) * dt, case["sides"])
+    out, ctx = run3d(m, bc, par, 8, 2.0, f0["phi"], f0["u"], src_fn(0), n, per_step_src=src_fn,
+                     V0=f0["V"], P0=f0["P"], init_V=False,
+                     prev=dict(phi=fm["phi"], u=fm["u"], P=fm["P"], V=fm["V"]))
+    check(out, 1e-10)
+
+
+def test_3d_manufactured_parity_electrode():
+    """eq. (81) manufactured solution with its electrode on x in [0, 1] of the bottom wall
+    and the natural condition on x in (1, 2): parity with the oracle step by step."""
+    K, dt, n = 6, 1e-3, 6
+    case = mms_setup("eq81", K, dt, Nz=8)
+    m, par, bc = case["mesh"], case["par"], case["bc"]
+    assert bc.electrodes
     f0, fm = mms_initial(case, dt)
     x, y, z = case["x"], case["y"], case["z"]
     mf = case["mf"]

@@ -60,6 +60,41 @@ def test_solve_matches_sparse_lu(periodic, top, precision):
         assert e < tol, (name, e)
 
 
+@pytest.mark.parametrize("periodic,segs,top_dir", [
+    (True, [(0.0, 1.0 / 3.0)], False),
+    (True, [(0.0, 1.0 / 3.0), (2.0 / 3.0, 1.0)], True),
+    (False, [(1.0 / 3.0, 2.0 / 3.0)], False),
+])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_potential_solve_with_electrode_segments(periodic, segs, top_dir, precision):
+    """Potential operator with partial electrode segments on the bottom wall (Dirichlet on
+    the segments, natural condition on the gaps, Sec. 5 test setups) against SciPy LU."""
+    torch = _torch()
+    n, K = 3, 7
+    xb = np.linspace(0.0, 1.0, n + 1)
+    m = Mesh2D(xb, xb, K, periodic_x=periodic)
+    side = {BOTTOM: WALL, TOP: OPEN}
+    if not periodic:
+        side.update({LEFT: WALL, RIGHT: WALL})
+    bc = BCs(side=side, pot_sides=(TOP,) if top_dir else (), electrodes=segs)
+    par = c1_params()
+    sch = Scheme(m, par, bc)
+    assert 0 < len(sch.dir["V"]) < m.Nx + (m.Nx if top_dir else 0)
+    ctx = gpu_context(m, par, bc, precision=precision, refine_iters=3)
+    rng = np.random.default_rng(11)
+    tol = 1e-11 if precision == 0 else 1e-9
+    for trial in range(2):
+        b = rng.standard_normal(m.Ng)
+        g = rng.standard_normal(m.Ng)
+        xr = sch.solve("V", 0, b, g)
+        bt = torch.tensor(b, device="cuda")
+        xt = torch.tensor(g, device="cuda")
+        ctx.solve(0, bt, xt)
+        torch.cuda.synchronize()
+        e = rel_err(xt.cpu().numpy(), xr)
+        assert e < tol, (trial, e)
+
+
 # ------------------------------------------------------------- full-step parity
 def run_pair(m, par, bc, phi0, u0, src, nsteps, nbatch=1, precision=0, equilibrium=False,
              per_step_src=None, init_V=True, V0=None, prev=None, P0=None, refine_iters=2):
