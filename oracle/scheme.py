@@ -530,6 +530,52 @@ class Scheme:
         return d
 
     # -- diagnostics ------------------------------------------------------------------
+    def energy_terms(self, phi, u, E):
+        """Discrete total energy of eq. (14), term by term, on the GLL quadrature:
+        kinetic  int 1/2 rho(phi) |u|^2,
+        mixing   int F(phi, grad phi) of eq. (double_well): 1/2 lambda phi^T K phi (assembled
+                 stiffness, per plane) + 1/2 lambda int (d_z phi)^2 (3D) + lambda/(4 eta^2) int (phi^2-1)^2,
+        electric int 1/2 D.E = 1/2 eps(phi) |E|^2 (D = eps E),
+        wall     int over the wall sides of Theta(phi), eq. (theta_def), with gamma = sigma =
+                 2 sqrt(2) lambda / (3 eta) and the constant (gamma_s1 + gamma_s2)/2 left out.
+        phi: (planes, Ng); u, E: tuples of d (planes, Ng) arrays.  3D integrates over z with Lz/Nz."""
+        m, P = self.m, self.par
+        phi = np.atleast_2d(phi)
+        wz = self.Lz / self.Nz if self.is3d else 1.0
+        Md = m.Mdiag[None, :]
+        rho = P.rho(phi)
+        kin = 0.5 * np.sum(Md * rho * sum(np.atleast_2d(c) ** 2 for c in u)) * wz
+        grad = sum(float(pl @ (m.Kst @ pl)) for pl in phi)
+        if self.is3d:
+            grad += float(np.sum(Md * self.dz(phi) ** 2))
+        bulk = np.sum(Md * (phi * phi - 1.0) ** 2)
+        mix = (0.5 * P.lam * grad + P.lam / (4.0 * P.eta ** 2) * bulk) * wz
+        elec = 0.5 * np.sum(Md * P.eps(phi) * sum(np.atleast_2d(c) ** 2 for c in E)) * wz
+        sigma = 2.0 * math.sqrt(2.0) * P.lam / (3.0 * P.eta)
+        cth = math.cos(math.radians(P.theta_s_deg))
+        theta = sigma * cth * phi * (phi * phi - 3.0) / 4.0
+        wall = float(np.sum(self.Bs[None, :] * theta)) * wz if len(self.wall_sides) else 0.0
+        return dict(kinetic=float(kin), mixing=float(mix), electric=float(elec), wall=wall,
+                    total=float(kin + mix + elec + wall))
+
+    def energy(self):
+        """energy_terms of the current state (E from the last potential update)."""
+        cur = self.state["cur"]
+        return self.energy_terms(cur["phi"], cur["u"], self.out["E"])
+
+    def march_to_equilibrium(self, src, tol, max_steps):
+        """Equilibrium system (u = 0): step until r_m = max |phi^{m+1} - phi^m| <= tol
+        (checked every step) or max_steps.  Returns (steps, r_m history)."""
+        hist = []
+        for n in range(max_steps):
+            prev = self.state["cur"]["phi"].copy()
+            self.step(src, equilibrium=True)
+            r = float(np.max(np.abs(self.state["cur"]["phi"] - prev)))
+            hist.append(r)
+            if r <= tol:
+                return n + 1, hist
+        return max_steps, hist
+
     def mass(self, f=None):
         """int_h phi over the domain (per plane summed; 3D includes Lz/Nz)."""
         f = self.state["cur"]["phi"] if f is None else f

@@ -309,3 +309,102 @@ def test_fixed_point_potential_converges_to_direct_solve():
     Vit, its = sch.iterate_potential(sch.zeros(), sch._src(src, "Vd"), tol=1e-14, maxit=2000)
     assert its < 2000
     np.testing.assert_allclose(Vit, Vdir, atol=1e-12)
+
+
+# ------------------------------------------------------------- energy of eq. (14)
+def _energy_scheme(nx, ny, K, periodic, side, par, Nz=None, Lz=0.0, xb=(0.0, 1.0), yb=(0.0, 1.0)):
+    m = Mesh2D(np.linspace(xb[0], xb[1], nx + 1), np.linspace(yb[0], yb[1], ny + 1), K,
+               periodic_x=periodic)
+    return m, Scheme(m, par, BCs(side=side, pot_sides=(BOTTOM,)), Nz=Nz, Lz=Lz)
+
+
+def test_energy_flat_interface_equals_surface_tension():
+    """A flat tanh interface (the 1D equilibrium profile of the double-well energy, eq.
+    double_well) carries mixing energy sigma per unit length: int F dy = 2 sqrt(2) lambda /
+    (3 eta) = sigma.  Side walls are periodic; the two wall terms cancel (Theta odd about 0
+    up to its constant, and phi odd about the mid-line)."""
+    eta = 0.04
+    par = Params(rho1=1, rho2=3, mu1=0.01, mu2=0.02, eps1=1, eps2=5, lam=0.02, eta=eta,
+                 gamma1=1e-3, theta_s_deg=60.0, dt=1e-4)
+    m, sch = _energy_scheme(1, 8, 12, True, {BOTTOM: WALL, TOP: WALL}, par)
+    phi = np.tanh((m.Y.ravel() - 0.5) / (math.sqrt(2.0) * eta))
+    zero = np.zeros(m.Ng)
+    e = sch.energy_terms(phi, (zero, zero), (zero, zero))
+    sigma = 2.0 * math.sqrt(2.0) * par.lam / (3.0 * eta)
+    assert abs(e["mixing"] - sigma) < 1e-6 * sigma, (e, sigma)
+    assert abs(e["wall"]) < 1e-13 and e["kinetic"] == 0.0 and e["electric"] == 0.0
+
+
+def test_energy_kinetic_electric_wall_closed_forms():
+    """Uniform phase phi = 1 (rho = rho1, eps = eps1), u = (sin(pi x) sin(pi y), 0),
+    E = (0, 2): kinetic rho1/8, electric 1/2 eps1 * 4, mixing 0, and with walls on all four
+    sides of the unit square the wall energy 4 Theta(1) = -4 sigma cos(theta_s) / 2."""
+    par = Params(rho1=2.0, rho2=7.0, mu1=0.01, mu2=0.02, eps1=3.0, eps2=5.0, lam=0.01,
+                 eta=0.02, gamma1=1e-3, theta_s_deg=50.0, dt=1e-4)
+    side = {BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}
+    m, sch = _energy_scheme(3, 3, 10, False, side, par)
+    x, y = m.X.ravel(), m.Y.ravel()
+    phi = np.ones(m.Ng)
+    ux = np.sin(math.pi * x) * np.sin(math.pi * y)
+    zero = np.zeros(m.Ng)
+    e = sch.energy_terms(phi, (ux, zero), (zero, 2.0 * np.ones(m.Ng)))
+    sigma = 2.0 * math.sqrt(2.0) * par.lam / (3.0 * par.eta)
+    assert abs(e["kinetic"] - par.rho1 / 8.0) < 1e-10
+    assert abs(e["electric"] - 0.5 * par.eps1 * 4.0) < 1e-12
+    assert abs(e["mixing"]) < 1e-12
+    wall = 4.0 * sigma * math.cos(math.radians(par.theta_s_deg)) * (1.0 * (1.0 - 3.0)) / 4.0
+    assert abs(e["wall"] - wall) < 1e-12 * abs(wall)
+    assert abs(e["total"] - (e["kinetic"] + e["electric"] + e["wall"])) < 1e-12
+
+
+def test_energy_3d_z_gradient_and_double_well():
+    """3D: phi = a cos(2 pi z / Lz), uniform in x-y on a periodic-x box: the z-gradient part
+    1/2 lambda a^2 (2 pi / Lz)^2 (Lz / 2) |A| and the double-well part
+    lambda / (4 eta^2) |A| Lz (3 a^4 / 8 - a^2 + 1), |A| the x-y area (trapezoid rule in z is
+    exact for these trigonometric polynomials)."""
+    a, Lz, Nz = 0.7, 1.3, 16
+    par = Params(rho1=1, rho2=3, mu1=0.01, mu2=0.02, eps1=1, eps2=5, lam=0.03, eta=0.05,
+                 gamma1=1e-3, theta_s_deg=90.0, dt=1e-4)
+    m, sch = _energy_scheme(2, 2, 6, True, {BOTTOM: WALL, TOP: OPEN}, par, Nz=Nz, Lz=Lz,
+                            xb=(0.0, 2.0), yb=(0.0, 0.5))
+    z = np.arange(Nz) * Lz / Nz
+    phi = np.broadcast_to((a * np.cos(2 * math.pi * z / Lz))[:, None], (Nz, m.Ng)).copy()
+    zero = np.zeros((Nz, m.Ng))
+    e = sch.energy_terms(phi, (zero, zero, zero), (zero, zero, zero))
+    area = 2.0 * 0.5
+    grad = 0.5 * par.lam * a * a * (2 * math.pi / Lz) ** 2 * (Lz / 2.0) * area
+    bulk = par.lam / (4 * par.eta ** 2) * area * Lz * (3 * a ** 4 / 8 - a * a + 1)
+    assert abs(e["mixing"] - (grad + bulk)) < 1e-11 * (grad + bulk), (e, grad, bulk)
+    assert abs(e["wall"]) < 1e-14     # theta_s = 90 degrees
+
+
+def test_equilibrium_marching_decreases_energy_and_stops_at_tolerance():
+    """Equilibrium system (u = 0, no sources): r_m = max |phi^{m+1} - phi^m| reaches the
+    tolerance; the total energy of eq. (14) does not increase over the march (gradient-flow
+    structure of the phase-field equation with the electric term) and the mass stays."""
+    par = Params(rho1=1, rho2=2, mu1=0.01, mu2=0.02, eps1=2.0, eps2=8.0, lam=0.01, eta=0.05,
+                 gamma1=1.0, theta_s_deg=70.0, dt=1e-3)
+    xb = np.linspace(0.0, 1.0, 3)
+    m = Mesh2D(xb, xb, 5, periodic_x=True)
+    bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, pot_sides=(BOTTOM,))
+    sch = Scheme(m, par, bc)
+    from synth import drop_field
+    phi0 = drop_field(m.X.ravel(), m.Y.ravel(), (0.5, 0.0), 0.3, par.eta)
+    sch.set_state(phi0)
+    vd = np.zeros(m.Ng)
+    src = dict(Vd=vd)
+    sch.init_potential(src)
+    e0, m0 = sch.energy()["total"], sch.mass()
+    energies = [e0]
+    steps, hist = 0, []
+    for chunk in range(40):
+        n, h = sch.march_to_equilibrium(src, 1e-6, 25)
+        steps += n
+        hist += h
+        energies.append(sch.energy()["total"])
+        if h[-1] <= 1e-6:
+            break
+    assert hist[-1] <= 1e-6 and all(r > 1e-6 for r in hist[:-1]), (steps, hist[-3:])
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(energies, energies[1:])), energies
+    assert energies[-1] < energies[0]
+    assert abs(sch.mass() - m0) < 1e-12 * abs(m0)
