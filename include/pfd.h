@@ -147,6 +147,21 @@ typedef struct {
   long steps;            /* steps taken since the last pfd_set_field             */
 } pfd_diag;
 
+/* Diagnostics of one instance (a 2D batch member, or the whole 3D field):
+ * the mass int_h phi (conserved by eq. 16), and the discrete total energy of
+ * eq. (14) term by term on the GLL quadrature: kinetic int 1/2 rho(phi)|u|^2;
+ * mixing int F(phi, grad phi) of eq. (double_well) with the gradient part from
+ * the assembled stiffness (plus (d_z phi)^2 in 3D); electric int 1/2 eps(phi)|E|^2
+ * (D = eps E); wall int Theta(phi) over the wall sides, eq. (theta_def), with
+ * gamma = sigma = 2 sqrt(2) lambda/(3 eta) and its constant term left out.
+ * 3D sums include the z weight lz/nz. */
+typedef struct {
+  double mass;
+  double kinetic, mixing, electric, wall, total;
+  double phi_max_abs;    /* max |phi| over the instance                          */
+  int nonfinite;         /* 1 if phi, |u|^2 or |E|^2 is not finite somewhere     */
+} pfd_stats;
+
 /* Human-readable name of a status code.  Never NULL. */
 const char* pfd_status_string(pfd_status s);
 
@@ -181,6 +196,20 @@ pfd_status pfd_get_coords(const pfd_ctx* ctx, double* x, double* y, double* z);
 
 /* Derived constants and diagnostics. */
 pfd_status pfd_get_diag(pfd_ctx* ctx, pfd_diag* d);
+
+/* Mass and energy of the current state (see pfd_stats) for every instance:
+ * out holds nbatch entries in 2D, one in 3D (host memory).  Uses E from the
+ * last step or pfd_init_potential.  Stream-ordered, then synchronises. */
+pfd_status pfd_get_stats(pfd_ctx* ctx, pfd_stats* out);
+
+/* March the equilibrium system (eq. 16 with u = 0: potential, psi and phi
+ * stages only) until r_m = max |phi^{m+1} - phi^m| over every node and
+ * instance is <= tol, checked after each step, or max_steps steps.  *steps
+ * (may be NULL) receives the steps taken, *residual (may be NULL) the last
+ * r_m.  PFD_ENOCONV if max_steps is reached, PFD_ENONFINITE (and the context
+ * fails) on a non-finite state.  Synchronises once per step. */
+pfd_status pfd_march_to_equilibrium(pfd_ctx* ctx, double tol, long max_steps, long* steps,
+                                    double* residual);
 
 /* Copy a field in or out.  level 0 = time level n, -1 = level n-1 (u, P, phi,
  * V, psi have two levels; E only level 0).  src/dst hold planes*Ny*Nx doubles,

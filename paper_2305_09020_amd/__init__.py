@@ -60,6 +60,12 @@ class Diag(ctypes.Structure):
                 ("nonfinite", ctypes.c_int), ("steps", ctypes.c_long)]
 
 
+class Stats(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("kinetic", ctypes.c_double), ("mixing", ctypes.c_double),
+                ("electric", ctypes.c_double), ("wall", ctypes.c_double), ("total", ctypes.c_double),
+                ("phi_max_abs", ctypes.c_double), ("nonfinite", ctypes.c_int)]
+
+
 _vp = ctypes.c_void_p
 _sig = {
     "pfd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -72,6 +78,10 @@ _sig = {
                                     ctypes.POINTER(ctypes.c_int)]),
     "pfd_get_coords": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "pfd_get_diag": (ctypes.c_int, [_vp, ctypes.POINTER(Diag)]),
+    "pfd_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Stats)]),
+    "pfd_march_to_equilibrium": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_long,
+                                                ctypes.POINTER(ctypes.c_long),
+                                                ctypes.POINTER(ctypes.c_double)]),
     "pfd_set_field": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int]),
     "pfd_get_field": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int]),
     "pfd_set_source": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
@@ -154,6 +164,7 @@ class Context:
         nx, ny, npl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(_lib.pfd_get_dims(h, ctypes.byref(nx), ctypes.byref(ny), ctypes.byref(npl)), h)
         self.Nx, self.Ny, self.planes = nx.value, ny.value, npl.value
+        self.planes_are_z = problem.mesh.nz > 0
         self.shape = (self.planes, self.Ny, self.Nx)
 
     def close(self):
@@ -245,6 +256,23 @@ class Context:
         us = ctypes.c_double(0)
         _check(_lib.pfd_profile_replay(self.h, k, int(reps), ctypes.byref(us)), self.h)
         return us.value
+
+    def stats(self):
+        """List (one per instance) of dicts: mass, kinetic, mixing, electric, wall, total,
+        phi_max_abs, nonfinite."""
+        n = 1 if self.planes_are_z else self.planes
+        arr = (Stats * n)()
+        _check(_lib.pfd_get_stats(self.h, arr), self.h)
+        return [{k: getattr(a, k) for k, _ in Stats._fields_} for a in arr]
+
+    def march_to_equilibrium(self, tol, max_steps):
+        """Equilibrium steps until max|phi^{m+1} - phi^m| <= tol; returns (steps, r_m).
+        Raises PfdError (ENOCONV) if max_steps is reached."""
+        n = ctypes.c_long(0)
+        r = ctypes.c_double(0.0)
+        _check(_lib.pfd_march_to_equilibrium(self.h, float(tol), int(max_steps), ctypes.byref(n),
+                                             ctypes.byref(r)), self.h)
+        return n.value, r.value
 
     def diag(self):
         d = Diag()

@@ -112,6 +112,7 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   }
   dbl += 3 * (size_t)Pg;                 // right sides
   dbl += 9 * (size_t)Pg;                 // r (3), U, Q2, tmp, tmp2, zero, Ybuf
+  dbl += (size_t)L->planes * PFD_STAT_NB * 8;  // diagnostics partials
   if (p->bc.n_electrodes > 0) dbl += (size_t)L->planes * (L->Nx * (size_t)L->Nx + L->Nx) + 4 * (size_t)L->Nx;
   dbl += 7 * (size_t)L->Ng;              // boundary masses, mass
   const int NN = std::max(L->Nx, L->Ny);
@@ -284,6 +285,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   c->d_status = (int*)carve(c, 64);
   c->d_norms = D(2 * c->planes + 2);
   c->d_red = D(2 * 64);
+  c->d_stats = D((long)c->planes * PFD_STAT_NB * 8);
   c->d_part = D(32 * (long)c->planes);
   c->d_beta2 = D(c->planes); c->d_betad = D(c->planes);
   for (int f = 0; f < 5; ++f) c->fam[f].dshift = D(c->planes);
@@ -603,6 +605,58 @@ extern "C" pfd_status pfd_step_async(pfd_ctx* c, int nsteps, int equilibrium) {
   if (c->failed) { c->err = "context failed earlier; set the fields again"; return PFD_ESTATE; }
   for (int i = 0; i < nsteps; ++i) HIPCHK(c->is3d ? step_once_3d(c, equilibrium) : step_once(c, equilibrium));
   c->steps += nsteps;
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_get_stats(pfd_ctx* c, pfd_stats* out) {
+  if (!c || !out) return PFD_EINVAL;
+  const int ninst = c->is3d ? 1 : c->planes;
+  std::vector<double> h((size_t)ninst * 8);
+  HIPCHK(stats(c, h.data()));
+  for (int i = 0; i < ninst; ++i) {
+    const double* o = &h[(size_t)i * 8];
+    pfd_stats& s = out[i];
+    s.mass = o[0];
+    s.kinetic = o[1];
+    s.mixing = o[2];
+    s.electric = o[3];
+    s.wall = o[4];
+    s.total = o[5];
+    s.phi_max_abs = o[6];
+    s.nonfinite = o[7] > 0.0 ? 1 : 0;
+  }
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_march_to_equilibrium(pfd_ctx* c, double tol, long max_steps, long* steps,
+                                               double* residual) {
+  if (!c || !(tol >= 0.0) || max_steps < 1) return PFD_EINVAL;
+  if (c->failed) { c->err = "context failed earlier; set the fields again"; return PFD_ESTATE; }
+  long n = 0;
+  double r = 0.0;
+  bool conv = false;
+  while (n < max_steps) {
+    HIPCHK(c->is3d ? step_once_3d(c, 1) : step_once(c, 1));
+    ++n;
+    ++c->steps;
+    double h[2];
+    HIPCHK(max_abs_diff(c, c->fld[F_PHI][c->cur], c->fld[F_PHI][1 - c->cur], h));
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    r = h[0];
+    if ((st & 1) || !std::isfinite(r)) {
+      c->failed = 1;
+      c->err = "non-finite value in the state";
+      if (steps) *steps = n;
+      if (residual) *residual = r;
+      return PFD_ENONFINITE;
+    }
+    if (r <= tol) { conv = true; break; }
+  }
+  if (steps) *steps = n;
+  if (residual) *residual = r;
+  if (!conv) { c->err = "equilibrium tolerance not reached"; return PFD_ENOCONV; }
   return PFD_OK;
 }
 

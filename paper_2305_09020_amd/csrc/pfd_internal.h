@@ -12,6 +12,7 @@
 
 #define PFD_KMAX 16
 #define PFD_NMAX 320  // max nodes per direction handled by the solve kernels
+#define PFD_STAT_NB 32  // blocks per instance of the diagnostics reduction
 
 namespace pfd {
 
@@ -116,6 +117,7 @@ struct pfd_ctx {
   double *bm_side[4] = {}, *bm_open = nullptr, *bm_wall = nullptr, *Mdiag = nullptr;
   double *d_hx = nullptr, *d_hy = nullptr, *d_w = nullptr, *d_D = nullptr;
   int* d_status = nullptr;                 // [0] nonfinite flag
+  double* d_stats = nullptr;               // block partials of the diagnostics
   double* d_norms = nullptr;               // per plane: ||r||^2, ||b||^2 (diagnostics)
   double* d_red = nullptr;                 // reduction scratch (planes)
   long steps = 0;
@@ -158,6 +160,9 @@ hipError_t step_once(pfd_ctx* c, int equilibrium);
 hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout);
 hipError_t update_E(pfd_ctx* c);
 hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* out_host2);
+// per-instance diagnostics: out[inst*8 + q], q = mass, kinetic, mixing, electric, wall, total,
+// max|phi|, non-finite count (host array of ninst*8; synchronises)
+hipError_t stats(pfd_ctx* c, double* out);
 hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us);
 hipError_t step_once_3d(pfd_ctx* c, int equilibrium);
 hipError_t potential_iteration_3d(pfd_ctx* c, const double* Vin, double* Vout);

@@ -813,15 +813,16 @@ static void plane_fix(pfd_ctx* c, int fam, double* f, int mode) {
 }
 
 static void residual(pfd_ctx* c, int fam, const double* b, const double* x, double* r, int apply_only,
-                     double* norms) {
+                     double* norms, const double* shift = nullptr) {
   Family& F = c->fam[fam];
+  const double* sh = shift ? shift : F.dshift;
   Dir1D& dx = c->dirs[F.ix];
   Dir1D& dy = c->dirs[F.iy];
   const long tot = (long)c->planes * c->Ng;
 #define RES_CASE(KK)                                                                                      \
   case KK:                                                                                                \
     LAUNCH(PFD_PROF_RESID, k_residual<KK>, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->planes,   \
-                       (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, F.dshift, b, x, r, \
+                       (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, r,       \
                        apply_only, norms, c->lift[fam].ebot);                                             \
     break;
   switch (c->K) {
@@ -1166,6 +1167,94 @@ hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* ou
     out_host2[1] = fmax(out_host2[1], h[2 * i + 1]);
   }
   return e;
+}
+
+// ------------------------------------------------------------------ diagnostics
+// Block partial sums per instance (blockIdx.y) of the quadrature sums behind eq. (14) and the
+// mass: q0 int phi, q1 int 1/2 rho |u|^2, q2 phi.(K phi) + int (d_z phi)^2, q3 int (phi^2-1)^2,
+// q4 int 1/2 eps |E|^2, q5 wall int phi (phi^2 - 3), q6 max|phi|, q7 non-finite count.
+// K phi is the x-y stiffness applied per plane (no mass shift).
+__global__ void k_stats(long Ng, long per_inst, Par P, const double* __restrict__ Mdiag,
+                        const double* __restrict__ bw, const double* __restrict__ phi,
+                        const double* __restrict__ ux, const double* __restrict__ uy,
+                        const double* __restrict__ uz, const double* __restrict__ Ex,
+                        const double* __restrict__ Ey, const double* __restrict__ Ez,
+                        const double* __restrict__ Kphi, const double* __restrict__ dzphi,
+                        double* __restrict__ part) {
+  __shared__ double red[8][WG];
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const long base = (long)blockIdx.y * per_inst;
+  for (long i = (long)blockIdx.x * WG + threadIdx.x; i < per_inst; i += (long)gridDim.x * WG) {
+    const long id = base + i;
+    const long node = id % Ng;
+    const double w = Mdiag[node], p = phi[id];
+    double u2 = ux[id] * ux[id] + uy[id] * uy[id];
+    double e2 = Ex[id] * Ex[id] + Ey[id] * Ey[id];
+    if (uz) u2 += uz[id] * uz[id];
+    if (Ez) e2 += Ez[id] * Ez[id];
+    const double rho = 0.5 * (P.rho1 + P.rho2) + 0.5 * (P.rho1 - P.rho2) * p;
+    const double dw = p * p - 1.0;
+    s[0] += w * p;
+    s[1] += 0.5 * w * rho * u2;
+    s[2] += p * Kphi[id];
+    if (dzphi) s[2] += w * dzphi[id] * dzphi[id];
+    s[3] += w * dw * dw;
+    s[4] += 0.5 * w * eps_of(P, p) * e2;
+    s[5] += bw[node] * p * (p * p - 3.0);
+    s[6] = fmax(s[6], fabs(p));
+    if (!isfinite(p) || !isfinite(u2) || !isfinite(e2)) s[7] += 1.0;
+  }
+  for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = s[q];
+  __syncthreads();
+  for (int o = WG / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int q = 0; q < 8; ++q)
+        red[q][threadIdx.x] = (q == 6) ? fmax(red[q][threadIdx.x], red[q][threadIdx.x + o])
+                                       : red[q][threadIdx.x] + red[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) part[((long)blockIdx.y * gridDim.x + blockIdx.x) * 8 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+hipError_t stats(pfd_ctx* c, double* out) {
+  const long tot = (long)c->planes * c->Ng;
+  const int ninst = c->is3d ? 1 : c->planes;
+  const long per = tot / ninst;
+  const int nb = PFD_STAT_NB;
+  const int cu = c->cur;
+  const double* phi = c->fld[F_PHI][cu];
+  double* Kphi = c->r;
+  double* dzphi = c->is3d ? c->r + tot : nullptr;
+  residual(c, PFD_FAM_PSI, nullptr, phi, Kphi, 1, nullptr, c->zero_buf);
+  if (c->is3d) ztrans(c, c->Dz, phi, dzphi, nullptr, 1.0, 0.0);
+  LAUNCH(PFD_PROF_OTHER, k_stats, dim3(nb, ninst), dim3(WG), 0, c->stream, c->Ng, per, c->par, c->Mdiag,
+         c->bm_wall, phi, c->fld[F_UX][cu], c->fld[F_UY][cu], c->is3d ? c->fld[F_UZ][cu] : nullptr,
+         c->fld[F_EX][0], c->fld[F_EY][0], c->is3d ? c->fld[F_EZ][0] : nullptr, Kphi, dzphi, c->d_stats);
+  std::vector<double> h((size_t)ninst * nb * 8);
+  hipError_t e = hipMemcpyAsync(h.data(), c->d_stats, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream);
+  if (!e) e = hipStreamSynchronize(c->stream);
+  if (e) return e;
+  const Par& P = c->par;
+  const double wz = c->is3d ? c->prob.mesh.lz / c->planes : 1.0;
+  const double sigma = 2.0 * std::sqrt(2.0) * P.lam / (3.0 * P.eta);
+  for (int i = 0; i < ninst; ++i) {
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < nb; ++b)
+      for (int q = 0; q < 8; ++q) {
+        const double v = h[((size_t)i * nb + b) * 8 + q];
+        s[q] = (q == 6) ? std::fmax(s[q], v) : s[q] + v;
+      }
+    double* o = out + (size_t)i * 8;
+    o[0] = s[0] * wz;
+    o[1] = s[1] * wz;
+    o[2] = (0.5 * P.lam * s[2] + P.lam / (4.0 * P.eta * P.eta) * s[3]) * wz;
+    o[3] = s[4] * wz;
+    o[4] = sigma * P.cos_theta * 0.25 * s[5] * wz;
+    o[5] = o[1] + o[2] + o[3] + o[4];
+    o[6] = s[6];
+    o[7] = s[7];
+  }
+  return hipSuccess;
 }
 
 // ============================================================ 3D: Fourier in z (Algorithm 2)
