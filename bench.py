@@ -210,6 +210,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--refine-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch the step kernels one by one instead of replaying a hipGraph")
     ap.add_argument("--only", choices=["refined", "fp64", "both"], default="both")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (reference for the "
@@ -238,6 +240,7 @@ def main():
         if a.only not in (name, "both"):
             continue
         ctx, its = make_context(prec, a.refine_iters, a.workload)
+        ctx.set_graph(not a.no_graph)
         t = time_steps(ctx, a.steps, a.warmup)
         dof = ctx.planes * ctx.Nx * ctx.Ny
         res[name] = dict(t=t, dof=dof, value=dof * a.steps / t, ctx=ctx,
@@ -262,13 +265,13 @@ def main():
         "config": ({"workload": "2D sessile drop, 20x20 elements order 8 (25,921 points), "
                                 "rho 1:1000, mu 1:100, eps 1:40, V_top {0,0.5,1,2} as 4 instances, "
                                 "dt 5e-5, closed box; %s path" % main_name,
-                    "instances": len(VTOP), "dof_per_step": r["dof"],
+                    "instances": len(VTOP), "dof_per_step": r["dof"], "graph": not a.no_graph,
                     "refine_iters": a.refine_iters if main_name == "refined" else 0}
                    if a.workload == "c2" else
                    {"workload": "3D drop, 16x16 elements order 8 x 128 Fourier planes (Lz = 2, "
                                 "2,130,048 points), perturbed sphere r = 0.3, rho 1:10, mu 1:2, "
                                 "eps 1:10, dt 1e-4, walls; %s path" % main_name,
-                    "instances": 1, "dof_per_step": r["dof"],
+                    "instances": 1, "dof_per_step": r["dof"], "graph": not a.no_graph,
                     "refine_iters": a.refine_iters if main_name == "refined" else 0}),
     }
     out["roofline"] = r["roofline"]

@@ -197,6 +197,14 @@ pfd_status pfd_get_coords(const pfd_ctx* ctx, double* x, double* y, double* z);
 /* Derived constants and diagnostics. */
 pfd_status pfd_get_diag(pfd_ctx* ctx, pfd_diag* d);
 
+/* on != 0: pfd_step / pfd_step_async / pfd_march_to_equilibrium replay a
+ * hipGraph of one whole step instead of launching its kernels one by one
+ * (captured on first use on a stream the context owns, one graph per parity of
+ * the time level and per step kind; the same kernels in the same order, so the
+ * results are identical).  Graphs are bypassed while profiling is on.  on == 0
+ * synchronises and frees the graphs. */
+pfd_status pfd_set_graph(pfd_ctx* ctx, int on);
+
 /* Mass and energy of the current state (see pfd_stats) for every instance:
  * out holds nbatch entries in 2D, one in 3D (host memory).  Uses E from the
  * last step or pfd_init_potential.  Stream-ordered, then synchronises. */

@@ -79,6 +79,7 @@ _sig = {
     "pfd_get_coords": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "pfd_get_diag": (ctypes.c_int, [_vp, ctypes.POINTER(Diag)]),
     "pfd_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Stats)]),
+    "pfd_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pfd_march_to_equilibrium": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_long,
                                                 ctypes.POINTER(ctypes.c_long),
                                                 ctypes.POINTER(ctypes.c_double)]),
@@ -256,6 +257,10 @@ class Context:
         us = ctypes.c_double(0)
         _check(_lib.pfd_profile_replay(self.h, k, int(reps), ctypes.byref(us)), self.h)
         return us.value
+
+    def set_graph(self, on=True):
+        """Replay a captured hipGraph per step (identical results, fewer launches)."""
+        _check(_lib.pfd_set_graph(self.h, int(bool(on))), self.h)
 
     def stats(self):
         """List (one per instance) of dicts: mass, kinetic, mixing, electric, wall, total,

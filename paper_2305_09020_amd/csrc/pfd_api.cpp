@@ -472,9 +472,13 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   return PFD_OK;
 }
 
+static void drop_graphs(pfd_ctx* c);
+
 extern "C" void pfd_destroy(pfd_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto& e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
@@ -600,10 +604,58 @@ extern "C" pfd_status pfd_init_potential(pfd_ctx* c, double tol, int max_iter, i
   return PFD_OK;
 }
 
+static void drop_graphs(pfd_ctx* c) {
+  for (auto& row : c->gexec)
+    for (auto& g : row)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+}
+
+// one step: eager launches, or the replay of a captured graph of the same launches
+static hipError_t one_step(pfd_ctx* c, int eq) {
+  if (!c->use_graph || c->prof_on || c->check_residual)
+    return c->is3d ? step_once_3d(c, eq) : step_once(c, eq);
+  if (c->is3d) refresh_spectral_sources(c);  // host-decided transforms stay outside the graph
+  const int cur = c->cur;
+  hipGraphExec_t& ex = c->gexec[cur][eq ? 1 : 0];
+  if (!ex) {
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e) { c->stream = user; return e; }
+    hipError_t es = c->is3d ? step_once_3d(c, eq) : step_once(c, eq);
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(c->cap_stream, &gr);
+    c->stream = user;
+    c->cur = cur;
+    if (!e) e = es;
+    if (!e) e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    if (gr) (void)hipGraphDestroy(gr);
+    if (e) { ex = nullptr; return e; }
+  }
+  hipError_t e = hipGraphLaunch(ex, c->stream);
+  if (e) return e;
+  c->cur = 1 - cur;
+  return hipSuccess;
+}
+
+extern "C" pfd_status pfd_set_graph(pfd_ctx* c, int on) {
+  if (!c) return PFD_EINVAL;
+  if (on && !c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  if (!on) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+  }
+  c->use_graph = on ? 1 : 0;
+  return PFD_OK;
+}
+
 extern "C" pfd_status pfd_step_async(pfd_ctx* c, int nsteps, int equilibrium) {
   if (!c || nsteps < 0) return PFD_EINVAL;
   if (c->failed) { c->err = "context failed earlier; set the fields again"; return PFD_ESTATE; }
-  for (int i = 0; i < nsteps; ++i) HIPCHK(c->is3d ? step_once_3d(c, equilibrium) : step_once(c, equilibrium));
+  for (int i = 0; i < nsteps; ++i) HIPCHK(one_step(c, equilibrium));
   c->steps += nsteps;
   return PFD_OK;
 }
@@ -636,7 +688,7 @@ extern "C" pfd_status pfd_march_to_equilibrium(pfd_ctx* c, double tol, long max_
   double r = 0.0;
   bool conv = false;
   while (n < max_steps) {
-    HIPCHK(c->is3d ? step_once_3d(c, 1) : step_once(c, 1));
+    HIPCHK(one_step(c, 1));
     ++n;
     ++c->steps;
     double h[2];

@@ -123,6 +123,10 @@ struct pfd_ctx {
   long steps = 0;
   int failed = 0;
   int check_residual = 0;
+  // hipGraph replay of whole steps: one executable per (parity of the current level, step kind)
+  int use_graph = 0;
+  hipStream_t cap_stream = nullptr;        // capture stream (the caller's may be the null stream)
+  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   double last_residual = 0.0;
   // per-kernel-class timing (pfd_profile_enable / pfd_profile_read)
   int prof_on = 0;
@@ -165,6 +169,7 @@ hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* ou
 hipError_t stats(pfd_ctx* c, double* out);
 hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us);
 hipError_t step_once_3d(pfd_ctx* c, int equilibrium);
+void refresh_spectral_sources(pfd_ctx* c);
 hipError_t potential_iteration_3d(pfd_ctx* c, const double* Vin, double* Vout);
 hipError_t to_spectral(pfd_ctx* c, const double* phys, double* spec);
 }  // namespace pfd

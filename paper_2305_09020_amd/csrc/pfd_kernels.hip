@@ -1101,9 +1101,7 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
                      S[PFD_SRC_G2], c->U, H(F_PHI, 0), H(F_PHI, -1), c->b[0], c->r, c->fld[F_PHI][nw]);
   solve(c, PFD_FAM_PHI, c->b[0], c->fld[F_PHI][nw], 1, 0, r0);
   if (equilibrium) {
-    hipMemsetAsync(c->fld[F_UX][nw], 0, sizeof(double) * tot, st);
-    hipMemsetAsync(c->fld[F_UY][nw], 0, sizeof(double) * tot, st);
-    hipMemsetAsync(c->fld[F_P][nw], 0, sizeof(double) * tot, st);
+    for (int f : {F_UX, F_UY, F_P}) LAUNCH(PFD_PROF_OTHER, k_fill, ng, nb, 0, st, tot, c->fld[f][nw], 0.0);
   } else {
     // ---- momentum terms, P (eq. 58)
     // phi^{n-1} now holds phi^{n+1}: the momentum kernel takes Q2 (built from phi*) from the psi stage
@@ -1363,7 +1361,7 @@ static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, c
 }
 
 // spectral copies of the Dirichlet sources that changed since the last step (reading R-dir3d)
-static void refresh_spectral_sources(pfd_ctx* c) {
+void refresh_spectral_sources(pfd_ctx* c) {
   const int ids[5] = {PFD_SRC_VD, PFD_SRC_F2, PFD_SRC_WX, PFD_SRC_WY, PFD_SRC_WZ};
   for (int s : ids)
     if (c->src_dirty[s]) {

@@ -1,0 +1,88 @@
+"""hipGraph replay of whole steps: the same kernels in the same order as the eager launches,
+so every replay must reproduce the eager state exactly (checked after each replay, with eager
+work and synchronisations in between)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.sem import Mesh2D, BOTTOM, TOP, LEFT, RIGHT
+from oracle.scheme import BCs, WALL, OPEN
+from cases import c1_params
+from gpu_cases import gpu_context
+from synth import drop_field
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _pair(nz, precision, electrodes=()):
+    xb = np.linspace(0.0, 1.0, 4)
+    if nz:
+        m = Mesh2D(xb, xb, 6, periodic_x=True)
+        bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, pot_sides=() if electrodes else (BOTTOM,),
+                 electrodes=list(electrodes))
+    else:
+        m = Mesh2D(xb, xb, 6)
+        bc = BCs(side={BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}, pot_sides=(BOTTOM, TOP))
+    par = c1_params()
+    ctxs = [gpu_context(m, par, bc, precision=precision, refine_iters=2, nz=nz, lz=1.5 if nz else 0.0)
+            for _ in range(2)]
+    ctxs[1].set_graph(True)
+    planes = nz if nz else 1
+    X, Y = m.X.ravel()[None, :], m.Y.ravel()[None, :]
+    Z = (np.arange(planes) * 1.5 / planes)[:, None] if nz else 0.0 * X
+    phi = np.tanh((np.sqrt((X - 0.5) ** 2 + (Y - 0.3) ** 2 + 0.2 * np.sin(2 * math.pi * Z / 1.5) ** 2)
+                   - 0.25) / (math.sqrt(2) * par.eta))
+    vd = np.where(np.isclose(Y, 1.0) | np.isclose(Y, 0.0), np.where(Y > 0.5, 1.0, 0.0), 0.0)
+    vd = np.broadcast_to(vd + 0.0 * phi, phi.shape).copy()
+    if electrodes:
+        vd = np.where(np.isclose(Y, 0.0) & (X >= 1.0 / 3.0 - 1e-12) & (X <= 2.0 / 3.0 + 1e-12), 1.5, 0.0)
+        vd = np.broadcast_to(vd + 0.0 * phi, phi.shape).copy()
+    shape = (planes, m.Ny, m.Nx)
+    for c in ctxs:
+        c.set_field("phi", phi.reshape(shape))
+        c.set_sources({"Vd": vd.reshape(shape)})
+        c.init_potential(tol=1e-12, max_iter=2000)
+    return ctxs
+
+
+FIELDS = ("phi", "psi", "V", "P", "ux", "uy", "Ex", "Ey")
+
+
+@pytest.mark.parametrize("nz,precision,equilibrium", [
+    (0, 0, False), (0, 1, False), (0, 1, True), (8, 0, False), (8, 1, False), (8, 1, True)])
+def test_graph_replays_equal_eager_steps(nz, precision, equilibrium):
+    torch = _torch()
+    eager, graph = _pair(nz, precision)
+    for n in range(5):
+        eager.step(1, equilibrium=equilibrium)
+        graph.step(1, equilibrium=equilibrium)
+        # eager work on the stream and a synchronisation between replays
+        junk = torch.randn(1000, device="cuda").sum().item()
+        assert math.isfinite(junk)
+        for k in FIELDS + (("uz", "Ez") if nz else ()):
+            a, b = eager.get_field(k), graph.get_field(k)
+            assert np.array_equal(a, b), (n, k, np.max(np.abs(a - b)))
+        se, sg = eager.stats(), graph.stats()
+        assert se == sg
+
+
+def test_graph_march_with_electrodes_equals_eager():
+    """Equilibrium marching through graph replays (3D, partial electrode) ends on the same
+    step count, residual and state as the eager march."""
+    _torch()
+    eager, graph = _pair(8, 1, electrodes=[(1.0 / 3.0, 2.0 / 3.0)])
+    res = []
+    for c in (eager, graph):
+        try:
+            res.append(c.march_to_equilibrium(1e-3, 40))
+        except Exception as e:       # ENOCONV is acceptable here; both must agree
+            res.append(str(e))
+    assert res[0] == res[1]
+    assert np.array_equal(eager.get_field("phi"), graph.get_field("phi"))
