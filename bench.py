@@ -110,8 +110,11 @@ def roofline(ctx, steps):
     avg = ctx.profile_replay(dom, 200) * 1e-6     # back-to-back replay, no per-launch events
     avg_bracketed = ms / 1e3 / n
     P, Nx, Ny = ctx.planes, ctx.Nx, ctx.Ny
+    variant, tune_us = ctx.solver_variant()
     if dom.startswith("gemm"):
-        per = float(Ny * Nx * (Nx + Ny) * P)
+        # four-pass variant: one GEMM pass per launch (mean 2*Ny*Nx*(Nx+Ny)/2 flops per plane);
+        # fused variant: two passes per launch
+        per = float(Ny * Nx * (Nx + Ny) * P) * (2.0 if variant == 1 else 1.0)
         achieved = per / avg / 1e12
         peak = PEAK[dom][0] / 1e12
     else:
@@ -122,7 +125,9 @@ def roofline(ctx, steps):
     return {"bound": PEAK[dom][2], "achieved": achieved, "peak": peak, "unit": PEAK[dom][1],
             "frac": achieved / peak, "traffic": traffic(dom, per), "kernel": dom,
             "avg_launch_us": avg * 1e6, "avg_launch_us_event_bracketed": avg_bracketed * 1e6,
-            "launches_per_step": n / steps, "per_launch": per, "class_time_share": share}
+            "launches_per_step": n / steps, "per_launch": per, "class_time_share": share,
+            "solver_variant": variant, "autotune_us_per_correction": tune_us,
+            "gemm_tile_config_per_site": ctx.gemm_config()[0]}
 
 
 def traffic(dom, per):

@@ -197,6 +197,42 @@ pfd_status pfd_get_coords(const pfd_ctx* ctx, double* x, double* y, double* z);
 /* Derived constants and diagnostics. */
 pfd_status pfd_get_diag(pfd_ctx* ctx, pfd_diag* d);
 
+/* Kernels of the fast-diagonalisation solves: 0 = four batched GEMM passes
+ * (16x16 MFMA tiles, split-K over four waves), 1 = two fused strip kernels
+ * (the strip intermediate stays in LDS).  pfd_create times one velocity
+ * correction with each in the context's solve precision and keeps the faster;
+ * variant -1 re-runs that autotuning.  Both compute the same correction up to
+ * rounding order.  Synchronises; drops captured graphs. */
+pfd_status pfd_set_solver_variant(pfd_ctx* ctx, int variant);
+/* Current variant and the autotuner's timings (us[2], microseconds per
+ * correction of variants 0 and 1; either may be NULL). */
+pfd_status pfd_get_solver_variant(const pfd_ctx* ctx, int* variant, double* us);
+
+/* Kernel of the FP64 residual b - (K + cM) x of the refinement: 0 = one
+ * thread per node reading its 2(2K+1) band neighbours through the caches,
+ * 1 = rows staged in LDS tiles (used when Nx <= 256 and the tile fits).
+ * pfd_create times both and keeps the faster.  The same sums in the same
+ * order (results agree to rounding).  Synchronises; drops captured graphs. */
+pfd_status pfd_set_residual_variant(pfd_ctx* ctx, int variant);
+pfd_status pfd_get_residual_variant(const pfd_ctx* ctx, int* variant, double* us);
+
+/* Kernel configuration of the batched GEMMs per call site (0..3: the four
+ * fast-diagonalisation passes, 4: the z transform; site -1: all).  cfg 0..7:
+ * register tiles {TM, TN, SK} = {1,1,4} {2,2,1} {2,2,2} {3,3,1} {3,3,2}
+ * {2,4,1} {4,2,1} {2,2,4}, a wave computing 16TM x 16TN of the output with SK
+ * waves splitting the contraction; cfg 8..15: the shared small matrix staged in
+ * LDS with the plane operand streamed, {W, SK} = {1,1} {2,1} {3,1} {1,2}
+ * {2,2} {3,2} {1,4} {2,4} (W 16-wide tiles per wave along the small
+ * dimension).  pfd_create times every configuration that applies on the real
+ * shapes and keeps each site's fastest (the autotuner); this overrides it (a
+ * configuration that does not apply to a site falls back to cfg 0).
+ * Synchronises; drops captured graphs. */
+pfd_status pfd_set_gemm_config(pfd_ctx* ctx, int site, int cfg);
+/* Chosen configuration per site (cfg[5]) and the autotuner's timings
+ * (us[5*16], microseconds per launch; 0 where not tuned or not applicable).
+ * Either may be NULL. */
+pfd_status pfd_get_gemm_config(const pfd_ctx* ctx, int* cfg, double* us);
+
 /* on != 0: pfd_step / pfd_step_async / pfd_march_to_equilibrium replay a
  * hipGraph of one whole step instead of launching its kernels one by one
  * (captured on first use on a stream the context owns, one graph per parity of

@@ -80,6 +80,14 @@ _sig = {
     "pfd_get_diag": (ctypes.c_int, [_vp, ctypes.POINTER(Diag)]),
     "pfd_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Stats)]),
     "pfd_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "pfd_set_solver_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "pfd_set_gemm_config": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "pfd_set_residual_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "pfd_get_residual_variant": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(ctypes.c_double)]),
+    "pfd_get_gemm_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
+    "pfd_get_solver_variant": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_double)]),
     "pfd_march_to_equilibrium": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_long,
                                                 ctypes.POINTER(ctypes.c_long),
                                                 ctypes.POINTER(ctypes.c_double)]),
@@ -257,6 +265,39 @@ class Context:
         us = ctypes.c_double(0)
         _check(_lib.pfd_profile_replay(self.h, k, int(reps), ctypes.byref(us)), self.h)
         return us.value
+
+    def set_solver_variant(self, variant):
+        """0: four GEMM passes, 1: fused strip kernels, -1: autotune again."""
+        _check(_lib.pfd_set_solver_variant(self.h, int(variant)), self.h)
+
+    def set_residual_variant(self, variant):
+        """0: per-node residual kernel, 1: LDS-tiled residual kernel."""
+        _check(_lib.pfd_set_residual_variant(self.h, int(variant)), self.h)
+
+    def residual_variant(self):
+        v = ctypes.c_int(0)
+        us = (ctypes.c_double * 2)()
+        _check(_lib.pfd_get_residual_variant(self.h, ctypes.byref(v), us), self.h)
+        return v.value, [us[0], us[1]]
+
+    def set_gemm_config(self, site, cfg):
+        """Force tile configuration cfg (0..15) at GEMM call site (0..4, -1 = all)."""
+        _check(_lib.pfd_set_gemm_config(self.h, int(site), int(cfg)), self.h)
+
+    def gemm_config(self):
+        """(chosen cfg per site [5], autotune us per (site, cfg) [5][16]; 0 = not applicable
+        or not tuned)."""
+        cfg = (ctypes.c_int * 5)()
+        us = (ctypes.c_double * 80)()
+        _check(_lib.pfd_get_gemm_config(self.h, cfg, us), self.h)
+        return list(cfg), [list(us[16 * s:16 * s + 16]) for s in range(5)]
+
+    def solver_variant(self):
+        """(variant, [us per correction of variant 0, variant 1]) from the autotuner."""
+        v = ctypes.c_int(0)
+        us = (ctypes.c_double * 2)()
+        _check(_lib.pfd_get_solver_variant(self.h, ctypes.byref(v), us), self.h)
+        return v.value, [us[0], us[1]]
 
     def set_graph(self, on=True):
         """Replay a captured hipGraph per step (identical results, fewer launches)."""

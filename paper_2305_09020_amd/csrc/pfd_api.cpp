@@ -468,6 +468,8 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     c->lift[f] = Lift{dx.dK0, dx.dKN, dy.dK0, dy.dKN, dx.dM1, dy.dM1, dx.dKb, dx.ddir, dy.ddir,
                       (f == PFD_FAM_V && c->elec.ng > 0) ? c->elec.d_ebot : nullptr};
   }
+  e = autotune(c);
+  if (e) { g_create_err = std::string("HIP error in create (autotune): ") + hipGetErrorString(e); delete c; return PFD_EHIP; }
   *out = c;
   return PFD_OK;
 }
@@ -639,6 +641,66 @@ static hipError_t one_step(pfd_ctx* c, int eq) {
   if (e) return e;
   c->cur = 1 - cur;
   return hipSuccess;
+}
+
+extern "C" pfd_status pfd_set_solver_variant(pfd_ctx* c, int variant) {
+  if (!c || variant < -1 || variant > 1) return PFD_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  if (variant < 0)
+    HIPCHK(autotune(c));
+  else
+    c->fdm_variant = variant;
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_set_gemm_config(pfd_ctx* c, int site, int cfg) {
+  if (!c || site < -1 || site >= PFD_GS_N || cfg < 0 || cfg >= PFD_GEMM_NCFG) return PFD_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  for (int s = 0; s < PFD_GS_N; ++s)
+    if (site < 0 || s == site) c->gemm_cfg[s][0] = c->gemm_cfg[s][1] = cfg;
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_get_gemm_config(const pfd_ctx* c, int* cfg, double* us) {
+  if (!c) return PFD_EINVAL;
+  const int ti = (c->prob.precision == PFD_REFINED_FP32) ? 0 : 1;
+  for (int s = 0; s < PFD_GS_N; ++s) {
+    const int t = (s == PFD_GS_Z) ? 1 : ti;
+    if (cfg) cfg[s] = c->gemm_cfg[s][t];
+    if (us)
+      for (int k = 0; k < PFD_GEMM_NCFG; ++k) us[s * PFD_GEMM_NCFG + k] = c->gemm_us[s][t][k];
+  }
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_set_residual_variant(pfd_ctx* c, int variant) {
+  if (!c || variant < 0 || variant > 1) return PFD_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  c->resid_variant = variant;
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_get_residual_variant(const pfd_ctx* c, int* variant, double* us) {
+  if (!c) return PFD_EINVAL;
+  if (variant) *variant = c->resid_variant;
+  if (us) {
+    us[0] = c->resid_us[0];
+    us[1] = c->resid_us[1];
+  }
+  return PFD_OK;
+}
+
+extern "C" pfd_status pfd_get_solver_variant(const pfd_ctx* c, int* variant, double* us) {
+  if (!c) return PFD_EINVAL;
+  if (variant) *variant = c->fdm_variant;
+  if (us) {
+    us[0] = c->fdm_us[0];
+    us[1] = c->fdm_us[1];
+  }
+  return PFD_OK;
 }
 
 extern "C" pfd_status pfd_set_graph(pfd_ctx* c, int on) {

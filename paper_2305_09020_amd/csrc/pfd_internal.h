@@ -13,6 +13,9 @@
 #define PFD_KMAX 16
 #define PFD_NMAX 320  // max nodes per direction handled by the solve kernels
 #define PFD_STAT_NB 32  // blocks per instance of the diagnostics reduction
+#define PFD_GEMM_NCFG 16  // tile configurations of the batched GEMM
+// GEMM call sites tuned separately: the four fast-diagonalisation passes and the z transform
+enum { PFD_GS_P1 = 0, PFD_GS_P2, PFD_GS_P3, PFD_GS_P4, PFD_GS_Z, PFD_GS_N };
 
 namespace pfd {
 
@@ -125,6 +128,14 @@ struct pfd_ctx {
   int check_residual = 0;
   // hipGraph replay of whole steps: one executable per (parity of the current level, step kind)
   int use_graph = 0;
+  // fast-diagonalisation kernels: 0 = four split-K GEMM passes, 1 = two fused strip kernels
+  // (chosen by timing both at create)
+  int fdm_variant = 1;
+  int resid_variant = 1;                   // residual: 0 = per-node global reads, 1 = LDS tiles
+  double resid_us[2] = {0.0, 0.0};
+  double fdm_us[2] = {0.0, 0.0};           // autotune timings (us per correction)
+  int gemm_cfg[PFD_GS_N][2] = {};          // tile configuration per (call site, FP32/FP64)
+  double gemm_us[PFD_GS_N][2][PFD_GEMM_NCFG] = {};  // autotune timings per configuration
   hipStream_t cap_stream = nullptr;        // capture stream (the caller's may be the null stream)
   hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   double last_residual = 0.0;
@@ -168,6 +179,7 @@ hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* ou
 // max|phi|, non-finite count (host array of ninst*8; synchronises)
 hipError_t stats(pfd_ctx* c, double* out);
 hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us);
+hipError_t autotune(pfd_ctx* c);
 hipError_t step_once_3d(pfd_ctx* c, int equilibrium);
 void refresh_spectral_sources(pfd_ctx* c);
 hipError_t potential_iteration_3d(pfd_ctx* c, const double* Vin, double* Vout);

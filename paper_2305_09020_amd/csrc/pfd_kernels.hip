@@ -18,6 +18,8 @@
 //    X += Sy T Sx^T, each a chain of two LDS-staged GEMMs per (plane, column
 //    block), templated on the compute type (double / float).
 #include <cmath>
+#include <functional>
+#include <type_traits>
 #include <vector>
 
 #include "pfd_internal.h"
@@ -628,6 +630,68 @@ __global__ void k_residual(int Nx, int Ny, int planes, int perx, const double* _
   }
 }
 
+// LDS-tiled variant of k_residual: a work-group takes RROWS rows of one plane; the rows
+// iy0-K .. iy0+RROWS-1+K of x are staged in LDS once (coalesced), each thread keeps the
+// 2K+1 x-band coefficients of its column in registers, and the 2(2K+1) neighbour reads of
+// every node come from LDS instead of L1/L2.  Needs Nx <= 256 (one column per thread).
+#define RROWS 16
+template <int K>
+__global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, const double* __restrict__ KxB,
+                                                      const double* __restrict__ Mx,
+                                                      const unsigned char* __restrict__ dirx,
+                                                      const double* __restrict__ KyB, const double* __restrict__ My,
+                                                      const unsigned char* __restrict__ diry,
+                                                      const double* __restrict__ shift, const double* __restrict__ bb,
+                                                      const double* __restrict__ x, double* __restrict__ r,
+                                                      int apply_only, const unsigned char* __restrict__ ebot) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* xs = reinterpret_cast<double*>(smem_raw);       // (RROWS + 2K) rows x Nx
+  const int pl = blockIdx.y, iy0 = blockIdx.x * RROWS;
+  const long Ng = (long)Nx * Ny;
+  const double* xp = x + pl * Ng;
+  const int nrows = RROWS + 2 * K;
+  for (int idx = threadIdx.x; idx < nrows * Nx; idx += 256) {
+    const int rr = idx / Nx, ix = idx - rr * Nx;
+    const int iy = iy0 - K + rr;
+    xs[idx] = (iy >= 0 && iy < Ny) ? xp[(long)iy * Nx + ix] : 0.0;
+  }
+  __syncthreads();
+  const int ix = threadIdx.x;
+  if (ix >= Nx) return;
+  double kx[2 * K + 1];
+#pragma unroll
+  for (int d = 0; d <= 2 * K; ++d) kx[d] = KxB[(long)d * Nx + ix];
+  int jx[2 * K + 1];
+#pragma unroll
+  for (int d = -K; d <= K; ++d) {
+    int j = ix + d;
+    if (perx) j = (j < 0) ? j + Nx : (j >= Nx ? j - Nx : j);
+    else j = (j < 0) ? 0 : (j >= Nx ? Nx - 1 : j);   // out-of-range band entries are zero
+    jx[d + K] = j;
+  }
+  const double mx = Mx[ix], sh = shift[pl];
+  const int rend = min(RROWS, Ny - iy0);
+  for (int rl = 0; rl < rend; ++rl) {
+    const int iy = iy0 + rl;
+    const double* row = xs + (rl + K) * Nx;
+    double ax = 0.0, ay = 0.0;
+#pragma unroll
+    for (int d = 0; d <= 2 * K; ++d) ax += kx[d] * row[jx[d]];
+#pragma unroll
+    for (int d = -K; d <= K; ++d) ay += KyB[(long)(d + K) * Ny + iy] * row[d * Nx + ix];
+    const double xv = row[ix];
+    const double my = My[iy];
+    const double Av = ax * my + mx * ay + sh * mx * my * xv;
+    const long id = pl * Ng + (long)iy * Nx + ix;
+    if (apply_only) {
+      r[id] = Av;
+    } else {
+      const bool dn = is_dir(dirx, diry, ebot, ix, iy);
+      r[id] = dn ? 0.0 : bb[id] - Av;
+    }
+  }
+}
+
 // Batched GEMM on the matrix cores for the fast-diagonalisation passes:
 //   C[p] (M x N) = A[p] (M x K) * B[p] (K x N), row-major, plane strides sA, sB (0: shared).
 // One work-group (four waves) computes one 16x16 output tile with v_mfma_{f64,f32}_16x16x4
@@ -670,7 +734,7 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA,
   // four waves split K: wave w takes the 16-wide slices w, w+4, w+8, ... of the contraction,
   // and the partial tiles are summed in LDS in a fixed order (deterministic)
   __shared__ T red[4][4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
   const int n0 = blockIdx.x * 16, m0 = blockIdx.y * 16, pl = blockIdx.z;
   const int m = m0 + r16, n = n0 + r16;
@@ -685,19 +749,28 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA,
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int k = kstart + 4 * g + s;
-    a[s] = (mok && k < K) ? T(Arow[k]) : T(0);
-    b[s] = (nok && k < K) ? ldb((long)k * N) : T(0);
+    const int kk = k < K ? k : K - 1;
+    a[s] = T(Arow[kk]);
+    b[s] = ldb((long)kk * N);
   }
   for (int k0 = kstart; k0 < K; k0 += 64) {
     const int k1 = k0 + 64;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int k = k1 + 4 * g + s;
-      an[s] = (mok && k < K) ? T(Arow[k]) : T(0);
-      bn[s] = (nok && k < K) ? ldb((long)k * N) : T(0);
+      const int kk = k < K ? k : K - 1;
+      an[s] = T(Arow[kk]);
+      bn[s] = ldb((long)kk * N);
     }
+    // loads are clamped in range and left unmasked (rows >= M and columns >= N are never
+    // stored); contraction indices >= K occur only in the last slice and are zeroed there
+    if (k0 + 16 <= K) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc = Mfma<T>::op(a[s], b[s], acc);
+      for (int s = 0; s < 4; ++s) acc = Mfma<T>::op(a[s], b[s], acc);
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = Mfma<T>::op((k0 + 4 * g + s < K) ? a[s] : T(0), b[s], acc);
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       a[s] = an[s];
@@ -728,13 +801,667 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA,
   }
 }
 
+// Register-blocked batched GEMM (same operands, layout and epilogues as k_gemm): one wave
+// computes a (16 TM) x (16 TN) block of C with TM*TN accumulator tiles, so each loaded A
+// fragment feeds TN and each B fragment TM matrix-core ops; the SK waves of a work-group take
+// the 16-wide contraction slices w, w+SK, ... and their partial blocks are summed through LDS
+// in a fixed order.  The next slice's fragments are loaded while the current one is multiplied.
+template <typename T, typename TA, typename TB, int EPI, int TM, int TN, int SK>
+__global__ void __launch_bounds__(64 * SK) k_gemmt(const TA* __restrict__ A, long sA, const TB* __restrict__ B,
+                                                   long sB, int M, int N, int K, T* __restrict__ C, long sC,
+                                                   const double* __restrict__ lr, const double* __restrict__ lc,
+                                                   const double* __restrict__ shift, double* __restrict__ X,
+                                                   const TB* __restrict__ B2, double cb1, double cb2) {
+  typedef typename Mfma<T>::V V;
+  constexpr int NR = SK > 1 ? SK - 1 : 1;
+  __shared__ T red[NR][TM * TN * 4][64];
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r16 = lane & 15, g = lane >> 4;
+  const int n0 = blockIdx.x * 16 * TN, m0 = blockIdx.y * 16 * TM, pl = blockIdx.z;
+  const TA* Ap = A + pl * sA;
+  const TB* Bp = B + pl * sB;
+  const TB* B2p = B2 ? B2 + pl * sB : nullptr;
+  long arow[TM];
+  int bcol[TN];
+  bool mok[TM], nok[TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int m = m0 + 16 * i + r16;
+    mok[i] = m < M;
+    arow[i] = (long)(mok[i] ? m : 0) * K;
+  }
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int n = n0 + 16 * j + r16;
+    nok[j] = n < N;
+    bcol[j] = nok[j] ? n : 0;
+  }
+  V acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = V{T(0), T(0), T(0), T(0)};
+  T a[TM][4], b[TN][4];
+  auto load = [&](int k0, T (&aa)[TM][4], T (&bb)[TN][4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * g + s;
+      const bool kok = k < K;
+      const int kk = kok ? k : 0;
+#pragma unroll
+      for (int i = 0; i < TM; ++i) aa[i][s] = T(Ap[arow[i] + kk]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const long o = (long)kk * N + bcol[j];
+        bb[j][s] = B2p ? T(cb1 * double(Bp[o]) + cb2 * double(B2p[o])) : T(Bp[o]);
+      }
+    }
+  };
+  const int kstep = 16 * SK;
+  if (16 * w < K) load(16 * w, a, b);
+  for (int k0 = 16 * w; k0 < K; k0 += kstep) {
+    T an[TM][4], bn[TN][4];
+    if (k0 + kstep < K) load(k0 + kstep, an, bn);
+    if (k0 + 16 <= K) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::op(a[i][s], b[j][s], acc[i][j]);
+    } else {   // last, partial slice: zero the contraction indices >= K
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const bool kok = k0 + 4 * g + s < K;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<T>::op(kok ? a[i][s] : T(0), b[j][s], acc[i][j]);
+      }
+    }
+    if (k0 + kstep < K) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i][s] = an[i][s];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j][s] = bn[j][s];
+      }
+    }
+  }
+  if (SK > 1) {
+    if (w > 0) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) red[w - 1][(i * TN + j) * 4 + q][lane] = acc[i][j][q];
+    }
+    __syncthreads();
+    if (w != 0) return;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          T v = acc[i][j][q];
+#pragma unroll
+          for (int r = 0; r < SK - 1; ++r) v += red[r][(i * TN + j) * 4 + q][lane];
+          acc[i][j][q] = v;
+        }
+  }
+  // accumulator layout: lane (g, r16) holds column r16 of four rows (Mfma<T>::row) of each tile
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int n = n0 + 16 * j + r16;
+      if (n >= N) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int mm = m0 + 16 * i + Mfma<T>::row(g, q);
+        if (mm >= M) continue;
+        const T v = acc[i][j][q];
+        const long o = pl * sC + (long)mm * N + n;
+        if (EPI == 0) {
+          C[o] = v;
+        } else if (EPI == 1) {
+          const double den = lr[mm] + lc[n] + shift[pl];
+          C[o] = (den != 0.0) ? T(double(v) / den) : T(0);
+        } else if (EPI == 2) {
+          X[o] += double(v);
+        } else {
+          X[o] = double(v);
+        }
+      }
+    }
+}
+
+// Small-operand-in-LDS batched GEMMs.  In every product of the solves and z transforms one
+// operand is a small shared matrix S (a 1D eigenvector matrix or a DFT matrix, <= 320^2) and the
+// other streams the field planes.  The work-group copies the slice of S it needs into LDS once
+// and streams the plane operand from HBM exactly once, with the contraction split into chunks of
+// four 16-wide slices whose loads are issued one chunk ahead.  The streamed dimension is
+// flattened over planes, so nothing is padded per plane.
+//   k_gemm_sr:  C (P*M x N) = A (P*M x K, streamed rows) * S (K x N)           [S right]
+//   k_gemm_sl:  C_p (M x N) = S (M x K) * B_p (K x N), columns (p, n) flattened [S left]
+// A work-group has four waves: 4/SK of them take 16-wide tiles of the streamed dimension and
+// SK split the contraction (partials summed through LDS in a fixed order); each wave holds W
+// accumulator tiles along the small dimension (16 W wide).  Epilogues as k_gemm.
+#define GEMM_CHUNK 4
+
+template <typename T, typename TA, int EPI, int W, int SK>
+__global__ void __launch_bounds__(256) k_gemm_sr(const TA* __restrict__ A, const T* __restrict__ S, int Mtot,
+                                                 int N, int K, T* __restrict__ C, double* __restrict__ X) {
+  typedef typename Mfma<T>::V V;
+  constexpr int WS = 4 / SK, NP = 16 * W + 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Sl = reinterpret_cast<T*>(smem_raw);
+  const int KP = (K + 15) & ~15;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r16 = lane & 15, g = lane >> 4;
+  const int n0 = blockIdx.y * 16 * W;
+  // S[k][n0 .. n0+16W) -> LDS (zero beyond K or N)
+  for (int idx = threadIdx.x; idx < KP * 16 * W; idx += 256) {
+    const int k = idx / (16 * W), j = idx - k * (16 * W);
+    const int n = n0 + j;
+    Sl[k * NP + j] = (k < K && n < N) ? S[(long)k * N + n] : T(0);
+  }
+  __syncthreads();
+  const int ms = w % WS, ks = w / WS;
+  const int m = (blockIdx.x * WS + ms) * 16 + r16;
+  const bool mok = m < Mtot;
+  const TA* Am = A + (long)(mok ? m : 0) * K;
+  V acc[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) acc[j] = V{T(0), T(0), T(0), T(0)};
+  const int nsl = KP / 16;                       // 16-wide slices; this wave takes ks, ks+SK, ...
+  const int nsw = nsl > ks ? (nsl - ks + SK - 1) / SK : 0;
+  const int nfull = nsw / GEMM_CHUNK, rem = nsw - nfull * GEMM_CHUNK;
+  T a[GEMM_CHUNK][4], an[GEMM_CHUNK][4];
+  // loads past the wave's last slice are clamped in range and never multiplied
+  auto load = [&](int c0, T (&aa)[GEMM_CHUNK][4]) {
+#pragma unroll
+    for (int q = 0; q < GEMM_CHUNK; ++q) {
+      const int sl = ks + SK * (c0 + q);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 16 * sl + 4 * g + s;
+        aa[q][s] = T(Am[k < K ? k : K - 1]);   // S rows >= K are zero in LDS
+      }
+    }
+  };
+  auto mma = [&](int sl, const T (&av)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const T* Srow = Sl + (16 * sl + 4 * g + s) * NP + r16;
+#pragma unroll
+      for (int j = 0; j < W; ++j) acc[j] = Mfma<T>::op(av[s], Srow[16 * j], acc[j]);
+    }
+  };
+  load(0, a);
+  for (int ch = 0; ch < nfull; ++ch) {
+    load((ch + 1) * GEMM_CHUNK, an);
+#pragma unroll
+    for (int q = 0; q < GEMM_CHUNK; ++q) mma(ks + SK * (ch * GEMM_CHUNK + q), a[q]);
+#pragma unroll
+    for (int q = 0; q < GEMM_CHUNK; ++q)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[q][s] = an[q][s];
+  }
+#pragma unroll
+  for (int q = 0; q < GEMM_CHUNK - 1; ++q)
+    if (q < rem) mma(ks + SK * (nfull * GEMM_CHUNK + q), a[q]);
+  if (SK > 1) {
+    T* red = Sl + KP * NP;   // [SK-1][WS][W*4][64]
+    __syncthreads();
+    if (ks > 0) {
+#pragma unroll
+      for (int j = 0; j < W; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[(((ks - 1) * WS + ms) * W * 4 + j * 4 + q) * 64 + lane] = acc[j][q];
+    }
+    __syncthreads();
+    if (ks != 0) return;
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T v = acc[j][q];
+        for (int r = 0; r < SK - 1; ++r) v += red[((r * WS + ms) * W * 4 + j * 4 + q) * 64 + lane];
+        acc[j][q] = v;
+      }
+  }
+  const int mb = (blockIdx.x * WS + ms) * 16;
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    const int n = n0 + 16 * j + r16;
+    if (n >= N) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int mm = mb + Mfma<T>::row(g, q);
+      if (mm >= Mtot) continue;
+      const long o = (long)mm * N + n;
+      if (EPI == 0)
+        C[o] = acc[j][q];
+      else if (EPI == 2)
+        X[o] += double(acc[j][q]);
+      else
+        X[o] = double(acc[j][q]);
+    }
+  }
+}
+
+template <typename T, typename TB, int EPI, int W, int SK>
+__global__ void __launch_bounds__(256) k_gemm_sl(const T* __restrict__ S, const TB* __restrict__ B, long sB, int planes,
+                                                 int M, int N, int K, T* __restrict__ C, long sC,
+                                                 const double* __restrict__ lr, const double* __restrict__ lc,
+                                                 const double* __restrict__ shift, const TB* __restrict__ B2,
+                                                 double cb1, double cb2) {
+  typedef typename Mfma<T>::V V;
+  constexpr int WS = 4 / SK, MP = 16 * W + 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Sl = reinterpret_cast<T*>(smem_raw);    // [k][i - m0] = S[i][k]
+  const int KP = (K + 15) & ~15;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r16 = lane & 15, g = lane >> 4;
+  const int m0 = blockIdx.y * 16 * W;
+  for (int idx = threadIdx.x; idx < 16 * W * KP; idx += 256) {
+    const int i = idx / KP, k = idx - i * KP;
+    const int mi = m0 + i;
+    Sl[k * MP + i] = (k < K && mi < M) ? S[(long)mi * K + k] : T(0);
+  }
+  __syncthreads();
+  const int ms = w % WS, ks = w / WS;
+  const long ctot = (long)planes * N;
+  const long cidx = ((long)blockIdx.x * WS + ms) * 16 + r16;
+  const bool cok = cidx < ctot;
+  const int p = cok ? (int)(cidx / N) : 0;
+  const int n = cok ? (int)(cidx - (long)p * N) : 0;
+  const TB* Bp = B + p * sB + n;
+  const TB* B2p = B2 ? B2 + p * sB + n : nullptr;
+  V acc[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) acc[j] = V{T(0), T(0), T(0), T(0)};
+  const int nsl = KP / 16;
+  const int nsw = nsl > ks ? (nsl - ks + SK - 1) / SK : 0;
+  const int nfull = nsw / GEMM_CHUNK, rem = nsw - nfull * GEMM_CHUNK;
+  T b[GEMM_CHUNK][4], bn[GEMM_CHUNK][4], b2[GEMM_CHUNK][4], b2n[GEMM_CHUNK][4];
+  // loads past the wave's last slice are clamped in range and never multiplied; the
+  // two-source combination is formed when the values are consumed
+  auto load = [&](int c0, T (&bb)[GEMM_CHUNK][4], T (&bb2)[GEMM_CHUNK][4]) {
+#pragma unroll
+    for (int q = 0; q < GEMM_CHUNK; ++q) {
+      const int sl = ks + SK * (c0 + q);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 16 * sl + 4 * g + s;
+        const long o = (long)(k < K ? k : K - 1) * N;   // S^T rows >= K are zero in LDS
+        bb[q][s] = T(Bp[o]);
+        if (B2p) bb2[q][s] = T(B2p[o]);
+      }
+    }
+  };
+  auto mma = [&](int sl, const T (&bv)[4], const T (&bv2)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const T x = B2p ? T(cb1 * double(bv[s]) + cb2 * double(bv2[s])) : bv[s];
+      const T* Srow = Sl + (16 * sl + 4 * g + s) * MP + r16;
+#pragma unroll
+      for (int t = 0; t < W; ++t) acc[t] = Mfma<T>::op(Srow[16 * t], x, acc[t]);
+    }
+  };
+  load(0, b, b2);
+  for (int ch = 0; ch < nfull; ++ch) {
+    load((ch + 1) * GEMM_CHUNK, bn, b2n);
+#pragma unroll
+    for (int q = 0; q < GEMM_CHUNK; ++q) mma(ks + SK * (ch * GEMM_CHUNK + q), b[q], b2[q]);
+#pragma unroll
+    for (int q = 0; q < GEMM_CHUNK; ++q)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        b[q][s] = bn[q][s];
+        b2[q][s] = b2n[q][s];
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < GEMM_CHUNK - 1; ++q)
+    if (q < rem) mma(ks + SK * (nfull * GEMM_CHUNK + q), b[q], b2[q]);
+  if (SK > 1) {
+    T* red = Sl + KP * MP;
+    __syncthreads();
+    if (ks > 0) {
+#pragma unroll
+      for (int t = 0; t < W; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[(((ks - 1) * WS + ms) * W * 4 + t * 4 + q) * 64 + lane] = acc[t][q];
+    }
+    __syncthreads();
+    if (ks != 0) return;
+#pragma unroll
+    for (int t = 0; t < W; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T v = acc[t][q];
+        for (int r = 0; r < SK - 1; ++r) v += red[((r * WS + ms) * W * 4 + t * 4 + q) * 64 + lane];
+        acc[t][q] = v;
+      }
+  }
+  if (!cok) return;
+  T* Cp = C + p * sC + n;
+#pragma unroll
+  for (int t = 0; t < W; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = m0 + 16 * t + Mfma<T>::row(g, q);
+      if (i >= M) continue;
+      if (EPI == 0) {
+        Cp[(long)i * N] = acc[t][q];
+      } else {
+        const double den = lr[i] + lc[n] + shift[p];
+        Cp[(long)i * N] = (den != 0.0) ? T(double(acc[t][q]) / den) : T(0);
+      }
+    }
+}
+
+// Configurations the autotuner chooses from.  0..7: register-blocked k_gemm / k_gemmt tiles
+// {TM, TN, SK} (entry 0 is k_gemm: 16 x 16 tile, four-wave split K); 8..15: the LDS kernels
+// k_gemm_sr / k_gemm_sl {W, SK} (used where one operand is shared by all planes and fits).
+struct GemmCfg {
+  int tm, tn, sk;
+};
+static const GemmCfg kGemmCfg[8] = {{1, 1, 4}, {2, 2, 1}, {2, 2, 2}, {3, 3, 1},
+                                    {3, 3, 2}, {2, 4, 1}, {4, 2, 1}, {2, 2, 4}};
+static const GemmCfg kLdsCfg[8] = {{1, 1, 0}, {2, 1, 0}, {3, 1, 0}, {1, 2, 0},
+                                   {2, 2, 0}, {3, 2, 0}, {1, 4, 0}, {2, 4, 0}};
+#define GEMM_LDS_MAX (64 * 1024)
+
 template <typename T, typename TA, typename TB, int EPI>
-static void gemm(pfd_ctx* c, int planes, const TA* A, long sA, const TB* B, long sB, int M, int N, int K,
+static bool gemm_launch(pfd_ctx* c, int cfg, int cls, int planes, const TA* A, long sA, const TB* B, long sB,
+                        int M, int N, int K, T* C, long sC, const double* lr, const double* lc,
+                        const double* shift, double* X, const TB* B2, double cb1, double cb2) {
+  ProfScope ps(c, cls);
+  if (cfg >= 8) {
+    const int W = kLdsCfg[cfg - 8].tm, SK = kLdsCfg[cfg - 8].tn, WS = 4 / SK;
+    const long KP = (K + 15) & ~15;
+    const size_t lds = sizeof(T) * (KP * (16 * W + 4) + (SK > 1 ? (long)(SK - 1) * WS * W * 4 * 64 : 0));
+    const bool sr = (sB == 0 && B2 == nullptr && EPI != 1 && (planes == 1 || (sA == (long)M * K && sC == (long)M * N)));
+    const bool sl = (sA == 0 && (EPI == 0 || EPI == 1));
+    if (lds > GEMM_LDS_MAX || (!sr && !sl)) return false;
+    if (sr) {
+      if constexpr (EPI != 1 && std::is_same<TB, T>::value) {
+        const int Mtot = planes * M;
+        dim3 grid((Mtot + 16 * WS - 1) / (16 * WS), (N + 16 * W - 1) / (16 * W));
+#define SR_CASE(W_, SK_)                                                                                   \
+  if (W == W_ && SK == SK_)                                                                                \
+    hipLaunchKernelGGL((k_gemm_sr<T, TA, EPI, W_, SK_>), grid, dim3(256), lds, c->stream, A, (const T*)B, Mtot, N, \
+                       K, C, X);
+        SR_CASE(1, 1) SR_CASE(2, 1) SR_CASE(3, 1) SR_CASE(1, 2) SR_CASE(2, 2) SR_CASE(3, 2) SR_CASE(1, 4)
+        SR_CASE(2, 4)
+#undef SR_CASE
+        return true;
+      }
+      return false;
+    }
+    if constexpr ((EPI == 0 || EPI == 1) && std::is_same<TA, T>::value) {
+      const long ctot = (long)planes * N;
+      dim3 grid((unsigned)((ctot + 16 * WS - 1) / (16 * WS)), (M + 16 * W - 1) / (16 * W));
+#define SL_CASE(W_, SK_)                                                                                   \
+  if (W == W_ && SK == SK_)                                                                                \
+    hipLaunchKernelGGL((k_gemm_sl<T, TB, EPI, W_, SK_>), grid, dim3(256), lds, c->stream, (const T*)A, B, sB,     \
+                       planes, M, N, K, C, sC, lr, lc, shift, B2, cb1, cb2);
+      SL_CASE(1, 1) SL_CASE(2, 1) SL_CASE(3, 1) SL_CASE(1, 2) SL_CASE(2, 2) SL_CASE(3, 2) SL_CASE(1, 4)
+      SL_CASE(2, 4)
+#undef SL_CASE
+      return true;
+    }
+    return false;
+  }
+  const GemmCfg& q = kGemmCfg[cfg];
+  dim3 grid((N + 16 * q.tn - 1) / (16 * q.tn), (M + 16 * q.tm - 1) / (16 * q.tm), planes);
+#define GEMMT_CASE(ID, TM_, TN_, SK_)                                                                  \
+  case ID:                                                                                             \
+    hipLaunchKernelGGL((k_gemmt<T, TA, TB, EPI, TM_, TN_, SK_>), grid, dim3(64 * SK_), 0, c->stream, A, sA, B, \
+                       sB, M, N, K, C, sC, lr, lc, shift, X, B2, cb1, cb2);                            \
+    break;
+  switch (cfg) {
+    case 0:
+      hipLaunchKernelGGL((k_gemm<T, TA, TB, EPI>), grid, dim3(256), 0, c->stream, A, sA, B, sB, M, N, K, C, sC, lr,
+                         lc, shift, X, B2, cb1, cb2);
+      break;
+    GEMMT_CASE(1, 2, 2, 1)
+    GEMMT_CASE(2, 2, 2, 2)
+    GEMMT_CASE(3, 3, 3, 1)
+    GEMMT_CASE(4, 3, 3, 2)
+    GEMMT_CASE(5, 2, 4, 1)
+    GEMMT_CASE(6, 4, 2, 1)
+    GEMMT_CASE(7, 2, 2, 4)
+    default:
+      return false;
+  }
+#undef GEMMT_CASE
+  return true;
+}
+
+template <typename T, typename TA, typename TB, int EPI>
+static void gemm(pfd_ctx* c, int site, int planes, const TA* A, long sA, const TB* B, long sB, int M, int N, int K,
                  T* C, long sC, const double* lr, const double* lc, const double* shift, double* X) {
-  dim3 grid((N + 15) / 16, (M + 15) / 16, planes);
-  ProfScope ps(c, sizeof(T) == 8 ? PFD_PROF_GEMM64 : PFD_PROF_GEMM32);
-  hipLaunchKernelGGL((k_gemm<T, TA, TB, EPI>), grid, dim3(256), 0, c->stream, A, sA, B, sB, M, N, K, C, sC, lr,
-                     lc, shift, X, (const TB*)nullptr, 1.0, 0.0);
+  const int cls = sizeof(T) == 8 ? PFD_PROF_GEMM64 : PFD_PROF_GEMM32;
+  if (!gemm_launch<T, TA, TB, EPI>(c, c->gemm_cfg[site][sizeof(T) == 8 ? 1 : 0], cls, planes, A, sA, B, sB, M, N,
+                                   K, C, sC, lr, lc, shift, X, (const TB*)nullptr, 1.0, 0.0))
+    gemm_launch<T, TA, TB, EPI>(c, 0, cls, planes, A, sA, B, sB, M, N, K, C, sC, lr, lc, shift, X,
+                                (const TB*)nullptr, 1.0, 0.0);
+}
+
+// ------------------------------------------------------------------ fused fast diagonalisation
+// One correction x (+)= Sy [ (Sy^T r Sx) ./ (ly (+) lx + shift) ] Sx^T in two launches instead of four
+// GEMM passes, each work-group owning one 16-wide strip of one plane, so the intermediate strip
+// stays in LDS:
+//   k_fdm1, column strip cs:  u = r Sx[:, cs] (Ny x 16, LDS);  t[:, cs] = (Sy^T u) ./ den  -> t
+//   k_fdm2, row strip rs:     v = Sy[rs, :] t (16 x Nx, LDS);  x[rs, :] (+)= v Sx^T
+// Small shared operands (Sx, Sy and their transposes, <= 320^2) are read through L1/L2; the
+// plane operands r, t are streamed once per strip.  MFMA 16x16x4 in the operand precision T
+// with the contraction permutation k = k0 + 4g + s of k_gemm; the four waves of a work-group
+// split the output tiles of each stage.  Work-groups of one plane are placed on one XCD (the
+// hardware hands work-groups to the eight XCDs round robin) when the plane count allows, so
+// the strips of a plane share that XCD's L2.
+#define FDM_LDU 17                          // LDS row pitch of u (bank spread)
+#define FDM_MAXT ((PFD_NMAX + 63) / 64)     // output tiles per wave (20 tiles over 4 waves)
+
+__device__ __forceinline__ void fdm_map(int nstrip, int planes, int& p, int& st) {
+  const int L = blockIdx.x;
+  if ((planes & 7) == 0) {
+    const int xcd = L & 7, idx = L >> 3;
+    p = xcd + 8 * (idx / nstrip);
+    st = idx % nstrip;
+  } else {
+    p = L / nstrip;
+    st = L % nstrip;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fdm1(int planes, int Ny, int Nx, long Ng, const double* __restrict__ r,
+                                              const T* __restrict__ SxT, const T* __restrict__ SyT,
+                                              const double* __restrict__ ly, const double* __restrict__ lx,
+                                              const double* __restrict__ shift, T* __restrict__ t) {
+  __shared__ T u[PFD_NMAX * FDM_LDU];
+  typedef typename Mfma<T>::V V;
+  const int nstrip = (Nx + 15) >> 4, mtiles = (Ny + 15) >> 4;
+  int p, cs;
+  fdm_map(nstrip, planes, p, cs);
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), r16 = lane & 15, g = lane >> 4;
+  const int n = cs * 16 + r16;
+  const bool nok = n < Nx;
+  const double* rp = r + (long)p * Ng;
+  // ---- u = r Sx[:, strip]: tiles mt = w, w+4, ... over the Ny rows
+  V acc[FDM_MAXT];
+#pragma unroll
+  for (int i = 0; i < FDM_MAXT; ++i) acc[i] = V{T(0), T(0), T(0), T(0)};
+  const T* Bn = SxT + (long)(nok ? n : 0) * Nx;   // row n of Sx^T = column n of Sx
+  for (int k0 = 0; k0 < Nx; k0 += 16) {
+    T b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * g + s;
+      const T bv = Bn[k < Nx ? k : Nx - 1];
+      b[s] = (nok && k < Nx) ? bv : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < FDM_MAXT; ++i) {
+      const int mt = w + 4 * i;
+      if (mt >= mtiles) break;
+      const int m = mt * 16 + r16;
+      const double* Am = rp + (long)(m < Ny ? m : 0) * Nx;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = k0 + 4 * g + s;
+        const T av = T(Am[k < Nx ? k : Nx - 1]);
+        const T a = (m < Ny && k < Nx) ? av : T(0);
+        acc[i] = Mfma<T>::op(a, b[s], acc[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < FDM_MAXT; ++i) {
+    const int mt = w + 4 * i;
+    if (mt >= mtiles) break;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) u[(mt * 16 + Mfma<T>::row(g, j)) * FDM_LDU + r16] = acc[i][j];
+  }
+  __syncthreads();
+  // ---- t[:, strip] = (Sy^T u) ./ den: tiles over the Ny rows again; u rows >= Ny are zero
+#pragma unroll
+  for (int i = 0; i < FDM_MAXT; ++i) acc[i] = V{T(0), T(0), T(0), T(0)};
+  const int K2 = mtiles * 16;
+  for (int k0 = 0; k0 < K2; k0 += 16) {
+    T b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) b[s] = u[(k0 + 4 * g + s) * FDM_LDU + r16];
+#pragma unroll
+    for (int i = 0; i < FDM_MAXT; ++i) {
+      const int at = w + 4 * i;
+      if (at >= mtiles) break;
+      const int a = at * 16 + r16;
+      const T* Aa = SyT + (long)(a < Ny ? a : 0) * Ny;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = k0 + 4 * g + s;
+        const T aw = Aa[k < Ny ? k : Ny - 1];
+        const T av = (a < Ny && k < Ny) ? aw : T(0);
+        acc[i] = Mfma<T>::op(av, b[s], acc[i]);
+      }
+    }
+  }
+  if (!nok) return;
+  const double lcol = lx[n] + shift[p];
+  T* tp = t + (long)p * Ng;
+#pragma unroll
+  for (int i = 0; i < FDM_MAXT; ++i) {
+    const int at = w + 4 * i;
+    if (at >= mtiles) break;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = at * 16 + Mfma<T>::row(g, j);
+      if (a >= Ny) continue;
+      const double den = ly[a] + lcol;
+      tp[(long)a * Nx + n] = (den != 0.0) ? T(double(acc[i][j]) / den) : T(0);
+    }
+  }
+}
+
+template <typename T, bool OVERWRITE>
+__global__ void __launch_bounds__(256) k_fdm2(int planes, int Ny, int Nx, long Ng, const T* __restrict__ t,
+                                              const T* __restrict__ Sy, const T* __restrict__ Sx,
+                                              double* __restrict__ x) {
+  __shared__ T v[16 * (PFD_NMAX + 1)];
+  typedef typename Mfma<T>::V V;
+  const int nstrip = (Ny + 15) >> 4, ntiles = (Nx + 15) >> 4;
+  const int ldv = ntiles * 16 + 1;
+  int p, rs;
+  fdm_map(nstrip, planes, p, rs);
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), r16 = lane & 15, g = lane >> 4;
+  const T* tp = t + (long)p * Ng;
+  // ---- v = Sy[strip, :] t: A operand row i = rs*16 + r16 of Sy (shared by the wave's tiles)
+  const int ia = rs * 16 + r16;
+  const bool iok = ia < Ny;
+  const T* Ai = Sy + (long)(iok ? ia : 0) * Ny;
+  V acc[FDM_MAXT];
+#pragma unroll
+  for (int i = 0; i < FDM_MAXT; ++i) acc[i] = V{T(0), T(0), T(0), T(0)};
+  for (int k0 = 0; k0 < Ny; k0 += 16) {
+    T a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = k0 + 4 * g + s;
+      const T av = Ai[k < Ny ? k : Ny - 1];
+      a[s] = (iok && k < Ny) ? av : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < FDM_MAXT; ++i) {
+      const int nt = w + 4 * i;
+      if (nt >= ntiles) break;
+      const int n = nt * 16 + r16;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = k0 + 4 * g + s;
+        const T bv = tp[(long)(k < Ny ? k : Ny - 1) * Nx + (n < Nx ? n : Nx - 1)];
+        const T b = (n < Nx && k < Ny) ? bv : T(0);
+        acc[i] = Mfma<T>::op(a[s], b, acc[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < FDM_MAXT; ++i) {
+    const int nt = w + 4 * i;
+    if (nt >= ntiles) break;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[Mfma<T>::row(g, j) * ldv + nt * 16 + r16] = acc[i][j];
+  }
+  __syncthreads();
+  // ---- x[strip, :] (+)= v Sx^T: B operand (k, n) = Sx[n][k]; v columns >= Nx are zero
+#pragma unroll
+  for (int i = 0; i < FDM_MAXT; ++i) acc[i] = V{T(0), T(0), T(0), T(0)};
+  const int K2 = ntiles * 16;
+  for (int k0 = 0; k0 < K2; k0 += 16) {
+    T a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[s] = v[r16 * ldv + k0 + 4 * g + s];
+#pragma unroll
+    for (int i = 0; i < FDM_MAXT; ++i) {
+      const int nt = w + 4 * i;
+      if (nt >= ntiles) break;
+      const int n = nt * 16 + r16;
+      const T* Bn = Sx + (long)(n < Nx ? n : 0) * Nx;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = k0 + 4 * g + s;
+        const T bv = Bn[k < Nx ? k : Nx - 1];
+        const T b = (n < Nx && k < Nx) ? bv : T(0);
+        acc[i] = Mfma<T>::op(a[s], b, acc[i]);
+      }
+    }
+  }
+  double* xp = x + (long)p * Ng;
+#pragma unroll
+  for (int i = 0; i < FDM_MAXT; ++i) {
+    const int nt = w + 4 * i;
+    if (nt >= ntiles) break;
+    const int n = nt * 16 + r16;
+    if (n >= Nx) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = rs * 16 + Mfma<T>::row(g, j);
+      if (row >= Ny) continue;
+      const long o = (long)row * Nx + n;
+      if (OVERWRITE)
+        xp[o] = double(acc[i][j]);
+      else
+        xp[o] += double(acc[i][j]);
+    }
+  }
 }
 
 // Deterministic per-plane sums: part[p*PCH + blk] = sum over chunk blk of w_i f_i
@@ -819,11 +1546,18 @@ static void residual(pfd_ctx* c, int fam, const double* b, const double* x, doub
   Dir1D& dx = c->dirs[F.ix];
   Dir1D& dy = c->dirs[F.iy];
   const long tot = (long)c->planes * c->Ng;
+  const size_t lds = sizeof(double) * (size_t)(RROWS + 2 * c->K) * c->Nx;
+  const bool tiled = !norms && c->Nx <= 256 && lds <= 64 * 1024 && c->resid_variant == 1;
 #define RES_CASE(KK)                                                                                      \
   case KK:                                                                                                \
-    LAUNCH(PFD_PROF_RESID, k_residual<KK>, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->planes,   \
-                       (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, r,       \
-                       apply_only, norms, c->lift[fam].ebot);                                             \
+    if (tiled)                                                                                            \
+      LAUNCH(PFD_PROF_RESID, k_residual_lds<KK>, dim3((c->Ny + RROWS - 1) / RROWS, c->planes), dim3(256), lds,  \
+             c->stream, c->Nx, c->Ny, (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, \
+             r, apply_only, c->lift[fam].ebot);                                                           \
+    else                                                                                                  \
+      LAUNCH(PFD_PROF_RESID, k_residual<KK>, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->planes, \
+             (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, r, apply_only, norms, \
+             c->lift[fam].ebot);                                                                          \
     break;
   switch (c->K) {
     RES_CASE(2) RES_CASE(3) RES_CASE(4) RES_CASE(5) RES_CASE(6) RES_CASE(7) RES_CASE(8) RES_CASE(9)
@@ -848,13 +1582,25 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
   const long Ng = c->Ng;
   T* t1 = reinterpret_cast<T*>(c->tmp);
   T* t2 = reinterpret_cast<T*>(c->tmp2);
-  gemm<T, double, T, 0>(c, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr, nullptr, nullptr);
-  gemm<T, T, T, 1>(c, P, SyT, 0, t1, Ng, Ny, Nx, Ny, t2, Ng, dy.dlam, dx.dlam, shift, nullptr);
-  gemm<T, T, T, 0>(c, P, Sy, 0, t2, Ng, Ny, Nx, Ny, t1, Ng, nullptr, nullptr, nullptr, nullptr);
+  if (c->fdm_variant == 1) {
+    const int cls = sizeof(T) == 8 ? PFD_PROF_GEMM64 : PFD_PROF_GEMM32;
+    LAUNCH(cls, k_fdm1<T>, dim3(P * ((Nx + 15) / 16)), dim3(256), 0, c->stream, P, Ny, Nx, Ng, r, SxT, SyT,
+           dy.dlam, dx.dlam, shift, t1);
+    if (overwrite)
+      LAUNCH(cls, (k_fdm2<T, true>), dim3(P * ((Ny + 15) / 16)), dim3(256), 0, c->stream, P, Ny, Nx, Ng,
+             (const T*)t1, Sy, Sx, x);
+    else
+      LAUNCH(cls, (k_fdm2<T, false>), dim3(P * ((Ny + 15) / 16)), dim3(256), 0, c->stream, P, Ny, Nx, Ng,
+             (const T*)t1, Sy, Sx, x);
+    return;
+  }
+  gemm<T, double, T, 0>(c, PFD_GS_P1, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr, nullptr, nullptr);
+  gemm<T, T, T, 1>(c, PFD_GS_P2, P, SyT, 0, t1, Ng, Ny, Nx, Ny, t2, Ng, dy.dlam, dx.dlam, shift, nullptr);
+  gemm<T, T, T, 0>(c, PFD_GS_P3, P, Sy, 0, t2, Ng, Ny, Nx, Ny, t1, Ng, nullptr, nullptr, nullptr, nullptr);
   if (overwrite)
-    gemm<T, T, T, 3>(c, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr, nullptr, nullptr, x);
+    gemm<T, T, T, 3>(c, PFD_GS_P4, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr, nullptr, nullptr, x);
   else
-    gemm<T, T, T, 2>(c, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr, nullptr, nullptr, x);
+    gemm<T, T, T, 2>(c, PFD_GS_P4, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr, nullptr, nullptr, x);
 }
 
 // Electrode gap nodes (potential family): with Y = A_FF^{-1} r_F from the base operator,
@@ -992,10 +1738,10 @@ hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us) {
   for (int i = 0; i < reps; ++i) {
     if (cls == PFD_PROF_GEMM32) {
       fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, c->r, scratch);
-      per = 4;
+      per = c->fdm_variant == 1 ? 2 : 4;
     } else if (cls == PFD_PROF_GEMM64) {
       fdm_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, c->r, scratch);
-      per = 4;
+      per = c->fdm_variant == 1 ? 2 : 4;
     } else {
       residual(c, PFD_FAM_U, c->b[1], scratch, c->r + 2 * (long)c->planes * c->Ng, 0, nullptr);
     }
@@ -1008,6 +1754,132 @@ hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us) {
   (void)hipEventDestroy(e1);
   c->prof_on = saved;
   *avg_us = 1e3 * ms / (double(reps) * per);
+  return e;
+}
+
+// Autotuner.  For every GEMM call site (the four fast-diagonalisation passes in the context's
+// solve precision, and the z transform in 3D) each tile configuration is timed on the real
+// shapes with scratch operands, and the fastest is kept; then one velocity-family correction
+// with the tuned passes is timed against the fused strip kernels and the faster variant kept.
+// Scratch buffers only; the state is not touched.
+template <typename T>
+static const T* pick(const float* f, const double* d);
+template <>
+const float* pick<float>(const float* f, const double*) { return f; }
+template <>
+const double* pick<double>(const float*, const double* d) { return d; }
+
+static double time_us(pfd_ctx* c, hipEvent_t e0, hipEvent_t e1, int reps, const std::function<void()>& f,
+                      hipError_t& e) {
+  f();
+  (void)hipEventRecord(e0, c->stream);
+  for (int i = 0; i < reps; ++i) f();
+  (void)hipEventRecord(e1, c->stream);
+  if (!e) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (!e) e = hipEventElapsedTime(&ms, e0, e1);
+  return 1e3 * ms / reps;
+}
+
+template <typename T>
+static void tune_fdm_sites(pfd_ctx* c, hipEvent_t e0, hipEvent_t e1, hipError_t& e) {
+  Family& F = c->fam[PFD_FAM_U];
+  Dir1D& dx = c->dirs[F.ix];
+  Dir1D& dy = c->dirs[F.iy];
+  const int P = c->planes, Nx = c->Nx, Ny = c->Ny;
+  const long Ng = c->Ng;
+  const int ti = sizeof(T) == 8 ? 1 : 0;
+  const int cls = ti ? PFD_PROF_GEMM64 : PFD_PROF_GEMM32;
+  T* t1 = reinterpret_cast<T*>(c->tmp);
+  T* t2 = reinterpret_cast<T*>(c->tmp2);
+  const T* Sx = pick<T>(dx.fS, dx.dS);
+  const T* SxT = pick<T>(dx.fST, dx.dST);
+  const T* Sy = pick<T>(dy.fS, dy.dS);
+  const T* SyT = pick<T>(dy.fST, dy.dST);
+  const double* r = c->zero_buf;
+  double* x = c->b[2];
+  for (int site = PFD_GS_P1; site <= PFD_GS_P4; ++site) {
+    int best = 0;
+    for (int cfg = 0; cfg < PFD_GEMM_NCFG && !e; ++cfg) {
+      auto run = [&]() -> bool {
+        switch (site) {
+          case PFD_GS_P1:
+            return gemm_launch<T, double, T, 0>(c, cfg, cls, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr,
+                                         nullptr, nullptr, (const T*)nullptr, 1.0, 0.0);
+          case PFD_GS_P2:
+            return gemm_launch<T, T, T, 1>(c, cfg, cls, P, SyT, 0, t1, Ng, Ny, Nx, Ny, t2, Ng, dy.dlam, dx.dlam, F.dshift,
+                                    nullptr, (const T*)nullptr, 1.0, 0.0);
+          case PFD_GS_P3:
+            return gemm_launch<T, T, T, 0>(c, cfg, cls, P, Sy, 0, t2, Ng, Ny, Nx, Ny, t1, Ng, nullptr, nullptr, nullptr,
+                                    nullptr, (const T*)nullptr, 1.0, 0.0);
+          default:
+            return gemm_launch<T, T, T, 2>(c, cfg, cls, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr,
+                                    nullptr, nullptr, x, (const T*)nullptr, 1.0, 0.0);
+        }
+      };
+      bool ok = true;
+      auto run_ok = [&]() { ok = run(); };
+      c->gemm_us[site][ti][cfg] = time_us(c, e0, e1, 5, run_ok, e);
+      if (!ok) c->gemm_us[site][ti][cfg] = 0.0;   // not applicable to this shape
+      else if (c->gemm_us[site][ti][cfg] < c->gemm_us[site][ti][best]) best = cfg;
+    }
+    c->gemm_cfg[site][ti] = best;
+  }
+}
+
+hipError_t autotune(pfd_ctx* c) {
+  Family& F = c->fam[PFD_FAM_U];
+  Dir1D& dx = c->dirs[F.ix];
+  Dir1D& dy = c->dirs[F.iy];
+  const bool fp32 = c->prob.precision == PFD_REFINED_FP32;
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e) return e;
+  e = hipEventCreate(&e1);
+  if (e) { (void)hipEventDestroy(e0); return e; }
+  const int saved = c->prof_on;
+  c->prof_on = 0;
+  if (fp32)
+    tune_fdm_sites<float>(c, e0, e1, e);
+  else
+    tune_fdm_sites<double>(c, e0, e1, e);
+  if (c->is3d && !e) {
+    int best = 0;
+    for (int cfg = 0; cfg < PFD_GEMM_NCFG && !e; ++cfg) {
+      auto run = [&]() -> bool {
+        return gemm_launch<double, double, double, 0>(c, cfg, PFD_PROF_ZFFT, 1, c->Wf, 0L, c->zero_buf, 0L, c->planes,
+                                               (int)c->Ng, c->planes, c->b[2], 0L, nullptr, nullptr, nullptr,
+                                               nullptr, (const double*)nullptr, 1.0, 0.0);
+      };
+      bool ok = true;
+      auto run_ok = [&]() { ok = run(); };
+      c->gemm_us[PFD_GS_Z][1][cfg] = time_us(c, e0, e1, 5, run_ok, e);
+      if (!ok) c->gemm_us[PFD_GS_Z][1][cfg] = 0.0;
+      else if (c->gemm_us[PFD_GS_Z][1][cfg] < c->gemm_us[PFD_GS_Z][1][best]) best = cfg;
+    }
+    c->gemm_cfg[PFD_GS_Z][1] = best;
+  }
+  for (int v = 0; v < 2 && !e; ++v) {   // residual kernels
+    c->resid_variant = v;
+    auto run = [&]() { residual(c, PFD_FAM_U, c->zero_buf, c->b[2], c->r, 0, nullptr); };
+    c->resid_us[v] = time_us(c, e0, e1, 10, run, e);
+  }
+  c->resid_variant = (c->resid_us[1] <= c->resid_us[0]) ? 1 : 0;
+  for (int v = 0; v < 2 && !e; ++v) {
+    c->fdm_variant = v;
+    auto run = [&]() {
+      if (fp32)
+        fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, c->zero_buf, c->b[2]);
+      else
+        fdm_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, c->zero_buf, c->b[2]);
+    };
+    c->fdm_us[v] = time_us(c, e0, e1, 10, run, e);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->prof_on = saved;
+  c->fdm_variant = (c->fdm_us[1] <= c->fdm_us[0]) ? 1 : 0;
+  if (!e) e = hipGetLastError();
   return e;
 }
 
@@ -1353,11 +2225,11 @@ static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, c
                    double c1 = 1.0, double c2 = 0.0);
 static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, const double* in2, double c1,
                    double c2) {
-  ProfScope ps(c, PFD_PROF_ZFFT);
-  dim3 grid(((int)c->Ng + 15) / 16, (c->planes + 15) / 16, 1);
-  hipLaunchKernelGGL((k_gemm<double, double, double, 0>), grid, dim3(256), 0, c->stream, W, 0L, in, 0L, c->planes,
-                     (int)c->Ng, c->planes, out, 0L, (const double*)nullptr, (const double*)nullptr,
-                     (const double*)nullptr, (double*)nullptr, in2, c1, c2);
+  if (!gemm_launch<double, double, double, 0>(c, c->gemm_cfg[PFD_GS_Z][1], PFD_PROF_ZFFT, 1, W, 0L, in, 0L,
+                                              c->planes, (int)c->Ng, c->planes, out, 0L, nullptr, nullptr, nullptr,
+                                              nullptr, in2, c1, c2))
+    gemm_launch<double, double, double, 0>(c, 0, PFD_PROF_ZFFT, 1, W, 0L, in, 0L, c->planes, (int)c->Ng, c->planes,
+                                           out, 0L, nullptr, nullptr, nullptr, nullptr, in2, c1, c2);
 }
 
 // spectral copies of the Dirichlet sources that changed since the last step (reading R-dir3d)

@@ -42,7 +42,8 @@ def packed_mode(p, Nz):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_3d_mode_solves_match_sparse_lu(precision):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_3d_mode_solves_match_sparse_lu(precision, variant):
     """Every per-mode operator K + (c_f + beta_k^2) M (eqs. 74-78), including the k = 0
     singular pressure and the Nyquist mode, against SciPy LU on random data."""
     torch = _torch()
@@ -51,6 +52,7 @@ def test_3d_mode_solves_match_sparse_lu(precision):
     par = c1_params()
     sch = Scheme(m, par, bc, Nz=Nz, Lz=Lz)
     ctx = gpu_context(m, par, bc, nz=Nz, lz=Lz, precision=precision, refine_iters=3)
+    ctx.set_solver_variant(variant)
     rng = np.random.default_rng(7)
     tol = 1e-11 if precision == 0 else 1e-9
     for fam, name in enumerate(("V", "psi", "phi", "P", "u")):
@@ -215,3 +217,31 @@ def test_3d_manufactured_parity_electrode():
                      V0=f0["V"], P0=f0["P"], init_V=False,
                      prev=dict(phi=fm["phi"], u=fm["u"], P=fm["P"], V=fm["V"]))
     check(out, 1e-10)
+
+
+@pytest.mark.parametrize("cfg", list(range(16)))
+def test_3d_z_transform_every_tile_configuration(cfg):
+    """The z transforms (packed DFT matrices on the matrix cores) with each GEMM tile
+    configuration forced: 3D equilibrium steps still match the oracle."""
+    _torch()
+    Nz, Lz = 8, 1.0
+    m, bc = box3d(n=2, K=5, Nz=Nz, Lz=Lz)
+    par = c1_params()
+    phi0 = _ellipsoid(m, Nz, Lz, par.eta)
+    vd = np.broadcast_to(np.where(np.isclose(m.Y.ravel(), 1.0), 2.0, 0.0)[None, :], (Nz, m.Ng)).copy()
+    ctx0 = gpu_context(m, par, bc, nz=Nz, lz=Lz)
+    ctx0.set_gemm_config(4, cfg)
+    sch = Scheme(m, par, bc, Nz=Nz, Lz=Lz)
+    sch.set_state(phi0)
+    shape = (Nz, m.Ny, m.Nx)
+    ctx0.set_field("phi", phi0.reshape(shape))
+    ctx0.set_sources({"Vd": vd.reshape(shape)})
+    sch.init_potential(dict(Vd=vd))
+    ctx0.init_potential(tol=1e-13, max_iter=20000)
+    for n in range(2):
+        o = sch.step(dict(Vd=vd), equilibrium=True)
+        ctx0.step(1, equilibrium=True)
+    for k in ("phi", "V", "Ez"):
+        ref = o[k]
+        got = ctx0.get_field(k).reshape(Nz, -1)
+        assert rel_err(got, ref) < 1e-10, (k, rel_err(got, ref))

@@ -38,7 +38,8 @@ def box_case(n=4, K=6, periodic=False, top=WALL, par=None):
 # ------------------------------------------------------------------ solver (P8)
 @pytest.mark.parametrize("periodic,top", [(False, WALL), (True, OPEN)])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_solve_matches_sparse_lu(periodic, top, precision):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_solve_matches_sparse_lu(periodic, top, precision, variant):
     """Each constant operator K + c M (families V, psi, phi, P, u) solved by the
     library matches SciPy's sparse LU of the assembled matrix on random data,
     with random Dirichlet values (remark after Algorithm 2)."""
@@ -46,6 +47,7 @@ def test_solve_matches_sparse_lu(periodic, top, precision):
     m, bc, par = box_case(n=3, K=7, periodic=periodic, top=top)
     sch = Scheme(m, par, bc)
     ctx = gpu_context(m, par, bc, precision=precision, refine_iters=3)
+    ctx.set_solver_variant(variant)
     rng = np.random.default_rng(230509020)
     tol = 1e-11 if precision == 0 else 1e-9
     for fam, name in enumerate(("V", "psi", "phi", "P", "u")):
@@ -287,3 +289,86 @@ def test_nonfinite_state_is_reported():
     with pytest.raises(pfd.PfdError) as ei:
         ctx.step(1)
     assert ei.value.code == pfd.ESTATE
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solver_variants_agree_on_benchmark_shapes(precision):
+    """Both fast-diagonalisation kernel variants (four GEMM passes; fused strips) on the
+    benchmark configuration's shapes (4 planes of 161 x 161, K = 8): the same solution of
+    every family up to rounding, and the autotuner's choice is one of them."""
+    torch = _torch()
+    from synth import C2, c2_param_dict
+    import paper_2305_09020_amd as pfd
+    xb = np.linspace(0.0, 1.0, C2["nx"] + 1)
+    prob = pfd.make_problem(xb, xb, C2["K"], c2_param_dict(), [pfd.WALL] * 4, [1, 1, 0, 0], nbatch=4,
+                            precision=precision, refine_iters=3)
+    ctx = pfd.Context(prob)
+    v, us = ctx.solver_variant()
+    assert v in (0, 1) and us[0] > 0 and us[1] > 0
+    rng = np.random.default_rng(3)
+    n = ctx.planes * ctx.Ny * ctx.Nx
+    for fam in range(5):
+        b = torch.tensor(rng.standard_normal(n), device="cuda")
+        g = torch.tensor(rng.standard_normal(n), device="cuda")
+        out = []
+        for var in (0, 1):
+            ctx.set_solver_variant(var)
+            x = g.clone()
+            ctx.solve(fam, b, x)
+            out.append(x.cpu().numpy())
+        e = rel_err(out[1], out[0])
+        assert e < (1e-12 if precision == 0 else 1e-9), (fam, e)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_gemm_tile_configuration_solves(precision):
+    """Each tile configuration of the batched GEMM (forced at all call sites, four-pass
+    solver) solves every family to the sparse-LU solution; the autotuner's timings cover
+    every configuration of the four passes."""
+    torch = _torch()
+    m, bc, par = box_case(n=3, K=7, periodic=True, top=OPEN)
+    sch = Scheme(m, par, bc)
+    ctx = gpu_context(m, par, bc, precision=precision, refine_iters=3)
+    cfg, us = ctx.gemm_config()
+    assert all(0 <= c < 16 for c in cfg)
+    assert all(t > 0 for site in range(4) for t in us[site][:8])
+    ctx.set_solver_variant(0)
+    rng = np.random.default_rng(17)
+    tol = 1e-11 if precision == 0 else 1e-9
+    cases = []
+    for fam, name in enumerate(("V", "psi", "phi", "P", "u")):
+        b = rng.standard_normal(m.Ng)
+        g = rng.standard_normal(m.Ng)
+        cases.append((fam, b, g, sch.solve(name, 0, b, g)))
+    for c in range(16):
+        ctx.set_gemm_config(-1, c)
+        for fam, b, g, xr in cases:
+            xt = torch.tensor(g, device="cuda")
+            ctx.solve(fam, torch.tensor(b, device="cuda"), xt)
+            torch.cuda.synchronize()
+            e = rel_err(xt.cpu().numpy(), xr)
+            assert e < tol, (c, fam, e)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_residual_kernel_variants_identical(periodic):
+    """Both residual kernels (per-node; LDS-tiled rows) give the same refined solves (same
+    sums in the same order; only the compiler's fused multiply-adds may differ) and the
+    autotuner timed both."""
+    torch = _torch()
+    m, bc, par = box_case(n=5, K=8, periodic=periodic, top=OPEN if periodic else WALL)
+    ctx = gpu_context(m, par, bc, nbatch=3, precision=1, refine_iters=3)
+    v, us = ctx.residual_variant()
+    assert v in (0, 1) and us[0] > 0 and us[1] > 0
+    rng = np.random.default_rng(9)
+    n = ctx.planes * m.Ng
+    for fam in range(5):
+        b = torch.tensor(rng.standard_normal(n), device="cuda")
+        g = torch.tensor(rng.standard_normal(n), device="cuda")
+        out = []
+        for var in (0, 1):
+            ctx.set_residual_variant(var)
+            x = g.clone()
+            ctx.solve(fam, b, x)
+            out.append(x.cpu().numpy())
+        assert rel_err(out[1], out[0]) < 1e-13, (fam, rel_err(out[1], out[0]))
