@@ -38,7 +38,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from synth import C2, C3, c2_param_dict, c3_param_dict, c3_phi0, drop_field  # noqa: E402
+from synth import (C2, C3, C4, c2_param_dict, c3_param_dict, c3_phi0, c4_instances,  # noqa: E402
+                   c4_param_dict, drop_field)
 
 VTOP = (0.0, 0.5, 1.0, 2.0)
 
@@ -74,6 +75,111 @@ def make_context(precision, refine_iters, workload="c2"):
     ctx.set_source("Vd", vd)
     its = ctx.init_potential(tol=1e-12, max_iter=20000)
     return ctx, its
+
+
+class C4Run:
+    """The batched workload: 64 independent 2D instances (n x n elements, n in 8..24, order
+    4..10, seeded) on one stream, stepped through one hipGraph launch per step."""
+
+    def __init__(self, precision, refine_iters):
+        import torch
+        import paper_2305_09020_amd as pfd
+        self.ctxs = []
+        self.stream = torch.cuda.current_stream()
+        for inst in c4_instances():
+            xb = np.linspace(0.0, 1.0, inst["n"] + 1)
+            par = c4_param_dict(inst["eps_ratio"])
+            prob = pfd.make_problem(xb, xb, inst["K"], par, [pfd.WALL] * 4, [1, 1, 0, 0],
+                                    precision=precision, refine_iters=refine_iters)
+            ctx = pfd.Context(prob, stream=self.stream)
+            x, y, _ = ctx.coords()
+            X, Y = np.meshgrid(x, y)
+            ctx.set_field("phi", drop_field(X, Y, C4["center"], C4["r"], par["eta"])[None])
+            ctx.set_source("Vd", np.where(np.isclose(Y, 1.0), inst["vtop"], 0.0)[None])
+            ctx.init_potential(tol=1e-12, max_iter=20000)
+            self.ctxs.append(ctx)
+        self.batch = pfd.Batch(self.ctxs, nlanes=4)
+        self.dof = sum(c.planes * c.Nx * c.Ny for c in self.ctxs)
+
+    def step(self, n):
+        self.batch.step(n)
+
+    step_async = step
+
+    def diag(self):
+        return dict(nonfinite=max(c.diag()["nonfinite"] for c in self.ctxs))
+
+
+def roofline_c4(run, steps):
+    """Dominant class over all instances: per-instance launch counts from an instrumented run
+    (instances stepped by plain launches), per-instance average launch time from back-to-back
+    replays; achieved = sum(launches x algorithmic flops or bytes) / sum(launches x time)."""
+    for c in run.ctxs:
+        c.profile_enable(True)
+    run.batch.step(steps)
+    profs = [c.profile_read() for c in run.ctxs]
+    for c in run.ctxs:
+        c.profile_enable(False)
+    tot = {}
+    for p in profs:
+        for k, (ms, n) in p.items():
+            if n > 0:
+                a = tot.setdefault(k, [0.0, 0])
+                a[0] += ms
+                a[1] += n
+    dom = max((k for k in tot if k in PEAK), key=lambda k: tot[k][0])
+    work = 0.0
+    time_s = 0.0
+    for c, p in zip(run.ctxs, profs):
+        n = p.get(dom, (0.0, 0))[1]
+        if n == 0:
+            continue
+        avg = c.profile_replay(dom, 50) * 1e-6
+        P, Nx, Ny = c.planes, c.Nx, c.Ny
+        if dom.startswith("gemm"):
+            per = float(Ny * Nx * (Nx + Ny) * P) * (2.0 if c.solver_variant()[0] == 1 else 1.0)
+        else:
+            per = float(24 * P * Nx * Ny)
+        work += n * per
+        time_s += n * avg
+    scale = 1e12 if dom.startswith("gemm") else 1e9
+    achieved = work / time_s / scale
+    peak = PEAK[dom][0] / scale
+    share = {k: round(v[0] / sum(x[0] for x in tot.values()), 4) for k, v in tot.items()}
+    return {"bound": PEAK[dom][2], "achieved": achieved, "peak": peak, "unit": PEAK[dom][1],
+            "frac": achieved / peak, "traffic": None, "kernel": dom,
+            "avg_launch_us": time_s / max(1, sum(p.get(dom, (0, 0))[1] for p in profs)) * 1e6,
+            "launches_per_step": tot[dom][1] / steps, "class_time_share": share,
+            "note": "all 64 instances; per-launch work differs per instance"}
+
+
+def cpu_baseline_c4(nsteps=10):
+    """The FP64 oracle on the first instance of the batched workload, a few steps after its
+    one-time sparse-LU factorisation."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from oracle.sem import Mesh2D, BOTTOM, TOP, LEFT, RIGHT
+    from oracle.scheme import Scheme, Params, BCs, WALL
+    inst = c4_instances()[0]
+    par = Params(**c4_param_dict(inst["eps_ratio"]))
+    xb = np.linspace(0.0, 1.0, inst["n"] + 1)
+    m = Mesh2D(xb, xb, inst["K"])
+    bc = BCs(side={BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}, pot_sides=(BOTTOM, TOP))
+    sch = Scheme(m, par, bc)
+    sch.set_state(drop_field(m.X, m.Y, C4["center"], C4["r"], par.eta).ravel())
+    src = dict(Vd=np.where(np.isclose(m.Y.ravel(), 1.0), inst["vtop"], 0.0))
+    sch.init_potential(src)
+    t0 = time.perf_counter()
+    sch.step(src)
+    tset = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        sch.step(src)
+    t = time.perf_counter() - t0
+    return dict(value=m.Ng * nsteps / t, unit="DOF-steps/s", cores=1, kind="oracle",
+                sample="instance 0 of the batch (%dx%d elements, K = %d), %d steps after the first; "
+                       "first step incl. sparse-LU set-up %.1f s excluded; single-threaded SciPy/NumPy "
+                       "(host has %d cores)" % (inst["n"], inst["n"], inst["K"], nsteps, tset,
+                                                os.cpu_count() or 0))
 
 
 def time_steps(ctx, steps, warmup):
@@ -209,8 +315,9 @@ def cpu_baseline_c3(nsteps=1):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
-                    help="c2: the 2D benchmark configuration (default); c3: the 3D configuration")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
+                    help="c2: the 2D benchmark configuration (default); c3: the 3D configuration; "
+                         "c4: 64 uneven 2D instances in one batch")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--refine-iters", type=int, default=2)
@@ -239,17 +346,24 @@ def main():
     import paper_2305_09020_amd as pfd
     torch.cuda.set_device(0)
     if a.steps is None:
-        a.steps = C2["steps"] if a.workload == "c2" else C3["steps"]
+        a.steps = {"c2": C2["steps"], "c3": C3["steps"], "c4": C4["steps"]}[a.workload]
     res = {}
     for name, prec in (("refined", pfd.REFINED_FP32), ("fp64", pfd.PLAIN_FP64)):
         if a.only not in (name, "both"):
             continue
-        ctx, its = make_context(prec, a.refine_iters, a.workload)
-        ctx.set_graph(not a.no_graph)
-        t = time_steps(ctx, a.steps, a.warmup)
-        dof = ctx.planes * ctx.Nx * ctx.Ny
-        res[name] = dict(t=t, dof=dof, value=dof * a.steps / t, ctx=ctx,
-                         roofline=roofline(ctx, min(a.steps, 200 if a.workload == "c2" else 20)))
+        if a.workload == "c4":
+            ctx, its = C4Run(prec, a.refine_iters), 0
+            t = time_steps(ctx, a.steps, a.warmup)
+            dof = ctx.dof
+            res[name] = dict(t=t, dof=dof, value=dof * a.steps / t, ctx=ctx,
+                             roofline=roofline_c4(ctx, 5))
+        else:
+            ctx, its = make_context(prec, a.refine_iters, a.workload)
+            ctx.set_graph(not a.no_graph)
+            t = time_steps(ctx, a.steps, a.warmup)
+            dof = ctx.planes * ctx.Nx * ctx.Ny
+            res[name] = dict(t=t, dof=dof, value=dof * a.steps / t, ctx=ctx,
+                             roofline=roofline(ctx, min(a.steps, 200 if a.workload == "c2" else 20)))
         print("# %-7s %.3f ms/step  %.4e DOF-steps/s  (V0 fixed point: %d iterations)"
               % (name, 1e3 * t / a.steps, dof * a.steps / t, its), file=sys.stderr, flush=True)
     main_name = "refined" if "refined" in res else "fp64"
@@ -273,6 +387,13 @@ def main():
                     "instances": len(VTOP), "dof_per_step": r["dof"], "graph": not a.no_graph,
                     "refine_iters": a.refine_iters if main_name == "refined" else 0}
                    if a.workload == "c2" else
+                   {"workload": "64 independent 2D drops in one batch (one hipGraph launch per step): "
+                                "n x n elements with n ~ U{8..24}, order ~ U{4..10}, V_top ~ U[0,2], "
+                                "eps ratio ~ U[1.5,40], seed 1, eta 0.02, dt 1e-4, closed boxes; "
+                                "%s path" % main_name,
+                    "instances": C4["n_inst"], "dof_per_step": r["dof"], "graph": True,
+                    "refine_iters": a.refine_iters if main_name == "refined" else 0}
+                   if a.workload == "c4" else
                    {"workload": "3D drop, 16x16 elements order 8 x 128 Fourier planes (Lz = 2, "
                                 "2,130,048 points), perturbed sphere r = 0.3, rho 1:10, mu 1:2, "
                                 "eps 1:10, dt 1e-4, walls; %s path" % main_name,
@@ -285,7 +406,7 @@ def main():
         out["refined_over_fp64"] = res["refined"]["value"] / res["fp64"]["value"]
         out["fp64_roofline"] = res["fp64"]["roofline"]
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline() if a.workload == "c2" else cpu_baseline_c3()
+        out["cpu_baseline"] = {"c2": cpu_baseline, "c3": cpu_baseline_c3, "c4": cpu_baseline_c4}[a.workload]()
     print(json.dumps(out), flush=True)
 
 

@@ -241,6 +241,28 @@ pfd_status pfd_get_gemm_config(const pfd_ctx* ctx, int* cfg, double* us);
  * synchronises and frees the graphs. */
 pfd_status pfd_set_graph(pfd_ctx* ctx, int on);
 
+/* ------------------------------------------------------------------ batches
+ * A batch steps independent contexts together: instances of uneven mesh,
+ * order, parameters and precision (2D or 3D) that were all created on one
+ * stream.  Each step is one hipGraph launch holding every instance's step as
+ * parallel branches (the instances are spread over nlanes capture streams,
+ * 1..16, default 4 when nlanes < 1), captured on first use per parity of the
+ * time level and step kind.  The contexts stay owned by the caller, keep
+ * their own workspaces and kernels, and are used as usual between batch
+ * steps (set/get fields, sources, stats); destroy the batch before them.
+ * Instances at different time-level parities, or with profiling on, are
+ * stepped by plain launches in order. */
+typedef struct pfd_batch pfd_batch;
+pfd_status pfd_batch_create(pfd_ctx* const* ctxs, int n, int nlanes, pfd_batch** out);
+/* nsteps steps of every instance (equilibrium != 0: the equilibrium system),
+ * then one synchronisation: PFD_ENONFINITE if any instance's state became
+ * non-finite (that instance fails as in pfd_step; the others have stepped). */
+pfd_status pfd_batch_step(pfd_batch* b, int nsteps, int equilibrium);
+void pfd_batch_destroy(pfd_batch* b);
+/* Message of the last error on b (or of the last failed pfd_batch_create when
+ * b is NULL). */
+const char* pfd_batch_last_error(const pfd_batch* b);
+
 /* Mass and energy of the current state (see pfd_stats) for every instance:
  * out holds nbatch entries in 2D, one in 3D (host memory).  Uses E from the
  * last step or pfd_init_potential.  Stream-ordered, then synchronises. */

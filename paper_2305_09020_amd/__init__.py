@@ -80,6 +80,10 @@ _sig = {
     "pfd_get_diag": (ctypes.c_int, [_vp, ctypes.POINTER(Diag)]),
     "pfd_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Stats)]),
     "pfd_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "pfd_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "pfd_batch_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "pfd_batch_destroy": (None, [_vp]),
+    "pfd_batch_last_error": (ctypes.c_char_p, [_vp]),
     "pfd_set_solver_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pfd_set_gemm_config": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "pfd_set_residual_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -325,3 +329,34 @@ class Context:
         _check(_lib.pfd_get_diag(self.h, ctypes.byref(d)), self.h)
         return dict(derived=list(d.derived), last_residual=d.last_residual,
                     nonfinite=d.nonfinite, steps=d.steps)
+
+
+class Batch:
+    """Independent contexts (uneven meshes, orders, parameters) created on one stream,
+    stepped together: one hipGraph launch per step with every instance as a parallel branch."""
+
+    def __init__(self, contexts, nlanes=4):
+        self.contexts = list(contexts)
+        arr = (_vp * len(self.contexts))(*[c.h for c in self.contexts])
+        h = _vp()
+        code = _lib.pfd_batch_create(arr, len(self.contexts), int(nlanes), ctypes.byref(h))
+        if code != OK:
+            raise PfdError(code, _lib.pfd_batch_last_error(None).decode())
+        self.h = h
+        self._destroy = _lib.pfd_batch_destroy
+
+    def step(self, nsteps=1, equilibrium=False):
+        code = _lib.pfd_batch_step(self.h, int(nsteps), int(bool(equilibrium)))
+        if code != OK:
+            raise PfdError(code, _lib.pfd_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -89,3 +89,30 @@ def c3_phi0(X, Y, Z):
     r = C3["r"] * (1.0 + 0.01 * xi)
     d = np.sqrt((X - C3["center"][0]) ** 2 + (Y - C3["center"][1]) ** 2 + (Z - C3["center"][2]) ** 2)
     return np.tanh((d - r) / (math.sqrt(2.0) * c3_param_dict()["eta"]))
+
+
+# ---- batched workload: 64 independent 2D instances of uneven mesh and order
+C4 = dict(name="C4", n_inst=64, seed=1, n_range=(8, 24), K_range=(4, 10), vtop=(0.0, 2.0),
+          eps_ratio=(1.5, 40.0), steps=200, center=(0.5, 0.5), r=0.25)
+
+
+def c4_param_dict(eps_ratio, dt=1e-4):
+    """C1's fluids with eta = 0.02 and permittivities 0.1 : 0.1*eps_ratio."""
+    eta = 0.02
+    return dict(rho1=1.0, rho2=2.0, mu1=0.01, mu2=0.02, eps1=0.1, eps2=0.1 * eps_ratio,
+                lam=lam_from_sigma(1.0, eta), eta=eta, gamma1=1e-4, theta_s_deg=90.0, dt=dt)
+
+
+def c4_instances(n_inst=None, seed=None):
+    """Seeded instance list: square meshes n x n with n ~ U{8..24}, order K ~ U{4..10},
+    top voltage ~ U[0, 2], permittivity ratio ~ U[1.5, 40] (numpy PCG64)."""
+    n_inst = C4["n_inst"] if n_inst is None else n_inst
+    rng = np.random.default_rng(C4["seed"] if seed is None else seed)
+    out = []
+    for _ in range(n_inst):
+        n = int(rng.integers(C4["n_range"][0], C4["n_range"][1] + 1))
+        K = int(rng.integers(C4["K_range"][0], C4["K_range"][1] + 1))
+        v = float(rng.uniform(*C4["vtop"]))
+        er = float(rng.uniform(*C4["eps_ratio"]))
+        out.append(dict(n=n, K=K, vtop=v, eps_ratio=er))
+    return out

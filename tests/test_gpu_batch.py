@@ -1,0 +1,94 @@
+"""Batches of uneven instances stepped through one hipGraph per step: every instance matches
+the same context stepped on its own (same kernels), and the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.sem import Mesh2D, BOTTOM, TOP, LEFT, RIGHT
+from oracle.scheme import Scheme, Params, BCs, WALL, OPEN
+from gpu_cases import gpu_context, rel_err, params_dict
+from synth import drop_field, c4_param_dict
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("phi", "psi", "V", "P", "ux", "uy", "Ex", "Ey")
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _instance(n, K, vtop, eps_ratio, precision, nz=0):
+    par = Params(**{k if k != "lam" else "lam": v for k, v in c4_param_dict(eps_ratio).items()})
+    xb = np.linspace(0.0, 1.0, n + 1)
+    if nz:
+        m = Mesh2D(xb, xb, K, periodic_x=True)
+        bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, pot_sides=(BOTTOM, TOP))
+    else:
+        m = Mesh2D(xb, xb, K)
+        bc = BCs(side={BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}, pot_sides=(BOTTOM, TOP))
+    ctx = gpu_context(m, par, bc, precision=precision, refine_iters=2, nz=nz, lz=1.0 if nz else 0.0)
+    planes = max(nz, 1)
+    phi = drop_field(m.X.ravel(), m.Y.ravel(), (0.5, 0.5), 0.25, par.eta)
+    phi = np.broadcast_to(phi, (planes, m.Ng)).copy()
+    vd = np.where(np.isclose(m.Y.ravel(), 1.0), vtop, 0.0)
+    vd = np.broadcast_to(vd, (planes, m.Ng)).copy()
+    shape = (planes, m.Ny, m.Nx)
+    ctx.set_field("phi", phi.reshape(shape))
+    ctx.set_sources({"Vd": vd.reshape(shape)})
+    ctx.init_potential(tol=1e-12, max_iter=5000)
+    return ctx, (m, par, bc, phi, vd)
+
+
+SPECS = [(2, 5, 1.0, 4.0, 0), (3, 4, 0.5, 20.0, 0), (2, 7, 2.0, 1.5, 0), (2, 5, 1.5, 10.0, 8)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_graph_equals_separate_steps(precision):
+    """Four uneven instances (three 2D meshes of different order, one 3D) in one batch:
+    after each of 4 batch steps every field equals the same instance stepped alone."""
+    _torch()
+    import paper_2305_09020_amd as pfd
+    batch_ctx = [_instance(*s[:4], precision, nz=s[4])[0] for s in SPECS]
+    solo_ctx = [_instance(*s[:4], precision, nz=s[4])[0] for s in SPECS]
+    for a, b in zip(batch_ctx, solo_ctx):       # same kernels on both sides
+        cfg, _ = a.gemm_config()
+        for site, c in enumerate(cfg):
+            b.set_gemm_config(site, c)
+        b.set_solver_variant(a.solver_variant()[0])
+        b.set_residual_variant(a.residual_variant()[0])
+    batch = pfd.Batch(batch_ctx, nlanes=3)
+    for n in range(4):
+        batch.step(1)
+        for c in solo_ctx:
+            c.step(1)
+        for i, (a, b) in enumerate(zip(batch_ctx, solo_ctx)):
+            for k in FIELDS:
+                fa, fb = a.get_field(k), b.get_field(k)
+                assert np.array_equal(fa, fb), (n, i, k, np.max(np.abs(fa - fb)))
+    batch.close()
+
+
+def test_batch_instance_matches_oracle():
+    """A 2D instance stepped inside a batch with two others follows the oracle (refined
+    path, 1e-8 per field)."""
+    _torch()
+    import paper_2305_09020_amd as pfd
+    ctxs, infos = zip(*[_instance(*s[:4], 1) for s in SPECS[:3]])
+    batch = pfd.Batch(list(ctxs))
+    m, par, bc, phi, vd = infos[1]
+    sch = Scheme(m, par, bc)
+    sch.set_state(phi[0])
+    sch.init_potential(dict(Vd=vd[0]))
+    for n in range(3):
+        o = sch.step(dict(Vd=vd[0]))
+        batch.step(1)
+        for k in FIELDS:
+            ref = o[k][0] if np.ndim(o[k]) > 1 else o[k]
+            got = ctxs[1].get_field(k).ravel()
+            scale = max(np.linalg.norm(ref), 1e-12 * np.linalg.norm(o["phi"]))
+            assert np.linalg.norm(got - np.ravel(ref)) / scale < 1e-8, (n, k)
+    batch.close()
