@@ -116,3 +116,57 @@ def c4_instances(n_inst=None, seed=None):
         er = float(rng.uniform(*C4["eps_ratio"]))
         out.append(dict(n=n, K=K, vtop=v, eps_ratio=er))
     return out
+
+
+# ---- equilibrium workload with partial electrodes (learned warm start)
+C5 = dict(name="C5", nx=12, ny=12, K=6, nz=64, lx=1.0, ly=0.5, lz=1.0, center=(0.5, 0.0, 0.5),
+          r=0.25, eta=0.02, lam_gamma1=0.1, dt=1e-5, eps1=1e-3, vrange=(0.0, 2.0), eps_ratio=(1.5, 40.0),
+          theta=(60.0, 120.0), n_train=512, n_test=32, seed_train=2, seed_test=3)
+
+
+def c5_electrodes(nx=None, lx=None):
+    """Bottom-wall electrode segments: the x-elements cycle (+V, gap, -V, gap); returns
+    [(x0, x1, sign)] for the electrode elements."""
+    nx = C5["nx"] if nx is None else nx
+    lx = C5["lx"] if lx is None else lx
+    h = lx / nx
+    out = []
+    for e in range(nx):
+        t = e % 4
+        if t == 0:
+            out.append((e * h, (e + 1) * h, 1.0))
+        elif t == 2:
+            out.append((e * h, (e + 1) * h, -1.0))
+    return out
+
+
+def c5_param_dict(eps_ratio, theta_deg, dt=None, eta=None, eps1=None):
+    """Equilibrium-system parameters: eta = 0.02, lambda gamma1 = 0.1, eps1 = 1e-3 (phase 1,
+    phi = +1, the ambient fluid) and eps2 = eps1 * eps_ratio (the drop, phi = -1).  The
+    permittivity scale keeps eps2 V^2 <= 0.16 at the largest voltage and ratio: the oracle's
+    equilibrium march diverges within a few steps from about eps2 V^2 = 0.3 whatever the step."""
+    eta = C5["eta"] if eta is None else eta
+    eps1 = C5["eps1"] if eps1 is None else eps1
+    lam = lam_from_sigma(1.0, eta)
+    return dict(rho1=1.0, rho2=1.0, mu1=0.01, mu2=0.01, eps1=eps1, eps2=eps1 * float(eps_ratio), lam=lam,
+                eta=eta, gamma1=C5["lam_gamma1"] / lam, theta_s_deg=float(theta_deg),
+                dt=C5["dt"] if dt is None else dt)
+
+
+def c5_samples(n, seed):
+    """Seeded parameter draws (V, eps ratio, contact angle), numpy PCG64."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        out.append((float(rng.uniform(*C5["vrange"])), float(rng.uniform(*C5["eps_ratio"])),
+                    float(rng.uniform(*C5["theta"]))))
+    return out
+
+
+def c5_vd(X, Y, V, electrodes, tol=1e-12):
+    """Dirichlet data on the electrode nodes of the bottom row: +V / -V by segment."""
+    vd = np.zeros_like(np.asarray(X, dtype=float))
+    bottom = np.isclose(Y, 0.0)
+    for (x0, x1, sgn) in electrodes:
+        vd = np.where(bottom & (X >= x0 - tol) & (X <= x1 + tol), sgn * V, vd)
+    return vd
