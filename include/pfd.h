@@ -197,6 +197,13 @@ pfd_status pfd_get_coords(const pfd_ctx* ctx, double* x, double* y, double* z);
 /* Derived constants and diagnostics. */
 pfd_status pfd_get_diag(pfd_ctx* ctx, pfd_diag* d);
 
+/* Change the permittivities and the contact angle of a context (the constant
+ * operators and their factors do not depend on them, so the set-up stays);
+ * every other parameter must equal the current one (PFD_EINVAL otherwise).
+ * Synchronises; drops captured graphs.  Used to march many equilibrium
+ * problems on one context. */
+pfd_status pfd_update_params(pfd_ctx* ctx, const pfd_params* par);
+
 /* Kernels of the fast-diagonalisation solves: 0 = four batched GEMM passes
  * (16x16 MFMA tiles, split-K over four waves), 1 = two fused strip kernels
  * (the strip intermediate stays in LDS).  pfd_create times one velocity
@@ -262,6 +269,59 @@ void pfd_batch_destroy(pfd_batch* b);
 /* Message of the last error on b (or of the last failed pfd_batch_create when
  * b is NULL). */
 const char* pfd_batch_last_error(const pfd_batch* b);
+
+/* ------------------------------------------------------------ learned warm start
+ * A small network, trained on equilibria the method computes, that maps the
+ * three parameters of an equilibrium problem (voltage, permittivity ratio,
+ * contact angle, each scaled to [-1, 1] by the caller) to the equilibrium
+ * phase field on the grid (n_out values, the context's field layout), used as
+ * the starting state of pfd_march_to_equilibrium; the march to the residual
+ * tolerance stays the judge of the result.  Not in the paper.
+ *   a1 = W1 p + b1, h1 = gelu(a1); a2 = W2 h1 + b2, h2 = gelu(a2);
+ *   y = W3 h2 + b3;  loss = mean over batch and outputs of (y - t)^2
+ * gelu(x) = x Phi(x).  Hidden sizes are fixed at 64 and 128.  FP32 master
+ * weights in one blob [W1 (64x3) | b1 | W2 (128x64) | b2 | W3 (n_out x 128) |
+ * b3], row-major; the output layer and its two backward products run on the
+ * matrix cores with BF16 operands (W3, h2 and dL/dy rounded to nearest even)
+ * and FP32 accumulation; Adam (0.9, 0.999, 1e-8).  Training inputs stay on the
+ * device: params (S x 3, FP32) and targets (S x n_out, FP32). */
+typedef struct pfd_ws pfd_ws;
+typedef struct {
+  int hidden1;               /* must be 64  */
+  int hidden2;               /* must be 128 */
+  long n_out;                /* grid values of one field, >= 16 */
+  unsigned long long seed;   /* initial weights: N(0, 1/fan_in), W3 scaled by 0.01 */
+} pfd_ws_arch;
+long pfd_ws_num_weights(const pfd_ws_arch* a);
+pfd_status pfd_ws_workspace_query(const pfd_ws_arch* a, size_t* dev_bytes);
+/* dev_ws: caller-owned device buffer of dev_bytes, 256-byte aligned. */
+pfd_status pfd_ws_create(const pfd_ws_arch* a, void* dev_ws, size_t dev_bytes, void* stream, pfd_ws** out);
+void pfd_ws_destroy(pfd_ws* ws);
+const char* pfd_ws_last_error(const pfd_ws* ws);
+/* Host copies of the FP32 weight blob (pfd_ws_num_weights floats). */
+pfd_status pfd_ws_get_weights(pfd_ws* ws, float* host);
+pfd_status pfd_ws_set_weights(pfd_ws* ws, const float* host);
+/* b3 = mean of the S training targets (device). */
+pfd_status pfd_ws_init_output_bias(pfd_ws* ws, const float* targets, long S);
+/* Gradient of the loss on the minibatch idx[0..B) (host indices into the
+ * device params/targets, 1 <= B <= 32) into grad_host (a weight blob; may be
+ * NULL) and *loss.  Synchronises. */
+pfd_status pfd_ws_gradients(pfd_ws* ws, const float* params, const float* targets, const int* idx, int B,
+                            float* grad_host, double* loss);
+/* One Adam step with step size lr on the minibatch idx[0..B); *loss if not NULL. */
+pfd_status pfd_ws_train_step(pfd_ws* ws, const float* params, const float* targets, const int* idx, int B,
+                             float lr, double* loss);
+/* steps Adam steps on minibatches of B drawn without replacement per epoch
+ * from the S samples (shuffled by a generator seeded with seed), step size
+ * decaying from lr to 0.05 lr (cosine); loss_history[steps] (host, may be
+ * NULL) receives each step's minibatch loss.  Synchronises. */
+pfd_status pfd_ws_train(pfd_ws* ws, const float* params, const float* targets, long S, int steps, int B, float lr,
+                        unsigned long long seed, double* loss_history);
+/* Prediction for one input p_host[3] into out (device, n_out FP64).  With
+ * weights (device, n_out FP64: the quadrature weights of the field's integral)
+ * the prediction is shifted by a constant so that sum(weights * out) = mass
+ * (mass conservation of eq. 16 fixes the equilibrium's integral).  Synchronises. */
+pfd_status pfd_ws_predict(pfd_ws* ws, const float* p_host, const double* weights, double mass, double* out);
 
 /* Mass and energy of the current state (see pfd_stats) for every instance:
  * out holds nbatch entries in 2D, one in 3D (host memory).  Uses E from the

@@ -66,6 +66,11 @@ class Stats(ctypes.Structure):
                 ("phi_max_abs", ctypes.c_double), ("nonfinite", ctypes.c_int)]
 
 
+class WsArch(ctypes.Structure):
+    _fields_ = [("hidden1", ctypes.c_int), ("hidden2", ctypes.c_int), ("n_out", ctypes.c_long),
+                ("seed", ctypes.c_ulonglong)]
+
+
 _vp = ctypes.c_void_p
 _sig = {
     "pfd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -85,6 +90,21 @@ _sig = {
     "pfd_batch_destroy": (None, [_vp]),
     "pfd_batch_last_error": (ctypes.c_char_p, [_vp]),
     "pfd_set_solver_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "pfd_update_params": (ctypes.c_int, [_vp, ctypes.POINTER(Params)]),
+    "pfd_ws_num_weights": (ctypes.c_long, [ctypes.POINTER(WsArch)]),
+    "pfd_ws_workspace_query": (ctypes.c_int, [ctypes.POINTER(WsArch), ctypes.POINTER(ctypes.c_size_t)]),
+    "pfd_ws_create": (ctypes.c_int, [ctypes.POINTER(WsArch), _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    "pfd_ws_destroy": (None, [_vp]),
+    "pfd_ws_last_error": (ctypes.c_char_p, [_vp]),
+    "pfd_ws_get_weights": (ctypes.c_int, [_vp, _vp]),
+    "pfd_ws_set_weights": (ctypes.c_int, [_vp, _vp]),
+    "pfd_ws_init_output_bias": (ctypes.c_int, [_vp, _vp, ctypes.c_long]),
+    "pfd_ws_gradients": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "pfd_ws_train_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_float,
+                                         ctypes.POINTER(ctypes.c_double)]),
+    "pfd_ws_train": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_long, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                                    ctypes.c_ulonglong, _vp]),
+    "pfd_ws_predict": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp]),
     "pfd_set_gemm_config": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "pfd_set_residual_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pfd_get_residual_variant": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
@@ -270,6 +290,14 @@ class Context:
         _check(_lib.pfd_profile_replay(self.h, k, int(reps), ctypes.byref(us)), self.h)
         return us.value
 
+    def update_params(self, params):
+        """Change eps1, eps2 and theta_s_deg (every other parameter must stay as created)."""
+        g = params.get
+        par = Params(g("rho1"), g("rho2"), g("mu1"), g("mu2"), g("eps1"), g("eps2"), g("lam"),
+                     g("eta"), g("gamma1"), g("theta_s_deg"), g("dt"), int(g("bdf", 2)),
+                     float(g("S", 0.0)), float(g("nu_m", 0.0)))
+        _check(_lib.pfd_update_params(self.h, ctypes.byref(par)), self.h)
+
     def set_solver_variant(self, variant):
         """0: four GEMM passes, 1: fused strip kernels, -1: autotune again."""
         _check(_lib.pfd_set_solver_variant(self.h, int(variant)), self.h)
@@ -360,3 +388,93 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class WarmStart:
+    """The learned warm start (hand-written HIP training and inference kernels): a network
+    from three scaled parameters to a field of n_out values.  Device memory is one torch
+    uint8 workspace owned by this object."""
+
+    def __init__(self, n_out, seed=0, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.arch = WsArch(64, 128, int(n_out), int(seed))
+        self.n_out = int(n_out)
+        self.nw = _lib.pfd_ws_num_weights(ctypes.byref(self.arch))
+        n = ctypes.c_size_t(0)
+        _check(_lib.pfd_ws_workspace_query(ctypes.byref(self.arch), ctypes.byref(n)))
+        self.ws = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        h = _vp()
+        _check(_lib.pfd_ws_create(ctypes.byref(self.arch), _vp(base + off), n.value,
+                                  _vp(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self._destroy = _lib.pfd_ws_destroy
+
+    def _chk(self, code):
+        if code != OK:
+            raise PfdError(code, _lib.pfd_ws_last_error(self.h).decode())
+
+    def get_weights(self):
+        w = np.zeros(self.nw, dtype=np.float32)
+        self._chk(_lib.pfd_ws_get_weights(self.h, _vp(w.ctypes.data)))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.size == self.nw
+        self._chk(_lib.pfd_ws_set_weights(self.h, _vp(w.ctypes.data)))
+
+    def init_output_bias(self, targets):
+        self._chk(_lib.pfd_ws_init_output_bias(self.h, _vp(targets.data_ptr()), targets.shape[0]))
+
+    def gradients(self, params, targets, idx):
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        g = np.zeros(self.nw, dtype=np.float32)
+        loss = ctypes.c_double(0.0)
+        self._chk(_lib.pfd_ws_gradients(self.h, _vp(params.data_ptr()), _vp(targets.data_ptr()),
+                                        _vp(idx.ctypes.data), len(idx), _vp(g.ctypes.data), ctypes.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, params, targets, idx, lr):
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        loss = ctypes.c_double(0.0)
+        self._chk(_lib.pfd_ws_train_step(self.h, _vp(params.data_ptr()), _vp(targets.data_ptr()),
+                                         _vp(idx.ctypes.data), len(idx), float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def train(self, params, targets, steps, batch=32, lr=2e-3, seed=0):
+        hist = np.zeros(max(int(steps), 1))
+        self._chk(_lib.pfd_ws_train(self.h, _vp(params.data_ptr()), _vp(targets.data_ptr()), params.shape[0],
+                                    int(steps), int(batch), float(lr), int(seed), _vp(hist.ctypes.data)))
+        return hist[:steps]
+
+    def predict(self, p, out, weights=None, mass=0.0):
+        """Field for inputs p (3 scaled values) into out (float64 device tensor of n_out);
+        with weights (float64 device tensor) shifted to sum(weights * out) = mass."""
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        self._chk(_lib.pfd_ws_predict(self.h, _vp(p.ctypes.data), _vp(weights.data_ptr()) if weights is not None
+                                      else None, float(mass), _vp(out.data_ptr())))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ws_inputs(V, eps_ratio, theta_deg, vmax=2.0, rmin=1.5, rmax=40.0, tmin=60.0, tmax=120.0):
+    """Network inputs of the learned warm start: voltage and contact angle mapped linearly,
+    the permittivity ratio logarithmically, from their sampling ranges to [-1, 1]."""
+    import math
+    return np.array([2.0 * V / vmax - 1.0,
+                     2.0 * (math.log(eps_ratio) - math.log(rmin)) / (math.log(rmax) - math.log(rmin)) - 1.0,
+                     2.0 * (theta_deg - tmin) / (tmax - tmin) - 1.0], dtype=np.float32)

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpfd.so")
-SOURCES = ["pfd_setup.cpp", "pfd_api.cpp", "pfd_kernels.hip", "pfd_batch.cpp"]
+SOURCES = ["pfd_setup.cpp", "pfd_api.cpp", "pfd_kernels.hip", "pfd_batch.cpp", "pfd_ws.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -643,6 +643,27 @@ static hipError_t one_step(pfd_ctx* c, int eq) {
   return hipSuccess;
 }
 
+extern "C" pfd_status pfd_update_params(pfd_ctx* c, const pfd_params* q) {
+  if (!c || !q) return PFD_EINVAL;
+  const pfd_params& o = c->prob.par;
+  if (q->rho1 != o.rho1 || q->rho2 != o.rho2 || q->mu1 != o.mu1 || q->mu2 != o.mu2 || q->lambda != o.lambda ||
+      q->eta != o.eta || q->gamma1 != o.gamma1 || q->dt != o.dt || q->bdf_order != o.bdf_order || q->S != o.S ||
+      q->nu_m != o.nu_m) {
+    c->err = "only eps1, eps2 and theta_s_deg may change after create";
+    return PFD_EINVAL;
+  }
+  if (!(q->eps1 > 0.0) || !(q->eps2 > 0.0)) { c->err = "permittivities must be positive"; return PFD_EINVAL; }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_graphs(c);   // kernel arguments change
+  c->prob.par = *q;
+  Par& P = c->par;
+  P.eps1 = q->eps1;
+  P.eps2 = q->eps2;
+  P.eps0 = std::max(q->eps1, q->eps2);
+  P.cos_theta = std::cos(q->theta_s_deg * M_PI / 180.0);
+  return PFD_OK;
+}
+
 extern "C" pfd_status pfd_set_solver_variant(pfd_ctx* c, int variant) {
   if (!c || variant < -1 || variant > 1) return PFD_EINVAL;
   HIPCHK(hipStreamSynchronize(c->stream));
