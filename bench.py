@@ -38,8 +38,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from synth import (C2, C3, C4, c2_param_dict, c3_param_dict, c3_phi0, c4_instances,  # noqa: E402
-                   c4_param_dict, drop_field)
+from synth import (C2, C3, C4, C5, c2_param_dict, c3_param_dict, c3_phi0, c4_instances,  # noqa: E402
+                   c4_param_dict, c5_electrodes, c5_param_dict, c5_samples, c5_vd, drop_field)
 
 VTOP = (0.0, 0.5, 1.0, 2.0)
 
@@ -182,6 +182,139 @@ def cpu_baseline_c4(nsteps=10):
                                                 os.cpu_count() or 0))
 
 
+def run_c5(a):
+    """Equilibrium workload with the learned warm start: 12x12 elements of order 6 x 64
+    Fourier planes, x-periodic, open top, bottom electrodes cycling (+V, gap, -V, gap); the
+    equilibrium system (eq. 16, u = 0) marched to max|phi^{m+1} - phi^m| <= tol on one
+    context whose permittivities and contact angle change per sample.  Training equilibria
+    (seed 2) are generated by the march itself, the network is trained on the GPU by the
+    library's kernels, and held-out problems (seed 3) are marched from the plain initial drop
+    and from the network's mass-projected prediction."""
+    import torch
+    import paper_2305_09020_amd as pfd
+    eta, dt, tol = C5["eta_run"], C5["dt_run"], C5["tol"]
+    n_train = a.c5_train if a.c5_train is not None else C5["n_train_run"]
+    n_test = a.c5_test if a.c5_test is not None else C5["n_test_run"]
+    xb = np.linspace(0.0, C5["lx"], C5["nx"] + 1)
+    yb = np.linspace(0.0, C5["ly"], C5["ny"] + 1)
+    el = c5_electrodes()
+    prob = pfd.make_problem(xb, yb, C5["K"], c5_param_dict(10.0, 90.0, dt=dt, eta=eta),
+                            [pfd.WALL, pfd.OPEN, pfd.WALL, pfd.WALL], [0, 0, 0, 0], periodic_x=True,
+                            nz=C5["nz"], lz=C5["lz"], precision=pfd.REFINED_FP32, refine_iters=a.refine_iters,
+                            electrodes=[(x0, x1) for x0, x1, _ in el])
+    ctx = pfd.Context(prob)
+    ctx.set_graph(not a.no_graph)
+    x, y, z = ctx.coords()
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    phi0 = drop_field(X, Y, C5["center"][:2], C5["r"], eta, Z=Z, zc=C5["center"][2])
+    wts = ctx.mass_weights()
+    mass0 = float(np.sum(wts * phi0))
+    N = phi0.size
+    dof = N
+    stats = dict(steps=0, seconds=0.0)
+
+    zero = np.zeros(phi0.shape)
+
+    def march(V, er, th, start):
+        ctx.update_params(c5_param_dict(er, th, dt=dt, eta=eta))
+        ctx.set_source("Vd", c5_vd(X, Y, V, el))
+        for k in ("psi", "V"):           # no history from the previous problem
+            ctx.set_field(k, zero)
+            ctx.set_field(k, zero, level=-1)
+        ctx.set_field("phi", start)
+        ctx.init_potential(tol=1e-10, max_iter=5000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            n, r = ctx.march_to_equilibrium(tol, C5["max_steps"])
+            ok = True
+        except pfd.PfdError as e:
+            if e.code not in (pfd.ENOCONV, pfd.ENONFINITE):
+                raise
+            n, ok = C5["max_steps"] if e.code == pfd.ENOCONV else 0, False
+        t = time.perf_counter() - t0
+        stats["steps"] += n
+        stats["seconds"] += t
+        return n, t, ok
+
+    t_gen = time.perf_counter()
+    train = c5_samples(n_train, C5["seed_train"])
+    T = torch.empty((n_train, N), dtype=torch.float32, device="cuda")
+    kept = []
+    for i, (V, er, th) in enumerate(train):
+        n, t, ok = march(V, er, th, phi0)
+        if ok:   # only equilibria the march reached to the tolerance become training data
+            T[len(kept)] = torch.tensor(ctx.get_field("phi").ravel(), dtype=torch.float32, device="cuda")
+            kept.append((V, er, th))
+        print("# train %d/%d: %d steps %.2f s%s" % (i + 1, n_train, n, t, "" if ok else " (not converged)"),
+              file=sys.stderr, flush=True)
+    t_gen = time.perf_counter() - t_gen
+    T = T[:len(kept)].contiguous()
+    P = torch.tensor(np.stack([pfd.ws_inputs(*d) for d in kept]), device="cuda")
+    ws = pfd.WarmStart(N, seed=C5["seed_train"])
+    ws.init_output_bias(T)
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter()
+    hist = ws.train(P, T, steps=a.c5_train_steps, batch=32, lr=2e-3, seed=1)
+    t_tr = time.perf_counter() - t_tr
+    print("# trained %d steps in %.1f s: loss %.3g -> %.3g" % (a.c5_train_steps, t_tr, hist[0], hist[-1]),
+          file=sys.stderr, flush=True)
+    wt = torch.tensor(wts.ravel(), device="cuda")
+    out = torch.empty(N, dtype=torch.float64, device="cuda")
+    rows = []
+    for i, (V, er, th) in enumerate(c5_samples(n_test, C5["seed_test"])):
+        n_p, t_p, ok_p = march(V, er, th, phi0)
+        e_p = ctx.stats()[0]["total"]
+        f_p = ctx.get_field("phi").ravel()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ws.predict(pfd.ws_inputs(V, er, th), out, weights=wt, mass=mass0)
+        torch.cuda.synchronize()
+        t_pred = time.perf_counter() - t0
+        start = out.cpu().numpy().reshape(phi0.shape)
+        err0 = float(np.max(np.abs(start.ravel() - f_p)))
+        n_w, t_w, ok_w = march(V, er, th, start)
+        e_w = ctx.stats()[0]["total"]
+        f_w = ctx.get_field("phi").ravel()
+        rows.append(dict(steps_plain=n_p, steps_warm=n_w, converged_plain=ok_p, converged_warm=ok_w,
+                         s_plain=t_p, s_warm=t_w + t_pred, energy_plain=e_p, energy_warm=e_w,
+                         same_equilibrium=bool(abs(e_w - e_p) <= 1e-6 * abs(e_p)),
+                         start_error=err0, energy_rel_diff=abs(e_w - e_p) / abs(e_p),
+                         sorted_field_diff=float(np.max(np.abs(np.sort(f_w) - np.sort(f_p))))))
+        print("# test %d: plain %d steps %.2f s, warm %d steps %.2f s (start error %.3g)"
+              % (i, n_p, t_p, n_w, t_w + t_pred, err0), file=sys.stderr, flush=True)
+    sp = np.array([r_["steps_plain"] for r_ in rows], dtype=float)
+    sw = np.array([r_["steps_warm"] for r_ in rows], dtype=float)
+    same = np.array([r_["same_equilibrium"] for r_ in rows])
+    value = dof * stats["steps"] / stats["seconds"]
+    out_line = {
+        "metric": "DOF-steps/s on 1 GPU, FP32-refined vs plain FP64 at 1e-8 rel err; % roofline",
+        "value": value, "unit": "DOF-steps/s", "n_gpus": 1, "steps": int(stats["steps"]), "warmup": 0,
+        "ms_per_step": 1e3 * stats["seconds"] / stats["steps"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "3D equilibrium march with learned warm start: 12x12 elements order 6 x 64 "
+                               "Fourier planes (336,384 points), x-periodic, open top, electrodes "
+                               "(+V, gap, -V, gap) x 3, eta %g, dt %g, tol %g; V ~ U[0,2], eps ratio ~ "
+                               "U[1.5,40], contact angle ~ U[60,120]; %d training / %d held-out problems"
+                               % (eta, dt, tol, n_train, n_test),
+                   "dof_per_step": dof, "graph": not a.no_graph, "refine_iters": a.refine_iters},
+        "warm_start": {"train_samples": len(kept), "train_draws": n_train, "generation_s": t_gen, "train_steps": a.c5_train_steps,
+                       "train_s": t_tr, "loss_first": float(hist[0]), "loss_last": float(np.mean(hist[-20:])),
+                       "mean_steps_plain": float(sp.mean()), "mean_steps_warm": float(sw.mean()),
+                       "step_ratio_plain_over_warm": float(sp.mean() / sw.mean()),
+                       "same_equilibrium": int(same.sum()), "other_equilibrium": int((~same).sum()),
+                       "step_ratio_same_equilibrium": float(sp[same].mean() / sw[same].mean()) if same.any() else None,
+                       "other_equilibrium_lower_energy_warm": int(sum(1 for r_ in rows if not r_["same_equilibrium"]
+                                                                       and r_["energy_warm"] < r_["energy_plain"])),
+                       "mean_s_plain": float(np.mean([r_["s_plain"] for r_ in rows])),
+                       "mean_s_warm": float(np.mean([r_["s_warm"] for r_ in rows])),
+                       "max_energy_rel_diff": float(max(r_["energy_rel_diff"] for r_ in rows)),
+                       "max_sorted_field_diff": float(max(r_["sorted_field_diff"] for r_ in rows)),
+                       "per_problem": rows},
+    }
+    print(json.dumps(out_line), flush=True)
+
+
 def time_steps(ctx, steps, warmup):
     import torch
     ctx.step(warmup)
@@ -315,9 +448,13 @@ def cpu_baseline_c3(nsteps=1):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
                     help="c2: the 2D benchmark configuration (default); c3: the 3D configuration; "
-                         "c4: 64 uneven 2D instances in one batch")
+                         "c4: 64 uneven 2D instances in one batch; c5: equilibrium march with the "
+                         "learned warm start (about 10 minutes)")
+    ap.add_argument("--c5-train", type=int, default=None, help="training equilibria for c5")
+    ap.add_argument("--c5-train-steps", type=int, default=3000)
+    ap.add_argument("--c5-test", type=int, default=None, help="held-out problems for c5")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--refine-iters", type=int, default=2)
@@ -345,6 +482,9 @@ def main():
     import torch
     import paper_2305_09020_amd as pfd
     torch.cuda.set_device(0)
+    if a.workload == "c5":
+        run_c5(a)
+        return
     if a.steps is None:
         a.steps = {"c2": C2["steps"], "c3": C3["steps"], "c4": C4["steps"]}[a.workload]
     res = {}

@@ -197,6 +197,11 @@ pfd_status pfd_get_coords(const pfd_ctx* ctx, double* x, double* y, double* z);
 /* Derived constants and diagnostics. */
 pfd_status pfd_get_diag(pfd_ctx* ctx, pfd_diag* d);
 
+/* Quadrature weights of one plane's nodes (host, Nx*Ny doubles): the discrete
+ * integral of a field is sum over planes and nodes of w * f (the GLL mass
+ * matrix; in 3D times lz/nz). */
+pfd_status pfd_get_mass_weights(pfd_ctx* ctx, double* w);
+
 /* Change the permittivities and the contact angle of a context (the constant
  * operators and their factors do not depend on them, so the set-up stays);
  * every other parameter must equal the current one (PFD_EINVAL otherwise).
@@ -230,14 +235,16 @@ pfd_status pfd_get_residual_variant(const pfd_ctx* ctx, int* variant, double* us
  * waves splitting the contraction; cfg 8..15: the shared small matrix staged in
  * LDS with the plane operand streamed, {W, SK} = {1,1} {2,1} {3,1} {1,2}
  * {2,2} {3,2} {1,4} {2,4} (W 16-wide tiles per wave along the small
- * dimension).  pfd_create times every configuration that applies on the real
+ * dimension); cfg 16 (site 4 only, power-of-two nz <= 2048): the batched
+ * radix-2 FFT along z in LDS instead of the dense DFT matrices.  pfd_create times every configuration that applies on the real
  * shapes and keeps each site's fastest (the autotuner); this overrides it (a
  * configuration that does not apply to a site falls back to cfg 0).
  * Synchronises; drops captured graphs. */
 pfd_status pfd_set_gemm_config(pfd_ctx* ctx, int site, int cfg);
 /* Chosen configuration per site (cfg[5]) and the autotuner's timings
- * (us[5*16], microseconds per launch; 0 where not tuned or not applicable).
- * Either may be NULL. */
+ * (us[5*17]: site s, configuration k at us[17 s + k], microseconds per launch,
+ * 0 where not tuned or not applicable; k = 16 is the FFT of site 4).  Either
+ * may be NULL. */
 pfd_status pfd_get_gemm_config(const pfd_ctx* ctx, int* cfg, double* us);
 
 /* on != 0: pfd_step / pfd_step_async / pfd_march_to_equilibrium replay a

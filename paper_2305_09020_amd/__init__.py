@@ -91,6 +91,7 @@ _sig = {
     "pfd_batch_last_error": (ctypes.c_char_p, [_vp]),
     "pfd_set_solver_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pfd_update_params": (ctypes.c_int, [_vp, ctypes.POINTER(Params)]),
+    "pfd_get_mass_weights": (ctypes.c_int, [_vp, _dp]),
     "pfd_ws_num_weights": (ctypes.c_long, [ctypes.POINTER(WsArch)]),
     "pfd_ws_workspace_query": (ctypes.c_int, [ctypes.POINTER(WsArch), ctypes.POINTER(ctypes.c_size_t)]),
     "pfd_ws_create": (ctypes.c_int, [ctypes.POINTER(WsArch), _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
@@ -290,6 +291,12 @@ class Context:
         _check(_lib.pfd_profile_replay(self.h, k, int(reps), ctypes.byref(us)), self.h)
         return us.value
 
+    def mass_weights(self):
+        """Quadrature weights (planes, Ny, Nx): the discrete integral is sum(w * f)."""
+        w = np.zeros(self.Ny * self.Nx)
+        _check(_lib.pfd_get_mass_weights(self.h, w.ctypes.data_as(_dp)), self.h)
+        return np.broadcast_to(w.reshape(1, self.Ny, self.Nx), self.shape).copy()
+
     def update_params(self, params):
         """Change eps1, eps2 and theta_s_deg (every other parameter must stay as created)."""
         g = params.get
@@ -313,16 +320,16 @@ class Context:
         return v.value, [us[0], us[1]]
 
     def set_gemm_config(self, site, cfg):
-        """Force tile configuration cfg (0..15) at GEMM call site (0..4, -1 = all)."""
+        """Force configuration cfg (0..15; 16 = the FFT at site 4) at call site (0..4, -1 = all)."""
         _check(_lib.pfd_set_gemm_config(self.h, int(site), int(cfg)), self.h)
 
     def gemm_config(self):
-        """(chosen cfg per site [5], autotune us per (site, cfg) [5][16]; 0 = not applicable
-        or not tuned)."""
+        """(chosen cfg per site [5], autotune us per (site, cfg) [5][17]; 0 = not applicable
+        or not tuned; cfg 16 of site 4 is the z FFT)."""
         cfg = (ctypes.c_int * 5)()
-        us = (ctypes.c_double * 80)()
+        us = (ctypes.c_double * 85)()
         _check(_lib.pfd_get_gemm_config(self.h, cfg, us), self.h)
-        return list(cfg), [list(us[16 * s:16 * s + 16]) for s in range(5)]
+        return list(cfg), [list(us[17 * s:17 * s + 17]) for s in range(5)]
 
     def solver_variant(self):
         """(variant, [us per correction of variant 0, variant 1]) from the autotuner."""

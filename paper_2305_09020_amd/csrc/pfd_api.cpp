@@ -109,6 +109,7 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
     dbl += 16 * (size_t)Pg;              // physical / spectral / z-derivative temporaries
     dbl += 5 * (size_t)Pg;               // spectral Dirichlet data
     dbl += 4 * (size_t)m.nz * m.nz + 64; // DFT matrices
+    dbl += (size_t)m.nz + 2 + 64;        // FFT twiddles
   }
   dbl += 3 * (size_t)Pg;                 // right sides
   dbl += 9 * (size_t)Pg;                 // r (3), U, Q2, tmp, tmp2, zero, Ybuf
@@ -273,6 +274,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     for (int s : {PFD_SRC_VD, PFD_SRC_F2, PFD_SRC_WX, PFD_SRC_WY, PFD_SRC_WZ}) c->srcS[s] = D(Pg);
     const long NZ2 = (long)m.nz * m.nz;
     c->Wf = D(NZ2); c->Wi = D(NZ2); c->Wd = D(NZ2); c->Dz = D(NZ2);
+    c->twr = D(m.nz / 2 + 1); c->twi = D(m.nz / 2 + 1);
   }
   for (int i = 0; i < 3; ++i) c->b[i] = D(Pg);
   c->r = D(3 * Pg); c->U = D(Pg); c->Q2 = D(Pg); c->tmp = D(Pg); c->tmp2 = D(Pg);
@@ -395,6 +397,16 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     if (!e) e = up(c->Wi, Wi.data(), nz2);
     if (!e) e = up(c->Wd, Wd.data(), nz2);
     if (!e) e = up(c->Dz, Dz.data(), nz2);
+    std::vector<double> tr(m.nz / 2 + 1), ti(m.nz / 2 + 1);
+    for (int k = 0; k <= m.nz / 2; ++k) {
+      tr[k] = std::cos(2.0 * M_PI * k / m.nz);
+      ti[k] = -std::sin(2.0 * M_PI * k / m.nz);
+    }
+    if (!e) e = up(c->twr, tr.data(), 8 * (m.nz / 2 + 1));
+    if (!e) e = up(c->twi, ti.data(), 8 * (m.nz / 2 + 1));
+    c->zlg = 0;
+    if ((m.nz & (m.nz - 1)) == 0 && m.nz >= 4 && m.nz <= 2048)   // the FFT tile holds 2048 points
+      while ((1 << c->zlg) < m.nz) ++c->zlg;
     for (int f : {F_UX, F_UY, F_UZ, F_P, F_PHI, F_PSI, F_V})
       for (int l = 0; l < 2 && !e; ++l) e = hipMemsetAsync(c->spec[f][l], 0, 8 * Pg, c->stream);
     for (int s : {PFD_SRC_VD, PFD_SRC_F2, PFD_SRC_WX, PFD_SRC_WY, PFD_SRC_WZ})
@@ -643,6 +655,15 @@ static hipError_t one_step(pfd_ctx* c, int eq) {
   return hipSuccess;
 }
 
+extern "C" pfd_status pfd_get_mass_weights(pfd_ctx* c, double* w) {
+  if (!c || !w) return PFD_EINVAL;
+  HIPCHK(hipMemcpyAsync(w, c->Mdiag, sizeof(double) * c->Ng, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->is3d)
+    for (long i = 0; i < c->Ng; ++i) w[i] *= c->prob.mesh.lz / c->planes;
+  return PFD_OK;
+}
+
 extern "C" pfd_status pfd_update_params(pfd_ctx* c, const pfd_params* q) {
   if (!c || !q) return PFD_EINVAL;
   const pfd_params& o = c->prob.par;
@@ -676,7 +697,8 @@ extern "C" pfd_status pfd_set_solver_variant(pfd_ctx* c, int variant) {
 }
 
 extern "C" pfd_status pfd_set_gemm_config(pfd_ctx* c, int site, int cfg) {
-  if (!c || site < -1 || site >= PFD_GS_N || cfg < 0 || cfg >= PFD_GEMM_NCFG) return PFD_EINVAL;
+  if (!c || site < -1 || site >= PFD_GS_N || cfg < 0) return PFD_EINVAL;
+  if (cfg >= PFD_GEMM_NCFG && !(cfg == PFD_ZFFT_CFG && site == PFD_GS_Z && c->zlg > 0)) return PFD_EINVAL;
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
   for (int s = 0; s < PFD_GS_N; ++s)
@@ -690,8 +712,10 @@ extern "C" pfd_status pfd_get_gemm_config(const pfd_ctx* c, int* cfg, double* us
   for (int s = 0; s < PFD_GS_N; ++s) {
     const int t = (s == PFD_GS_Z) ? 1 : ti;
     if (cfg) cfg[s] = c->gemm_cfg[s][t];
-    if (us)
-      for (int k = 0; k < PFD_GEMM_NCFG; ++k) us[s * PFD_GEMM_NCFG + k] = c->gemm_us[s][t][k];
+    if (us) {
+      for (int k = 0; k < PFD_GEMM_NCFG; ++k) us[s * (PFD_GEMM_NCFG + 1) + k] = c->gemm_us[s][t][k];
+      us[s * (PFD_GEMM_NCFG + 1) + PFD_GEMM_NCFG] = (s == PFD_GS_Z) ? c->zfft_us : 0.0;
+    }
   }
   return PFD_OK;
 }

@@ -16,6 +16,7 @@
 #define PFD_GEMM_NCFG 16  // tile configurations of the batched GEMM
 // GEMM call sites tuned separately: the four fast-diagonalisation passes and the z transform
 enum { PFD_GS_P1 = 0, PFD_GS_P2, PFD_GS_P3, PFD_GS_P4, PFD_GS_Z, PFD_GS_N };
+#define PFD_ZFFT_CFG 16  // z-transform site only: the batched FFT instead of a GEMM
 
 namespace pfd {
 
@@ -109,6 +110,9 @@ struct pfd_ctx {
   double *Lb[7] = {}, *b[3] = {}, *r = nullptr, *U = nullptr, *Q2 = nullptr;
   // 3D (Fourier in z): packed DFT matrices, spectral state, temporaries
   double *Wf = nullptr, *Wi = nullptr, *Wd = nullptr, *Dz = nullptr;
+  double *twr = nullptr, *twi = nullptr;   // FFT twiddles exp(-2 pi i k / nz), k < nz/2
+  int zlg = 0;                             // log2(nz) when nz is a power of two, else 0
+  double zfft_us = 0.0;                    // autotune timing of the FFT (us per transform)
   double* spec[pfd::F_NSTATE][2] = {};     // spectral copies of u, P, phi, psi, V (two levels)
   double *ph[5] = {}, *sp[5] = {}, *dz[6] = {};
   double* srcS[PFD_NSRC] = {};             // spectral Dirichlet data (VD, F2, WX, WY, WZ)

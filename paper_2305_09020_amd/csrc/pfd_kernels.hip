@@ -1757,6 +1757,9 @@ hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us) {
   return e;
 }
 
+static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, const double* in2, double c1,
+                   double c2);
+
 // Autotuner.  For every GEMM call site (the four fast-diagonalisation passes in the context's
 // solve precision, and the z transform in 3D) each tile configuration is timed on the real
 // shapes with scratch operands, and the fastest is kept; then one velocity-family correction
@@ -1858,6 +1861,13 @@ hipError_t autotune(pfd_ctx* c) {
       else if (c->gemm_us[PFD_GS_Z][1][cfg] < c->gemm_us[PFD_GS_Z][1][best]) best = cfg;
     }
     c->gemm_cfg[PFD_GS_Z][1] = best;
+    if (c->zlg > 0 && !e) {   // the FFT, for power-of-two plane counts
+      const int saved_cfg = c->gemm_cfg[PFD_GS_Z][1];
+      c->gemm_cfg[PFD_GS_Z][1] = PFD_ZFFT_CFG;
+      auto run = [&]() { ztrans(c, c->Wf, c->zero_buf, c->b[2], nullptr, 1.0, 0.0); };
+      c->zfft_us = time_us(c, e0, e1, 5, run, e);
+      if (!(c->zfft_us < c->gemm_us[PFD_GS_Z][1][best])) c->gemm_cfg[PFD_GS_Z][1] = saved_cfg;
+    }
   }
   for (int v = 0; v < 2 && !e; ++v) {   // residual kernels
     c->resid_variant = v;
@@ -2220,11 +2230,191 @@ __global__ void k_u_rhs3(Geo g, const double* L1, const double* LBx, const doubl
   Az[id] = dss(g, LAz, pl, ix, iy) + bmo[node] * f1z[id];
 }
 
+// ------------------------------------------------------------------ FFT along z
+// Batched real FFT along z for a power-of-two number of planes (the dense-DFT GEMM above
+// covers any even count): a work-group takes NB consecutive nodes and all Nz samples, stages
+// them in LDS as complex values in bit-reversed order and runs the log2(Nz) radix-2 stages
+// there (Cooley-Tukey, decimation in time; twiddles exp(-2 pi i k/Nz) from a table).  Modes
+// (same results as the packed DFT matrices up to rounding):
+//   0  forward   f -> packed spectrum / Nz            (Wf)
+//   1  inverse   packed spectrum -> f                 (Wi)
+//   2  d/dz of a packed spectrum -> physical          (Wd: i beta_k, k = 0 and Nyquist -> 0)
+//   3  physical d/dz: forward, i beta_k, inverse      (Dz)
+// Packed layout: plane 0 = Re c_0, plane 1 = Re c_{Nz/2}, planes 2k, 2k+1 = Re, Im c_k.
+#define ZFFT_LDS (32 * 1024)
+#define ZFFT_PTS 2048                 // complex points per work-group (Nz x nodes)
+#define ZFFT_PER (ZFFT_PTS / 256)     // per thread
+
+// one radix-2 stage for all nodes of the tile: butterfly t = j * NB + node (node fastest)
+__device__ __forceinline__ void zfft_pass(double* re, double* im, int lg, int lgnb, const double* twr,
+                                          const double* twi, double sgn) {
+  const int nbm = (1 << lgnb) - 1;
+  for (int s = 0; s < lg; ++s) {
+    const int m = 1 << s;
+#pragma unroll
+    for (int q = 0; q < ZFFT_PER / 2; ++q) {
+      const int t = threadIdx.x + 256 * q;
+      const int node = t & nbm, j = t >> lgnb;
+      const int pos = j & (m - 1), grp = j >> s;
+      const int i0 = (grp << (s + 1)) + pos, i1 = i0 + m;
+      const int tw = pos << (lg - s - 1);
+      const double wr = twr[tw], wi = sgn * twi[tw];
+      const int a0 = (i0 << lgnb) + node, a1 = (i1 << lgnb) + node;
+      const double br = re[a1], bi = im[a1];
+      const double xr = wr * br - wi * bi, xi = wr * bi + wi * br;
+      const double ar = re[a0], ai = im[a0];
+      re[a0] = ar + xr;
+      im[a0] = ai + xi;
+      re[a1] = ar - xr;
+      im[a1] = ai - xi;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int zfft_rev(int v, int lg) { return (int)(__brev((unsigned)v) >> (32 - lg)); }
+
+__global__ void __launch_bounds__(256) k_zfft(int mode, int lg, long Ng, const double* __restrict__ in,
+                                              const double* __restrict__ in2, double c1, double c2,
+                                              const double* __restrict__ twr_g, const double* __restrict__ twi_g,
+                                              const double* __restrict__ betad, double* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int Nz = 1 << lg;
+  const int lgnb = 11 - lg;                 // Nz * NB = 2048
+  const int NB = 1 << lgnb, nbm = NB - 1;
+  double* re = reinterpret_cast<double*>(smem_raw);
+  double* im = re + ZFFT_PTS;
+  double* twr = im + ZFFT_PTS;              // twiddles (Nz/2 + 1 each)
+  double* twi = twr + 1025;
+  for (int k = threadIdx.x; k <= Nz / 2; k += 256) {
+    twr[k] = twr_g[k];
+    twi[k] = twi_g[k];
+  }
+  const long n0 = (long)blockIdx.x * NB;
+  const int nb = (int)min((long)NB, Ng - n0);
+  // all loads of the tile first (independent), then the LDS writes
+  double v[ZFFT_PER];
+#pragma unroll
+  for (int q = 0; q < ZFFT_PER; ++q) {
+    const int t = threadIdx.x + 256 * q;
+    const int z = t >> lgnb, node = t & nbm;
+    const int nn = node < nb ? node : 0;
+    const long o = (long)z * Ng + n0 + nn;
+    v[q] = in2 ? c1 * in[o] + c2 * in2[o] : in[o];
+    if (node >= nb) v[q] = 0.0;
+  }
+  if (mode == 0 || mode == 3) {
+#pragma unroll
+    for (int q = 0; q < ZFFT_PER; ++q) {   // real samples into bit-reversed complex positions
+      const int t = threadIdx.x + 256 * q;
+      const int z = t >> lgnb, node = t & nbm;
+      const int a = (zfft_rev(z, lg) << lgnb) + node;
+      re[a] = v[q];
+      im[a] = 0.0;
+    }
+    __syncthreads();
+    zfft_pass(re, im, lg, lgnb, twr, twi, 1.0);
+    if (mode == 0) {
+      const double sc = 1.0 / Nz;
+#pragma unroll
+      for (int q = 0; q < ZFFT_PER; ++q) {
+        const int t = threadIdx.x + 256 * q;
+        const int p = t >> lgnb, node = t & nbm;
+        if (node >= nb) continue;
+        double w;
+        if (p == 0) w = re[node];
+        else if (p == 1) w = re[((Nz / 2) << lgnb) + node];
+        else w = (p & 1) ? im[((p >> 1) << lgnb) + node] : re[((p >> 1) << lgnb) + node];
+        out[(long)p * Ng + n0 + node] = sc * w;
+      }
+      return;
+    }
+    // mode 3: c_k -> i beta_k c_k / Nz (k = 0 and the Nyquist mode -> 0), then the inverse below
+    for (int t = threadIdx.x; t < ((Nz / 2 + 1) << lgnb); t += 256) {
+      const int k = t >> lgnb, node = t & nbm;
+      const int a = (k << lgnb) + node;
+      if (k == 0 || k == Nz / 2) {
+        re[a] = 0.0;
+        im[a] = 0.0;
+      } else {
+        const double b = betad[2 * k] / Nz;
+        const double cr = re[a], ci = im[a];
+        re[a] = -b * ci;
+        im[a] = b * cr;
+      }
+    }
+    __syncthreads();
+  } else {
+    // packed spectrum (modes 1, 2) -> c_k, k = 0..Nz/2, at plain positions
+#pragma unroll
+    for (int q = 0; q < ZFFT_PER; ++q) {
+      const int t = threadIdx.x + 256 * q;
+      const int p = t >> lgnb, node = t & nbm;
+      const int k = (p < 2) ? (p == 0 ? 0 : Nz / 2) : (p >> 1);
+      const bool imag = p >= 2 && (p & 1);
+      double w = v[q];
+      if (mode == 2) {   // i beta_k c_k: the real part gets -beta Im, the imaginary part beta Re
+        const double b = (k == 0 || k == Nz / 2) ? 0.0 : betad[2 * k];
+        w *= b;
+      }
+      const int a = (k << lgnb) + node;
+      if (mode == 2) {
+        if (imag) re[a] = -w;
+        else im[a] = w;
+        if (p < 2) re[a] = 0.0;     // no imaginary input for k = 0, Nyquist
+      } else {
+        if (imag) im[a] = w;
+        else re[a] = w;
+        if (p < 2) im[a] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  // Hermitian completion c_{Nz-k} = conj(c_k), bit-reversal permutation (pair swaps), inverse
+  // transform (sign +), real part out
+  for (int t = threadIdx.x; t < ((Nz / 2 - 1) << lgnb); t += 256) {
+    const int k = 1 + (t >> lgnb), node = t & nbm;
+    re[((Nz - k) << lgnb) + node] = re[(k << lgnb) + node];
+    im[((Nz - k) << lgnb) + node] = -im[(k << lgnb) + node];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < ZFFT_PER; ++q) {
+    const int t = threadIdx.x + 256 * q;
+    const int z = t >> lgnb, node = t & nbm;
+    const int r = zfft_rev(z, lg);
+    if (z < r) {
+      const int a = (z << lgnb) + node, b = (r << lgnb) + node;
+      const double ar = re[a], ai = im[a];
+      re[a] = re[b];
+      im[a] = im[b];
+      re[b] = ar;
+      im[b] = ai;
+    }
+  }
+  __syncthreads();
+  zfft_pass(re, im, lg, lgnb, twr, twi, -1.0);
+#pragma unroll
+  for (int q = 0; q < ZFFT_PER; ++q) {
+    const int t = threadIdx.x + 256 * q;
+    const int z = t >> lgnb, node = t & nbm;
+    if (node < nb) out[(long)z * Ng + n0 + node] = re[(z << lgnb) + node];
+  }
+}
+
 // out = W in  (or W (c1 in + c2 in2)) along z for every node: one GEMM, M = K = Nz, N = Ng
 static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, const double* in2 = nullptr,
                    double c1 = 1.0, double c2 = 0.0);
 static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, const double* in2, double c1,
                    double c2) {
+  if (c->gemm_cfg[PFD_GS_Z][1] == PFD_ZFFT_CFG && c->zlg > 0) {   // the FFT instead of the DFT GEMM
+    const int mode = (W == c->Wf) ? 0 : (W == c->Wi) ? 1 : (W == c->Wd) ? 2 : 3;
+    const int NB = ZFFT_PTS / c->planes;
+    const size_t lds = sizeof(double) * (2 * ZFFT_PTS + 2 * 1025);
+    LAUNCH(PFD_PROF_ZFFT, k_zfft, dim3((unsigned)((c->Ng + NB - 1) / NB)), dim3(256), lds, c->stream, mode, c->zlg,
+           c->Ng, in, in2, c1, c2, c->twr, c->twi, c->d_betad, out);
+    return;
+  }
   if (!gemm_launch<double, double, double, 0>(c, c->gemm_cfg[PFD_GS_Z][1], PFD_PROF_ZFFT, 1, W, 0L, in, 0L,
                                               c->planes, (int)c->Ng, c->planes, out, 0L, nullptr, nullptr, nullptr,
                                               nullptr, in2, c1, c2))

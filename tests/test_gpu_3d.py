@@ -219,10 +219,11 @@ def test_3d_manufactured_parity_electrode():
     check(out, 1e-10)
 
 
-@pytest.mark.parametrize("cfg", list(range(16)))
+@pytest.mark.parametrize("cfg", list(range(17)))
 def test_3d_z_transform_every_tile_configuration(cfg):
-    """The z transforms (packed DFT matrices on the matrix cores) with each GEMM tile
-    configuration forced: 3D equilibrium steps still match the oracle."""
+    """The z transforms with each GEMM configuration of the packed DFT matrices forced
+    (0..15), and with the batched radix-2 FFT (16): 3D equilibrium steps still match the
+    oracle (forward, inverse and both derivative transforms are used)."""
     _torch()
     Nz, Lz = 8, 1.0
     m, bc = box3d(n=2, K=5, Nz=Nz, Lz=Lz)
@@ -245,3 +246,27 @@ def test_3d_z_transform_every_tile_configuration(cfg):
         ref = o[k]
         got = ctx0.get_field(k).reshape(Nz, -1)
         assert rel_err(got, ref) < 1e-10, (k, rel_err(got, ref))
+
+
+@pytest.mark.parametrize("nz", [4, 16, 64])
+def test_3d_fft_equals_dft_gemm(nz):
+    """Full steps with the FFT and with the dense-DFT GEMM on the same context agree to
+    rounding (power-of-two plane counts; closed box, drop)."""
+    torch = _torch()
+    Lz = 1.3
+    m, bc = box3d(n=2, K=4, Nz=nz, Lz=Lz)
+    par = c1_params()
+    phi0 = _ellipsoid(m, nz, Lz, par.eta)
+    vd = np.broadcast_to(np.where(np.isclose(m.Y.ravel(), 1.0), 1.0, 0.0)[None, :], (nz, m.Ng)).copy()
+    shape = (nz, m.Ny, m.Nx)
+    res = []
+    for cfg in (0, 16):
+        ctx = gpu_context(m, par, bc, nz=nz, lz=Lz)
+        ctx.set_gemm_config(4, cfg)
+        ctx.set_field("phi", phi0.reshape(shape))
+        ctx.set_sources({"Vd": vd.reshape(shape)})
+        ctx.init_potential(tol=1e-13, max_iter=20000)
+        ctx.step(3)
+        res.append({k: ctx.get_field(k) for k in ("phi", "V", "P", "ux", "uz", "Ez")})
+    for k in res[0]:
+        assert rel_err(res[1][k], res[0][k]) < 1e-11, (k, rel_err(res[1][k], res[0][k]))

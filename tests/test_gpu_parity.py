@@ -332,6 +332,7 @@ def test_every_gemm_tile_configuration_solves(precision):
     cfg, us = ctx.gemm_config()
     assert all(0 <= c < 16 for c in cfg)
     assert all(t > 0 for site in range(4) for t in us[site][:8])
+    assert all(len(u) == 17 for u in us)
     ctx.set_solver_variant(0)
     rng = np.random.default_rng(17)
     tol = 1e-11 if precision == 0 else 1e-9
