@@ -336,7 +336,7 @@ PEAK = {"gemm64": (78.6e12, "TFLOP/s", "mfma"), "gemm32": (157.3e12, "TFLOP/s", 
         "residual": (8.0e12, "GB/s", "hbm")}
 
 
-def roofline(ctx, steps):
+def roofline(ctx, steps, workload="c2", path="refined"):
     """Per-class kernel time over `steps` instrumented steps; roofline of the dominant
     class among those with an algorithmic per-launch figure."""
     ctx.profile_enable(True)
@@ -362,27 +362,31 @@ def roofline(ctx, steps):
         peak = PEAK[dom][0] / 1e9
     share = {k: round(v[0] / sum(x[0] for x in tot.values()), 4) for k, v in tot.items()}
     return {"bound": PEAK[dom][2], "achieved": achieved, "peak": peak, "unit": PEAK[dom][1],
-            "frac": achieved / peak, "traffic": traffic(dom, per), "kernel": dom,
+            "frac": achieved / peak, "traffic": traffic(dom, workload, path), "kernel": dom,
             "avg_launch_us": avg * 1e6, "avg_launch_us_event_bracketed": avg_bracketed * 1e6,
             "launches_per_step": n / steps, "per_launch": per, "class_time_share": share,
             "solver_variant": variant, "autotune_us_per_correction": tune_us,
             "gemm_tile_config_per_site": ctx.gemm_config()[0]}
 
 
-def traffic(dom, per):
+def traffic(dom, workload, path):
     """HBM bytes per launch of the class from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE passes, scaled by a plain copy kernel), only while the
-    kernel source is the one the counters were taken on; else None."""
+    profiles/hbm_traffic_<workload>.txt (FETCH_SIZE and WRITE_SIZE passes, scaled by a plain
+    copy), only while pfd_kernels.hip is the source the counters were taken on; else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "fdm_gemm_c2_counters.json")
-    if not os.path.exists(path):
+    f = os.path.join(ROOT, "profiles", "hbm_traffic_%s.txt" % workload)
+    if not os.path.exists(f):
         return None
-    rec = json.load(open(path))
     src = os.path.join(ROOT, "paper_2305_09020_amd", "csrc", "pfd_kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
-        return None
-    cls = rec.get("classes", {}).get(dom)
-    return None if cls is None else cls["hbm_bytes_per_launch"]
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    ok = False
+    for line in open(f):
+        if line.startswith("# kernel source sha256") and line.strip().endswith(sha):
+            ok = True
+        parts = line.split()
+        if ok and len(parts) == 6 and parts[0] == path and parts[1] == dom:
+            return float(parts[5])
+    return None
 
 
 def cpu_baseline(nsteps=40):
@@ -503,7 +507,7 @@ def main():
             t = time_steps(ctx, a.steps, a.warmup)
             dof = ctx.planes * ctx.Nx * ctx.Ny
             res[name] = dict(t=t, dof=dof, value=dof * a.steps / t, ctx=ctx,
-                             roofline=roofline(ctx, min(a.steps, 200 if a.workload == "c2" else 20)))
+                             roofline=roofline(ctx, min(a.steps, 200 if a.workload == "c2" else 20), a.workload, name))
         print("# %-7s %.3f ms/step  %.4e DOF-steps/s  (V0 fixed point: %d iterations)"
               % (name, 1e3 * t / a.steps, dof * a.steps / t, its), file=sys.stderr, flush=True)
     main_name = "refined" if "refined" in res else "fp64"
