@@ -112,7 +112,8 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
     dbl += (size_t)m.nz + 2 + 64;        // FFT twiddles
   }
   dbl += 3 * (size_t)Pg;                 // right sides
-  dbl += 9 * (size_t)Pg;                 // r (3), U, Q2, tmp, tmp2, zero, Ybuf
+  dbl += 13 * (size_t)Pg;                // r (3), U, Q2, tmp (3), tmp2 (3), zero, Ybuf
+  dbl += 15 * (size_t)L->planes + 64;    // family shifts, repeated per stacked component
   dbl += (size_t)L->planes * PFD_STAT_NB * 8;  // diagnostics partials
   if (p->bc.n_electrodes > 0) dbl += (size_t)L->planes * (L->Nx * (size_t)L->Nx + L->Nx) + 4 * (size_t)L->Nx;
   dbl += 7 * (size_t)L->Ng;              // boundary masses, mass
@@ -261,12 +262,26 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   // ---- carve the workspace
   const long Pg = (long)c->planes * c->Ng, Pl = (long)c->planes * c->Nl;
   auto D = [&](long n) { return (double*)carve(c, sizeof(double) * n); };
+  // the velocity components of a level are contiguous: their solves run as one plane stack
+  for (int l = 0; l < 2; ++l) {
+    double* blk = D(3 * Pg);
+    c->fld[F_UX][l] = blk;
+    c->fld[F_UY][l] = blk ? blk + Pg : nullptr;
+    c->fld[F_UZ][l] = blk ? blk + 2 * Pg : nullptr;
+  }
   for (int f = 0; f < F_NSTATE; ++f)
-    for (int l = 0; l < 2; ++l) c->fld[f][l] = D(Pg);
+    if (f != F_UX && f != F_UY && f != F_UZ)
+      for (int l = 0; l < 2; ++l) c->fld[f][l] = D(Pg);
   for (int s = 0; s < PFD_NSRC; ++s) c->src[s] = D(Pg);
   for (int i = 0; i < (c->is3d ? 7 : 3); ++i) c->Lb[i] = D(Pl);
   if (c->is3d) {
-    for (int f : {F_UX, F_UY, F_UZ, F_P, F_PHI, F_PSI, F_V})
+    for (int l = 0; l < 2; ++l) {
+      double* blk = D(3 * Pg);
+      c->spec[F_UX][l] = blk;
+      c->spec[F_UY][l] = blk ? blk + Pg : nullptr;
+      c->spec[F_UZ][l] = blk ? blk + 2 * Pg : nullptr;
+    }
+    for (int f : {F_P, F_PHI, F_PSI, F_V})
       for (int l = 0; l < 2; ++l) c->spec[f][l] = D(Pg);
     for (int i = 0; i < 5; ++i) c->ph[i] = D(Pg);
     for (int i = 0; i < 5; ++i) c->sp[i] = D(Pg);
@@ -276,8 +291,11 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     c->Wf = D(NZ2); c->Wi = D(NZ2); c->Wd = D(NZ2); c->Dz = D(NZ2);
     c->twr = D(m.nz / 2 + 1); c->twi = D(m.nz / 2 + 1);
   }
-  for (int i = 0; i < 3; ++i) c->b[i] = D(Pg);
-  c->r = D(3 * Pg); c->U = D(Pg); c->Q2 = D(Pg); c->tmp = D(Pg); c->tmp2 = D(Pg);
+  {
+    double* blk = D(3 * Pg);   // right sides, contiguous (stacked velocity components)
+    for (int i = 0; i < 3; ++i) c->b[i] = blk ? blk + i * Pg : nullptr;
+  }
+  c->r = D(3 * Pg); c->U = D(Pg); c->Q2 = D(Pg); c->tmp = D(3 * Pg); c->tmp2 = D(3 * Pg);
   double* zero = D(Pg);
   c->Ybuf = D(Pg);
   for (int s = 0; s < 4; ++s) c->bm_side[s] = D(c->Ng);
@@ -290,7 +308,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   c->d_stats = D((long)c->planes * PFD_STAT_NB * 8);
   c->d_part = D(32 * (long)c->planes);
   c->d_beta2 = D(c->planes); c->d_betad = D(c->planes);
-  for (int f = 0; f < 5; ++f) c->fam[f].dshift = D(c->planes);
+  for (int f = 0; f < 5; ++f) c->fam[f].dshift = D(3 * c->planes);   // repeated per stacked component
   for (auto& d : c->dirs) {
     const long NN = (long)d.N * d.N;
     d.dS = D(NN); d.dST = D(NN); d.dKb = D((long)(2 * K + 1) * d.N); d.dlam = D(d.N); d.dM1 = D(d.N);
@@ -390,7 +408,8 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   if (!e) e = up(c->d_D, c->D.data(), 8 * (K + 1) * (K + 1));
   if (!e) e = up(c->d_beta2, c->beta2.data(), 8 * c->planes);
   if (!e) e = up(c->d_betad, c->betad.data(), 8 * c->planes);
-  for (int f = 0; f < 5 && !e; ++f) e = up(c->fam[f].dshift, c->fam[f].hshift.data(), 8 * c->planes);
+  for (int f = 0; f < 5 && !e; ++f)
+    for (int k = 0; k < 3 && !e; ++k) e = up(c->fam[f].dshift + k * c->planes, c->fam[f].hshift.data(), 8 * c->planes);
   if (c->is3d && !e) {
     const size_t nz2 = 8 * (size_t)m.nz * m.nz;
     e = up(c->Wf, Wf.data(), nz2);

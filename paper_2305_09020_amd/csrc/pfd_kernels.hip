@@ -1540,22 +1540,23 @@ static void plane_fix(pfd_ctx* c, int fam, double* f, int mode) {
 }
 
 static void residual(pfd_ctx* c, int fam, const double* b, const double* x, double* r, int apply_only,
-                     double* norms, const double* shift = nullptr) {
+                     double* norms, const double* shift = nullptr, int np = 0) {
   Family& F = c->fam[fam];
   const double* sh = shift ? shift : F.dshift;
   Dir1D& dx = c->dirs[F.ix];
   Dir1D& dy = c->dirs[F.iy];
-  const long tot = (long)c->planes * c->Ng;
+  const int planes = np > 0 ? np : c->planes;   // np: stacked components as extra planes
+  const long tot = (long)planes * c->Ng;
   const size_t lds = sizeof(double) * (size_t)(RROWS + 2 * c->K) * c->Nx;
   const bool tiled = !norms && c->Nx <= 256 && lds <= 64 * 1024 && c->resid_variant == 1;
 #define RES_CASE(KK)                                                                                      \
   case KK:                                                                                                \
     if (tiled)                                                                                            \
-      LAUNCH(PFD_PROF_RESID, k_residual_lds<KK>, dim3((c->Ny + RROWS - 1) / RROWS, c->planes), dim3(256), lds,  \
+      LAUNCH(PFD_PROF_RESID, k_residual_lds<KK>, dim3((c->Ny + RROWS - 1) / RROWS, planes), dim3(256), lds,     \
              c->stream, c->Nx, c->Ny, (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, \
              r, apply_only, c->lift[fam].ebot);                                                           \
     else                                                                                                  \
-      LAUNCH(PFD_PROF_RESID, k_residual<KK>, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->planes, \
+      LAUNCH(PFD_PROF_RESID, k_residual<KK>, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, planes,    \
              (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, r, apply_only, norms, \
              c->lift[fam].ebot);                                                                          \
     break;
@@ -1577,8 +1578,8 @@ hipError_t apply(pfd_ctx* c, int fam, const double* x, double* y, int ncomp) {
 template <typename T>
 static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const double* shift, const T* Sx,
                         const T* SxT, const T* Sy, const T* SyT, const double* r, double* x,
-                        bool overwrite = false) {
-  const int Nx = c->Nx, Ny = c->Ny, P = c->planes;
+                        bool overwrite = false, int np = 0) {
+  const int Nx = c->Nx, Ny = c->Ny, P = np > 0 ? np : c->planes;   // np: stacked components
   const long Ng = c->Ng;
   T* t1 = reinterpret_cast<T*>(c->tmp);
   T* t2 = reinterpret_cast<T*>(c->tmp2);
@@ -1680,31 +1681,38 @@ hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp, int
   const long tot = (long)c->planes * c->Ng;
   const bool fp32 = c->prob.precision == PFD_REFINED_FP32;
   const int iters = fp32 ? (c->prob.refine_iters > 0 ? c->prob.refine_iters : 2) : 1;
-  for (int comp = 0; comp < ncomp; ++comp) {
-    const double* bc = b + comp * tot;
-    double* xc = x + comp * tot;
+  const bool elec = fam == PFD_FAM_V && c->elec.ng > 0;
+  // up to three contiguous components (the velocity) are solved as one stack of planes: the
+  // family's shift array repeats per component; singular and electrode solves go one by one
+  const bool stack = ncomp > 1 && ncomp <= 3 && !F.any_singular && !elec;
+  const int groups = stack ? 1 : ncomp;
+  const int np = stack ? c->planes * ncomp : c->planes;
+  for (int gi = 0; gi < groups; ++gi) {
+    const double* bc = b + gi * tot;
+    double* xc = x + gi * tot;
     for (int it = 0; it < iters; ++it) {
       const double* rin = c->r;
       if (it == 0 && r0) {
-        rin = r0 + comp * tot;
+        rin = r0 + gi * tot;
       } else {
-        residual(c, fam, bc, xc, c->r, 0, nullptr);
+        residual(c, fam, bc, xc, c->r, 0, nullptr, nullptr, np);
         if (F.any_singular && project) plane_fix(c, fam, c->r, 1);
       }
-      const bool elec = fam == PFD_FAM_V && c->elec.ng > 0;
       if (fp32 && elec)
         elec_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, rin, xc);
       else if (elec)
         elec_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, rin, xc);
       else if (fp32)
-        fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, rin, xc);
+        fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, rin, xc, false, np);
       else
-        fdm_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, rin, xc);
+        fdm_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, rin, xc, false, np);
     }
     if (F.any_singular && (project || fp32)) plane_fix(c, fam, xc, 0);
-    if (c->check_residual) {
+  }
+  if (c->check_residual) {
+    for (int comp = 0; comp < ncomp; ++comp) {
       hipMemsetAsync(c->d_norms, 0, sizeof(double) * 2 * c->planes, c->stream);
-      residual(c, fam, bc, xc, c->r, 0, c->d_norms);
+      residual(c, fam, b + comp * tot, x + comp * tot, c->r, 0, c->d_norms);
       std::vector<double> h(2 * c->planes);
       hipMemcpyAsync(h.data(), c->d_norms, sizeof(double) * 2 * c->planes, hipMemcpyDeviceToHost, c->stream);
       hipStreamSynchronize(c->stream);
@@ -2000,8 +2008,7 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
                        S[PFD_SRC_F1X], S[PFD_SRC_F1Y], S[PFD_SRC_WX], S[PFD_SRC_WY], H(F_UX, 0), H(F_UX, -1),
                        H(F_UY, 0), H(F_UY, -1), c->b[1], c->b[2], c->r, c->r + tot, c->fld[F_UX][nw],
                        c->fld[F_UY][nw]);
-    solve(c, PFD_FAM_U, c->b[1], c->fld[F_UX][nw], 1, 0, r0);
-    solve(c, PFD_FAM_U, c->b[2], c->fld[F_UY][nw], 1, 0, warm ? nullptr : c->r + tot);
+    solve(c, PFD_FAM_U, c->b[1], c->fld[F_UX][nw], 2, 0, r0);   // both components as one stack
   }
   LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
   if (!equilibrium)
@@ -2539,10 +2546,8 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
       LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_U], As[i], Bs[i], 0, 1.0,
              (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[ws[i]], H(uf[i], 0),
              H(uf[i], -1), c->b[i], c->r + i * tot, c->spec[uf[i]][nw]);
-    for (int i = 0; i < 3; ++i) {
-      solve(c, PFD_FAM_U, c->b[i], c->spec[uf[i]][nw], 1, 0, warm ? nullptr : c->r + i * tot);
-      ztrans(c, c->Wi, c->spec[uf[i]][nw], c->fld[uf[i]][nw]);
-    }
+    solve(c, PFD_FAM_U, c->b[0], c->spec[F_UX][nw], 3, 0, warm ? nullptr : c->r);   // one stack of 3
+    for (int i = 0; i < 3; ++i) ztrans(c, c->Wi, c->spec[uf[i]][nw], c->fld[uf[i]][nw]);
   }
   LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
   if (!equilibrium) LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_UX][nw], c->d_status);

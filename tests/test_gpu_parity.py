@@ -184,12 +184,12 @@ def test_c1_drop_step_parity_refined_fp32(iters):
     check_parity(out, 1e-8)
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-8)])
-def test_benchmark_workload_parity(precision, tol):
+@pytest.mark.parametrize("precision,tol,iters", [(0, 1e-9, 0), (1, 1e-8, 2)])
+def test_benchmark_workload_parity(precision, tol, iters):
     """The benchmark workload (20x20 elements, K = 8, sessile drop, rho 1:1000, mu 1:100,
     eps 1:40) at full size: two of its instances (V_top = 0.5 and 2) in one context,
-    every field after each of 6 steps.  FP64 path 1e-9, FP32-refined path (the
-    benchmark's 2 corrections) 1e-8.  The velocity starts from rest and is ~1e-5 after a
+    every field after each of 6 steps.  FP64 path 1e-9, FP32-refined path (the benchmark's
+    2 corrections per solve; one correction leaves u about 1e-3 off) 1e-8.  The velocity starts from rest and is ~1e-5 after a
     few steps while the O(1-100) pressure and inertia terms of its equation nearly cancel,
     so rounding differences between the two FP64 implementations appear ~1e-9 relative
     to |u|: u is held to the 1e-8 bound on both paths."""
@@ -202,7 +202,7 @@ def test_benchmark_workload_parity(precision, tol):
     phi1 = drop_field(m.X, m.Y, C2["center"], C2["r"], par.eta)
     vd = np.stack([np.where(np.isclose(m.Y, 1.0), v, 0.0) for v in (0.5, 2.0)])
     out, ctx = run_pair(m, par, bc, np.stack([phi1] * 2), None, dict(Vd=vd), 6, nbatch=2,
-                        precision=precision, refine_iters=2)
+                        precision=precision, refine_iters=iters)
     check_parity(out, tol, field_tol=dict(ux=1e-8, uy=1e-8))
 
 
