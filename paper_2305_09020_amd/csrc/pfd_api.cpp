@@ -121,7 +121,7 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   dbl += 8 * (3 * (size_t)NN * NN + 3 * NN + 8);  // up to 8 distinct 1D operators
   dbl += 8 * (size_t)NN * NN;            // float copies (as doubles, generous)
   dbl += 2 * (size_t)(m.nx + m.ny + 2) + (PFD_KMAX + 1) * (PFD_KMAX + 2);
-  dbl += 48 * (size_t)L->planes + 256;   // shifts, norms, reductions
+  dbl += 48 * (size_t)L->planes + 1280;  // shifts, norms, reductions (1024 block maxima)
   L->bytes = dbl * sizeof(double) + 256 * 128;  // alignment slack
   return PFD_OK;
 }
@@ -304,7 +304,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   c->d_w = D(K + 1); c->d_D = D((long)(K + 1) * (K + 1));
   c->d_status = (int*)carve(c, 64);
   c->d_norms = D(2 * c->planes + 2);
-  c->d_red = D(2 * 64);
+  c->d_red = D(2 * 512);
   c->d_stats = D((long)c->planes * PFD_STAT_NB * 8);
   c->d_part = D(32 * (long)c->planes);
   c->d_beta2 = D(c->planes); c->d_betad = D(c->planes);

@@ -2010,9 +2010,9 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
                        c->fld[F_UY][nw]);
     solve(c, PFD_FAM_U, c->b[1], c->fld[F_UX][nw], 2, 0, r0);   // both components as one stack
   }
-  LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
+  LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
   if (!equilibrium)
-    LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_UX][nw], c->d_status);
+    LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot, c->fld[F_UX][nw], c->d_status);
   c->cur = nw;
   return hipGetLastError();
 }
@@ -2043,9 +2043,9 @@ __global__ void k_maxdiff(long N, const double* a, const double* b, double* out)
 
 hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* out_host2) {
   const long N = (long)c->planes * c->Ng;
-  const int nb = 64;
+  const int nb = (int)std::min(512L, (long)nblk(N));
   LAUNCH(PFD_PROF_OTHER, k_maxdiff, dim3(nb), dim3(WG), 0, c->stream, N, a, b, c->d_red);
-  double h[2 * 64];
+  double h[2 * 512];
   hipMemcpyAsync(h, c->d_red, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, c->stream);
   hipError_t e = hipStreamSynchronize(c->stream);
   out_host2[0] = out_host2[1] = 0.0;
@@ -2549,8 +2549,8 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
     solve(c, PFD_FAM_U, c->b[0], c->spec[F_UX][nw], 3, 0, warm ? nullptr : c->r);   // one stack of 3
     for (int i = 0; i < 3; ++i) ztrans(c, c->Wi, c->spec[uf[i]][nw], c->fld[uf[i]][nw]);
   }
-  LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
-  if (!equilibrium) LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(64), dim3(WG), 0, st, tot, c->fld[F_UX][nw], c->d_status);
+  LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
+  if (!equilibrium) LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot, c->fld[F_UX][nw], c->d_status);
   c->cur = nw;
   return hipGetLastError();
 }
