@@ -235,8 +235,10 @@ pfd_status pfd_get_residual_variant(const pfd_ctx* ctx, int* variant, double* us
  * waves splitting the contraction; cfg 8..15: the shared small matrix staged in
  * LDS with the plane operand streamed, {W, SK} = {1,1} {2,1} {3,1} {1,2}
  * {2,2} {3,2} {1,4} {2,4} (W 16-wide tiles per wave along the small
- * dimension); cfg 16 (site 4 only, power-of-two nz <= 2048): the batched
- * radix-2 FFT along z in LDS instead of the dense DFT matrices.  pfd_create times every configuration that applies on the real
+ * dimension); cfg 16 (site 4 only, power-of-two 4 <= nz <= 256): the batched
+ * FFT along z (two real node columns per complex transform, registers and one
+ * LDS exchange) instead of the dense DFT matrices.  pfd_create times every
+ * configuration that applies on the real
  * shapes and keeps each site's fastest (the autotuner); this overrides it (a
  * configuration that does not apply to a site falls back to cfg 0).
  * Synchronises; drops captured graphs. */

@@ -424,7 +424,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     if (!e) e = up(c->twr, tr.data(), 8 * (m.nz / 2 + 1));
     if (!e) e = up(c->twi, ti.data(), 8 * (m.nz / 2 + 1));
     c->zlg = 0;
-    if ((m.nz & (m.nz - 1)) == 0 && m.nz >= 4 && m.nz <= 2048)   // the FFT tile holds 2048 points
+    if ((m.nz & (m.nz - 1)) == 0 && m.nz >= 4 && m.nz <= 256)   // FFT kernels for 4..256 planes
       while ((1 << c->zlg) < m.nz) ++c->zlg;
     for (int f : {F_UX, F_UY, F_UZ, F_P, F_PHI, F_PSI, F_V})
       for (int l = 0; l < 2 && !e; ++l) e = hipMemsetAsync(c->spec[f][l], 0, 8 * Pg, c->stream);

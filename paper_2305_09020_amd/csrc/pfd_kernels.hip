@@ -2238,195 +2238,328 @@ __global__ void k_u_rhs3(Geo g, const double* L1, const double* LBx, const doubl
 }
 
 // ------------------------------------------------------------------ FFT along z
-// Batched real FFT along z for a power-of-two number of planes (the dense-DFT GEMM above
-// covers any even count): a work-group takes NB consecutive nodes and all Nz samples, stages
-// them in LDS as complex values in bit-reversed order and runs the log2(Nz) radix-2 stages
-// there (Cooley-Tukey, decimation in time; twiddles exp(-2 pi i k/Nz) from a table).  Modes
-// (same results as the packed DFT matrices up to rounding):
+// Batched real FFT along z for a power-of-two number of planes Nz = 4..256 (the dense-DFT GEMM
+// above covers any even count).  Two real node columns a, b travel as one complex sequence
+// z = f_a + i f_b; the length-Nz transform is split as Nz = N1 N2 (four-step / Cooley-Tukey
+// with one LDS exchange): a thread holds N1 samples z_{n2 + N2 n1} in registers and transforms
+// over n1, multiplies by exp(-2 pi i n2 k1 / Nz), and after the LDS exchange a thread transforms
+// the N2 values of one k1 over n2, giving c_{k1 + N1 k2}.  The inverse runs the same steps in
+// the mirrored order.  The spectra of the two real columns are separated with
+// C_a = (Z_k + conj Z_{Nz-k}) / 2, C_b = (Z_k - conj Z_{Nz-k}) / 2i, and joined again as
+// Z = C_a + i C_b for the inverse.  Modes (same results as the packed DFT matrices up to
+// rounding):
 //   0  forward   f -> packed spectrum / Nz            (Wf)
 //   1  inverse   packed spectrum -> f                 (Wi)
 //   2  d/dz of a packed spectrum -> physical          (Wd: i beta_k, k = 0 and Nyquist -> 0)
 //   3  physical d/dz: forward, i beta_k, inverse      (Dz)
 // Packed layout: plane 0 = Re c_0, plane 1 = Re c_{Nz/2}, planes 2k, 2k+1 = Re, Im c_k.
-#define ZFFT_LDS (32 * 1024)
-#define ZFFT_PTS 2048                 // complex points per work-group (Nz x nodes)
-#define ZFFT_PER (ZFFT_PTS / 256)     // per thread
+// Multiplying by i beta(k) with beta odd in k (beta(Nz-k) = -beta(k)) keeps Z = C_a + i C_b
+// consistent, so modes 2 and 3 apply it to Z directly.  One launch runs up to ZB_MAX
+// independent transforms (blockIdx.y), each with its own mode, input and output.
+template <int N>
+struct ZLog2 {
+  static constexpr int v = 1 + ZLog2<N / 2>::v;
+};
+template <>
+struct ZLog2<1> {
+  static constexpr int v = 0;
+};
 
-// one radix-2 stage for all nodes of the tile: butterfly t = j * NB + node (node fastest)
-__device__ __forceinline__ void zfft_pass(double* re, double* im, int lg, int lgnb, const double* twr,
-                                          const double* twi, double sgn) {
-  const int nbm = (1 << lgnb) - 1;
-  for (int s = 0; s < lg; ++s) {
+// in-register DFT of length N (radix-2, decimation in time, natural order in and out):
+// x_j <- sum_i x_i w^{+-ij}, w = exp(-2 pi i / N), twiddles W_Nz^m = (wr[m], wi[m]) from LDS
+template <int N, int NZ, bool INV>
+__device__ __forceinline__ void zdft_reg(double (&re)[N], double (&im)[N], const double* wr, const double* wi) {
+  constexpr int L = ZLog2<N>::v;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    int r = 0;
+#pragma unroll
+    for (int bit = 0; bit < L; ++bit) r |= ((i >> bit) & 1) << (L - 1 - bit);
+    if (i < r) {
+      const double tr = re[i], ti = im[i];
+      re[i] = re[r];
+      im[i] = im[r];
+      re[r] = tr;
+      im[r] = ti;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < L; ++s) {
     const int m = 1 << s;
 #pragma unroll
-    for (int q = 0; q < ZFFT_PER / 2; ++q) {
-      const int t = threadIdx.x + 256 * q;
-      const int node = t & nbm, j = t >> lgnb;
-      const int pos = j & (m - 1), grp = j >> s;
-      const int i0 = (grp << (s + 1)) + pos, i1 = i0 + m;
-      const int tw = pos << (lg - s - 1);
-      const double wr = twr[tw], wi = sgn * twi[tw];
-      const int a0 = (i0 << lgnb) + node, a1 = (i1 << lgnb) + node;
-      const double br = re[a1], bi = im[a1];
-      const double xr = wr * br - wi * bi, xi = wr * bi + wi * br;
-      const double ar = re[a0], ai = im[a0];
-      re[a0] = ar + xr;
-      im[a0] = ai + xi;
-      re[a1] = ar - xr;
-      im[a1] = ai - xi;
-    }
-    __syncthreads();
+    for (int g = 0; g < N; g += 2 * m)
+#pragma unroll
+      for (int p = 0; p < m; ++p) {
+        const int a = g + p, b = a + m;
+        double xr = re[b], xi = im[b];
+        if (p != 0) {
+          const int tw = p * (NZ / (2 * m));
+          const double c = wr[tw], sn = INV ? -wi[tw] : wi[tw];
+          const double yr = c * xr - sn * xi;
+          xi = c * xi + sn * xr;
+          xr = yr;
+        }
+        re[b] = re[a] - xr;
+        im[b] = im[a] - xi;
+        re[a] += xr;
+        im[a] += xi;
+      }
   }
 }
 
-__device__ __forceinline__ int zfft_rev(int v, int lg) { return (int)(__brev((unsigned)v) >> (32 - lg)); }
+// i beta(k) as a multiplier of Z_k (0 for k = 0 and the Nyquist mode)
+template <int NZ>
+__device__ __forceinline__ double zbeta(int k, const double* __restrict__ betad) {
+  const bool lo = k < NZ / 2;
+  const int kk = lo ? k : NZ - k;
+  const double b = betad[2 * (kk < NZ / 2 ? kk : 0)];
+  return (k == 0 || k == NZ / 2) ? 0.0 : (lo ? b : -b);
+}
 
-__global__ void __launch_bounds__(256) k_zfft(int mode, int lg, long Ng, const double* __restrict__ in,
-                                              const double* __restrict__ in2, double c1, double c2,
-                                              const double* __restrict__ twr_g, const double* __restrict__ twi_g,
-                                              const double* __restrict__ betad, double* __restrict__ out) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int Nz = 1 << lg;
-  const int lgnb = 11 - lg;                 // Nz * NB = 2048
-  const int NB = 1 << lgnb, nbm = NB - 1;
-  double* re = reinterpret_cast<double*>(smem_raw);
-  double* im = re + ZFFT_PTS;
-  double* twr = im + ZFFT_PTS;              // twiddles (Nz/2 + 1 each)
-  double* twi = twr + 1025;
-  for (int k = threadIdx.x; k <= Nz / 2; k += 256) {
-    twr[k] = twr_g[k];
-    twi[k] = twi_g[k];
+// work-group: P column pairs (nodes n0 + c and n0 + P + c), T = P N2 threads; thread t owns
+// column c = t % P and row t / P (n2 in the first half-transform, k1 = t / P + N2 r in the second)
+template <int LG>
+struct ZfftShape {
+  static constexpr int NZ = 1 << LG, N1 = 1 << ((LG + 1) / 2), N2 = 1 << (LG / 2);
+  static constexpr int P = (2048 / NZ) < 64 ? (2048 / NZ) : 64;
+  static constexpr int T = P * N2;
+  static constexpr int RS = N2 * P + P;   // LDS stride between k1 rows (padded)
+};
+
+#define ZB_MAX 6
+struct ZBatch {
+  const double* in[ZB_MAX];
+  const double* in2[ZB_MAX];   // second input (c1 in + c2 in2) when the kernel is built for it
+  double* out[ZB_MAX];
+  int mode[ZB_MAX];
+};
+
+template <int LG, bool TWO>
+__global__ void __launch_bounds__(ZfftShape<LG>::T) k_zfft(ZBatch zb, long Ng, double c1, double c2,
+                                                           const double* __restrict__ twr_g,
+                                                           const double* __restrict__ twi_g,
+                                                           const double* __restrict__ betad) {
+  using S = ZfftShape<LG>;
+  constexpr int NZ = S::NZ, N1 = S::N1, N2 = S::N2, P = S::P, T = S::T, RS = S::RS;
+  __shared__ double lr[N1 * RS], li[N1 * RS], wr[NZ], wi[NZ];
+  const int e = blockIdx.y;
+  const int mode = zb.mode[e];
+  const double* __restrict__ in = zb.in[e];
+  const double* __restrict__ in2 = zb.in2[e];
+  double* __restrict__ out = zb.out[e];
+  const int t = threadIdx.x;
+  for (int m = t; m < NZ; m += T) {   // W_Nz^m for m = 0..Nz-1 from the half table
+    const bool lo = m <= NZ / 2;
+    const int mm = lo ? m : NZ - m;
+    wr[m] = twr_g[mm];
+    wi[m] = lo ? twi_g[mm] : -twi_g[mm];
   }
-  const long n0 = (long)blockIdx.x * NB;
-  const int nb = (int)min((long)NB, Ng - n0);
-  // all loads of the tile first (independent), then the LDS writes
-  double v[ZFFT_PER];
+  const int c = t % P, row = t / P;
+  const long n0 = (long)blockIdx.x * (2 * P);
+  const long na = n0 + c, nb = n0 + P + c;
+  const bool va = na < Ng, vb = nb < Ng;
+  const long ia = va ? na : 0, ib = vb ? nb : 0;   // clamped addresses, values masked after the load
+  // the N1 input planes row + N2 q of both columns (coalesced along the nodes)
+  double xr[N1], xi[N1];
 #pragma unroll
-  for (int q = 0; q < ZFFT_PER; ++q) {
-    const int t = threadIdx.x + 256 * q;
-    const int z = t >> lgnb, node = t & nbm;
-    const int nn = node < nb ? node : 0;
-    const long o = (long)z * Ng + n0 + nn;
-    v[q] = in2 ? c1 * in[o] + c2 * in2[o] : in[o];
-    if (node >= nb) v[q] = 0.0;
+  for (int q = 0; q < N1; ++q) {
+    const long o = (long)(row + N2 * q) * Ng;
+    double u = in[o + ia], v = in[o + ib];
+    if (TWO) {
+      u = c1 * u + c2 * in2[o + ia];
+      v = c1 * v + c2 * in2[o + ib];
+    }
+    xr[q] = va ? u : 0.0;
+    xi[q] = vb ? v : 0.0;
   }
+  __syncthreads();   // twiddle table
+
   if (mode == 0 || mode == 3) {
+    // first half: n2 = row, transform over n1
+    zdft_reg<N1, NZ, false>(xr, xi, wr, wi);
 #pragma unroll
-    for (int q = 0; q < ZFFT_PER; ++q) {   // real samples into bit-reversed complex positions
-      const int t = threadIdx.x + 256 * q;
-      const int z = t >> lgnb, node = t & nbm;
-      const int a = (zfft_rev(z, lg) << lgnb) + node;
-      re[a] = v[q];
-      im[a] = 0.0;
+    for (int k1 = 0; k1 < N1; ++k1) {
+      const int tw = row * k1;
+      const double cr = wr[tw], ci = wi[tw];
+      lr[k1 * RS + row * P + c] = cr * xr[k1] - ci * xi[k1];
+      li[k1 * RS + row * P + c] = cr * xi[k1] + ci * xr[k1];
     }
     __syncthreads();
-    zfft_pass(re, im, lg, lgnb, twr, twi, 1.0);
-    if (mode == 0) {
-      const double sc = 1.0 / Nz;
+    // second half: k1 = row + N2 r, transform over n2
 #pragma unroll
-      for (int q = 0; q < ZFFT_PER; ++q) {
-        const int t = threadIdx.x + 256 * q;
-        const int p = t >> lgnb, node = t & nbm;
-        if (node >= nb) continue;
-        double w;
-        if (p == 0) w = re[node];
-        else if (p == 1) w = re[((Nz / 2) << lgnb) + node];
-        else w = (p & 1) ? im[((p >> 1) << lgnb) + node] : re[((p >> 1) << lgnb) + node];
-        out[(long)p * Ng + n0 + node] = sc * w;
+    for (int r = 0; r < N1 / N2; ++r) {
+      const int k1 = row + N2 * r;
+      double yr[N2], yi[N2];
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) {
+        yr[n2] = lr[k1 * RS + n2 * P + c];
+        yi[n2] = li[k1 * RS + n2 * P + c];
+      }
+      zdft_reg<N2, NZ, false>(yr, yi, wr, wi);
+      if (mode == 3) {   // i beta(k) / Nz, then back over k2 and the conjugate twiddle
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+          const double b = zbeta<NZ>(k1 + N1 * k2, betad) * (1.0 / NZ);
+          const double zr = yr[k2];
+          yr[k2] = -b * yi[k2];
+          yi[k2] = b * zr;
+        }
+        zdft_reg<N2, NZ, true>(yr, yi, wr, wi);
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) {
+          const int tw = n2 * k1;
+          const double cr = wr[tw], ci = -wi[tw];
+          const double ur = cr * yr[n2] - ci * yi[n2], ui = cr * yi[n2] + ci * yr[n2];
+          yr[n2] = ur;
+          yi[n2] = ui;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < N2; ++j) {   // same LDS slots as read (k2 slots for mode 0)
+        lr[k1 * RS + j * P + c] = yr[j];
+        li[k1 * RS + j * P + c] = yi[j];
+      }
+    }
+    __syncthreads();
+    if (mode == 0) {
+      // packed output plane p = row + N2 q, separated spectra of columns a (real) and b (imag)
+      constexpr double sc = 1.0 / NZ;
+#pragma unroll
+      for (int q = 0; q < N1; ++q) {
+        const int p = row + N2 * q;
+        const int k = p == 0 ? 0 : (p == 1 ? NZ / 2 : (p >> 1));
+        const int km = (NZ - k) & (NZ - 1);
+        const int sk = (k % N1) * RS + (k / N1) * P + c, sm = (km % N1) * RS + (km / N1) * P + c;
+        const double zr = lr[sk], zi = li[sk], mr = lr[sm], mi = li[sm];
+        const bool imag = p >= 2 && (p & 1);
+        const double oa = imag ? 0.5 * (zi - mi) : 0.5 * (zr + mr);
+        const double ob = imag ? 0.5 * (mr - zr) : 0.5 * (zi + mi);
+        if (va) out[(long)p * Ng + na] = sc * oa;
+        if (vb) out[(long)p * Ng + nb] = sc * ob;
       }
       return;
     }
-    // mode 3: c_k -> i beta_k c_k / Nz (k = 0 and the Nyquist mode -> 0), then the inverse below
-    for (int t = threadIdx.x; t < ((Nz / 2 + 1) << lgnb); t += 256) {
-      const int k = t >> lgnb, node = t & nbm;
-      const int a = (k << lgnb) + node;
-      if (k == 0 || k == Nz / 2) {
-        re[a] = 0.0;
-        im[a] = 0.0;
-      } else {
-        const double b = betad[2 * k] / Nz;
-        const double cr = re[a], ci = im[a];
-        re[a] = -b * ci;
-        im[a] = b * cr;
-      }
-    }
-    __syncthreads();
   } else {
-    // packed spectrum (modes 1, 2) -> c_k, k = 0..Nz/2, at plain positions
+    // modes 1, 2: packed planes staged in LDS (plane p of column a at lr[p P + c], of b at li),
+    // then Z_k = C_a(k) + i C_b(k) with the Hermitian completion for k > Nz/2
 #pragma unroll
-    for (int q = 0; q < ZFFT_PER; ++q) {
-      const int t = threadIdx.x + 256 * q;
-      const int p = t >> lgnb, node = t & nbm;
-      const int k = (p < 2) ? (p == 0 ? 0 : Nz / 2) : (p >> 1);
-      const bool imag = p >= 2 && (p & 1);
-      double w = v[q];
-      if (mode == 2) {   // i beta_k c_k: the real part gets -beta Im, the imaginary part beta Re
-        const double b = (k == 0 || k == Nz / 2) ? 0.0 : betad[2 * k];
-        w *= b;
+    for (int q = 0; q < N1; ++q) {
+      lr[(row + N2 * q) * P + c] = xr[q];
+      li[(row + N2 * q) * P + c] = xi[q];
+    }
+    __syncthreads();
+    double zr_[N1], zi_[N1];   // Z for k1 = row + N2 r, k2: index r N2 + k2
+#pragma unroll
+    for (int r = 0; r < N1 / N2; ++r) {
+      const int k1 = row + N2 * r;
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const int k = k1 + N1 * k2;
+        const bool lo = k <= NZ / 2;
+        const int kk = lo ? k : NZ - k;
+        const bool cplx = kk != 0 && kk != NZ / 2;
+        const int pre = kk == 0 ? 0 : (kk == NZ / 2 ? 1 : 2 * kk), pim = cplx ? 2 * kk + 1 : 0;
+        const double sg = lo ? 1.0 : -1.0;
+        const double Ar = lr[pre * P + c], Br = li[pre * P + c];
+        const double Ai = cplx ? sg * lr[pim * P + c] : 0.0, Bi = cplx ? sg * li[pim * P + c] : 0.0;
+        double zr = Ar - Bi, zi = Ai + Br;
+        if (mode == 2) {
+          const double b = zbeta<NZ>(k, betad);
+          const double tr = zr;
+          zr = -b * zi;
+          zi = b * tr;
+        }
+        zr_[r * N2 + k2] = zr;
+        zi_[r * N2 + k2] = zi;
       }
-      const int a = (k << lgnb) + node;
-      if (mode == 2) {
-        if (imag) re[a] = -w;
-        else im[a] = w;
-        if (p < 2) re[a] = 0.0;     // no imaginary input for k = 0, Nyquist
-      } else {
-        if (imag) im[a] = w;
-        else re[a] = w;
-        if (p < 2) im[a] = 0.0;
+    }
+    __syncthreads();   // staging read before the slots are reused
+#pragma unroll
+    for (int r = 0; r < N1 / N2; ++r) {
+      const int k1 = row + N2 * r;
+      double yr[N2], yi[N2];
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        yr[k2] = zr_[r * N2 + k2];
+        yi[k2] = zi_[r * N2 + k2];
+      }
+      zdft_reg<N2, NZ, true>(yr, yi, wr, wi);
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) {
+        const int tw = n2 * k1;
+        const double cr = wr[tw], ci = -wi[tw];
+        lr[k1 * RS + n2 * P + c] = cr * yr[n2] - ci * yi[n2];
+        li[k1 * RS + n2 * P + c] = cr * yi[n2] + ci * yr[n2];
       }
     }
     __syncthreads();
   }
-  // Hermitian completion c_{Nz-k} = conj(c_k), bit-reversal permutation (pair swaps), inverse
-  // transform (sign +), real part out
-  for (int t = threadIdx.x; t < ((Nz / 2 - 1) << lgnb); t += 256) {
-    const int k = 1 + (t >> lgnb), node = t & nbm;
-    re[((Nz - k) << lgnb) + node] = re[(k << lgnb) + node];
-    im[((Nz - k) << lgnb) + node] = -im[(k << lgnb) + node];
-  }
-  __syncthreads();
+  // last half of the inverse: n2 = row, transform over k1, z_{n2 + N2 n1} = f_a + i f_b
 #pragma unroll
-  for (int q = 0; q < ZFFT_PER; ++q) {
-    const int t = threadIdx.x + 256 * q;
-    const int z = t >> lgnb, node = t & nbm;
-    const int r = zfft_rev(z, lg);
-    if (z < r) {
-      const int a = (z << lgnb) + node, b = (r << lgnb) + node;
-      const double ar = re[a], ai = im[a];
-      re[a] = re[b];
-      im[a] = im[b];
-      re[b] = ar;
-      im[b] = ai;
-    }
+  for (int k1 = 0; k1 < N1; ++k1) {
+    xr[k1] = lr[k1 * RS + row * P + c];
+    xi[k1] = li[k1 * RS + row * P + c];
   }
-  __syncthreads();
-  zfft_pass(re, im, lg, lgnb, twr, twi, -1.0);
+  zdft_reg<N1, NZ, true>(xr, xi, wr, wi);
 #pragma unroll
-  for (int q = 0; q < ZFFT_PER; ++q) {
-    const int t = threadIdx.x + 256 * q;
-    const int z = t >> lgnb, node = t & nbm;
-    if (node < nb) out[(long)z * Ng + n0 + node] = re[(z << lgnb) + node];
+  for (int n1 = 0; n1 < N1; ++n1) {
+    const long z = row + N2 * n1;
+    if (va) out[z * Ng + na] = xr[n1];
+    if (vb) out[z * Ng + nb] = xi[n1];
   }
+}
+
+template <int LG>
+static void zfft_launch(pfd_ctx* c, const ZBatch& zb, int n, bool two, double c1, double c2) {
+  using S = ZfftShape<LG>;
+  const dim3 grid((unsigned)((c->Ng + 2 * S::P - 1) / (2 * S::P)), (unsigned)n);
+  if (two)
+    LAUNCH(PFD_PROF_ZFFT, (k_zfft<LG, true>), grid, dim3(S::T), 0, c->stream, zb, c->Ng, c1, c2, c->twr, c->twi,
+           c->d_betad);
+  else
+    LAUNCH(PFD_PROF_ZFFT, (k_zfft<LG, false>), grid, dim3(S::T), 0, c->stream, zb, c->Ng, c1, c2, c->twr, c->twi,
+           c->d_betad);
 }
 
 // out = W in  (or W (c1 in + c2 in2)) along z for every node: one GEMM, M = K = Nz, N = Ng
 static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, const double* in2 = nullptr,
                    double c1 = 1.0, double c2 = 0.0);
+// n independent z transforms (n <= ZB_MAX), each W[i] in[i] (or W[i] (c1 in[i] + c2 in2[i]));
+// in2 is given for all of them or for none.  The FFT runs them as one launch.
+static void ztrans_n(pfd_ctx* c, int n, const double* const* W, const double* const* in, double* const* out,
+                     const double* const* in2 = nullptr, double c1 = 1.0, double c2 = 0.0) {
+  if (c->gemm_cfg[PFD_GS_Z][1] == PFD_ZFFT_CFG && c->zlg > 0 && n >= 1 && n <= ZB_MAX) {
+    ZBatch zb{};
+    for (int i = 0; i < n; ++i) {
+      zb.mode[i] = (W[i] == c->Wf) ? 0 : (W[i] == c->Wi) ? 1 : (W[i] == c->Wd) ? 2 : 3;
+      zb.in[i] = in[i];
+      zb.in2[i] = in2 ? in2[i] : in[i];
+      zb.out[i] = out[i];
+    }
+    const bool two = in2 != nullptr;
+    switch (c->zlg) {
+      case 2: zfft_launch<2>(c, zb, n, two, c1, c2); return;
+      case 3: zfft_launch<3>(c, zb, n, two, c1, c2); return;
+      case 4: zfft_launch<4>(c, zb, n, two, c1, c2); return;
+      case 5: zfft_launch<5>(c, zb, n, two, c1, c2); return;
+      case 6: zfft_launch<6>(c, zb, n, two, c1, c2); return;
+      case 7: zfft_launch<7>(c, zb, n, two, c1, c2); return;
+      case 8: zfft_launch<8>(c, zb, n, two, c1, c2); return;
+      default: break;   // not reached: zlg is set for 4 <= Nz <= 256 only
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    const double* b2 = in2 ? in2[i] : nullptr;
+    if (!gemm_launch<double, double, double, 0>(c, c->gemm_cfg[PFD_GS_Z][1], PFD_PROF_ZFFT, 1, W[i], 0L, in[i], 0L,
+                                                c->planes, (int)c->Ng, c->planes, out[i], 0L, nullptr, nullptr,
+                                                nullptr, nullptr, b2, c1, c2))
+      gemm_launch<double, double, double, 0>(c, 0, PFD_PROF_ZFFT, 1, W[i], 0L, in[i], 0L, c->planes, (int)c->Ng,
+                                             c->planes, out[i], 0L, nullptr, nullptr, nullptr, nullptr, b2, c1, c2);
+  }
+}
 static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, const double* in2, double c1,
                    double c2) {
-  if (c->gemm_cfg[PFD_GS_Z][1] == PFD_ZFFT_CFG && c->zlg > 0) {   // the FFT instead of the DFT GEMM
-    const int mode = (W == c->Wf) ? 0 : (W == c->Wi) ? 1 : (W == c->Wd) ? 2 : 3;
-    const int NB = ZFFT_PTS / c->planes;
-    const size_t lds = sizeof(double) * (2 * ZFFT_PTS + 2 * 1025);
-    LAUNCH(PFD_PROF_ZFFT, k_zfft, dim3((unsigned)((c->Ng + NB - 1) / NB)), dim3(256), lds, c->stream, mode, c->zlg,
-           c->Ng, in, in2, c1, c2, c->twr, c->twi, c->d_betad, out);
-    return;
-  }
-  if (!gemm_launch<double, double, double, 0>(c, c->gemm_cfg[PFD_GS_Z][1], PFD_PROF_ZFFT, 1, W, 0L, in, 0L,
-                                              c->planes, (int)c->Ng, c->planes, out, 0L, nullptr, nullptr, nullptr,
-                                              nullptr, in2, c1, c2))
-    gemm_launch<double, double, double, 0>(c, 0, PFD_PROF_ZFFT, 1, W, 0L, in, 0L, c->planes, (int)c->Ng, c->planes,
-                                           out, 0L, nullptr, nullptr, nullptr, nullptr, in2, c1, c2);
+  ztrans_n(c, 1, &W, &in, &out, in2 ? &in2 : nullptr, c1, c2);
 }
 
 // spectral copies of the Dirichlet sources that changed since the last step (reading R-dir3d)
@@ -2455,27 +2588,46 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
   double* const* S = c->src;
   double **ph = c->ph, **sp = c->sp, **dz = c->dz, **Lb = c->Lb;
   refresh_spectral_sources(c);
+  {
+    // z-derivatives of the extrapolated V, phi (and u, P) in one launch: dz[0..5]
+    const double* Ws[6] = {c->Wd, c->Wd, c->Wd, c->Wd, c->Wd, c->Wd};
+    const double* ins[6] = {SPEC(F_V, 0), SPEC(F_PHI, 0), nullptr, nullptr, nullptr, nullptr};
+    const double* olds[6] = {SPEC(F_V, -1), SPEC(F_PHI, -1), nullptr, nullptr, nullptr, nullptr};
+    if (!equilibrium) {
+      const int fs[4] = {F_UX, F_UY, F_UZ, F_P};
+      for (int i = 0; i < 4; ++i) {
+        ins[2 + i] = SPEC(fs[i], 0);
+        olds[2 + i] = SPEC(fs[i], -1);
+      }
+    }
+    ztrans_n(c, equilibrium ? 2 : 6, Ws, ins, dz, olds, P.cs_n, P.cs_o);
+  }
   // ---- V (eq. 74)
-  ztrans(c, c->Wd, SPEC(F_V, 0), dz[0], SPEC(F_V, -1), P.cs_n, P.cs_o);
   LAUNCH(PFD_PROF_ELEM, k_V_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), FLD(F_V, 0), FLD(F_V, -1),
          Lb[0]);
   LAUNCH(PFD_PROF_NODAL, k_V_rhs3, ng, nb, 0, st, g, P, Lb[0], c->Mdiag, S[PFD_SRC_FV], FLD(F_PHI, 0),
          FLD(F_PHI, -1), dz[0], ph[0], ph[1]);
-  ztrans(c, c->Wf, ph[0], sp[0]);
-  ztrans(c, c->Wf, ph[1], sp[1]);
+  const double* Wff[5] = {c->Wf, c->Wf, c->Wf, c->Wf, c->Wf};
+  const double* Wfi[3] = {c->Wi, c->Wi, c->Wi};
+  const double* Wid[2] = {c->Wi, c->Wd};
+  const double* ph01[2] = {ph[0], ph[1]};
+  ztrans_n(c, 2, Wff, ph01, sp);
   LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_V], sp[0], sp[1], 0, 1.0 / P.eps0,
          (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_VD], H(F_V, 0), H(F_V, -1),
          c->b[0], c->r, c->spec[F_V][nw]);
   solve(c, PFD_FAM_V, c->b[0], c->spec[F_V][nw], 1, 0, r0);
-  ztrans(c, c->Wi, c->spec[F_V][nw], c->fld[F_V][nw]);
-  // ---- E (eq. 78): E_x, E_y by plane-wise projection, E_z = i beta V (reading R-Ez)
-  ztrans(c, c->Wd, c->spec[F_V][nw], c->fld[F_EZ][0]);
+  {
+    // V and E_z = i beta V (reading R-Ez) from the new spectrum in one launch
+    const double* ins[2] = {c->spec[F_V][nw], c->spec[F_V][nw]};
+    double* outs[2] = {c->fld[F_V][nw], c->fld[F_EZ][0]};
+    ztrans_n(c, 2, Wid, ins, outs);
+  }
+  // ---- E (eq. 78): E_x, E_y by plane-wise projection
   LAUNCH(PFD_PROF_ELEM, k_E_elem, eg, eb, 0, st, g, c->fld[F_V][nw], Lb[0], Lb[1]);
   LAUNCH(PFD_PROF_NODAL, k_E_nodal, ng, nb, 0, st, g, Lb[0], Lb[1], c->Mdiag, (const double*)c->fld[F_EZ][0],
          c->fld[F_EX][0], c->fld[F_EY][0], c->fld[F_E2][0]);
   const double* E2 = c->fld[F_E2][0];
   // ---- psi (eq. 75)
-  ztrans(c, c->Wd, SPEC(F_PHI, 0), dz[1], SPEC(F_PHI, -1), P.cs_n, P.cs_o);
   const double* uxn = equilibrium ? c->zero_buf : FLD(F_UX, 0);
   const double* uxo = equilibrium ? c->zero_buf : FLD(F_UX, -1);
   const double* uyn = equilibrium ? c->zero_buf : FLD(F_UY, 0);
@@ -2486,8 +2638,7 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
          S[PFD_SRC_G], uzn, uzo, (const double*)dz[1], Lb[0]);
   LAUNCH(PFD_PROF_NODAL, k_psi_rhs3, ng, nb, 0, st, g, P, Lb[0], c->Mdiag, c->bm_open, c->bm_wall, S[PFD_SRC_G1],
          S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), E2, ph[0], ph[1], c->U, c->Q2);
-  ztrans(c, c->Wf, ph[0], sp[0]);
-  ztrans(c, c->Wf, ph[1], sp[1]);  // (M Q2)_hat, kept for Phi_hat below
+  ztrans_n(c, 2, Wff, ph01, sp);  // sp[1] = (M Q2)_hat, kept for Phi_hat below
   LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_PSI], sp[0], sp[1], 1, 1.0,
          (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, (const double*)nullptr, H(F_PSI, 0),
          H(F_PSI, -1), c->b[0], c->r, c->spec[F_PSI][nw]);
@@ -2500,7 +2651,12 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
          1.0, (const double*)c->spec[F_PSI][nw], -1.0, c->Mdiag, c->d_beta2, c->d_betad, (const double*)nullptr,
          H(F_PHI, 0), H(F_PHI, -1), c->b[0], c->r, c->spec[F_PHI][nw]);
   solve(c, PFD_FAM_PHI, c->b[0], c->spec[F_PHI][nw], 1, 0, r0);
-  ztrans(c, c->Wi, c->spec[F_PHI][nw], c->fld[F_PHI][nw]);
+  {
+    // phi, and its z-derivative for the momentum terms
+    const double* ins[2] = {c->spec[F_PHI][nw], c->spec[F_PHI][nw]};
+    double* outs[2] = {c->fld[F_PHI][nw], dz[0]};
+    ztrans_n(c, equilibrium ? 1 : 2, Wid, ins, outs);
+  }
   if (equilibrium) {
     for (int f : {F_UX, F_UY, F_UZ, F_P}) {
       LAUNCH(PFD_PROF_OTHER, k_fill, ng, nb, 0, st, tot, c->fld[f][nw], 0.0);
@@ -2508,14 +2664,9 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
     }
   } else {
     // ---- momentum terms (eq. 49 and the G, Y, K, J, L of Sec. 3.2.2)
-    ztrans(c, c->Wd, c->spec[F_PHI][nw], dz[0]);
     LAUNCH(PFD_PROF_NODAL, k_Phi_hat3, ng, nb, 0, st, g, P, c->spec[F_PSI][nw], c->spec[F_PHI][nw], sp[1],
            c->Mdiag, sp[2]);
-    ztrans(c, c->Wd, sp[2], dz[1]);
-    ztrans(c, c->Wd, SPEC(F_UX, 0), dz[2], SPEC(F_UX, -1), P.cs_n, P.cs_o);
-    ztrans(c, c->Wd, SPEC(F_UY, 0), dz[3], SPEC(F_UY, -1), P.cs_n, P.cs_o);
-    ztrans(c, c->Wd, SPEC(F_UZ, 0), dz[4], SPEC(F_UZ, -1), P.cs_n, P.cs_o);
-    ztrans(c, c->Wd, SPEC(F_P, 0), dz[5], SPEC(F_P, -1), P.cs_n, P.cs_o);
+    ztrans(c, c->Wd, sp[2], dz[1]);   // dz[2..5] were taken at the start of the step
     Mom3 z{FLD(F_UZ, 0), FLD(F_UZ, -1), dz[0], dz[1], dz[2], dz[3], dz[4], dz[5], S[PFD_SRC_FZ],
            Lb[3], Lb[4], Lb[5], Lb[6]};
     LAUNCH(PFD_PROF_ELEM, k_mom_elem<true>, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
@@ -2524,20 +2675,25 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
     // ---- P (eq. 77)
     LAUNCH(PFD_PROF_NODAL, k_P_rhs3, ng, nb, 0, st, g, P, Lb[0], Lb[3], S[PFD_SRC_WX], S[PFD_SRC_WY], ph[0],
            ph[1]);
-    ztrans(c, c->Wf, ph[0], sp[0]);
-    ztrans(c, c->Wf, ph[1], sp[1]);
+    ztrans_n(c, 2, Wff, ph01, sp);
     LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_P], sp[0], sp[1], 0, 1.0,
            (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_F2], H(F_P, 0),
            H(F_P, -1), c->b[0], c->r, c->spec[F_P][nw]);
     solve(c, PFD_FAM_P, c->b[0], c->spec[F_P][nw], 1, 0, r0);
-    ztrans(c, c->Wi, c->spec[F_P][nw], c->fld[F_P][nw]);
+    {
+      const double* ins[2] = {c->spec[F_P][nw], c->spec[F_P][nw]};
+      double* outs[2] = {c->fld[F_P][nw], dz[0]};
+      ztrans_n(c, 2, Wid, ins, outs);
+    }
     // ---- u (eq. 78)
-    ztrans(c, c->Wd, c->spec[F_P][nw], dz[0]);
     LAUNCH(PFD_PROF_ELEM, k_gradP_elem, eg, eb, 0, st, g, P, c->fld[F_P][nw], (const double*)dz[0], Lb[1], Lb[2],
            Lb[4]);
     LAUNCH(PFD_PROF_NODAL, k_u_rhs3, ng, nb, 0, st, g, Lb[1], Lb[5], Lb[2], Lb[6], Lb[4], c->bm_open,
            S[PFD_SRC_F1X], S[PFD_SRC_F1Y], S[PFD_SRC_F1Z], ph[0], ph[1], ph[2], ph[3], ph[4]);
-    for (int i = 0; i < 5; ++i) ztrans(c, c->Wf, ph[i], sp[i]);
+    {
+      const double* ins[5] = {ph[0], ph[1], ph[2], ph[3], ph[4]};
+      ztrans_n(c, 5, Wff, ins, sp);
+    }
     const int uf[3] = {F_UX, F_UY, F_UZ};
     const int ws[3] = {PFD_SRC_WX, PFD_SRC_WY, PFD_SRC_WZ};
     const double* Bs[3] = {sp[1], sp[3], nullptr};
@@ -2547,7 +2703,11 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
              (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[ws[i]], H(uf[i], 0),
              H(uf[i], -1), c->b[i], c->r + i * tot, c->spec[uf[i]][nw]);
     solve(c, PFD_FAM_U, c->b[0], c->spec[F_UX][nw], 3, 0, warm ? nullptr : c->r);   // one stack of 3
-    for (int i = 0; i < 3; ++i) ztrans(c, c->Wi, c->spec[uf[i]][nw], c->fld[uf[i]][nw]);
+    {
+      const double* ins[3] = {c->spec[F_UX][nw], c->spec[F_UY][nw], c->spec[F_UZ][nw]};
+      double* outs[3] = {c->fld[F_UX][nw], c->fld[F_UY][nw], c->fld[F_UZ][nw]};
+      ztrans_n(c, 3, Wfi, ins, outs);
+    }
   }
   LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
   if (!equilibrium) LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot, c->fld[F_UX][nw], c->d_status);
@@ -2573,9 +2733,11 @@ hipError_t potential_iteration_3d(pfd_ctx* c, const double* Vin, double* Vout) {
   LAUNCH(PFD_PROF_ELEM, k_V_elem, eg, eb, 0, st, g, P, phn, phn, Vin, Vin, c->Lb[0]);
   LAUNCH(PFD_PROF_NODAL, k_V_rhs3, ng, nb, 0, st, g, P, c->Lb[0], c->Mdiag, c->src[PFD_SRC_FV], phn, phn, dz[0],
          ph[0], ph[1]);
-  ztrans(c, c->Wf, ph[0], sp[0]);
-  ztrans(c, c->Wf, ph[1], sp[1]);
-  if (warm) ztrans(c, c->Wf, Vin, sp[2]);
+  {
+    const double* Wff[3] = {c->Wf, c->Wf, c->Wf};
+    const double* ins[3] = {ph[0], ph[1], Vin};
+    ztrans_n(c, warm ? 3 : 2, Wff, ins, sp);
+  }
   double* Vh = c->spec[F_V][1 - c->cur];
   LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_V], sp[0], sp[1], 0, 1.0 / P.eps0,
          (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_VD],
