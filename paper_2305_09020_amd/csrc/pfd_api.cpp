@@ -443,6 +443,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   Geo& g = c->geo;
   g.K = K; g.n = K + 1; g.nq = c->nq; g.nx = m.nx; g.ny = m.ny; g.Nx = c->Nx; g.Ny = c->Ny;
   g.periodic = per ? 1 : 0; g.planes = c->planes; g.Ng = c->Ng; g.Nl = c->Nl;
+  g.ppw = std::max(1, std::min(c->planes, 256 / c->nq));
   g.hx = c->d_hx; g.hy = c->d_hy; g.w = c->d_w; g.D = c->d_D;
   for (int s = 0; s < 4; ++s) {
     g.bm_side[s] = c->bm_side[s];

@@ -46,6 +46,7 @@ struct Family {
 // geometry passed to element / nodal kernels by value
 struct Geo {
   int K, n, nq, nx, ny, Nx, Ny, periodic, planes;
+  int ppw;                          // planes per element work-group (ppw nq <= 256 when nq <= 256)
   long Ng, Nl;
   const double *hx, *hy, *w, *D;    // device
   const double *bm_side[4];         // per-side boundary mass (device, Ng)

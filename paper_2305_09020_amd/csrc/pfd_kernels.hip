@@ -61,42 +61,63 @@ __device__ __forceinline__ void load_gll(const Geo& g, ElemLDS& s) {
   for (int i = threadIdx.x; i < g.n; i += blockDim.x) s.w[i] = g.w[i];
 }
 
-// d/dx at local (a,b) of an LDS element array f[b*n + p]
-__device__ __forceinline__ double ddx(const ElemLDS& s, int n, int a, int b, const double* f, double sx) {
-  double acc = 0.0;
-  for (int p = 0; p < n; ++p) acc += s.D[a * n + p] * f[b * n + p];
-  return sx * acc;
+// x- and y-derivatives of F element arrays f[b*n + p] at local (a,b), in one pass over row b
+// and column a: the D entries are read once for all arrays, each sum runs over p = 0..n-1
+template <int F>
+__device__ __forceinline__ void grad2(const ElemLDS& s, int n, int a, int b, const double* const (&f)[F], double sx,
+                                      double sy, double (&dx)[F], double (&dy)[F]) {
+#pragma unroll
+  for (int i = 0; i < F; ++i) dx[i] = dy[i] = 0.0;
+  for (int p = 0; p < n; ++p) {
+    const double da = s.D[a * n + p], db = s.D[b * n + p];
+#pragma unroll
+    for (int i = 0; i < F; ++i) {
+      dx[i] += da * f[i][b * n + p];
+      dy[i] += db * f[i][p * n + a];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < F; ++i) {
+    dx[i] *= sx;
+    dy[i] *= sy;
+  }
 }
-__device__ __forceinline__ double ddy(const ElemLDS& s, int n, int a, int b, const double* f, double sy) {
-  double acc = 0.0;
-  for (int p = 0; p < n; ++p) acc += s.D[b * n + p] * f[p * n + a];
-  return sy * acc;
-}
-// x-part of the weak divergence: sum_p D[p][a] gx[b*n+p]  (gx pre-multiplied by w_p)
-__device__ __forceinline__ double wdx(const ElemLDS& s, int n, int a, int b, const double* gx) {
-  double acc = 0.0;
-  for (int p = 0; p < n; ++p) acc += s.D[p * n + a] * gx[b * n + p];
-  return acc;
-}
-__device__ __forceinline__ double wdy(const ElemLDS& s, int n, int a, int b, const double* gy) {
-  double acc = 0.0;
-  for (int p = 0; p < n; ++p) acc += s.D[p * n + b] * gy[p * n + a];
-  return acc;
+// x- and y-parts of the weak divergence in one pass: sum_p D[p][a] gx[b*n+p] and
+// sum_p D[p][b] gy[p*n+a] (gx, gy pre-multiplied by the weights)
+__device__ __forceinline__ void wdxy(const ElemLDS& s, int n, int a, int b, const double* gx, const double* gy,
+                                     double& ox, double& oy) {
+  double ax = 0.0, ay = 0.0;
+  for (int p = 0; p < n; ++p) {
+    ax += s.D[p * n + a] * gx[b * n + p];
+    ay += s.D[p * n + b] * gy[p * n + a];
+  }
+  ox = ax;
+  oy = ay;
 }
 
+// A work-group takes one element on g.ppw consecutive planes (ppw nq <= 256 threads, so the
+// lanes are not left idle at small orders); thread = (sub-plane, local node t).  Element arrays
+// in LDS are declared with ELEM_ARRAY and point at the sub-plane's nq-slice.
+#define ELEM_LDS_N ((PFD_KMAX + 1) * (PFD_KMAX + 1) > 256 ? (PFD_KMAX + 1) * (PFD_KMAX + 1) : 256)
 #define ELEM_PROLOGUE                                                    \
-  const int e = blockIdx.x, pl = blockIdx.y;                             \
+  const int e = blockIdx.x;                                              \
   const int ex = e % g.nx, ey = e / g.nx;                                \
-  const int n = g.n, t = threadIdx.x;                                    \
-  const bool act = t < g.nq;                                             \
+  const int n = g.n, nq = g.nq;                                          \
+  const int sub = (int)threadIdx.x / nq, t = (int)threadIdx.x - sub * nq; \
+  const int pl = blockIdx.y * g.ppw + sub;                               \
+  const bool act = sub < g.ppw && pl < g.planes;                         \
+  const int so = act ? sub * nq : 0;                                     \
   const int a = act ? t % n : 0, b = act ? t / n : 0;                    \
   const double hx = g.hx[ex], hy = g.hy[ey];                             \
   const double sx = 2.0 / hx, sy = 2.0 / hy;                             \
-  const long pofs = (long)pl * g.Ng;                                     \
+  const long pofs = (long)(act ? pl : 0) * g.Ng;                         \
   const int gi = gidx(g, ex, ey, a, b);                                  \
-  const long lofs = ((long)pl * g.nx * g.ny + e) * g.nq + t;             \
+  const long lofs = ((long)(act ? pl : 0) * g.nx * g.ny + e) * nq + t;   \
   __shared__ ElemLDS s;                                                  \
   load_gll(g, s);
+#define ELEM_ARRAY(name)                 \
+  __shared__ double name##_all[ELEM_LDS_N]; \
+  double* const name = name##_all + so;
 
 // ------------------------------------------------------------------ DSS (gather-sum)
 // sum of the element-local contributions at global node (ix, iy) of plane pl
@@ -198,9 +219,9 @@ __device__ __forceinline__ void rhs_out(const Geo& g, const Par& P, const Lift& 
 __global__ void __launch_bounds__(WG) k_V_elem(Geo g, Par P, const double* phn, const double* pho,
                                                const double* Vn, const double* Vo, double* L0) {
   ELEM_PROLOGUE
-  __shared__ double sV[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sgx[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sgy[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  ELEM_ARRAY(sV)
+  ELEM_ARRAY(sgx)
+  ELEM_ARRAY(sgy)
   double phs = 0.0;
   if (act) {
     sV[t] = P.cs_n * Vn[pofs + gi] + P.cs_o * Vo[pofs + gi];
@@ -209,11 +230,18 @@ __global__ void __launch_bounds__(WG) k_V_elem(Geo g, Par P, const double* phn, 
   __syncthreads();
   if (act) {
     double r = eps_of(P, phs) - P.eps0;
-    sgx[t] = s.w[a] * r * ddx(s, n, a, b, sV, sx);
-    sgy[t] = s.w[b] * r * ddy(s, n, a, b, sV, sy);
+    const double* f[1] = {sV};
+    double dx[1], dy[1];
+    grad2<1>(s, n, a, b, f, sx, sy, dx, dy);
+    sgx[t] = s.w[a] * r * dx[0];
+    sgy[t] = s.w[b] * r * dy[0];
   }
   __syncthreads();
-  if (act) L0[lofs] = -(0.5 * hy * s.w[b] * wdx(s, n, a, b, sgx) + 0.5 * hx * s.w[a] * wdy(s, n, a, b, sgy));
+  if (act) {
+    double wx, wy;
+    wdxy(s, n, a, b, sgx, sgy, wx, wy);
+    L0[lofs] = -(0.5 * hy * s.w[b] * wx + 0.5 * hx * s.w[a] * wy);
+  }
 }
 
 // b = (DSS(L0) - M f_V)/eps0, Dirichlet values from VD
@@ -227,13 +255,16 @@ __global__ void k_V_rhs(Geo g, Par P, Lift L, const double* L0, const double* Md
 // =================================================================== stage E (eq. 55)
 __global__ void __launch_bounds__(WG) k_E_elem(Geo g, const double* V, double* L0, double* L1) {
   ELEM_PROLOGUE
-  __shared__ double sV[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  ELEM_ARRAY(sV)
   if (act) sV[t] = V[pofs + gi];
   __syncthreads();
   if (act) {
     double wq = 0.25 * hx * hy * s.w[a] * s.w[b];
-    L0[lofs] = wq * ddx(s, n, a, b, sV, sx);
-    L1[lofs] = wq * ddy(s, n, a, b, sV, sy);
+    const double* f[1] = {sV};
+    double dx[1], dy[1];
+    grad2<1>(s, n, a, b, f, sx, sy, dx, dy);
+    L0[lofs] = wq * dx[0];
+    L1[lofs] = wq * dy[0];
   }
 }
 
@@ -256,10 +287,10 @@ __global__ void __launch_bounds__(WG) k_psi_elem(Geo g, Par P, const double* phn
                                                  const double* uzn, const double* uzo, const double* dzphs,
                                                  double* L0) {
   ELEM_PROLOGUE
-  __shared__ double sph[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sQ2[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sgx[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sgy[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  ELEM_ARRAY(sph)
+  ELEM_ARRAY(sQ2)
+  ELEM_ARRAY(sgx)
+  ELEM_ARRAY(sgy)
   double phh = 0.0, uxs = 0.0, uys = 0.0, gg = 0.0;
   if (act) {
     double pn = phn[pofs + gi], po = pho[pofs + gi];
@@ -274,19 +305,24 @@ __global__ void __launch_bounds__(WG) k_psi_elem(Geo g, Par P, const double* phn
   __syncthreads();
   double q1 = 0.0;
   if (act) {
-    double adv = uxs * ddx(s, n, a, b, sph, sx) + uys * ddy(s, n, a, b, sph, sy);
+    const double* f[2] = {sph, sQ2};
+    double dx[2], dy[2];
+    grad2<2>(s, n, a, b, f, sx, sy, dx, dy);
+    double adv = uxs * dx[0] + uys * dy[0];
     if (uzn) {  // 3D: + u*_z d(phi*)/dz, the z-derivative taken from the spectral phi
       const long id = pofs + gi;
       adv += (P.cs_n * uzn[id] + P.cs_o * uzo[id]) * dzphs[id];
     }
     q1 = (gg - adv + phh / P.dt) / (P.lam * P.gamma1);
-    sgx[t] = s.w[a] * ddx(s, n, a, b, sQ2, sx);
-    sgy[t] = s.w[b] * ddy(s, n, a, b, sQ2, sy);
+    sgx[t] = s.w[a] * dx[1];
+    sgy[t] = s.w[b] * dy[1];
   }
   __syncthreads();
   if (act) {
     double wq = 0.25 * hx * hy * s.w[a] * s.w[b];
-    L0[lofs] = -wq * q1 + 0.5 * hy * s.w[b] * wdx(s, n, a, b, sgx) + 0.5 * hx * s.w[a] * wdy(s, n, a, b, sgy);
+    double wx, wy;
+    wdxy(s, n, a, b, sgx, sgy, wx, wy);
+    L0[lofs] = -wq * q1 + 0.5 * hy * s.w[b] * wx + 0.5 * hx * s.w[a] * wy;
   }
 }
 
@@ -348,18 +384,18 @@ __global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi
                                                  const double* fx, const double* fy, double* L0,
                                                  double* L1, double* L2, Mom3 z) {
   ELEM_PROLOGUE
-  __shared__ double sph[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sPhi[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sux[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double suy[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double suz[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sP[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sgx[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sgy[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sKz[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sfz[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sfx[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
-  __shared__ double sfy[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  ELEM_ARRAY(sph)
+  ELEM_ARRAY(sPhi)
+  ELEM_ARRAY(sux)
+  ELEM_ARRAY(suy)
+  ELEM_ARRAY(suz)
+  ELEM_ARRAY(sP)
+  ELEM_ARRAY(sgx)
+  ELEM_ARRAY(sgy)
+  ELEM_ARRAY(sKz)
+  ELEM_ARRAY(sfz)
+  ELEM_ARRAY(sfx)
+  ELEM_ARRAY(sfy)
   double ph = 0.0, ps = 0.0, e2 = 0.0, uh[3] = {0.0, 0.0, 0.0}, ff[3] = {0.0, 0.0, 0.0};
   if (act) {
     const long id = pofs + gi;
@@ -397,21 +433,27 @@ __global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi
     const double mu = 0.5 * (P.mu1 + P.mu2) + 0.5 * (P.mu1 - P.mu2) * pc;
     const double irho = 1.0 / rho;
     const double drr = 0.5 * (P.rho1 - P.rho2), dmm = 0.5 * (P.mu1 - P.mu2);
-    const double gph[3] = {ddx(s, n, a, b, sph, sx), ddy(s, n, a, b, sph, sy), Z3 ? z.dzphi[id] : 0.0};
+    // x, y derivatives of phi*, Phi, u*_x, u*_y, P*, u*_z
+    constexpr int NF = Z3 ? 6 : 5;
+    const double* fl[NF];
+    fl[0] = sph; fl[1] = sPhi; fl[2] = sux; fl[3] = suy; fl[4] = sP;
+    if (Z3) fl[NF - 1] = suz;
+    double dX[NF], dY[NF];
+    grad2<NF>(s, n, a, b, fl, sx, sy, dX, dY);
+    const double gph[3] = {dX[0], dY[0], Z3 ? z.dzphi[id] : 0.0};
     const double cnu = (rho * dmm - mu * drr) * irho * irho;  // grad(mu/rho) = cnu grad(phi)
     const double jc = 0.5 * (P.rho1 - P.rho2) * P.lam * P.gamma1;
-    const double Jt[3] = {jc * ddx(s, n, a, b, sPhi, sx), jc * ddy(s, n, a, b, sPhi, sy),
-                          Z3 ? jc * z.dzPhi[id] : 0.0};
+    const double Jt[3] = {jc * dX[1], jc * dY[1], Z3 ? jc * z.dzPhi[id] : 0.0};
     const double u[3] = {sux[t], suy[t], suz[t]};
     // gu[i][k] = d_i u*_k
     double gu[3][3];
-    gu[0][0] = ddx(s, n, a, b, sux, sx);
-    gu[0][1] = ddx(s, n, a, b, suy, sx);
-    gu[1][0] = ddy(s, n, a, b, sux, sy);
-    gu[1][1] = ddy(s, n, a, b, suy, sy);
+    gu[0][0] = dX[2];
+    gu[0][1] = dX[3];
+    gu[1][0] = dY[2];
+    gu[1][1] = dY[3];
     if (Z3) {
-      gu[0][2] = ddx(s, n, a, b, suz, sx);
-      gu[1][2] = ddy(s, n, a, b, suz, sy);
+      gu[0][2] = dX[NF - 1];
+      gu[1][2] = dY[NF - 1];
       gu[2][0] = z.dzux[id];
       gu[2][1] = z.dzuy[id];
       gu[2][2] = z.dzuz[id];
@@ -423,7 +465,7 @@ __global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi
     om[2] = gu[0][1] - gu[1][0];
     const double lap = ps - P.alpha * ph;
     const double dep = deps_of(P, ph);
-    const double gP[3] = {ddx(s, n, a, b, sP, sx), ddy(s, n, a, b, sP, sy), Z3 ? z.dzP[id] : 0.0};
+    const double gP[3] = {dX[4], dY[4], Z3 ? z.dzP[id] : 0.0};
     const double cP = 1.0 / P.rho0 - irho;
     const double gnu[3] = {cnu * gph[0], cnu * gph[1], cnu * gph[2]};
     const double cr[3] = {gnu[1] * om[2] - gnu[2] * om[1], gnu[2] * om[0] - gnu[0] * om[2],
@@ -456,17 +498,21 @@ __global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi
   if (act) {
     const double wq = 0.25 * hx * hy * s.w[a] * s.w[b];
     const double ewx = 0.5 * hx * s.w[a], ewy = 0.5 * hy * s.w[b];   // edge weights
-    double l0 = P.rho0 * (ewy * wdx(s, n, a, b, sgx) + ewx * wdy(s, n, a, b, sgy));
-    // x- and y-parts of the weak divergence of K components (K weighted by w_p inside)
-    double kz_y = 0.0, kz_x = 0.0, ky_x = 0.0, kx_y = 0.0;
+    // weak divergence of G (x, y parts) and of the K components (K weighted by w_p inside),
+    // one pass over row b and column a
+    double gdx = 0.0, gdy = 0.0, kz_y = 0.0, kz_x = 0.0, ky_x = 0.0, kx_y = 0.0;
     for (int p = 0; p < n; ++p) {
-      kz_y += s.D[p * n + b] * s.w[p] * sKz[p * n + a];
-      kz_x += s.D[p * n + a] * s.w[p] * sKz[b * n + p];
+      const double dpa = s.D[p * n + a], dpb = s.D[p * n + b], wp = s.w[p];
+      gdx += dpa * sgx[b * n + p];
+      gdy += dpb * sgy[p * n + a];
+      kz_y += dpb * wp * sKz[p * n + a];
+      kz_x += dpa * wp * sKz[b * n + p];
       if (Z3) {
-        ky_x += s.D[p * n + a] * s.w[p] * sfy[b * n + p];
-        kx_y += s.D[p * n + b] * s.w[p] * sfx[p * n + a];
+        ky_x += dpa * wp * sfy[b * n + p];
+        kx_y += dpb * wp * sfx[p * n + a];
       }
     }
+    double l0 = P.rho0 * (ewy * gdx + ewx * gdy);
     double l1 = wq * G[0] + ewx * kz_y;
     double l2 = wq * G[1] - ewy * kz_x;
     double laz = 0.0, lbp = 0.0;
@@ -546,13 +592,16 @@ __global__ void k_P_rhs(Geo g, Par P, Lift L, const double* L0, const double* wx
 __global__ void __launch_bounds__(WG) k_gradP_elem(Geo g, Par P, const double* Pnew, const double* dzP,
                                                    double* L1, double* L2, double* LAz) {
   ELEM_PROLOGUE
-  __shared__ double sP[(PFD_KMAX + 1) * (PFD_KMAX + 1)];
+  ELEM_ARRAY(sP)
   if (act) sP[t] = Pnew[pofs + gi];
   __syncthreads();
   if (act) {
     const double c = -0.25 * hx * hy * s.w[a] * s.w[b] / (P.nu_m * P.rho0);
-    L1[lofs] += c * ddx(s, n, a, b, sP, sx);
-    L2[lofs] += c * ddy(s, n, a, b, sP, sy);
+    const double* f[1] = {sP};
+    double dx[1], dy[1];
+    grad2<1>(s, n, a, b, f, sx, sy, dx, dy);
+    L1[lofs] += c * dx[0];
+    L2[lofs] += c * dy[0];
     if (dzP) LAz[lofs] += c * dzP[pofs + gi];
   }
 }
@@ -583,6 +632,28 @@ __global__ void k_check_finite(long N, const double* f, int* status) {
 }
 
 // =================================================================== solves
+// Copies n values into LDS with U independent loads in flight per thread: value(idx) is read for
+// every idx < n (the caller clamps addresses and masks values, so there is no branch around a
+// load) and store(idx, v) writes it.  Indices past n are clamped to n - 1, whose value is then
+// written twice (the same value), so neither loads nor stores sit under a branch.  A plain
+// strided loop would wait for each load in turn.
+template <int NT, int U, class T, class Value, class Store>
+__device__ __forceinline__ void stage_lds(int n, Value value, Store store) {
+  for (int base = 0; base < n; base += NT * U) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + (int)threadIdx.x + NT * u;
+      v[u] = value(idx < n ? idx : n - 1);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + (int)threadIdx.x + NT * u;
+      store(idx < n ? idx : n - 1, v[u]);
+    }
+  }
+}
+
 // r = b - (Kx (x) My + Mx (x) Ky + c_p Mx (x) My) x on free nodes, 0 on Dirichlet nodes.
 // The 1D stiffness matrices are stored banded and transposed: KxB[(d+K)*Nx + ix] =
 // Kx[ix][ix+d] (periodic wrap in x; zero outside the band), so consecutive threads read
@@ -650,11 +721,16 @@ __global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, 
   const long Ng = (long)Nx * Ny;
   const double* xp = x + pl * Ng;
   const int nrows = RROWS + 2 * K;
-  for (int idx = threadIdx.x; idx < nrows * Nx; idx += 256) {
-    const int rr = idx / Nx, ix = idx - rr * Nx;
-    const int iy = iy0 - K + rr;
-    xs[idx] = (iy >= 0 && iy < Ny) ? xp[(long)iy * Nx + ix] : 0.0;
-  }
+  stage_lds<256, 16, double>(
+      nrows * Nx,
+      [&](int idx) {
+        const int rr = idx / Nx, ix = idx - rr * Nx;
+        const int iy = iy0 - K + rr;
+        const bool ok = iy >= 0 && iy < Ny;
+        const double v = xp[(long)(ok ? iy : 0) * Nx + ix];
+        return ok ? v : 0.0;
+      },
+      [&](int idx, double v) { xs[idx] = v; });
   __syncthreads();
   const int ix = threadIdx.x;
   if (ix >= Nx) return;
@@ -964,11 +1040,19 @@ __global__ void __launch_bounds__(256) k_gemm_sr(const TA* __restrict__ A, const
   const int r16 = lane & 15, g = lane >> 4;
   const int n0 = blockIdx.y * 16 * W;
   // S[k][n0 .. n0+16W) -> LDS (zero beyond K or N)
-  for (int idx = threadIdx.x; idx < KP * 16 * W; idx += 256) {
-    const int k = idx / (16 * W), j = idx - k * (16 * W);
-    const int n = n0 + j;
-    Sl[k * NP + j] = (k < K && n < N) ? S[(long)k * N + n] : T(0);
-  }
+  stage_lds<256, 16, T>(
+      KP * 16 * W,
+      [&](int idx) {
+        const int k = idx / (16 * W), j = idx - k * (16 * W);
+        const int n = n0 + j;
+        const bool ok = k < K && n < N;
+        const T v = S[(long)(k < K ? k : K - 1) * N + (n < N ? n : N - 1)];
+        return ok ? v : T(0);
+      },
+      [&](int idx, T v) {
+        const int k = idx / (16 * W), j = idx - k * (16 * W);
+        Sl[k * NP + j] = v;
+      });
   __syncthreads();
   const int ms = w % WS, ks = w / WS;
   const int m = (blockIdx.x * WS + ms) * 16 + r16;
@@ -1068,11 +1152,19 @@ __global__ void __launch_bounds__(256) k_gemm_sl(const T* __restrict__ S, const 
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
   const int m0 = blockIdx.y * 16 * W;
-  for (int idx = threadIdx.x; idx < 16 * W * KP; idx += 256) {
-    const int i = idx / KP, k = idx - i * KP;
-    const int mi = m0 + i;
-    Sl[k * MP + i] = (k < K && mi < M) ? S[(long)mi * K + k] : T(0);
-  }
+  stage_lds<256, 16, T>(
+      16 * W * KP,
+      [&](int idx) {
+        const int i = idx / KP, k = idx - i * KP;
+        const int mi = m0 + i;
+        const bool ok = k < K && mi < M;
+        const T v = S[(long)(mi < M ? mi : M - 1) * K + (k < K ? k : K - 1)];
+        return ok ? v : T(0);
+      },
+      [&](int idx, T v) {
+        const int i = idx / KP, k = idx - i * KP;
+        Sl[k * MP + i] = v;
+      });
   __syncthreads();
   const int ms = w % WS, ks = w / WS;
   const long ctot = (long)planes * N;
@@ -1909,7 +2001,7 @@ static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, c
 
 hipError_t update_E(pfd_ctx* c) {
   const Geo& g = c->geo;
-  dim3 eg(c->geo.nx * c->geo.ny, c->planes), eb(((c->nq + 63) / 64) * 64);
+  dim3 eg(c->geo.nx * c->geo.ny, (c->planes + c->geo.ppw - 1) / c->geo.ppw), eb(((c->geo.ppw * c->nq + 63) / 64) * 64);
   const long tot = (long)c->planes * c->Ng;
   const double* Ez = nullptr;
   if (c->is3d) {
@@ -1928,7 +2020,7 @@ hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout) {
   Par P = c->par;
   P.cs_n = 1.0;
   P.cs_o = 0.0;
-  dim3 eg(g.nx * g.ny, c->planes), eb(((c->nq + 63) / 64) * 64);
+  dim3 eg(g.nx * g.ny, (c->planes + g.ppw - 1) / g.ppw), eb(((g.ppw * c->nq + 63) / 64) * 64);
   const long tot = (long)c->planes * c->Ng;
   const double* ph = FLD(F_PHI, 0);
   Dir1D& dx = c->dirs[c->fam[PFD_FAM_V].ix];
@@ -1946,7 +2038,7 @@ hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout) {
 hipError_t step_once(pfd_ctx* c, int equilibrium) {
   const Geo& g = c->geo;
   const Par& P = c->par;
-  dim3 eg(g.nx * g.ny, c->planes), eb(((c->nq + 63) / 64) * 64);
+  dim3 eg(g.nx * g.ny, (c->planes + g.ppw - 1) / g.ppw), eb(((g.ppw * c->nq + 63) / 64) * 64);
   const long tot = (long)c->planes * c->Ng;
   const dim3 ng(nblk(tot)), nb(WG);
   hipStream_t st = c->stream;
@@ -2577,7 +2669,7 @@ void refresh_spectral_sources(pfd_ctx* c) {
 hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
   const Geo& g = c->geo;
   const Par& P = c->par;
-  dim3 eg(g.nx * g.ny, c->planes), eb(((c->nq + 63) / 64) * 64);
+  dim3 eg(g.nx * g.ny, (c->planes + g.ppw - 1) / g.ppw), eb(((g.ppw * c->nq + 63) / 64) * 64);
   const long tot = (long)c->planes * c->Ng;
   const dim3 ng(nblk(tot)), nb(WG);
   hipStream_t st = c->stream;
@@ -2721,7 +2813,7 @@ hipError_t potential_iteration_3d(pfd_ctx* c, const double* Vin, double* Vout) {
   Par P = c->par;
   P.cs_n = 1.0;
   P.cs_o = 0.0;
-  dim3 eg(g.nx * g.ny, c->planes), eb(((c->nq + 63) / 64) * 64);
+  dim3 eg(g.nx * g.ny, (c->planes + g.ppw - 1) / g.ppw), eb(((g.ppw * c->nq + 63) / 64) * 64);
   const long tot = (long)c->planes * c->Ng;
   const dim3 ng(nblk(tot)), nb(WG);
   hipStream_t st = c->stream;
