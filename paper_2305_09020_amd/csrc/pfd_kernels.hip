@@ -702,9 +702,12 @@ __global__ void k_residual(int Nx, int Ny, int planes, int perx, const double* _
 }
 
 // LDS-tiled variant of k_residual: a work-group takes RROWS rows of one plane; the rows
-// iy0-K .. iy0+RROWS-1+K of x are staged in LDS once (coalesced), each thread keeps the
-// 2K+1 x-band coefficients of its column in registers, and the 2(2K+1) neighbour reads of
-// every node come from LDS instead of L1/L2.  Needs Nx <= 256 (one column per thread).
+// iy0-K .. iy0+RROWS-1+K of x are staged in LDS once (coalesced), with the y-band coefficients,
+// M_y and the Dirichlet flags of its rows.  Each thread owns one column: the 2K+1 x-band
+// coefficients of the column and the RROWS+2K values of x down the column sit in registers, so
+// the y-sums of all RROWS rows come from that window, and only the x-neighbours are read from
+// LDS.  All global loads (b of every row included) are issued before the row sums.  Needs
+// Nx <= 256 (one column per thread).
 #define RROWS 16
 template <int K>
 __global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, const double* __restrict__ KxB,
@@ -715,14 +718,17 @@ __global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, 
                                                       const double* __restrict__ shift, const double* __restrict__ bb,
                                                       const double* __restrict__ x, double* __restrict__ r,
                                                       int apply_only, const unsigned char* __restrict__ ebot) {
+  constexpr int NB = 2 * K + 1, NW = RROWS + 2 * K;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* xs = reinterpret_cast<double*>(smem_raw);       // (RROWS + 2K) rows x Nx
+  double* xs = reinterpret_cast<double*>(smem_raw);   // NW rows x Nx
+  double* kyl = xs + NW * Nx;                         // [RROWS][NB] y-band rows iy0..
+  double* myl = kyl + RROWS * NB;                     // [RROWS] M_y
+  double* dyl = myl + RROWS;                          // [RROWS] Dirichlet flag of the row
   const int pl = blockIdx.y, iy0 = blockIdx.x * RROWS;
   const long Ng = (long)Nx * Ny;
   const double* xp = x + pl * Ng;
-  const int nrows = RROWS + 2 * K;
   stage_lds<256, 16, double>(
-      nrows * Nx,
+      NW * Nx,
       [&](int idx) {
         const int rr = idx / Nx, ix = idx - rr * Nx;
         const int iy = iy0 - K + rr;
@@ -731,13 +737,26 @@ __global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, 
         return ok ? v : 0.0;
       },
       [&](int idx, double v) { xs[idx] = v; });
+  for (int idx = threadIdx.x; idx < RROWS * (NB + 2); idx += 256) {   // <= 2 rounds
+    const int rl = idx % RROWS, q = idx / RROWS;
+    const int iy = min(iy0 + rl, Ny - 1);
+    if (q < NB) kyl[rl * NB + q] = KyB[(long)q * Ny + iy];
+    else if (q == NB) myl[rl] = My[iy];
+    else dyl[rl] = diry[iy] ? 1.0 : 0.0;
+  }
   __syncthreads();
   const int ix = threadIdx.x;
   if (ix >= Nx) return;
-  double kx[2 * K + 1];
+  const int rend = min(RROWS, Ny - iy0);
+  double bv[RROWS];
+  if (!apply_only) {
 #pragma unroll
-  for (int d = 0; d <= 2 * K; ++d) kx[d] = KxB[(long)d * Nx + ix];
-  int jx[2 * K + 1];
+    for (int rl = 0; rl < RROWS; ++rl) bv[rl] = bb[pl * Ng + (long)min(iy0 + rl, Ny - 1) * Nx + ix];
+  }
+  double kx[NB];
+#pragma unroll
+  for (int d = 0; d < NB; ++d) kx[d] = KxB[(long)d * Nx + ix];
+  int jx[NB];
 #pragma unroll
   for (int d = -K; d <= K; ++d) {
     int j = ix + d;
@@ -746,24 +765,32 @@ __global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, 
     jx[d + K] = j;
   }
   const double mx = Mx[ix], sh = shift[pl];
-  const int rend = min(RROWS, Ny - iy0);
-  for (int rl = 0; rl < rend; ++rl) {
-    const int iy = iy0 + rl;
-    const double* row = xs + (rl + K) * Nx;
-    double ax = 0.0, ay = 0.0;
+  const bool dxn = dirx[ix] != 0;
+  const bool egap = ebot && !ebot[ix];   // bottom-row gap node of a partial electrode set
+  double win[NW];
 #pragma unroll
-    for (int d = 0; d <= 2 * K; ++d) ax += kx[d] * row[jx[d]];
+  for (int q = 0; q < NW; ++q) win[q] = xs[q * Nx + ix];
 #pragma unroll
-    for (int d = -K; d <= K; ++d) ay += KyB[(long)(d + K) * Ny + iy] * row[d * Nx + ix];
-    const double xv = row[ix];
-    const double my = My[iy];
-    const double Av = ax * my + mx * ay + sh * mx * my * xv;
-    const long id = pl * Ng + (long)iy * Nx + ix;
-    if (apply_only) {
-      r[id] = Av;
-    } else {
-      const bool dn = is_dir(dirx, diry, ebot, ix, iy);
-      r[id] = dn ? 0.0 : bb[id] - Av;
+  for (int rl = 0; rl < RROWS; ++rl) {
+    if (rl < rend) {
+      const int iy = iy0 + rl;
+      const double* row = xs + (rl + K) * Nx;
+      double ax = 0.0, ay = 0.0;
+#pragma unroll
+      for (int d = 0; d < NB; ++d) ax += kx[d] * row[jx[d]];
+#pragma unroll
+      for (int d = 0; d < NB; ++d) ay += kyl[rl * NB + d] * win[rl + d];
+      const double xv = win[rl + K];
+      const double my = myl[rl];
+      const double Av = ax * my + mx * ay + sh * mx * my * xv;
+      const long id = pl * Ng + (long)iy * Nx + ix;
+      if (apply_only) {
+        r[id] = Av;
+      } else {
+        // is_dir: x-Dirichlet column, or a y-Dirichlet row except the gap nodes of the bottom row
+        const bool dn = dxn || (dyl[rl] != 0.0 && !(iy == 0 && egap));
+        r[id] = dn ? 0.0 : bv[rl] - Av;
+      }
     }
   }
 }
@@ -1639,7 +1666,7 @@ static void residual(pfd_ctx* c, int fam, const double* b, const double* x, doub
   Dir1D& dy = c->dirs[F.iy];
   const int planes = np > 0 ? np : c->planes;   // np: stacked components as extra planes
   const long tot = (long)planes * c->Ng;
-  const size_t lds = sizeof(double) * (size_t)(RROWS + 2 * c->K) * c->Nx;
+  const size_t lds = sizeof(double) * ((size_t)(RROWS + 2 * c->K) * c->Nx + RROWS * (2 * c->K + 3));
   const bool tiled = !norms && c->Nx <= 256 && lds <= 64 * 1024 && c->resid_variant == 1;
 #define RES_CASE(KK)                                                                                      \
   case KK:                                                                                                \
