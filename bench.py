@@ -137,7 +137,7 @@ def roofline_c4(run, steps):
         avg = c.profile_replay(dom, 50) * 1e-6
         P, Nx, Ny = c.planes, c.Nx, c.Ny
         if dom.startswith("gemm"):
-            per = float(Ny * Nx * (Nx + Ny) * P) * (2.0 if c.solver_variant()[0] == 1 else 1.0)
+            per = float(Ny * Nx * (Nx + Ny) * P) * {0: 1.0, 1: 2.0, 2: 4.0 / 3.0}[c.solver_variant()[0]]
         else:
             per = float(24 * P * Nx * Ny)
         work += n * per
@@ -352,8 +352,8 @@ def roofline(ctx, steps, workload="c2", path="refined"):
     variant, tune_us = ctx.solver_variant()
     if dom.startswith("gemm"):
         # four-pass variant: one GEMM pass per launch (mean 2*Ny*Nx*(Nx+Ny)/2 flops per plane);
-        # fused variant: two passes per launch
-        per = float(Ny * Nx * (Nx + Ny) * P) * (2.0 if variant == 1 else 1.0)
+        # fused strip variant: two passes per launch; fused middle passes: four in three
+        per = float(Ny * Nx * (Nx + Ny) * P) * {0: 1.0, 1: 2.0, 2: 4.0 / 3.0}[variant]
         achieved = per / avg / 1e12
         peak = PEAK[dom][0] / 1e12
     else:

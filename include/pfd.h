@@ -210,14 +210,18 @@ pfd_status pfd_get_mass_weights(pfd_ctx* ctx, double* w);
 pfd_status pfd_update_params(pfd_ctx* ctx, const pfd_params* par);
 
 /* Kernels of the fast-diagonalisation solves: 0 = four batched GEMM passes
- * (16x16 MFMA tiles, split-K over four waves), 1 = two fused strip kernels
- * (the strip intermediate stays in LDS).  pfd_create times one velocity
- * correction with each in the context's solve precision and keeps the faster;
- * variant -1 re-runs that autotuning.  Both compute the same correction up to
- * rounding order.  Synchronises; drops captured graphs. */
+ * (tile configurations per pass from pfd_set_gemm_config), 1 = two fused
+ * strip kernels (the strip intermediate stays in LDS), 2 = three launches:
+ * the first and last passes as in 0, the two middle passes (along y, with the
+ * division by the eigenvalue sums between them) fused in one kernel that keeps
+ * a block of columns and its intermediate in LDS (falls back to 0 where that
+ * block does not fit in 64 KB).  pfd_create times one velocity correction
+ * with each in the context's solve precision and keeps the fastest; variant
+ * -1 re-runs that autotuning.  All compute the same correction up to rounding
+ * order.  Synchronises; drops captured graphs. */
 pfd_status pfd_set_solver_variant(pfd_ctx* ctx, int variant);
-/* Current variant and the autotuner's timings (us[2], microseconds per
- * correction of variants 0 and 1; either may be NULL). */
+/* Current variant and the autotuner's timings (us[3], microseconds per
+ * correction of variants 0, 1 and 2; either may be NULL). */
 pfd_status pfd_get_solver_variant(const pfd_ctx* ctx, int* variant, double* us);
 
 /* Kernel of the FP64 residual b - (K + cM) x of the refinement: 0 = one

@@ -306,7 +306,8 @@ class Context:
         _check(_lib.pfd_update_params(self.h, ctypes.byref(par)), self.h)
 
     def set_solver_variant(self, variant):
-        """0: four GEMM passes, 1: fused strip kernels, -1: autotune again."""
+        """0: four GEMM passes, 1: fused strip kernels, 2: fused middle passes (three
+        launches), -1: autotune again."""
         _check(_lib.pfd_set_solver_variant(self.h, int(variant)), self.h)
 
     def set_residual_variant(self, variant):
@@ -332,11 +333,11 @@ class Context:
         return list(cfg), [list(us[17 * s:17 * s + 17]) for s in range(5)]
 
     def solver_variant(self):
-        """(variant, [us per correction of variant 0, variant 1]) from the autotuner."""
+        """(variant, [us per correction of variants 0, 1, 2]) from the autotuner."""
         v = ctypes.c_int(0)
-        us = (ctypes.c_double * 2)()
+        us = (ctypes.c_double * 3)()
         _check(_lib.pfd_get_solver_variant(self.h, ctypes.byref(v), us), self.h)
-        return v.value, [us[0], us[1]]
+        return v.value, [us[0], us[1], us[2]]
 
     def set_graph(self, on=True):
         """Replay a captured hipGraph per step (identical results, fewer launches)."""

@@ -120,6 +120,8 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   const int NN = std::max(L->Nx, L->Ny);
   dbl += 8 * (3 * (size_t)NN * NN + 3 * NN + 8);  // up to 8 distinct 1D operators
   dbl += 8 * (size_t)NN * NN;            // float copies (as doubles, generous)
+  const size_t NP = (size_t)((NN + 15) & ~15);
+  dbl += 8 * 3 * NP * NP + 64;           // S, S^T in fragment order, double and float
   dbl += 2 * (size_t)(m.nx + m.ny + 2) + (PFD_KMAX + 1) * (PFD_KMAX + 2);
   dbl += 48 * (size_t)L->planes + 1280;  // shifts, norms, reductions (1024 block maxima)
   L->bytes = dbl * sizeof(double) + 256 * 128;  // alignment slack
@@ -315,6 +317,10 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     d.dK0 = D(d.N); d.dKN = D(d.N);
     d.fS = (float*)carve(c, sizeof(float) * NN);
     d.fST = (float*)carve(c, sizeof(float) * NN);
+    const long NP2 = (long)((d.N + 15) & ~15) * ((d.N + 15) & ~15);
+    d.dSw = D(NP2); d.dSTw = D(NP2);
+    d.fSw = (float*)carve(c, sizeof(float) * NP2);
+    d.fSTw = (float*)carve(c, sizeof(float) * NP2);
     d.ddir = (unsigned char*)carve(c, d.N);
   }
   bool ok = c->fld[0][0] && zero && c->fam[4].dshift;
@@ -347,6 +353,31 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     e = up(d.dM1, d.M1.data(), 8 * N); if (e) break;
     e = up(d.fS, f1.data(), 4 * N * N); if (e) break;
     e = up(d.fST, f2.data(), 4 * N * N); if (e) break;
+    {
+      // MFMA fragment order of S and S^T as left operands: tile (mt, sl), lane, then the four
+      // contraction entries k = 16 sl + 4 (lane / 16) + s of row 16 mt + lane % 16
+      const int KS = (N + 15) / 16;
+      const size_t NP2 = (size_t)KS * 16 * KS * 16;
+      std::vector<double> w1(NP2, 0.0), w2(NP2, 0.0);
+      std::vector<float> v1(NP2, 0.0f), v2(NP2, 0.0f);
+      for (int mt = 0; mt < KS; ++mt)
+        for (int sl = 0; sl < KS; ++sl)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int q = 0; q < 4; ++q) {
+              const int i = 16 * mt + (lane & 15), k = 16 * sl + 4 * (lane >> 4) + q;
+              const size_t o = (((size_t)mt * KS + sl) * 64 + lane) * 4 + q;
+              if (i < N && k < N) {
+                w1[o] = d.S[(size_t)i * N + k];
+                w2[o] = d.S[(size_t)k * N + i];
+                v1[o] = (float)w1[o];
+                v2[o] = (float)w2[o];
+              }
+            }
+      e = up(d.dSw, w1.data(), 8 * NP2); if (e) break;
+      e = up(d.dSTw, w2.data(), 8 * NP2); if (e) break;
+      e = up(d.fSw, v1.data(), 4 * NP2); if (e) break;
+      e = up(d.fSTw, v2.data(), 4 * NP2); if (e) break;
+    }
     e = up(d.ddir, dd.data(), N); if (e) break;
     std::vector<double> k0(N), kn(N);
     for (int i = 0; i < N; ++i) {
@@ -706,7 +737,7 @@ extern "C" pfd_status pfd_update_params(pfd_ctx* c, const pfd_params* q) {
 }
 
 extern "C" pfd_status pfd_set_solver_variant(pfd_ctx* c, int variant) {
-  if (!c || variant < -1 || variant > 1) return PFD_EINVAL;
+  if (!c || variant < -1 || variant > 2) return PFD_EINVAL;
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
   if (variant < 0)
@@ -761,10 +792,8 @@ extern "C" pfd_status pfd_get_residual_variant(const pfd_ctx* c, int* variant, d
 extern "C" pfd_status pfd_get_solver_variant(const pfd_ctx* c, int* variant, double* us) {
   if (!c) return PFD_EINVAL;
   if (variant) *variant = c->fdm_variant;
-  if (us) {
-    us[0] = c->fdm_us[0];
-    us[1] = c->fdm_us[1];
-  }
+  if (us)
+    for (int v = 0; v < 3; ++v) us[v] = c->fdm_us[v];
   return PFD_OK;
 }
 

@@ -32,6 +32,9 @@ struct Dir1D {
   double *dK0 = nullptr, *dKN = nullptr;  // first and last columns of K1 (Dirichlet lifting)
   std::vector<double> Kb;            // banded transposed stiffness: Kb[(d+K)*N + i] = K1[i][i+d]
   float *fS = nullptr, *fST = nullptr;
+  // S and S^T in MFMA fragment order (frag_layout), zero-padded to a multiple of 16
+  double *dSw = nullptr, *dSTw = nullptr;
+  float *fSw = nullptr, *fSTw = nullptr;
   unsigned char* ddir = nullptr;
 };
 
@@ -138,7 +141,8 @@ struct pfd_ctx {
   int fdm_variant = 1;
   int resid_variant = 1;                   // residual: 0 = per-node global reads, 1 = LDS tiles
   double resid_us[2] = {0.0, 0.0};
-  double fdm_us[2] = {0.0, 0.0};           // autotune timings (us per correction)
+  double fdm_us[3] = {0.0, 0.0, 0.0};      // autotune timings (us per correction)
+  int mid_tn = 1, mid_best_tn = 1;         // column tiles per work-group of the fused middle passes
   int gemm_cfg[PFD_GS_N][2] = {};          // tile configuration per (call site, FP32/FP64)
   double gemm_us[PFD_GS_N][2][PFD_GEMM_NCFG] = {};  // autotune timings per configuration
   hipStream_t cap_stream = nullptr;        // capture stream (the caller's may be the null stream)

@@ -1692,8 +1692,196 @@ hipError_t apply(pfd_ctx* c, int fam, const double* x, double* y, int ncomp) {
   return hipGetLastError();
 }
 
+// the float or the double copy of an operator matrix
+template <typename T>
+static const T* pick(const float* f, const double* d);
+template <>
+const float* pick<float>(const float* f, const double*) { return f; }
+template <>
+const double* pick<double>(const float*, const double* d) { return d; }
+
+// Fused middle passes of the fast-diagonalisation correction on a block of CW = 16 TN columns
+// (flattened over planes, as in k_gemm_sl):
+//   U = (Sy^T T1) ./ (ly_i + lx_j + c_p)   (0 where the denominator vanishes)
+//   T3 = Sy U
+// with the T1 block and U kept in LDS, so the intermediate never goes to memory and one launch
+// replaces two.  The shared matrices come pre-arranged in MFMA fragment order (frag_layout:
+// for every 16x16 tile (mt, sl) and lane, the four contraction entries the lane multiplies
+// are consecutive), so a lane reads each fragment with one vector load; the next slice is
+// loaded while the current one is multiplied.  Wave w takes row tiles w, w + nw, ...
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  typedef float V __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ void load(const float* p, float (&o)[4]) {
+    const V v = *reinterpret_cast<const V*>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+};
+template <>
+struct Vec4<double> {
+  typedef double V __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ void load(const double* p, double (&o)[4]) {
+    const V a = reinterpret_cast<const V*>(p)[0], b = reinterpret_cast<const V*>(p)[1];
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+  }
+};
+
+#define FDM_MID_LDC(CW) ((CW) + 4)
+
+template <typename T, int RT, int TN>
+__device__ __forceinline__ void fdm_mid_pass(const T* __restrict__ Aw, const T* Bl, int KS, int MT, int nw, int w,
+                                             int lane, typename Mfma<T>::V (&acc)[RT][TN]) {
+  typedef typename Mfma<T>::V V;
+  constexpr int LDC = FDM_MID_LDC(16 * TN);
+  const int r16 = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < TN; ++ct) acc[rt][ct] = V{T(0), T(0), T(0), T(0)};
+  T a[RT][4], an[RT][4];
+  auto loadA = [&](int sl, T (&aa)[RT][4]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int mt = min(w + nw * rt, MT - 1);   // clamped; tiles past MT are not multiplied
+      Vec4<T>::load(Aw + ((long)(mt * KS + sl) * 64 + lane) * 4, aa[rt]);
+    }
+  };
+  loadA(0, a);
+  for (int sl = 0; sl < KS; ++sl) {
+    if (sl + 1 < KS) loadA(sl + 1, an);
+    T b[TN][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int ct = 0; ct < TN; ++ct) b[ct][s] = Bl[(16 * sl + 4 * g + s) * LDC + 16 * ct + r16];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      if (w + nw * rt < MT) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int ct = 0; ct < TN; ++ct) acc[rt][ct] = Mfma<T>::op(a[rt][s], b[ct][s], acc[rt][ct]);
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[rt][s] = an[rt][s];
+  }
+}
+
+template <typename T, int RT, int TN>
+__global__ void __launch_bounds__(1024) k_fdm_mid(int planes, int Ny, int Nx, long Ng, const T* __restrict__ SyTw,
+                                                  const T* __restrict__ Syw, const T* __restrict__ T1,
+                                                  const double* __restrict__ ly, const double* __restrict__ lx,
+                                                  const double* __restrict__ shift, T* __restrict__ T3) {
+  typedef typename Mfma<T>::V V;
+  constexpr int CW = 16 * TN, LDC = FDM_MID_LDC(CW);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int KP = (Ny + 15) & ~15, MT = KP / 16;
+  T* Bt = reinterpret_cast<T*>(smem_raw);   // [KP][LDC]  T1 block (rows >= Ny zero)
+  T* Us = Bt + KP * LDC;                    // [KP][LDC]  U block
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6, nt = blockDim.x;
+  const int r16 = lane & 15, g = lane >> 4;
+  const long ctot = (long)planes * Nx, c0 = (long)blockIdx.x * CW;
+  // stage the T1 block (coalesced along the columns), 8 loads in flight per thread
+  for (int base = 0; base < KP * CW; base += 8 * nt) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = min(base + (int)threadIdx.x + nt * u, KP * CW - 1);
+      const int k = idx / CW, j = idx - k * CW;
+      const long ci = c0 + j;
+      const bool ok = k < Ny && ci < ctot;
+      const long cc = ci < ctot ? ci : ctot - 1;
+      const long p = cc / Nx;
+      const T x = T1[p * Ng + (long)(k < Ny ? k : Ny - 1) * Nx + (cc - p * Nx)];
+      v[u] = ok ? x : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = min(base + (int)threadIdx.x + nt * u, KP * CW - 1);
+      const int k = idx / CW, j = idx - k * CW;
+      Bt[k * LDC + j] = v[u];
+    }
+  }
+  __syncthreads();
+  V acc[RT][TN];
+  fdm_mid_pass<T, RT, TN>(SyTw, Bt, MT, MT, nw, w, lane, acc);
+  // U = acc ./ (ly_i + lx_n + c_p) into LDS (rows >= Ny and columns past the end: 0)
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int mt = w + nw * rt;
+    if (mt >= MT) continue;
+#pragma unroll
+    for (int ct = 0; ct < TN; ++ct) {
+      const int j = 16 * ct + r16;
+      const long ci = c0 + j;
+      const long cc = ci < ctot ? ci : ctot - 1;
+      const long p = cc / Nx;
+      const int n = (int)(cc - p * Nx);
+      const double lxs = lx[n] + shift[p];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 16 * mt + Mfma<T>::row(g, q);
+        const int ic = i < Ny ? i : Ny - 1;
+        const double den = ly[ic] + lxs;
+        const T u = (i < Ny && ci < ctot && den != 0.0) ? T(double(acc[rt][ct][q]) / den) : T(0);
+        Us[i * LDC + j] = u;
+      }
+    }
+  }
+  __syncthreads();
+  fdm_mid_pass<T, RT, TN>(Syw, Us, MT, MT, nw, w, lane, acc);
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int mt = w + nw * rt;
+    if (mt >= MT) continue;
+#pragma unroll
+    for (int ct = 0; ct < TN; ++ct) {
+      const long ci = c0 + 16 * ct + r16;
+      if (ci >= ctot) continue;
+      const long p = ci / Nx;
+      const int n = (int)(ci - p * Nx);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 16 * mt + Mfma<T>::row(g, q);
+        if (i < Ny) T3[p * Ng + (long)i * Nx + n] = acc[rt][ct][q];
+      }
+    }
+  }
+}
+
+// launch of k_fdm_mid for the y-direction operator dy; false if it does not apply (LDS)
+template <typename T>
+static bool fdm_mid_launch(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const double* shift, int P, const T* t1,
+                           T* t3, int tn) {
+  const int Ny = c->Ny, Nx = c->Nx;
+  const int KP = (Ny + 15) & ~15, MT = KP / 16;
+  const int RT = (MT + 15) / 16;
+  const int nw = (MT + RT - 1) / RT;
+  const size_t lds = 2 * sizeof(T) * (size_t)KP * FDM_MID_LDC(16 * tn);
+  if (lds > GEMM_LDS_MAX || RT > 2 || (tn != 1 && tn != 2)) return false;
+  const T* SyTw = pick<T>(dy.fSTw, dy.dSTw);
+  const T* Syw = pick<T>(dy.fSw, dy.dSw);
+  const long ctot = (long)P * Nx;
+  const dim3 grid((unsigned)((ctot + 16 * tn - 1) / (16 * tn))), block(64 * nw);
+  const int cls = sizeof(T) == 8 ? PFD_PROF_GEMM64 : PFD_PROF_GEMM32;
+#define MID_CASE(RT_, TN_)                                                                                   \
+  if (RT == RT_ && tn == TN_)                                                                                \
+    LAUNCH(cls, (k_fdm_mid<T, RT_, TN_>), grid, block, lds, c->stream, P, Ny, Nx, c->Ng, SyTw, Syw, t1, dy.dlam, \
+           dx.dlam, shift, t3);
+  MID_CASE(1, 1) MID_CASE(1, 2) MID_CASE(2, 1) MID_CASE(2, 2)
+#undef MID_CASE
+  return true;
+}
+
 // Fast-diagonalisation correction  x += Sy [ (Sy^T r Sx) ./ (ly_i + lx_j + c_p) ] Sx^T
-// as four batched GEMMs over all planes (Sx, Sy shared by every plane).
+// as four batched GEMMs over all planes (Sx, Sy shared by every plane); variant 1: two fused
+// strip kernels; variant 2: the two middle passes fused (three launches).
 template <typename T>
 static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const double* shift, const T* Sx,
                         const T* SxT, const T* Sy, const T* SyT, const double* r, double* x,
@@ -1715,8 +1903,12 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
     return;
   }
   gemm<T, double, T, 0>(c, PFD_GS_P1, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr, nullptr, nullptr);
-  gemm<T, T, T, 1>(c, PFD_GS_P2, P, SyT, 0, t1, Ng, Ny, Nx, Ny, t2, Ng, dy.dlam, dx.dlam, shift, nullptr);
-  gemm<T, T, T, 0>(c, PFD_GS_P3, P, Sy, 0, t2, Ng, Ny, Nx, Ny, t1, Ng, nullptr, nullptr, nullptr, nullptr);
+  if (!(c->fdm_variant == 2 && fdm_mid_launch<T>(c, dx, dy, shift, P, t1, t2, c->mid_tn))) {
+    gemm<T, T, T, 1>(c, PFD_GS_P2, P, SyT, 0, t1, Ng, Ny, Nx, Ny, t2, Ng, dy.dlam, dx.dlam, shift, nullptr);
+    gemm<T, T, T, 0>(c, PFD_GS_P3, P, Sy, 0, t2, Ng, Ny, Nx, Ny, t1, Ng, nullptr, nullptr, nullptr, nullptr);
+  } else {
+    std::swap(t1, t2);   // the fused passes wrote T3 to t2
+  }
   if (overwrite)
     gemm<T, T, T, 3>(c, PFD_GS_P4, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr, nullptr, nullptr, x);
   else
@@ -1865,10 +2057,10 @@ hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us) {
   for (int i = 0; i < reps; ++i) {
     if (cls == PFD_PROF_GEMM32) {
       fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, c->r, scratch);
-      per = c->fdm_variant == 1 ? 2 : 4;
+      per = c->fdm_variant == 1 ? 2 : (c->fdm_variant == 2 ? 3 : 4);
     } else if (cls == PFD_PROF_GEMM64) {
       fdm_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, c->r, scratch);
-      per = c->fdm_variant == 1 ? 2 : 4;
+      per = c->fdm_variant == 1 ? 2 : (c->fdm_variant == 2 ? 3 : 4);
     } else {
       residual(c, PFD_FAM_U, c->b[1], scratch, c->r + 2 * (long)c->planes * c->Ng, 0, nullptr);
     }
@@ -1892,12 +2084,6 @@ static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, c
 // shapes with scratch operands, and the fastest is kept; then one velocity-family correction
 // with the tuned passes is timed against the fused strip kernels and the faster variant kept.
 // Scratch buffers only; the state is not touched.
-template <typename T>
-static const T* pick(const float* f, const double* d);
-template <>
-const float* pick<float>(const float* f, const double*) { return f; }
-template <>
-const double* pick<double>(const float*, const double* d) { return d; }
 
 static double time_us(pfd_ctx* c, hipEvent_t e0, hipEvent_t e1, int reps, const std::function<void()>& f,
                       hipError_t& e) {
@@ -2002,20 +2188,36 @@ hipError_t autotune(pfd_ctx* c) {
     c->resid_us[v] = time_us(c, e0, e1, 10, run, e);
   }
   c->resid_variant = (c->resid_us[1] <= c->resid_us[0]) ? 1 : 0;
+  auto run_fdm = [&]() {
+    if (fp32)
+      fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, c->zero_buf, c->b[2]);
+    else
+      fdm_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, c->zero_buf, c->b[2]);
+  };
   for (int v = 0; v < 2 && !e; ++v) {
     c->fdm_variant = v;
-    auto run = [&]() {
-      if (fp32)
-        fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, c->zero_buf, c->b[2]);
-      else
-        fdm_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, c->zero_buf, c->b[2]);
-    };
-    c->fdm_us[v] = time_us(c, e0, e1, 10, run, e);
+    c->fdm_us[v] = time_us(c, e0, e1, 10, run_fdm, e);
+  }
+  {   // fused middle passes: the column-block width with the faster correction
+    c->fdm_variant = 2;
+    c->fdm_us[2] = 0.0;
+    for (int tn = 1; tn <= 2 && !e; ++tn) {
+      const size_t lds = 2 * (fp32 ? 4 : 8) * (size_t)((c->Ny + 15) & ~15) * FDM_MID_LDC(16 * tn);
+      if (lds > GEMM_LDS_MAX) continue;
+      c->mid_tn = tn;
+      const double us = time_us(c, e0, e1, 10, run_fdm, e);
+      if (c->fdm_us[2] == 0.0 || us < c->fdm_us[2]) {
+        c->fdm_us[2] = us;
+        c->mid_best_tn = tn;
+      }
+    }
+    c->mid_tn = c->mid_best_tn;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->prof_on = saved;
   c->fdm_variant = (c->fdm_us[1] <= c->fdm_us[0]) ? 1 : 0;
+  if (c->fdm_us[2] > 0.0 && c->fdm_us[2] < c->fdm_us[c->fdm_variant]) c->fdm_variant = 2;
   if (!e) e = hipGetLastError();
   return e;
 }

@@ -42,7 +42,7 @@ def packed_mode(p, Nz):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_3d_mode_solves_match_sparse_lu(precision, variant):
     """Every per-mode operator K + (c_f + beta_k^2) M (eqs. 74-78), including the k = 0
     singular pressure and the Nyquist mode, against SciPy LU on random data."""

@@ -38,7 +38,7 @@ def box_case(n=4, K=6, periodic=False, top=WALL, par=None):
 # ------------------------------------------------------------------ solver (P8)
 @pytest.mark.parametrize("periodic,top", [(False, WALL), (True, OPEN)])
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_solve_matches_sparse_lu(periodic, top, precision, variant):
     """Each constant operator K + c M (families V, psi, phi, P, u) solved by the
     library matches SciPy's sparse LU of the assembled matrix on random data,
@@ -293,9 +293,9 @@ def test_nonfinite_state_is_reported():
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_solver_variants_agree_on_benchmark_shapes(precision):
-    """Both fast-diagonalisation kernel variants (four GEMM passes; fused strips) on the
-    benchmark configuration's shapes (4 planes of 161 x 161, K = 8): the same solution of
-    every family up to rounding, and the autotuner's choice is one of them."""
+    """The fast-diagonalisation kernel variants (four GEMM passes; fused strips; fused middle
+    passes) on the benchmark configuration's shapes (4 planes of 161 x 161, K = 8): the same
+    solution of every family up to rounding, and the autotuner's choice is one of them."""
     torch = _torch()
     from synth import C2, c2_param_dict
     import paper_2305_09020_amd as pfd
@@ -304,20 +304,49 @@ def test_solver_variants_agree_on_benchmark_shapes(precision):
                             precision=precision, refine_iters=3)
     ctx = pfd.Context(prob)
     v, us = ctx.solver_variant()
-    assert v in (0, 1) and us[0] > 0 and us[1] > 0
+    assert v in (0, 1, 2) and us[0] > 0 and us[1] > 0 and us[2] > 0
     rng = np.random.default_rng(3)
     n = ctx.planes * ctx.Ny * ctx.Nx
     for fam in range(5):
         b = torch.tensor(rng.standard_normal(n), device="cuda")
         g = torch.tensor(rng.standard_normal(n), device="cuda")
         out = []
-        for var in (0, 1):
+        for var in (0, 1, 2):
             ctx.set_solver_variant(var)
             x = g.clone()
             ctx.solve(fam, b, x)
             out.append(x.cpu().numpy())
-        e = rel_err(out[1], out[0])
-        assert e < (1e-12 if precision == 0 else 1e-9), (fam, e)
+        for var in (1, 2):
+            e = rel_err(out[var], out[0])
+            assert e < (1e-12 if precision == 0 else 1e-9), (fam, var, e)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_middle_passes_tall_mesh(precision):
+    """A mesh with Ny = 265 (more than 16 row tiles, so a wave of the fused middle-pass
+    kernel takes two; in FP64 its LDS block does not fit and the variant falls back to the
+    four passes): every family solves to the sparse-LU solution with variant 2."""
+    torch = _torch()
+    xb = np.linspace(0.0, 0.2, 3)
+    yb = np.linspace(0.0, 1.0, 34)
+    m = Mesh2D(xb, yb, 8, periodic_x=False)
+    bc = BCs(side={BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}, pot_sides=(BOTTOM, TOP))
+    par = c1_params()
+    sch = Scheme(m, par, bc)
+    ctx = gpu_context(m, par, bc, precision=precision, refine_iters=3)
+    assert ctx.Ny == 265
+    ctx.set_solver_variant(2)
+    rng = np.random.default_rng(29)
+    tol = 1e-11 if precision == 0 else 1e-9
+    for fam, name in enumerate(("V", "psi", "phi", "P", "u")):
+        b = rng.standard_normal(m.Ng)
+        g = rng.standard_normal(m.Ng)
+        xr = sch.solve(name, 0, b, g)
+        bt = torch.tensor(b, device="cuda")
+        xt = torch.tensor(g, device="cuda")
+        ctx.solve(fam, bt, xt)
+        torch.cuda.synchronize()
+        assert rel_err(xt.cpu().numpy(), xr) < tol, (name, rel_err(xt.cpu().numpy(), xr))
 
 
 @pytest.mark.parametrize("precision", [0, 1])
