@@ -226,9 +226,16 @@ pfd_status pfd_get_solver_variant(const pfd_ctx* ctx, int* variant, double* us);
 
 /* Kernel of the FP64 residual b - (K + cM) x of the refinement: 0 = one
  * thread per node reading its 2(2K+1) band neighbours through the caches,
- * 1 = rows staged in LDS tiles (used when Nx <= 256 and the tile fits).
- * pfd_create times both and keeps the faster.  The same sums in the same
- * order (results agree to rounding).  Synchronises; drops captured graphs. */
+ * 1 = rows staged in LDS tiles (used when Nx <= 256 and the tile fits),
+ * 2 = as 1 inside the refinement of the FP32-refined path, with the first
+ * fast-diagonalisation pass (the rows times Sx) done in the same launch on
+ * the matrix cores (not with solver variant 1, the electrode gap-node solve
+ * or a singular operator's projection, where 1 is used).  pfd_create times
+ * 0 and 1 and keeps the faster, then (refined contexts) the fused launch
+ * against the separate residual and first pass.  The same sums in the same
+ * order (results agree to rounding).  us[3] of pfd_get_residual_variant: us
+ * per residual of 0 and 1, us per fused launch (0 if not timed).
+ * Synchronises; drops captured graphs. */
 pfd_status pfd_set_residual_variant(pfd_ctx* ctx, int variant);
 pfd_status pfd_get_residual_variant(const pfd_ctx* ctx, int* variant, double* us);
 

@@ -311,14 +311,16 @@ class Context:
         _check(_lib.pfd_set_solver_variant(self.h, int(variant)), self.h)
 
     def set_residual_variant(self, variant):
-        """0: per-node residual kernel, 1: LDS-tiled residual kernel."""
+        """0: per-node residual kernel, 1: LDS-tiled residual kernel, 2: LDS-tiled residual
+        fused with the first fast-diagonalisation pass (refined path)."""
         _check(_lib.pfd_set_residual_variant(self.h, int(variant)), self.h)
 
     def residual_variant(self):
+        """(variant, [us per residual of variants 0 and 1, us per fused residual + first pass])."""
         v = ctypes.c_int(0)
-        us = (ctypes.c_double * 2)()
+        us = (ctypes.c_double * 3)()
         _check(_lib.pfd_get_residual_variant(self.h, ctypes.byref(v), us), self.h)
-        return v.value, [us[0], us[1]]
+        return v.value, [us[0], us[1], us[2]]
 
     def set_gemm_config(self, site, cfg):
         """Force configuration cfg (0..15; 16 = the FFT at site 4) at call site (0..4, -1 = all)."""

@@ -124,13 +124,16 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   dbl += 8 * 3 * NP * NP + 64;           // S, S^T in fragment order, double and float
   dbl += 2 * (size_t)(m.nx + m.ny + 2) + (PFD_KMAX + 1) * (PFD_KMAX + 2);
   dbl += 48 * (size_t)L->planes + 1280;  // shifts, norms, reductions (1024 block maxima)
-  L->bytes = dbl * sizeof(double) + 256 * 128;  // alignment slack
+  L->bytes = dbl * sizeof(double) + 256 * 1024;  // alignment slack (256 B per allocation)
   return PFD_OK;
 }
 
 void* carve(pfd_ctx* c, size_t bytes) {
   size_t off = (c->ws_used + 255) & ~(size_t)255;
-  if (off + bytes > c->ws_bytes) return nullptr;
+  if (off + bytes > c->ws_bytes) {
+    c->ws_fail = true;
+    return nullptr;
+  }
   c->ws_used = off + bytes;
   return c->ws + off;
 }
@@ -323,7 +326,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     d.fSTw = (float*)carve(c, sizeof(float) * NP2);
     d.ddir = (unsigned char*)carve(c, d.N);
   }
-  bool ok = c->fld[0][0] && zero && c->fam[4].dshift;
+  bool ok = !c->ws_fail && c->fld[0][0] && zero && c->fam[4].dshift;
   for (auto& d : c->dirs) ok = ok && d.ddir;
   if (!ok) { g_create_err = "workspace too small (layout)"; delete c; return PFD_ENOMEM; }
   (void)zero;
@@ -772,7 +775,7 @@ extern "C" pfd_status pfd_get_gemm_config(const pfd_ctx* c, int* cfg, double* us
 }
 
 extern "C" pfd_status pfd_set_residual_variant(pfd_ctx* c, int variant) {
-  if (!c || variant < 0 || variant > 1) return PFD_EINVAL;
+  if (!c || variant < 0 || variant > 2) return PFD_EINVAL;
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
   c->resid_variant = variant;
@@ -782,10 +785,8 @@ extern "C" pfd_status pfd_set_residual_variant(pfd_ctx* c, int variant) {
 extern "C" pfd_status pfd_get_residual_variant(const pfd_ctx* c, int* variant, double* us) {
   if (!c) return PFD_EINVAL;
   if (variant) *variant = c->resid_variant;
-  if (us) {
-    us[0] = c->resid_us[0];
-    us[1] = c->resid_us[1];
-  }
+  if (us)
+    for (int v = 0; v < 3; ++v) us[v] = c->resid_us[v];
   return PFD_OK;
 }
 

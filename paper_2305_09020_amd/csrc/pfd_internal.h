@@ -107,6 +107,7 @@ struct pfd_ctx {
   // device buffers
   char* ws = nullptr;
   size_t ws_bytes = 0, ws_used = 0;
+  bool ws_fail = false;                    // some workspace carve did not fit
   double* fld[pfd::F_NSTATE][2] = {};     // state fields, two time levels
   int cur = 0;                             // index of level n
   int set_old[pfd::F_NSTATE] = {};         // level n-1 explicitly set
@@ -139,8 +140,9 @@ struct pfd_ctx {
   // fast-diagonalisation kernels: 0 = four split-K GEMM passes, 1 = two fused strip kernels
   // (chosen by timing both at create)
   int fdm_variant = 1;
-  int resid_variant = 1;                   // residual: 0 = per-node global reads, 1 = LDS tiles
-  double resid_us[2] = {0.0, 0.0};
+  int resid_variant = 1;                   // residual: 0 = per-node global reads, 1 = LDS tiles,
+                                           // 2 = LDS tiles fused with the first FDM pass (refined)
+  double resid_us[3] = {0.0, 0.0, 0.0};
   double fdm_us[3] = {0.0, 0.0, 0.0};      // autotune timings (us per correction)
   int mid_tn = 1, mid_best_tn = 1;         // column tiles per work-group of the fused middle passes
   int gemm_cfg[PFD_GS_N][2] = {};          // tile configuration per (call site, FP32/FP64)

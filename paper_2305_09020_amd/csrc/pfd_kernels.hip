@@ -707,20 +707,21 @@ __global__ void k_residual(int Nx, int Ny, int planes, int perx, const double* _
 // coefficients of the column and the RROWS+2K values of x down the column sit in registers, so
 // the y-sums of all RROWS rows come from that window, and only the x-neighbours are read from
 // LDS.  All global loads (b of every row included) are issued before the row sums.  Needs
-// Nx <= 256 (one column per thread).
+// Nx <= 256 (one column per thread).  res_rows leaves the result of row rl, column ix to
+// out(rl, iy, ix, value); the LDS it uses is res_rows_lds(Nx) doubles from xs.
 #define RROWS 16
-template <int K>
-__global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, const double* __restrict__ KxB,
-                                                      const double* __restrict__ Mx,
-                                                      const unsigned char* __restrict__ dirx,
-                                                      const double* __restrict__ KyB, const double* __restrict__ My,
-                                                      const unsigned char* __restrict__ diry,
-                                                      const double* __restrict__ shift, const double* __restrict__ bb,
-                                                      const double* __restrict__ x, double* __restrict__ r,
-                                                      int apply_only, const unsigned char* __restrict__ ebot) {
+__host__ __device__ constexpr long res_rows_lds(int K, int Nx) {
+  return (long)(RROWS + 2 * K) * Nx + RROWS * (2 * K + 3);
+}
+
+template <int K, class Out>
+__device__ __forceinline__ void res_rows(int Nx, int Ny, int perx, const double* __restrict__ KxB,
+                                         const double* __restrict__ Mx, const unsigned char* __restrict__ dirx,
+                                         const double* __restrict__ KyB, const double* __restrict__ My,
+                                         const unsigned char* __restrict__ diry, const double* __restrict__ shift,
+                                         const double* __restrict__ bb, const double* __restrict__ x, int apply_only,
+                                         const unsigned char* __restrict__ ebot, double* xs, Out out) {
   constexpr int NB = 2 * K + 1, NW = RROWS + 2 * K;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* xs = reinterpret_cast<double*>(smem_raw);   // NW rows x Nx
   double* kyl = xs + NW * Nx;                         // [RROWS][NB] y-band rows iy0..
   double* myl = kyl + RROWS * NB;                     // [RROWS] M_y
   double* dyl = myl + RROWS;                          // [RROWS] Dirichlet flag of the row
@@ -783,16 +784,31 @@ __global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, 
       const double xv = win[rl + K];
       const double my = myl[rl];
       const double Av = ax * my + mx * ay + sh * mx * my * xv;
-      const long id = pl * Ng + (long)iy * Nx + ix;
       if (apply_only) {
-        r[id] = Av;
+        out(rl, iy, ix, Av);
       } else {
         // is_dir: x-Dirichlet column, or a y-Dirichlet row except the gap nodes of the bottom row
         const bool dn = dxn || (dyl[rl] != 0.0 && !(iy == 0 && egap));
-        r[id] = dn ? 0.0 : bv[rl] - Av;
+        out(rl, iy, ix, dn ? 0.0 : bv[rl] - Av);
       }
     }
   }
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, const double* __restrict__ KxB,
+                                                      const double* __restrict__ Mx,
+                                                      const unsigned char* __restrict__ dirx,
+                                                      const double* __restrict__ KyB, const double* __restrict__ My,
+                                                      const unsigned char* __restrict__ diry,
+                                                      const double* __restrict__ shift, const double* __restrict__ bb,
+                                                      const double* __restrict__ x, double* __restrict__ r,
+                                                      int apply_only, const unsigned char* __restrict__ ebot) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* xs = reinterpret_cast<double*>(smem_raw);
+  const long Ng = (long)Nx * Ny, pofs = (long)blockIdx.y * Ng;
+  res_rows<K>(Nx, Ny, perx, KxB, Mx, dirx, KyB, My, diry, shift, bb, x, apply_only, ebot, xs,
+              [&](int, int iy, int ix, double v) { r[pofs + (long)iy * Nx + ix] = v; });
 }
 
 // Batched GEMM on the matrix cores for the fast-diagonalisation passes:
@@ -1666,8 +1682,8 @@ static void residual(pfd_ctx* c, int fam, const double* b, const double* x, doub
   Dir1D& dy = c->dirs[F.iy];
   const int planes = np > 0 ? np : c->planes;   // np: stacked components as extra planes
   const long tot = (long)planes * c->Ng;
-  const size_t lds = sizeof(double) * ((size_t)(RROWS + 2 * c->K) * c->Nx + RROWS * (2 * c->K + 3));
-  const bool tiled = !norms && c->Nx <= 256 && lds <= 64 * 1024 && c->resid_variant == 1;
+  const size_t lds = sizeof(double) * (size_t)res_rows_lds(c->K, c->Nx);
+  const bool tiled = !norms && c->Nx <= 256 && lds <= 64 * 1024 && c->resid_variant >= 1;
 #define RES_CASE(KK)                                                                                      \
   case KK:                                                                                                \
     if (tiled)                                                                                            \
@@ -1734,41 +1750,54 @@ template <typename T, int RT, int TN>
 __device__ __forceinline__ void fdm_mid_pass(const T* __restrict__ Aw, const T* Bl, int KS, int MT, int nw, int w,
                                              int lane, typename Mfma<T>::V (&acc)[RT][TN]) {
   typedef typename Mfma<T>::V V;
-  constexpr int LDC = FDM_MID_LDC(16 * TN);
+  constexpr int LDC = FDM_MID_LDC(16 * TN), CH = 4;   // slices per prefetched chunk
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < TN; ++ct) acc[rt][ct] = V{T(0), T(0), T(0), T(0)};
-  T a[RT][4], an[RT][4];
-  auto loadA = [&](int sl, T (&aa)[RT][4]) {
+  T a[CH][RT][4], an[CH][RT][4];
+  // fragments of CH consecutive slices (clamped in range; those past KS are not multiplied)
+  auto loadA = [&](int c0, T (&aa)[CH][RT][4]) {
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      const int mt = min(w + nw * rt, MT - 1);   // clamped; tiles past MT are not multiplied
-      Vec4<T>::load(Aw + ((long)(mt * KS + sl) * 64 + lane) * 4, aa[rt]);
+    for (int q = 0; q < CH; ++q) {
+      const int sl = min(c0 + q, KS - 1);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const int mt = min(w + nw * rt, MT - 1);   // tiles past MT are not multiplied either
+        Vec4<T>::load(Aw + ((long)(mt * KS + sl) * 64 + lane) * 4, aa[q][rt]);
+      }
     }
   };
   loadA(0, a);
-  for (int sl = 0; sl < KS; ++sl) {
-    if (sl + 1 < KS) loadA(sl + 1, an);
-    T b[TN][4];
+  for (int c0 = 0; c0 < KS; c0 += CH) {
+    if (c0 + CH < KS) loadA(c0 + CH, an);
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int ct = 0; ct < TN; ++ct) b[ct][s] = Bl[(16 * sl + 4 * g + s) * LDC + 16 * ct + r16];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      if (w + nw * rt < MT) {
+    for (int q = 0; q < CH; ++q) {
+      const int sl = c0 + q;
+      if (sl < KS) {
+        T b[TN][4];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int ct = 0; ct < TN; ++ct) acc[rt][ct] = Mfma<T>::op(a[rt][s], b[ct][s], acc[rt][ct]);
+          for (int ct = 0; ct < TN; ++ct) b[ct][s] = Bl[(16 * sl + 4 * g + s) * LDC + 16 * ct + r16];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          if (w + nw * rt < MT) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+              for (int ct = 0; ct < TN; ++ct) acc[rt][ct] = Mfma<T>::op(a[q][rt][s], b[ct][s], acc[rt][ct]);
+          }
+        }
       }
     }
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int q = 0; q < CH; ++q)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) a[rt][s] = an[rt][s];
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[q][rt][s] = an[q][rt][s];
   }
 }
 
@@ -1864,7 +1893,7 @@ static bool fdm_mid_launch(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const d
   const int RT = (MT + 15) / 16;
   const int nw = (MT + RT - 1) / RT;
   const size_t lds = 2 * sizeof(T) * (size_t)KP * FDM_MID_LDC(16 * tn);
-  if (lds > GEMM_LDS_MAX || RT > 2 || (tn != 1 && tn != 2)) return false;
+  if (lds > GEMM_LDS_MAX || RT > 2 || (RT == 2 && sizeof(T) == 8) || (tn != 1 && tn != 2)) return false;
   const T* SyTw = pick<T>(dy.fSTw, dy.dSTw);
   const T* Syw = pick<T>(dy.fSw, dy.dSw);
   const long ctot = (long)P * Nx;
@@ -1874,9 +1903,108 @@ static bool fdm_mid_launch(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const d
   if (RT == RT_ && tn == TN_)                                                                                \
     LAUNCH(cls, (k_fdm_mid<T, RT_, TN_>), grid, block, lds, c->stream, P, Ny, Nx, c->Ng, SyTw, Syw, t1, dy.dlam, \
            dx.dlam, shift, t3);
-  MID_CASE(1, 1) MID_CASE(1, 2) MID_CASE(2, 1) MID_CASE(2, 2)
+  MID_CASE(1, 1) MID_CASE(1, 2)
+  if constexpr (sizeof(T) == 4) {   // two row tiles per wave only where the FP32 block fits
+    MID_CASE(2, 1) MID_CASE(2, 2)
+  }
 #undef MID_CASE
   return true;
+}
+
+// The refined path's FP64 residual of RROWS rows fused with the first fast-diagonalisation
+// pass: T1[rows] = float(b - A x)[rows] Sx.  The residual rows (res_rows) go to LDS in FP32,
+// zero past Ny and Nx, and the rows x Sx product runs on the matrix cores, each wave taking
+// column tiles w, w + 4, ...  Sx comes in B-fragment order, which is the fragment order of
+// Sx^T as a left operand (frag_layout of S^T): for column tile nt, slice sl and lane, the four
+// entries Sx[16 sl + 4 (lane / 16) + s][16 nt + lane % 16].
+#define RESP1_NTW 4   // column tiles per wave (Nx <= 256)
+template <int K>
+__global__ void __launch_bounds__(256) k_res_p1(int Nx, int Ny, int perx, const double* __restrict__ KxB,
+                                                const double* __restrict__ Mx, const unsigned char* __restrict__ dirx,
+                                                const double* __restrict__ KyB, const double* __restrict__ My,
+                                                const unsigned char* __restrict__ diry,
+                                                const double* __restrict__ shift, const double* __restrict__ bb,
+                                                const double* __restrict__ x, const unsigned char* __restrict__ ebot,
+                                                const float* __restrict__ SxB, float* __restrict__ T1) {
+  typedef Mfma<float>::V V;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* xs = reinterpret_cast<double*>(smem_raw);
+  const int KPX = (Nx + 15) & ~15, KS = KPX / 16, LDR = KPX + 4;
+  float* Rl = reinterpret_cast<float*>(xs + res_rows_lds(K, Nx));   // [RROWS][LDR]
+  for (int idx = threadIdx.x; idx < RROWS * LDR; idx += 256) Rl[idx] = 0.0f;
+  __syncthreads();   // zero fill before the residual rows land (res_rows syncs after its staging)
+  res_rows<K>(Nx, Ny, perx, KxB, Mx, dirx, KyB, My, diry, shift, bb, x, 0, ebot, xs,
+              [&](int rl, int, int ix, double v) { Rl[rl * LDR + ix] = float(v); });
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r16 = lane & 15, g = lane >> 4;
+  const int NT = KS;   // column tiles of the square product
+  V acc[RESP1_NTW];
+#pragma unroll
+  for (int j = 0; j < RESP1_NTW; ++j) acc[j] = V{0.f, 0.f, 0.f, 0.f};
+  float bq[RESP1_NTW][4], bn[RESP1_NTW][4];
+  auto loadB = [&](int sl, float (&bb)[RESP1_NTW][4]) {   // tiles past NT clamped, not multiplied
+#pragma unroll
+    for (int j = 0; j < RESP1_NTW; ++j) {
+      const int nt = min(w + 4 * j, NT - 1);
+      Vec4<float>::load(SxB + ((long)(nt * KS + sl) * 64 + lane) * 4, bb[j]);
+    }
+  };
+  loadB(0, bq);
+  for (int sl = 0; sl < KS; ++sl) {
+    if (sl + 1 < KS) loadB(sl + 1, bn);
+    const Mfma<float>::V av = *reinterpret_cast<const Mfma<float>::V*>(Rl + r16 * LDR + 16 * sl + 4 * g);
+#pragma unroll
+    for (int j = 0; j < RESP1_NTW; ++j) {
+      if (w + 4 * j < NT) {
+        acc[j] = Mfma<float>::op(av.x, bq[j][0], acc[j]);
+        acc[j] = Mfma<float>::op(av.y, bq[j][1], acc[j]);
+        acc[j] = Mfma<float>::op(av.z, bq[j][2], acc[j]);
+        acc[j] = Mfma<float>::op(av.w, bq[j][3], acc[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < RESP1_NTW; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bq[j][q] = bn[j][q];
+  }
+  const long Ng = (long)Nx * Ny, pofs = (long)blockIdx.y * Ng;
+  const int iy0 = blockIdx.x * RROWS;
+#pragma unroll
+  for (int j = 0; j < RESP1_NTW; ++j) {
+    const int nt = w + 4 * j;
+    const int n = 16 * nt + r16;
+    if (nt >= NT || n >= Nx) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int iy = iy0 + Mfma<float>::row(g, q);
+      if (iy < Ny) T1[pofs + (long)iy * Nx + n] = acc[j][q];
+    }
+  }
+}
+
+// refined path: T1 = float(b - A x) Sx for family fam in one launch (k_res_p1); false where it
+// does not apply (Nx > 256 or the LDS tile too large)
+static bool res_p1_launch(pfd_ctx* c, int fam, const double* b, const double* x, int np, float* t1) {
+  Family& F = c->fam[fam];
+  const Dir1D& dx = c->dirs[F.ix];
+  const Dir1D& dy = c->dirs[F.iy];
+  const int KPX = (c->Nx + 15) & ~15;
+  const size_t lds = sizeof(double) * (size_t)res_rows_lds(c->K, c->Nx) + sizeof(float) * RROWS * (KPX + 4);
+  if (c->Nx > 256 || lds > 64 * 1024) return false;
+  const dim3 grid((c->Ny + RROWS - 1) / RROWS, np);
+#define RP1_CASE(KK)                                                                                        \
+  case KK:                                                                                                  \
+    LAUNCH(PFD_PROF_RESID, k_res_p1<KK>, grid, dim3(256), lds, c->stream, c->Nx, c->Ny, (int)dx.periodic, dx.dKb, \
+           dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, (const double*)F.dshift, b, x, c->lift[fam].ebot,          \
+           (const float*)dx.fSTw, t1);                                                                      \
+    return true;
+  switch (c->K) {
+    RP1_CASE(2) RP1_CASE(3) RP1_CASE(4) RP1_CASE(5) RP1_CASE(6) RP1_CASE(7) RP1_CASE(8) RP1_CASE(9)
+    RP1_CASE(10) RP1_CASE(11) RP1_CASE(12) RP1_CASE(13) RP1_CASE(14) RP1_CASE(15) RP1_CASE(16)
+  }
+#undef RP1_CASE
+  return false;
 }
 
 // Fast-diagonalisation correction  x += Sy [ (Sy^T r Sx) ./ (ly_i + lx_j + c_p) ] Sx^T
@@ -1885,7 +2013,7 @@ static bool fdm_mid_launch(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const d
 template <typename T>
 static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const double* shift, const T* Sx,
                         const T* SxT, const T* Sy, const T* SyT, const double* r, double* x,
-                        bool overwrite = false, int np = 0) {
+                        bool overwrite = false, int np = 0, bool t1_ready = false) {
   const int Nx = c->Nx, Ny = c->Ny, P = np > 0 ? np : c->planes;   // np: stacked components
   const long Ng = c->Ng;
   T* t1 = reinterpret_cast<T*>(c->tmp);
@@ -1902,7 +2030,8 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
              (const T*)t1, Sy, Sx, x);
     return;
   }
-  gemm<T, double, T, 0>(c, PFD_GS_P1, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr, nullptr, nullptr);
+  if (!t1_ready)   // else the first pass came with the residual (k_res_p1)
+    gemm<T, double, T, 0>(c, PFD_GS_P1, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr, nullptr, nullptr);
   if (!(c->fdm_variant == 2 && fdm_mid_launch<T>(c, dx, dy, shift, P, t1, t2, c->mid_tn))) {
     gemm<T, T, T, 1>(c, PFD_GS_P2, P, SyT, 0, t1, Ng, Ny, Nx, Ny, t2, Ng, dy.dlam, dx.dlam, shift, nullptr);
     gemm<T, T, T, 0>(c, PFD_GS_P3, P, Sy, 0, t2, Ng, Ny, Nx, Ny, t1, Ng, nullptr, nullptr, nullptr, nullptr);
@@ -2003,8 +2132,12 @@ hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp, int
     double* xc = x + gi * tot;
     for (int it = 0; it < iters; ++it) {
       const double* rin = c->r;
+      bool t1_ready = false;   // residual fused with the first pass (refined path, variant 2)
       if (it == 0 && r0) {
         rin = r0 + gi * tot;
+      } else if (fp32 && !elec && c->resid_variant == 2 && c->fdm_variant != 1 && !(F.any_singular && project) &&
+                 res_p1_launch(c, fam, bc, xc, np, reinterpret_cast<float*>(c->tmp))) {
+        t1_ready = true;
       } else {
         residual(c, fam, bc, xc, c->r, 0, nullptr, nullptr, np);
         if (F.any_singular && project) plane_fix(c, fam, c->r, 1);
@@ -2014,7 +2147,7 @@ hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp, int
       else if (elec)
         elec_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, rin, xc);
       else if (fp32)
-        fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, rin, xc, false, np);
+        fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, rin, xc, false, np, t1_ready);
       else
         fdm_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, rin, xc, false, np);
     }
@@ -2213,11 +2346,29 @@ hipError_t autotune(pfd_ctx* c) {
     }
     c->mid_tn = c->mid_best_tn;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  c->prof_on = saved;
   c->fdm_variant = (c->fdm_us[1] <= c->fdm_us[0]) ? 1 : 0;
   if (c->fdm_us[2] > 0.0 && c->fdm_us[2] < c->fdm_us[c->fdm_variant]) c->fdm_variant = 2;
+  c->resid_us[2] = 0.0;
+  if (fp32 && c->fdm_variant != 1 && !e) {
+    // residual fused with the first pass against the separate residual and first-pass GEMM
+    float* t1 = reinterpret_cast<float*>(c->tmp);
+    bool ok = true;
+    auto fused = [&]() { ok = res_p1_launch(c, PFD_FAM_U, c->zero_buf, c->b[2], c->planes, t1); };
+    auto separate = [&]() {
+      residual(c, PFD_FAM_U, c->zero_buf, c->b[2], c->r, 0, nullptr);
+      gemm<float, double, float, 0>(c, PFD_GS_P1, c->planes, c->r, c->Ng, dx.fS, 0, c->Ny, c->Nx, c->Nx, t1,
+                                    c->Ng, nullptr, nullptr, nullptr, nullptr);
+    };
+    const double us_f = time_us(c, e0, e1, 10, fused, e);
+    const double us_s = time_us(c, e0, e1, 10, separate, e);
+    if (ok) {
+      c->resid_us[2] = us_f;
+      if (us_f < us_s) c->resid_variant = 2;
+    }
+  }
+  (void)hipEventDestroy(e0);   // after the last timing that records them
+  (void)hipEventDestroy(e1);
+  c->prof_on = saved;
   if (!e) e = hipGetLastError();
   return e;
 }
