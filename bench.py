@@ -366,6 +366,7 @@ def roofline(ctx, steps, workload="c2", path="refined"):
             "avg_launch_us": avg * 1e6, "avg_launch_us_event_bracketed": avg_bracketed * 1e6,
             "launches_per_step": n / steps, "per_launch": per, "class_time_share": share,
             "solver_variant": variant, "autotune_us_per_correction": tune_us,
+            "residual_variant": ctx.residual_variant()[0], "autotune_us_residual": ctx.residual_variant()[1],
             "gemm_tile_config_per_site": ctx.gemm_config()[0]}
 
 

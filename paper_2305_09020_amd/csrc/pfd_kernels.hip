@@ -1942,31 +1942,44 @@ __global__ void __launch_bounds__(256) k_res_p1(int Nx, int Ny, int perx, const 
   V acc[RESP1_NTW];
 #pragma unroll
   for (int j = 0; j < RESP1_NTW; ++j) acc[j] = V{0.f, 0.f, 0.f, 0.f};
-  float bq[RESP1_NTW][4], bn[RESP1_NTW][4];
-  auto loadB = [&](int sl, float (&bb)[RESP1_NTW][4]) {   // tiles past NT clamped, not multiplied
+  constexpr int CH = 4;   // slices per prefetched chunk of Sx fragments
+  float bq[CH][RESP1_NTW][4], bn[CH][RESP1_NTW][4];
+  auto loadB = [&](int c0, float (&bb)[CH][RESP1_NTW][4]) {   // clamped; past KS / NT not multiplied
 #pragma unroll
-    for (int j = 0; j < RESP1_NTW; ++j) {
-      const int nt = min(w + 4 * j, NT - 1);
-      Vec4<float>::load(SxB + ((long)(nt * KS + sl) * 64 + lane) * 4, bb[j]);
+    for (int q = 0; q < CH; ++q) {
+      const int sl = min(c0 + q, KS - 1);
+#pragma unroll
+      for (int j = 0; j < RESP1_NTW; ++j) {
+        const int nt = min(w + 4 * j, NT - 1);
+        Vec4<float>::load(SxB + ((long)(nt * KS + sl) * 64 + lane) * 4, bb[q][j]);
+      }
     }
   };
   loadB(0, bq);
-  for (int sl = 0; sl < KS; ++sl) {
-    if (sl + 1 < KS) loadB(sl + 1, bn);
-    const Mfma<float>::V av = *reinterpret_cast<const Mfma<float>::V*>(Rl + r16 * LDR + 16 * sl + 4 * g);
+  for (int c0 = 0; c0 < KS; c0 += CH) {
+    if (c0 + CH < KS) loadB(c0 + CH, bn);
 #pragma unroll
-    for (int j = 0; j < RESP1_NTW; ++j) {
-      if (w + 4 * j < NT) {
-        acc[j] = Mfma<float>::op(av.x, bq[j][0], acc[j]);
-        acc[j] = Mfma<float>::op(av.y, bq[j][1], acc[j]);
-        acc[j] = Mfma<float>::op(av.z, bq[j][2], acc[j]);
-        acc[j] = Mfma<float>::op(av.w, bq[j][3], acc[j]);
+    for (int q = 0; q < CH; ++q) {
+      const int sl = c0 + q;
+      if (sl < KS) {
+        const Mfma<float>::V av = *reinterpret_cast<const Mfma<float>::V*>(Rl + r16 * LDR + 16 * sl + 4 * g);
+#pragma unroll
+        for (int j = 0; j < RESP1_NTW; ++j) {
+          if (w + 4 * j < NT) {
+            acc[j] = Mfma<float>::op(av.x, bq[q][j][0], acc[j]);
+            acc[j] = Mfma<float>::op(av.y, bq[q][j][1], acc[j]);
+            acc[j] = Mfma<float>::op(av.z, bq[q][j][2], acc[j]);
+            acc[j] = Mfma<float>::op(av.w, bq[q][j][3], acc[j]);
+          }
+        }
       }
     }
 #pragma unroll
-    for (int j = 0; j < RESP1_NTW; ++j)
+    for (int q = 0; q < CH; ++q)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) bq[j][q] = bn[j][q];
+      for (int j = 0; j < RESP1_NTW; ++j)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bq[q][j][k] = bn[q][j][k];
   }
   const long Ng = (long)Nx * Ny, pofs = (long)blockIdx.y * Ng;
   const int iy0 = blockIdx.x * RROWS;
