@@ -12,7 +12,7 @@ import sys
 
 CLASSES = [("gemm64", lambda n: ("k_gemm" in n or "k_fdm" in n) and ("<double" in n or "IdE" in n)),
            ("gemm32", lambda n: ("k_gemm" in n or "k_fdm" in n) and ("<float" in n or "IfE" in n)),
-           ("residual", lambda n: "k_residual" in n),
+           ("residual", lambda n: "k_residual" in n or "k_res_p1" in n),
            ("zfft", lambda n: "k_zfft" in n),
            ("element", lambda n: "_elem" in n),
            ("nodal", lambda n: "_rhs" in n or "k_E_nodal" in n or "k_Phi_hat3" in n or "k_phi_bnd3" in n)]
