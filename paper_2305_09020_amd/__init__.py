@@ -108,6 +108,8 @@ _sig = {
     "pfd_ws_predict": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, _vp]),
     "pfd_set_gemm_config": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "pfd_set_residual_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "pfd_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "pfd_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
     "pfd_get_residual_variant": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int),
                                                 ctypes.POINTER(ctypes.c_double)]),
     "pfd_get_gemm_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
@@ -309,6 +311,18 @@ class Context:
         """0: four GEMM passes, 1: fused strip kernels, 2: fused middle passes (three
         launches), -1: autotune again."""
         _check(_lib.pfd_set_solver_variant(self.h, int(variant)), self.h)
+
+    def tuning(self):
+        """The autotuner's choices (opaque list of ints) for set_tuning on another context."""
+        cnt = ctypes.c_int(0)
+        _check(_lib.pfd_get_tuning(self.h, None, 0, ctypes.byref(cnt)), self.h)
+        vals = (ctypes.c_int * cnt.value)()
+        _check(_lib.pfd_get_tuning(self.h, vals, cnt.value, ctypes.byref(cnt)), self.h)
+        return list(vals)
+
+    def set_tuning(self, vals):
+        arr = (ctypes.c_int * len(vals))(*vals)
+        _check(_lib.pfd_set_tuning(self.h, arr, len(vals)), self.h)
 
     def set_residual_variant(self, variant):
         """0: per-node residual kernel, 1: LDS-tiled residual kernel, 2: LDS-tiled residual

@@ -145,6 +145,7 @@ struct pfd_ctx {
   double resid_us[3] = {0.0, 0.0, 0.0};
   double fdm_us[3] = {0.0, 0.0, 0.0};      // autotune timings (us per correction)
   int mid_tn = 1, mid_best_tn = 1;         // column tiles per work-group of the fused middle passes
+  int p4_tg = 0;                           // refined last pass: 0 = GEMM, else k_p4 column tiles per wave
   int gemm_cfg[PFD_GS_N][2] = {};          // tile configuration per (call site, FP32/FP64)
   double gemm_us[PFD_GS_N][2][PFD_GEMM_NCFG] = {};  // autotune timings per configuration
   hipStream_t cap_stream = nullptr;        // capture stream (the caller's may be the null stream)

@@ -1805,7 +1805,7 @@ template <typename T, int RT, int TN>
 __global__ void __launch_bounds__(1024) k_fdm_mid(int planes, int Ny, int Nx, long Ng, const T* __restrict__ SyTw,
                                                   const T* __restrict__ Syw, const T* __restrict__ T1,
                                                   const double* __restrict__ ly, const double* __restrict__ lx,
-                                                  const double* __restrict__ shift, T* __restrict__ T3) {
+                                                  const double* __restrict__ shift, T* __restrict__ T3, int ldo) {
   typedef typename Mfma<T>::V V;
   constexpr int CW = 16 * TN, LDC = FDM_MID_LDC(CW);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1878,7 +1878,7 @@ __global__ void __launch_bounds__(1024) k_fdm_mid(int planes, int Ny, int Nx, lo
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = 16 * mt + Mfma<T>::row(g, q);
-        if (i < Ny) T3[p * Ng + (long)i * Nx + n] = acc[rt][ct][q];
+        if (i < Ny) T3[(p * Ny + i) * (long)ldo + n] = acc[rt][ct][q];   // row stride ldo (>= Nx)
       }
     }
   }
@@ -1887,7 +1887,7 @@ __global__ void __launch_bounds__(1024) k_fdm_mid(int planes, int Ny, int Nx, lo
 // launch of k_fdm_mid for the y-direction operator dy; false if it does not apply (LDS)
 template <typename T>
 static bool fdm_mid_launch(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const double* shift, int P, const T* t1,
-                           T* t3, int tn) {
+                           T* t3, int tn, int ldo) {
   const int Ny = c->Ny, Nx = c->Nx;
   const int KP = (Ny + 15) & ~15, MT = KP / 16;
   const int RT = (MT + 15) / 16;
@@ -1902,7 +1902,7 @@ static bool fdm_mid_launch(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const d
 #define MID_CASE(RT_, TN_)                                                                                   \
   if (RT == RT_ && tn == TN_)                                                                                \
     LAUNCH(cls, (k_fdm_mid<T, RT_, TN_>), grid, block, lds, c->stream, P, Ny, Nx, c->Ng, SyTw, Syw, t1, dy.dlam, \
-           dx.dlam, shift, t3);
+           dx.dlam, shift, t3, ldo);
   MID_CASE(1, 1) MID_CASE(1, 2)
   if constexpr (sizeof(T) == 4) {   // two row tiles per wave only where the FP32 block fits
     MID_CASE(2, 1) MID_CASE(2, 2)
@@ -1996,6 +1996,100 @@ __global__ void __launch_bounds__(256) k_res_p1(int Nx, int Ny, int perx, const 
   }
 }
 
+// Last fast-diagonalisation pass of the refined path, x (+)= T3 Sx^T, after k_fdm_mid wrote T3
+// (FP32) with the padded row stride KPX = Nx rounded up to 16: a lane then reads each A fragment
+// (four consecutive contraction entries of its row) with one 16-byte load, and Sx^T comes as
+// right operand in fragment order (which is the fragment order of Sx as a left operand).  A wave
+// takes one 16-row tile of the flattened planes x rows and TG column tiles; contraction entries
+// past Nx are masked to zero.  EPI 2: x += ; EPI 3: x = .
+template <int EPI, int TG>
+__global__ void __launch_bounds__(256) k_p4(const float* __restrict__ T3, int Mtot, int Nx, int KPX,
+                                            const float* __restrict__ SxFw, double* __restrict__ X) {
+  typedef Mfma<float>::V V;
+  const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
+  const int KS = KPX / 16, NT = KS, NG = (NT + TG - 1) / TG, MT = (Mtot + 15) / 16;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  const int rt = wid / NG, grp = wid - rt * NG;
+  if (rt >= MT) return;   // no barrier in this kernel: a whole wave leaves
+  const int m = min(16 * rt + r16, Mtot - 1);   // clamped row; rows past Mtot are not stored
+  const float* Ar = T3 + (long)m * KPX + 4 * g;
+  V acc[TG];
+#pragma unroll
+  for (int j = 0; j < TG; ++j) acc[j] = V{0.f, 0.f, 0.f, 0.f};
+  constexpr int CH = 2;
+  float a[CH][4], an[CH][4], b[CH][TG][4], bn[CH][TG][4];
+  auto load = [&](int c0, float (&aa)[CH][4], float (&bb)[CH][TG][4]) {
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int sl = min(c0 + q, KS - 1);
+      Vec4<float>::load(Ar + 16 * sl, aa[q]);
+#pragma unroll
+      for (int j = 0; j < TG; ++j) {
+        const int nt = min(grp * TG + j, NT - 1);
+        Vec4<float>::load(SxFw + ((long)(nt * KS + sl) * 64 + lane) * 4, bb[q][j]);
+      }
+    }
+  };
+  load(0, a, b);
+  for (int c0 = 0; c0 < KS; c0 += CH) {
+    if (c0 + CH < KS) load(c0 + CH, an, bn);
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int sl = c0 + q;
+      if (sl < KS) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float av = (16 * sl + 4 * g + s < Nx) ? a[q][s] : 0.f;   // padding columns
+#pragma unroll
+          for (int j = 0; j < TG; ++j)
+            if (grp * TG + j < NT) acc[j] = Mfma<float>::op(av, b[q][j][s], acc[j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[q][s] = an[q][s];
+#pragma unroll
+      for (int j = 0; j < TG; ++j)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) b[q][j][s] = bn[q][j][s];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TG; ++j) {
+    const int nt = grp * TG + j;
+    const int n = 16 * nt + r16;
+    if (nt >= NT || n >= Nx) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int mm = 16 * rt + Mfma<float>::row(g, q);
+      if (mm >= Mtot) continue;
+      if (EPI == 2) X[(long)mm * Nx + n] += double(acc[j][q]);
+      else X[(long)mm * Nx + n] = double(acc[j][q]);
+    }
+  }
+}
+
+// k_p4 over P planes (tg column tiles per wave); false where it does not apply
+static bool p4_launch(pfd_ctx* c, const Dir1D& dx, int P, const float* t3, double* x, bool overwrite, int tg) {
+  const int Nx = c->Nx, KPX = (Nx + 15) & ~15, NT = KPX / 16;
+  if (tg < 1 || tg > 4) return false;
+  const long Mtot = (long)P * c->Ny;
+  const long waves = ((Mtot + 15) / 16) * ((NT + tg - 1) / tg);
+  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+#define P4_CASE(TG_)                                                                                       \
+  if (tg == TG_) {                                                                                         \
+    if (overwrite)                                                                                         \
+      LAUNCH(PFD_PROF_GEMM32, (k_p4<3, TG_>), grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x); \
+    else                                                                                                   \
+      LAUNCH(PFD_PROF_GEMM32, (k_p4<2, TG_>), grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x); \
+  }
+  P4_CASE(1) P4_CASE(2) P4_CASE(3) P4_CASE(4)
+#undef P4_CASE
+  return true;
+}
+
 // refined path: T1 = float(b - A x) Sx for family fam in one launch (k_res_p1); false where it
 // does not apply (Nx > 256 or the LDS tile too large)
 static bool res_p1_launch(pfd_ctx* c, int fam, const double* b, const double* x, int np, float* t1) {
@@ -2045,10 +2139,21 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
   }
   if (!t1_ready)   // else the first pass came with the residual (k_res_p1)
     gemm<T, double, T, 0>(c, PFD_GS_P1, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr, nullptr, nullptr);
-  if (!(c->fdm_variant == 2 && fdm_mid_launch<T>(c, dx, dy, shift, P, t1, t2, c->mid_tn))) {
+  // refined path with the fused middle passes: T3 with the padded row stride for k_p4
+  // (the padded FP32 block must fit the scratch buffer: 3 planes-worth of FP64 fields)
+  const bool pad = sizeof(T) == 4 && c->fdm_variant == 2 && c->p4_tg > 0 &&
+                   (long)P * Ny * ((Nx + 15) & ~15) <= 6L * c->planes * Ng;
+  if (!(c->fdm_variant == 2 && fdm_mid_launch<T>(c, dx, dy, shift, P, t1, t2, c->mid_tn,
+                                                 pad ? ((Nx + 15) & ~15) : Nx))) {
     gemm<T, T, T, 1>(c, PFD_GS_P2, P, SyT, 0, t1, Ng, Ny, Nx, Ny, t2, Ng, dy.dlam, dx.dlam, shift, nullptr);
     gemm<T, T, T, 0>(c, PFD_GS_P3, P, Sy, 0, t2, Ng, Ny, Nx, Ny, t1, Ng, nullptr, nullptr, nullptr, nullptr);
   } else {
+    if (pad) {
+      if constexpr (sizeof(T) == 4) {
+        p4_launch(c, dx, P, t2, x, overwrite, c->p4_tg);
+        return;
+      }
+    }
     std::swap(t1, t2);   // the fused passes wrote T3 to t2
   }
   if (overwrite)
@@ -2351,6 +2456,7 @@ hipError_t autotune(pfd_ctx* c) {
       const size_t lds = 2 * (fp32 ? 4 : 8) * (size_t)((c->Ny + 15) & ~15) * FDM_MID_LDC(16 * tn);
       if (lds > GEMM_LDS_MAX) continue;
       c->mid_tn = tn;
+      c->p4_tg = 0;
       const double us = time_us(c, e0, e1, 10, run_fdm, e);
       if (c->fdm_us[2] == 0.0 || us < c->fdm_us[2]) {
         c->fdm_us[2] = us;
@@ -2358,6 +2464,16 @@ hipError_t autotune(pfd_ctx* c) {
       }
     }
     c->mid_tn = c->mid_best_tn;
+    int best_tg = 0;
+    for (int tg = 1; tg <= 4 && fp32 && c->fdm_us[2] > 0.0 && !e; ++tg) {   // the refined last pass
+      c->p4_tg = tg;
+      const double us = time_us(c, e0, e1, 10, run_fdm, e);
+      if (us < c->fdm_us[2]) {
+        c->fdm_us[2] = us;
+        best_tg = tg;
+      }
+    }
+    c->p4_tg = best_tg;
   }
   c->fdm_variant = (c->fdm_us[1] <= c->fdm_us[0]) ? 1 : 0;
   if (c->fdm_us[2] > 0.0 && c->fdm_us[2] < c->fdm_us[c->fdm_variant]) c->fdm_variant = 2;

@@ -23,11 +23,7 @@ def _torch():
 
 def _pin(b, a):
     """Same kernels on b as the autotuner chose for a."""
-    cfg, _ = a.gemm_config()
-    for site, c in enumerate(cfg):
-        b.set_gemm_config(site, c)
-    b.set_solver_variant(a.solver_variant()[0])
-    b.set_residual_variant(a.residual_variant()[0])
+    b.set_tuning(a.tuning())
 
 
 def _instance(n, K, vtop, eps_ratio, precision, nz=0, tune_from=None):

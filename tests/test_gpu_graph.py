@@ -35,11 +35,7 @@ def _pair(nz, precision, electrodes=()):
             for _ in range(2)]
     # the autotuner may pick different kernels for the two contexts (timing noise): pin the
     # second to the first's choice so that both run the same kernels in the same order
-    cfg, _ = ctxs[0].gemm_config()
-    for site, c in enumerate(cfg):
-        ctxs[1].set_gemm_config(site, c)
-    ctxs[1].set_solver_variant(ctxs[0].solver_variant()[0])
-    ctxs[1].set_residual_variant(ctxs[0].residual_variant()[0])
+    ctxs[1].set_tuning(ctxs[0].tuning())
     ctxs[1].set_graph(True)
     planes = nz if nz else 1
     X, Y = m.X.ravel()[None, :], m.Y.ravel()[None, :]

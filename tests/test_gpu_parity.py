@@ -321,6 +321,31 @@ def test_solver_variants_agree_on_benchmark_shapes(precision):
             assert e < (1e-12 if precision == 0 else 1e-9), (fam, var, e)
 
 
+@pytest.mark.parametrize("tg", [0, 1, 2, 3, 4])
+def test_refined_last_pass_every_width(tg):
+    """Refined solves with the fused middle passes and each form of the last pass (GEMM; the
+    padded-row matrix-core kernel with 1-4 column tiles per wave) match SciPy's sparse LU for
+    every family on a 3-plane batch (Nx = 41: three column tiles, the last one ragged)."""
+    torch = _torch()
+    m, bc, par = box_case(n=5, K=8, periodic=True, top=OPEN)
+    sch = Scheme(m, par, bc)
+    ctx = gpu_context(m, par, bc, nbatch=3, precision=1, refine_iters=3)
+    t = ctx.tuning()
+    t[-4] = 2      # fused middle passes
+    t[-1] = tg     # last pass
+    ctx.set_tuning(t)
+    assert ctx.tuning() == t
+    rng = np.random.default_rng(37 + tg)
+    for fam, name in enumerate(("V", "psi", "phi", "P", "u")):
+        b = rng.standard_normal((3, m.Ng))
+        g = rng.standard_normal((3, m.Ng))
+        xr = np.stack([sch.solve(name, 0, b[i], g[i]) for i in range(3)])
+        xt = torch.tensor(g.ravel(), device="cuda")
+        ctx.solve(fam, torch.tensor(b.ravel(), device="cuda"), xt)
+        torch.cuda.synchronize()
+        assert rel_err(xt.cpu().numpy(), xr) < 1e-9, (name, rel_err(xt.cpu().numpy(), xr))
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_fused_middle_passes_tall_mesh(precision):
     """A mesh with Ny = 265 (more than 16 row tiles, so a wave of the fused middle-pass
