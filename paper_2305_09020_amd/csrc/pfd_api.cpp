@@ -113,6 +113,7 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   }
   dbl += 3 * (size_t)Pg;                 // right sides
   dbl += 13 * (size_t)Pg;                // r (3), U, Q2, tmp (3), tmp2 (3), zero, Ybuf
+  dbl += 14 * (size_t)Pg;                // right sides per family and level (u: three components)
   dbl += 15 * (size_t)L->planes + 64;    // family shifts, repeated per stacked component
   dbl += (size_t)L->planes * PFD_STAT_NB * 8;  // diagnostics partials
   if (p->bc.n_electrodes > 0) dbl += (size_t)L->planes * (L->Nx * (size_t)L->Nx + L->Nx) + 4 * (size_t)L->Nx;
@@ -301,6 +302,8 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     for (int i = 0; i < 3; ++i) c->b[i] = blk ? blk + i * Pg : nullptr;
   }
   c->r = D(3 * Pg); c->U = D(Pg); c->Q2 = D(Pg); c->tmp = D(3 * Pg); c->tmp2 = D(3 * Pg);
+  for (int f = 0; f < 5; ++f)
+    for (int l = 0; l < 2; ++l) c->bh[f][l] = D((f == PFD_FAM_U ? 3 : 1) * Pg);
   double* zero = D(Pg);
   c->Ybuf = D(Pg);
   for (int s = 0; s < 4; ++s) c->bm_side[s] = D(c->Ng);
@@ -326,7 +329,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     d.fSTw = (float*)carve(c, sizeof(float) * NP2);
     d.ddir = (unsigned char*)carve(c, d.N);
   }
-  bool ok = !c->ws_fail && c->fld[0][0] && zero && c->fam[4].dshift;
+  bool ok = !c->ws_fail && c->fld[0][0] && zero && c->fam[4].dshift && c->bh[PFD_FAM_U][1];
   for (auto& d : c->dirs) ok = ok && d.ddir;
   if (!ok) { g_create_err = "workspace too small (layout)"; delete c; return PFD_ENOMEM; }
   (void)zero;
@@ -611,6 +614,7 @@ extern "C" pfd_status pfd_set_field(pfd_ctx* c, int f, int level, const double* 
     if (level == 0) HIPCHK(to_spectral(c, c->fld[f][lv], c->spec[f][1 - lv]));
   }
   if (!on_device) HIPCHK(hipStreamSynchronize(c->stream));
+  forget_rhs(c);
   c->failed = 0;
   c->steps = 0;
   HIPCHK(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
@@ -631,6 +635,7 @@ extern "C" pfd_status pfd_set_source(pfd_ctx* c, int s, const double* src, int o
   if (!c || s < 0 || s >= PFD_NSRC) return PFD_EINVAL;
   const size_t bytes = sizeof(double) * c->planes * c->Ng;
   c->src_dirty[s] = 1;
+  forget_rhs(c);
   if (!src) {
     HIPCHK(hipMemsetAsync(c->src[s], 0, bytes, c->stream));
   } else {
@@ -644,6 +649,7 @@ extern "C" pfd_status pfd_set_source(pfd_ctx* c, int s, const double* src, int o
 extern "C" pfd_status pfd_init_potential(pfd_ctx* c, double tol, int max_iter, int* iters) {
   if (!c) return PFD_EINVAL;
   if (max_iter < 1) { c->err = "max_iter must be >= 1"; return PFD_EINVAL; }
+  forget_rhs(c);
   double* A = c->fld[F_V][c->cur];
   double* B = c->fld[F_V][1 - c->cur];
   int it = 0;
@@ -672,6 +678,26 @@ extern "C" pfd_status pfd_init_potential(pfd_ctx* c, double tol, int max_iter, i
   return PFD_OK;
 }
 
+// recycling of the right sides (refined path): state kept on the host, outside any graph
+void pfd::forget_rhs(pfd_ctx* c) {
+  for (int& h : c->bhist) h = 0;
+}
+void pfd::begin_step(pfd_ctx* c, int eq) {
+  const bool refined = c->prob.precision == PFD_REFINED_FP32;
+  bool ok = refined;
+  for (int f = 0; f < 5; ++f)
+    if (!eq || f == PFD_FAM_V || f == PFD_FAM_PSI || f == PFD_FAM_PHI) ok = ok && c->bhist[f] >= 2;
+  c->rec_on = ok;
+}
+void pfd::end_step(pfd_ctx* c, int eq) {
+  for (int f = 0; f < 5; ++f) {
+    const bool solved = !eq || f == PFD_FAM_V || f == PFD_FAM_PSI || f == PFD_FAM_PHI;
+    c->bhist[f] = solved ? std::min(2, c->bhist[f] + 1) : 0;
+  }
+  c->rec_on = false;
+}
+static hipError_t one_step_launch(pfd_ctx* c, int eq);
+
 static void drop_graphs(pfd_ctx* c) {
   for (auto& row : c->gexec)
     for (auto& g : row)
@@ -683,7 +709,17 @@ static void drop_graphs(pfd_ctx* c) {
 
 // one step: eager launches, or the replay of a captured graph of the same launches
 static hipError_t one_step(pfd_ctx* c, int eq) {
-  if (!c->use_graph || c->prof_on || c->check_residual)
+  begin_step(c, eq);
+  hipError_t es = one_step_launch(c, eq);
+  end_step(c, eq);
+  return es;
+}
+
+// one step's launches (begin_step decided whether it recycles the right sides)
+static hipError_t one_step_launch(pfd_ctx* c, int eq) {
+  const bool refined = c->prob.precision == PFD_REFINED_FP32;
+  // graphs hold the recycling form of a refined step only (the two steps before it run eagerly)
+  if (!c->use_graph || c->prof_on || c->check_residual || (refined && !c->rec_on))
     return c->is3d ? step_once_3d(c, eq) : step_once(c, eq);
   if (c->is3d) refresh_spectral_sources(c);  // host-decided transforms stay outside the graph
   const int cur = c->cur;
@@ -730,6 +766,7 @@ extern "C" pfd_status pfd_update_params(pfd_ctx* c, const pfd_params* q) {
   if (!(q->eps1 > 0.0) || !(q->eps2 > 0.0)) { c->err = "permittivities must be positive"; return PFD_EINVAL; }
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);   // kernel arguments change
+  forget_rhs(c);    // and the potential's operator may
   c->prob.par = *q;
   Par& P = c->par;
   P.eps1 = q->eps1;

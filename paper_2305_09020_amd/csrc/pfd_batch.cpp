@@ -133,7 +133,14 @@ extern "C" pfd_status pfd_batch_step(pfd_batch* b, int nsteps, int equilibrium) 
     profiling = profiling || c->prof_on || c->check_residual;
   }
   for (int s = 0; s < nsteps; ++s) {
-    if (!aligned || profiling) {
+    // refined instances recycle their right sides once two steps are recorded; the graph holds
+    // that form only, so until every refined instance is there the steps run eagerly
+    bool rec_ok = true;
+    for (pfd_ctx* c : b->ctx) {
+      begin_step(c, eq);
+      if (c->prob.precision == PFD_REFINED_FP32 && !c->rec_on) rec_ok = false;
+    }
+    if (!aligned || profiling || !rec_ok) {
       // instances at different time-level parities (or instrumented): plain launches in order
       for (pfd_ctx* c : b->ctx) BCHK(eager_step(c, eq));
     } else {
@@ -145,7 +152,10 @@ extern "C" pfd_status pfd_batch_step(pfd_batch* b, int nsteps, int equilibrium) 
       BCHK(hipGraphLaunch(ex, b->stream));
       for (pfd_ctx* c : b->ctx) c->cur = 1 - cur;
     }
-    for (pfd_ctx* c : b->ctx) ++c->steps;
+    for (pfd_ctx* c : b->ctx) {
+      end_step(c, eq);
+      ++c->steps;
+    }
   }
   // non-finite check of every instance (one synchronisation)
   std::vector<int> st(b->ctx.size(), 0);

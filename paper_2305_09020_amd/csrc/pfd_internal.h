@@ -73,6 +73,9 @@ enum { F_UX = 0, F_UY, F_UZ, F_P, F_PHI, F_PSI, F_V, F_EX, F_EY, F_EZ, F_E2, F_N
 struct Lift {
   const double *Kx0, *KxN, *Ky0, *KyN, *Mx, *My, *KxB;
   const unsigned char *dirx, *diry, *ebot;
+  // FP32-refined path, set per launch: the family's right side b^n of the previous step (the
+  // slot written now holds b^{n-1}); the first residual is then b - (cs_n b^n + cs_o b^{n-1})
+  const double* bprev = nullptr;
 };
 
 // gap-node Schur complement data of the potential family (electrode segments)
@@ -146,6 +149,12 @@ struct pfd_ctx {
   double fdm_us[3] = {0.0, 0.0, 0.0};      // autotune timings (us per correction)
   int mid_tn = 1, mid_best_tn = 1;         // column tiles per work-group of the fused middle passes
   int p4_tg = 0;                           // refined last pass: 0 = GEMM, else k_p4 column tiles per wave
+  // right sides of the step's solves per family and time level (u: three components), and how
+  // many consecutive steps solved the family with them (the refined path recycles them for its
+  // first residual once two are recorded: A x^n = b^n to the refinement's accuracy)
+  double* bh[5][2] = {};
+  int bhist[5] = {0, 0, 0, 0, 0};
+  bool rec_on = false;                     // this step recycles (decided before the step)
   int gemm_cfg[PFD_GS_N][2] = {};          // tile configuration per (call site, FP32/FP64)
   double gemm_us[PFD_GS_N][2][PFD_GEMM_NCFG] = {};  // autotune timings per configuration
   hipStream_t cap_stream = nullptr;        // capture stream (the caller's may be the null stream)
@@ -193,6 +202,11 @@ hipError_t stats(pfd_ctx* c, double* out);
 hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us);
 hipError_t autotune(pfd_ctx* c);
 hipError_t step_once_3d(pfd_ctx* c, int equilibrium);
+// right-side recycling state of the refined path (host side): forget after any change of the
+// state, sources or operators; begin_step decides whether a step recycles, end_step records it
+void forget_rhs(pfd_ctx* c);
+void begin_step(pfd_ctx* c, int eq);
+void end_step(pfd_ctx* c, int eq);
 void refresh_spectral_sources(pfd_ctx* c);
 hipError_t potential_iteration_3d(pfd_ctx* c, const double* Vin, double* Vout);
 hipError_t to_spectral(pfd_ctx* c, const double* phys, double* spec);

@@ -170,7 +170,8 @@ __device__ __forceinline__ double dss(const Geo& g, const double* L, int pl, int
 // Right side of a solve and its initial guess.
 //  * warm start (Fn != nullptr, FP32-refined path): x0 = extrapolated history
 //    cs_n Fn + cs_o Fo (Dirichlet data on Dirichlet nodes), so the low-precision
-//    corrections act on a small residual; the solve computes the first residual.
+//    corrections act on a small residual; the solve computes the first residual, or (L.bprev,
+//    right sides of the two previous steps kept) it is formed here from them.
 //  * cold start (FP64 path): x0 = Dirichlet data x_D, zero elsewhere, and the first
 //    residual r = b - A x_D is folded in here: each family's Dirichlet set is a union of
 //    whole sides, so (A x_D) at a free node needs only the first and last columns of the
@@ -186,10 +187,14 @@ __device__ __forceinline__ bool is_dir(const unsigned char* dirx, const unsigned
 __device__ __forceinline__ void rhs_out(const Geo& g, const Par& P, const Lift& L, const double* gD,
                                         const double* Fn, const double* Fo, long id, long pofs, int ix, int iy,
                                         double b, double* bb, double* r, double* x0) {
+  const double bo = L.bprev ? bb[id] : 0.0;   // b^{n-1}, in the slot that now takes b^{n+1}
   bb[id] = b;
   const bool dn = is_dir(L.dirx, L.diry, L.ebot, ix, iy);
   if (Fn) {
     x0[id] = dn ? gD[id] : P.cs_n * Fn[id] + P.cs_o * Fo[id];
+    // recycled first residual: A x^n = b^n, A x^{n-1} = b^{n-1} and the Dirichlet data did not
+    // change, so b - A x0 = b - (cs_n b^n + cs_o b^{n-1}) on free nodes
+    if (L.bprev) r[id] = dn ? 0.0 : b - (P.cs_n * L.bprev[id] + P.cs_o * bo);
     return;
   }
   if (dn) {
@@ -331,7 +336,7 @@ __global__ void __launch_bounds__(WG) k_psi_elem(Geo g, Par P, const double* phn
 __global__ void k_psi_rhs(Geo g, Par P, const double* L0, const double* bmo, const double* bmw,
                           const double* g1, const double* g2, const double* g3, const double* phn,
                           const double* pho, const double* E2, const double* Fn, const double* Fo,
-                          double* bb, double* U, double* Q2, double* r, double* x0) {
+                          double* bb, double* U, double* Q2, double* r, double* x0, const double* bprev) {
   NODAL_PROLOGUE
   double phs = P.cs_n * phn[id] + P.cs_o * pho[id];
   double u = -g3[id] - thp_of(P, phs);
@@ -339,9 +344,11 @@ __global__ void k_psi_rhs(Geo g, Par P, const double* L0, const double* bmo, con
   Q2[id] = h_of(P, phs) - P.S / (P.eta * P.eta) * phs - deps_of(P, phs) * E2[id] / (2.0 * P.lam);
   const double v = dss(g, L0, pl, ix, iy) + bmo[node] * (g1[id] + P.c_psi * g2[id]) +
                    bmw[node] * (g1[id] + P.c_psi * u);
+  const double bo = bprev ? bb[id] : 0.0;   // recycled first residual (as rhs_out)
   bb[id] = v;  // no Dirichlet node: cold start r = b, x0 = 0
   if (Fn) {
     x0[id] = P.cs_n * Fn[id] + P.cs_o * Fo[id];
+    if (bprev) r[id] = v - (P.cs_n * bprev[id] + P.cs_o * bo);
   } else {
     r[id] = v;
     x0[id] = 0.0;
@@ -351,12 +358,14 @@ __global__ void k_psi_rhs(Geo g, Par P, const double* L0, const double* bmo, con
 // =================================================================== stage phi (eq. 57)
 __global__ void k_phi_rhs(Geo g, Par P, const double* Mdiag, const double* psi, const double* bmo,
                           const double* bmw, const double* g2, const double* U, const double* Fn,
-                          const double* Fo, double* bb, double* r, double* x0) {
+                          const double* Fo, double* bb, double* r, double* x0, const double* bprev) {
   NODAL_PROLOGUE
   const double v = -Mdiag[node] * psi[id] + bmo[node] * g2[id] + bmw[node] * U[id];
+  const double bo = bprev ? bb[id] : 0.0;   // recycled first residual (as rhs_out)
   bb[id] = v;  // no Dirichlet node
   if (Fn) {
     x0[id] = P.cs_n * Fn[id] + P.cs_o * Fo[id];
+    if (bprev) r[id] = v - (P.cs_n * bprev[id] + P.cs_o * bo);
   } else {
     r[id] = v;
     x0[id] = 0.0;
@@ -613,8 +622,10 @@ __global__ void k_u_rhs(Geo g, Par P, Lift L, const double* L1, const double* L2
                         double* bx, double* by, double* rx, double* ry, double* x0x, double* x0y) {
   NODAL_PROLOGUE
   const long pofs = (long)pl * g.Ng;
+  Lift Ly = L;   // the y component's history follows the x component's (contiguous blocks)
+  if (Ly.bprev) Ly.bprev += (long)g.planes * g.Ng;
   rhs_out(g, P, L, wx, Fxn, Fxo, id, pofs, ix, iy, dss(g, L1, pl, ix, iy) + bmo[node] * f1x[id], bx, rx, x0x);
-  rhs_out(g, P, L, wy, Fyn, Fyo, id, pofs, ix, iy, dss(g, L2, pl, ix, iy) + bmo[node] * f1y[id], by, ry, x0y);
+  rhs_out(g, P, Ly, wy, Fyn, Fyo, id, pofs, ix, iy, dss(g, L2, pl, ix, iy) + bmo[node] * f1y[id], by, ry, x0y);
 }
 
 __global__ void k_fill(long N, double* f, double v) {
@@ -2557,6 +2568,16 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
   const bool warm = c->prob.precision == PFD_REFINED_FP32;
   auto H = [&](int f, int lv) -> const double* { return warm ? FLD(f, lv) : nullptr; };
   double* r0 = warm ? nullptr : c->r;
+  // right sides: b^{n+1} of each family goes to bh[f][nw]; with recycling (refined path, two
+  // previous solves recorded) the first residual is formed from bh[f][cur] (= b^n) and b^{n-1}
+  auto BB = [&](int f) { return c->bh[f][nw]; };
+  auto LR = [&](int f) {
+    Lift L = c->lift[f];
+    L.bprev = c->rec_on ? c->bh[f][c->cur] : nullptr;
+    return L;
+  };
+  auto BP = [&](int f) -> const double* { return c->rec_on ? c->bh[f][c->cur] : nullptr; };
+  double* rr = (warm && c->rec_on) ? c->r : r0;   // the solve's first residual, when formed above
   double* const* S = c->src;
   // ---- V (eq. 54)
   {
@@ -2566,9 +2587,9 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
                        c->Lb[0]);
     (void)dx;
     (void)dy;
-    LAUNCH(PFD_PROF_NODAL, k_V_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_V], c->Lb[0], c->Mdiag, S[PFD_SRC_FV],
-                       S[PFD_SRC_VD], H(F_V, 0), H(F_V, -1), c->b[0], c->r, c->fld[F_V][nw]);
-    solve(c, PFD_FAM_V, c->b[0], c->fld[F_V][nw], 1, 0, r0);
+    LAUNCH(PFD_PROF_NODAL, k_V_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_V), c->Lb[0], c->Mdiag, S[PFD_SRC_FV],
+                       S[PFD_SRC_VD], H(F_V, 0), H(F_V, -1), BB(PFD_FAM_V), c->r, c->fld[F_V][nw]);
+    solve(c, PFD_FAM_V, BB(PFD_FAM_V), c->fld[F_V][nw], 1, 0, rr);
   }
   // ---- E (eq. 55)
   LAUNCH(PFD_PROF_ELEM, k_E_elem, eg, eb, 0, st, g, c->fld[F_V][nw], c->Lb[0], c->Lb[1]);
@@ -2585,12 +2606,13 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
                      S[PFD_SRC_G], (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, c->Lb[0]);
   LAUNCH(PFD_PROF_NODAL, k_psi_rhs, ng, nb, 0, st, g, P, c->Lb[0], c->bm_open, c->bm_wall, S[PFD_SRC_G1],
                      S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), E2, H(F_PSI, 0), H(F_PSI, -1),
-                     c->b[0], c->U, c->Q2, c->r, c->fld[F_PSI][nw]);
-  solve(c, PFD_FAM_PSI, c->b[0], c->fld[F_PSI][nw], 1, 0, r0);
+                     BB(PFD_FAM_PSI), c->U, c->Q2, c->r, c->fld[F_PSI][nw], BP(PFD_FAM_PSI));
+  solve(c, PFD_FAM_PSI, BB(PFD_FAM_PSI), c->fld[F_PSI][nw], 1, 0, rr);
   // ---- phi (eq. 57)
   LAUNCH(PFD_PROF_NODAL, k_phi_rhs, ng, nb, 0, st, g, P, c->Mdiag, c->fld[F_PSI][nw], c->bm_open, c->bm_wall,
-                     S[PFD_SRC_G2], c->U, H(F_PHI, 0), H(F_PHI, -1), c->b[0], c->r, c->fld[F_PHI][nw]);
-  solve(c, PFD_FAM_PHI, c->b[0], c->fld[F_PHI][nw], 1, 0, r0);
+                     S[PFD_SRC_G2], c->U, H(F_PHI, 0), H(F_PHI, -1), BB(PFD_FAM_PHI), c->r, c->fld[F_PHI][nw],
+                     BP(PFD_FAM_PHI));
+  solve(c, PFD_FAM_PHI, BB(PFD_FAM_PHI), c->fld[F_PHI][nw], 1, 0, rr);
   if (equilibrium) {
     for (int f : {F_UX, F_UY, F_P}) LAUNCH(PFD_PROF_OTHER, k_fill, ng, nb, 0, st, tot, c->fld[f][nw], 0.0);
   } else {
@@ -2599,17 +2621,17 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
     LAUNCH(PFD_PROF_ELEM, k_mom_elem<false>, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
                        FLD(F_UX, 0), FLD(F_UX, -1), FLD(F_UY, 0), FLD(F_UY, -1), FLD(F_P, 0),
                        FLD(F_P, -1), S[PFD_SRC_FX], S[PFD_SRC_FY], c->Lb[0], c->Lb[1], c->Lb[2], Mom3{});
-    LAUNCH(PFD_PROF_NODAL, k_P_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_P], c->Lb[0], S[PFD_SRC_WX], S[PFD_SRC_WY],
-                       S[PFD_SRC_F2], H(F_P, 0), H(F_P, -1), c->b[0], c->r, c->fld[F_P][nw]);
-    solve(c, PFD_FAM_P, c->b[0], c->fld[F_P][nw], 1, 0, r0);
+    LAUNCH(PFD_PROF_NODAL, k_P_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_P), c->Lb[0], S[PFD_SRC_WX], S[PFD_SRC_WY],
+                       S[PFD_SRC_F2], H(F_P, 0), H(F_P, -1), BB(PFD_FAM_P), c->r, c->fld[F_P][nw]);
+    solve(c, PFD_FAM_P, BB(PFD_FAM_P), c->fld[F_P][nw], 1, 0, rr);
     // ---- u (eq. 59)
     LAUNCH(PFD_PROF_ELEM, k_gradP_elem, eg, eb, 0, st, g, P, c->fld[F_P][nw], (const double*)nullptr, c->Lb[1],
            c->Lb[2], (double*)nullptr);
-    LAUNCH(PFD_PROF_NODAL, k_u_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_U], c->Lb[1], c->Lb[2], c->bm_open,
+    LAUNCH(PFD_PROF_NODAL, k_u_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_U), c->Lb[1], c->Lb[2], c->bm_open,
                        S[PFD_SRC_F1X], S[PFD_SRC_F1Y], S[PFD_SRC_WX], S[PFD_SRC_WY], H(F_UX, 0), H(F_UX, -1),
-                       H(F_UY, 0), H(F_UY, -1), c->b[1], c->b[2], c->r, c->r + tot, c->fld[F_UX][nw],
-                       c->fld[F_UY][nw]);
-    solve(c, PFD_FAM_U, c->b[1], c->fld[F_UX][nw], 2, 0, r0);   // both components as one stack
+                       H(F_UY, 0), H(F_UY, -1), BB(PFD_FAM_U), BB(PFD_FAM_U) + tot, c->r, c->r + tot,
+                       c->fld[F_UX][nw], c->fld[F_UY][nw]);
+    solve(c, PFD_FAM_U, BB(PFD_FAM_U), c->fld[F_UX][nw], 2, 0, rr);   // both components as one stack
   }
   LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
   if (!equilibrium)
@@ -3186,6 +3208,14 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
   const bool warm = c->prob.precision == PFD_REFINED_FP32;
   auto H = [&](int f, int lv) -> const double* { return warm ? SPEC(f, lv) : nullptr; };
   double* r0 = warm ? nullptr : c->r;
+  // right sides per family and level, recycled for the refined path's first residual (as in 2D)
+  auto BB = [&](int f) { return c->bh[f][nw]; };
+  auto LR = [&](int f, int comp) {
+    Lift L = c->lift[f];
+    L.bprev = c->rec_on ? c->bh[f][c->cur] + comp * tot : nullptr;
+    return L;
+  };
+  double* rr = (warm && c->rec_on) ? c->r : r0;
   double* const* S = c->src;
   double **ph = c->ph, **sp = c->sp, **dz = c->dz, **Lb = c->Lb;
   refresh_spectral_sources(c);
@@ -3213,10 +3243,10 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
   const double* Wid[2] = {c->Wi, c->Wd};
   const double* ph01[2] = {ph[0], ph[1]};
   ztrans_n(c, 2, Wff, ph01, sp);
-  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_V], sp[0], sp[1], 0, 1.0 / P.eps0,
+  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_V, 0), sp[0], sp[1], 0, 1.0 / P.eps0,
          (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_VD], H(F_V, 0), H(F_V, -1),
-         c->b[0], c->r, c->spec[F_V][nw]);
-  solve(c, PFD_FAM_V, c->b[0], c->spec[F_V][nw], 1, 0, r0);
+         BB(PFD_FAM_V), c->r, c->spec[F_V][nw]);
+  solve(c, PFD_FAM_V, BB(PFD_FAM_V), c->spec[F_V][nw], 1, 0, rr);
   {
     // V and E_z = i beta V (reading R-Ez) from the new spectrum in one launch
     const double* ins[2] = {c->spec[F_V][nw], c->spec[F_V][nw]};
@@ -3240,18 +3270,18 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
   LAUNCH(PFD_PROF_NODAL, k_psi_rhs3, ng, nb, 0, st, g, P, Lb[0], c->Mdiag, c->bm_open, c->bm_wall, S[PFD_SRC_G1],
          S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), E2, ph[0], ph[1], c->U, c->Q2);
   ztrans_n(c, 2, Wff, ph01, sp);  // sp[1] = (M Q2)_hat, kept for Phi_hat below
-  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_PSI], sp[0], sp[1], 1, 1.0,
+  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_PSI, 0), sp[0], sp[1], 1, 1.0,
          (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, (const double*)nullptr, H(F_PSI, 0),
-         H(F_PSI, -1), c->b[0], c->r, c->spec[F_PSI][nw]);
-  solve(c, PFD_FAM_PSI, c->b[0], c->spec[F_PSI][nw], 1, 0, r0);
+         H(F_PSI, -1), BB(PFD_FAM_PSI), c->r, c->spec[F_PSI][nw]);
+  solve(c, PFD_FAM_PSI, BB(PFD_FAM_PSI), c->spec[F_PSI][nw], 1, 0, rr);
   ztrans(c, c->Wi, c->spec[F_PSI][nw], c->fld[F_PSI][nw]);
   // ---- phi (eq. 76, reading R-psi)
   LAUNCH(PFD_PROF_NODAL, k_phi_bnd3, ng, nb, 0, st, g, c->bm_open, c->bm_wall, S[PFD_SRC_G2], c->U, ph[0]);
   ztrans(c, c->Wf, ph[0], sp[0]);
-  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_PHI], sp[0], (const double*)nullptr, 0,
+  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_PHI, 0), sp[0], (const double*)nullptr, 0,
          1.0, (const double*)c->spec[F_PSI][nw], -1.0, c->Mdiag, c->d_beta2, c->d_betad, (const double*)nullptr,
-         H(F_PHI, 0), H(F_PHI, -1), c->b[0], c->r, c->spec[F_PHI][nw]);
-  solve(c, PFD_FAM_PHI, c->b[0], c->spec[F_PHI][nw], 1, 0, r0);
+         H(F_PHI, 0), H(F_PHI, -1), BB(PFD_FAM_PHI), c->r, c->spec[F_PHI][nw]);
+  solve(c, PFD_FAM_PHI, BB(PFD_FAM_PHI), c->spec[F_PHI][nw], 1, 0, rr);
   {
     // phi, and its z-derivative for the momentum terms
     const double* ins[2] = {c->spec[F_PHI][nw], c->spec[F_PHI][nw]};
@@ -3277,10 +3307,10 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
     LAUNCH(PFD_PROF_NODAL, k_P_rhs3, ng, nb, 0, st, g, P, Lb[0], Lb[3], S[PFD_SRC_WX], S[PFD_SRC_WY], ph[0],
            ph[1]);
     ztrans_n(c, 2, Wff, ph01, sp);
-    LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_P], sp[0], sp[1], 0, 1.0,
+    LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_P, 0), sp[0], sp[1], 0, 1.0,
            (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_F2], H(F_P, 0),
-           H(F_P, -1), c->b[0], c->r, c->spec[F_P][nw]);
-    solve(c, PFD_FAM_P, c->b[0], c->spec[F_P][nw], 1, 0, r0);
+           H(F_P, -1), BB(PFD_FAM_P), c->r, c->spec[F_P][nw]);
+    solve(c, PFD_FAM_P, BB(PFD_FAM_P), c->spec[F_P][nw], 1, 0, rr);
     {
       const double* ins[2] = {c->spec[F_P][nw], c->spec[F_P][nw]};
       double* outs[2] = {c->fld[F_P][nw], dz[0]};
@@ -3300,10 +3330,10 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
     const double* Bs[3] = {sp[1], sp[3], nullptr};
     const double* As[3] = {sp[0], sp[2], sp[4]};
     for (int i = 0; i < 3; ++i)
-      LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_U], As[i], Bs[i], 0, 1.0,
+      LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_U, i), As[i], Bs[i], 0, 1.0,
              (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[ws[i]], H(uf[i], 0),
-             H(uf[i], -1), c->b[i], c->r + i * tot, c->spec[uf[i]][nw]);
-    solve(c, PFD_FAM_U, c->b[0], c->spec[F_UX][nw], 3, 0, warm ? nullptr : c->r);   // one stack of 3
+             H(uf[i], -1), BB(PFD_FAM_U) + i * tot, c->r + i * tot, c->spec[uf[i]][nw]);
+    solve(c, PFD_FAM_U, BB(PFD_FAM_U), c->spec[F_UX][nw], 3, 0, rr);   // one stack of 3
     {
       const double* ins[3] = {c->spec[F_UX][nw], c->spec[F_UY][nw], c->spec[F_UZ][nw]};
       double* outs[3] = {c->fld[F_UX][nw], c->fld[F_UY][nw], c->fld[F_UZ][nw]};

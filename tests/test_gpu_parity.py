@@ -206,6 +206,46 @@ def test_benchmark_workload_parity(precision, tol, iters):
     check_parity(out, tol, field_tol=dict(ux=1e-8, uy=1e-8))
 
 
+@pytest.mark.parametrize("nz", [0, 8])
+def test_recycled_first_residual_matches_explicit(nz):
+    """The refined path forms its first residual from the right sides of the two previous
+    steps once they are recorded.  Against a twin context that is made to forget them before
+    every step (re-setting a source, so every step computes the residual explicitly): the
+    same fields to 1e-10 after 12 steps (2D closed box with walls and singular pressure; 3D
+    periodic box with an open top), and the recycled context matches the FP64 path to 1e-8."""
+    torch = _torch()
+    if nz:
+        xb = np.linspace(0.0, 1.0, 4)
+        m = Mesh2D(xb, xb, 6, periodic_x=True)
+        bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, pot_sides=(BOTTOM, TOP))
+    else:
+        m, bc, _ = box_case(n=4, K=6)
+    par = c1_params()
+    planes = nz if nz else 2
+    X, Y = m.X.ravel()[None, :], m.Y.ravel()[None, :]
+    Z = (np.arange(planes) / planes)[:, None] if nz else np.arange(planes)[:, None] * 0.05
+    phi = np.tanh((np.sqrt((X - 0.5) ** 2 + (Y - 0.3) ** 2 + 0.1 * np.sin(2 * math.pi * Z) ** 2) - 0.25)
+                  / (math.sqrt(2) * par.eta))
+    vd = np.broadcast_to(np.where(np.isclose(Y, 1.0), 1.0, 0.0), phi.shape).copy()
+    shape = (planes, m.Ny, m.Nx)
+    ctxs = [gpu_context(m, par, bc, nbatch=1 if nz else planes, precision=p, refine_iters=2, nz=nz,
+                        lz=1.0 if nz else 0.0) for p in (1, 1, 0)]
+    ctxs[1].set_tuning(ctxs[0].tuning())
+    for c in ctxs:
+        c.set_field("phi", phi.reshape(shape))
+        c.set_sources({"Vd": vd.reshape(shape)})
+        c.init_potential(tol=1e-12, max_iter=2000)
+    for n in range(12):
+        ctxs[0].step(1)
+        ctxs[1].set_sources({"Vd": vd.reshape(shape)})   # forgets the recorded right sides
+        ctxs[1].step(1)
+        ctxs[2].step(1)
+    for k in ("phi", "psi", "V", "P", "ux", "uy"):
+        a, b, f = (c.get_field(k) for c in ctxs)
+        assert rel_err(a, b) < 1e-10, (k, rel_err(a, b))
+        assert rel_err(a, f) < 1e-8, (k, rel_err(a, f))
+
+
 def test_batched_instances_equal_oracle_runs():
     """Three instances in one context (one per plane) with different top
     voltages: each matches its own oracle run."""
