@@ -76,7 +76,12 @@ typedef enum {
   PFD_NSRC
 } pfd_source;
 
-/* precision of the constant-coefficient solves */
+/* precision of the constant-coefficient solves.  PFD_REFINED_FP32 starts every solve of a
+ * step from the extrapolated history and applies refine_iters FP32 corrections, each on an
+ * FP64 residual; once two consecutive steps have solved a family, the first residual is formed
+ * from the right sides of those two steps (A x^n = b^n) instead of a stencil pass.  That record
+ * is forgotten by pfd_set_field, pfd_set_source, pfd_init_potential and pfd_update_params, and
+ * for P and u by an equilibrium step (which does not solve them). */
 typedef enum {
   PFD_PLAIN_FP64 = 0,   /* FP64 fast-diagonalisation solve                     */
   PFD_REFINED_FP32 = 1  /* FP32 solve + FP64 residual iterative refinement     */
