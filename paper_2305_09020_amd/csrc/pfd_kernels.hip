@@ -634,11 +634,14 @@ __global__ void k_fill(long N, double* f, double v) {
 }
 
 // non-finite guard on a field: sets status[0]
-__global__ void k_check_finite(long N, const double* f, int* status) {
+// sticky non-finite flag over f (and f2 when given), one launch
+__global__ void k_check_finite(long N, const double* f, const double* f2, int* status) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   bool bad = false;
-  for (; i < N; i += (long)gridDim.x * blockDim.x)
+  for (; i < N; i += (long)gridDim.x * blockDim.x) {
     if (!isfinite(f[i])) bad = true;
+    if (f2 && !isfinite(f2[i])) bad = true;
+  }
   if (bad) atomicOr(status, 1);
 }
 
@@ -2633,9 +2636,9 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
                        c->fld[F_UX][nw], c->fld[F_UY][nw]);
     solve(c, PFD_FAM_U, BB(PFD_FAM_U), c->fld[F_UX][nw], 2, 0, rr);   // both components as one stack
   }
-  LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
-  if (!equilibrium)
-    LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot, c->fld[F_UX][nw], c->d_status);
+  LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot,
+         (const double*)c->fld[F_PHI][nw], equilibrium ? (const double*)nullptr : (const double*)c->fld[F_UX][nw],
+         c->d_status);
   c->cur = nw;
   return hipGetLastError();
 }
@@ -3340,8 +3343,9 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
       ztrans_n(c, 3, Wfi, ins, outs);
     }
   }
-  LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot, c->fld[F_PHI][nw], c->d_status);
-  if (!equilibrium) LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot, c->fld[F_UX][nw], c->d_status);
+  LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot,
+         (const double*)c->fld[F_PHI][nw], equilibrium ? (const double*)nullptr : (const double*)c->fld[F_UX][nw],
+         c->d_status);
   c->cur = nw;
   return hipGetLastError();
 }
