@@ -367,6 +367,7 @@ def roofline(ctx, steps, workload="c2", path="refined"):
             "launches_per_step": n / steps, "per_launch": per, "class_time_share": share,
             "solver_variant": variant, "autotune_us_per_correction": tune_us,
             "residual_variant": ctx.residual_variant()[0], "autotune_us_residual": ctx.residual_variant()[1],
+            "tuning": ctx.tuning(),
             "gemm_tile_config_per_site": ctx.gemm_config()[0]}
 
 

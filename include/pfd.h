@@ -232,7 +232,7 @@ pfd_status pfd_get_solver_variant(const pfd_ctx* ctx, int* variant, double* us);
 /* Every choice of the autotuner (tile configurations per call site and precision, solver and
  * residual variants, block widths of the fused kernels) as an opaque list of integers, to copy
  * to another context of the same shapes so that both run the same kernels in the same order
- * (bit-identical results).  pfd_get_tuning writes min(n, count) values and the count (14) to
+ * (bit-identical results).  pfd_get_tuning writes min(n, count) values and the count (15) to
  * *count (either may be 0 / NULL); pfd_set_tuning takes exactly that count and rejects values
  * out of range (PFD_EINVAL).  Synchronises; drops captured graphs. */
 pfd_status pfd_get_tuning(const pfd_ctx* ctx, int* vals, int n, int* count);

@@ -813,7 +813,7 @@ extern "C" pfd_status pfd_get_gemm_config(const pfd_ctx* c, int* cfg, double* us
 
 extern "C" pfd_status pfd_get_tuning(const pfd_ctx* c, int* vals, int n, int* count) {
   if (!c || n < 0 || (n > 0 && !vals)) return PFD_EINVAL;
-  int t[2 * PFD_GS_N + 4];
+  int t[2 * PFD_GS_N + 5];
   int k = 0;
   for (int s = 0; s < PFD_GS_N; ++s) {
     t[k++] = c->gemm_cfg[s][0];
@@ -823,13 +823,14 @@ extern "C" pfd_status pfd_get_tuning(const pfd_ctx* c, int* vals, int n, int* co
   t[k++] = c->resid_variant;
   t[k++] = c->mid_tn;
   t[k++] = c->p4_tg;
+  t[k++] = c->p1_srp;
   for (int i = 0; i < k && i < n; ++i) vals[i] = t[i];
   if (count) *count = k;
   return PFD_OK;
 }
 
 extern "C" pfd_status pfd_set_tuning(pfd_ctx* c, const int* vals, int n) {
-  if (!c || !vals || n != 2 * PFD_GS_N + 4) return PFD_EINVAL;
+  if (!c || !vals || n != 2 * PFD_GS_N + 5) return PFD_EINVAL;
   for (int s = 0; s < PFD_GS_N; ++s)
     for (int t = 0; t < 2; ++t) {
       const int cfg = vals[2 * s + t];
@@ -837,7 +838,8 @@ extern "C" pfd_status pfd_set_tuning(pfd_ctx* c, const int* vals, int n) {
         return PFD_EINVAL;
     }
   const int* v = vals + 2 * PFD_GS_N;
-  if (v[0] < 0 || v[0] > 2 || v[1] < 0 || v[1] > 2 || v[2] < 1 || v[2] > 2 || v[3] < 0 || v[3] > 4)
+  if (v[0] < 0 || v[0] > 2 || v[1] < 0 || v[1] > 2 || v[2] < 1 || v[2] > 2 || v[3] < 0 || v[3] > 5 || v[4] < 0 ||
+      v[4] > 1)
     return PFD_EINVAL;
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
@@ -847,6 +849,7 @@ extern "C" pfd_status pfd_set_tuning(pfd_ctx* c, const int* vals, int n) {
   c->resid_variant = v[1];
   c->mid_tn = c->mid_best_tn = v[2];
   c->p4_tg = v[3];
+  c->p1_srp = v[4];
   return PFD_OK;
 }
 

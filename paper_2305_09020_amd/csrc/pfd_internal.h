@@ -148,7 +148,10 @@ struct pfd_ctx {
   double resid_us[3] = {0.0, 0.0, 0.0};
   double fdm_us[3] = {0.0, 0.0, 0.0};      // autotune timings (us per correction)
   int mid_tn = 1, mid_best_tn = 1;         // column tiles per work-group of the fused middle passes
-  int p4_tg = 0;                           // refined last pass: 0 = GEMM, else k_p4 column tiles per wave
+  int p4_tg = 0;                           // refined last pass: 0 = GEMM, 1..4 = k_p4 column tiles per
+                                           // wave, 5 = k_srp (matrix resident in LDS)
+  int p1_srp = 0;                          // refined first pass through k_srp
+  int num_cu = 256, lds_max = 65536;       // device: compute units, LDS bytes a work-group may use
   // right sides of the step's solves per family and time level (u: three components), and how
   // many consecutive steps solved the family with them (the refined path recycles them for its
   // first residual once two are recorded: A x^n = b^n to the refinement's accuracy)

@@ -2104,6 +2104,118 @@ static bool p4_launch(pfd_ctx* c, const Dir1D& dx, int P, const float* t3, doubl
   return true;
 }
 
+// First / last fast-diagonalisation pass of the refined path with the shared matrix resident in
+// LDS for the whole launch: C = A S, A (Mtot x K, row stride lda, FP64 or FP32) times S (K x N,
+// B-fragment order, i.e. the fragment order of S^T as a left operand), one work-group per CU
+// looping over 16-row tiles of A (staged through LDS in FP32, coalesced; the next tile is
+// loaded while the current one is multiplied), wave w taking column tiles w, w + nw, ...  The
+// matrix (up to 320^2 FP32) is read from L2 once per work-group instead of once per tile.
+// EPI 0: C = acc (FP32, row stride ldc); 2: X += acc; 3: X = acc.  Needs K, N <= 32 * 16.
+template <typename TA, int EPI>
+__global__ void __launch_bounds__(1024) k_srp(const TA* __restrict__ A, int lda, int Mtot, int K, int N,
+                                              const float* __restrict__ SB, float* __restrict__ C,
+                                              double* __restrict__ X, int ldc) {
+  typedef Mfma<float>::V V;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int KP = (K + 15) & ~15, KS = KP / 16, NT = (N + 15) / 16, LDA = KP + 4;
+  float* Sl = reinterpret_cast<float*>(smem_raw);   // NT * KS * 256 (fragment order)
+  float* Al = Sl + (long)NT * KS * 256;             // [16][LDA]
+  const int nt_thr = blockDim.x, tid = threadIdx.x;
+  const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nt_thr >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  for (int idx = 4 * tid; idx < NT * KS * 256; idx += 4 * nt_thr)
+    *reinterpret_cast<V*>(Sl + idx) = *reinterpret_cast<const V*>(SB + idx);
+  const int MT = (Mtot + 15) / 16;
+  // a tile's 16 x KP values take one round of at most 8 per thread (16 KP <= 8 * 64 nw); the
+  // next tile's are loaded into registers while the current one is multiplied
+  float v[8];
+  auto load_tile = [&](int t) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = min(tid + nt_thr * u, 16 * KP - 1);
+      const int r = idx / KP, k = idx - r * KP;
+      const int m = 16 * t + r;
+      const bool ok = m < Mtot && k < K;
+      const float x = float(A[(long)(m < Mtot ? m : Mtot - 1) * lda + (k < K ? k : K - 1)]);
+      v[u] = ok ? x : 0.f;
+    }
+  };
+  if (blockIdx.x < MT) load_tile(blockIdx.x);
+  for (int t = blockIdx.x; t < MT; t += gridDim.x) {
+    __syncthreads();   // the matrix is staged / the previous tile's rows are read
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = tid + nt_thr * u;
+      if (idx < 16 * KP) {
+        const int r = idx / KP, k = idx - r * KP;
+        Al[r * LDA + k] = v[u];
+      }
+    }
+    __syncthreads();
+    if (t + (int)gridDim.x < MT) load_tile(t + gridDim.x);
+    for (int nt = w; nt < NT; nt += nw) {
+      // two accumulators (even and odd slices) halve the dependent chain of matrix-core ops
+      V acc = V{0.f, 0.f, 0.f, 0.f}, acc1 = V{0.f, 0.f, 0.f, 0.f};
+      int sl = 0;
+      for (; sl + 1 < KS; sl += 2) {
+        const V a4 = *reinterpret_cast<const V*>(Al + r16 * LDA + 16 * sl + 4 * g);
+        const V b4 = *reinterpret_cast<const V*>(Sl + ((long)(nt * KS + sl) * 64 + lane) * 4);
+        const V a5 = *reinterpret_cast<const V*>(Al + r16 * LDA + 16 * sl + 16 + 4 * g);
+        const V b5 = *reinterpret_cast<const V*>(Sl + ((long)(nt * KS + sl + 1) * 64 + lane) * 4);
+        acc = Mfma<float>::op(a4.x, b4.x, acc);
+        acc1 = Mfma<float>::op(a5.x, b5.x, acc1);
+        acc = Mfma<float>::op(a4.y, b4.y, acc);
+        acc1 = Mfma<float>::op(a5.y, b5.y, acc1);
+        acc = Mfma<float>::op(a4.z, b4.z, acc);
+        acc1 = Mfma<float>::op(a5.z, b5.z, acc1);
+        acc = Mfma<float>::op(a4.w, b4.w, acc);
+        acc1 = Mfma<float>::op(a5.w, b5.w, acc1);
+      }
+      if (sl < KS) {
+        const V a4 = *reinterpret_cast<const V*>(Al + r16 * LDA + 16 * sl + 4 * g);
+        const V b4 = *reinterpret_cast<const V*>(Sl + ((long)(nt * KS + sl) * 64 + lane) * 4);
+        acc = Mfma<float>::op(a4.x, b4.x, acc);
+        acc = Mfma<float>::op(a4.y, b4.y, acc);
+        acc = Mfma<float>::op(a4.z, b4.z, acc);
+        acc = Mfma<float>::op(a4.w, b4.w, acc);
+      }
+      acc += acc1;
+      const int n = 16 * nt + r16;
+      if (n >= N) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = 16 * t + Mfma<float>::row(g, q);
+        if (m >= Mtot) continue;
+        if (EPI == 0) C[(long)m * ldc + n] = acc[q];
+        else if (EPI == 2) X[(long)m * ldc + n] += double(acc[q]);
+        else X[(long)m * ldc + n] = double(acc[q]);
+      }
+    }
+  }
+}
+
+// bytes of LDS k_srp needs for a K x N matrix; 0 where it exceeds what a work-group may have
+static size_t srp_lds(pfd_ctx* c, int K, int N) {
+  const size_t KP = (K + 15) & ~15, NT = (N + 15) / 16;
+  const size_t b = sizeof(float) * (NT * 16 * KP + 16 * (KP + 4));
+  if (16 * KP > 8 * 64 * std::min<size_t>(NT, 16)) return 0;   // one register round per tile
+  return b <= (size_t)c->lds_max ? b : 0;
+}
+
+// k_srp over P planes of Ny rows; false where it does not apply
+template <typename TA, int EPI>
+static bool srp_launch(pfd_ctx* c, int P, const TA* A, int lda, int K, int N, const float* SB, float* C, double* X,
+                       int ldc) {
+  const size_t lds = srp_lds(c, K, N);
+  if (!lds) return false;
+  const int Mtot = P * c->Ny, MT = (Mtot + 15) / 16, NT = (N + 15) / 16;
+  const int nw = NT < 16 ? NT : 16;
+  const unsigned grid = (unsigned)std::min(MT, c->num_cu);
+  LAUNCH(PFD_PROF_GEMM32, (k_srp<TA, EPI>), dim3(grid), dim3(64 * nw), lds, c->stream, A, lda, Mtot, K, N, SB, C, X,
+         ldc);
+  return true;
+}
+
 // refined path: T1 = float(b - A x) Sx for family fam in one launch (k_res_p1); false where it
 // does not apply (Nx > 256 or the LDS tile too large)
 static bool res_p1_launch(pfd_ctx* c, int fam, const double* b, const double* x, int np, float* t1) {
@@ -2151,8 +2263,13 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
              (const T*)t1, Sy, Sx, x);
     return;
   }
-  if (!t1_ready)   // else the first pass came with the residual (k_res_p1)
-    gemm<T, double, T, 0>(c, PFD_GS_P1, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr, nullptr, nullptr);
+  if (!t1_ready) {   // else the first pass came with the residual (k_res_p1)
+    bool done = false;
+    if constexpr (sizeof(T) == 4)
+      done = c->p1_srp && srp_launch<double, 0>(c, P, r, Nx, Nx, Nx, dx.fSTw, t1, nullptr, Nx);
+    if (!done)
+      gemm<T, double, T, 0>(c, PFD_GS_P1, P, r, Ng, Sx, 0, Ny, Nx, Nx, t1, Ng, nullptr, nullptr, nullptr, nullptr);
+  }
   // refined path with the fused middle passes: T3 with the padded row stride for k_p4
   // (the padded FP32 block must fit the scratch buffer: 3 planes-worth of FP64 fields)
   const bool pad = sizeof(T) == 4 && c->fdm_variant == 2 && c->p4_tg > 0 &&
@@ -2164,11 +2281,20 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
   } else {
     if (pad) {
       if constexpr (sizeof(T) == 4) {
-        p4_launch(c, dx, P, t2, x, overwrite, c->p4_tg);
+        const int KPX = (Nx + 15) & ~15;
+        if (c->p4_tg == 5 && (overwrite ? srp_launch<float, 3>(c, P, t2, KPX, Nx, Nx, dx.fSw, nullptr, x, Nx)
+                                        : srp_launch<float, 2>(c, P, t2, KPX, Nx, Nx, dx.fSw, nullptr, x, Nx)))
+          return;
+        p4_launch(c, dx, P, t2, x, overwrite, c->p4_tg == 5 ? 1 : c->p4_tg);   // reads the padded rows
         return;
       }
     }
     std::swap(t1, t2);   // the fused passes wrote T3 to t2
+  }
+  if constexpr (sizeof(T) == 4) {
+    if (c->p4_tg == 5 && (overwrite ? srp_launch<float, 3>(c, P, t1, Nx, Nx, Nx, dx.fSw, nullptr, x, Nx)
+                                    : srp_launch<float, 2>(c, P, t1, Nx, Nx, Nx, dx.fSw, nullptr, x, Nx)))
+      return;
   }
   if (overwrite)
     gemm<T, T, T, 3>(c, PFD_GS_P4, P, t1, Ng, SxT, 0, Ny, Nx, Nx, (T*)nullptr, Ng, nullptr, nullptr, nullptr, x);
@@ -2420,6 +2546,27 @@ hipError_t autotune(pfd_ctx* c) {
   if (e) { (void)hipEventDestroy(e0); return e; }
   const int saved = c->prof_on;
   c->prof_on = 0;
+  {
+    // device limits for the LDS-resident pass kernels (k_srp): compute units and the LDS a
+    // work-group may take (gfx950: 160 KB, above the default dynamic limit)
+    int dev = 0, v = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) c->num_cu = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      c->lds_max = v;
+    bool ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_srp<double, 0>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max) == hipSuccess;
+    ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_srp<float, 2>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max) == hipSuccess;
+    ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_srp<float, 3>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      c->lds_max = std::min(c->lds_max, 64 * 1024);
+    }
+  }
+  c->p1_srp = 0;
+  c->p4_tg = 0;
   if (fp32)
     tune_fdm_sites<float>(c, e0, e1, e);
   else
@@ -2479,7 +2626,8 @@ hipError_t autotune(pfd_ctx* c) {
     }
     c->mid_tn = c->mid_best_tn;
     int best_tg = 0;
-    for (int tg = 1; tg <= 4 && fp32 && c->fdm_us[2] > 0.0 && !e; ++tg) {   // the refined last pass
+    const int tg_max = srp_lds(c, c->Nx, c->Nx) ? 5 : 4;
+    for (int tg = 1; tg <= tg_max && fp32 && c->fdm_us[2] > 0.0 && !e; ++tg) {   // the refined last pass
       c->p4_tg = tg;
       const double us = time_us(c, e0, e1, 10, run_fdm, e);
       if (us < c->fdm_us[2]) {
@@ -2491,6 +2639,12 @@ hipError_t autotune(pfd_ctx* c) {
   }
   c->fdm_variant = (c->fdm_us[1] <= c->fdm_us[0]) ? 1 : 0;
   if (c->fdm_us[2] > 0.0 && c->fdm_us[2] < c->fdm_us[c->fdm_variant]) c->fdm_variant = 2;
+  if (fp32 && c->fdm_variant != 1 && srp_lds(c, c->Nx, c->Nx) && !e) {   // refined first pass with Sx in LDS
+    c->p1_srp = 1;
+    const double us = time_us(c, e0, e1, 10, run_fdm, e);
+    if (us < c->fdm_us[c->fdm_variant]) c->fdm_us[c->fdm_variant] = us;
+    else c->p1_srp = 0;
+  }
   c->resid_us[2] = 0.0;
   if (fp32 && c->fdm_variant != 1 && !e) {
     // residual fused with the first pass against the separate residual and first-pass GEMM
