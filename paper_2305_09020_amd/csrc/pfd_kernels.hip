@@ -1096,21 +1096,6 @@ __global__ void __launch_bounds__(256) k_gemm_sr(const TA* __restrict__ A, const
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
   const int n0 = blockIdx.y * 16 * W;
-  // S[k][n0 .. n0+16W) -> LDS (zero beyond K or N)
-  stage_lds<256, 16, T>(
-      KP * 16 * W,
-      [&](int idx) {
-        const int k = idx / (16 * W), j = idx - k * (16 * W);
-        const int n = n0 + j;
-        const bool ok = k < K && n < N;
-        const T v = S[(long)(k < K ? k : K - 1) * N + (n < N ? n : N - 1)];
-        return ok ? v : T(0);
-      },
-      [&](int idx, T v) {
-        const int k = idx / (16 * W), j = idx - k * (16 * W);
-        Sl[k * NP + j] = v;
-      });
-  __syncthreads();
   const int ms = w % WS, ks = w / WS;
   const int m = (blockIdx.x * WS + ms) * 16 + r16;
   const bool mok = m < Mtot;
@@ -1142,7 +1127,22 @@ __global__ void __launch_bounds__(256) k_gemm_sr(const TA* __restrict__ A, const
       for (int j = 0; j < W; ++j) acc[j] = Mfma<T>::op(av[s], Srow[16 * j], acc[j]);
     }
   };
-  load(0, a);
+  load(0, a);   // the first chunk of A is in flight while S is staged
+  // S[k][n0 .. n0+16W) -> LDS (zero beyond K or N)
+  stage_lds<256, 16, T>(
+      KP * 16 * W,
+      [&](int idx) {
+        const int k = idx / (16 * W), j = idx - k * (16 * W);
+        const int n = n0 + j;
+        const bool ok = k < K && n < N;
+        const T v = S[(long)(k < K ? k : K - 1) * N + (n < N ? n : N - 1)];
+        return ok ? v : T(0);
+      },
+      [&](int idx, T v) {
+        const int k = idx / (16 * W), j = idx - k * (16 * W);
+        Sl[k * NP + j] = v;
+      });
+  __syncthreads();
   for (int ch = 0; ch < nfull; ++ch) {
     load((ch + 1) * GEMM_CHUNK, an);
 #pragma unroll
@@ -1209,20 +1209,6 @@ __global__ void __launch_bounds__(256) k_gemm_sl(const T* __restrict__ S, const 
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
   const int m0 = blockIdx.y * 16 * W;
-  stage_lds<256, 16, T>(
-      16 * W * KP,
-      [&](int idx) {
-        const int i = idx / KP, k = idx - i * KP;
-        const int mi = m0 + i;
-        const bool ok = k < K && mi < M;
-        const T v = S[(long)(mi < M ? mi : M - 1) * K + (k < K ? k : K - 1)];
-        return ok ? v : T(0);
-      },
-      [&](int idx, T v) {
-        const int i = idx / KP, k = idx - i * KP;
-        Sl[k * MP + i] = v;
-      });
-  __syncthreads();
   const int ms = w % WS, ks = w / WS;
   const long ctot = (long)planes * N;
   const long cidx = ((long)blockIdx.x * WS + ms) * 16 + r16;
@@ -1262,7 +1248,21 @@ __global__ void __launch_bounds__(256) k_gemm_sl(const T* __restrict__ S, const 
       for (int t = 0; t < W; ++t) acc[t] = Mfma<T>::op(Srow[16 * t], x, acc[t]);
     }
   };
-  load(0, b, b2);
+  load(0, b, b2);   // the first chunk of B is in flight while S is staged
+  stage_lds<256, 16, T>(
+      16 * W * KP,
+      [&](int idx) {
+        const int i = idx / KP, k = idx - i * KP;
+        const int mi = m0 + i;
+        const bool ok = k < K && mi < M;
+        const T v = S[(long)(mi < M ? mi : M - 1) * K + (k < K ? k : K - 1)];
+        return ok ? v : T(0);
+      },
+      [&](int idx, T v) {
+        const int i = idx / KP, k = idx - i * KP;
+        Sl[k * MP + i] = v;
+      });
+  __syncthreads();
   for (int ch = 0; ch < nfull; ++ch) {
     load((ch + 1) * GEMM_CHUNK, bn, b2n);
 #pragma unroll
@@ -1760,32 +1760,39 @@ struct Vec4<double> {
 
 #define FDM_MID_LDC(CW) ((CW) + 4)
 
+#define FDM_MID_CH 4   // 16-slices per prefetched chunk of fragments
+
+// fragments of FDM_MID_CH consecutive slices from c0 for the wave's row tiles (clamped in
+// range; slices past KS and tiles past MT are not multiplied)
+template <typename T, int RT>
+__device__ __forceinline__ void fdm_mid_load(const T* __restrict__ Aw, int c0, int KS, int MT, int nw, int w,
+                                             int lane, T (&aa)[FDM_MID_CH][RT][4]) {
+#pragma unroll
+  for (int q = 0; q < FDM_MID_CH; ++q) {
+    const int sl = min(c0 + q, KS - 1);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int mt = min(w + nw * rt, MT - 1);
+      Vec4<T>::load(Aw + ((long)(mt * KS + sl) * 64 + lane) * 4, aa[q][rt]);
+    }
+  }
+}
+
+// one pass acc = Aw (fragment order) x Bl (LDS); a holds the first chunk (fdm_mid_load(.., 0, ..))
 template <typename T, int RT, int TN>
 __device__ __forceinline__ void fdm_mid_pass(const T* __restrict__ Aw, const T* Bl, int KS, int MT, int nw, int w,
-                                             int lane, typename Mfma<T>::V (&acc)[RT][TN]) {
+                                             int lane, T (&a)[FDM_MID_CH][RT][4],
+                                             typename Mfma<T>::V (&acc)[RT][TN]) {
   typedef typename Mfma<T>::V V;
-  constexpr int LDC = FDM_MID_LDC(16 * TN), CH = 4;   // slices per prefetched chunk
+  constexpr int LDC = FDM_MID_LDC(16 * TN), CH = FDM_MID_CH;
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < TN; ++ct) acc[rt][ct] = V{T(0), T(0), T(0), T(0)};
-  T a[CH][RT][4], an[CH][RT][4];
-  // fragments of CH consecutive slices (clamped in range; those past KS are not multiplied)
-  auto loadA = [&](int c0, T (&aa)[CH][RT][4]) {
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int sl = min(c0 + q, KS - 1);
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        const int mt = min(w + nw * rt, MT - 1);   // tiles past MT are not multiplied either
-        Vec4<T>::load(Aw + ((long)(mt * KS + sl) * 64 + lane) * 4, aa[q][rt]);
-      }
-    }
-  };
-  loadA(0, a);
+  T an[CH][RT][4];
   for (int c0 = 0; c0 < KS; c0 += CH) {
-    if (c0 + CH < KS) loadA(c0 + CH, an);
+    if (c0 + CH < KS) fdm_mid_load<T, RT>(Aw, c0 + CH, KS, MT, nw, w, lane, an);
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       const int sl = c0 + q;
@@ -1830,6 +1837,8 @@ __global__ void __launch_bounds__(1024) k_fdm_mid(int planes, int Ny, int Nx, lo
   const int nw = blockDim.x >> 6, nt = blockDim.x;
   const int r16 = lane & 15, g = lane >> 4;
   const long ctot = (long)planes * Nx, c0 = (long)blockIdx.x * CW;
+  T afr[FDM_MID_CH][RT][4];   // the first fragments of Sy^T are in flight while T1 is staged
+  fdm_mid_load<T, RT>(SyTw, 0, MT, MT, nw, w, lane, afr);
   // stage the T1 block (coalesced along the columns), 8 loads in flight per thread
   for (int base = 0; base < KP * CW; base += 8 * nt) {
     T v[8];
@@ -1853,7 +1862,8 @@ __global__ void __launch_bounds__(1024) k_fdm_mid(int planes, int Ny, int Nx, lo
   }
   __syncthreads();
   V acc[RT][TN];
-  fdm_mid_pass<T, RT, TN>(SyTw, Bt, MT, MT, nw, w, lane, acc);
+  fdm_mid_pass<T, RT, TN>(SyTw, Bt, MT, MT, nw, w, lane, afr, acc);
+  fdm_mid_load<T, RT>(Syw, 0, MT, MT, nw, w, lane, afr);   // in flight during the division
   // U = acc ./ (ly_i + lx_n + c_p) into LDS (rows >= Ny and columns past the end: 0)
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
@@ -1878,7 +1888,7 @@ __global__ void __launch_bounds__(1024) k_fdm_mid(int planes, int Ny, int Nx, lo
     }
   }
   __syncthreads();
-  fdm_mid_pass<T, RT, TN>(Syw, Us, MT, MT, nw, w, lane, acc);
+  fdm_mid_pass<T, RT, TN>(Syw, Us, MT, MT, nw, w, lane, afr, acc);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     const int mt = w + nw * rt;
