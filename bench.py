@@ -551,6 +551,16 @@ def main():
         out["fp64_value"] = res["fp64"]["value"]
         out["refined_over_fp64"] = res["refined"]["value"] / res["fp64"]["value"]
         out["fp64_roofline"] = res["fp64"]["roofline"]
+        if a.workload in ("c2", "c3"):
+            # both contexts started from the same state and took the same steps (warmup,
+            # timed, instrumented): field-wise max |refined - fp64| / max |fp64|
+            n_cmp = a.warmup + a.steps + min(a.steps, 200 if a.workload == "c2" else 20)
+            names = ("phi", "psi", "V", "P", "ux", "uy") + (("uz",) if a.workload == "c3" else ())
+            errs = {}
+            for k in names:
+                f, g = res["fp64"]["ctx"].get_field(k), res["refined"]["ctx"].get_field(k)
+                errs[k] = float(np.abs(g - f).max() / max(float(np.abs(f).max()), 1e-300))
+            out["refined_vs_fp64"] = {"steps": n_cmp, "max_rel_err": errs}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = {"c2": cpu_baseline, "c3": cpu_baseline_c3, "c4": cpu_baseline_c4}[a.workload]()
     print(json.dumps(out), flush=True)

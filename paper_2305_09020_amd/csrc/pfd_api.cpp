@@ -683,8 +683,10 @@ void pfd::forget_rhs(pfd_ctx* c) {
   for (int& h : c->bhist) h = 0;
 }
 void pfd::begin_step(pfd_ctx* c, int eq) {
-  const bool refined = c->prob.precision == PFD_REFINED_FP32;
-  bool ok = refined;
+  // one correction per solve takes the exact residual: a recycled one would leave each step's
+  // final residual in the next two steps' right sides, growing without the second correction
+  const int iters = c->prob.refine_iters > 0 ? c->prob.refine_iters : 2;
+  bool ok = c->prob.precision == PFD_REFINED_FP32 && iters >= 2;
   for (int f = 0; f < 5; ++f)
     if (!eq || f == PFD_FAM_V || f == PFD_FAM_PSI || f == PFD_FAM_PHI) ok = ok && c->bhist[f] >= 2;
   c->rec_on = ok;

@@ -716,13 +716,14 @@ __global__ void k_residual(int Nx, int Ny, int planes, int perx, const double* _
 }
 
 // LDS-tiled variant of k_residual: a work-group takes RROWS rows of one plane; the rows
-// iy0-K .. iy0+RROWS-1+K of x are staged in LDS once (coalesced), with the y-band coefficients,
-// M_y and the Dirichlet flags of its rows.  Each thread owns one column: the 2K+1 x-band
-// coefficients of the column and the RROWS+2K values of x down the column sit in registers, so
-// the y-sums of all RROWS rows come from that window, and only the x-neighbours are read from
-// LDS.  All global loads (b of every row included) are issued before the row sums.  Needs
-// Nx <= 256 (one column per thread).  res_rows leaves the result of row rl, column ix to
-// out(rl, iy, ix, value); the LDS it uses is res_rows_lds(Nx) doubles from xs.
+// iy0-K .. iy0+RROWS-1+K of x are staged in LDS once (coalesced).  Each thread owns one column:
+// the 2K+1 x-band coefficients of the column and the RROWS+2K values of x down the column sit in
+// registers, so the y-sums of all RROWS rows come from that window, and only the x-neighbours
+// are read from LDS, as are the y-band coefficients, M_y and the Dirichlet flags of the
+// work-group's rows (staged with x).  b of the column's rows is requested before the staging, so
+// its latency overlaps it.  Needs Nx <= 256 (one column per thread).  res_rows leaves the result
+// of row rl, column ix to out(rl, iy, ix, value); the LDS it uses is res_rows_lds(Nx) doubles
+// from xs.
 #define RROWS 16
 __host__ __device__ constexpr long res_rows_lds(int K, int Nx) {
   return (long)(RROWS + 2 * K) * Nx + RROWS * (2 * K + 3);
@@ -736,19 +737,25 @@ __device__ __forceinline__ void res_rows(int Nx, int Ny, int perx, const double*
                                          const double* __restrict__ bb, const double* __restrict__ x, int apply_only,
                                          const unsigned char* __restrict__ ebot, double* xs, Out out) {
   constexpr int NB = 2 * K + 1, NW = RROWS + 2 * K;
-  double* kyl = xs + NW * Nx;                         // [RROWS][NB] y-band rows iy0..
-  double* myl = kyl + RROWS * NB;                     // [RROWS] M_y
-  double* dyl = myl + RROWS;                          // [RROWS] Dirichlet flag of the row
+  double* kyl = xs + NW * Nx;     // [RROWS][NB] y-band rows iy0..
+  double* myl = kyl + RROWS * NB;   // [RROWS] M_y
+  double* dyl = myl + RROWS;        // [RROWS] Dirichlet flag of the row
   const int pl = blockIdx.y, iy0 = blockIdx.x * RROWS;
   const long Ng = (long)Nx * Ny;
   const double* xp = x + pl * Ng;
+  const int ix = threadIdx.x, ixc = ix < Nx ? ix : Nx - 1;   // threads past Nx load column Nx - 1
+  double bv[RROWS];
+  if (!apply_only) {
+#pragma unroll
+    for (int rl = 0; rl < RROWS; ++rl) bv[rl] = bb[pl * Ng + (long)min(iy0 + rl, Ny - 1) * Nx + ixc];
+  }
   stage_lds<256, 16, double>(
       NW * Nx,
       [&](int idx) {
-        const int rr = idx / Nx, ix = idx - rr * Nx;
+        const int rr = idx / Nx, jx = idx - rr * Nx;
         const int iy = iy0 - K + rr;
         const bool ok = iy >= 0 && iy < Ny;
-        const double v = xp[(long)(ok ? iy : 0) * Nx + ix];
+        const double v = xp[(long)(ok ? iy : 0) * Nx + jx];
         return ok ? v : 0.0;
       },
       [&](int idx, double v) { xs[idx] = v; });
@@ -759,18 +766,15 @@ __device__ __forceinline__ void res_rows(int Nx, int Ny, int perx, const double*
     else if (q == NB) myl[rl] = My[iy];
     else dyl[rl] = diry[iy] ? 1.0 : 0.0;
   }
-  __syncthreads();
-  const int ix = threadIdx.x;
-  if (ix >= Nx) return;
-  const int rend = min(RROWS, Ny - iy0);
-  double bv[RROWS];
-  if (!apply_only) {
-#pragma unroll
-    for (int rl = 0; rl < RROWS; ++rl) bv[rl] = bb[pl * Ng + (long)min(iy0 + rl, Ny - 1) * Nx + ix];
-  }
   double kx[NB];
 #pragma unroll
-  for (int d = 0; d < NB; ++d) kx[d] = KxB[(long)d * Nx + ix];
+  for (int d = 0; d < NB; ++d) kx[d] = KxB[(long)d * Nx + ixc];
+  const double mx = Mx[ixc], sh = shift[pl];
+  const bool dxn = dirx[ixc] != 0;
+  const bool egap = ebot && !ebot[ixc];   // bottom-row gap node of a partial electrode set
+  __syncthreads();
+  if (ix >= Nx) return;
+  const int rend = min(RROWS, Ny - iy0);
   int jx[NB];
 #pragma unroll
   for (int d = -K; d <= K; ++d) {
@@ -779,9 +783,6 @@ __device__ __forceinline__ void res_rows(int Nx, int Ny, int perx, const double*
     else j = (j < 0) ? 0 : (j >= Nx ? Nx - 1 : j);   // out-of-range band entries are zero
     jx[d + K] = j;
   }
-  const double mx = Mx[ix], sh = shift[pl];
-  const bool dxn = dirx[ix] != 0;
-  const bool egap = ebot && !ebot[ix];   // bottom-row gap node of a partial electrode set
   double win[NW];
 #pragma unroll
   for (int q = 0; q < NW; ++q) win[q] = xs[q * Nx + ix];
