@@ -716,7 +716,9 @@ __global__ void k_residual(int Nx, int Ny, int planes, int perx, const double* _
 }
 
 // LDS-tiled variant of k_residual: a work-group takes RROWS rows of one plane; the rows
-// iy0-K .. iy0+RROWS-1+K of x are staged in LDS once (coalesced).  Each thread owns one column:
+// iy0-K .. iy0+RROWS-1+K of x are staged in LDS once (coalesced), each with K halo entries on
+// either side (the periodic images in x, else zeros, which meet zero band coefficients), so the
+// x-neighbours of column ix sit at fixed offsets from it.  Each thread owns one column:
 // the 2K+1 x-band coefficients of the column and the RROWS+2K values of x down the column sit in
 // registers, so the y-sums of all RROWS rows come from that window, and only the x-neighbours
 // are read from LDS, as are the y-band coefficients, M_y and the Dirichlet flags of the
@@ -726,7 +728,7 @@ __global__ void k_residual(int Nx, int Ny, int planes, int perx, const double* _
 // from xs.
 #define RROWS 16
 __host__ __device__ constexpr long res_rows_lds(int K, int Nx) {
-  return (long)(RROWS + 2 * K) * Nx + RROWS * (2 * K + 3);
+  return (long)(RROWS + 2 * K) * (Nx + 2 * K) + RROWS * (2 * K + 3);
 }
 
 template <int K, class Out>
@@ -737,7 +739,8 @@ __device__ __forceinline__ void res_rows(int Nx, int Ny, int perx, const double*
                                          const double* __restrict__ bb, const double* __restrict__ x, int apply_only,
                                          const unsigned char* __restrict__ ebot, double* xs, Out out) {
   constexpr int NB = 2 * K + 1, NW = RROWS + 2 * K;
-  double* kyl = xs + NW * Nx;     // [RROWS][NB] y-band rows iy0..
+  const int LR = Nx + 2 * K;        // staged row: x[iy][ix] at K + ix
+  double* kyl = xs + NW * LR;       // [RROWS][NB] y-band rows iy0..
   double* myl = kyl + RROWS * NB;   // [RROWS] M_y
   double* dyl = myl + RROWS;        // [RROWS] Dirichlet flag of the row
   const int pl = blockIdx.y, iy0 = blockIdx.x * RROWS;
@@ -750,12 +753,15 @@ __device__ __forceinline__ void res_rows(int Nx, int Ny, int perx, const double*
     for (int rl = 0; rl < RROWS; ++rl) bv[rl] = bb[pl * Ng + (long)min(iy0 + rl, Ny - 1) * Nx + ixc];
   }
   stage_lds<256, 16, double>(
-      NW * Nx,
+      NW * LR,
       [&](int idx) {
-        const int rr = idx / Nx, jx = idx - rr * Nx;
+        const int rr = idx / LR;
+        int jx = idx - rr * LR - K;
+        const bool in = jx >= 0 && jx < Nx;
+        if (perx) jx = jx < 0 ? jx + Nx : (jx >= Nx ? jx - Nx : jx);
         const int iy = iy0 - K + rr;
-        const bool ok = iy >= 0 && iy < Ny;
-        const double v = xp[(long)(ok ? iy : 0) * Nx + jx];
+        const bool ok = iy >= 0 && iy < Ny && (in || perx);
+        const double v = xp[(long)(ok ? iy : 0) * Nx + (ok ? jx : 0)];
         return ok ? v : 0.0;
       },
       [&](int idx, double v) { xs[idx] = v; });
@@ -775,25 +781,17 @@ __device__ __forceinline__ void res_rows(int Nx, int Ny, int perx, const double*
   __syncthreads();
   if (ix >= Nx) return;
   const int rend = min(RROWS, Ny - iy0);
-  int jx[NB];
-#pragma unroll
-  for (int d = -K; d <= K; ++d) {
-    int j = ix + d;
-    if (perx) j = (j < 0) ? j + Nx : (j >= Nx ? j - Nx : j);
-    else j = (j < 0) ? 0 : (j >= Nx ? Nx - 1 : j);   // out-of-range band entries are zero
-    jx[d + K] = j;
-  }
   double win[NW];
 #pragma unroll
-  for (int q = 0; q < NW; ++q) win[q] = xs[q * Nx + ix];
+  for (int q = 0; q < NW; ++q) win[q] = xs[q * LR + K + ix];
 #pragma unroll
   for (int rl = 0; rl < RROWS; ++rl) {
     if (rl < rend) {
       const int iy = iy0 + rl;
-      const double* row = xs + (rl + K) * Nx;
+      const double* row = xs + (rl + K) * LR + ix;   // x[iy][ix + d - K] at row[d]
       double ax = 0.0, ay = 0.0;
 #pragma unroll
-      for (int d = 0; d < NB; ++d) ax += kx[d] * row[jx[d]];
+      for (int d = 0; d < NB; ++d) ax += kx[d] * row[d];
 #pragma unroll
       for (int d = 0; d < NB; ++d) ay += kyl[rl * NB + d] * win[rl + d];
       const double xv = win[rl + K];
@@ -1942,9 +1940,9 @@ static bool fdm_mid_launch(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const d
 // column tiles w, w + 4, ...  Sx comes in B-fragment order, which is the fragment order of
 // Sx^T as a left operand (frag_layout of S^T): for column tile nt, slice sl and lane, the four
 // entries Sx[16 sl + 4 (lane / 16) + s][16 nt + lane % 16].
-#define RESP1_NTW 4   // column tiles per wave (Nx <= 256)
-template <int K>
-__global__ void __launch_bounds__(256) k_res_p1(int Nx, int Ny, int perx, const double* __restrict__ KxB,
+// NTW: column tiles per wave, ceil(KPX / 64) (3 up to Nx = 192, 4 up to 256).
+template <int K, int NTW>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8 && NTW == 3 ? 3 : 1))) k_res_p1(int Nx, int Ny, int perx, const double* __restrict__ KxB,
                                                 const double* __restrict__ Mx, const unsigned char* __restrict__ dirx,
                                                 const double* __restrict__ KyB, const double* __restrict__ My,
                                                 const unsigned char* __restrict__ diry,
@@ -1964,17 +1962,17 @@ __global__ void __launch_bounds__(256) k_res_p1(int Nx, int Ny, int perx, const 
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
   const int NT = KS;   // column tiles of the square product
-  V acc[RESP1_NTW];
+  V acc[NTW];
 #pragma unroll
-  for (int j = 0; j < RESP1_NTW; ++j) acc[j] = V{0.f, 0.f, 0.f, 0.f};
+  for (int j = 0; j < NTW; ++j) acc[j] = V{0.f, 0.f, 0.f, 0.f};
   constexpr int CH = 4;   // slices per prefetched chunk of Sx fragments
-  float bq[CH][RESP1_NTW][4], bn[CH][RESP1_NTW][4];
-  auto loadB = [&](int c0, float (&bb)[CH][RESP1_NTW][4]) {   // clamped; past KS / NT not multiplied
+  float bq[CH][NTW][4], bn[CH][NTW][4];
+  auto loadB = [&](int c0, float (&bb)[CH][NTW][4]) {   // clamped; past KS / NT not multiplied
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       const int sl = min(c0 + q, KS - 1);
 #pragma unroll
-      for (int j = 0; j < RESP1_NTW; ++j) {
+      for (int j = 0; j < NTW; ++j) {
         const int nt = min(w + 4 * j, NT - 1);
         Vec4<float>::load(SxB + ((long)(nt * KS + sl) * 64 + lane) * 4, bb[q][j]);
       }
@@ -1989,7 +1987,7 @@ __global__ void __launch_bounds__(256) k_res_p1(int Nx, int Ny, int perx, const 
       if (sl < KS) {
         const Mfma<float>::V av = *reinterpret_cast<const Mfma<float>::V*>(Rl + r16 * LDR + 16 * sl + 4 * g);
 #pragma unroll
-        for (int j = 0; j < RESP1_NTW; ++j) {
+        for (int j = 0; j < NTW; ++j) {
           if (w + 4 * j < NT) {
             acc[j] = Mfma<float>::op(av.x, bq[q][j][0], acc[j]);
             acc[j] = Mfma<float>::op(av.y, bq[q][j][1], acc[j]);
@@ -2002,14 +2000,14 @@ __global__ void __launch_bounds__(256) k_res_p1(int Nx, int Ny, int perx, const 
 #pragma unroll
     for (int q = 0; q < CH; ++q)
 #pragma unroll
-      for (int j = 0; j < RESP1_NTW; ++j)
+      for (int j = 0; j < NTW; ++j)
 #pragma unroll
         for (int k = 0; k < 4; ++k) bq[q][j][k] = bn[q][j][k];
   }
   const long Ng = (long)Nx * Ny, pofs = (long)blockIdx.y * Ng;
   const int iy0 = blockIdx.x * RROWS;
 #pragma unroll
-  for (int j = 0; j < RESP1_NTW; ++j) {
+  for (int j = 0; j < NTW; ++j) {
     const int nt = w + 4 * j;
     const int n = 16 * nt + r16;
     if (nt >= NT || n >= Nx) continue;
@@ -2237,11 +2235,17 @@ static bool res_p1_launch(pfd_ctx* c, int fam, const double* b, const double* x,
   const size_t lds = sizeof(double) * (size_t)res_rows_lds(c->K, c->Nx) + sizeof(float) * RROWS * (KPX + 4);
   if (c->Nx > 256 || lds > 64 * 1024) return false;
   const dim3 grid((c->Ny + RROWS - 1) / RROWS, np);
-#define RP1_CASE(KK)                                                                                        \
-  case KK:                                                                                                  \
-    LAUNCH(PFD_PROF_RESID, k_res_p1<KK>, grid, dim3(256), lds, c->stream, c->Nx, c->Ny, (int)dx.periodic, dx.dKb, \
-           dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, (const double*)F.dshift, b, x, c->lift[fam].ebot,          \
-           (const float*)dx.fSTw, t1);                                                                      \
+  const bool three = KPX <= 192;   // column tiles per wave
+#define RP1_CASE(KK)                                                                                         \
+  case KK:                                                                                                   \
+    if (three)                                                                                               \
+      LAUNCH(PFD_PROF_RESID, (k_res_p1<KK, 3>), grid, dim3(256), lds, c->stream, c->Nx, c->Ny, (int)dx.periodic, \
+             dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, (const double*)F.dshift, b, x, c->lift[fam].ebot,  \
+             (const float*)dx.fSTw, t1);                                                                     \
+    else                                                                                                     \
+      LAUNCH(PFD_PROF_RESID, (k_res_p1<KK, 4>), grid, dim3(256), lds, c->stream, c->Nx, c->Ny, (int)dx.periodic, \
+             dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, (const double*)F.dshift, b, x, c->lift[fam].ebot,  \
+             (const float*)dx.fSTw, t1);                                                                     \
     return true;
   switch (c->K) {
     RP1_CASE(2) RP1_CASE(3) RP1_CASE(4) RP1_CASE(5) RP1_CASE(6) RP1_CASE(7) RP1_CASE(8) RP1_CASE(9)
