@@ -3116,7 +3116,7 @@ __device__ __forceinline__ double zbeta(int k, const double* __restrict__ betad)
 template <int LG>
 struct ZfftShape {
   static constexpr int NZ = 1 << LG, N1 = 1 << ((LG + 1) / 2), N2 = 1 << (LG / 2);
-  static constexpr int P = (2048 / NZ) < 64 ? (2048 / NZ) : 64;
+  static constexpr int P = (4096 / NZ) < 64 ? (4096 / NZ) : 64;
   static constexpr int T = P * N2;
   static constexpr int RS = N2 * P + P;   // LDS stride between k1 rows (padded)
 };
