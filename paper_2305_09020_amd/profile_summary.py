@@ -11,7 +11,10 @@ import os
 import sys
 
 CLASSES = [("gemm64", lambda n: ("k_gemm" in n or "k_fdm" in n) and ("<double" in n or "IdE" in n)),
-           ("gemm32", lambda n: ("k_gemm" in n or "k_fdm" in n) and ("<float" in n or "IfE" in n)),
+           # FP32 matrix-core passes: the GEMMs and fused middle passes in float, and the
+           # refined path's first / last pass kernels (k_srp, k_p4), which compute in FP32
+           ("gemm32", lambda n: (("k_gemm" in n or "k_fdm" in n) and ("<float" in n or "IfE" in n))
+            or "k_p4" in n or "k_srp" in n),
            ("residual", lambda n: "k_residual" in n or "k_res_p1" in n),
            ("zfft", lambda n: "k_zfft" in n),
            ("element", lambda n: "_elem" in n),
