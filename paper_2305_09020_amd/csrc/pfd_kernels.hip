@@ -17,6 +17,7 @@
 //    fast-diagonalisation passes  T = (Sy^T R Sx) ./ (ly_i + lx_j + c_p)  and
 //    X += Sy T Sx^T, each a chain of two LDS-staged GEMMs per (plane, column
 //    block), templated on the compute type (double / float).
+#include <climits>
 #include <cmath>
 #include <functional>
 #include <type_traits>
@@ -1759,15 +1760,20 @@ struct Vec4<double> {
 
 #define FDM_MID_LDC(CW) ((CW) + 4)
 
-#define FDM_MID_CH 4   // 16-slices per prefetched chunk of fragments
+// 16-slices per prefetched chunk of fragments: 4 in FP32, 2 in FP64 (seven waves per SIMD, so
+// three 9-wave work-groups share a CU)
+template <typename T>
+struct MidCh {
+  static constexpr int v = sizeof(T) == 8 ? 2 : 4;
+};
 
-// fragments of FDM_MID_CH consecutive slices from c0 for the wave's row tiles (clamped in
+// fragments of MidCh<T>::v consecutive slices from c0 for the wave's row tiles (clamped in
 // range; slices past KS and tiles past MT are not multiplied)
 template <typename T, int RT>
 __device__ __forceinline__ void fdm_mid_load(const T* __restrict__ Aw, int c0, int KS, int MT, int nw, int w,
-                                             int lane, T (&aa)[FDM_MID_CH][RT][4]) {
+                                             int lane, T (&aa)[MidCh<T>::v][RT][4]) {
 #pragma unroll
-  for (int q = 0; q < FDM_MID_CH; ++q) {
+  for (int q = 0; q < MidCh<T>::v; ++q) {
     const int sl = min(c0 + q, KS - 1);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -1780,10 +1786,10 @@ __device__ __forceinline__ void fdm_mid_load(const T* __restrict__ Aw, int c0, i
 // one pass acc = Aw (fragment order) x Bl (LDS); a holds the first chunk (fdm_mid_load(.., 0, ..))
 template <typename T, int RT, int TN>
 __device__ __forceinline__ void fdm_mid_pass(const T* __restrict__ Aw, const T* Bl, int KS, int MT, int nw, int w,
-                                             int lane, T (&a)[FDM_MID_CH][RT][4],
+                                             int lane, T (&a)[MidCh<T>::v][RT][4],
                                              typename Mfma<T>::V (&acc)[RT][TN]) {
   typedef typename Mfma<T>::V V;
-  constexpr int LDC = FDM_MID_LDC(16 * TN), CH = FDM_MID_CH;
+  constexpr int LDC = FDM_MID_LDC(16 * TN), CH = MidCh<T>::v;
   const int r16 = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -1822,7 +1828,7 @@ __device__ __forceinline__ void fdm_mid_pass(const T* __restrict__ Aw, const T* 
 }
 
 template <typename T, int RT, int TN>
-__global__ void __launch_bounds__(1024) k_fdm_mid(int planes, int Ny, int Nx, long Ng, const T* __restrict__ SyTw,
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 7 : 1))) k_fdm_mid(int planes, int Ny, int Nx, long Ng, const T* __restrict__ SyTw,
                                                   const T* __restrict__ Syw, const T* __restrict__ T1,
                                                   const double* __restrict__ ly, const double* __restrict__ lx,
                                                   const double* __restrict__ shift, T* __restrict__ T3, int ldo) {
@@ -1836,24 +1842,27 @@ __global__ void __launch_bounds__(1024) k_fdm_mid(int planes, int Ny, int Nx, lo
   const int nw = blockDim.x >> 6, nt = blockDim.x;
   const int r16 = lane & 15, g = lane >> 4;
   const long ctot = (long)planes * Nx, c0 = (long)blockIdx.x * CW;
-  T afr[FDM_MID_CH][RT][4];   // the first fragments of Sy^T are in flight while T1 is staged
+  T afr[MidCh<T>::v][RT][4];   // the first fragments of Sy^T are in flight while T1 is staged
   fdm_mid_load<T, RT>(SyTw, 0, MT, MT, nw, w, lane, afr);
-  // stage the T1 block (coalesced along the columns), 8 loads in flight per thread
-  for (int base = 0; base < KP * CW; base += 8 * nt) {
-    T v[8];
+  // stage the T1 block (coalesced along the columns), SU loads in flight per thread (column
+  // indices fit an int: the launcher checks planes * Nx)
+  constexpr int SU = sizeof(T) == 8 ? 4 : 8;
+  const int ctoti = (int)ctot, c0i = (int)c0;
+  for (int base = 0; base < KP * CW; base += SU * nt) {
+    T v[SU];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < SU; ++u) {
       const int idx = min(base + (int)threadIdx.x + nt * u, KP * CW - 1);
       const int k = idx / CW, j = idx - k * CW;
-      const long ci = c0 + j;
-      const bool ok = k < Ny && ci < ctot;
-      const long cc = ci < ctot ? ci : ctot - 1;
-      const long p = cc / Nx;
+      const int ci = c0i + j;
+      const bool ok = k < Ny && ci < ctoti;
+      const int cc = ci < ctoti ? ci : ctoti - 1;
+      const int p = cc / Nx;
       const T x = T1[p * Ng + (long)(k < Ny ? k : Ny - 1) * Nx + (cc - p * Nx)];
       v[u] = ok ? x : T(0);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < SU; ++u) {
       const int idx = min(base + (int)threadIdx.x + nt * u, KP * CW - 1);
       const int k = idx / CW, j = idx - k * CW;
       Bt[k * LDC + j] = v[u];
@@ -1920,6 +1929,7 @@ static bool fdm_mid_launch(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const d
   const T* SyTw = pick<T>(dy.fSTw, dy.dSTw);
   const T* Syw = pick<T>(dy.fSw, dy.dSw);
   const long ctot = (long)P * Nx;
+  if (ctot + 64 > INT_MAX) return false;   // the kernel indexes columns with ints
   const dim3 grid((unsigned)((ctot + 16 * tn - 1) / (16 * tn))), block(64 * nw);
   const int cls = sizeof(T) == 8 ? PFD_PROF_GEMM64 : PFD_PROF_GEMM32;
 #define MID_CASE(RT_, TN_)                                                                                   \
