@@ -100,12 +100,27 @@ __device__ __forceinline__ void wdxy(const ElemLDS& s, int n, int a, int b, cons
 // lanes are not left idle at small orders); thread = (sub-plane, local node t).  Element arrays
 // in LDS are declared with ELEM_ARRAY and point at the sub-plane's nq-slice.
 #define ELEM_LDS_N ((PFD_KMAX + 1) * (PFD_KMAX + 1) > 256 ? (PFD_KMAX + 1) * (PFD_KMAX + 1) : 256)
+
+// The dispatcher hands work-groups to the eight XCDs in turn (linear id mod 8), and each XCD has
+// its own L2.  xcd_tile maps a 2D grid's linear id to a logical tile (bx, by), bx fastest, so that
+// each XCD takes one contiguous range of logical tiles: neighbouring tiles, which share halo rows
+// or element edges, are then read through one L2.  A bijection of the grid for any size.
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+  constexpr int NXCD = 8;
+  const int gx = gridDim.x, total = gx * gridDim.y, lin = blockIdx.x + gx * blockIdx.y;
+  const int q = total / NXCD, r = total - q * NXCD, x = lin % NXCD, j = lin / NXCD;
+  const int lb = x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+  by = lb / gx;
+  bx = lb - by * gx;
+}
+
 #define ELEM_PROLOGUE                                                    \
-  const int e = blockIdx.x;                                              \
+  int e, pgrp;                                                           \
+  xcd_tile(e, pgrp);                                                     \
   const int ex = e % g.nx, ey = e / g.nx;                                \
   const int n = g.n, nq = g.nq;                                          \
   const int sub = (int)threadIdx.x / nq, t = (int)threadIdx.x - sub * nq; \
-  const int pl = blockIdx.y * g.ppw + sub;                               \
+  const int pl = pgrp * g.ppw + sub;                                     \
   const bool act = sub < g.ppw && pl < g.planes;                         \
   const int so = act ? sub * nq : 0;                                     \
   const int a = act ? t % n : 0, b = act ? t / n : 0;                    \
@@ -744,7 +759,9 @@ __device__ __forceinline__ void res_rows(int Nx, int Ny, int perx, const double*
   double* kyl = xs + NW * LR;       // [RROWS][NB] y-band rows iy0..
   double* myl = kyl + RROWS * NB;   // [RROWS] M_y
   double* dyl = myl + RROWS;        // [RROWS] Dirichlet flag of the row
-  const int pl = blockIdx.y, iy0 = blockIdx.x * RROWS;
+  int rb, pl;
+  xcd_tile(rb, pl);
+  const int iy0 = rb * RROWS;
   const long Ng = (long)Nx * Ny;
   const double* xp = x + pl * Ng;
   const int ix = threadIdx.x, ixc = ix < Nx ? ix : Nx - 1;   // threads past Nx load column Nx - 1
@@ -820,7 +837,9 @@ __global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, 
                                                       int apply_only, const unsigned char* __restrict__ ebot) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* xs = reinterpret_cast<double*>(smem_raw);
-  const long Ng = (long)Nx * Ny, pofs = (long)blockIdx.y * Ng;
+  int rb, pl;
+  xcd_tile(rb, pl);   // the tile res_rows takes
+  const long Ng = (long)Nx * Ny, pofs = (long)pl * Ng;
   res_rows<K>(Nx, Ny, perx, KxB, Mx, dirx, KyB, My, diry, shift, bb, x, apply_only, ebot, xs,
               [&](int, int iy, int ix, double v) { r[pofs + (long)iy * Nx + ix] = v; });
 }
@@ -2014,8 +2033,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8
 #pragma unroll
         for (int k = 0; k < 4; ++k) bq[q][j][k] = bn[q][j][k];
   }
-  const long Ng = (long)Nx * Ny, pofs = (long)blockIdx.y * Ng;
-  const int iy0 = blockIdx.x * RROWS;
+  int rb, pl;
+  xcd_tile(rb, pl);   // the tile res_rows took
+  const long Ng = (long)Nx * Ny, pofs = (long)pl * Ng;
+  const int iy0 = rb * RROWS;
 #pragma unroll
   for (int j = 0; j < NTW; ++j) {
     const int nt = w + 4 * j;
