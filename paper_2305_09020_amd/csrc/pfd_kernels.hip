@@ -113,6 +113,16 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
   by = lb / gx;
   bx = lb - by * gx;
 }
+// the same with by fastest in the logical order: the tiles of one bx (which share a streamed
+// operand block) land on one XCD
+__device__ __forceinline__ void xcd_tile_yfast(int& bx, int& by) {
+  constexpr int NXCD = 8;
+  const int gy = gridDim.y, total = gridDim.x * gy, lin = blockIdx.x + gridDim.x * blockIdx.y;
+  const int q = total / NXCD, r = total - q * NXCD, x = lin % NXCD, j = lin / NXCD;
+  const int lb = x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+  bx = lb / gy;
+  by = lb - bx * gy;
+}
 
 #define ELEM_PROLOGUE                                                    \
   int e, pgrp;                                                           \
@@ -1114,9 +1124,11 @@ __global__ void __launch_bounds__(256) k_gemm_sr(const TA* __restrict__ A, const
   const int KP = (K + 15) & ~15;
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
-  const int n0 = blockIdx.y * 16 * W;
+  int tbx, tby;
+  xcd_tile_yfast(tbx, tby);   // row tile tbx, column block tby
+  const int n0 = tby * 16 * W;
   const int ms = w % WS, ks = w / WS;
-  const int m = (blockIdx.x * WS + ms) * 16 + r16;
+  const int m = (tbx * WS + ms) * 16 + r16;
   const bool mok = m < Mtot;
   const TA* Am = A + (long)(mok ? m : 0) * K;
   V acc[W];
@@ -1194,7 +1206,7 @@ __global__ void __launch_bounds__(256) k_gemm_sr(const TA* __restrict__ A, const
         acc[j][q] = v;
       }
   }
-  const int mb = (blockIdx.x * WS + ms) * 16;
+  const int mb = (tbx * WS + ms) * 16;
 #pragma unroll
   for (int j = 0; j < W; ++j) {
     const int n = n0 + 16 * j + r16;
@@ -1227,10 +1239,12 @@ __global__ void __launch_bounds__(256) k_gemm_sl(const T* __restrict__ S, const 
   const int KP = (K + 15) & ~15;
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
-  const int m0 = blockIdx.y * 16 * W;
+  int tbx, tby;
+  xcd_tile_yfast(tbx, tby);   // column tile tbx, row block tby
+  const int m0 = tby * 16 * W;
   const int ms = w % WS, ks = w / WS;
   const long ctot = (long)planes * N;
-  const long cidx = ((long)blockIdx.x * WS + ms) * 16 + r16;
+  const long cidx = ((long)tbx * WS + ms) * 16 + r16;
   const bool cok = cidx < ctot;
   const int p = cok ? (int)(cidx / N) : 0;
   const int n = cok ? (int)(cidx - (long)p * N) : 0;
