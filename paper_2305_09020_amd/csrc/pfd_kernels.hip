@@ -1913,17 +1913,17 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(RT ==
 #pragma unroll
     for (int ct = 0; ct < TN; ++ct) {
       const int j = 16 * ct + r16;
-      const long ci = c0 + j;
-      const long cc = ci < ctot ? ci : ctot - 1;
-      const long p = cc / Nx;
-      const int n = (int)(cc - p * Nx);
+      const int ci = c0i + j;
+      const int cc = ci < ctoti ? ci : ctoti - 1;
+      const int p = cc / Nx;
+      const int n = cc - p * Nx;
       const double lxs = lx[n] + shift[p];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = 16 * mt + Mfma<T>::row(g, q);
         const int ic = i < Ny ? i : Ny - 1;
         const double den = ly[ic] + lxs;
-        const T u = (i < Ny && ci < ctot && den != 0.0) ? T(double(acc[rt][ct][q]) / den) : T(0);
+        const T u = (i < Ny && ci < ctoti && den != 0.0) ? T(double(acc[rt][ct][q]) / den) : T(0);
         Us[i * LDC + j] = u;
       }
     }
@@ -1936,14 +1936,14 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(RT ==
     if (mt >= MT) continue;
 #pragma unroll
     for (int ct = 0; ct < TN; ++ct) {
-      const long ci = c0 + 16 * ct + r16;
-      if (ci >= ctot) continue;
-      const long p = ci / Nx;
-      const int n = (int)(ci - p * Nx);
+      const int ci = c0i + 16 * ct + r16;
+      if (ci >= ctoti) continue;
+      const int p = ci / Nx;
+      const int n = ci - p * Nx;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = 16 * mt + Mfma<T>::row(g, q);
-        if (i < Ny) T3[(p * Ny + i) * (long)ldo + n] = acc[rt][ct][q];   // row stride ldo (>= Nx)
+        if (i < Ny) T3[((long)p * Ny + i) * (long)ldo + n] = acc[rt][ct][q];   // row stride ldo (>= Nx)
       }
     }
   }
