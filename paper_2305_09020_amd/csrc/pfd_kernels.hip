@@ -2084,7 +2084,7 @@ __global__ void __launch_bounds__(256) k_p4(const float* __restrict__ T3, int Mt
   V acc[TG];
 #pragma unroll
   for (int j = 0; j < TG; ++j) acc[j] = V{0.f, 0.f, 0.f, 0.f};
-  constexpr int CH = 2;
+  constexpr int CH = TG == 1 ? 4 : 2;   // slices per prefetched chunk (registers grow with TG)
   float a[CH][4], an[CH][4], b[CH][TG][4], bn[CH][TG][4];
   auto load = [&](int c0, float (&aa)[CH][4], float (&bb)[CH][TG][4]) {
 #pragma unroll
