@@ -152,6 +152,7 @@ struct pfd_ctx {
                                            // wave, 5 = k_srp (matrix resident in LDS)
   int p1_srp = 0;                          // refined first pass through k_srp
   int num_cu = 256, lds_max = 65536;       // device: compute units, LDS bytes a work-group may use
+  long long hold_ticks = 50000;            // 0.5 ms of the device wall clock (autotuner's stream hold)
   // right sides of the step's solves per family and time level (u: three components), and how
   // many consecutive steps solved the family with them (the refined path recycles them for its
   // first residual once two are recorded: A x^n = b^n to the refinement's accuracy)

@@ -2536,13 +2536,25 @@ static void ztrans(pfd_ctx* c, const double* W, const double* in, double* out, c
 // with the tuned passes is timed against the fused strip kernels and the faster variant kept.
 // Scratch buffers only; the state is not touched.
 
+// Holds the stream for `ticks` of the device's constant-rate wall clock (one lane; the loop ends
+// when the clock has advanced that far).
+__global__ void k_hold(long long ticks) {
+  const long long t0 = wall_clock64();
+  while (wall_clock64() - t0 < ticks) {
+  }
+}
+
 // average time of f over reps back-to-back calls, the least of three such runs (a single run
-// picked between candidates within a few per cent of each other by clock and queue noise)
+// picked between candidates within a few per cent of each other by clock and queue noise).
+// Each run starts behind a 0.5 ms hold of the stream, so the host has queued every call before
+// the first one starts: small kernels are then timed back to back on the GPU, as a captured
+// step replays them, not at the rate the host can launch them.
 static double time_us(pfd_ctx* c, hipEvent_t e0, hipEvent_t e1, int reps, const std::function<void()>& f,
                       hipError_t& e) {
   f();
   double best = 0.0;
   for (int run = 0; run < 3 && !e; ++run) {
+    hipLaunchKernelGGL(k_hold, dim3(1), dim3(1), 0, c->stream, c->hold_ticks);
     (void)hipEventRecord(e0, c->stream);
     for (int i = 0; i < reps; ++i) f();
     (void)hipEventRecord(e1, c->stream);
@@ -2621,6 +2633,8 @@ hipError_t autotune(pfd_ctx* c) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) c->num_cu = v;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
       c->lds_max = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) == hipSuccess && v > 0)
+      c->hold_ticks = (long long)v / 2;   // kHz -> ticks in 0.5 ms
     bool ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_srp<double, 0>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max) == hipSuccess;
     ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_srp<float, 2>),
