@@ -149,7 +149,8 @@ struct pfd_ctx {
   double fdm_us[3] = {0.0, 0.0, 0.0};      // autotune timings (us per correction)
   int mid_tn = 1, mid_best_tn = 1;         // column tiles per work-group of the fused middle passes
   int p4_tg = 0;                           // refined last pass: 0 = GEMM, 1..4 = k_p4 column tiles per
-                                           // wave, 5 = k_srp (matrix resident in LDS)
+                                           // wave, 5 = k_srp (matrix resident in LDS), 6 = k_p4 one
+                                           // tile with four-slice fragment chunks
   int p1_srp = 0;                          // refined first pass through k_srp
   int num_cu = 256, lds_max = 65536;       // device: compute units, LDS bytes a work-group may use
   long long hold_ticks = 50000;            // 0.5 ms of the device wall clock (autotuner's stream hold)

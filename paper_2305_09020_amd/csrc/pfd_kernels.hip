@@ -2069,8 +2069,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8
 // (four consecutive contraction entries of its row) with one 16-byte load, and Sx^T comes as
 // right operand in fragment order (which is the fragment order of Sx as a left operand).  A wave
 // takes one 16-row tile of the flattened planes x rows and TG column tiles; contraction entries
-// past Nx are masked to zero.  EPI 2: x += ; EPI 3: x = .
-template <int EPI, int TG>
+// past Nx are masked to zero; fragments come CH slices per prefetched chunk.  EPI 2: x += ;
+// EPI 3: x = .
+template <int EPI, int TG, int CH>
 __global__ void __launch_bounds__(256) k_p4(const float* __restrict__ T3, int Mtot, int Nx, int KPX,
                                             const float* __restrict__ SxFw, double* __restrict__ X) {
   typedef Mfma<float>::V V;
@@ -2084,7 +2085,6 @@ __global__ void __launch_bounds__(256) k_p4(const float* __restrict__ T3, int Mt
   V acc[TG];
 #pragma unroll
   for (int j = 0; j < TG; ++j) acc[j] = V{0.f, 0.f, 0.f, 0.f};
-  constexpr int CH = TG == 1 ? 4 : 2;   // slices per prefetched chunk (registers grow with TG)
   float a[CH][4], an[CH][4], b[CH][TG][4], bn[CH][TG][4];
   auto load = [&](int c0, float (&aa)[CH][4], float (&bb)[CH][TG][4]) {
 #pragma unroll
@@ -2140,20 +2140,22 @@ __global__ void __launch_bounds__(256) k_p4(const float* __restrict__ T3, int Mt
 }
 
 // k_p4 over P planes (tg column tiles per wave); false where it does not apply
-static bool p4_launch(pfd_ctx* c, const Dir1D& dx, int P, const float* t3, double* x, bool overwrite, int tg) {
+// form: 1..4 column tiles per wave with two-slice chunks, 6 one tile with four-slice chunks
+static bool p4_launch(pfd_ctx* c, const Dir1D& dx, int P, const float* t3, double* x, bool overwrite, int form) {
   const int Nx = c->Nx, KPX = (Nx + 15) & ~15, NT = KPX / 16;
-  if (tg < 1 || tg > 4) return false;
+  if (!((form >= 1 && form <= 4) || form == 6)) return false;
+  const int tg = form == 6 ? 1 : form;
   const long Mtot = (long)P * c->Ny;
   const long waves = ((Mtot + 15) / 16) * ((NT + tg - 1) / tg);
   const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
-#define P4_CASE(TG_)                                                                                       \
-  if (tg == TG_) {                                                                                         \
-    if (overwrite)                                                                                         \
-      LAUNCH(PFD_PROF_GEMM32, (k_p4<3, TG_>), grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x); \
-    else                                                                                                   \
-      LAUNCH(PFD_PROF_GEMM32, (k_p4<2, TG_>), grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x); \
+#define P4_CASE(F_, TG_, CH_)                                                                                 \
+  if (form == F_) {                                                                                           \
+    if (overwrite)                                                                                            \
+      LAUNCH(PFD_PROF_GEMM32, (k_p4<3, TG_, CH_>), grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x); \
+    else                                                                                                      \
+      LAUNCH(PFD_PROF_GEMM32, (k_p4<2, TG_, CH_>), grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x); \
   }
-  P4_CASE(1) P4_CASE(2) P4_CASE(3) P4_CASE(4)
+  P4_CASE(1, 1, 2) P4_CASE(2, 2, 2) P4_CASE(3, 3, 2) P4_CASE(4, 4, 2) P4_CASE(6, 1, 4)
 #undef P4_CASE
   return true;
 }
@@ -2707,8 +2709,10 @@ hipError_t autotune(pfd_ctx* c) {
     }
     c->mid_tn = c->mid_best_tn;
     int best_tg = 0;
-    const int tg_max = srp_lds(c, c->Nx, c->Nx) ? 5 : 4;
-    for (int tg = 1; tg <= tg_max && fp32 && c->fdm_us[2] > 0.0 && !e; ++tg) {   // the refined last pass
+    const bool srp_ok = srp_lds(c, c->Nx, c->Nx);
+    for (const int tg : {1, 6, 2, 3, 4, 5}) {   // the refined last pass: each form of k_p4, k_srp
+      if (!fp32 || !(c->fdm_us[2] > 0.0) || e) break;
+      if (tg == 5 && !srp_ok) continue;
       c->p4_tg = tg;
       const double us = time_us(c, e0, e1, 10, run_fdm, e);
       if (us < c->fdm_us[2]) {

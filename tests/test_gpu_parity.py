@@ -361,11 +361,12 @@ def test_solver_variants_agree_on_benchmark_shapes(precision):
             assert e < (1e-12 if precision == 0 else 1e-9), (fam, var, e)
 
 
-@pytest.mark.parametrize("tg,p1", [(0, 0), (1, 0), (2, 0), (3, 0), (4, 0), (5, 0), (0, 1), (5, 1)])
+@pytest.mark.parametrize("tg,p1", [(0, 0), (1, 0), (2, 0), (3, 0), (4, 0), (5, 0), (6, 0), (0, 1), (5, 1)])
 def test_refined_last_pass_every_width(tg, p1):
     """Refined solves with the fused middle passes and each form of the last pass (GEMM; the
-    padded-row matrix-core kernel with 1-4 column tiles per wave; the kernel with Sx resident
-    in LDS) and of the first pass (GEMM; Sx resident in LDS) match SciPy's sparse LU for every
+    padded-row matrix-core kernel with 1-4 column tiles per wave, and with one tile and
+    four-slice fragment chunks; the kernel with Sx resident in LDS) and of the first pass
+    (GEMM; Sx resident in LDS) match SciPy's sparse LU for every
     family on a 3-plane batch (Nx = 41: three column tiles, the last one ragged)."""
     torch = _torch()
     m, bc, par = box_case(n=5, K=8, periodic=True, top=OPEN)
