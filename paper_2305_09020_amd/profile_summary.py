@@ -58,15 +58,23 @@ def main(src, dst):
                  "# instrumented and replay runs; kernel durations are the profiler's",
                  "#", "# %-64s %7s %12s %10s %6s %s" % ("kernel", "calls", "total_us", "avg_us", "pct", "class")]
         tot = collections.defaultdict(lambda: [0.0, 0])
-        for r in csv.DictReader(open(os.path.join(src, "stats_%s" % wl, "run_kernel_stats.csv"))):
+        rows = list(csv.DictReader(open(os.path.join(src, "stats_%s" % wl, "run_kernel_stats.csv"))))
+        # the autotuner's stream holds (k_hold: a timed wait before each timing run) are no work
+        holds = [r for r in rows if "k_hold" in r["Name"]]
+        rows = [r for r in rows if "k_hold" not in r["Name"]]
+        grand = sum(float(r["TotalDurationNs"]) for r in rows)
+        if holds:
+            lines.insert(5, "# (the autotuner's stream holds, k_hold: %d launches, %.1f us, are left out)"
+                         % (sum(int(r["Calls"]) for r in holds), sum(float(r["TotalDurationNs"]) for r in holds) / 1e3))
+        for r in rows:
             n = r["Name"]
             c = cls_of(n)
             tot[c][0] += float(r["TotalDurationNs"])
             tot[c][1] += int(r["Calls"])
-            if float(r["Percentage"]) >= 0.3:
+            pct = 100.0 * float(r["TotalDurationNs"]) / grand
+            if pct >= 0.3:
                 lines.append("  %-64s %7s %12.1f %10.2f %6.2f %s" % (n.split("(")[0][:64], r["Calls"],
-                             float(r["TotalDurationNs"]) / 1e3, float(r["AverageNs"]) / 1e3,
-                             float(r["Percentage"]), c))
+                             float(r["TotalDurationNs"]) / 1e3, float(r["AverageNs"]) / 1e3, pct, c))
         lines.append("#")
         for c, (t, n) in sorted(tot.items(), key=lambda kv: -kv[1][0]):
             lines.append("# class %-9s %8.1f us total, average launch %8.2f us over %d launches" % (c, t / 1e3, t / n / 1e3, n))
