@@ -713,17 +713,20 @@ __global__ void k_residual(int Nx, int Ny, int planes, int perx, const double* _
   const int iy = node / Nx, ix = node - iy * Nx;
   const double* xp = x + pl * Ng;
   const double* xrow = xp + (long)iy * Nx;
+  // neighbour indices are clamped, not skipped: the band coefficients outside the operator are
+  // zero, and with no branch around them all 4K+2 loads are issued together
   double ax = 0.0, ay = 0.0;
 #pragma unroll
   for (int d = -K; d <= K; ++d) {
     int j = ix + d;
-    if (perx) { j = (j < 0) ? j + Nx : (j >= Nx ? j - Nx : j); } else if (j < 0 || j >= Nx) continue;
+    if (perx) j = (j < 0) ? j + Nx : (j >= Nx ? j - Nx : j);
+    else j = (j < 0) ? 0 : (j >= Nx ? Nx - 1 : j);
     ax += KxB[(long)(d + K) * Nx + ix] * xrow[j];
   }
 #pragma unroll
   for (int d = -K; d <= K; ++d) {
-    const int j = iy + d;
-    if (j < 0 || j >= Ny) continue;
+    int j = iy + d;
+    j = (j < 0) ? 0 : (j >= Ny ? Ny - 1 : j);
     ay += KyB[(long)(d + K) * Ny + iy] * xp[(long)j * Nx + ix];
   }
   const double xv = xrow[ix];
