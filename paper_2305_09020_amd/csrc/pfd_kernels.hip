@@ -148,40 +148,53 @@ __device__ __forceinline__ void xcd_tile_yfast(int& bx, int& by) {
 // ------------------------------------------------------------------ DSS (gather-sum)
 // sum of the element-local contributions at global node (ix, iy) of plane pl
 __device__ __forceinline__ double dss(const Geo& g, const double* L, int pl, int ix, int iy) {
-  int exs[2], as[2], nxe = 0;
-  int eys[2], bs[2], nye = 0;
+  // the (at most) two elements along x and along y that hold the node, as (element, local index)
+  // pairs with a 0/1 weight; an absent second pair repeats the first with weight 0, so the four
+  // loads always issue together (no branch around them) and absent terms add exact zeros
   const int K = g.K;
-  if (g.periodic) {
-    if (ix % K == 0) {
-      int ex = ix / K;
-      exs[nxe] = (ex == 0) ? g.nx - 1 : ex - 1; as[nxe++] = K;
-      exs[nxe] = ex; as[nxe++] = 0;
-    } else {
-      exs[nxe] = ix / K; as[nxe++] = ix % K;
-    }
+  int ex0, a0, ex1, a1;
+  double wx1;
+  if (ix % K == 0) {
+    const int ex = ix / K;
+    const bool left = g.periodic || ex > 0, right = g.periodic || ex < g.nx;
+    const int el = ex == 0 ? g.nx - 1 : ex - 1;   // the left element (wrapped when periodic)
+    ex0 = left ? el : ex;
+    a0 = left ? K : 0;
+    ex1 = ex < g.nx ? ex : el;                    // a node past the last element has only one
+    a1 = ex < g.nx ? 0 : K;
+    wx1 = (left && right) ? 1.0 : 0.0;
   } else {
-    if (ix % K == 0) {
-      int ex = ix / K;
-      if (ex > 0) { exs[nxe] = ex - 1; as[nxe++] = K; }
-      if (ex < g.nx) { exs[nxe] = ex; as[nxe++] = 0; }
-    } else {
-      exs[nxe] = ix / K; as[nxe++] = ix % K;
-    }
+    ex0 = ex1 = ix / K;
+    a0 = a1 = ix % K;
+    wx1 = 0.0;
   }
+  int ey0, b0, ey1, b1;
+  double wy1;
   if (iy % K == 0) {
-    int ey = iy / K;
-    if (ey > 0) { eys[nye] = ey - 1; bs[nye++] = K; }
-    if (ey < g.ny) { eys[nye] = ey; bs[nye++] = 0; }
+    const int ey = iy / K;
+    const bool below = ey > 0, above = ey < g.ny;
+    ey0 = below ? ey - 1 : ey;
+    b0 = below ? K : 0;
+    ey1 = above ? ey : ey - 1;
+    b1 = above ? 0 : K;
+    wy1 = (below && above) ? 1.0 : 0.0;
   } else {
-    eys[nye] = iy / K; bs[nye++] = iy % K;
+    ey0 = ey1 = iy / K;
+    b0 = b1 = iy % K;
+    wy1 = 0.0;
   }
-  double acc = 0.0;
   const long base = (long)pl * g.nx * g.ny;
-  for (int j = 0; j < nye; ++j)
-    for (int i = 0; i < nxe; ++i) {
-      long e = base + eys[j] * g.nx + exs[i];
-      acc += L[e * g.nq + bs[j] * g.n + as[i]];
-    }
+  const double* L00 = L + (base + (long)ey0 * g.nx + ex0) * g.nq + b0 * g.n + a0;
+  const double* L01 = L + (base + (long)ey0 * g.nx + ex1) * g.nq + b0 * g.n + a1;
+  const double* L10 = L + (base + (long)ey1 * g.nx + ex0) * g.nq + b1 * g.n + a0;
+  const double* L11 = L + (base + (long)ey1 * g.nx + ex1) * g.nq + b1 * g.n + a1;
+  const double v00 = *L00, v01 = *L01, v10 = *L10, v11 = *L11;
+  // same order of the present terms as a loop over (y pair, x pair)
+  double acc = 0.0;
+  acc += v00;
+  acc += wx1 * v01;
+  acc += wy1 * v10;
+  acc += wy1 * wx1 * v11;
   return acc;
 }
 
