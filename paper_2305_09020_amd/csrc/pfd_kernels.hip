@@ -218,9 +218,10 @@ __device__ __forceinline__ double dss(const Geo& g, const double* L, int pl, int
 // Dirichlet node of a family (gap nodes of a partial electrode row are unknowns)
 __device__ __forceinline__ bool is_dir(const unsigned char* dirx, const unsigned char* diry,
                                        const unsigned char* ebot, int ix, int iy) {
-  if (dirx[ix]) return true;
-  if (!diry[iy]) return false;
-  return !(iy == 0 && ebot && !ebot[ix]);
+  // the flag loads are issued together (ebot is the same for every thread: null or not)
+  const bool dxi = dirx[ix] != 0, dyi = diry[iy] != 0;
+  const bool gap = ebot && ebot[ix] == 0 && iy == 0;   // bottom-row gap node of an electrode set
+  return dxi || (dyi && !gap);
 }
 
 __device__ __forceinline__ void rhs_out(const Geo& g, const Par& P, const Lift& L, const double* gD,
@@ -229,8 +230,10 @@ __device__ __forceinline__ void rhs_out(const Geo& g, const Par& P, const Lift& 
   const double bo = L.bprev ? bb[id] : 0.0;   // b^{n-1}, in the slot that now takes b^{n+1}
   bb[id] = b;
   const bool dn = is_dir(L.dirx, L.diry, L.ebot, ix, iy);
+  const double gd = gD ? gD[id] : 0.0;   // (no Dirichlet data: no Dirichlet node)
   if (Fn) {
-    x0[id] = dn ? gD[id] : P.cs_n * Fn[id] + P.cs_o * Fo[id];
+    const double fn = Fn[id], fo = Fo[id];
+    x0[id] = dn ? gd : P.cs_n * fn + P.cs_o * fo;
     // recycled first residual: A x^n = b^n, A x^{n-1} = b^{n-1} and the Dirichlet data did not
     // change, so b - A x0 = b - (cs_n b^n + cs_o b^{n-1}) on free nodes
     if (L.bprev) r[id] = dn ? 0.0 : b - (P.cs_n * L.bprev[id] + P.cs_o * bo);
@@ -238,14 +241,24 @@ __device__ __forceinline__ void rhs_out(const Geo& g, const Par& P, const Lift& 
   }
   if (dn) {
     r[id] = 0.0;
-    x0[id] = gD[id];
+    x0[id] = gd;
     return;
   }
   double ax = 0.0, ay = 0.0;
-  if (L.dirx[0]) ax += L.Kx0[ix] * gD[pofs + (long)iy * g.Nx];
-  if (L.dirx[g.Nx - 1]) ax += L.KxN[ix] * gD[pofs + (long)iy * g.Nx + g.Nx - 1];
-  if (L.diry[0] && iy > 0 && (!L.ebot || L.ebot[ix])) ay += L.Ky0[iy] * gD[pofs + ix];
-  if (L.diry[g.Ny - 1]) ay += L.KyN[iy] * gD[pofs + (long)(g.Ny - 1) * g.Nx + ix];
+  if (gD) {
+    // lift of the Dirichlet sides: every term loaded (the coupling columns and the data exist
+    // for every side), the flags only select, so no load waits behind a flag
+    const bool dx0 = L.dirx[0] != 0, dxN = L.dirx[g.Nx - 1] != 0, dyN = L.diry[g.Ny - 1] != 0;
+    const bool dy0 = L.diry[0] != 0 && iy > 0 && (!L.ebot || L.ebot[ix]);
+    const double t0 = L.Kx0[ix] * gD[pofs + (long)iy * g.Nx];
+    const double tN = L.KxN[ix] * gD[pofs + (long)iy * g.Nx + g.Nx - 1];
+    const double s0 = L.Ky0[iy] * gD[pofs + ix];
+    const double sN = L.KyN[iy] * gD[pofs + (long)(g.Ny - 1) * g.Nx + ix];
+    if (dx0) ax += t0;
+    if (dxN) ax += tN;
+    if (dy0) ay += s0;
+    if (dyN) ay += sN;
+  }
   if (L.ebot && iy == 0) {  // gap node: coupling along the bottom row to the electrode nodes
     for (int d = -g.K; d <= g.K; ++d) {
       int j = ix + d;
