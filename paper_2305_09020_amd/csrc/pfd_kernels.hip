@@ -485,6 +485,17 @@ __global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi
     ff[0] = fx[id];
     ff[1] = fy[id];
   }
+  // the z-derivatives (3D) are requested before the barrier: in flight during the x, y sums
+  double zphi = 0.0, zPhi = 0.0, zux = 0.0, zuy = 0.0, zuz = 0.0, zP = 0.0;
+  if (Z3 && act) {
+    const long id = pofs + gi;
+    zphi = z.dzphi[id];
+    zPhi = z.dzPhi[id];
+    zux = z.dzux[id];
+    zuy = z.dzuy[id];
+    zuz = z.dzuz[id];
+    zP = z.dzP[id];
+  }
   __syncthreads();
   double G[3] = {0.0, 0.0, 0.0}, Kv[3] = {0.0, 0.0, 0.0}, om[3] = {0.0, 0.0, 0.0}, mr = 0.0;
   if (act) {
@@ -501,10 +512,10 @@ __global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi
     if (Z3) fl[NF - 1] = suz;
     double dX[NF], dY[NF];
     grad2<NF>(s, n, a, b, fl, sx, sy, dX, dY);
-    const double gph[3] = {dX[0], dY[0], Z3 ? z.dzphi[id] : 0.0};
+    const double gph[3] = {dX[0], dY[0], zphi};
     const double cnu = (rho * dmm - mu * drr) * irho * irho;  // grad(mu/rho) = cnu grad(phi)
     const double jc = 0.5 * (P.rho1 - P.rho2) * P.lam * P.gamma1;
-    const double Jt[3] = {jc * dX[1], jc * dY[1], Z3 ? jc * z.dzPhi[id] : 0.0};
+    const double Jt[3] = {jc * dX[1], jc * dY[1], Z3 ? jc * zPhi : 0.0};
     const double u[3] = {sux[t], suy[t], suz[t]};
     // gu[i][k] = d_i u*_k
     double gu[3][3];
@@ -515,9 +526,9 @@ __global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi
     if (Z3) {
       gu[0][2] = dX[NF - 1];
       gu[1][2] = dY[NF - 1];
-      gu[2][0] = z.dzux[id];
-      gu[2][1] = z.dzuy[id];
-      gu[2][2] = z.dzuz[id];
+      gu[2][0] = zux;
+      gu[2][1] = zuy;
+      gu[2][2] = zuz;
     } else {
       gu[0][2] = gu[1][2] = gu[2][0] = gu[2][1] = gu[2][2] = 0.0;
     }
@@ -526,7 +537,7 @@ __global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi
     om[2] = gu[0][1] - gu[1][0];
     const double lap = ps - P.alpha * ph;
     const double dep = deps_of(P, ph);
-    const double gP[3] = {dX[4], dY[4], Z3 ? z.dzP[id] : 0.0};
+    const double gP[3] = {dX[4], dY[4], zP};
     const double cP = 1.0 / P.rho0 - irho;
     const double gnu[3] = {cnu * gph[0], cnu * gph[1], cnu * gph[2]};
     const double cr[3] = {gnu[1] * om[2] - gnu[2] * om[1], gnu[2] * om[0] - gnu[0] * om[2],
