@@ -1900,6 +1900,9 @@ __device__ __forceinline__ void fdm_mid_pass(const T* __restrict__ Aw, const T* 
   }
 }
 
+// One row tile per wave (RT = 1) is held to 72 VGPRs (seven waves per SIMD): at 129 rows (nine
+// row tiles, so nine waves per work-group) three work-groups then fit a CU (27 of 28 wave
+// slots), and the grid of a 128-plane solve runs in one round.
 template <typename T, int RT, int TN>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 7 : 1))) k_fdm_mid(int planes, int Ny, int Nx, long Ng, const T* __restrict__ SyTw,
                                                   const T* __restrict__ Syw, const T* __restrict__ T1,
