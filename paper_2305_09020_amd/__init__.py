@@ -15,6 +15,10 @@ LIBPATH = os.path.join(HERE, "libpfd.so")
 
 if not os.path.exists(LIBPATH):
     raise ImportError("libpfd.so is not built (run paper_2305_09020_amd/build.py)")
+# torch ships its own HIP runtime: loading it before the library makes the library's HIP
+# dependency resolve to that same runtime (one per process).  Loaded the other way round, the
+# process held two runtimes and the library's found no device.
+import torch  # noqa: E402,F401
 _lib = ctypes.CDLL(LIBPATH)
 
 # ---- enums (mirror include/pfd.h) -------------------------------------------------

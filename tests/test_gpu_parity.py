@@ -206,6 +206,34 @@ def test_benchmark_workload_parity(precision, tol, iters):
     check_parity(out, tol, field_tol=dict(ux=1e-8, uy=1e-8))
 
 
+def test_single_correction_forms_exact_residual():
+    """With one FP32 correction per solve the first residual is formed exactly every step (a
+    recycled one would carry each step's final residual into the next right sides, where no
+    second correction removes it): a context stepped plainly and a twin made to forget the
+    previous right sides before every step give the same fields."""
+    _torch()
+    m, bc, _ = box_case(n=4, K=6)
+    par = c1_params()
+    X, Y = m.X.ravel()[None, :], m.Y.ravel()[None, :]
+    phi = np.tanh((np.sqrt((X - 0.5) ** 2 + (Y - 0.3) ** 2) - 0.25) / (math.sqrt(2) * par.eta))
+    phi = np.repeat(phi, 2, axis=0)
+    vd = np.broadcast_to(np.where(np.isclose(Y, 1.0), 1.0, 0.0), phi.shape).copy()
+    shape = (2, m.Ny, m.Nx)
+    ctxs = [gpu_context(m, par, bc, nbatch=2, precision=1, refine_iters=1) for _ in range(2)]
+    ctxs[1].set_tuning(ctxs[0].tuning())
+    for c in ctxs:
+        c.set_field("phi", phi.reshape(shape))
+        c.set_sources({"Vd": vd.reshape(shape)})
+        c.init_potential(tol=1e-12, max_iter=2000)
+    for n in range(8):
+        ctxs[0].step(1)
+        ctxs[1].set_sources({"Vd": vd.reshape(shape)})   # forgets the recorded right sides
+        ctxs[1].step(1)
+    for k in ("phi", "psi", "V", "P", "ux", "uy"):
+        a, b = (c.get_field(k) for c in ctxs)
+        assert rel_err(a, b) < 1e-14, (k, rel_err(a, b))
+
+
 @pytest.mark.parametrize("nz", [0, 8])
 def test_recycled_first_residual_matches_explicit(nz):
     """The refined path forms its first residual from the right sides of the two previous
