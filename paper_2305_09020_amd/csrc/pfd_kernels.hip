@@ -736,7 +736,7 @@ __device__ __forceinline__ void stage_lds(int n, Value value, Store store) {
 // Kx[ix][ix+d] (periodic wrap in x; zero outside the band), so consecutive threads read
 // consecutive coefficients.  apply_only = 1 computes y = A x on every node.
 template <int K>
-__global__ void k_residual(int Nx, int Ny, int planes, int perx, const double* __restrict__ KxB,
+__global__ void __launch_bounds__(WG) k_residual(int Nx, int Ny, int planes, int perx, const double* __restrict__ KxB,
                            const double* __restrict__ Mx, const unsigned char* __restrict__ dirx,
                            const double* __restrict__ KyB, const double* __restrict__ My,
                            const unsigned char* __restrict__ diry, const double* __restrict__ shift,
@@ -2044,7 +2044,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8
   __syncthreads();   // zero fill before the residual rows land (res_rows syncs after its staging)
   res_rows<K>(Nx, Ny, perx, KxB, Mx, dirx, KyB, My, diry, shift, bb, x, 0, ebot, xs,
               [&](int rl, int, int ix, double v) { Rl[rl * LDR + ix] = float(v); });
-  __syncthreads();
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
   const int NT = KS;   // column tiles of the square product
@@ -2064,7 +2063,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8
       }
     }
   };
-  loadB(0, bq);
+  loadB(0, bq);   // the first Sx fragments are in flight while the other waves finish their rows
+  __syncthreads();
   for (int c0 = 0; c0 < KS; c0 += CH) {
     if (c0 + CH < KS) loadB(c0 + CH, bn);
 #pragma unroll
@@ -3071,8 +3071,11 @@ __global__ void k_spec_rhs(Geo g, Par P, Lift L, const double* A, const double* 
   double v = A[id];
   if (B) {
     if (bmode == 0) {
+      // the partner plane of a (cos, sin) pair; planes 0 and 1 have beta = 0 and read their
+      // neighbour only to add a zero, so the load waits behind no test of beta
       const double bd = betad[pl];
-      if (bd != 0.0) v += ((pl & 1) == 0) ? -bd * B[id + g.Ng] : bd * B[id - g.Ng];
+      const double bp = B[((pl & 1) == 0) ? id + g.Ng : id - g.Ng];
+      v += ((pl & 1) == 0) ? -bd * bp : bd * bp;
     } else {
       v += beta2[pl] * B[id];
     }
