@@ -359,6 +359,12 @@ __global__ void __launch_bounds__(WG) k_psi_elem(Geo g, Par P, const double* phn
     uys = P.cs_n * uyn[pofs + gi] + P.cs_o * uyo[pofs + gi];
     gg = gsrc[pofs + gi];
   }
+  // 3D: u*_z d(phi*)/dz (the z-derivative taken from the spectral phi), loaded before the barrier
+  double uzd = 0.0;
+  if (uzn && act) {
+    const long id = pofs + gi;
+    uzd = (P.cs_n * uzn[id] + P.cs_o * uzo[id]) * dzphs[id];
+  }
   __syncthreads();
   double q1 = 0.0;
   if (act) {
@@ -366,10 +372,7 @@ __global__ void __launch_bounds__(WG) k_psi_elem(Geo g, Par P, const double* phn
     double dx[2], dy[2];
     grad2<2>(s, n, a, b, f, sx, sy, dx, dy);
     double adv = uxs * dx[0] + uys * dy[0];
-    if (uzn) {  // 3D: + u*_z d(phi*)/dz, the z-derivative taken from the spectral phi
-      const long id = pofs + gi;
-      adv += (P.cs_n * uzn[id] + P.cs_o * uzo[id]) * dzphs[id];
-    }
+    if (uzn) adv += uzd;
     q1 = (gg - adv + phh / P.dt) / (P.lam * P.gamma1);
     sgx[t] = s.w[a] * dx[1];
     sgy[t] = s.w[b] * dy[1];
@@ -665,16 +668,27 @@ __global__ void __launch_bounds__(WG) k_gradP_elem(Geo g, Par P, const double* P
                                                    double* L1, double* L2, double* LAz) {
   ELEM_PROLOGUE
   ELEM_ARRAY(sP)
-  if (act) sP[t] = Pnew[pofs + gi];
+  // the element-local sums this kernel adds to (and the 3D z-derivative) are requested before
+  // the barrier, so they arrive while the x, y derivatives are formed
+  double l1 = 0.0, l2 = 0.0, laz = 0.0, dzp = 0.0;
+  if (act) {
+    sP[t] = Pnew[pofs + gi];
+    l1 = L1[lofs];
+    l2 = L2[lofs];
+    if (dzP) {
+      laz = LAz[lofs];
+      dzp = dzP[pofs + gi];
+    }
+  }
   __syncthreads();
   if (act) {
     const double c = -0.25 * hx * hy * s.w[a] * s.w[b] / (P.nu_m * P.rho0);
     const double* f[1] = {sP};
     double dx[1], dy[1];
     grad2<1>(s, n, a, b, f, sx, sy, dx, dy);
-    L1[lofs] += c * dx[0];
-    L2[lofs] += c * dy[0];
-    if (dzP) LAz[lofs] += c * dzP[pofs + gi];
+    L1[lofs] = l1 + c * dx[0];
+    L2[lofs] = l2 + c * dy[0];
+    if (dzP) LAz[lofs] = laz + c * dzp;
   }
 }
 
