@@ -135,7 +135,9 @@ class Scheme:
     Sources passed to step() are nodal arrays at t^{n+1} (missing -> 0).
     """
 
-    def __init__(self, mesh: Mesh2D, par: Params, bc: BCs, Nz=None, Lz=None):
+    def __init__(self, mesh: Mesh2D, par: Params, bc: BCs, Nz=None, Lz=None, lu_order="COLAMD"):
+        # lu_order: column ordering of SuperLU (any ordering solves the same systems exactly;
+        # a second ordering gives a second, equally valid rounding of the same scheme)
         self.m, self.par, self.bc = mesh, par, bc
         self.c = par.derived()
         self.is3d = Nz is not None
@@ -184,6 +186,7 @@ class Scheme:
         self.shift = {"V": 0.0, "psi": self.c["c_psi"], "phi": self.c["c_phi"],
                       "P": 0.0, "u": self.c["c_u"]}
         self._lu = {}
+        self.lu_order = lu_order
         self.n = 0
         self.state = None
 
@@ -224,9 +227,9 @@ class Scheme:
         if singular:
             mm = m.Mdiag.reshape(-1, 1)
             Ab = sp.bmat([[A, sp.csr_matrix(mm)], [sp.csr_matrix(mm.T), None]]).tocsc()
-            lu = spla.splu(Ab)
+            lu = spla.splu(Ab, permc_spec=self.lu_order)
         else:
-            lu = spla.splu(A[free][:, free].tocsc())
+            lu = spla.splu(A[free][:, free].tocsc(), permc_spec=self.lu_order)
         ent = dict(A=A, free=free, D=D, lu=lu, singular=singular)
         self._lu[key] = ent
         return ent

@@ -408,3 +408,49 @@ def test_equilibrium_marching_decreases_energy_and_stops_at_tolerance():
     assert all(b <= a + 1e-12 * abs(a) for a, b in zip(energies, energies[1:])), energies
     assert energies[-1] < energies[0]
     assert abs(sch.mass() - m0) < 1e-12 * abs(m0)
+
+
+def test_nyquist_mode_potential_and_derivative_closed_form():
+    """Reading R-nyq (Sec. 3.2.2, Fourier modes k = 0..Nz/2 of eqs. 74 and 78): the Nyquist
+    mode keeps beta^2 = (pi Nz / Lz)^2 in its operator and has no first z-derivative.
+    Laplace problem (phi = 1, so eps(phi) = eps0 and Remark 3.1 is one solve) in the box
+    with V = 0 at the bottom and V = cos(beta_1 z) + cos(beta_N z) on the top (beta_N z_j =
+    pi j, so the second term is the Nyquist mode (-1)^j), insulated sides:
+      V = sinh(beta_1 y)/sinh(beta_1) cos(beta_1 z) + sinh(beta_N y)/sinh(beta_N) (-1)^j,
+      E = grad V at the nodes: E_z = -beta_1 sinh(beta_1 y)/sinh(beta_1) sin(beta_1 z) (the
+      Nyquist term contributes nothing), E_y the y-derivative of both terms.
+    The discrete fields converge exponentially in K to these; a wrong Nyquist shift (0, or
+    a mode off by one), a Nyquist derivative that is not dropped, or the sign of E_z would
+    leave an O(1) error."""
+    Nz, Lz = 8, 8.0
+    b1, bN = 2 * np.pi / Lz, np.pi * Nz / Lz
+    errs = []
+    for K in (6, 10):
+        xb = np.linspace(0, 1, 3)
+        m = Mesh2D(xb, xb, K)
+        bc = BCs(side={BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}, pot_sides=(BOTTOM, TOP))
+        par = Params(rho1=1.0, rho2=2.0, mu1=0.01, mu2=0.02, eps1=4.0, eps2=1.0,
+                     lam=3 * 0.05 / (2 * math.sqrt(2)), eta=0.05, gamma1=1e-2,
+                     theta_s_deg=90.0, dt=1e-5)
+        sch = Scheme(m, par, bc, Nz=Nz, Lz=Lz)
+        z = np.arange(Nz) * Lz / Nz
+        Y = m.Y.ravel()[None, :]
+        Z = z[:, None] + 0 * Y
+        top = np.isclose(Y, 1.0) + 0 * Z
+        vd = top * (np.cos(b1 * Z) + np.cos(bN * Z))
+        sch.set_state(np.ones((Nz, m.Ng)))
+        sch.init_potential(dict(Vd=vd))
+        o = sch.step(dict(Vd=vd), equilibrium=True)
+        sy1, syN = np.sinh(b1 * Y) / np.sinh(b1), np.sinh(bN * Y) / np.sinh(bN)
+        cy1, cyN = b1 * np.cosh(b1 * Y) / np.sinh(b1), bN * np.cosh(bN * Y) / np.sinh(bN)
+        V = sy1 * np.cos(b1 * Z) + syN * np.cos(bN * Z)
+        Ey = cy1 * np.cos(b1 * Z) + cyN * np.cos(bN * Z)
+        Ez = -b1 * sy1 * np.sin(b1 * Z)
+        errs.append((np.abs(o["V"] - V).max(), np.abs(o["Ey"] - Ey).max() / np.abs(Ey).max(),
+                     np.abs(o["Ez"] - Ez).max() / np.abs(Ez).max()))
+        # the Nyquist mode itself: its part of E_z vanishes identically
+        VN = np.fft.rfft(o["V"], axis=0)[-1]
+        assert np.abs(VN).max() > 0.1
+    (v6, y6, z6), (v10, y10, z10) = errs
+    assert v10 < 1e-9 and y10 < 1e-7 and z10 < 1e-9, errs
+    assert v10 < 1e-2 * v6 and y10 < 1e-2 * y6, errs
