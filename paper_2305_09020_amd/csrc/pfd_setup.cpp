@@ -160,6 +160,119 @@ void assemble_1d(int ne, const double* bp, int K, bool periodic, const std::vect
 
 // Fast-diagonalisation factors for one direction with Dirichlet flags at the
 // two ends (ignored when periodic).  Dirichlet rows of S are zero.
+// Refines an approximate orthonormal eigenbasis Q (m x m, column j an eigenvector, from the
+// FP64 Jacobi above) of the symmetric B_ab = K1[fa][fb] / sqrt(M[fa] M[fb]) in extended
+// precision (long double, 64-bit significand): two Newton-Schulz steps Q <- Q (3I - Q^T Q)/2
+// restore orthonormality, C = Q^T B Q is then diagonal up to the FP64 Jacobi's residual, and
+// cyclic Jacobi sweeps on C (a rotation where |c_pq| > u sqrt(c_pp c_qq), the relative
+// criterion of Demmel & Veselic 1992, so small eigenvalues keep their relative accuracy) are
+// accumulated into Q.  With the exact null vector w (singular operator: no Dirichlet node),
+// column 0 is set to w, the others are projected off it, and the sweeps leave column 0 out.
+// The FP64 Jacobi alone stops relative to the largest eigenvalues, which left the smooth
+// (small-eigenvalue) eigenvectors, and so the fast-diagonalisation inverse, accurate to only
+// about 1e-12 on a 161-node operator.
+static void refine_eig_ld(int m, const std::vector<int>& fr, const std::vector<double>& K1,
+                          const std::vector<double>& M1, int N, bool singular, std::vector<double>& lam,
+                          std::vector<double>& Qd) {
+  typedef long double LD;
+  std::vector<LD> B((size_t)m * m), Q((size_t)m * m), T((size_t)m * m), G((size_t)m * m);
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b < m; ++b)
+      B[(size_t)a * m + b] = (LD)K1[(size_t)fr[a] * N + fr[b]] / sqrtl((LD)M1[fr[a]] * (LD)M1[fr[b]]);
+  for (size_t i = 0; i < Q.size(); ++i) Q[i] = Qd[i];
+  auto matmul_tn = [&](const std::vector<LD>& X, const std::vector<LD>& Y, std::vector<LD>& Z) {   // Z = X^T Y
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        LD acc = 0.0L;
+        for (int k = 0; k < m; ++k) acc += X[(size_t)k * m + i] * Y[(size_t)k * m + j];
+        Z[(size_t)i * m + j] = acc;
+      }
+  };
+  auto newton_schulz = [&]() {
+    matmul_tn(Q, Q, G);   // G = Q^T Q
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) G[(size_t)i * m + j] = (i == j ? 1.5L : 0.0L) - 0.5L * G[(size_t)i * m + j];
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        LD acc = 0.0L;
+        for (int k = 0; k < m; ++k) acc += Q[(size_t)i * m + k] * G[(size_t)k * m + j];
+        T[(size_t)i * m + j] = acc;
+      }
+    Q.swap(T);
+  };
+  int j0 = 0;
+  if (singular) {
+    std::vector<LD> wv(m);
+    LD nrm = 0.0L;
+    for (int a = 0; a < m; ++a) {
+      wv[a] = sqrtl((LD)M1[fr[a]]);
+      nrm += wv[a] * wv[a];
+    }
+    nrm = sqrtl(nrm);
+    for (int a = 0; a < m; ++a) wv[a] /= nrm;
+    // the FP64 Jacobi sorted the null pair first; replace it by w and project the rest off w
+    for (int a = 0; a < m; ++a) Q[(size_t)a * m] = wv[a];
+    for (int j = 1; j < m; ++j) {
+      LD dot = 0.0L;
+      for (int a = 0; a < m; ++a) dot += wv[a] * Q[(size_t)a * m + j];
+      for (int a = 0; a < m; ++a) Q[(size_t)a * m + j] -= dot * wv[a];
+    }
+    j0 = 1;
+  }
+  newton_schulz();
+  newton_schulz();
+  // C = Q^T B Q
+  std::vector<LD> BQ((size_t)m * m), C((size_t)m * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      LD acc = 0.0L;
+      for (int k = 0; k < m; ++k) acc += B[(size_t)i * m + k] * Q[(size_t)k * m + j];
+      BQ[(size_t)i * m + j] = acc;
+    }
+  matmul_tn(Q, BQ, C);
+  auto c = [&](int i, int j) -> LD& { return C[(size_t)i * m + j]; };
+  const LD u = 1.1e-19L;
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    int rot = 0;
+    for (int p = j0; p < m - 1; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const LD apq = c(p, q);
+        if (fabsl(apq) <= u * sqrtl(fabsl(c(p, p) * c(q, q)))) continue;
+        ++rot;
+        const LD theta = (c(q, q) - c(p, p)) / (2.0L * apq);
+        const LD t = (theta >= 0 ? 1.0L : -1.0L) / (fabsl(theta) + sqrtl(theta * theta + 1.0L));
+        const LD cs = 1.0L / sqrtl(t * t + 1.0L), sn = t * cs;
+        for (int k = 0; k < m; ++k) {
+          const LD akp = c(k, p), akq = c(k, q);
+          c(k, p) = cs * akp - sn * akq;
+          c(k, q) = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < m; ++k) {
+          const LD apk = c(p, k), aqk = c(q, k);
+          c(p, k) = cs * apk - sn * aqk;
+          c(q, k) = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < m; ++k) {
+          const LD vkp = Q[(size_t)k * m + p], vkq = Q[(size_t)k * m + q];
+          Q[(size_t)k * m + p] = cs * vkp - sn * vkq;
+          Q[(size_t)k * m + q] = sn * vkp + cs * vkq;
+        }
+      }
+    if (rot == 0) break;
+  }
+  // ascending eigenvalues (the null pair stays first)
+  std::vector<int> idx(m);
+  for (int i = 0; i < m; ++i) idx[i] = i;
+  std::sort(idx.begin() + j0, idx.end(), [&](int x, int y) { return c(x, x) < c(y, y); });
+  lam.assign(m, 0.0);
+  std::vector<double> W((size_t)m * m);
+  for (int j = 0; j < m; ++j) {
+    lam[j] = (singular && j == 0) ? 0.0 : (double)c(idx[j], idx[j]);
+    for (int k = 0; k < m; ++k) W[(size_t)k * m + j] = (double)(Q[(size_t)k * m + idx[j]] / sqrtl((LD)M1[fr[k]]));
+  }
+  Qd.swap(W);   // now S restricted to the free nodes: Q / sqrt(M)
+}
+
 void build_dir1d(Dir1D& d, int ne, const double* bp, int K, bool periodic, bool dir_lo, bool dir_hi,
                  const std::vector<double>& xi, const std::vector<double>& w,
                  const std::vector<double>& D) {
@@ -183,18 +296,12 @@ void build_dir1d(Dir1D& d, int ne, const double* bp, int K, bool periodic, bool 
                              std::sqrt(d.M1[fr[a]] * d.M1[fr[b]]);
   sym_eig(m, B, lam, Q);
   d.singular = (m == N);  // no Dirichlet node: constants are in the kernel
+  refine_eig_ld(m, fr, d.K1, d.M1, N, d.singular, lam, Q);   // Q <- eigenvectors / sqrt(M)
   d.S.assign((size_t)N * N, 0.0);
   d.lam.assign(N, 1.0);
   for (int j = 0; j < m; ++j) {
     d.lam[j] = lam[j];
-    for (int a = 0; a < m; ++a) d.S[(size_t)fr[a] * N + j] = Q[(size_t)a * m + j] / std::sqrt(d.M1[fr[a]]);
-  }
-  if (d.singular) {
-    // the lowest pair is exactly (0, 1/sqrt(sum M))
-    double tot = 0.0;
-    for (int i = 0; i < N; ++i) tot += d.M1[i];
-    d.lam[0] = 0.0;
-    for (int i = 0; i < N; ++i) d.S[(size_t)i * N + 0] = 1.0 / std::sqrt(tot);
+    for (int a = 0; a < m; ++a) d.S[(size_t)fr[a] * N + j] = Q[(size_t)a * m + j];
   }
   d.nfree = m;
   // banded, transposed copy of the stiffness for the residual kernel
