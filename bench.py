@@ -44,12 +44,12 @@ from synth import (C2, C3, C4, C5, c2_param_dict, c3_param_dict, c3_phi0, c4_ins
 VTOP = (0.0, 0.5, 1.0, 2.0)
 
 
-def make_context_c3(precision, refine_iters):
+def make_context_c3(precision, refine_max):
     """3D workload: 16x16 elements, K = 8, 128 Fourier planes, perturbed sphere."""
     import paper_2305_09020_amd as pfd
     xb = np.linspace(0.0, 1.0, C3["nx"] + 1)
     prob = pfd.make_problem(xb, xb, C3["K"], c3_param_dict(), [pfd.WALL] * 4, [1, 1, 0, 0],
-                            nz=C3["nz"], lz=C3["lz"], precision=precision, refine_iters=refine_iters)
+                            nz=C3["nz"], lz=C3["lz"], precision=precision, refine_max=refine_max)
     ctx = pfd.Context(prob)
     x, y, z = ctx.coords()
     Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
@@ -59,13 +59,13 @@ def make_context_c3(precision, refine_iters):
     return ctx, its
 
 
-def make_context(precision, refine_iters, workload="c2"):
+def make_context(precision, refine_max, workload="c2"):
     import paper_2305_09020_amd as pfd
     if workload == "c3":
-        return make_context_c3(precision, refine_iters)
+        return make_context_c3(precision, refine_max)
     xb = np.linspace(0.0, 1.0, C2["nx"] + 1)
     prob = pfd.make_problem(xb, xb, C2["K"], c2_param_dict(), [pfd.WALL] * 4, [1, 1, 0, 0],
-                            nbatch=len(VTOP), precision=precision, refine_iters=refine_iters)
+                            nbatch=len(VTOP), precision=precision, refine_max=refine_max)
     ctx = pfd.Context(prob)
     x, y, _ = ctx.coords()
     X, Y = np.meshgrid(x, y)
@@ -81,7 +81,7 @@ class C4Run:
     """The batched workload: 64 independent 2D instances (n x n elements, n in 8..24, order
     4..10, seeded) on one stream, stepped through one hipGraph launch per step."""
 
-    def __init__(self, precision, refine_iters):
+    def __init__(self, precision, refine_max):
         import torch
         import paper_2305_09020_amd as pfd
         self.ctxs = []
@@ -90,7 +90,7 @@ class C4Run:
             xb = np.linspace(0.0, 1.0, inst["n"] + 1)
             par = c4_param_dict(inst["eps_ratio"])
             prob = pfd.make_problem(xb, xb, inst["K"], par, [pfd.WALL] * 4, [1, 1, 0, 0],
-                                    precision=precision, refine_iters=refine_iters)
+                                    precision=precision, refine_max=refine_max)
             ctx = pfd.Context(prob, stream=self.stream)
             x, y, _ = ctx.coords()
             X, Y = np.meshgrid(x, y)
@@ -200,7 +200,7 @@ def run_c5(a):
     el = c5_electrodes()
     prob = pfd.make_problem(xb, yb, C5["K"], c5_param_dict(10.0, 90.0, dt=dt, eta=eta),
                             [pfd.WALL, pfd.OPEN, pfd.WALL, pfd.WALL], [0, 0, 0, 0], periodic_x=True,
-                            nz=C5["nz"], lz=C5["lz"], precision=pfd.REFINED_FP32, refine_iters=a.refine_iters,
+                            nz=C5["nz"], lz=C5["lz"], precision=pfd.REFINED_FP32, refine_max=a.refine_max,
                             electrodes=[(x0, x1) for x0, x1, _ in el])
     ctx = pfd.Context(prob)
     ctx.set_graph(not a.no_graph)
@@ -297,7 +297,7 @@ def run_c5(a):
                                "(+V, gap, -V, gap) x 3, eta %g, dt %g, tol %g; V ~ U[0,2], eps ratio ~ "
                                "U[1.5,40], contact angle ~ U[60,120]; %d training / %d held-out problems"
                                % (eta, dt, tol, n_train, n_test),
-                   "dof_per_step": dof, "graph": not a.no_graph, "refine_iters": a.refine_iters},
+                   "dof_per_step": dof, "graph": not a.no_graph, "refine_max": a.refine_max},
         "warm_start": {"train_samples": len(kept), "train_draws": n_train, "generation_s": t_gen, "train_steps": a.c5_train_steps,
                        "train_s": t_tr, "loss_first": float(hist[0]), "loss_last": float(np.mean(hist[-20:])),
                        "mean_steps_plain": float(sp.mean()), "mean_steps_warm": float(sw.mean()),
@@ -463,7 +463,7 @@ def main():
     ap.add_argument("--c5-test", type=int, default=None, help="held-out problems for c5")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--refine-iters", type=int, default=2)
+    ap.add_argument("--refine-max", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the step kernels one by one instead of replaying a hipGraph")
@@ -498,13 +498,13 @@ def main():
         if a.only not in (name, "both"):
             continue
         if a.workload == "c4":
-            ctx, its = C4Run(prec, a.refine_iters), 0
+            ctx, its = C4Run(prec, a.refine_max), 0
             t = time_steps(ctx, a.steps, a.warmup)
             dof = ctx.dof
             res[name] = dict(t=t, dof=dof, value=dof * a.steps / t, ctx=ctx,
                              roofline=roofline_c4(ctx, 5))
         else:
-            ctx, its = make_context(prec, a.refine_iters, a.workload)
+            ctx, its = make_context(prec, a.refine_max, a.workload)
             ctx.set_graph(not a.no_graph)
             t = time_steps(ctx, a.steps, a.warmup)
             dof = ctx.planes * ctx.Nx * ctx.Ny
@@ -531,20 +531,20 @@ def main():
                                 "rho 1:1000, mu 1:100, eps 1:40, V_top {0,0.5,1,2} as 4 instances, "
                                 "dt 5e-5, closed box; %s path" % main_name,
                     "instances": len(VTOP), "dof_per_step": r["dof"], "graph": not a.no_graph,
-                    "refine_iters": a.refine_iters if main_name == "refined" else 0}
+                    "refine_max": a.refine_max if main_name == "refined" else 0}
                    if a.workload == "c2" else
                    {"workload": "64 independent 2D drops in one batch (one hipGraph launch per step): "
                                 "n x n elements with n ~ U{8..24}, order ~ U{4..10}, V_top ~ U[0,2], "
                                 "eps ratio ~ U[1.5,40], seed 1, eta 0.02, dt 1e-4, closed boxes; "
                                 "%s path" % main_name,
                     "instances": C4["n_inst"], "dof_per_step": r["dof"], "graph": True,
-                    "refine_iters": a.refine_iters if main_name == "refined" else 0}
+                    "refine_max": a.refine_max if main_name == "refined" else 0}
                    if a.workload == "c4" else
                    {"workload": "3D drop, 16x16 elements order 8 x 128 Fourier planes (Lz = 2, "
                                 "2,130,048 points), perturbed sphere r = 0.3, rho 1:10, mu 1:2, "
                                 "eps 1:10, dt 1e-4, walls; %s path" % main_name,
                     "instances": 1, "dof_per_step": r["dof"], "graph": not a.no_graph,
-                    "refine_iters": a.refine_iters if main_name == "refined" else 0}),
+                    "refine_max": a.refine_max if main_name == "refined" else 0}),
     }
     out["roofline"] = r["roofline"]
     if "fp64" in res and "refined" in res:

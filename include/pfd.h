@@ -45,7 +45,10 @@ typedef enum {
   PFD_ENOMEM = 2,      /* workspace too small                                  */
   PFD_EHIP = 3,        /* HIP runtime error                                    */
   PFD_ENONFINITE = 4,  /* a NaN/Inf appeared in the state during a step        */
-  PFD_ENOCONV = 5,     /* iterative refinement / fixed point did not converge  */
+  PFD_ENOCONV = 5,     /* a refined solve missed its stop rule within refine_max
+                          corrections (pfd_step, pfd_step_async's later pfd_get_diag,
+                          pfd_batch_step, pfd_march_to_equilibrium), or a fixed point /
+                          equilibrium march missed its tolerance                 */
   PFD_ESTATE = 6,      /* context failed earlier or is not initialised         */
   PFD_ENOTIMPL = 7
 } pfd_status;
@@ -76,12 +79,27 @@ typedef enum {
   PFD_NSRC
 } pfd_source;
 
-/* precision of the constant-coefficient solves.  PFD_REFINED_FP32 starts every solve of a
- * step from the extrapolated history and applies refine_iters FP32 corrections, each on an
- * FP64 residual; once two consecutive steps have solved a family, the first residual is formed
- * from the right sides of those two steps (A x^n = b^n) instead of a stencil pass.  That record
- * is forgotten by pfd_set_field, pfd_set_source, pfd_init_potential and pfd_update_params, and
- * for P and u by an equilibrium step (which does not solve them). */
+/* precision of the constant-coefficient solves (the mixed-precision iterative refinement of
+ * the constant matrices of Sec. 3, remark after Algorithm 2).
+ * PFD_REFINED_FP32 applies, per solve, FP32 fast-diagonalisation corrections x += A~^{-1} r on
+ * FP64 residuals r = b - A x until the normwise backward error of x (perturbations of A)
+ *     eta = ||r||_2 / (||A||_2 ||x||_2)
+ * (over the free nodes of all planes and stacked components, ||A_p||_2 bounded from the 1D
+ * eigenvalues) is <= refine_tol, at most refine_max corrections; every FP64 residual is
+ * tested on the device, and once a test passes the rest of the solve's kernels return at once
+ * (so a captured step stays one graph).  A solve still above refine_tol after refine_max
+ * corrections makes the stepping call return PFD_ENOCONV (the state is kept and valid, only
+ * less accurate; the context does not fail).  Solves start from the extrapolated history;
+ * once two consecutive steps have solved a family, the first residual is formed from the right
+ * sides of those two steps (A x^n = b^n, to the stop rule) instead of a stencil pass, and the
+ * first correction takes it untested.  That record is forgotten by pfd_set_field,
+ * pfd_set_source, pfd_init_potential and pfd_update_params, and for P and u by an equilibrium
+ * step (which does not solve them).
+ * Precision ladder: at pfd_create each (family, plane) operator gets the condition estimate
+ * kappa = (max lx + max ly + c_p) / (min lx + min ly + c_p) from its generalised 1D
+ * eigenvalues; planes with kappa 2^-24 > 1/2 (the singular closed-box pressure and k = 0
+ * pressure mode in particular) take one FP64 correction (a direct solve) instead.
+ * pfd_get_refine_stats reports the estimates, the split and the corrections taken. */
 typedef enum {
   PFD_PLAIN_FP64 = 0,   /* FP64 fast-diagonalisation solve                     */
   PFD_REFINED_FP32 = 1  /* FP32 solve + FP64 residual iterative refinement     */
@@ -140,17 +158,37 @@ typedef struct {
   pfd_params par;
   pfd_bcs bc;
   int precision;         /* pfd_precision                                        */
-  int refine_iters;      /* corrections per solve in PFD_REFINED_FP32 (0 -> 2)   */
+  int refine_max;        /* PFD_REFINED_FP32: most corrections per solve, 0..64
+                            (0 -> PFD_REFINE_MAX_DEFAULT)                         */
+  double refine_tol;     /* PFD_REFINED_FP32: stop rule on eta, [0, 1)
+                            (0 -> PFD_REFINE_TOL_DEFAULT)                         */
 } pfd_problem;
+
+#define PFD_REFINE_MAX_DEFAULT 4
+#define PFD_REFINE_TOL_DEFAULT 1e-15
 
 typedef struct pfd_ctx pfd_ctx;
 
 typedef struct {
   double derived[10];    /* gamma0, S, alpha, c_psi, c_phi, eps0, rho0, nu_m, c_u, -  */
-  double last_residual;  /* max over the last step's solves of ||b-Ax||_2/||b||_2 (if checked) */
+  double last_residual;  /* refined path: max over families of the backward error eta of
+                            the last test of each family's last solve (0 on the plain path) */
   int nonfinite;         /* 1 if a non-finite value was seen                     */
+  int unconverged;       /* bit f set: a family-f solve missed the stop rule since the last
+                            pfd_step / pfd_get_diag / pfd_batch_step (cleared by this call) */
   long steps;            /* steps taken since the last pfd_set_field             */
 } pfd_diag;
+
+/* Iterative refinement record of one solve family (pfd_get_refine_stats). */
+typedef struct {
+  int n_fp64_planes;     /* planes [0, n) solved by one FP64 correction (precision ladder);
+                            all planes on the plain FP64 path                    */
+  int last_corrections;  /* FP32 corrections the last solve took                 */
+  int max_corrections;   /* most corrections of one solve since the last reset   */
+  long failures;         /* solves that missed the stop rule since the last reset */
+  double last_eta;       /* backward error of the last test                      */
+  double kappa_min, kappa_max;  /* condition estimates over the planes (inf: singular) */
+} pfd_refine_stats;
 
 /* Diagnostics of one instance (a 2D batch member, or the whole 3D field):
  * the mass int_h phi (conserved by eq. 16), and the discrete total energy of
@@ -166,6 +204,11 @@ typedef struct {
   double phi_max_abs;    /* max |phi| over the instance                          */
   int nonfinite;         /* 1 if phi, |u|^2 or |E|^2 is not finite somewhere     */
 } pfd_stats;
+
+/* Refinement record of the five solve families (out[5], host; index = PFD_FAM_*), see
+ * pfd_precision.  reset != 0 clears the corrections maximum and the failure count afterwards.
+ * Synchronises the context's stream. */
+pfd_status pfd_get_refine_stats(pfd_ctx* ctx, pfd_refine_stats* out, int reset);
 
 /* Human-readable name of a status code.  Never NULL. */
 const char* pfd_status_string(pfd_status s);

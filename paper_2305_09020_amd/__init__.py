@@ -56,12 +56,19 @@ class BCs(ctypes.Structure):
 
 class Problem(ctypes.Structure):
     _fields_ = [("mesh", Mesh), ("par", Params), ("bc", BCs), ("precision", ctypes.c_int),
-                ("refine_iters", ctypes.c_int)]
+                ("refine_max", ctypes.c_int), ("refine_tol", ctypes.c_double)]
 
 
 class Diag(ctypes.Structure):
     _fields_ = [("derived", ctypes.c_double * 10), ("last_residual", ctypes.c_double),
-                ("nonfinite", ctypes.c_int), ("steps", ctypes.c_long)]
+                ("nonfinite", ctypes.c_int), ("unconverged", ctypes.c_int), ("steps", ctypes.c_long)]
+
+
+class RefineStats(ctypes.Structure):
+    _fields_ = [("n_fp64_planes", ctypes.c_int), ("last_corrections", ctypes.c_int),
+                ("max_corrections", ctypes.c_int), ("failures", ctypes.c_long),
+                ("last_eta", ctypes.c_double), ("kappa_min", ctypes.c_double),
+                ("kappa_max", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -88,6 +95,7 @@ _sig = {
     "pfd_get_coords": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "pfd_get_diag": (ctypes.c_int, [_vp, ctypes.POINTER(Diag)]),
     "pfd_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Stats)]),
+    "pfd_get_refine_stats": (ctypes.c_int, [_vp, ctypes.POINTER(RefineStats), ctypes.c_int]),
     "pfd_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pfd_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
     "pfd_batch_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
@@ -155,9 +163,10 @@ def _check(code, ctx=None):
 
 
 def make_problem(xb, yb, K, params, side_type, pot_dirichlet, periodic_x=False, nbatch=1,
-                 nz=0, lz=0.0, precision=PLAIN_FP64, refine_iters=0, electrodes=()):
+                 nz=0, lz=0.0, precision=PLAIN_FP64, refine_max=0, refine_tol=0.0, electrodes=()):
     """Build the C problem struct.  params: mapping with rho1, rho2, mu1, mu2, eps1, eps2,
-    lam, eta, gamma1, theta_s_deg, dt and optional bdf (2), S (0), nu_m (0)."""
+    lam, eta, gamma1, theta_s_deg, dt and optional bdf (2), S (0), nu_m (0).  refine_max /
+    refine_tol: correction cap and backward-error stop rule of the refined path (0: defaults)."""
     xb = np.ascontiguousarray(xb, dtype=np.float64)
     yb = np.ascontiguousarray(yb, dtype=np.float64)
     pr = Problem()
@@ -173,7 +182,8 @@ def make_problem(xb, yb, K, params, side_type, pot_dirichlet, periodic_x=False, 
     e1 = np.ascontiguousarray([e[1] for e in electrodes], dtype=np.float64)
     pr.bc = BCs(st, pd, len(electrodes), e0.ctypes.data_as(_dp), e1.ctypes.data_as(_dp))
     pr.precision = precision
-    pr.refine_iters = refine_iters
+    pr.refine_max = int(refine_max)
+    pr.refine_tol = float(refine_tol)
     pr._keep = (xb, yb, e0, e1)   # keep host arrays alive while pr is used
     return pr
 
@@ -384,7 +394,15 @@ class Context:
         d = Diag()
         _check(_lib.pfd_get_diag(self.h, ctypes.byref(d)), self.h)
         return dict(derived=list(d.derived), last_residual=d.last_residual,
-                    nonfinite=d.nonfinite, steps=d.steps)
+                    nonfinite=d.nonfinite, unconverged=d.unconverged, steps=d.steps)
+
+    def refine_stats(self, reset=False):
+        """Per solve family (V, psi, phi, P, u): FP64 planes of the precision ladder,
+        corrections of the last solve and the most since the last reset, failed solves, the
+        last backward error and the condition estimates."""
+        arr = (RefineStats * 5)()
+        _check(_lib.pfd_get_refine_stats(self.h, arr, int(bool(reset))), self.h)
+        return [{k: getattr(a, k) for k, _ in RefineStats._fields_} for a in arr]
 
 
 class Batch:

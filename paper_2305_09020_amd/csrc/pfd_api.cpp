@@ -47,6 +47,11 @@ struct Layout {
   size_t bytes;
 };
 
+// work-groups of the largest residual launch (three stacked components, either residual kernel)
+long refine_blocks(int Ny, int planes, long Pg) {
+  return std::max(3 * Pg / 256 + 1, (long)((Ny + 15) / 16) * 3 * planes) + 16;
+}
+
 pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   if (!p) { *err = "null problem"; return PFD_EINVAL; }
   const pfd_mesh& m = p->mesh;
@@ -66,6 +71,9 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   }
   if (q.bdf_order != 1 && q.bdf_order != 2) { *err = "bdf_order must be 1 or 2"; return PFD_EINVAL; }
   if (p->precision != PFD_PLAIN_FP64 && p->precision != PFD_REFINED_FP32) { *err = "bad precision"; return PFD_EINVAL; }
+  if (p->refine_max < 0 || p->refine_max > 64 || !(p->refine_tol >= 0.0) || !(p->refine_tol < 1.0)) {
+    *err = "refine_max must be in [0,64] and refine_tol in [0,1)"; return PFD_EINVAL;
+  }
   if (m.nz < 0 || m.nz == 1 || (m.nz > 0 && m.nz % 2)) { *err = "nz must be 0 (2D) or even >= 2"; return PFD_EINVAL; }
   if (m.nz > 0 && !(m.lz > 0)) { *err = "lz must be positive in 3D"; return PFD_EINVAL; }
   if (m.nz > 512) { *err = "nz above 512 is not supported"; return PFD_EINVAL; }
@@ -125,6 +133,7 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   dbl += 8 * 3 * NP * NP + 64;           // S, S^T in fragment order, double and float
   dbl += 2 * (size_t)(m.nx + m.ny + 2) + (PFD_KMAX + 1) * (PFD_KMAX + 2);
   dbl += 48 * (size_t)L->planes + 1280;  // shifts, norms, reductions (1024 block maxima)
+  dbl += 2 * (size_t)refine_blocks(L->Ny, L->planes, Pg) + 5 * (size_t)L->planes + 64;  // refinement test
   L->bytes = dbl * sizeof(double) + 256 * 1024;  // alignment slack (256 B per allocation)
   return PFD_OK;
 }
@@ -311,8 +320,12 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   c->d_hx = D(m.nx); c->d_hy = D(m.ny);
   c->d_w = D(K + 1); c->d_D = D((long)(K + 1) * (K + 1));
   c->d_status = (int*)carve(c, 64);
-  c->d_norms = D(2 * c->planes + 2);
   c->d_red = D(2 * 512);
+  c->rpart_max = refine_blocks(c->Ny, c->planes, Pg);
+  c->d_rpart = D(2 * c->rpart_max);
+  c->d_gate = (int*)carve(c, 64);
+  c->d_rstat = D(20);
+  for (int f = 0; f < 5; ++f) c->d_anorm[f] = D(c->planes);
   c->d_stats = D((long)c->planes * PFD_STAT_NB * 8);
   c->d_part = D(32 * (long)c->planes);
   c->d_beta2 = D(c->planes); c->d_betad = D(c->planes);
@@ -329,7 +342,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
     d.fSTw = (float*)carve(c, sizeof(float) * NP2);
     d.ddir = (unsigned char*)carve(c, d.N);
   }
-  bool ok = !c->ws_fail && c->fld[0][0] && zero && c->fam[4].dshift && c->bh[PFD_FAM_U][1];
+  bool ok = !c->ws_fail && c->fld[0][0] && zero && c->fam[4].dshift && c->bh[PFD_FAM_U][1] && c->d_anorm[4];
   for (auto& d : c->dirs) ok = ok && d.ddir;
   if (!ok) { g_create_err = "workspace too small (layout)"; delete c; return PFD_ENOMEM; }
   (void)zero;
@@ -435,6 +448,51 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
       if (sing && F.hshift[p] == 0.0) F.any_singular = true;
     }
   }
+  // precision ladder and the refinement test's operator norms.  Per plane, the generalised
+  // eigenvalues of (A, M) are lx_i + ly_j + c_p, so kappa = (max lx + max ly + c_p) /
+  // (min lx + min ly + c_p) is the condition number of M^{-1/2} A M^{-1/2}, and ||A_p||_2 <=
+  // max(M) (max lx + max ly + c_p).  An FP32 correction reduces the error by about kappa u32
+  // (u32 = 2^-24), so planes with kappa u32 > 1/2 -- the singular ones (kappa infinite) in
+  // particular -- take one FP64 correction instead (they must form a prefix of the planes,
+  // which holds here: only the first Fourier plane can be singular).
+  const double u32 = std::ldexp(1.0, -24);
+  std::vector<double> an[5];
+  for (int f = 0; f < 5; ++f) {
+    const Dir1D& dx = c->dirs[c->fam[f].ix];
+    const Dir1D& dy = c->dirs[c->fam[f].iy];
+    auto mm = [](const Dir1D& d, double& lo, double& hi, double& mx) {
+      lo = 1e300; hi = -1e300; mx = 0.0;
+      for (int j = 0; j < d.nfree; ++j) { lo = std::min(lo, d.lam[j]); hi = std::max(hi, d.lam[j]); }
+      for (int i = 0; i < d.N; ++i) mx = std::max(mx, d.M1[i]);
+    };
+    double xlo, xhi, xm, ylo, yhi, ym;
+    mm(dx, xlo, xhi, xm);
+    mm(dy, ylo, yhi, ym);
+    an[f].assign(c->planes, 0.0);
+    c->kappa_min[f] = 1e300;
+    c->kappa_max[f] = 0.0;
+    std::vector<char> need64(c->planes, 0);
+    for (int p = 0; p < c->planes; ++p) {
+      const double sh = c->fam[f].hshift[p];
+      const double hi = xhi + yhi + sh, lo = xlo + ylo + sh;
+      an[f][p] = xm * ym * hi;
+      const double kap = lo > 1e-12 * hi ? hi / lo : HUGE_VAL;
+      c->kappa_min[f] = std::min(c->kappa_min[f], kap);
+      c->kappa_max[f] = std::max(c->kappa_max[f], kap);
+      need64[p] = kap * u32 > 0.5;
+    }
+    int n64 = 0;
+    while (n64 < c->planes && need64[n64]) ++n64;
+    for (int p = n64; p < c->planes; ++p)
+      if (need64[p]) n64 = c->planes;   // not a prefix: the whole family in FP64
+    if (f == PFD_FAM_V && bc.n_electrodes > 0 && !bc.pot_dirichlet[PFD_BOTTOM] && n64 > 0) n64 = c->planes;
+    c->n64[f] = n64;
+  }
+  for (int f = 0; f < 5 && !e; ++f) e = up(c->d_anorm[f], an[f].data(), 8 * c->planes);
+  if (!e) e = hipMemsetAsync(c->d_gate, 0, 64, c->stream);
+  if (!e) e = hipMemsetAsync(c->d_rstat, 0, 8 * 20, c->stream);
+  c->refine_max = prob->refine_max > 0 ? prob->refine_max : PFD_REFINE_MAX_DEFAULT;
+  c->refine_tol = prob->refine_tol > 0 ? prob->refine_tol : PFD_REFINE_TOL_DEFAULT;
   if (!e) for (int s = 0; s < 4; ++s) { e = up(c->bm_side[s], bs[s].data(), 8 * c->Ng); if (e) break; }
   if (!e) e = up(c->bm_open, bo.data(), 8 * c->Ng);
   if (!e) e = up(c->bm_wall, bw.data(), 8 * c->Ng);
@@ -579,14 +637,63 @@ extern "C" pfd_status pfd_get_diag(pfd_ctx* c, pfd_diag* d) {
   const Par& P = c->par;
   double v[10] = {P.gamma0, P.S, P.alpha, P.c_psi, P.c_phi, P.eps0, P.rho0, P.nu_m, P.c_u, 0.0};
   std::memcpy(d->derived, v, sizeof(v));
-  int st = 0;
-  hipError_t e = hipMemcpyAsync(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  int st[2] = {0, 0};
+  double rs[20];
+  hipError_t e = hipMemcpyAsync(st, c->d_status, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (!e) e = hipMemcpyAsync(rs, c->d_rstat, sizeof(rs), hipMemcpyDeviceToHost, c->stream);
+  if (!e) e = hipMemsetAsync(c->d_status + 1, 0, sizeof(int), c->stream);
   if (!e) e = hipStreamSynchronize(c->stream);
   if (e) { c->err = hipGetErrorString(e); return PFD_EHIP; }
-  d->nonfinite = st & 1;
-  d->last_residual = c->last_residual;
+  d->nonfinite = st[0] & 1;
+  d->unconverged = st[1];
+  d->last_residual = 0.0;
+  if (c->prob.precision == PFD_REFINED_FP32)
+    for (int f = 0; f < 5; ++f)
+      if (c->n64[f] < c->planes) d->last_residual = std::max(d->last_residual, rs[4 * f + 1]);
   d->steps = c->steps;
   return PFD_OK;
+}
+
+extern "C" pfd_status pfd_get_refine_stats(pfd_ctx* c, pfd_refine_stats* out, int reset) {
+  if (!c || !out) return PFD_EINVAL;
+  double rs[20];
+  HIPCHK(hipMemcpyAsync(rs, c->d_rstat, sizeof(rs), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const bool refined = c->prob.precision == PFD_REFINED_FP32;
+  for (int f = 0; f < 5; ++f) {
+    pfd_refine_stats& o = out[f];
+    o.n_fp64_planes = refined ? c->n64[f] : c->planes;
+    o.last_corrections = (int)rs[4 * f];
+    o.last_eta = rs[4 * f + 1];
+    o.max_corrections = (int)rs[4 * f + 2];
+    o.failures = (long)rs[4 * f + 3];
+    o.kappa_min = c->kappa_min[f];
+    o.kappa_max = c->kappa_max[f];
+  }
+  if (reset) {
+    for (int f = 0; f < 5; ++f) rs[4 * f + 2] = rs[4 * f + 3] = 0.0;
+    HIPCHK(hipMemcpyAsync(c->d_rstat, rs, sizeof(rs), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  return PFD_OK;
+}
+
+// Status words of a context after stream-ordered work: [0] bit 0 non-finite, [1] bit f a
+// family-f refined solve missed the stop rule.  Reads both and clears [1].  Synchronises.
+hipError_t pfd::read_status(pfd_ctx* c, int* st) {
+  hipError_t e = hipMemcpyAsync(st, c->d_status, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (!e) e = hipMemsetAsync(c->d_status + 1, 0, sizeof(int), c->stream);
+  if (!e) e = hipStreamSynchronize(c->stream);
+  return e;
+}
+
+// the PFD_ENOCONV message of a family mask
+std::string pfd::unconverged_msg(int mask) {
+  static const char* nm[5] = {"V", "psi", "phi", "P", "u"};
+  std::string m = "iterative refinement missed its stop rule (family";
+  for (int f = 0; f < 5; ++f)
+    if (mask & (1 << f)) m += std::string(" ") + nm[f];
+  return m + ")";
 }
 
 static double* field_ptr(pfd_ctx* c, int f, int level) {
@@ -683,12 +790,12 @@ void pfd::forget_rhs(pfd_ctx* c) {
   for (int& h : c->bhist) h = 0;
 }
 void pfd::begin_step(pfd_ctx* c, int eq) {
-  // one correction per solve takes the exact residual: a recycled one would leave each step's
-  // final residual in the next two steps' right sides, growing without the second correction
-  const int iters = c->prob.refine_iters > 0 ? c->prob.refine_iters : 2;
-  bool ok = c->prob.precision == PFD_REFINED_FP32 && iters >= 2;
+  // the recycled first residual needs the two previous solves of every refined family to have
+  // met the stop rule (tested on the device; a miss is reported as PFD_ENOCONV)
+  bool ok = c->prob.precision == PFD_REFINED_FP32;
   for (int f = 0; f < 5; ++f)
-    if (!eq || f == PFD_FAM_V || f == PFD_FAM_PSI || f == PFD_FAM_PHI) ok = ok && c->bhist[f] >= 2;
+    if ((!eq || f == PFD_FAM_V || f == PFD_FAM_PSI || f == PFD_FAM_PHI) && warm_start(c, f))
+      ok = ok && c->bhist[f] >= 2;
   c->rec_on = ok;
 }
 void pfd::end_step(pfd_ctx* c, int eq) {
@@ -701,6 +808,7 @@ void pfd::end_step(pfd_ctx* c, int eq) {
 static hipError_t one_step_launch(pfd_ctx* c, int eq);
 
 static void drop_graphs(pfd_ctx* c) {
+  ++c->graph_gen;   // a batch holding this context's launches recaptures
   for (auto& row : c->gexec)
     for (auto& g : row)
       if (g) {
@@ -721,7 +829,7 @@ static hipError_t one_step(pfd_ctx* c, int eq) {
 static hipError_t one_step_launch(pfd_ctx* c, int eq) {
   const bool refined = c->prob.precision == PFD_REFINED_FP32;
   // graphs hold the recycling form of a refined step only (the two steps before it run eagerly)
-  if (!c->use_graph || c->prof_on || c->check_residual || (refined && !c->rec_on))
+  if (!c->use_graph || c->prof_on || (refined && !c->rec_on))
     return c->is3d ? step_once_3d(c, eq) : step_once(c, eq);
   if (c->is3d) refresh_spectral_sources(c);  // host-decided transforms stay outside the graph
   const int cur = c->cur;
@@ -931,16 +1039,21 @@ extern "C" pfd_status pfd_march_to_equilibrium(pfd_ctx* c, double tol, long max_
     ++c->steps;
     double h[2];
     HIPCHK(max_abs_diff(c, c->fld[F_PHI][c->cur], c->fld[F_PHI][1 - c->cur], h));
-    int st = 0;
-    HIPCHK(hipMemcpyAsync(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    int st[2] = {0, 0};
+    HIPCHK(read_status(c, st));
     r = h[0];
-    if ((st & 1) || !std::isfinite(r)) {
+    if ((st[0] & 1) || !std::isfinite(r)) {
       c->failed = 1;
       c->err = "non-finite value in the state";
       if (steps) *steps = n;
       if (residual) *residual = r;
       return PFD_ENONFINITE;
+    }
+    if (st[1]) {
+      c->err = unconverged_msg(st[1]);
+      if (steps) *steps = n;
+      if (residual) *residual = r;
+      return PFD_ENOCONV;
     }
     if (r <= tol) { conv = true; break; }
   }
@@ -953,20 +1066,23 @@ extern "C" pfd_status pfd_march_to_equilibrium(pfd_ctx* c, double tol, long max_
 extern "C" pfd_status pfd_step(pfd_ctx* c, int nsteps, int equilibrium) {
   pfd_status s = pfd_step_async(c, nsteps, equilibrium);
   if (s != PFD_OK) return s;
-  int st = 0;
-  HIPCHK(hipMemcpyAsync(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  if (st & 1) {
+  int st[2] = {0, 0};
+  HIPCHK(read_status(c, st));
+  if (st[0] & 1) {
     c->failed = 1;
     c->err = "non-finite value in the state";
     return PFD_ENONFINITE;
+  }
+  if (st[1]) {
+    c->err = unconverged_msg(st[1]);
+    return PFD_ENOCONV;
   }
   return PFD_OK;
 }
 
 extern "C" pfd_status pfd_solve(pfd_ctx* c, int fam, const double* b, double* x) {
   if (!c || !b || !x || fam < 0 || fam > 4) return PFD_EINVAL;
-  HIPCHK(solve(c, fam, b, x, 1, 1, nullptr));
+  HIPCHK(solve(c, fam, b, x, 1, 1, nullptr, false));
   return PFD_OK;
 }
 

@@ -20,6 +20,9 @@ struct pfd_batch {
   std::vector<hipStream_t> lanes;         // capture branches
   std::vector<hipEvent_t> ev;             // fork event + one join event per lane
   hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  // members' graph generations when each graph was captured: a member whose kernels or
+  // kernel arguments changed since (parameters, variants, tuning) makes the graph stale
+  std::vector<unsigned long> gen[2][2];
   std::string err;
 };
 
@@ -130,7 +133,7 @@ extern "C" pfd_status pfd_batch_step(pfd_batch* b, int nsteps, int equilibrium) 
       return PFD_ESTATE;
     }
     aligned = aligned && c->cur == b->ctx[0]->cur;
-    profiling = profiling || c->prof_on || c->check_residual;
+    profiling = profiling || c->prof_on;
   }
   for (int s = 0; s < nsteps; ++s) {
     // refined instances recycle their right sides once two steps are recorded; the graph holds
@@ -148,7 +151,19 @@ extern "C" pfd_status pfd_batch_step(pfd_batch* b, int nsteps, int equilibrium) 
         if (c->is3d) refresh_spectral_sources(c);   // host-decided transforms stay outside
       const int cur = b->ctx[0]->cur;
       hipGraphExec_t& ex = b->gexec[cur][eq];
-      if (!ex) BCHK(capture(b, eq, &ex));
+      std::vector<unsigned long>& gen = b->gen[cur][eq];
+      bool stale = gen.size() != b->ctx.size();
+      for (size_t i = 0; i < b->ctx.size() && !stale; ++i) stale = gen[i] != b->ctx[i]->graph_gen;
+      if (ex && stale) {
+        BCHK(hipStreamSynchronize(b->stream));
+        (void)hipGraphExecDestroy(ex);
+        ex = nullptr;
+      }
+      if (!ex) {
+        BCHK(capture(b, eq, &ex));
+        gen.resize(b->ctx.size());
+        for (size_t i = 0; i < b->ctx.size(); ++i) gen[i] = b->ctx[i]->graph_gen;
+      }
       BCHK(hipGraphLaunch(ex, b->stream));
       for (pfd_ctx* c : b->ctx) c->cur = 1 - cur;
     }
@@ -157,18 +172,25 @@ extern "C" pfd_status pfd_batch_step(pfd_batch* b, int nsteps, int equilibrium) 
       ++c->steps;
     }
   }
-  // non-finite check of every instance (one synchronisation)
-  std::vector<int> st(b->ctx.size(), 0);
-  for (size_t i = 0; i < b->ctx.size(); ++i)
-    BCHK(hipMemcpyAsync(&st[i], b->ctx[i]->d_status, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  // non-finite and refinement checks of every instance (one synchronisation)
+  std::vector<int> st(2 * b->ctx.size(), 0);
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    BCHK(hipMemcpyAsync(&st[2 * i], b->ctx[i]->d_status, 2 * sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    BCHK(hipMemsetAsync(b->ctx[i]->d_status + 1, 0, sizeof(int), b->stream));
+  }
   BCHK(hipStreamSynchronize(b->stream));
   pfd_status ret = PFD_OK;
-  for (size_t i = 0; i < b->ctx.size(); ++i)
-    if (st[i] & 1) {
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    if (st[2 * i] & 1) {
       b->ctx[i]->failed = 1;
       b->ctx[i]->err = "non-finite value in the state";
       b->err = "non-finite value in instance " + std::to_string(i);
       ret = PFD_ENONFINITE;
+    } else if (st[2 * i + 1] && ret == PFD_OK) {
+      b->ctx[i]->err = unconverged_msg(st[2 * i + 1]);
+      b->err = "instance " + std::to_string(i) + ": " + b->ctx[i]->err;
+      ret = PFD_ENOCONV;
     }
+  }
   return ret;
 }

@@ -133,11 +133,22 @@ struct pfd_ctx {
   double *d_hx = nullptr, *d_hy = nullptr, *d_w = nullptr, *d_D = nullptr;
   int* d_status = nullptr;                 // [0] nonfinite flag
   double* d_stats = nullptr;               // block partials of the diagnostics
-  double* d_norms = nullptr;               // per plane: ||r||^2, ||b||^2 (diagnostics)
   double* d_red = nullptr;                 // reduction scratch (planes)
+  // refinement of the FP32-refined path (convergence test of every FP64 residual)
+  double* d_rpart = nullptr;               // block partials of the test: r^2, (||A_p|| x)^2
+  long rpart_max = 0;                      // blocks the partial array holds
+  int* d_gate = nullptr;                   // 1 once the current solve has converged
+  double* d_rstat = nullptr;               // per family: corrections, backward error, max, failures
+  double* d_anorm[5] = {};                 // per family and plane: bound of ||A_p||_2
+  const int* gate = nullptr;               // gate the kernels being launched read (nullptr: none)
+  double refine_tol = 0.0;                 // stop at ||r|| <= tol (||A|| ||x|| + ||b||)
+  int refine_max = 0;                      // corrections before PFD_ENOCONV
+  // precision ladder: per family the planes [0, n64) take FP64 corrections (singular or
+  // ill-conditioned operators), the rest FP32 with refinement; condition estimates per family
+  int n64[5] = {0, 0, 0, 0, 0};
+  double kappa_min[5] = {}, kappa_max[5] = {};
   long steps = 0;
   int failed = 0;
-  int check_residual = 0;
   // hipGraph replay of whole steps: one executable per (parity of the current level, step kind)
   int use_graph = 0;
   // fast-diagonalisation kernels: 0 = four split-K GEMM passes, 1 = two fused strip kernels
@@ -164,7 +175,7 @@ struct pfd_ctx {
   double gemm_us[PFD_GS_N][2][PFD_GEMM_NCFG] = {};  // autotune timings per configuration
   hipStream_t cap_stream = nullptr;        // capture stream (the caller's may be the null stream)
   hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-  double last_residual = 0.0;
+  unsigned long graph_gen = 0;             // bumped whenever captured launches become stale
   // per-kernel-class timing (pfd_profile_enable / pfd_profile_read)
   int prof_on = 0;
   std::vector<hipEvent_t> ev_pool;
@@ -195,7 +206,12 @@ void electrode_schur_inverse(const Dir1D& dx, const Dir1D& dy, const std::vector
                              std::vector<double>& Sinv);
 
 // kernels (pfd_kernels.hip); all enqueue on ctx->stream
-hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp, int project, const double* r0);
+hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp, int project, const double* r0,
+                 bool r0_exact);
+// the family's solves start from the extrapolated history: FP32-refined planes exist
+inline bool warm_start(const pfd_ctx* c, int fam) {
+  return c->prob.precision == PFD_REFINED_FP32 && c->n64[fam] < c->planes;
+}
 hipError_t apply(pfd_ctx* c, int fam, const double* x, double* y, int ncomp);
 hipError_t step_once(pfd_ctx* c, int equilibrium);
 hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout);
@@ -207,6 +223,10 @@ hipError_t stats(pfd_ctx* c, double* out);
 hipError_t replay(pfd_ctx* c, int cls, int reps, double* avg_us);
 hipError_t autotune(pfd_ctx* c);
 hipError_t step_once_3d(pfd_ctx* c, int equilibrium);
+// status words: st[0] bit 0 non-finite; st[1] refined families that missed the stop rule
+// (cleared by the read); synchronises
+hipError_t read_status(pfd_ctx* c, int* st);
+std::string unconverged_msg(int mask);
 // right-side recycling state of the refined path (host side): forget after any change of the
 // state, sources or operators; begin_step decides whether a step recycles, end_step records it
 void forget_rhs(pfd_ctx* c);

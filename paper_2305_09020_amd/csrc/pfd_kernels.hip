@@ -723,6 +723,94 @@ __global__ void k_check_finite(long N, const double* f, const double* f2, int* s
 }
 
 // =================================================================== solves
+// Convergence test of the iterative refinement, taken on every FP64 residual r = b - A x the
+// refined path forms.  The stop rule is the normwise backward error of x with respect to
+// perturbations of A (Rigal & Gaches 1967 with the right side held exact):
+//   eta = ||r||_2 / (||A||_2 ||x||_2) <= tol
+// over the free nodes of every plane (and stacked component) of the solve, with the per-plane
+// bound ||A_p||_2 <= max(Mx) max(My) (max lx + max ly + c_p) from the 1D eigenvalues.  (With
+// b = A x up to r, ||b|| <= ||A|| ||x|| + ||r||, so eta is within a factor 2 of the variant
+// with ||b|| added to the denominator; two sums keep the fused residual kernel within its
+// register budget.)  Each work-group of a residual kernel reduces its nodes' r^2 and
+// ||A_p||^2 x^2 (wavefront shuffles, then the four waves in order) and stores the two sums;
+// k_chk_decide, launched next, adds them in work-group order (so the result does not depend on
+// scheduling), decides, and writes the gate the rest of the solve's kernels read: 1 =
+// converged, return at once.  (The kernel boundary publishes the partial sums; a
+// per-work-group device-scope release would write back the whole L2 of its XCD every time.)
+struct Chk {
+  double* part;          // [work-groups][2] partial sums (nullptr: no test)
+  const int* gin;        // read on entry: a set gate skips the launch (nullptr: not gated)
+  const double* anorm;   // per plane bound of ||A_p||_2 (stacked components repeat it)
+  int nplane;            // planes per component (anorm index = plane % nplane)
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// two block sums in a fixed order (every thread gets them); red: 2 doubles per wave of LDS
+__device__ __forceinline__ void block_sum2(double& a, double& x, double* red) {
+  a = wave_sum(a);
+  x = wave_sum(x);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[2 * w] = a;
+    red[2 * w + 1] = x;
+  }
+  __syncthreads();
+  a = x = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    a += red[2 * i];
+    x += red[2 * i + 1];
+  }
+  __syncthreads();
+}
+
+// Called by every thread of a residual work-group after its nodes were summed into
+// (r2, ax2): the work-group's partial sums
+__device__ void chk_store(const Chk& ck, double r2, double ax2) {
+  __shared__ double red[32];
+  block_sum2(r2, ax2, red);
+  if (threadIdx.x == 0) {
+    const long bid = blockIdx.x + (long)gridDim.x * blockIdx.y;
+    ck.part[2 * bid] = r2;
+    ck.part[2 * bid + 1] = ax2;
+  }
+}
+
+// One work-group: the test of the nblk partial sums the residual kernel before it stored.
+// stat (family record): corrections, eta, max corrections, failed solves; status[1] gets bit
+// fam when the test after the last allowed correction fails.
+__global__ void __launch_bounds__(256) k_chk_decide(const double* __restrict__ part, long nblk,
+                                                    const int* __restrict__ gin, int* __restrict__ gate,
+                                                    double* __restrict__ stat, int* __restrict__ status,
+                                                    double tol, int it, int last, int fam) {
+  if (gin && *gin) return;
+  __shared__ double red[32];
+  double R = 0.0, X = 0.0;
+  for (long i = threadIdx.x; i < nblk; i += blockDim.x) {
+    R += part[2 * i];
+    X += part[2 * i + 1];
+  }
+  block_sum2(R, X, red);
+  if (threadIdx.x == 0) {
+    const double eta = X > 0.0 ? sqrt(R / X) : (R > 0.0 ? HUGE_VAL : 0.0);
+    const bool conv = eta <= tol;
+    *gate = conv ? 1 : 0;
+    stat[1] = eta;
+    if (conv || last) {
+      stat[0] = it;
+      stat[2] = fmax(stat[2], (double)it);
+      if (!conv) {
+        stat[3] += 1.0;
+        atomicOr(status + 1, 1 << fam);
+      }
+    }
+  }
+}
+
 // Copies n values into LDS with U independent loads in flight per thread: value(idx) is read for
 // every idx < n (the caller clamps addresses and masks values, so there is no branch around a
 // load) and store(idx, v) writes it.  Indices past n are clamped to n - 1, whose value is then
@@ -755,10 +843,13 @@ __global__ void __launch_bounds__(WG) k_residual(int Nx, int Ny, int planes, int
                            const double* __restrict__ KyB, const double* __restrict__ My,
                            const unsigned char* __restrict__ diry, const double* __restrict__ shift,
                            const double* __restrict__ bb, const double* __restrict__ x, double* __restrict__ r,
-                           int apply_only, double* norms, const unsigned char* __restrict__ ebot) {
+                           int apply_only, const unsigned char* __restrict__ ebot, Chk ck) {
+  if (ck.gin && *ck.gin) return;
   const long Ng = (long)Nx * Ny;
-  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= planes * Ng) return;
+  const long id0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double r2 = 0.0, ax2 = 0.0;
+  if (id0 < planes * Ng) {
+  const long id = id0;
   const int pl = (int)(id / Ng);
   const int node = (int)(id - pl * Ng);
   const int iy = node / Nx, ix = node - iy * Nx;
@@ -784,15 +875,19 @@ __global__ void __launch_bounds__(WG) k_residual(int Nx, int Ny, int planes, int
   const double Av = ax * My[iy] + Mx[ix] * ay + shift[pl] * Mx[ix] * My[iy] * xv;
   if (apply_only) {
     r[id] = Av;
-    return;
+  } else {
+    const bool dn = is_dir(dirx, diry, ebot, ix, iy);
+    const double bv = bb[id];
+    const double v = dn ? 0.0 : bv - Av;
+    r[id] = v;
+    if (ck.part && !dn) {
+      const double an = ck.anorm[pl % ck.nplane];
+      r2 = v * v;
+      ax2 = an * an * xv * xv;
+    }
   }
-  const bool dn = is_dir(dirx, diry, ebot, ix, iy);
-  const double v = dn ? 0.0 : bb[id] - Av;
-  r[id] = v;
-  if (norms) {  // diagnostics only
-    atomicAdd(&norms[2 * pl], v * v);
-    atomicAdd(&norms[2 * pl + 1], dn ? 0.0 : bb[id] * bb[id]);
   }
+  if (ck.part) chk_store(ck, r2, ax2);
 }
 
 // LDS-tiled variant of k_residual: a work-group takes RROWS rows of one plane; the rows
@@ -804,8 +899,9 @@ __global__ void __launch_bounds__(WG) k_residual(int Nx, int Ny, int planes, int
 // are read from LDS, as are the y-band coefficients, M_y and the Dirichlet flags of the
 // work-group's rows (staged with x).  b of the column's rows is requested before the staging, so
 // its latency overlaps it.  Needs Nx <= 256 (one column per thread).  res_rows leaves the result
-// of row rl, column ix to out(rl, iy, ix, value); the LDS it uses is res_rows_lds(Nx) doubles
-// from xs.
+// of row rl, column ix to out(rl, iy, ix, value, b, x) (b and x of a free node, 0 on Dirichlet
+// nodes and for apply_only, for the convergence test); the LDS it uses is res_rows_lds(Nx)
+// doubles from xs.
 #define RROWS 16
 __host__ __device__ constexpr long res_rows_lds(int K, int Nx) {
   return (long)(RROWS + 2 * K) * (Nx + 2 * K) + RROWS * (2 * K + 3);
@@ -880,11 +976,11 @@ __device__ __forceinline__ void res_rows(int Nx, int Ny, int perx, const double*
       const double my = myl[rl];
       const double Av = ax * my + mx * ay + sh * mx * my * xv;
       if (apply_only) {
-        out(rl, iy, ix, Av);
+        out(rl, iy, ix, Av, 0.0, 0.0);
       } else {
         // is_dir: x-Dirichlet column, or a y-Dirichlet row except the gap nodes of the bottom row
         const bool dn = dxn || (dyl[rl] != 0.0 && !(iy == 0 && egap));
-        out(rl, iy, ix, dn ? 0.0 : bv[rl] - Av);
+        out(rl, iy, ix, dn ? 0.0 : bv[rl] - Av, dn ? 0.0 : bv[rl], dn ? 0.0 : xv);
       }
     }
   }
@@ -898,14 +994,25 @@ __global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, 
                                                       const unsigned char* __restrict__ diry,
                                                       const double* __restrict__ shift, const double* __restrict__ bb,
                                                       const double* __restrict__ x, double* __restrict__ r,
-                                                      int apply_only, const unsigned char* __restrict__ ebot) {
+                                                      int apply_only, const unsigned char* __restrict__ ebot,
+                                                      Chk ck) {
+  if (ck.gin && *ck.gin) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* xs = reinterpret_cast<double*>(smem_raw);
   int rb, pl;
   xcd_tile(rb, pl);   // the tile res_rows takes
   const long Ng = (long)Nx * Ny, pofs = (long)pl * Ng;
+  double r2 = 0.0, x2 = 0.0;
   res_rows<K>(Nx, Ny, perx, KxB, Mx, dirx, KyB, My, diry, shift, bb, x, apply_only, ebot, xs,
-              [&](int, int iy, int ix, double v) { r[pofs + (long)iy * Nx + ix] = v; });
+              [&](int, int iy, int ix, double v, double bv, double xv) {
+                r[pofs + (long)iy * Nx + ix] = v;
+                r2 += v * v;
+                x2 += xv * xv;
+              });
+  if (ck.part) {
+    const double an = ck.anorm[pl % ck.nplane];
+    chk_store(ck, r2, an * an * x2);
+  }
 }
 
 // Batched GEMM on the matrix cores for the fast-diagonalisation passes:
@@ -945,7 +1052,9 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA,
                                               int M, int N, int K, T* __restrict__ C, long sC,
                                               const double* __restrict__ lr, const double* __restrict__ lc,
                                               const double* __restrict__ shift, double* __restrict__ X,
-                                              const TB* __restrict__ B2, double cb1, double cb2) {
+                                              const TB* __restrict__ B2, double cb1, double cb2,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   // B2 != nullptr: the right operand is cb1 B + cb2 B2 (e.g. the BDF extrapolation of a field)
   // four waves split K: wave w takes the 16-wide slices w, w+4, w+8, ... of the contraction,
   // and the partial tiles are summed in LDS in a fixed order (deterministic)
@@ -1027,7 +1136,9 @@ __global__ void __launch_bounds__(64 * SK) k_gemmt(const TA* __restrict__ A, lon
                                                    long sB, int M, int N, int K, T* __restrict__ C, long sC,
                                                    const double* __restrict__ lr, const double* __restrict__ lc,
                                                    const double* __restrict__ shift, double* __restrict__ X,
-                                                   const TB* __restrict__ B2, double cb1, double cb2) {
+                                                   const TB* __restrict__ B2, double cb1, double cb2,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef typename Mfma<T>::V V;
   constexpr int NR = SK > 1 ? SK - 1 : 1;
   __shared__ T red[NR][TM * TN * 4][64];
@@ -1170,7 +1281,9 @@ __global__ void __launch_bounds__(64 * SK) k_gemmt(const TA* __restrict__ A, lon
 
 template <typename T, typename TA, int EPI, int W, int SK>
 __global__ void __launch_bounds__(256) k_gemm_sr(const TA* __restrict__ A, const T* __restrict__ S, int Mtot,
-                                                 int N, int K, T* __restrict__ C, double* __restrict__ X) {
+                                                 int N, int K, T* __restrict__ C, double* __restrict__ X,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef typename Mfma<T>::V V;
   constexpr int WS = 4 / SK, NP = 16 * W + 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1285,7 +1398,9 @@ __global__ void __launch_bounds__(256) k_gemm_sl(const T* __restrict__ S, const 
                                                  int M, int N, int K, T* __restrict__ C, long sC,
                                                  const double* __restrict__ lr, const double* __restrict__ lc,
                                                  const double* __restrict__ shift, const TB* __restrict__ B2,
-                                                 double cb1, double cb2) {
+                                                 double cb1, double cb2,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef typename Mfma<T>::V V;
   constexpr int WS = 4 / SK, MP = 16 * W + 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1433,7 +1548,7 @@ static bool gemm_launch(pfd_ctx* c, int cfg, int cls, int planes, const TA* A, l
 #define SR_CASE(W_, SK_)                                                                                   \
   if (W == W_ && SK == SK_)                                                                                \
     hipLaunchKernelGGL((k_gemm_sr<T, TA, EPI, W_, SK_>), grid, dim3(256), lds, c->stream, A, (const T*)B, Mtot, N, \
-                       K, C, X);
+                       K, C, X, c->gate);
         SR_CASE(1, 1) SR_CASE(2, 1) SR_CASE(3, 1) SR_CASE(1, 2) SR_CASE(2, 2) SR_CASE(3, 2) SR_CASE(1, 4)
         SR_CASE(2, 4)
 #undef SR_CASE
@@ -1447,7 +1562,7 @@ static bool gemm_launch(pfd_ctx* c, int cfg, int cls, int planes, const TA* A, l
 #define SL_CASE(W_, SK_)                                                                                   \
   if (W == W_ && SK == SK_)                                                                                \
     hipLaunchKernelGGL((k_gemm_sl<T, TB, EPI, W_, SK_>), grid, dim3(256), lds, c->stream, (const T*)A, B, sB,     \
-                       planes, M, N, K, C, sC, lr, lc, shift, B2, cb1, cb2);
+                       planes, M, N, K, C, sC, lr, lc, shift, B2, cb1, cb2, c->gate);
       SL_CASE(1, 1) SL_CASE(2, 1) SL_CASE(3, 1) SL_CASE(1, 2) SL_CASE(2, 2) SL_CASE(3, 2) SL_CASE(1, 4)
       SL_CASE(2, 4)
 #undef SL_CASE
@@ -1460,12 +1575,12 @@ static bool gemm_launch(pfd_ctx* c, int cfg, int cls, int planes, const TA* A, l
 #define GEMMT_CASE(ID, TM_, TN_, SK_)                                                                  \
   case ID:                                                                                             \
     hipLaunchKernelGGL((k_gemmt<T, TA, TB, EPI, TM_, TN_, SK_>), grid, dim3(64 * SK_), 0, c->stream, A, sA, B, \
-                       sB, M, N, K, C, sC, lr, lc, shift, X, B2, cb1, cb2);                            \
+                       sB, M, N, K, C, sC, lr, lc, shift, X, B2, cb1, cb2, c->gate);                   \
     break;
   switch (cfg) {
     case 0:
       hipLaunchKernelGGL((k_gemm<T, TA, TB, EPI>), grid, dim3(256), 0, c->stream, A, sA, B, sB, M, N, K, C, sC, lr,
-                         lc, shift, X, B2, cb1, cb2);
+                         lc, shift, X, B2, cb1, cb2, c->gate);
       break;
     GEMMT_CASE(1, 2, 2, 1)
     GEMMT_CASE(2, 2, 2, 2)
@@ -1522,7 +1637,9 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_fdm1(int planes, int Ny, int Nx, long Ng, const double* __restrict__ r,
                                               const T* __restrict__ SxT, const T* __restrict__ SyT,
                                               const double* __restrict__ ly, const double* __restrict__ lx,
-                                              const double* __restrict__ shift, T* __restrict__ t) {
+                                              const double* __restrict__ shift, T* __restrict__ t,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   __shared__ T u[PFD_NMAX * FDM_LDU];
   typedef typename Mfma<T>::V V;
   const int nstrip = (Nx + 15) >> 4, mtiles = (Ny + 15) >> 4;
@@ -1611,7 +1728,9 @@ __global__ void __launch_bounds__(256) k_fdm1(int planes, int Ny, int Nx, long N
 template <typename T, bool OVERWRITE>
 __global__ void __launch_bounds__(256) k_fdm2(int planes, int Ny, int Nx, long Ng, const T* __restrict__ t,
                                               const T* __restrict__ Sy, const T* __restrict__ Sx,
-                                              double* __restrict__ x) {
+                                              double* __restrict__ x,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   __shared__ T v[16 * (PFD_NMAX + 1)];
   typedef typename Mfma<T>::V V;
   const int nstrip = (Ny + 15) >> 4, ntiles = (Nx + 15) >> 4;
@@ -1707,7 +1826,9 @@ __global__ void __launch_bounds__(256) k_fdm2(int planes, int Ny, int Nx, long N
 //   mode 1 (range projection):     f -= (sum f)/(sum M) * M
 #define PCH 32
 __global__ void k_plane_sums(long Ng, const double* __restrict__ Mdiag, const double* __restrict__ shift,
-                             const double* __restrict__ f, int weighted, double* __restrict__ part) {
+                             const double* __restrict__ f, int weighted, double* __restrict__ part,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   const int blk = blockIdx.x, pl = blockIdx.y;
   __shared__ double sm[WG];
   double a = 0.0;
@@ -1727,7 +1848,9 @@ __global__ void k_plane_sums(long Ng, const double* __restrict__ Mdiag, const do
 }
 
 __global__ void k_plane_sub(long Ng, int planes, const double* __restrict__ Mdiag, const double* __restrict__ shift,
-                            const double* __restrict__ part, double Mtot, int mode, double* __restrict__ f) {
+                            const double* __restrict__ part, double Mtot, int mode, double* __restrict__ f,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= planes * Ng) return;
   const int pl = (int)(id / Ng);
@@ -1770,13 +1893,22 @@ static void plane_fix(pfd_ctx* c, int fam, double* f, int mode) {
   Family& F = c->fam[fam];
   const long tot = (long)c->planes * c->Ng;
   LAUNCH(PFD_PROF_OTHER, k_plane_sums, dim3(PCH, c->planes), dim3(WG), 0, c->stream, c->Ng, c->Mdiag, F.dshift, f,
-                     mode == 0 ? 1 : 0, c->d_part);
+                     mode == 0 ? 1 : 0, c->d_part, c->gate);
   LAUNCH(PFD_PROF_OTHER, k_plane_sub, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Ng, c->planes, c->Mdiag, F.dshift,
-                     c->d_part, c->Mtot, mode, f);
+                     c->d_part, c->Mtot, mode, f, c->gate);
 }
 
-static void residual(pfd_ctx* c, int fam, const double* b, const double* x, double* r, int apply_only,
-                     double* norms, const double* shift = nullptr, int np = 0) {
+// A convergence test that is off (plain residual or apply)
+static Chk no_chk() {
+  Chk k{};
+  return k;
+}
+
+// r = b - A x (apply_only: r = A x) on np planes from b, x, r and the per-plane shifts sh
+// (default: all planes of the family); ck: the refinement's convergence test, or none.
+// Returns the number of work-groups (partial sums of the test).
+static long residual(pfd_ctx* c, int fam, const double* b, const double* x, double* r, int apply_only,
+                     const Chk* ck = nullptr, const double* shift = nullptr, int np = 0) {
   Family& F = c->fam[fam];
   const double* sh = shift ? shift : F.dshift;
   Dir1D& dx = c->dirs[F.ix];
@@ -1784,23 +1916,25 @@ static void residual(pfd_ctx* c, int fam, const double* b, const double* x, doub
   const int planes = np > 0 ? np : c->planes;   // np: stacked components as extra planes
   const long tot = (long)planes * c->Ng;
   const size_t lds = sizeof(double) * (size_t)res_rows_lds(c->K, c->Nx);
-  const bool tiled = !norms && c->Nx <= 256 && lds <= 64 * 1024 && c->resid_variant >= 1;
+  const bool tiled = c->Nx <= 256 && lds <= 64 * 1024 && c->resid_variant >= 1;
+  const Chk k = ck ? *ck : no_chk();
 #define RES_CASE(KK)                                                                                      \
   case KK:                                                                                                \
     if (tiled)                                                                                            \
       LAUNCH(PFD_PROF_RESID, k_residual_lds<KK>, dim3((c->Ny + RROWS - 1) / RROWS, planes), dim3(256), lds,     \
              c->stream, c->Nx, c->Ny, (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, \
-             r, apply_only, c->lift[fam].ebot);                                                           \
+             r, apply_only, c->lift[fam].ebot, k);                                                        \
     else                                                                                                  \
       LAUNCH(PFD_PROF_RESID, k_residual<KK>, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, planes,    \
-             (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, r, apply_only, norms, \
-             c->lift[fam].ebot);                                                                          \
+             (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, r, apply_only,     \
+             c->lift[fam].ebot, k);                                                                       \
     break;
   switch (c->K) {
     RES_CASE(2) RES_CASE(3) RES_CASE(4) RES_CASE(5) RES_CASE(6) RES_CASE(7) RES_CASE(8) RES_CASE(9)
     RES_CASE(10) RES_CASE(11) RES_CASE(12) RES_CASE(13) RES_CASE(14) RES_CASE(15) RES_CASE(16)
   }
 #undef RES_CASE
+  return tiled ? (long)((c->Ny + RROWS - 1) / RROWS) * planes : (long)nblk(tot);
 }
 
 hipError_t apply(pfd_ctx* c, int fam, const double* x, double* y, int ncomp) {
@@ -1921,7 +2055,9 @@ template <typename T, int RT, int TN>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 7 : 1))) k_fdm_mid(int planes, int Ny, int Nx, long Ng, const T* __restrict__ SyTw,
                                                   const T* __restrict__ Syw, const T* __restrict__ T1,
                                                   const double* __restrict__ ly, const double* __restrict__ lx,
-                                                  const double* __restrict__ shift, T* __restrict__ T3, int ldo) {
+                                                  const double* __restrict__ shift, T* __restrict__ T3, int ldo,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef typename Mfma<T>::V V;
   constexpr int CW = 16 * TN, LDC = FDM_MID_LDC(CW);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -2025,7 +2161,7 @@ static bool fdm_mid_launch(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const d
 #define MID_CASE(RT_, TN_)                                                                                   \
   if (RT == RT_ && tn == TN_)                                                                                \
     LAUNCH(cls, (k_fdm_mid<T, RT_, TN_>), grid, block, lds, c->stream, P, Ny, Nx, c->Ng, SyTw, Syw, t1, dy.dlam, \
-           dx.dlam, shift, t3, ldo);
+           dx.dlam, shift, t3, ldo, c->gate);
   MID_CASE(1, 1) MID_CASE(1, 2)
   if constexpr (sizeof(T) == 4) {   // two row tiles per wave only where the FP32 block fits
     MID_CASE(2, 1) MID_CASE(2, 2)
@@ -2048,7 +2184,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8
                                                 const unsigned char* __restrict__ diry,
                                                 const double* __restrict__ shift, const double* __restrict__ bb,
                                                 const double* __restrict__ x, const unsigned char* __restrict__ ebot,
-                                                const float* __restrict__ SxB, float* __restrict__ T1) {
+                                                const float* __restrict__ SxB, float* __restrict__ T1, Chk ck) {
+  if (ck.gin && *ck.gin) return;
   typedef Mfma<float>::V V;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* xs = reinterpret_cast<double*>(smem_raw);
@@ -2056,8 +2193,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8
   float* Rl = reinterpret_cast<float*>(xs + res_rows_lds(K, Nx));   // [RROWS][LDR]
   for (int idx = threadIdx.x; idx < RROWS * LDR; idx += 256) Rl[idx] = 0.0f;
   __syncthreads();   // zero fill before the residual rows land (res_rows syncs after its staging)
+  double r2 = 0.0, x2 = 0.0;
   res_rows<K>(Nx, Ny, perx, KxB, Mx, dirx, KyB, My, diry, shift, bb, x, 0, ebot, xs,
-              [&](int rl, int, int ix, double v) { Rl[rl * LDR + ix] = float(v); });
+              [&](int rl, int, int ix, double v, double bv, double xv) {
+                Rl[rl * LDR + ix] = float(v);
+                r2 += v * v;
+                x2 += xv * xv;
+              });
+  if (ck.part) {   // the test's sums leave the registers before the matrix-core phase
+    int rb0, pl0;
+    xcd_tile(rb0, pl0);
+    const double an = ck.anorm[pl0 % ck.nplane];
+    chk_store(ck, r2, an * an * x2);
+  }
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
   const int NT = KS;   // column tiles of the square product
@@ -2130,7 +2278,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8
 // EPI 3: x = .
 template <int EPI, int TG, int CH>
 __global__ void __launch_bounds__(256) k_p4(const float* __restrict__ T3, int Mtot, int Nx, int KPX,
-                                            const float* __restrict__ SxFw, double* __restrict__ X) {
+                                            const float* __restrict__ SxFw, double* __restrict__ X,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef Mfma<float>::V V;
   const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
   const int KS = KPX / 16, NT = KS, NG = (NT + TG - 1) / TG, MT = (Mtot + 15) / 16;
@@ -2208,9 +2358,11 @@ static bool p4_launch(pfd_ctx* c, const Dir1D& dx, int P, const float* t3, doubl
 #define P4_CASE(F_, TG_, CH_)                                                                                 \
   if (form == F_) {                                                                                           \
     if (overwrite)                                                                                            \
-      LAUNCH(PFD_PROF_GEMM32, (k_p4<3, TG_, CH_>), grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x); \
+      LAUNCH(PFD_PROF_GEMM32, (k_p4<3, TG_, CH_>), grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x, \
+             c->gate);                                                                                        \
     else                                                                                                      \
-      LAUNCH(PFD_PROF_GEMM32, (k_p4<2, TG_, CH_>), grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x); \
+      LAUNCH(PFD_PROF_GEMM32, (k_p4<2, TG_, CH_>), grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x, \
+             c->gate);                                                                                        \
   }
   P4_CASE(1, 1, 2) P4_CASE(2, 2, 2) P4_CASE(3, 3, 2) P4_CASE(4, 4, 2) P4_CASE(6, 1, 4)
 #undef P4_CASE
@@ -2227,7 +2379,9 @@ static bool p4_launch(pfd_ctx* c, const Dir1D& dx, int P, const float* t3, doubl
 template <typename TA, int EPI>
 __global__ void __launch_bounds__(1024) k_srp(const TA* __restrict__ A, int lda, int Mtot, int K, int N,
                                               const float* __restrict__ SB, float* __restrict__ C,
-                                              double* __restrict__ X, int ldc) {
+                                              double* __restrict__ X, int ldc,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef Mfma<float>::V V;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int KP = (K + 15) & ~15, KS = KP / 16, NT = (N + 15) / 16, LDA = KP + 4;
@@ -2325,13 +2479,14 @@ static bool srp_launch(pfd_ctx* c, int P, const TA* A, int lda, int K, int N, co
   const int nw = NT < 16 ? NT : 16;
   const unsigned grid = (unsigned)std::min(MT, c->num_cu);
   LAUNCH(PFD_PROF_GEMM32, (k_srp<TA, EPI>), dim3(grid), dim3(64 * nw), lds, c->stream, A, lda, Mtot, K, N, SB, C, X,
-         ldc);
+         ldc, c->gate);
   return true;
 }
 
 // refined path: T1 = float(b - A x) Sx for family fam in one launch (k_res_p1); false where it
 // does not apply (Nx > 256 or the LDS tile too large)
-static bool res_p1_launch(pfd_ctx* c, int fam, const double* b, const double* x, int np, float* t1) {
+static bool res_p1_launch(pfd_ctx* c, int fam, const double* b, const double* x, const double* shift, int np,
+                          float* t1, const Chk& ck) {
   Family& F = c->fam[fam];
   const Dir1D& dx = c->dirs[F.ix];
   const Dir1D& dy = c->dirs[F.iy];
@@ -2344,12 +2499,12 @@ static bool res_p1_launch(pfd_ctx* c, int fam, const double* b, const double* x,
   case KK:                                                                                                   \
     if (three)                                                                                               \
       LAUNCH(PFD_PROF_RESID, (k_res_p1<KK, 3>), grid, dim3(256), lds, c->stream, c->Nx, c->Ny, (int)dx.periodic, \
-             dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, (const double*)F.dshift, b, x, c->lift[fam].ebot,  \
-             (const float*)dx.fSTw, t1);                                                                     \
+             dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, shift, b, x, c->lift[fam].ebot,                 \
+             (const float*)dx.fSTw, t1, ck);                                                                 \
     else                                                                                                     \
       LAUNCH(PFD_PROF_RESID, (k_res_p1<KK, 4>), grid, dim3(256), lds, c->stream, c->Nx, c->Ny, (int)dx.periodic, \
-             dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, (const double*)F.dshift, b, x, c->lift[fam].ebot,  \
-             (const float*)dx.fSTw, t1);                                                                     \
+             dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, shift, b, x, c->lift[fam].ebot,                 \
+             (const float*)dx.fSTw, t1, ck);                                                                 \
     return true;
   switch (c->K) {
     RP1_CASE(2) RP1_CASE(3) RP1_CASE(4) RP1_CASE(5) RP1_CASE(6) RP1_CASE(7) RP1_CASE(8) RP1_CASE(9)
@@ -2373,13 +2528,13 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
   if (c->fdm_variant == 1) {
     const int cls = sizeof(T) == 8 ? PFD_PROF_GEMM64 : PFD_PROF_GEMM32;
     LAUNCH(cls, k_fdm1<T>, dim3(P * ((Nx + 15) / 16)), dim3(256), 0, c->stream, P, Ny, Nx, Ng, r, SxT, SyT,
-           dy.dlam, dx.dlam, shift, t1);
+           dy.dlam, dx.dlam, shift, t1, c->gate);
     if (overwrite)
       LAUNCH(cls, (k_fdm2<T, true>), dim3(P * ((Ny + 15) / 16)), dim3(256), 0, c->stream, P, Ny, Nx, Ng,
-             (const T*)t1, Sy, Sx, x);
+             (const T*)t1, Sy, Sx, x, c->gate);
     else
       LAUNCH(cls, (k_fdm2<T, false>), dim3(P * ((Ny + 15) / 16)), dim3(256), 0, c->stream, P, Ny, Nx, Ng,
-             (const T*)t1, Sy, Sx, x);
+             (const T*)t1, Sy, Sx, x, c->gate);
     return;
   }
   if (!t1_ready) {   // else the first pass came with the residual (k_res_p1)
@@ -2427,7 +2582,9 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
 __global__ void k_elec_gap(int Nx, int Ny, int K, long Ng, int ng, const int* __restrict__ gap,
                            const double* __restrict__ Mx, const double* __restrict__ Ky0,
                            const double* __restrict__ r, const double* __restrict__ Y,
-                           const double* __restrict__ Sinv, double* __restrict__ dG) {
+                           const double* __restrict__ Sinv, double* __restrict__ dG,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   __shared__ double t[PFD_NMAX];
   const int pl = blockIdx.x;
   const double* rp = r + pl * Ng;
@@ -2452,7 +2609,9 @@ __global__ void k_elec_gap(int Nx, int Ny, int K, long Ng, int ng, const int* __
 __global__ void k_elec_z(int Nx, int Ny, int K, int planes, int ng, const int* __restrict__ gapidx,
                          const double* __restrict__ Mx, const double* __restrict__ Ky0,
                          const double* __restrict__ dG, const double* __restrict__ Y, double* __restrict__ z,
-                         double* __restrict__ x) {
+                         double* __restrict__ x,
+    const int* __restrict__ gate) {
+  if (gate && *gate) return;   // the refinement has converged: nothing left to do
   const long Ng = (long)Nx * Ny;
   const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= planes * Ng) return;
@@ -2479,69 +2638,120 @@ static void elec_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const dou
   double* z = c->r + tot;   // scratch block of r (the potential solve uses block 0)
   fdm_correct<T>(c, dx, dy, shift, Sx, SxT, Sy, SyT, r, c->Ybuf, true);
   LAUNCH(PFD_PROF_OTHER, k_elec_gap, dim3(c->planes), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->K, c->Ng,
-         c->elec.ng, c->elec.d_gap, dx.dM1, dy.dK0, r, c->Ybuf, c->elec.d_Sinv, c->elec.d_dG);
+         c->elec.ng, c->elec.d_gap, dx.dM1, dy.dK0, r, c->Ybuf, c->elec.d_Sinv, c->elec.d_dG, c->gate);
   LAUNCH(PFD_PROF_OTHER, k_elec_z, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->K, c->planes,
-         c->elec.ng, c->elec.d_gapidx, dx.dM1, dy.dK0, c->elec.d_dG, c->Ybuf, z, x);
+         c->elec.ng, c->elec.d_gapidx, dx.dM1, dy.dK0, c->elec.d_dG, c->Ybuf, z, x, c->gate);
   fdm_correct<T>(c, dx, dy, shift, Sx, SxT, Sy, SyT, z, x);
 }
 
-// Solve (K + c M) x = b for ncomp stacked right sides (each planes*Ng), x holding the initial
-// guess and the Dirichlet values.  r0 != nullptr: the first residual b - A x is given
-// (stacked like b).  project != 0: the right side may be incompatible on singular planes
-// (general entry point) and the initial guess arbitrary, so the residual is projected and
-// the gauge int_h x = 0 imposed; the step's own right sides are compatible and start
-// from x0 = x_D, whose corrections keep int_h x = 0 up to rounding.
-hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp, int project, const double* r0) {
+// One FP64 fast-diagonalisation correction (a direct solve) of planes [p0, p0 + np) of one
+// component: x += A^{-1} r with r = b - A x formed here unless r0 (exact) is given.  project:
+// the right side may be incompatible on singular planes and the guess arbitrary (general entry
+// point), so the residual is projected onto the range; singular planes get the gauge
+// int_h x = 0 afterwards.
+static void solve64(pfd_ctx* c, int fam, const double* b, double* x, int p0, int np, int project,
+                    const double* r0) {
   Family& F = c->fam[fam];
   Dir1D& dx = c->dirs[F.ix];
   Dir1D& dy = c->dirs[F.iy];
-  const long tot = (long)c->planes * c->Ng;
-  const bool fp32 = c->prob.precision == PFD_REFINED_FP32;
-  const int iters = fp32 ? (c->prob.refine_iters > 0 ? c->prob.refine_iters : 2) : 1;
-  const bool elec = fam == PFD_FAM_V && c->elec.ng > 0;
-  // up to three contiguous components (the velocity) are solved as one stack of planes: the
-  // family's shift array repeats per component; singular and electrode solves go one by one
-  const bool stack = ncomp > 1 && ncomp <= 3 && !F.any_singular && !elec;
-  const int groups = stack ? 1 : ncomp;
-  const int np = stack ? c->planes * ncomp : c->planes;
-  for (int gi = 0; gi < groups; ++gi) {
-    const double* bc = b + gi * tot;
-    double* xc = x + gi * tot;
-    for (int it = 0; it < iters; ++it) {
-      const double* rin = c->r;
-      bool t1_ready = false;   // residual fused with the first pass (refined path, variant 2)
-      if (it == 0 && r0) {
-        rin = r0 + gi * tot;
-      } else if (fp32 && !elec && c->resid_variant == 2 && c->fdm_variant != 1 && !(F.any_singular && project) &&
-                 res_p1_launch(c, fam, bc, xc, np, reinterpret_cast<float*>(c->tmp))) {
-        t1_ready = true;
-      } else {
-        residual(c, fam, bc, xc, c->r, 0, nullptr, nullptr, np);
-        if (F.any_singular && project) plane_fix(c, fam, c->r, 1);
-      }
-      if (fp32 && elec)
-        elec_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, rin, xc);
-      else if (elec)
-        elec_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, rin, xc);
-      else if (fp32)
-        fdm_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, rin, xc, false, np, t1_ready);
-      else
-        fdm_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, rin, xc, false, np);
-    }
-    if (F.any_singular && (project || fp32)) plane_fix(c, fam, xc, 0);
+  const bool elec = fam == PFD_FAM_V && c->elec.ng > 0;   // all planes (no plane split)
+  const long o = (long)p0 * c->Ng;
+  const double* sh = F.dshift + p0;
+  const double* rin = r0;
+  if (!rin) {
+    residual(c, fam, b + o, x + o, c->r + o, 0, nullptr, sh, np);
+    if (F.any_singular && project) plane_fix(c, fam, c->r, 1);
+    rin = c->r + o;
   }
-  if (c->check_residual) {
-    for (int comp = 0; comp < ncomp; ++comp) {
-      hipMemsetAsync(c->d_norms, 0, sizeof(double) * 2 * c->planes, c->stream);
-      residual(c, fam, b + comp * tot, x + comp * tot, c->r, 0, c->d_norms);
-      std::vector<double> h(2 * c->planes);
-      hipMemcpyAsync(h.data(), c->d_norms, sizeof(double) * 2 * c->planes, hipMemcpyDeviceToHost, c->stream);
-      hipStreamSynchronize(c->stream);
-      for (int p = 0; p < c->planes; ++p) {
-        double rel = std::sqrt(h[2 * p]) / std::max(1e-300, std::sqrt(h[2 * p + 1]));
-        if (h[2 * p + 1] > 0 && rel > c->last_residual) c->last_residual = rel;
-      }
+  if (elec)
+    elec_correct<double>(c, dx, dy, F.dshift, dx.dS, dx.dST, dy.dS, dy.dST, rin, x);
+  else
+    fdm_correct<double>(c, dx, dy, sh, dx.dS, dx.dST, dy.dS, dy.dST, rin, x + o, false, np);
+}
+
+// FP32 corrections with FP64 residuals (iterative refinement) on planes [p0, p0 + np/ncomp) of
+// ncomp stacked components (np planes in all).  r0: the first residual, recycled from the right
+// sides (the first correction then takes it untested).  Every later residual is tested (Chk) and
+// sets the gate; the corrections after it, and the remaining tests, return at once once it is
+// set, so the whole sequence can be captured in a graph.  After refine_max corrections a last
+// test records non-convergence (status bit, returned as PFD_ENOCONV by the stepping calls).
+static void refine32(pfd_ctx* c, int fam, const double* b, double* x, int p0, int np, const double* r0) {
+  Family& F = c->fam[fam];
+  Dir1D& dx = c->dirs[F.ix];
+  Dir1D& dy = c->dirs[F.iy];
+  const bool elec = fam == PFD_FAM_V && c->elec.ng > 0;
+  const long o = (long)p0 * c->Ng;
+  const double* sh = F.dshift + p0;
+  const int per = c->planes - p0;   // planes per component in this range
+  Chk ck{};
+  ck.part = c->d_rpart;
+  ck.anorm = c->d_anorm[fam] + p0;
+  ck.nplane = per;
+  // the test of the residual just formed: its partial sums -> gate and record
+  auto decide = [&](long nb, int it, int last, const int* gin) {
+    LAUNCH(PFD_PROF_OTHER, k_chk_decide, dim3(1), dim3(256), 0, c->stream, (const double*)c->d_rpart, nb, gin,
+           c->d_gate, c->d_rstat + 4 * fam, c->d_status, c->refine_tol, it, last, fam);
+  };
+  const int maxit = c->refine_max;
+  bool tested = false;   // a test of this solve has written the gate
+  for (int it = 0; it < maxit; ++it) {
+    const double* rin = c->r + o;
+    bool t1_ready = false;
+    if (it == 0 && r0) {
+      rin = r0 + o;
+    } else {
+      const int* gin = tested ? c->d_gate : nullptr;
+      ck.gin = gin;
+      long nb = (long)((c->Ny + RROWS - 1) / RROWS) * np;
+      if (!elec && c->resid_variant == 2 && c->fdm_variant != 1 &&
+          res_p1_launch(c, fam, b + o, x + o, sh, np, reinterpret_cast<float*>(c->tmp), ck))
+        t1_ready = true;
+      else
+        nb = residual(c, fam, b + o, x + o, c->r + o, 0, &ck, sh, np);
+      decide(nb, it, 0, gin);
+      tested = true;
     }
+    c->gate = tested ? c->d_gate : nullptr;
+    if (elec)
+      elec_correct<float>(c, dx, dy, F.dshift, dx.fS, dx.fST, dy.fS, dy.fST, rin, x);
+    else
+      fdm_correct<float>(c, dx, dy, sh, dx.fS, dx.fST, dy.fS, dy.fST, rin, x + o, false, np, t1_ready);
+    c->gate = nullptr;
+  }
+  const int* gin = tested ? c->d_gate : nullptr;
+  ck.gin = gin;
+  const long nb = residual(c, fam, b + o, x + o, c->r + o, 0, &ck, sh, np);
+  decide(nb, maxit, 1, gin);
+}
+
+// Solve (K + c M) x = b for ncomp stacked right sides (each planes*Ng), x holding the initial
+// guess and the Dirichlet values.  r0 != nullptr: the first residual b - A x is given (stacked
+// like b): exact on the plain FP64 path and on families the FP32-refined path solves in FP64
+// (r0_exact), recycled from the right sides otherwise.  project != 0: the right side may be
+// incompatible on singular planes and the initial guess arbitrary (general entry point).
+// The precision ladder splits a family's planes: [0, n64) by one FP64 correction (singular
+// and ill-conditioned operators), the rest by FP32 iterative refinement (refined path only).
+hipError_t solve(pfd_ctx* c, int fam, const double* b, double* x, int ncomp, int project, const double* r0,
+                 bool r0_exact) {
+  Family& F = c->fam[fam];
+  const long tot = (long)c->planes * c->Ng;
+  const bool refined = c->prob.precision == PFD_REFINED_FP32;
+  const int n64 = refined ? c->n64[fam] : c->planes;
+  const bool elec = fam == PFD_FAM_V && c->elec.ng > 0;
+  for (int comp = 0; comp < ncomp; ++comp) {
+    if (n64 == 0) break;
+    const double* rc = (r0 && (r0_exact || !refined)) ? r0 + comp * tot : nullptr;
+    solve64(c, fam, b + comp * tot, x + comp * tot, 0, n64, project, rc);
+    if (F.any_singular) plane_fix(c, fam, x + comp * tot, 0);
+  }
+  if (n64 < c->planes) {
+    // up to three contiguous components (the velocity) are refined as one stack of planes;
+    // electrode solves go one by one
+    const bool stack = ncomp > 1 && ncomp <= 3 && n64 == 0 && !elec;
+    const int groups = stack ? 1 : ncomp;
+    const int np = (c->planes - n64) * (stack ? ncomp : 1);
+    for (int gi = 0; gi < groups; ++gi)
+      refine32(c, fam, b + gi * tot, x + gi * tot, n64, np, r0 ? r0 + gi * tot : nullptr);
   }
   return hipGetLastError();
 }
@@ -2792,7 +3002,9 @@ hipError_t autotune(pfd_ctx* c) {
     // residual fused with the first pass against the separate residual and first-pass GEMM
     float* t1 = reinterpret_cast<float*>(c->tmp);
     bool ok = true;
-    auto fused = [&]() { ok = res_p1_launch(c, PFD_FAM_U, c->zero_buf, c->b[2], c->planes, t1); };
+    auto fused = [&]() {
+      ok = res_p1_launch(c, PFD_FAM_U, c->zero_buf, c->b[2], c->fam[PFD_FAM_U].dshift, c->planes, t1, no_chk());
+    };
     auto separate = [&]() {
       residual(c, PFD_FAM_U, c->zero_buf, c->b[2], c->r, 0, nullptr);
       gemm<float, double, float, 0>(c, PFD_GS_P1, c->planes, c->r, c->Ng, dx.fS, 0, c->Ny, c->Nx, c->Nx, t1,
@@ -2847,11 +3059,11 @@ hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout) {
   (void)dx;
   (void)dy;
   LAUNCH(PFD_PROF_ELEM, k_V_elem, eg, eb, 0, c->stream, g, P, ph, ph, Vin, Vin, c->Lb[0]);
-  const bool warm = c->prob.precision == PFD_REFINED_FP32;
+  const bool warm = warm_start(c, PFD_FAM_V);
   LAUNCH(PFD_PROF_NODAL, k_V_rhs, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, P, c->lift[PFD_FAM_V], c->Lb[0],
                      c->Mdiag, c->src[PFD_SRC_FV], c->src[PFD_SRC_VD], warm ? Vin : nullptr, Vin, c->b[0], c->r,
                      Vout);
-  return solve(c, PFD_FAM_V, c->b[0], Vout, 1, 0, warm ? nullptr : c->r);
+  return solve(c, PFD_FAM_V, c->b[0], Vout, 1, 0, warm ? nullptr : c->r, !warm);
 }
 
 hipError_t step_once(pfd_ctx* c, int equilibrium) {
@@ -2862,21 +3074,22 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
   const dim3 ng(nblk(tot)), nb(WG);
   hipStream_t st = c->stream;
   const int nw = 1 - c->cur;  // level n+1 overwrites level n-1
-  // FP32-refined solves start from the extrapolated history (warm), FP64 ones from the
-  // Dirichlet data with the first residual folded into the right-side kernels (cold)
-  const bool warm = c->prob.precision == PFD_REFINED_FP32;
-  auto H = [&](int f, int lv) -> const double* { return warm ? FLD(f, lv) : nullptr; };
-  double* r0 = warm ? nullptr : c->r;
+  // Families refined in FP32 start from the extrapolated history (warm); FP64 solves start from
+  // the Dirichlet data with the first residual folded into the right-side kernels (cold)
+  auto W = [&](int fam) { return warm_start(c, fam); };
+  auto H = [&](int fam, int f, int lv) -> const double* { return W(fam) ? FLD(f, lv) : nullptr; };
   // right sides: b^{n+1} of each family goes to bh[f][nw]; with recycling (refined path, two
   // previous solves recorded) the first residual is formed from bh[f][cur] (= b^n) and b^{n-1}
+  auto REC = [&](int fam) { return W(fam) && c->rec_on; };
   auto BB = [&](int f) { return c->bh[f][nw]; };
   auto LR = [&](int f) {
     Lift L = c->lift[f];
-    L.bprev = c->rec_on ? c->bh[f][c->cur] : nullptr;
+    L.bprev = REC(f) ? c->bh[f][c->cur] : nullptr;
     return L;
   };
-  auto BP = [&](int f) -> const double* { return c->rec_on ? c->bh[f][c->cur] : nullptr; };
-  double* rr = (warm && c->rec_on) ? c->r : r0;   // the solve's first residual, when formed above
+  auto BP = [&](int f) -> const double* { return REC(f) ? c->bh[f][c->cur] : nullptr; };
+  // the solve's first residual, when the right-side kernel formed it (exact when cold)
+  auto RR = [&](int f) -> double* { return (!W(f) || REC(f)) ? c->r : nullptr; };
   double* const* S = c->src;
   // ---- V (eq. 54)
   {
@@ -2887,8 +3100,9 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
     (void)dx;
     (void)dy;
     LAUNCH(PFD_PROF_NODAL, k_V_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_V), c->Lb[0], c->Mdiag, S[PFD_SRC_FV],
-                       S[PFD_SRC_VD], H(F_V, 0), H(F_V, -1), BB(PFD_FAM_V), c->r, c->fld[F_V][nw]);
-    solve(c, PFD_FAM_V, BB(PFD_FAM_V), c->fld[F_V][nw], 1, 0, rr);
+                       S[PFD_SRC_VD], H(PFD_FAM_V, F_V, 0), H(PFD_FAM_V, F_V, -1), BB(PFD_FAM_V), c->r,
+                       c->fld[F_V][nw]);
+    solve(c, PFD_FAM_V, BB(PFD_FAM_V), c->fld[F_V][nw], 1, 0, RR(PFD_FAM_V), !W(PFD_FAM_V));
   }
   // ---- E (eq. 55)
   LAUNCH(PFD_PROF_ELEM, k_E_elem, eg, eb, 0, st, g, c->fld[F_V][nw], c->Lb[0], c->Lb[1]);
@@ -2904,14 +3118,15 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
   LAUNCH(PFD_PROF_ELEM, k_psi_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), uxn, uxo, uyn, uyo, E2,
                      S[PFD_SRC_G], (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, c->Lb[0]);
   LAUNCH(PFD_PROF_NODAL, k_psi_rhs, ng, nb, 0, st, g, P, c->Lb[0], c->bm_open, c->bm_wall, S[PFD_SRC_G1],
-                     S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), E2, H(F_PSI, 0), H(F_PSI, -1),
-                     BB(PFD_FAM_PSI), c->U, c->Q2, c->r, c->fld[F_PSI][nw], BP(PFD_FAM_PSI));
-  solve(c, PFD_FAM_PSI, BB(PFD_FAM_PSI), c->fld[F_PSI][nw], 1, 0, rr);
+                     S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), E2, H(PFD_FAM_PSI, F_PSI, 0),
+                     H(PFD_FAM_PSI, F_PSI, -1), BB(PFD_FAM_PSI), c->U, c->Q2, c->r, c->fld[F_PSI][nw],
+                     BP(PFD_FAM_PSI));
+  solve(c, PFD_FAM_PSI, BB(PFD_FAM_PSI), c->fld[F_PSI][nw], 1, 0, RR(PFD_FAM_PSI), !W(PFD_FAM_PSI));
   // ---- phi (eq. 57)
   LAUNCH(PFD_PROF_NODAL, k_phi_rhs, ng, nb, 0, st, g, P, c->Mdiag, c->fld[F_PSI][nw], c->bm_open, c->bm_wall,
-                     S[PFD_SRC_G2], c->U, H(F_PHI, 0), H(F_PHI, -1), BB(PFD_FAM_PHI), c->r, c->fld[F_PHI][nw],
-                     BP(PFD_FAM_PHI));
-  solve(c, PFD_FAM_PHI, BB(PFD_FAM_PHI), c->fld[F_PHI][nw], 1, 0, rr);
+                     S[PFD_SRC_G2], c->U, H(PFD_FAM_PHI, F_PHI, 0), H(PFD_FAM_PHI, F_PHI, -1), BB(PFD_FAM_PHI),
+                     c->r, c->fld[F_PHI][nw], BP(PFD_FAM_PHI));
+  solve(c, PFD_FAM_PHI, BB(PFD_FAM_PHI), c->fld[F_PHI][nw], 1, 0, RR(PFD_FAM_PHI), !W(PFD_FAM_PHI));
   if (equilibrium) {
     for (int f : {F_UX, F_UY, F_P}) LAUNCH(PFD_PROF_OTHER, k_fill, ng, nb, 0, st, tot, c->fld[f][nw], 0.0);
   } else {
@@ -2921,16 +3136,18 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
                        FLD(F_UX, 0), FLD(F_UX, -1), FLD(F_UY, 0), FLD(F_UY, -1), FLD(F_P, 0),
                        FLD(F_P, -1), S[PFD_SRC_FX], S[PFD_SRC_FY], c->Lb[0], c->Lb[1], c->Lb[2], Mom3{});
     LAUNCH(PFD_PROF_NODAL, k_P_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_P), c->Lb[0], S[PFD_SRC_WX], S[PFD_SRC_WY],
-                       S[PFD_SRC_F2], H(F_P, 0), H(F_P, -1), BB(PFD_FAM_P), c->r, c->fld[F_P][nw]);
-    solve(c, PFD_FAM_P, BB(PFD_FAM_P), c->fld[F_P][nw], 1, 0, rr);
+                       S[PFD_SRC_F2], H(PFD_FAM_P, F_P, 0), H(PFD_FAM_P, F_P, -1), BB(PFD_FAM_P), c->r,
+                       c->fld[F_P][nw]);
+    solve(c, PFD_FAM_P, BB(PFD_FAM_P), c->fld[F_P][nw], 1, 0, RR(PFD_FAM_P), !W(PFD_FAM_P));
     // ---- u (eq. 59)
     LAUNCH(PFD_PROF_ELEM, k_gradP_elem, eg, eb, 0, st, g, P, c->fld[F_P][nw], (const double*)nullptr, c->Lb[1],
            c->Lb[2], (double*)nullptr);
     LAUNCH(PFD_PROF_NODAL, k_u_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_U), c->Lb[1], c->Lb[2], c->bm_open,
-                       S[PFD_SRC_F1X], S[PFD_SRC_F1Y], S[PFD_SRC_WX], S[PFD_SRC_WY], H(F_UX, 0), H(F_UX, -1),
-                       H(F_UY, 0), H(F_UY, -1), BB(PFD_FAM_U), BB(PFD_FAM_U) + tot, c->r, c->r + tot,
-                       c->fld[F_UX][nw], c->fld[F_UY][nw]);
-    solve(c, PFD_FAM_U, BB(PFD_FAM_U), c->fld[F_UX][nw], 2, 0, rr);   // both components as one stack
+                       S[PFD_SRC_F1X], S[PFD_SRC_F1Y], S[PFD_SRC_WX], S[PFD_SRC_WY], H(PFD_FAM_U, F_UX, 0),
+                       H(PFD_FAM_U, F_UX, -1), H(PFD_FAM_U, F_UY, 0), H(PFD_FAM_U, F_UY, -1), BB(PFD_FAM_U),
+                       BB(PFD_FAM_U) + tot, c->r, c->r + tot, c->fld[F_UX][nw], c->fld[F_UY][nw]);
+    // both components as one stack
+    solve(c, PFD_FAM_U, BB(PFD_FAM_U), c->fld[F_UX][nw], 2, 0, RR(PFD_FAM_U), !W(PFD_FAM_U));
   }
   LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot,
          (const double*)c->fld[F_PHI][nw], equilibrium ? (const double*)nullptr : (const double*)c->fld[F_UX][nw],
@@ -3507,17 +3724,17 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
   const dim3 ng(nblk(tot)), nb(WG);
   hipStream_t st = c->stream;
   const int nw = 1 - c->cur;
-  const bool warm = c->prob.precision == PFD_REFINED_FP32;
-  auto H = [&](int f, int lv) -> const double* { return warm ? SPEC(f, lv) : nullptr; };
-  double* r0 = warm ? nullptr : c->r;
+  auto W = [&](int fam) { return warm_start(c, fam); };
+  auto H = [&](int fam, int f, int lv) -> const double* { return W(fam) ? SPEC(f, lv) : nullptr; };
   // right sides per family and level, recycled for the refined path's first residual (as in 2D)
+  auto REC = [&](int fam) { return W(fam) && c->rec_on; };
   auto BB = [&](int f) { return c->bh[f][nw]; };
   auto LR = [&](int f, int comp) {
     Lift L = c->lift[f];
-    L.bprev = c->rec_on ? c->bh[f][c->cur] + comp * tot : nullptr;
+    L.bprev = REC(f) ? c->bh[f][c->cur] + comp * tot : nullptr;
     return L;
   };
-  double* rr = (warm && c->rec_on) ? c->r : r0;
+  auto RR = [&](int f) -> double* { return (!W(f) || REC(f)) ? c->r : nullptr; };
   double* const* S = c->src;
   double **ph = c->ph, **sp = c->sp, **dz = c->dz, **Lb = c->Lb;
   refresh_spectral_sources(c);
@@ -3546,9 +3763,9 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
   const double* ph01[2] = {ph[0], ph[1]};
   ztrans_n(c, 2, Wff, ph01, sp);
   LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_V, 0), sp[0], sp[1], 0, 1.0 / P.eps0,
-         (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_VD], H(F_V, 0), H(F_V, -1),
-         BB(PFD_FAM_V), c->r, c->spec[F_V][nw]);
-  solve(c, PFD_FAM_V, BB(PFD_FAM_V), c->spec[F_V][nw], 1, 0, rr);
+         (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_VD], H(PFD_FAM_V, F_V, 0),
+         H(PFD_FAM_V, F_V, -1), BB(PFD_FAM_V), c->r, c->spec[F_V][nw]);
+  solve(c, PFD_FAM_V, BB(PFD_FAM_V), c->spec[F_V][nw], 1, 0, RR(PFD_FAM_V), !W(PFD_FAM_V));
   {
     // V and E_z = i beta V (reading R-Ez) from the new spectrum in one launch
     const double* ins[2] = {c->spec[F_V][nw], c->spec[F_V][nw]};
@@ -3573,17 +3790,17 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
          S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), E2, ph[0], ph[1], c->U, c->Q2);
   ztrans_n(c, 2, Wff, ph01, sp);  // sp[1] = (M Q2)_hat, kept for Phi_hat below
   LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_PSI, 0), sp[0], sp[1], 1, 1.0,
-         (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, (const double*)nullptr, H(F_PSI, 0),
-         H(F_PSI, -1), BB(PFD_FAM_PSI), c->r, c->spec[F_PSI][nw]);
-  solve(c, PFD_FAM_PSI, BB(PFD_FAM_PSI), c->spec[F_PSI][nw], 1, 0, rr);
+         (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, (const double*)nullptr,
+         H(PFD_FAM_PSI, F_PSI, 0), H(PFD_FAM_PSI, F_PSI, -1), BB(PFD_FAM_PSI), c->r, c->spec[F_PSI][nw]);
+  solve(c, PFD_FAM_PSI, BB(PFD_FAM_PSI), c->spec[F_PSI][nw], 1, 0, RR(PFD_FAM_PSI), !W(PFD_FAM_PSI));
   ztrans(c, c->Wi, c->spec[F_PSI][nw], c->fld[F_PSI][nw]);
   // ---- phi (eq. 76, reading R-psi)
   LAUNCH(PFD_PROF_NODAL, k_phi_bnd3, ng, nb, 0, st, g, c->bm_open, c->bm_wall, S[PFD_SRC_G2], c->U, ph[0]);
   ztrans(c, c->Wf, ph[0], sp[0]);
   LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_PHI, 0), sp[0], (const double*)nullptr, 0,
          1.0, (const double*)c->spec[F_PSI][nw], -1.0, c->Mdiag, c->d_beta2, c->d_betad, (const double*)nullptr,
-         H(F_PHI, 0), H(F_PHI, -1), BB(PFD_FAM_PHI), c->r, c->spec[F_PHI][nw]);
-  solve(c, PFD_FAM_PHI, BB(PFD_FAM_PHI), c->spec[F_PHI][nw], 1, 0, rr);
+         H(PFD_FAM_PHI, F_PHI, 0), H(PFD_FAM_PHI, F_PHI, -1), BB(PFD_FAM_PHI), c->r, c->spec[F_PHI][nw]);
+  solve(c, PFD_FAM_PHI, BB(PFD_FAM_PHI), c->spec[F_PHI][nw], 1, 0, RR(PFD_FAM_PHI), !W(PFD_FAM_PHI));
   {
     // phi, and its z-derivative for the momentum terms
     const double* ins[2] = {c->spec[F_PHI][nw], c->spec[F_PHI][nw]};
@@ -3610,9 +3827,9 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
            ph[1]);
     ztrans_n(c, 2, Wff, ph01, sp);
     LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_P, 0), sp[0], sp[1], 0, 1.0,
-           (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_F2], H(F_P, 0),
-           H(F_P, -1), BB(PFD_FAM_P), c->r, c->spec[F_P][nw]);
-    solve(c, PFD_FAM_P, BB(PFD_FAM_P), c->spec[F_P][nw], 1, 0, rr);
+           (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_F2],
+           H(PFD_FAM_P, F_P, 0), H(PFD_FAM_P, F_P, -1), BB(PFD_FAM_P), c->r, c->spec[F_P][nw]);
+    solve(c, PFD_FAM_P, BB(PFD_FAM_P), c->spec[F_P][nw], 1, 0, RR(PFD_FAM_P), !W(PFD_FAM_P));
     {
       const double* ins[2] = {c->spec[F_P][nw], c->spec[F_P][nw]};
       double* outs[2] = {c->fld[F_P][nw], dz[0]};
@@ -3633,9 +3850,10 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
     const double* As[3] = {sp[0], sp[2], sp[4]};
     for (int i = 0; i < 3; ++i)
       LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_U, i), As[i], Bs[i], 0, 1.0,
-             (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[ws[i]], H(uf[i], 0),
-             H(uf[i], -1), BB(PFD_FAM_U) + i * tot, c->r + i * tot, c->spec[uf[i]][nw]);
-    solve(c, PFD_FAM_U, BB(PFD_FAM_U), c->spec[F_UX][nw], 3, 0, rr);   // one stack of 3
+             (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[ws[i]],
+             H(PFD_FAM_U, uf[i], 0), H(PFD_FAM_U, uf[i], -1), BB(PFD_FAM_U) + i * tot, c->r + i * tot,
+             c->spec[uf[i]][nw]);
+    solve(c, PFD_FAM_U, BB(PFD_FAM_U), c->spec[F_UX][nw], 3, 0, RR(PFD_FAM_U), !W(PFD_FAM_U));   // one stack
     {
       const double* ins[3] = {c->spec[F_UX][nw], c->spec[F_UY][nw], c->spec[F_UZ][nw]};
       double* outs[3] = {c->fld[F_UX][nw], c->fld[F_UY][nw], c->fld[F_UZ][nw]};
@@ -3659,7 +3877,7 @@ hipError_t potential_iteration_3d(pfd_ctx* c, const double* Vin, double* Vout) {
   const long tot = (long)c->planes * c->Ng;
   const dim3 ng(nblk(tot)), nb(WG);
   hipStream_t st = c->stream;
-  const bool warm = c->prob.precision == PFD_REFINED_FP32;
+  const bool warm = warm_start(c, PFD_FAM_V);
   double **ph = c->ph, **sp = c->sp, **dz = c->dz;
   refresh_spectral_sources(c);
   const double* phn = FLD(F_PHI, 0);
@@ -3676,7 +3894,7 @@ hipError_t potential_iteration_3d(pfd_ctx* c, const double* Vin, double* Vout) {
   LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_V], sp[0], sp[1], 0, 1.0 / P.eps0,
          (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_VD],
          warm ? (const double*)sp[2] : nullptr, (const double*)sp[2], c->b[0], c->r, Vh);
-  hipError_t e = solve(c, PFD_FAM_V, c->b[0], Vh, 1, 0, warm ? nullptr : c->r);
+  hipError_t e = solve(c, PFD_FAM_V, c->b[0], Vh, 1, 0, warm ? nullptr : c->r, !warm);
   ztrans(c, c->Wi, Vh, Vout);
   return e != hipSuccess ? e : hipGetLastError();
 }

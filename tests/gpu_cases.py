@@ -12,7 +12,7 @@ def params_dict(par):
                 theta_s_deg=par.theta_s_deg, dt=par.dt, bdf=par.bdf, S=par.S, nu_m=par.nu_m)
 
 
-def gpu_context(mesh, par, bc, nbatch=1, precision=0, refine_iters=0, nz=0, lz=0.0):
+def gpu_context(mesh, par, bc, nbatch=1, precision=0, refine_max=0, nz=0, lz=0.0, refine_tol=0.0):
     import paper_2305_09020_amd as pfd
     st = [pfd.WALL] * 4
     for s, typ in bc.side.items():
@@ -20,7 +20,8 @@ def gpu_context(mesh, par, bc, nbatch=1, precision=0, refine_iters=0, nz=0, lz=0
     pdir = [1 if s in bc.pot_sides else 0 for s in range(4)]
     prob = pfd.make_problem(mesh.xb, mesh.yb, mesh.K, params_dict(par), st, pdir,
                             periodic_x=mesh.periodic_x, nbatch=nbatch, nz=nz, lz=lz, precision=precision,
-                            refine_iters=refine_iters, electrodes=bc.electrodes)
+                            refine_max=refine_max, refine_tol=refine_tol,
+                            electrodes=bc.electrodes)
     return pfd.Context(prob)
 
 

@@ -35,7 +35,7 @@ def _instance(n, K, vtop, eps_ratio, precision, nz=0, tune_from=None):
     else:
         m = Mesh2D(xb, xb, K)
         bc = BCs(side={BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}, pot_sides=(BOTTOM, TOP))
-    ctx = gpu_context(m, par, bc, precision=precision, refine_iters=2, nz=nz, lz=1.0 if nz else 0.0)
+    ctx = gpu_context(m, par, bc, precision=precision, nz=nz, lz=1.0 if nz else 0.0)
     if tune_from is not None:   # before the initial potential, which the kernels also compute
         _pin(ctx, tune_from)
     planes = max(nz, 1)

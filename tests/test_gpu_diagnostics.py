@@ -118,7 +118,7 @@ def test_march_to_equilibrium_matches_oracle(precision, tol):
     sch.init_potential(src)
     n_ref, hist = sch.march_to_equilibrium(src, 1e-6, 2000)
     assert hist[-1] <= 1e-6
-    ctx = gpu_context(m, par, bc, precision=precision, refine_iters=2)
+    ctx = gpu_context(m, par, bc, precision=precision)
     ctx.set_field("phi", phi0.reshape(1, m.Ny, m.Nx))
     ctx.set_sources({"Vd": src["Vd"].reshape(1, m.Ny, m.Nx)})
     ctx.init_potential(tol=1e-13, max_iter=100)

@@ -31,7 +31,7 @@ def _pair(nz, precision, electrodes=()):
         m = Mesh2D(xb, xb, 6)
         bc = BCs(side={BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}, pot_sides=(BOTTOM, TOP))
     par = c1_params()
-    ctxs = [gpu_context(m, par, bc, precision=precision, refine_iters=2, nz=nz, lz=1.5 if nz else 0.0)
+    ctxs = [gpu_context(m, par, bc, precision=precision, nz=nz, lz=1.5 if nz else 0.0)
             for _ in range(2)]
     # the autotuner may pick different kernels for the two contexts (timing noise): pin the
     # second to the first's choice so that both run the same kernels in the same order

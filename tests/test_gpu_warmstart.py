@@ -152,7 +152,7 @@ def test_warm_start_reduces_equilibrium_steps():
     eta, dt, tol = 0.05, 5e-5, 1e-7
     base = c5_param_dict(10.0, 90.0, dt=dt, eta=eta)
     prob = pfd.make_problem(xb, yb, K, base, [pfd.WALL, pfd.OPEN, pfd.WALL, pfd.WALL], [0, 0, 0, 0],
-                            periodic_x=True, precision=pfd.REFINED_FP32, refine_iters=2,
+                            periodic_x=True, precision=pfd.REFINED_FP32,
                             electrodes=[(a, b) for a, b, _ in el])
     ctx = pfd.Context(prob)
     ctx.set_graph(True)
