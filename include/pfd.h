@@ -456,6 +456,17 @@ pfd_status pfd_solve(pfd_ctx* ctx, int fam, const double* b, double* x);
 /* y = (K + (c_f + beta_p^2) M) x on every plane (device arrays). */
 pfd_status pfd_apply(pfd_ctx* ctx, int fam, const double* x, double* y);
 
+/* pfd_solve for callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid allocation): the same kernels in the same order (the
+ * result equals pfd_solve's), with the solve's scratch (residual, fast-diagonalisation
+ * intermediates, refinement test sums and gate, electrode gap buffers) taken from one static
+ * device array of 64 MiB that the library holds on every device until the process ends,
+ * instead of the context's workspace.  Allocates nothing.  The context's device must be
+ * current.  PFD_ENOMEM (message with the bytes needed) when the context's planes * Nx * Ny
+ * exceeds what the array holds (about 10 doubles per node: 838,000 nodes).  Every call on a
+ * device shares the array: calls that overlap on one device race; serialise them. */
+pfd_status pfd_solve_static(pfd_ctx* ctx, int fam, const double* b, double* x);
+
 /* Kernel classes timed by pfd_profile_read */
 enum {
   PFD_PROF_GEMM64 = 0,   /* fast-diagonalisation GEMM passes, FP64 (MFMA)          */

@@ -138,6 +138,7 @@ _sig = {
     "pfd_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "pfd_step_async": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "pfd_solve": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
+    "pfd_solve_static": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
     "pfd_apply": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
     "pfd_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pfd_profile_replay": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
@@ -284,6 +285,10 @@ class Context:
     def solve(self, fam, b, x):
         """Device tensors b, x (float64, planes*Ny*Nx); x: guess + Dirichlet values in, solution out."""
         _check(_lib.pfd_solve(self.h, fam, _vp(b.data_ptr()), _vp(x.data_ptr())), self.h)
+
+    def solve_static(self, fam, b, x):
+        """solve() with the scratch from the library's static device array (no allocation)."""
+        _check(_lib.pfd_solve_static(self.h, fam, _vp(b.data_ptr()), _vp(x.data_ptr())), self.h)
 
     def apply(self, fam, x, y):
         _check(_lib.pfd_apply(self.h, fam, _vp(x.data_ptr()), _vp(y.data_ptr())), self.h)

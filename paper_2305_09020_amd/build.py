@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpfd.so")
-SOURCES = ["pfd_setup.cpp", "pfd_api.cpp", "pfd_kernels.hip", "pfd_batch.cpp", "pfd_ws.hip"]
+SOURCES = ["pfd_setup.cpp", "pfd_api.cpp", "pfd_kernels.hip", "pfd_batch.cpp", "pfd_ws.hip", "pfd_static.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -172,6 +172,7 @@ extern "C" pfd_status pfd_create(const pfd_problem* prob, void* dev_ws, size_t d
   c->prob.mesh.xb = nullptr;  // host pointers are not kept
   c->prob.mesh.yb = nullptr;
   c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
   c->ws = (char*)dev_ws;
   c->ws_bytes = dev_bytes;
   c->Nx = L.Nx; c->Ny = L.Ny; c->planes = L.planes; c->is3d = L.is3d;

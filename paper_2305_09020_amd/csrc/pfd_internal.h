@@ -94,6 +94,7 @@ struct pfd_ctx {
   pfd_problem prob;
   std::string err;
   hipStream_t stream = nullptr;
+  int device = 0;                          // current device at pfd_create
   int Nx = 0, Ny = 0, planes = 0, is3d = 0;
   long Ng = 0, Nl = 0;
   int K = 0, n = 0, nq = 0;
