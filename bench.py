@@ -1,35 +1,37 @@
 #!/usr/bin/env python3
-"""Throughput of the decoupled phase-field step (Algorithm 1) on one MI355X.
+"""Throughput of the decoupled phase-field step (Algorithms 1 and 2) on one MI355X.
 
-Workload (the benchmark configuration of the 2D larger case): [0,1]^2, 20x20
-spectral elements of order 8 (161 x 161 = 25,921 grid points per instance), a
-sessile drop (half disc r = 0.25 at (0.5, 0), tanh profile eta = 0.01, contact
-angle 90 deg), density ratio 1000, viscosity ratio 100, permittivity ratio 40,
-closed box, V = 0 at the bottom and V_top in {0, 0.5, 1, 2} at the top: the four
-voltages run as four instances of one context, dt = 5e-5.  Inputs are
-synthetic and seeded (synth module); no dataset is involved.
+Default workload (the 2D benchmark configuration): [0,1]^2, 20x20 spectral elements of
+order 8 (161 x 161 = 25,921 grid points per instance), a sessile drop (half disc r = 0.25
+at (0.5, 0), tanh profile eta = 0.01, contact angle 90 deg), density ratio 1000, viscosity
+ratio 100, permittivity ratio 40, closed box, V = 0 at the bottom and V_top in
+{0, 0.5, 1, 2} at the top as four instances of one context, dt = 5e-5.  Inputs are
+synthetic and seeded (synth module); no dataset is involved.  Other workloads:
+--workload c1 (4x4 elements, order 6), c3 (3D, 16x16 elements of order 8 x 128 Fourier
+planes), c4 (64 uneven 2D instances in one batch), c5 (equilibrium march with the learned
+warm start).
 
-Metric: DOF-steps/s = (grid points x instances) x steps / wall time of the
-step loop (HIP events on the library's stream, inputs resident in HBM).  The
-FP32-refined path (FP32 fast-diagonalisation solves + FP64 residual iterative
-refinement) is the reported value; the plain FP64 path is timed beside it.
+Metric: DOF-steps/s = (grid points x instances or planes) x steps / time of the step loop
+(HIP events on the library's stream around the graph replays, inputs resident in HBM; the
+median of three timed repeats).  The FP32-refined path (FP32 fast-diagonalisation
+corrections + FP64 residual iterative refinement to its stop rule) is the reported value;
+the plain FP64 path is timed beside it.
 
 One JSON line is printed.  Extra keys:
-  roofline      the dominant kernel class of the reported path, from HIP events the
-                library records on its own stream around every launch during a second
-                run of the same steps (pfd_profile_enable / pfd_profile_read):
-                  fast-diagonalisation GEMM passes: algorithmic flops per launch
-                    = Ny*Nx*(Nx+Ny)*planes (mean of the four passes 2*Ny*Nx*K*planes),
-                    against the dense MFMA peak of their precision;
-                  residual: algorithmic bytes per launch = 24*planes*Ny*Nx (read b, x;
-                    write r), against HBM bandwidth;
-  cpu_baseline  the FP64 oracle (NumPy/SciPy) on a bounded sample of the same
-                workload (one instance, some steps after its one-time LU set-up).
+  roofline      the whole step as one graph launch against HBM bandwidth: algorithmic bytes
+                per step B_alg = F x 8 B x DOF with F the FP64 field passes the method needs
+                (38 for the 2D full model, 46 for 3D, 16 for the equilibrium system), over the
+                measured step time; traffic = HBM bytes per step from the rocprofv3
+                FETCH_SIZE / WRITE_SIZE summary in profiles/ (while the kernel sources match
+                it), plus the per-class split of the step (instrumented run).
+  refinement    corrections per solve family and the last backward error of the refined path.
+  cpu_baseline  the FP64 oracle (NumPy/SciPy) on a bounded sample of the same workload.
 """
 import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -38,148 +40,282 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from synth import (C2, C3, C4, C5, c2_param_dict, c3_param_dict, c3_phi0, c4_instances,  # noqa: E402
-                   c4_param_dict, c5_electrodes, c5_param_dict, c5_samples, c5_vd, drop_field)
+from synth import (C1, C2, C3, C4, C5, c1_param_dict, c2_param_dict, c3_param_dict, c3_phi0,  # noqa: E402
+                   c4_instances, c4_param_dict, c5_electrodes, c5_param_dict, c5_samples, c5_vd, drop_field)
 
 VTOP = (0.0, 0.5, 1.0, 2.0)
+HBM_PEAK_GBS = 8000.0
+FAMILIES = ("V", "psi", "phi", "P", "u")
 
 
-def make_context_c3(precision, refine_max):
-    """3D workload: 16x16 elements, K = 8, 128 Fourier planes, perturbed sphere."""
-    import paper_2305_09020_amd as pfd
-    xb = np.linspace(0.0, 1.0, C3["nx"] + 1)
-    prob = pfd.make_problem(xb, xb, C3["K"], c3_param_dict(), [pfd.WALL] * 4, [1, 1, 0, 0],
-                            nz=C3["nz"], lz=C3["lz"], precision=precision, refine_max=refine_max)
-    ctx = pfd.Context(prob)
-    x, y, z = ctx.coords()
-    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
-    ctx.set_field("phi", c3_phi0(X, Y, Z))
-    ctx.set_source("Vd", np.where(np.isclose(Y, 1.0), 1.0, 0.0))
-    its = ctx.init_potential(tol=1e-12, max_iter=20000)
-    return ctx, its
+class Run:
+    """One benchmark workload on the GPU: a context (or a batch of contexts) on one stream."""
 
-
-def make_context(precision, refine_max, workload="c2"):
-    import paper_2305_09020_amd as pfd
-    if workload == "c3":
-        return make_context_c3(precision, refine_max)
-    xb = np.linspace(0.0, 1.0, C2["nx"] + 1)
-    prob = pfd.make_problem(xb, xb, C2["K"], c2_param_dict(), [pfd.WALL] * 4, [1, 1, 0, 0],
-                            nbatch=len(VTOP), precision=precision, refine_max=refine_max)
-    ctx = pfd.Context(prob)
-    x, y, _ = ctx.coords()
-    X, Y = np.meshgrid(x, y)
-    phi = drop_field(X, Y, C2["center"], C2["r"], c2_param_dict()["eta"])
-    ctx.set_field("phi", np.stack([phi] * len(VTOP)))
-    vd = np.stack([np.where(np.isclose(Y, 1.0), v, 0.0) for v in VTOP])
-    ctx.set_source("Vd", vd)
-    its = ctx.init_potential(tol=1e-12, max_iter=20000)
-    return ctx, its
-
-
-class C4Run:
-    """The batched workload: 64 independent 2D instances (n x n elements, n in 8..24, order
-    4..10, seeded) on one stream, stepped through one hipGraph launch per step."""
-
-    def __init__(self, precision, refine_max):
-        import torch
-        import paper_2305_09020_amd as pfd
-        self.ctxs = []
-        self.stream = torch.cuda.current_stream()
-        for inst in c4_instances():
-            xb = np.linspace(0.0, 1.0, inst["n"] + 1)
-            par = c4_param_dict(inst["eps_ratio"])
-            prob = pfd.make_problem(xb, xb, inst["K"], par, [pfd.WALL] * 4, [1, 1, 0, 0],
-                                    precision=precision, refine_max=refine_max)
-            ctx = pfd.Context(prob, stream=self.stream)
-            x, y, _ = ctx.coords()
-            X, Y = np.meshgrid(x, y)
-            ctx.set_field("phi", drop_field(X, Y, C4["center"], C4["r"], par["eta"])[None])
-            ctx.set_source("Vd", np.where(np.isclose(Y, 1.0), inst["vtop"], 0.0)[None])
-            ctx.init_potential(tol=1e-12, max_iter=20000)
-            self.ctxs.append(ctx)
-        self.batch = pfd.Batch(self.ctxs, nlanes=4)
-        self.dof = sum(c.planes * c.Nx * c.Ny for c in self.ctxs)
+    def __init__(self, ctxs, dof, F, desc, batch=None, equilibrium=False):
+        self.ctxs = ctxs
+        self.ctx = ctxs[0]
+        self.stream = self.ctx.stream
+        self.dof = dof
+        self.F = F
+        self.desc = desc
+        self.batch = batch
+        self.equilibrium = equilibrium
 
     def step(self, n):
-        self.batch.step(n)
+        if self.batch is not None:
+            self.batch.step(n, self.equilibrium)
+        else:
+            self.ctx.step(n, self.equilibrium)
 
-    step_async = step
+    def step_async(self, n):
+        if self.batch is not None:
+            self.batch.step(n, self.equilibrium)
+        else:
+            self.ctx.step_async(n, self.equilibrium)
 
-    def diag(self):
-        return dict(nonfinite=max(c.diag()["nonfinite"] for c in self.ctxs))
+    def nonfinite(self):
+        return max(c.diag()["nonfinite"] for c in self.ctxs)
 
 
-def roofline_c4(run, steps):
-    """Dominant class over all instances: per-instance launch counts from an instrumented run
-    (instances stepped by plain launches), per-instance average launch time from back-to-back
-    replays; achieved = sum(launches x algorithmic flops or bytes) / sum(launches x time)."""
+def _ctx2d(pfd, n, K, par, vtops, center, r, precision, stream=None):
+    xb = np.linspace(0.0, 1.0, n + 1)
+    prob = pfd.make_problem(xb, xb, K, par, [pfd.WALL] * 4, [1, 1, 0, 0], nbatch=len(vtops),
+                            precision=precision)
+    ctx = pfd.Context(prob, stream=stream)
+    x, y, _ = ctx.coords()
+    X, Y = np.meshgrid(x, y)
+    phi = drop_field(X, Y, center, r, par["eta"])
+    ctx.set_field("phi", np.stack([phi] * len(vtops)))
+    ctx.set_source("Vd", np.stack([np.where(np.isclose(Y, 1.0), v, 0.0) for v in vtops]))
+    ctx.init_potential(tol=1e-14, max_iter=20000)
+    return ctx
+
+
+def build_workload(name, precision, graph=True):
+    """The GPU side of a workload (contexts built, initial potential solved)."""
+    import torch
+    import paper_2305_09020_amd as pfd
+    if name == "c1":
+        ctx = _ctx2d(pfd, C1["nx"], C1["K"], c1_param_dict(), C1["vtop"], C1["center"], C1["r"], precision)
+        ctx.set_graph(graph)
+        return Run([ctx], ctx.planes * ctx.Nx * ctx.Ny, 38,
+                   "2D drop, 4x4 elements order 6 (625 points), rho 1:2, mu 1:2, eps 1:4, V_top 1, "
+                   "dt 1e-4, closed box")
+    if name == "c2":
+        ctx = _ctx2d(pfd, C2["nx"], C2["K"], c2_param_dict(), VTOP, C2["center"], C2["r"], precision)
+        ctx.set_graph(graph)
+        return Run([ctx], ctx.planes * ctx.Nx * ctx.Ny, 38,
+                   "2D sessile drop, 20x20 elements order 8 (25,921 points), rho 1:1000, mu 1:100, "
+                   "eps 1:40, V_top {0,0.5,1,2} as 4 instances, dt 5e-5, closed box")
+    if name == "c3":
+        xb = np.linspace(0.0, 1.0, C3["nx"] + 1)
+        prob = pfd.make_problem(xb, xb, C3["K"], c3_param_dict(), [pfd.WALL] * 4, [1, 1, 0, 0],
+                                nz=C3["nz"], lz=C3["lz"], precision=precision)
+        ctx = pfd.Context(prob)
+        x, y, z = ctx.coords()
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        ctx.set_field("phi", c3_phi0(X, Y, Z))
+        ctx.set_source("Vd", np.where(np.isclose(Y, 1.0), 1.0, 0.0))
+        ctx.init_potential(tol=1e-12, max_iter=20000)
+        ctx.set_graph(graph)
+        return Run([ctx], ctx.planes * ctx.Nx * ctx.Ny, 46,
+                   "3D drop, 16x16 elements order 8 x 128 Fourier planes (Lz = 2, 2,130,048 points), "
+                   "perturbed sphere r = 0.3, rho 1:10, mu 1:2, eps 1:10, dt 1e-4, walls")
+    if name == "c4":
+        stream = torch.cuda.current_stream()
+        ctxs = []
+        for inst in c4_instances():
+            ctxs.append(_ctx2d(pfd, inst["n"], inst["K"], c4_param_dict(inst["eps_ratio"]), (inst["vtop"],),
+                               C4["center"], C4["r"], precision, stream=stream))
+        batch = pfd.Batch(ctxs, nlanes=4)
+        return Run(ctxs, sum(c.planes * c.Nx * c.Ny for c in ctxs), 38,
+                   "64 independent 2D drops in one batch (one hipGraph launch per step): n x n "
+                   "elements with n ~ U{8..24}, order ~ U{4..10}, V_top ~ U[0,2], eps ratio ~ "
+                   "U[1.5,40], seed 1, eta 0.02, dt 1e-4, closed boxes", batch=batch)
+    raise ValueError("unknown workload %s" % name)
+
+
+def time_steps(run, steps, warmup, repeats=3):
+    """Seconds for `steps` steps: median of `repeats` timed loops (HIP events on the
+    library's stream), after `warmup` untimed steps."""
+    import torch
+    run.step(warmup)
+    st = run.stream
+    ts = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        run.step_async(steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    if run.nonfinite():
+        raise RuntimeError("non-finite state during the timed steps")
+    return statistics.median(ts), ts
+
+
+def probe_copy_bandwidth():
+    """Device-to-device copy of 2 GiB (read + write 4 GiB moved): a measured HBM ceiling."""
+    import torch
+    a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 5 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    return gbs
+
+
+def _sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    cs = os.path.join(ROOT, "paper_2305_09020_amd", "csrc")
+    for f in sorted(os.listdir(cs)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            h.update(open(os.path.join(cs, f), "rb").read())
+    return h.hexdigest()
+
+
+def traffic(workload, path):
+    """HBM bytes per step and per launch of each kernel class from the committed rocprofv3
+    counter summary profiles/hbm_traffic_<workload>.txt (FETCH_SIZE and WRITE_SIZE passes over
+    the steady-state steps, scaled by what the counters read for a plain device copy), only
+    while the library sources hash to the value the counters were taken on; else None."""
+    f = os.path.join(ROOT, "profiles", "hbm_traffic_%s.txt" % workload)
+    if not os.path.exists(f):
+        return None, {}
+    sha = _sources_sha()
+    ok = False
+    step, per_class = None, {}
+    for line in open(f):
+        if line.startswith("# library sources sha256") and line.strip().endswith(sha):
+            ok = True
+        parts = line.split()
+        if not ok or len(parts) < 3 or parts[1] != path:
+            continue
+        if parts[0] == "step":
+            step = float(parts[2])
+        elif parts[0] == "class" and len(parts) == 4:
+            per_class[parts[2]] = float(parts[3])
+    return step, per_class
+
+
+def class_profile(run, steps):
+    """Per kernel class: share of the step's kernel time, launches per step and the average
+    launch (HIP events the library records around every launch during `steps` extra steps;
+    the instrumented steps run eagerly)."""
     for c in run.ctxs:
         c.profile_enable(True)
-    run.batch.step(steps)
-    profs = [c.profile_read() for c in run.ctxs]
-    for c in run.ctxs:
-        c.profile_enable(False)
+    run.step(steps)
     tot = {}
-    for p in profs:
-        for k, (ms, n) in p.items():
-            if n > 0:
+    for c in run.ctxs:
+        for k, (ms, n) in c.profile_read().items():
+            if n:
                 a = tot.setdefault(k, [0.0, 0])
                 a[0] += ms
                 a[1] += n
-    dom = max((k for k in tot if k in PEAK), key=lambda k: tot[k][0])
-    work = 0.0
-    time_s = 0.0
-    for c, p in zip(run.ctxs, profs):
-        n = p.get(dom, (0.0, 0))[1]
-        if n == 0:
-            continue
-        avg = c.profile_replay(dom, 50) * 1e-6
-        P, Nx, Ny = c.planes, c.Nx, c.Ny
-        if dom.startswith("gemm"):
-            per = float(Ny * Nx * (Nx + Ny) * P) * {0: 1.0, 1: 2.0, 2: 4.0 / 3.0}[c.solver_variant()[0]]
-        else:
-            per = float(24 * P * Nx * Ny)
-        work += n * per
-        time_s += n * avg
-    scale = 1e12 if dom.startswith("gemm") else 1e9
-    achieved = work / time_s / scale
-    peak = PEAK[dom][0] / scale
-    share = {k: round(v[0] / sum(x[0] for x in tot.values()), 4) for k, v in tot.items()}
-    return {"bound": PEAK[dom][2], "achieved": achieved, "peak": peak, "unit": PEAK[dom][1],
-            "frac": achieved / peak, "traffic": None, "kernel": dom,
-            "avg_launch_us": time_s / max(1, sum(p.get(dom, (0, 0))[1] for p in profs)) * 1e6,
-            "launches_per_step": tot[dom][1] / steps, "class_time_share": share,
-            "note": "all 64 instances; per-launch work differs per instance"}
+        c.profile_enable(False)
+    all_ms = sum(v[0] for v in tot.values())
+    return {k: {"share": round(v[0] / all_ms, 4), "launches_per_step": v[1] / steps,
+                "avg_launch_us": round(1e3 * v[0] / v[1], 3)} for k, v in sorted(tot.items(), key=lambda kv: -kv[1][0])}
 
 
-def cpu_baseline_c4(nsteps=10):
-    """The FP64 oracle on the first instance of the batched workload, a few steps after its
-    one-time sparse-LU factorisation."""
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
+def roofline(run, t_step, workload, path, classes, probe_gbs):
+    b_alg = float(run.F * 8 * run.dof)
+    achieved = b_alg / t_step / 1e9
+    step_traffic, class_traffic = traffic(workload, path)
+    for k, v in classes.items():
+        if k in class_traffic:
+            v["traffic_per_launch"] = class_traffic[k]
+            v["traffic_GBps"] = round(class_traffic[k] / (v["avg_launch_us"] * 1e-6) / 1e9, 1)
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "traffic": step_traffic, "kernel": "whole step (one hipGraph launch)",
+           "alg_bytes_per_step": b_alg, "field_passes_F": run.F, "dof": run.dof, "step_us": t_step * 1e6,
+           "traffic_over_alg": (step_traffic / b_alg) if step_traffic else None,
+           "probe_copy_GBps": probe_gbs, "frac_of_probe": achieved / probe_gbs if probe_gbs else None,
+           "classes": classes}
+    return out
+
+
+def refinement(run):
+    """Corrections per solve family of the last step and the most over the run (first
+    context), FP64-rung planes, the last backward error and condition estimates."""
+    st = run.ctx.refine_stats()
+    return {f: {"fp64_planes": s["n_fp64_planes"], "last_corrections": s["last_corrections"],
+                "max_corrections": s["max_corrections"], "failures": s["failures"],
+                "last_eta": s["last_eta"], "kappa": [s["kappa_min"], s["kappa_max"]]}
+            for f, s in zip(FAMILIES, st)}
+
+
+# ------------------------------------------------------------------ the oracle on the host
+def _oracle_run(workload):
+    """(scheme, source dict, dof) of one oracle instance of the workload, initial state set."""
     from oracle.sem import Mesh2D, BOTTOM, TOP, LEFT, RIGHT
     from oracle.scheme import Scheme, Params, BCs, WALL
-    inst = c4_instances()[0]
-    par = Params(**c4_param_dict(inst["eps_ratio"]))
-    xb = np.linspace(0.0, 1.0, inst["n"] + 1)
-    m = Mesh2D(xb, xb, inst["K"])
     bc = BCs(side={BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}, pot_sides=(BOTTOM, TOP))
-    sch = Scheme(m, par, bc)
-    sch.set_state(drop_field(m.X, m.Y, C4["center"], C4["r"], par.eta).ravel())
-    src = dict(Vd=np.where(np.isclose(m.Y.ravel(), 1.0), inst["vtop"], 0.0))
-    sch.init_potential(src)
-    t0 = time.perf_counter()
-    sch.step(src)
-    tset = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for _ in range(nsteps):
-        sch.step(src)
-    t = time.perf_counter() - t0
-    return dict(value=m.Ng * nsteps / t, unit="DOF-steps/s", cores=1, kind="oracle",
-                sample="instance 0 of the batch (%dx%d elements, K = %d), %d steps after the first; "
-                       "first step incl. sparse-LU set-up %.1f s excluded; single-threaded SciPy/NumPy "
-                       "(host has %d cores)" % (inst["n"], inst["n"], inst["K"], nsteps, tset,
-                                                os.cpu_count() or 0))
+    if workload in ("c1", "c2", "c4"):
+        if workload == "c4":
+            inst = c4_instances()[0]
+            n, K, pd, v, cen, r = inst["n"], inst["K"], c4_param_dict(inst["eps_ratio"]), inst["vtop"], C4["center"], C4["r"]
+        elif workload == "c2":
+            n, K, pd, v, cen, r = C2["nx"], C2["K"], c2_param_dict(), 1.0, C2["center"], C2["r"]
+        else:
+            n, K, pd, v, cen, r = C1["nx"], C1["K"], c1_param_dict(), 1.0, C1["center"], C1["r"]
+        par = Params(**pd)
+        xb = np.linspace(0.0, 1.0, n + 1)
+        m = Mesh2D(xb, xb, K)
+        sch = Scheme(m, par, bc)
+        sch.set_state(drop_field(m.X, m.Y, cen, r, par.eta).ravel())
+        src = dict(Vd=np.where(np.isclose(m.Y.ravel(), 1.0), v, 0.0))
+        sch.init_potential(src)
+        return sch, src, m.Ng, "one instance (V_top = %g) of the workload, %dx%d elements, K = %d" % (v, n, n, K)
+    par = Params(**c3_param_dict())
+    xb = np.linspace(0.0, 1.0, C3["nx"] + 1)
+    m = Mesh2D(xb, xb, C3["K"])
+    sch = Scheme(m, par, bc, Nz=C3["nz"], Lz=C3["lz"])
+    Z = np.broadcast_to(sch.z[:, None], (C3["nz"], m.Ng))
+    X = np.broadcast_to(m.X.ravel()[None, :], Z.shape)
+    Y = np.broadcast_to(m.Y.ravel()[None, :], Z.shape)
+    sch.set_state(c3_phi0(X, Y, Z))
+    src = dict(Vd=np.where(np.isclose(Y, 1.0), 1.0, 0.0))
+    sch.state["cur"]["V"] = np.array(Y)   # linear start V = y (the V0 fixed point is not timed)
+    sch.state["old"]["V"] = sch.state["cur"]["V"].copy()
+    return sch, src, m.Ng * C3["nz"], "the 3D workload at full size"
+
+
+def cpu_baseline(workload, nsteps):
+    """The FP64 oracle (sparse LU, NumPy element loops) on the host: `nsteps` steps after its
+    first (which includes the one-time LU factorisations, timed separately), once with the
+    BLAS / OpenMP pools held to one thread and once with all of them."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from threadpoolctl import threadpool_limits, threadpool_info
+    res = {}
+    for label, lim in (("one", 1), ("all", None)):
+        with threadpool_limits(limits=lim):
+            sch, src, dof, what = _oracle_run(workload)
+            t0 = time.perf_counter()
+            sch.step(src)
+            tset = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            for _ in range(nsteps):
+                sch.step(src)
+            res[label] = (dof * nsteps / (time.perf_counter() - t0), tset)
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return dict(value=res["one"][0], unit="DOF-steps/s", cores=1, kind="oracle",
+                value_all_threads=res["all"][0], threads_all=threads,
+                sample="%s, %d steps after the first (first step incl. sparse-LU set-up %.1f s excluded); "
+                       "SciPy SuperLU (sequential) and NumPy; value: BLAS pools at one thread; "
+                       "value_all_threads: pools at %d threads; host has %d cores"
+                       % (what, nsteps, res["one"][1], threads, os.cpu_count() or 0))
 
 
 def run_c5(a):
@@ -200,7 +336,7 @@ def run_c5(a):
     el = c5_electrodes()
     prob = pfd.make_problem(xb, yb, C5["K"], c5_param_dict(10.0, 90.0, dt=dt, eta=eta),
                             [pfd.WALL, pfd.OPEN, pfd.WALL, pfd.WALL], [0, 0, 0, 0], periodic_x=True,
-                            nz=C5["nz"], lz=C5["lz"], precision=pfd.REFINED_FP32, refine_max=a.refine_max,
+                            nz=C5["nz"], lz=C5["lz"], precision=pfd.REFINED_FP32,
                             electrodes=[(x0, x1) for x0, x1, _ in el])
     ctx = pfd.Context(prob)
     ctx.set_graph(not a.no_graph)
@@ -292,12 +428,16 @@ def run_c5(a):
         "value": value, "unit": "DOF-steps/s", "n_gpus": 1, "steps": int(stats["steps"]), "warmup": 0,
         "ms_per_step": 1e3 * stats["seconds"] / stats["steps"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "roofline": {"bound": "hbm", "achieved": 16 * 8 * dof * stats["steps"] / stats["seconds"] / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": 16 * 8 * dof * stats["steps"] / stats["seconds"] / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole equilibrium step (F = 16 field passes), host-synchronised march"},
         "config": {"workload": "3D equilibrium march with learned warm start: 12x12 elements order 6 x 64 "
                                "Fourier planes (336,384 points), x-periodic, open top, electrodes "
                                "(+V, gap, -V, gap) x 3, eta %g, dt %g, tol %g; V ~ U[0,2], eps ratio ~ "
                                "U[1.5,40], contact angle ~ U[60,120]; %d training / %d held-out problems"
                                % (eta, dt, tol, n_train, n_test),
-                   "dof_per_step": dof, "graph": not a.no_graph, "refine_max": a.refine_max},
+                   "dof_per_step": dof, "graph": not a.no_graph},
         "warm_start": {"train_samples": len(kept), "train_draws": n_train, "generation_s": t_gen, "train_steps": a.c5_train_steps,
                        "train_s": t_tr, "loss_first": float(hist[0]), "loss_last": float(np.mean(hist[-20:])),
                        "mean_steps_plain": float(sp.mean()), "mean_steps_warm": float(sw.mean()),
@@ -315,155 +455,21 @@ def run_c5(a):
     print(json.dumps(out_line), flush=True)
 
 
-def time_steps(ctx, steps, warmup):
-    import torch
-    ctx.step(warmup)
-    st = ctx.stream
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    ctx.step_async(steps)
-    e1.record(st)
-    torch.cuda.synchronize()
-    d = ctx.diag()
-    if d["nonfinite"]:
-        raise RuntimeError("non-finite state during the timed steps")
-    return e0.elapsed_time(e1) / 1e3
-
-
-PEAK = {"gemm64": (78.6e12, "TFLOP/s", "mfma"), "gemm32": (157.3e12, "TFLOP/s", "mfma"),
-        "residual": (8.0e12, "GB/s", "hbm")}
-
-
-def roofline(ctx, steps, workload="c2", path="refined"):
-    """Per-class kernel time over `steps` instrumented steps; roofline of the dominant
-    class among those with an algorithmic per-launch figure."""
-    ctx.profile_enable(True)
-    ctx.step_async(steps)
-    prof = ctx.profile_read()
-    ctx.profile_enable(False)
-    tot = {k: v for k, v in prof.items() if v[1] > 0}
-    dom = max((k for k in tot if k in PEAK), key=lambda k: tot[k][0])
-    ms, n = tot[dom]
-    avg = ctx.profile_replay(dom, 200) * 1e-6     # back-to-back replay, no per-launch events
-    avg_bracketed = ms / 1e3 / n
-    P, Nx, Ny = ctx.planes, ctx.Nx, ctx.Ny
-    variant, tune_us = ctx.solver_variant()
-    if dom.startswith("gemm"):
-        # four-pass variant: one GEMM pass per launch (mean 2*Ny*Nx*(Nx+Ny)/2 flops per plane);
-        # fused strip variant: two passes per launch; fused middle passes: four in three
-        per = float(Ny * Nx * (Nx + Ny) * P) * {0: 1.0, 1: 2.0, 2: 4.0 / 3.0}[variant]
-        achieved = per / avg / 1e12
-        peak = PEAK[dom][0] / 1e12
-    else:
-        per = float(24 * P * Nx * Ny)
-        achieved = per / avg / 1e9
-        peak = PEAK[dom][0] / 1e9
-    share = {k: round(v[0] / sum(x[0] for x in tot.values()), 4) for k, v in tot.items()}
-    return {"bound": PEAK[dom][2], "achieved": achieved, "peak": peak, "unit": PEAK[dom][1],
-            "frac": achieved / peak, "traffic": traffic(dom, workload, path), "kernel": dom,
-            "avg_launch_us": avg * 1e6, "avg_launch_us_event_bracketed": avg_bracketed * 1e6,
-            "launches_per_step": n / steps, "per_launch": per, "class_time_share": share,
-            "solver_variant": variant, "autotune_us_per_correction": tune_us,
-            "residual_variant": ctx.residual_variant()[0], "autotune_us_residual": ctx.residual_variant()[1],
-            "tuning": ctx.tuning(),
-            "gemm_tile_config_per_site": ctx.gemm_config()[0]}
-
-
-def traffic(dom, workload, path):
-    """HBM bytes per launch of the class from the committed rocprofv3 counter summary
-    profiles/hbm_traffic_<workload>.txt (FETCH_SIZE and WRITE_SIZE passes, scaled by a plain
-    copy), only while pfd_kernels.hip is the source the counters were taken on; else None."""
-    import hashlib
-    f = os.path.join(ROOT, "profiles", "hbm_traffic_%s.txt" % workload)
-    if not os.path.exists(f):
-        return None
-    src = os.path.join(ROOT, "paper_2305_09020_amd", "csrc", "pfd_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    ok = False
-    for line in open(f):
-        if line.startswith("# kernel source sha256") and line.strip().endswith(sha):
-            ok = True
-        parts = line.split()
-        if ok and len(parts) == 6 and parts[0] == path and parts[1] == dom:
-            return float(parts[5])
-    return None
-
-
-def cpu_baseline(nsteps=40):
-    """The FP64 oracle on one instance of the workload (V_top = 1): a few steps after
-    its one-time sparse-LU factorisation (timed separately, not included)."""
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from oracle.sem import Mesh2D, BOTTOM, TOP, LEFT, RIGHT
-    from oracle.scheme import Scheme, Params, BCs, WALL
-    par = Params(**c2_param_dict())
-    xb = np.linspace(0.0, 1.0, C2["nx"] + 1)
-    m = Mesh2D(xb, xb, C2["K"])
-    bc = BCs(side={BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}, pot_sides=(BOTTOM, TOP))
-    sch = Scheme(m, par, bc)
-    sch.set_state(drop_field(m.X, m.Y, C2["center"], C2["r"], par.eta).ravel())
-    src = dict(Vd=np.where(np.isclose(m.Y.ravel(), 1.0), 1.0, 0.0))
-    sch.init_potential(src)
-    t0 = time.perf_counter()
-    sch.step(src)                      # first step factorises the constant matrices
-    tset = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for _ in range(nsteps):
-        sch.step(src)
-    t = time.perf_counter() - t0
-    return dict(value=m.Ng * nsteps / t, unit="DOF-steps/s", cores=1, kind="oracle",
-                sample="one instance (V_top = 1) of the workload, %d steps after the first; "
-                       "first step incl. sparse-LU set-up %.1f s excluded; SciPy SuperLU and "
-                       "NumPy element loops run single-threaded (host has %d cores)"
-                       % (nsteps, tset, os.cpu_count() or 0))
-
-
-def cpu_baseline_c3(nsteps=1):
-    """The FP64 oracle on the 3D workload at full size: one step after its first (the
-    first includes the per-mode sparse-LU set-up, timed separately)."""
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from oracle.sem import Mesh2D, BOTTOM, TOP, LEFT, RIGHT
-    from oracle.scheme import Scheme, Params, BCs, WALL
-    par = Params(**c3_param_dict())
-    xb = np.linspace(0.0, 1.0, C3["nx"] + 1)
-    m = Mesh2D(xb, xb, C3["K"])
-    bc = BCs(side={BOTTOM: WALL, TOP: WALL, LEFT: WALL, RIGHT: WALL}, pot_sides=(BOTTOM, TOP))
-    sch = Scheme(m, par, bc, Nz=C3["nz"], Lz=C3["lz"])
-    Z = np.broadcast_to(sch.z[:, None], (C3["nz"], m.Ng))
-    X = np.broadcast_to(m.X.ravel()[None, :], Z.shape)
-    Y = np.broadcast_to(m.Y.ravel()[None, :], Z.shape)
-    sch.set_state(c3_phi0(X, Y, Z))
-    src = dict(Vd=np.where(np.isclose(Y, 1.0), 1.0, 0.0))
-    sch.state["cur"]["V"] = np.array(Y)   # linear start V = y (the V0 fixed point is not timed)
-    sch.state["old"]["V"] = sch.state["cur"]["V"].copy()
-    t0 = time.perf_counter()
-    sch.step(src)
-    tset = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for _ in range(nsteps):
-        sch.step(src)
-    t = time.perf_counter() - t0
-    dof = m.Ng * C3["nz"]
-    return dict(value=dof * nsteps / t, unit="DOF-steps/s", cores=1, kind="oracle",
-                sample="the 3D workload at full size, %d step(s) after the first; first step incl. "
-                       "per-mode sparse-LU set-up %.1f s excluded; single-threaded SciPy/NumPy "
-                       "(host has %d cores)" % (nsteps, tset, os.cpu_count() or 0))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
-                    help="c2: the 2D benchmark configuration (default); c3: the 3D configuration; "
-                         "c4: 64 uneven 2D instances in one batch; c5: equilibrium march with the "
-                         "learned warm start (about 10 minutes)")
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "c4", "c5"], default="c2",
+                    help="c2: the 2D benchmark configuration (default); c1: its small case; c3: the 3D "
+                         "configuration; c4: 64 uneven 2D instances in one batch; c5: equilibrium march "
+                         "with the learned warm start (about 10 minutes)")
     ap.add_argument("--c5-train", type=int, default=None, help="training equilibria for c5")
     ap.add_argument("--c5-train-steps", type=int, default=3000)
     ap.add_argument("--c5-test", type=int, default=None, help="held-out problems for c5")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--refine-max", type=int, default=0)
+    ap.add_argument("--repeats", type=int, default=3, help="timed loops; the median is reported")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the step kernels one by one instead of replaying a hipGraph")
@@ -472,8 +478,13 @@ def main():
                     help="only run a plain 256 MiB device copy 5 times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
     a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the step would shard by Fourier mode in 3D; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2305_09020_amd as pfd
     if a.calibrate_copy:
-        import torch
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(5):
@@ -481,88 +492,57 @@ def main():
         torch.cuda.synchronize()
         print("copied 5 x %d bytes" % (src.numel() * 8))
         return
-    if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the step would shard by Fourier mode in 3D; see the design notes)", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    import paper_2305_09020_amd as pfd
     torch.cuda.set_device(0)
     if a.workload == "c5":
         run_c5(a)
         return
     if a.steps is None:
-        a.steps = {"c2": C2["steps"], "c3": C3["steps"], "c4": C4["steps"]}[a.workload]
+        a.steps = {"c1": C1["steps"], "c2": C2["steps"], "c3": C3["steps"], "c4": C4["steps"]}[a.workload]
+    probe = probe_copy_bandwidth()
     res = {}
     for name, prec in (("refined", pfd.REFINED_FP32), ("fp64", pfd.PLAIN_FP64)):
         if a.only not in (name, "both"):
             continue
-        if a.workload == "c4":
-            ctx, its = C4Run(prec, a.refine_max), 0
-            t = time_steps(ctx, a.steps, a.warmup)
-            dof = ctx.dof
-            res[name] = dict(t=t, dof=dof, value=dof * a.steps / t, ctx=ctx,
-                             roofline=roofline_c4(ctx, 5))
-        else:
-            ctx, its = make_context(prec, a.refine_max, a.workload)
-            ctx.set_graph(not a.no_graph)
-            t = time_steps(ctx, a.steps, a.warmup)
-            dof = ctx.planes * ctx.Nx * ctx.Ny
-            res[name] = dict(t=t, dof=dof, value=dof * a.steps / t, ctx=ctx,
-                             roofline=roofline(ctx, min(a.steps, 200 if a.workload == "c2" else 20), a.workload, name))
-        print("# %-7s %.3f ms/step  %.4e DOF-steps/s  (V0 fixed point: %d iterations)"
-              % (name, 1e3 * t / a.steps, dof * a.steps / t, its), file=sys.stderr, flush=True)
+        run = build_workload(a.workload, prec, graph=not a.no_graph)
+        t, ts = time_steps(run, a.steps, a.warmup, a.repeats)
+        nprof = min(a.steps, 50 if a.workload in ("c1", "c2") else 10)
+        classes = class_profile(run, nprof)
+        res[name] = dict(t=t, ts=ts, run=run, value=run.dof * a.steps / t,
+                         roofline=roofline(run, t / a.steps, a.workload, name, classes, probe),
+                         refinement=refinement(run) if prec == pfd.REFINED_FP32 else None,
+                         nsteps=a.warmup + a.repeats * a.steps + nprof)
+        print("# %-7s %.3f ms/step  %.4e DOF-steps/s  (repeats: %s ms/step)"
+              % (name, 1e3 * t / a.steps, run.dof * a.steps / t,
+                 " ".join("%.3f" % (1e3 * x / a.steps) for x in ts)), file=sys.stderr, flush=True)
     main_name = "refined" if "refined" in res else "fp64"
     r = res[main_name]
     out = {
         "metric": "DOF-steps/s on 1 GPU, FP32-refined vs plain FP64 at 1e-8 rel err; % roofline",
-        "value": r["value"],
-        "unit": "DOF-steps/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": 1e3 * r["t"] / a.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64+f32" if main_name == "refined" else "f64",
-        "data": "synthetic",
-        "config": ({"workload": "2D sessile drop, 20x20 elements order 8 (25,921 points), "
-                                "rho 1:1000, mu 1:100, eps 1:40, V_top {0,0.5,1,2} as 4 instances, "
-                                "dt 5e-5, closed box; %s path" % main_name,
-                    "instances": len(VTOP), "dof_per_step": r["dof"], "graph": not a.no_graph,
-                    "refine_max": a.refine_max if main_name == "refined" else 0}
-                   if a.workload == "c2" else
-                   {"workload": "64 independent 2D drops in one batch (one hipGraph launch per step): "
-                                "n x n elements with n ~ U{8..24}, order ~ U{4..10}, V_top ~ U[0,2], "
-                                "eps ratio ~ U[1.5,40], seed 1, eta 0.02, dt 1e-4, closed boxes; "
-                                "%s path" % main_name,
-                    "instances": C4["n_inst"], "dof_per_step": r["dof"], "graph": True,
-                    "refine_max": a.refine_max if main_name == "refined" else 0}
-                   if a.workload == "c4" else
-                   {"workload": "3D drop, 16x16 elements order 8 x 128 Fourier planes (Lz = 2, "
-                                "2,130,048 points), perturbed sphere r = 0.3, rho 1:10, mu 1:2, "
-                                "eps 1:10, dt 1e-4, walls; %s path" % main_name,
-                    "instances": 1, "dof_per_step": r["dof"], "graph": not a.no_graph,
-                    "refine_max": a.refine_max if main_name == "refined" else 0}),
+        "value": r["value"], "unit": "DOF-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": 1e3 * r["t"] / a.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32" if main_name == "refined" else "f64", "data": "synthetic",
+        "config": {"workload": r["run"].desc + "; %s path" % main_name, "dof_per_step": r["run"].dof,
+                   "graph": not a.no_graph, "timed_repeats": a.repeats},
+        "roofline": r["roofline"],
     }
-    out["roofline"] = r["roofline"]
+    if r["refinement"]:
+        out["refinement"] = r["refinement"]
     if "fp64" in res and "refined" in res:
         out["fp64_value"] = res["fp64"]["value"]
+        out["fp64_ms_per_step"] = 1e3 * res["fp64"]["t"] / a.steps
         out["refined_over_fp64"] = res["refined"]["value"] / res["fp64"]["value"]
         out["fp64_roofline"] = res["fp64"]["roofline"]
-        if a.workload in ("c2", "c3"):
-            # both contexts started from the same state and took the same steps (warmup,
+        if a.workload != "c4":
+            # both contexts started from the same state and took the same steps (warm-up,
             # timed, instrumented): field-wise max |refined - fp64| / max |fp64|
-            n_cmp = a.warmup + a.steps + min(a.steps, 200 if a.workload == "c2" else 20)
             names = ("phi", "psi", "V", "P", "ux", "uy") + (("uz",) if a.workload == "c3" else ())
             errs = {}
             for k in names:
-                f, g = res["fp64"]["ctx"].get_field(k), res["refined"]["ctx"].get_field(k)
+                f, g = res["fp64"]["run"].ctx.get_field(k), res["refined"]["run"].ctx.get_field(k)
                 errs[k] = float(np.abs(g - f).max() / max(float(np.abs(f).max()), 1e-300))
-            out["refined_vs_fp64"] = {"steps": n_cmp, "max_rel_err": errs}
+            out["refined_vs_fp64"] = {"steps": res["refined"]["nsteps"], "max_rel_err": errs}
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = {"c2": cpu_baseline, "c3": cpu_baseline_c3, "c4": cpu_baseline_c4}[a.workload]()
+        out["cpu_baseline"] = cpu_baseline(a.workload, {"c1": 100, "c2": 40, "c3": 1, "c4": 10}[a.workload])
     print(json.dumps(out), flush=True)
 
 
