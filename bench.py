@@ -40,8 +40,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from synth import (C1, C2, C3, C4, C5, c1_param_dict, c2_param_dict, c3_param_dict, c3_phi0,  # noqa: E402
-                   c4_instances, c4_param_dict, c5_electrodes, c5_param_dict, c5_samples, c5_vd, drop_field)
+from synth import (C1, C2, C3, C4, C5, X6, c1_param_dict, c2_param_dict, c3_param_dict, c3_phi0,  # noqa: E402
+                   c4_instances, c4_param_dict, c5_electrodes, c5_param_dict, c5_samples, c5_vd, drop_field,
+                   x6_param_dict, x6_vd)
 
 VTOP = (0.0, 0.5, 1.0, 2.0)
 HBM_PEAK_GBS = 8000.0
@@ -132,6 +133,58 @@ def build_workload(name, precision, graph=True):
                    "64 independent 2D drops in one batch (one hipGraph launch per step): n x n "
                    "elements with n ~ U{8..24}, order ~ U{4..10}, V_top ~ U[0,2], eps ratio ~ "
                    "U[1.5,40], seed 1, eta 0.02, dt 1e-4, closed boxes", batch=batch)
+    if name == "x6":
+        par = x6_param_dict()
+        xb = np.linspace(0.0, X6["lx"], X6["nx"] + 1)
+        yb = np.linspace(0.0, X6["ly"], X6["ny"] + 1)
+        prob = pfd.make_problem(xb, yb, X6["K"], par, [pfd.WALL, pfd.OPEN, pfd.WALL, pfd.WALL], [0, 0, 0, 0],
+                                periodic_x=True, precision=precision,
+                                electrodes=[(a, b) for a, b, _ in X6["electrodes"]])
+        ctx = pfd.Context(prob)
+        x, y, _ = ctx.coords()
+        X, Y = np.meshgrid(x, y)
+        ctx.set_field("phi", drop_field(X, Y, X6["center"], X6["r"], par["eta"])[None])
+        ctx.set_source("Vd", x6_vd(X, Y)[None])
+        ctx.init_potential(tol=1e-14, max_iter=20000)
+        ctx.set_graph(graph)
+        return Run([ctx], ctx.planes * ctx.Nx * ctx.Ny, 38,
+                   "the paper's drop transport (Sec. 4.4.1): [0,1.6] x [0,0.5], 16x4 elements order 12 "
+                   "(9,408 points), x-periodic, open top, electrodes -V,+V,-V,+V on the left half of the "
+                   "bottom wall, semicircular drop r = 0.35 at (1.2, 0), Table 1 normalisation "
+                   "(rho 235.9:235.9, mu 1:2, eps 1:8.1, eta 0.01, dt 1e-6)")
+    if name in ("x3", "x4"):
+        from synth import X3, X4, x3_param_dict, x3_electrodes, x4_mesh_y, x4_param_dict, x4_phi0, electrode_vd
+        if name == "x3":
+            el = x3_electrodes()
+            prob = pfd.make_problem(np.linspace(0.0, X3["lx"], X3["nx"] + 1), np.array(X3["yb"]), X3["K"],
+                                    x3_param_dict(), [pfd.WALL, pfd.OPEN, pfd.WALL, pfd.WALL], [0, 0, 0, 0],
+                                    periodic_x=True, nz=X3["nz"], lz=X3["lz"], precision=precision,
+                                    electrodes=[(a, b) for a, b, _ in el])
+            ctx = pfd.Context(prob)
+            x, y, z = ctx.coords()
+            Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+            ctx.set_field("phi", drop_field(X, Y, X3["center"][:2], X3["r"], X3["eta"], Z=Z, zc=X3["center"][2]))
+            desc = ("the paper's 3D dielectric drop on an electrode array (Sec. 4.2), equilibrium system: "
+                    "[0,5/3] x [0,2/3] x [0,3.5), 20x6 elements order 12 x 120 Fourier planes (2,102,400 "
+                    "points), x-periodic, open top, ten electrodes alternating +-V0, hemisphere r = 0.5, "
+                    "eps 1:32, eta 0.02, dt 2e-6")
+        else:
+            el = X4["electrodes"]
+            prob = pfd.make_problem(np.linspace(0.0, X4["lx"], X4["nx"] + 1), x4_mesh_y(), X4["K"], x4_param_dict(),
+                                    [pfd.WALL, pfd.OPEN, pfd.WALL, pfd.WALL], [0, 0, 0, 0], periodic_x=True,
+                                    precision=precision, electrodes=[(a, b) for a, b, _ in el])
+            ctx = pfd.Context(prob)
+            x, y, _ = ctx.coords()
+            X, Y = np.meshgrid(x, y)
+            ctx.set_field("phi", x4_phi0(Y)[None])
+            X, Y = X[None], Y[None]
+            desc = ("the paper's dielectric film (Sec. 4.3), equilibrium system: [0,8] x [0,5], 16 x (5+4+4) "
+                    "elements order 12 (30,144 points), x-periodic, open top, electrodes at 0 and V0, flat "
+                    "film of thickness 1, eps 1:10, eta 0.01, S 2, dt 2e-6")
+        ctx.set_source("Vd", electrode_vd(X, Y, el))
+        ctx.init_potential(tol=1e-12, max_iter=20000)
+        ctx.set_graph(graph)
+        return Run([ctx], ctx.planes * ctx.Nx * ctx.Ny, 16, desc, equilibrium=True)
     raise ValueError("unknown workload %s" % name)
 
 
@@ -278,6 +331,17 @@ def _oracle_run(workload):
         src = dict(Vd=np.where(np.isclose(m.Y.ravel(), 1.0), v, 0.0))
         sch.init_potential(src)
         return sch, src, m.Ng, "one instance (V_top = %g) of the workload, %dx%d elements, K = %d" % (v, n, n, K)
+    if workload == "x6":
+        from oracle.scheme import OPEN
+        par = Params(**x6_param_dict())
+        m = Mesh2D(np.linspace(0.0, X6["lx"], X6["nx"] + 1), np.linspace(0.0, X6["ly"], X6["ny"] + 1), X6["K"],
+                   periodic_x=True)
+        bcx = BCs(side={BOTTOM: WALL, TOP: OPEN}, electrodes=[(a, b) for a, b, _ in X6["electrodes"]])
+        sch = Scheme(m, par, bcx)
+        sch.set_state(drop_field(m.X, m.Y, X6["center"], X6["r"], par.eta).ravel())
+        src = dict(Vd=x6_vd(m.X.ravel(), m.Y.ravel()))
+        sch.init_potential(src)
+        return sch, src, m.Ng, "the drop-transport workload at full size"
     par = Params(**c3_param_dict())
     xb = np.linspace(0.0, 1.0, C3["nx"] + 1)
     m = Mesh2D(xb, xb, C3["K"])
@@ -460,10 +524,11 @@ def run_c5(a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["c1", "c2", "c3", "c4", "c5"], default="c2",
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "c4", "c5", "x6", "x3", "x4"], default="c2",
                     help="c2: the 2D benchmark configuration (default); c1: its small case; c3: the 3D "
                          "configuration; c4: 64 uneven 2D instances in one batch; c5: equilibrium march "
-                         "with the learned warm start (about 10 minutes)")
+                         "with the learned warm start (about 10 minutes); x6: the paper's drop transport; x3, x4: "
+                         "the paper's 3D drop and 2D film equilibrium marches")
     ap.add_argument("--c5-train", type=int, default=None, help="training equilibria for c5")
     ap.add_argument("--c5-train-steps", type=int, default=3000)
     ap.add_argument("--c5-test", type=int, default=None, help="held-out problems for c5")
@@ -497,7 +562,8 @@ def main():
         run_c5(a)
         return
     if a.steps is None:
-        a.steps = {"c1": C1["steps"], "c2": C2["steps"], "c3": C3["steps"], "c4": C4["steps"]}[a.workload]
+        a.steps = {"c1": C1["steps"], "c2": C2["steps"], "c3": C3["steps"], "c4": C4["steps"],
+                   "x6": X6["steps"], "x3": 200, "x4": 500}[a.workload]
     probe = probe_copy_bandwidth()
     res = {}
     for name, prec in (("refined", pfd.REFINED_FP32), ("fp64", pfd.PLAIN_FP64)):
@@ -505,7 +571,7 @@ def main():
             continue
         run = build_workload(a.workload, prec, graph=not a.no_graph)
         t, ts = time_steps(run, a.steps, a.warmup, a.repeats)
-        nprof = min(a.steps, 50 if a.workload in ("c1", "c2") else 10)
+        nprof = min(a.steps, 50 if a.workload in ("c1", "c2", "x6", "x4") else 10)
         classes = class_profile(run, nprof)
         res[name] = dict(t=t, ts=ts, run=run, value=run.dof * a.steps / t,
                          roofline=roofline(run, t / a.steps, a.workload, name, classes, probe),
@@ -532,17 +598,18 @@ def main():
         out["fp64_ms_per_step"] = 1e3 * res["fp64"]["t"] / a.steps
         out["refined_over_fp64"] = res["refined"]["value"] / res["fp64"]["value"]
         out["fp64_roofline"] = res["fp64"]["roofline"]
-        if a.workload != "c4":
+        if a.workload not in ("c4",):
             # both contexts started from the same state and took the same steps (warm-up,
             # timed, instrumented): field-wise max |refined - fp64| / max |fp64|
-            names = ("phi", "psi", "V", "P", "ux", "uy") + (("uz",) if a.workload == "c3" else ())
+            names = ((("phi", "psi", "V") if a.workload in ("x3", "x4") else ("phi", "psi", "V", "P", "ux", "uy"))
+                     + (("uz",) if a.workload == "c3" else ()))
             errs = {}
             for k in names:
                 f, g = res["fp64"]["run"].ctx.get_field(k), res["refined"]["run"].ctx.get_field(k)
                 errs[k] = float(np.abs(g - f).max() / max(float(np.abs(f).max()), 1e-300))
             out["refined_vs_fp64"] = {"steps": res["refined"]["nsteps"], "max_rel_err": errs}
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(a.workload, {"c1": 100, "c2": 40, "c3": 1, "c4": 10}[a.workload])
+    if not a.no_cpu_baseline and a.workload not in ("x3", "x4"):
+        out["cpu_baseline"] = cpu_baseline(a.workload, {"c1": 100, "c2": 40, "c3": 1, "c4": 10, "x6": 60}[a.workload])
     print(json.dumps(out), flush=True)
 
 

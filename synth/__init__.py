@@ -174,3 +174,111 @@ def c5_vd(X, Y, V, electrodes, tol=1e-12):
     for (x0, x1, sgn) in electrodes:
         vd = np.where(bottom & (X >= x0 - tol) & (X <= x1 + tol), sgn * V, vd)
     return vd
+
+
+# ---- the paper's drop transport (Sec. 4.4.1): a dielectric drop pulled along a wall by an
+# electrode array, in the normalised units of its Table 1
+X6 = dict(name="X6", lx=1.6, ly=0.5, nx=16, ny=4, K=12, center=(1.2, 0.0), r=0.35, steps=2000,
+          # bottom-wall electrodes (x0, x1, sign of the voltage V0); the right half is bare
+          electrodes=((0.1, 0.2, -1.0), (0.3, 0.4, 1.0), (0.5, 0.6, -1.0), (0.7, 0.8, 1.0)),
+          # dimensional inputs of Sec. 4.4.1 (SI units)
+          L0=1e-3, V0=300.0, sigma=2.84e-2, rho=429.7, mu1=12.048e-4, eps_vac=8.854e-12,
+          eps_ratio=8.1, eta=0.01, gamma1=5e-6, dt=1e-6, theta=90.0)
+
+
+def x6_param_dict():
+    """Normalised parameters of the drop-transport run: lengths by L0, potentials by V0,
+    viscosities by mu1, permittivities by the vacuum value, densities by mu1^2/(eps V0^2),
+    lambda by eps V0^2, gamma1 by L0^2/mu1, time by L0^2 mu1/(eps V0^2) (Table 1)."""
+    L0, V0, mu0, e0 = X6["L0"], X6["V0"], X6["mu1"], X6["eps_vac"]
+    rho_n = mu0 ** 2 / (e0 * V0 ** 2)
+    lam = 3.0 / (2.0 * math.sqrt(2.0)) * X6["sigma"] * X6["eta"] * L0 / (e0 * V0 ** 2)
+    return dict(rho1=X6["rho"] / rho_n, rho2=X6["rho"] / rho_n, mu1=1.0, mu2=2.0, eps1=1.0,
+                eps2=X6["eps_ratio"], lam=lam, eta=X6["eta"], gamma1=X6["gamma1"],
+                theta_s_deg=X6["theta"], dt=X6["dt"])
+
+
+def x6_vd(X, Y, tol=1e-12):
+    """Electrode voltages (+-1 in units of V0) on the electrode nodes of the bottom row."""
+    vd = np.zeros_like(np.asarray(X, dtype=float))
+    bottom = np.isclose(Y, 0.0)
+    for (x0, x1, sgn) in X6["electrodes"]:
+        vd = np.where(bottom & (X >= x0 - tol) & (X <= x1 + tol), sgn, vd)
+    return vd
+
+
+# ---- the paper's 3D dielectric drop on an electrode array (Sec. 4.2), equilibrium system,
+# normalised as its Table 2 (lengths by L0 = 1.2 mm, potential by V0, permittivities by
+# L0 sigma / V0^2); the contact angle is not stated there: 90 deg (the initial hemisphere)
+X3 = dict(name="X3", lx=5.0 / 3.0, ly=2.0 / 3.0, lz=3.5, nx=20, ny=6, K=12, nz=120,
+          # six elements along y, finer at the wall where the drop and the field gradients sit
+          yb=(0.0, 0.04, 0.1, 0.18, 0.3, 0.46, 2.0 / 3.0),
+          center=(5.0 / 6.0, 0.0, 1.75), r=0.5, eta=0.02, lam_gamma1=0.1, dt=2e-6,
+          L0=1.2e-3, sigma=3.857e-2, eps_vac=8.854e-12, eps_ratio=32.0, V0=150.0, theta=90.0, steps=200)
+
+
+def x3_param_dict(V0=None):
+    """Equilibrium-system parameters of the 3D drop: eps1 = eps_vac V0^2 / (L0 sigma),
+    eps2 = 32 eps1, lambda = 3 sigma eta / (2 sqrt 2) with sigma = 1, lambda gamma1 = 0.1."""
+    V0 = X3["V0"] if V0 is None else V0
+    e1 = X3["eps_vac"] * V0 ** 2 / (X3["L0"] * X3["sigma"])
+    lam = lam_from_sigma(1.0, X3["eta"])
+    return dict(rho1=1.0, rho2=1.0, mu1=0.01, mu2=0.01, eps1=e1, eps2=X3["eps_ratio"] * e1, lam=lam,
+                eta=X3["eta"], gamma1=X3["lam_gamma1"] / lam, theta_s_deg=X3["theta"], dt=X3["dt"])
+
+
+def x3_electrodes():
+    """The x-elements alternate electrode / gap (width L0/12 each, 20 elements over 5/3):
+    electrodes on the even elements, voltages alternating +1, -1; [(x0, x1, sign)]."""
+    h = X3["lx"] / X3["nx"]
+    out = []
+    for e in range(0, X3["nx"], 2):
+        out.append((e * h, (e + 1) * h, 1.0 if (e // 2) % 2 == 0 else -1.0))
+    return out
+
+
+def electrode_vd(X, Y, electrodes, tol=1e-12):
+    """Dirichlet data on the electrode nodes of the bottom row: sign * 1 by segment."""
+    vd = np.zeros_like(np.asarray(X, dtype=float))
+    bottom = np.isclose(Y, 0.0)
+    for (x0, x1, sgn) in electrodes:
+        vd = np.where(bottom & (X >= x0 - tol) & (X <= x1 + tol), sgn, vd)
+    return vd
+
+
+# ---- the paper's 2D dielectric film (Sec. 4.3), equilibrium system, normalised with
+# L0 = d/2 (so the domain is [0,8] x [0,5]) and Vd = 100 V; electrodes on x in [1,3]
+# (V = 0) and [5,7] (V = V0); the film thickness h0, its permittivity, the electrode width
+# and the element counts along x are not fixed there (proposals here)
+X4 = dict(name="X4", lx=8.0, ly=5.0, nx=16, K=12, h0=1.0, amp=0.2, ny_regions=(5, 4, 4),
+          electrodes=((1.0, 3.0, 0.0), (5.0, 7.0, 1.0)), eta=0.01, lam_gamma1=0.1, dt=2e-6,
+          d=1e-4, Vd=100.0, sigma=2.84e-2, eps_vac=8.854e-12, eps_ratio=10.0, theta=90.0, steps=500)
+
+
+def x4_mesh_y():
+    """y breakpoints: near-wall region [0, h0 - A/2] and wave region [h0 - A/2, h0 + A/2] with
+    uniform elements, the upper region up to 5 with elements growing by 1.6."""
+    n1, n2, n3 = X4["ny_regions"]
+    a, b = X4["h0"] - X4["amp"] / 2, X4["h0"] + X4["amp"] / 2
+    ys = list(np.linspace(0.0, a, n1 + 1)) + list(np.linspace(a, b, n2 + 1))[1:]
+    g = 1.6 ** np.arange(n3)
+    ys += list(b + (X4["ly"] - b) * np.cumsum(g) / g.sum())
+    return np.array(ys)
+
+
+def x4_param_dict():
+    """Equilibrium-system parameters of the film.  The stabiliser is set to S = 2: the paper
+    only bounds S from below, by the value that splits the Cahn-Hilliard step into two
+    Helmholtz problems (0.548 here), and at that value the march diverges (the oracle's too,
+    at any voltage); the linear stabilisation of the double well needs S of the order of
+    max h'(phi) eta^2 = 2 (S = 1 still diverged, S = 2 marched stably at V0 = 1 and 3)."""
+    L0 = X4["d"] / 2.0
+    e1 = X4["eps_vac"] * X4["Vd"] ** 2 / (L0 * X4["sigma"])
+    lam = lam_from_sigma(1.0, X4["eta"])
+    return dict(rho1=1.0, rho2=1.0, mu1=0.01, mu2=0.01, eps1=e1, eps2=X4["eps_ratio"] * e1, lam=lam,
+                eta=X4["eta"], gamma1=X4["lam_gamma1"] / lam, theta_s_deg=X4["theta"], dt=X4["dt"], S=2.0)
+
+
+def x4_phi0(Y):
+    """Flat film of thickness h0: phi = tanh((y - h0) / (sqrt 2 eta)) (film phi = -1)."""
+    return np.tanh((np.asarray(Y) - X4["h0"]) / (math.sqrt(2.0) * X4["eta"]))
