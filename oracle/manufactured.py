@@ -60,7 +60,26 @@ def exact_box():
     return dict(u=(u, v, s.Integer(0)), P=P, phi=phi, V=V)
 
 
-EXACT = {"eq80": (2, exact_2d), "eq81": (3, exact_3d), "box": (2, exact_box)}
+def exact_slab():
+    """A 3D solution between no-slip walls at y = -1 and y = 1 (not from the paper;
+    it exercises the 3D terms without tangential wall motion): u = curl(b, 0, a)
+    with a = sin^2(pi y) cos(pi x) cos(pi z) sin t and
+    b = sin^2(pi y) sin(pi x) sin(pi z) sin t, so div u = 0 and u = 0 on both walls,
+    and every component varies along z."""
+    pi = s.pi
+    a = s.sin(pi * Y) ** 2 * s.cos(pi * X) * s.cos(pi * Z) * s.sin(T)
+    b = s.sin(pi * Y) ** 2 * s.sin(pi * X) * s.sin(pi * Z) * s.sin(T)
+    u = s.diff(a, Y)
+    v = -s.diff(a, X) + s.diff(b, Z)
+    w = -s.diff(b, Y)
+    P = s.cos(pi * X) * s.cos(pi * Y) * s.sin(pi * Z) * s.cos(T)
+    phi = s.Rational(1, 2) * s.cos(pi * X) * s.cos(pi * Y) * s.cos(pi * Z) * s.sin(T)
+    V = s.sin(pi * X) * s.cos(pi * Y) * s.cos(pi * Z)
+    return dict(u=(u, v, w), P=P, phi=phi, V=V)
+
+
+EXACT = {"eq80": (2, exact_2d), "eq81": (3, exact_3d), "box": (2, exact_box),
+         "slab": (3, exact_slab)}
 
 
 def _grad(f):
@@ -127,7 +146,8 @@ def _ev(fn, x, y, z, t):
 class Manufactured:
     """Evaluate the exact fields and sources on given node coordinates.
 
-    kind: "eq80" (2D, eq. 80), "eq81" (3D, eq. 81) or "box" (2D closed box).
+    kind: "eq80" (2D, eq. 80), "eq81" (3D, eq. 81), "box" (2D closed box) or
+    "slab" (3D between two no-slip walls).
     Boundary sources are nodal; the side of each boundary node is given by masks.
     A node on two sides (a corner) takes the value of the side listed last; the
     "box" solution has zero normal-derivative data on every side, so its

@@ -30,6 +30,10 @@ def mms_setup(kind, K, dt, Nz=8, S=0.0, par=None):
     eq80: [0,2]x[0,1], two elements, x-periodic, wall at y=0 (V Dirichlet), open top.
     eq81: [0,2]x[-1,1]x[0,2], two elements split at x=1, Nz planes, V Dirichlet on
           x in [0,1] of the bottom wall, Neumann on x in [1,2].
+    eq81b: eq81 with V Dirichlet on the whole bottom wall.
+    eq81w: eq81 with walls at y=-1 and y=1 (V Dirichlet on both), no open boundary.
+    slab: the eq81w domain and sides on 4x4 elements, with a solution that vanishes on
+          both walls.
     box:  [0,1]^2, 2x2 elements, walls everywhere, V Dirichlet at y=0 and y=1.
     """
     par = par or mms_params(dt, S)
@@ -37,12 +41,18 @@ def mms_setup(kind, K, dt, Nz=8, S=0.0, par=None):
         m = Mesh2D([0.0, 1.0, 2.0], [0.0, 1.0], K, periodic_x=True)
         bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, pot_sides=(BOTTOM,))
         sch = Scheme(m, par, bc)
-    elif kind in ("eq81", "eq81b"):
-        m = Mesh2D([0.0, 1.0, 2.0], [-1.0, 1.0], K, periodic_x=True)
+    elif kind in ("eq81", "eq81b", "eq81w", "slab"):
+        if kind == "slab":
+            m = Mesh2D([0.0, 0.5, 1.0, 1.5, 2.0], [-1.0, -0.5, 0.0, 0.5, 1.0], K,
+                       periodic_x=True)
+        else:
+            m = Mesh2D([0.0, 1.0, 2.0], [-1.0, 1.0], K, periodic_x=True)
         if kind == "eq81":
             bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, electrodes=[(0.0, 1.0)])
-        else:  # same solution with V Dirichlet on the whole bottom wall
+        elif kind == "eq81b":  # same solution with V Dirichlet on the whole bottom wall
             bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, pot_sides=(BOTTOM,))
+        else:  # two walls (no open boundary), V Dirichlet on both
+            bc = BCs(side={BOTTOM: WALL, TOP: WALL}, pot_sides=(BOTTOM, TOP))
         sch = Scheme(m, par, bc, Nz=Nz, Lz=2.0)
     elif kind == "box":
         m = Mesh2D([0.0, 0.5, 1.0], [0.0, 0.5, 1.0], K, periodic_x=False)
@@ -62,7 +72,7 @@ def mms_setup(kind, K, dt, Nz=8, S=0.0, par=None):
         g[m.side_nodes(s)] = True
         mask = np.broadcast_to(g[None, :], (Nzz, m.Ng)).copy()
         sides.append((mask, NORMALS[s], bc.side[s]))
-    mf = Manufactured("eq81" if kind == "eq81b" else kind, par)
+    mf = Manufactured("eq81" if kind in ("eq81b", "eq81w") else kind, par)
     return dict(mesh=m, bc=bc, sch=sch, par=par, x=x, y=y, z=z, sides=sides, mf=mf)
 
 
