@@ -415,7 +415,7 @@ def run_c5(a):
 
     zero = np.zeros(phi0.shape)
 
-    def march(V, er, th, start):
+    def march(V, er, th, start, max_steps=C5["max_steps"]):
         ctx.update_params(c5_param_dict(er, th, dt=dt, eta=eta))
         ctx.set_source("Vd", c5_vd(X, Y, V, el))
         for k in ("psi", "V"):           # no history from the previous problem
@@ -426,12 +426,12 @@ def run_c5(a):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
-            n, r = ctx.march_to_equilibrium(tol, C5["max_steps"])
+            n, r = ctx.march_to_equilibrium(tol, max_steps)
             ok = True
         except pfd.PfdError as e:
             if e.code not in (pfd.ENOCONV, pfd.ENONFINITE):
                 raise
-            n, ok = C5["max_steps"] if e.code == pfd.ENOCONV else 0, False
+            n, ok = max_steps if e.code == pfd.ENOCONV else 0, False
         t = time.perf_counter() - t0
         stats["steps"] += n
         stats["seconds"] += t
@@ -442,7 +442,7 @@ def run_c5(a):
     T = torch.empty((n_train, N), dtype=torch.float32, device="cuda")
     kept = []
     for i, (V, er, th) in enumerate(train):
-        n, t, ok = march(V, er, th, phi0)
+        n, t, ok = march(V, er, th, phi0, C5["gen_max_steps"])
         if ok:   # only equilibria the march reached to the tolerance become training data
             T[len(kept)] = torch.tensor(ctx.get_field("phi").ravel(), dtype=torch.float32, device="cuda")
             kept.append((V, er, th))
@@ -451,7 +451,7 @@ def run_c5(a):
     t_gen = time.perf_counter() - t_gen
     T = T[:len(kept)].contiguous()
     P = torch.tensor(np.stack([pfd.ws_inputs(*d) for d in kept]), device="cuda")
-    ws = pfd.WarmStart(N, seed=C5["seed_train"])
+    ws = pfd.WarmStart(phi0.shape, periodic=(True, False, True), seed=C5["seed_train"])
     ws.init_output_bias(T)
     torch.cuda.synchronize()
     t_tr = time.perf_counter()
@@ -476,13 +476,16 @@ def run_c5(a):
         n_w, t_w, ok_w = march(V, er, th, start)
         e_w = ctx.stats()[0]["total"]
         f_w = ctx.get_field("phi").ravel()
+        dmax = float(np.max(np.abs(f_w - f_p)))
+        m_p, m_w = float(np.sum(wts.ravel() * f_p)), float(np.sum(wts.ravel() * f_w))
         rows.append(dict(steps_plain=n_p, steps_warm=n_w, converged_plain=ok_p, converged_warm=ok_w,
                          s_plain=t_p, s_warm=t_w + t_pred, energy_plain=e_p, energy_warm=e_w,
-                         same_equilibrium=bool(abs(e_w - e_p) <= 1e-6 * abs(e_p)),
-                         start_error=err0, energy_rel_diff=abs(e_w - e_p) / abs(e_p),
+                         same_equilibrium=bool(ok_p and ok_w and dmax <= 1e-4),
+                         start_error=err0, field_diff=dmax, mass_rel_diff=abs(m_w - m_p) / abs(m_p),
+                         energy_rel_diff=abs(e_w - e_p) / abs(e_p),
                          sorted_field_diff=float(np.max(np.abs(np.sort(f_w) - np.sort(f_p))))))
-        print("# test %d: plain %d steps %.2f s, warm %d steps %.2f s (start error %.3g)"
-              % (i, n_p, t_p, n_w, t_w + t_pred, err0), file=sys.stderr, flush=True)
+        print("# test %d: plain %d steps %.2f s, warm %d steps %.2f s (start error %.3g, final |dphi| %.3g)"
+              % (i, n_p, t_p, n_w, t_w + t_pred, err0, dmax), file=sys.stderr, flush=True)
     sp = np.array([r_["steps_plain"] for r_ in rows], dtype=float)
     sw = np.array([r_["steps_warm"] for r_ in rows], dtype=float)
     same = np.array([r_["same_equilibrium"] for r_ in rows])
@@ -513,6 +516,9 @@ def run_c5(a):
                        "mean_s_plain": float(np.mean([r_["s_plain"] for r_ in rows])),
                        "mean_s_warm": float(np.mean([r_["s_warm"] for r_ in rows])),
                        "max_energy_rel_diff": float(max(r_["energy_rel_diff"] for r_ in rows)),
+                       "max_mass_rel_diff": float(max(r_["mass_rel_diff"] for r_ in rows)),
+                       "max_field_diff_same": float(max([r_["field_diff"] for r_ in rows if r_["same_equilibrium"]]
+                                                        or [float("nan")])),
                        "max_sorted_field_diff": float(max(r_["sorted_field_diff"] for r_ in rows)),
                        "per_problem": rows},
     }

@@ -351,24 +351,39 @@ const char* pfd_batch_last_error(const pfd_batch* b);
  * A small network, trained on equilibria the method computes, that maps the
  * three parameters of an equilibrium problem (voltage, permittivity ratio,
  * contact angle, each scaled to [-1, 1] by the caller) to the equilibrium
- * phase field on the grid (n_out values, the context's field layout), used as
- * the starting state of pfd_march_to_equilibrium; the march to the residual
- * tolerance stays the judge of the result.  Not in the paper.
- *   a1 = W1 p + b1, h1 = gelu(a1); a2 = W2 h1 + b2, h2 = gelu(a2);
- *   y = W3 h2 + b3;  loss = mean over batch and outputs of (y - t)^2
- * gelu(x) = x Phi(x).  Hidden sizes are fixed at 64 and 128.  FP32 master
- * weights in one blob [W1 (64x3) | b1 | W2 (128x64) | b2 | W3 (n_out x 128) |
- * b3], row-major; the output layer and its two backward products run on the
- * matrix cores with BF16 operands (W3, h2 and dL/dy rounded to nearest even)
- * and FP32 accumulation; Adam (0.9, 0.999, 1e-8).  Training inputs stay on the
- * device: params (S x 3, FP32) and targets (S x n_out, FP32). */
+ * phase field on the field's grid (nz x ny x nx values, z slowest: the
+ * context's field layout), used as the starting state of
+ * pfd_march_to_equilibrium; the march to the residual tolerance stays the
+ * judge of the result.  Not in the paper.  A convolutional decoder:
+ *   a1 = W1 p + b1, h1 = gelu(a1)   (64);  a2 = W2 h1 + b2, h2 = gelu(a2) (128)
+ *   x0 = W3 h2 + b3                 (16 channels on a Z0 x Y0 x X0 latent grid,
+ *                                    Z0 = ceil(nz / 8), likewise Y0, X0)
+ *   for s = 1..3: a_s = conv(up(x_{s-1}); K_s) + c_s, x_s = gelu(a_s)
+ *     (up doubles each axis by nearest neighbour; conv is 3x3x3, 16 -> 16
+ *      channels, K_s[tap][out][in], tap = 9 (dz+1) + 3 (dy+1) + (dx+1); a
+ *      neighbour outside the grid wraps along an axis that is periodic with
+ *      8 Z0 = nz exactly, and is zero along any other)
+ *   y = the nz x ny x nx corner of sum_c wo[c] x_3[c], plus bo
+ *   loss = mean over batch and outputs of (y - t)^2
+ * gelu(x) = x Phi(x).  FP32 master weights in one blob [W1 (64x3) | b1 |
+ * W2 (128x64) | b2 | W3 (L0 x 128, L0 = 16 Z0 Y0 X0) | b3 | K1 (27x16x16) | c1
+ * | K2 | c2 | K3 | c3 | wo (16) | bo (nz ny nx)], row-major, activations
+ * channel-last.  The latent layer, the convolutions and all their backward
+ * products run on the matrix cores with BF16 operands (rounded to nearest
+ * even: h2, W3, x0, every x_s, the K_s, and dL/da_s, dL/dx0) and FP32
+ * accumulation; Adam (0.9, 0.999, 1e-8).  Training inputs stay on the device:
+ * params (S x 3, FP32) and targets (S x nz ny nx, FP32). */
 typedef struct pfd_ws pfd_ws;
 typedef struct {
   int hidden1;               /* must be 64  */
   int hidden2;               /* must be 128 */
-  long n_out;                /* grid values of one field, >= 16 */
-  unsigned long long seed;   /* initial weights: N(0, 1/fan_in), W3 scaled by 0.01 */
+  int channels;              /* must be 16  */
+  int nz, ny, nx;            /* output grid, each 1..4096, nz ny nx >= 16 */
+  int periodic_z, periodic_y, periodic_x;   /* nonzero: the axis may wrap */
+  unsigned long long seed;   /* initial weights: N(0, 1/fan_in) (convolutions
+                                N(0, 2/432)), wo N(0, 1e-4), biases 0 */
 } pfd_ws_arch;
+/* Weights in the blob, or 0 if the architecture is invalid. */
 long pfd_ws_num_weights(const pfd_ws_arch* a);
 pfd_status pfd_ws_workspace_query(const pfd_ws_arch* a, size_t* dev_bytes);
 /* dev_ws: caller-owned device buffer of dev_bytes, 256-byte aligned. */
@@ -378,7 +393,7 @@ const char* pfd_ws_last_error(const pfd_ws* ws);
 /* Host copies of the FP32 weight blob (pfd_ws_num_weights floats). */
 pfd_status pfd_ws_get_weights(pfd_ws* ws, float* host);
 pfd_status pfd_ws_set_weights(pfd_ws* ws, const float* host);
-/* b3 = mean of the S training targets (device). */
+/* bo = mean of the S training targets (device). */
 pfd_status pfd_ws_init_output_bias(pfd_ws* ws, const float* targets, long S);
 /* Gradient of the loss on the minibatch idx[0..B) (host indices into the
  * device params/targets, 1 <= B <= 32) into grad_host (a weight blob; may be
@@ -394,8 +409,8 @@ pfd_status pfd_ws_train_step(pfd_ws* ws, const float* params, const float* targe
  * NULL) receives each step's minibatch loss.  Synchronises. */
 pfd_status pfd_ws_train(pfd_ws* ws, const float* params, const float* targets, long S, int steps, int B, float lr,
                         unsigned long long seed, double* loss_history);
-/* Prediction for one input p_host[3] into out (device, n_out FP64).  With
- * weights (device, n_out FP64: the quadrature weights of the field's integral)
+/* Prediction for one input p_host[3] into out (device, nz ny nx FP64).  With
+ * weights (device, nz ny nx FP64: the quadrature weights of the field's integral)
  * the prediction is shifted by a constant so that sum(weights * out) = mass
  * (mass conservation of eq. 16 fixes the equilibrium's integral).  Synchronises. */
 pfd_status pfd_ws_predict(pfd_ws* ws, const float* p_host, const double* weights, double mass, double* out);

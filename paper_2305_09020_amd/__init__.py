@@ -78,7 +78,9 @@ class Stats(ctypes.Structure):
 
 
 class WsArch(ctypes.Structure):
-    _fields_ = [("hidden1", ctypes.c_int), ("hidden2", ctypes.c_int), ("n_out", ctypes.c_long),
+    _fields_ = [("hidden1", ctypes.c_int), ("hidden2", ctypes.c_int), ("channels", ctypes.c_int),
+                ("nz", ctypes.c_int), ("ny", ctypes.c_int), ("nx", ctypes.c_int),
+                ("periodic_z", ctypes.c_int), ("periodic_y", ctypes.c_int), ("periodic_x", ctypes.c_int),
                 ("seed", ctypes.c_ulonglong)]
 
 
@@ -442,16 +444,21 @@ class Batch:
 
 
 class WarmStart:
-    """The learned warm start (hand-written HIP training and inference kernels): a network
-    from three scaled parameters to a field of n_out values.  Device memory is one torch
-    uint8 workspace owned by this object."""
+    """The learned warm start (hand-written HIP training and inference kernels): a
+    convolutional decoder from three scaled parameters to a field on the grid
+    (nz, ny, nx), z slowest; periodic = (z, y, x) flags.  Device memory is one torch uint8
+    workspace owned by this object."""
 
-    def __init__(self, n_out, seed=0, device="cuda", stream=None):
+    def __init__(self, grid, periodic=(False, False, False), seed=0, device="cuda", stream=None):
         import torch
         self.torch = torch
-        self.arch = WsArch(64, 128, int(n_out), int(seed))
-        self.n_out = int(n_out)
+        nz, ny, nx = (int(v) for v in grid)
+        self.arch = WsArch(64, 128, 16, nz, ny, nx, int(bool(periodic[0])), int(bool(periodic[1])),
+                           int(bool(periodic[2])), int(seed))
+        self.n_out = nz * ny * nx
         self.nw = _lib.pfd_ws_num_weights(ctypes.byref(self.arch))
+        if self.nw <= 0:
+            raise PfdError(EINVAL, "invalid warm-start grid %r" % (tuple(grid),))
         n = ctypes.c_size_t(0)
         _check(_lib.pfd_ws_workspace_query(ctypes.byref(self.arch), ctypes.byref(n)))
         self.ws = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
@@ -503,7 +510,7 @@ class WarmStart:
         return hist[:steps]
 
     def predict(self, p, out, weights=None, mass=0.0):
-        """Field for inputs p (3 scaled values) into out (float64 device tensor of n_out);
+        """Field for inputs p (3 scaled values) into out (float64 device tensor of nz ny nx);
         with weights (float64 device tensor) shifted to sum(weights * out) = mass."""
         p = np.ascontiguousarray(p, dtype=np.float32)
         self._chk(_lib.pfd_ws_predict(self.h, _vp(p.ctypes.data), _vp(weights.data_ptr()) if weights is not None
