@@ -164,7 +164,7 @@ typedef struct {
                             (0 -> PFD_REFINE_TOL_DEFAULT)                         */
 } pfd_problem;
 
-#define PFD_REFINE_MAX_DEFAULT 4
+#define PFD_REFINE_MAX_DEFAULT 3
 #define PFD_REFINE_TOL_DEFAULT 1e-15
 
 typedef struct pfd_ctx pfd_ctx;

@@ -94,3 +94,33 @@ def test_batch_instance_matches_oracle():
             scale = max(np.linalg.norm(ref), 1e-12 * np.linalg.norm(o["phi"]))
             assert np.linalg.norm(got - np.ravel(ref)) / scale < 1e-8, (n, k)
     batch.close()
+
+
+def test_batch_recaptures_after_member_changes():
+    """A member's parameters changed between batch steps (pfd_update_params): the batch's
+    graphs are recaptured (the member's graph generation changed), so the member keeps
+    matching the same instance stepped alone with the same change."""
+    _torch()
+    import paper_2305_09020_amd as pfd
+    precision = 1
+    batch_ctx = [_instance(*s[:4], precision, nz=s[4])[0] for s in SPECS[:3]]
+    solo_ctx = [_instance(*s[:4], precision, nz=s[4], tune_from=a)[0] for s, a in zip(SPECS[:3], batch_ctx)]
+    batch = pfd.Batch(batch_ctx, nlanes=2)
+    new = c4_param_dict(30.0)        # permittivity ratio 20 -> 30 on instance 1
+    new["theta_s_deg"] = 80.0
+    for n in range(4):
+        if n == 2:
+            batch_ctx[1].update_params(new)
+            solo_ctx[1].update_params(new)
+        batch.step(1)
+        for c in solo_ctx:
+            c.step(1)
+        for i, (a, b) in enumerate(zip(batch_ctx, solo_ctx)):
+            for k in FIELDS:
+                fa, fb = a.get_field(k), b.get_field(k)
+                assert np.array_equal(fa, fb), (n, i, k, np.max(np.abs(fa - fb)))
+    # and the change took effect: instance 1 differs from a twin that kept the old parameters
+    twin = _instance(*SPECS[1][:4], precision, tune_from=batch_ctx[1])[0]
+    twin.step(4)
+    assert not np.array_equal(twin.get_field("phi"), batch_ctx[1].get_field("phi"))
+    batch.close()
