@@ -125,9 +125,11 @@ def build_workload(name, precision, graph=True):
     if name == "c4":
         stream = torch.cuda.current_stream()
         ctxs = []
-        for inst in c4_instances():
+        for i, inst in enumerate(c4_instances()):
             ctxs.append(_ctx2d(pfd, inst["n"], inst["K"], c4_param_dict(inst["eps_ratio"]), (inst["vtop"],),
                                C4["center"], C4["r"], precision, stream=stream))
+            if (i + 1) % 16 == 0:
+                print("# c4: %d instances created" % (i + 1), file=sys.stderr, flush=True)
         batch = pfd.Batch(ctxs, nlanes=4)
         return Run(ctxs, sum(c.planes * c.Nx * c.Ny for c in ctxs), 38,
                    "64 independent 2D drops in one batch (one hipGraph launch per step): n x n "
