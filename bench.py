@@ -333,6 +333,24 @@ def _oracle_run(workload):
         src = dict(Vd=np.where(np.isclose(m.Y.ravel(), 1.0), v, 0.0))
         sch.init_potential(src)
         return sch, src, m.Ng, "one instance (V_top = %g) of the workload, %dx%d elements, K = %d" % (v, n, n, K)
+    if workload == "c5":
+        from oracle.scheme import OPEN
+        nz, eta = C5_ORACLE_PLANES, C5["eta_run"]
+        par = Params(**c5_param_dict(10.0, 90.0, dt=C5["dt_run"], eta=eta))
+        m = Mesh2D(np.linspace(0.0, C5["lx"], C5["nx"] + 1), np.linspace(0.0, C5["ly"], C5["ny"] + 1), C5["K"],
+                   periodic_x=True)
+        el = c5_electrodes()
+        sch = Scheme(m, par, BCs(side={BOTTOM: WALL, TOP: OPEN}, electrodes=[(a, b_) for a, b_, _ in el]),
+                     Nz=nz, Lz=C5["lz"])
+        Z = np.broadcast_to(sch.z[:, None], (nz, m.Ng))
+        X = np.broadcast_to(m.X.ravel()[None, :], Z.shape)
+        Y = np.broadcast_to(m.Y.ravel()[None, :], Z.shape)
+        sch.set_state(drop_field(X, Y, C5["center"][:2], C5["r"], eta, Z=Z, zc=C5["center"][2]))
+        src = dict(Vd=c5_vd(X, Y, 1.0, el))
+        sch.init_potential(src)
+        return sch, src, m.Ng * nz, ("the equilibrium workload's mesh (12x12 elements, K = 6) with %d of its %d "
+                                     "Fourier planes, equilibrium steps (V = 1, eps ratio 10, contact angle 90)"
+                                     % (nz, C5["nz"]))
     if workload == "x6":
         from oracle.scheme import OPEN
         par = Params(**x6_param_dict())
@@ -361,9 +379,10 @@ def _oracle_run(workload):
 
 
 C3_ORACLE_PLANES = 16
+C5_ORACLE_PLANES = 8
 
 
-def cpu_baseline(workload, nsteps):
+def cpu_baseline(workload, nsteps, equilibrium=False):
     """The FP64 oracle (sparse LU, NumPy element loops) on the host: `nsteps` steps after its
     first (which includes the one-time LU factorisations, timed separately), once with the
     BLAS / OpenMP pools held to one thread and then `nsteps` more with all of them."""
@@ -373,14 +392,14 @@ def cpu_baseline(workload, nsteps):
     sch, src, dof, what = _oracle_run(workload)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        sch.step(src)
+        sch.step(src, equilibrium=equilibrium)
         tset = time.perf_counter() - t0
     print("# oracle baseline: first step (with the sparse-LU set-up) %.1f s" % tset, file=sys.stderr, flush=True)
     for label, lim in (("one", 1), ("all", None)):
         with threadpool_limits(limits=lim):
             t0 = time.perf_counter()
             for i in range(nsteps):
-                sch.step(src)
+                sch.step(src, equilibrium=equilibrium)
                 if (i + 1) % 10 == 0 or i + 1 == nsteps:
                     print("# oracle baseline (%s): %d/%d steps, %.1f s" % (label, i + 1, nsteps,
                                                                           time.perf_counter() - t0),
@@ -535,6 +554,8 @@ def run_c5(a):
                        "max_sorted_field_diff": float(max(r_["sorted_field_diff"] for r_ in rows)),
                        "per_problem": rows},
     }
+    if not a.no_cpu_baseline:
+        out_line["cpu_baseline"] = cpu_baseline("c5", 20, equilibrium=True)
     print(json.dumps(out_line), flush=True)
 
 
