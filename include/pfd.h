@@ -113,7 +113,7 @@ enum { PFD_FAM_V = 0, PFD_FAM_PSI = 1, PFD_FAM_PHI = 2, PFD_FAM_P = 3, PFD_FAM_U
 
 typedef struct {
   int nx, ny;            /* elements along x and y (tensor-product mesh)        */
-  int K;                 /* element order, 2 <= K <= 16                         */
+  int K;                 /* element order, 2 <= K <= 15                         */
   const double* xb;      /* nx+1 increasing x breakpoints (host)                */
   const double* yb;      /* ny+1 increasing y breakpoints (host)                */
   int periodic_x;        /* 1: x = xb[0] and x = xb[nx] identified              */
@@ -218,7 +218,7 @@ const char* pfd_status_string(pfd_status s);
 const char* pfd_last_error(const pfd_ctx* ctx);
 
 /* Device bytes the context for *prob needs.  Host-only; validates prob
- * (PFD_EINVAL for: K outside [2,16], nx or ny < 1, non-increasing breakpoints,
+ * (PFD_EINVAL for: K outside [2,15], nx or ny < 1, non-increasing breakpoints,
  * dt <= 0, eta <= 0, odd or < 2 nz, nbatch < 1 or nbatch > 1 in 3D, an
  * electrode segment not on element edges, no V Dirichlet node at all). */
 pfd_status pfd_workspace_query(const pfd_problem* prob, size_t* dev_bytes);

@@ -55,7 +55,8 @@ long refine_blocks(int Ny, int planes, long Pg) {
 pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
   if (!p) { *err = "null problem"; return PFD_EINVAL; }
   const pfd_mesh& m = p->mesh;
-  if (m.K < 2 || m.K > PFD_KMAX) { *err = "K must be in [2,16]"; return PFD_EINVAL; }
+  // the (K+1)^2 nodes of an element are one work-group of at most 256 threads
+  if (m.K < 2 || m.K > PFD_KMAX_STEP) { *err = "K must be in [2,15]"; return PFD_EINVAL; }
   if (m.nx < 1 || m.ny < 1 || !m.xb || !m.yb) { *err = "bad element counts or breakpoints"; return PFD_EINVAL; }
   if (m.periodic_x && m.nx < 2) { *err = "periodic x needs nx >= 2"; return PFD_EINVAL; }
   for (int i = 0; i < m.nx; ++i)

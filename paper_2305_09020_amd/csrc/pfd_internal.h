@@ -10,7 +10,8 @@
 
 #include "../../include/pfd.h"
 
-#define PFD_KMAX 16
+#define PFD_KMAX 16        // array bounds of the 1D tables
+#define PFD_KMAX_STEP 15   // highest order accepted: (K+1)^2 <= 256 element nodes per work-group
 #define PFD_NMAX 320  // max nodes per direction handled by the solve kernels
 #define PFD_STAT_NB 32  // blocks per instance of the diagnostics reduction
 #define PFD_GEMM_NCFG 16  // tile configurations of the batched GEMM
