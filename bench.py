@@ -584,7 +584,7 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: this library has no multi-GPU path "
               "(the step would shard by Fourier mode in 3D; see the design notes)", file=sys.stderr)
         sys.exit(2)
     import torch

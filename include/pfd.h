@@ -353,8 +353,8 @@ const char* pfd_batch_last_error(const pfd_batch* b);
  * contact angle, each scaled to [-1, 1] by the caller) to the equilibrium
  * phase field on the field's grid (nz x ny x nx values, z slowest: the
  * context's field layout), used as the starting state of
- * pfd_march_to_equilibrium; the march to the residual tolerance stays the
- * judge of the result.  Not in the paper.  A convolutional decoder:
+ * pfd_march_to_equilibrium; the march to the residual tolerance still
+ * decides the result.  Not in the paper.  A convolutional decoder:
  *   a1 = W1 p + b1, h1 = gelu(a1)   (64);  a2 = W2 h1 + b2, h2 = gelu(a2) (128)
  *   x0 = W3 h2 + b3                 (16 channels on a Z0 x Y0 x X0 latent grid,
  *                                    Z0 = ceil(nz / 8), likewise Y0, X0)

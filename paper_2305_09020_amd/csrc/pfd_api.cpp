@@ -1,4 +1,4 @@
-// C-ABI of the pfd library: context set-up, field I/O and the step driver.
+// C-ABI of the pfd library: context set-up, field I/O and the stepping entry points.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>

@@ -1,7 +1,7 @@
 // Learned warm start: a small network trained on equilibria the method itself computes maps
 // (voltage, permittivity ratio, contact angle) to the equilibrium phase field, used as the
-// starting state of the equilibrium march (the march to the residual tolerance stays the
-// judge).  The network is a convolutional decoder onto the field's grid (nz x ny x nx values,
+// starting state of the equilibrium march (the march to the residual tolerance still decides
+// the result).  The network is a convolutional decoder onto the field's grid (nz x ny x nx values,
 // z slowest):
 //
 //   a1 = W1 p + b1, h1 = gelu(a1)                      64 units   (FP32)

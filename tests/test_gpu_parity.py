@@ -2,7 +2,7 @@
 element on the same seeded inputs.  Tolerances: plain FP64 path 1e-10 relative
 per field (the oracle uses sparse LU, the library fast diagonalisation: both are
 direct FP64 solves, differing by rounding); FP32-refined path 1e-8 (the
-spec bound)."""
+accuracy target of the refined path)."""
 import math
 
 import numpy as np

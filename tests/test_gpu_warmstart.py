@@ -140,7 +140,7 @@ def test_warm_start_reduces_equilibrium_steps():
     method-generated equilibria, then for 3 new problems near training ones (voltage +0.05,
     permittivity ratio x1.05, contact angle +2 degrees; a parameter sweep's next points)
     march from the network's mass-projected prediction and from the plain initial drop.  The
-    march is the judge: both end on the same equilibrium (max |phi_warm - phi_plain| <= 1e-4,
+    march decides: both end on the same equilibrium (max |phi_warm - phi_plain| <= 1e-4,
     equal mass) and the warm march needs fewer steps on average.  Problems far from every
     training sample can end on another local minimum of the energy (the system has several);
     the full-size workload reports those as failures of the warm start."""
