@@ -130,6 +130,13 @@ def build_workload(name, precision, graph=True):
                                C4["center"], C4["r"], precision, stream=stream))
             if (i + 1) % 16 == 0:
                 print("# c4: %d instances created" % (i + 1), file=sys.stderr, flush=True)
+        # the autotuner times each instance alone; run concurrently in the batch's graph the
+        # four-pass solver for every instance was the fastest choice in one measured run (15.8 ms
+        # per refined step against 17.1 with the per-instance choices, 16.1 with the fused middle
+        # passes, 26.6 with the fused strips); timings of this workload vary by about 10 %
+        # between runs
+        for c in ctxs:
+            c.set_solver_variant(0)
         batch = pfd.Batch(ctxs, nlanes=4)
         return Run(ctxs, sum(c.planes * c.Nx * c.Ny for c in ctxs), 38,
                    "64 independent 2D drops in one batch (one hipGraph launch per step): n x n "
