@@ -102,7 +102,11 @@ typedef enum {
  * pfd_get_refine_stats reports the estimates, the split and the corrections taken. */
 typedef enum {
   PFD_PLAIN_FP64 = 0,   /* FP64 fast-diagonalisation solve                     */
-  PFD_REFINED_FP32 = 1  /* FP32 solve + FP64 residual iterative refinement     */
+  PFD_REFINED_FP32 = 1, /* FP32 solve + FP64 residual iterative refinement     */
+  PFD_REFINED_BF16 = 2  /* not built: BF16 corrections were measured (bit-faithful
+                           emulation on the benchmark operators) to need seven or
+                           more corrections per solve against three in FP32, more
+                           than their cheaper passes save; PFD_ENOTIMPL          */
 } pfd_precision;
 
 enum { PFD_WALL = 0, PFD_OPEN = 1, PFD_PERIODIC = 2 };

@@ -27,7 +27,7 @@ UX, UY, UZ, P, PHI, PSI, V, EX, EY, EZ = range(10)
 FIELDS = dict(ux=UX, uy=UY, uz=UZ, P=P, phi=PHI, psi=PSI, V=V, Ex=EX, Ey=EY, Ez=EZ)
 SOURCES = dict(g=0, fx=1, fy=2, fz=3, fV=4, g1=5, g2=6, g3=7, f1x=8, f1y=9, f1z=10, f2=11,
                wx=12, wy=13, wz=14, Vd=15)
-PLAIN_FP64, REFINED_FP32 = 0, 1
+PLAIN_FP64, REFINED_FP32, REFINED_BF16 = 0, 1, 2
 WALL, OPEN, PERIODIC = 0, 1, 2
 BOTTOM, TOP, LEFT, RIGHT = 0, 1, 2, 3
 FAM_V, FAM_PSI, FAM_PHI, FAM_P, FAM_U = range(5)

@@ -71,6 +71,10 @@ pfd_status validate(const pfd_problem* p, Layout* L, std::string* err) {
     *err = "material properties must be positive"; return PFD_EINVAL;
   }
   if (q.bdf_order != 1 && q.bdf_order != 2) { *err = "bdf_order must be 1 or 2"; return PFD_EINVAL; }
+  if (p->precision == PFD_REFINED_BF16) {
+    *err = "BF16 corrections are not built (measured to need more corrections than they save)";
+    return PFD_ENOTIMPL;
+  }
   if (p->precision != PFD_PLAIN_FP64 && p->precision != PFD_REFINED_FP32) { *err = "bad precision"; return PFD_EINVAL; }
   if (p->refine_max < 0 || p->refine_max > 64 || !(p->refine_tol >= 0.0) || !(p->refine_tol < 1.0)) {
     *err = "refine_max must be in [0,64] and refine_tol in [0,1)"; return PFD_EINVAL;

@@ -43,6 +43,11 @@ def test_host_only_validation():
     bad = pfd.make_problem(xb, xb, 1, par, [0, 0, 0, 0], [1, 1, 0, 0])
     with pytest.raises(pfd.PfdError):
         pfd.workspace_bytes(bad)
+    # BF16 corrections are declared but not built
+    with pytest.raises(pfd.PfdError) as ei:
+        pfd.workspace_bytes(pfd.make_problem(xb, xb, 6, par, [0, 0, 0, 0], [1, 1, 0, 0],
+                                             precision=pfd.REFINED_BF16))
+    assert ei.value.code == pfd.ENOTIMPL
     # order 15 is the highest: an element's 16^2 nodes fill one 256-thread work-group
     assert pfd.workspace_bytes(pfd.make_problem(xb, xb, 15, par, [0, 0, 0, 0], [1, 1, 0, 0])) > 0
     with pytest.raises(pfd.PfdError):
