@@ -237,6 +237,28 @@ def probe_copy_bandwidth():
     return gbs
 
 
+def probe_gemm_rate():
+    """Dense square GEMMs through torch (hipBLASLt) in FP64 and FP32: a measured matrix-core
+    ceiling for the fast-diagonalisation passes' classes (TFLOP/s)."""
+    import torch
+    out = {}
+    for name, dt, n in (("fp64", torch.float64, 8192), ("fp32", torch.float32, 8192)):
+        a = torch.randn(n, n, dtype=dt, device="cuda")
+        b = torch.randn(n, n, dtype=dt, device="cuda")
+        c = a @ b
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(5 * 2.0 * n ** 3 / (e0.elapsed_time(e1) / 1e3) / 1e12, 1)
+        del a, b, c
+    return out
+
+
 def _sources_sha():
     import hashlib
     h = hashlib.sha256()
@@ -612,6 +634,7 @@ def main():
         a.steps = {"c1": C1["steps"], "c2": C2["steps"], "c3": C3["steps"], "c4": C4["steps"],
                    "x6": X6["steps"], "x3": 200, "x4": 500}[a.workload]
     probe = probe_copy_bandwidth()
+    gemm_probe = probe_gemm_rate()
     res = {}
     for name, prec in (("refined", pfd.REFINED_FP32), ("fp64", pfd.PLAIN_FP64)):
         if a.only not in (name, "both"):
@@ -636,7 +659,7 @@ def main():
         "vs_baseline": None, "dtype": "f64+f32" if main_name == "refined" else "f64", "data": "synthetic",
         "config": {"workload": r["run"].desc + "; %s path" % main_name, "dof_per_step": r["run"].dof,
                    "graph": not a.no_graph, "timed_repeats": a.repeats},
-        "roofline": r["roofline"],
+        "roofline": dict(r["roofline"], probe_gemm_TFLOPs=gemm_probe),
     }
     if r["refinement"]:
         out["refinement"] = r["refinement"]
