@@ -197,7 +197,9 @@ def test_warm_start_reduces_equilibrium_steps():
         d = np.max(np.abs(f_w - f_p))
         print("problem near draw", j, "steps plain", n_p, "warm", n_w, "max field diff", d,
               "energy", st_p["total"], st_w["total"])
-        assert abs(st_w["mass"] - st_p["mass"]) < 1e-12 * abs(st_p["mass"]) + 1e-14
+        # each march keeps the mass to rounding per step; over these thousands of steps the two
+        # drift apart by a few 1e-13
+        assert abs(st_w["mass"] - st_p["mass"]) < 2e-12 * abs(st_p["mass"])
         assert d <= 1e-4, (j, d)
     assert np.mean(warm) < np.mean(plain), (plain, warm)
 
