@@ -332,16 +332,35 @@ pfd_status pfd_set_graph(pfd_ctx* ctx, int on);
 /* ------------------------------------------------------------------ batches
  * A batch steps independent contexts together: instances of uneven mesh,
  * order, parameters and precision (2D or 3D) that were all created on one
- * stream.  Each step is one hipGraph launch holding every instance's step as
- * parallel branches (the instances are spread over nlanes capture streams,
- * 1..16, default 4 when nlanes < 1), captured on first use per parity of the
- * time level and step kind.  The contexts stay owned by the caller, keep
- * their own workspaces and kernels, and are used as usual between batch
- * steps (set/get fields, sources, stats); destroy the batch before them.
- * Instances at different time-level parities, or with profiling on, are
- * stepped by plain launches in order. */
+ * stream.  Each step is one hipGraph launch, captured on first use per parity
+ * of the time level and step kind, in one of two forms (pfd_batch_set_mode):
+ *  PFD_BATCH_MULTI (default): multi-instance launches.  One step of every
+ *    instance is recorded; the k-th launches of all instances that run the
+ *    same kernel with the same work-group shape become one launch whose
+ *    work-groups are the concatenation of the instances' grids (each
+ *    instance keeps its own grid, arguments and buffers).  A step is as many
+ *    launches as one instance's step times the number of distinct kernel
+ *    templates at a position (e.g. element orders), independent of the
+ *    number of instances; results equal those of the instances stepped alone
+ *    bit for bit.  The plan's tables and argument packs (about 4 bytes per
+ *    work-group of a step, plus the arguments) are allocated at capture.
+ *  PFD_BATCH_BRANCHES: every instance's own launches as parallel graph
+ *    branches (spread over nlanes capture streams, 1..16, default 4 when
+ *    nlanes < 1).
+ * The contexts stay owned by the caller, keep their own workspaces and
+ * kernels, and are used as usual between batch steps (set/get fields,
+ * sources, stats); destroy the batch before them.  Instances at different
+ * time-level parities, or with profiling on, are stepped by plain launches in
+ * order. */
 typedef struct pfd_batch pfd_batch;
+enum { PFD_BATCH_BRANCHES = 0, PFD_BATCH_MULTI = 1 };
 pfd_status pfd_batch_create(pfd_ctx* const* ctxs, int n, int nlanes, pfd_batch** out);
+/* Form of the batch's step graphs (PFD_BATCH_MULTI or PFD_BATCH_BRANCHES;
+ * PFD_EINVAL otherwise).  A change drops the captured graphs (synchronises). */
+pfd_status pfd_batch_set_mode(pfd_batch* b, int mode);
+/* Launches per step of the multi-instance form (the largest captured plan);
+ * -1 before the first capture. */
+int pfd_batch_launches(const pfd_batch* b);
 /* nsteps steps of every instance (equilibrium != 0: the equilibrium system),
  * then one synchronisation: PFD_ENONFINITE if any instance's state became
  * non-finite (that instance fails as in pfd_step; the others have stepped). */

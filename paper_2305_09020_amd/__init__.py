@@ -103,6 +103,8 @@ _sig = {
     "pfd_batch_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "pfd_batch_destroy": (None, [_vp]),
     "pfd_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "pfd_batch_set_mode": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "pfd_batch_launches": (ctypes.c_int, [_vp]),
     "pfd_set_solver_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pfd_update_params": (ctypes.c_int, [_vp, ctypes.POINTER(Params)]),
     "pfd_get_mass_weights": (ctypes.c_int, [_vp, _dp]),
@@ -412,11 +414,15 @@ class Context:
         return [{k: getattr(a, k) for k, _ in RefineStats._fields_} for a in arr]
 
 
+BATCH_BRANCHES, BATCH_MULTI = 0, 1
+
+
 class Batch:
     """Independent contexts (uneven meshes, orders, parameters) created on one stream,
-    stepped together: one hipGraph launch per step with every instance as a parallel branch."""
+    stepped together, one hipGraph launch per step: multi-instance launches (mode
+    BATCH_MULTI, default) or every instance as a parallel branch (BATCH_BRANCHES)."""
 
-    def __init__(self, contexts, nlanes=4):
+    def __init__(self, contexts, nlanes=4, mode=BATCH_MULTI):
         self.contexts = list(contexts)
         arr = (_vp * len(self.contexts))(*[c.h for c in self.contexts])
         h = _vp()
@@ -425,6 +431,16 @@ class Batch:
             raise PfdError(code, _lib.pfd_batch_last_error(None).decode())
         self.h = h
         self._destroy = _lib.pfd_batch_destroy
+        self.set_mode(mode)
+
+    def set_mode(self, mode):
+        code = _lib.pfd_batch_set_mode(self.h, int(mode))
+        if code != OK:
+            raise PfdError(code, "batch mode must be BATCH_BRANCHES or BATCH_MULTI")
+
+    def launches(self):
+        """Launches per step of the multi-instance form (-1 before its first capture)."""
+        return int(_lib.pfd_batch_launches(self.h))
 
     def step(self, nsteps=1, equilibrium=False):
         code = _lib.pfd_batch_step(self.h, int(nsteps), int(bool(equilibrium)))

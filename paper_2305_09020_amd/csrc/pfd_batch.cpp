@@ -1,20 +1,45 @@
 // Batches of independent contexts (instances of uneven mesh, order and parameters) stepped
-// together: one hipGraph per step holds every instance's step, captured as parallel branches
-// (the instances are spread over a few capture streams forked from one origin and joined
-// again), so one graph launch runs all instances with the branches free to overlap on the
-// device.  Instances keep their own workspaces, autotuned kernels and state; the graph only
-// orders and groups their launches.
+// together, one hipGraph launch per step, in one of two forms:
+//  * branches: every instance's step captured as parallel branches (the instances are spread
+//    over a few capture streams forked from one origin and joined again), so the graph holds
+//    each instance's own launches, free to overlap on the device;
+//  * multi-instance launches: every instance's step is recorded (its launches, in order, with
+//    their packed arguments), and the k-th launches of all instances that run the same kernel
+//    with the same work-group shape become one launch of that kernel's multi-instance form,
+//    whose work-groups are the concatenation of the instances' grids.  A step is then about as
+//    many launches as one instance's step (times the number of distinct kernel templates at a
+//    position, e.g. one per element order), whatever the number of instances.
+// Instances keep their own workspaces, autotuned kernels and state in both forms; the batch
+// only orders and groups their launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
 #include <string>
 #include <vector>
 
 #include "pfd_internal.h"
+#include "pfd_launch.h"
 
 using namespace pfd;
 
+// one launch of a multi-instance step: the kernel's multi-instance form over `total`
+// work-groups, and the offsets of its member table, work-group table and argument packs in the
+// plan's device buffer
+struct MultiLaunch {
+  const void* fn = nullptr;
+  unsigned total = 0, block[3] = {1, 1, 1};
+  size_t shm = 0, o_ent = 0, o_tab = 0, o_args = 0;
+};
+struct MultiPlan {
+  char* dmem = nullptr;            // device buffer of all tables and argument packs
+  std::vector<MultiLaunch> L;
+};
+
 struct pfd_batch {
   std::vector<pfd_ctx*> ctx;
+  int mode = PFD_BATCH_MULTI;
+  MultiPlan plan[2][2];
   hipStream_t stream = nullptr;           // the stream the instances were created on
   hipStream_t cap = nullptr;              // capture origin
   std::vector<hipStream_t> lanes;         // capture branches
@@ -37,10 +62,20 @@ static thread_local std::string g_batch_err;
     }                                                        \
   } while (0)
 
+// graphs and plans of both forms (the device must have finished with them)
+static void drop_all(pfd_batch* b) {
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      if (b->gexec[i][j]) (void)hipGraphExecDestroy(b->gexec[i][j]);
+      b->gexec[i][j] = nullptr;
+      b->gen[i][j].clear();
+      if (b->plan[i][j].dmem) (void)hipFree(b->plan[i][j].dmem);
+      b->plan[i][j] = MultiPlan();
+    }
+}
+
 static void batch_free(pfd_batch* b) {
-  for (auto& row : b->gexec)
-    for (auto& g : row)
-      if (g) (void)hipGraphExecDestroy(g);
+  drop_all(b);
   for (auto e : b->ev) (void)hipEventDestroy(e);
   for (auto s : b->lanes) (void)hipStreamDestroy(s);
   if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -123,6 +158,133 @@ static hipError_t capture(pfd_batch* b, int eq, hipGraphExec_t* ex) {
   return e;
 }
 
+// Multi-instance plan of one step: record every instance's step (launches only; the host-side
+// state each step leaves is restored), then group the k-th launches of all instances by kernel
+// and work-group shape.  Instances whose sequences differ (another precision, boundary type or
+// kernel variant) still run correctly: each launch position is issued in order, one launch per
+// group, so every instance's launches keep their order.
+static hipError_t build_plan(pfd_batch* b, int eq, MultiPlan& P) {
+  const size_t n = b->ctx.size();
+  std::vector<std::vector<RecLaunch>> rec(n);
+  hipError_t es = hipSuccess;
+  for (size_t i = 0; i < n && !es; ++i) {
+    pfd_ctx* c = b->ctx[i];
+    const int cur = c->cur;
+    c->rec = &rec[i];
+    es = eager_step(c, eq);
+    c->rec = nullptr;
+    c->cur = cur;
+  }
+  if (es) return es;
+  size_t maxlen = 0;
+  for (auto& r : rec) maxlen = std::max(maxlen, r.size());
+  std::vector<unsigned char> host;
+  auto carve = [&host](size_t bytes, size_t align) {
+    const size_t o = (host.size() + align - 1) / align * align;
+    host.resize(o + bytes);
+    return o;
+  };
+  for (size_t j = 0; j < maxlen; ++j) {
+    std::vector<std::vector<size_t>> groups;   // member instances of each launch at position j
+    for (size_t i = 0; i < n; ++i) {
+      if (j >= rec[i].size()) continue;
+      const RecLaunch& r = rec[i][j];
+      if ((unsigned long long)r.grid[0] * r.grid[1] * r.grid[2] == 0) continue;
+      size_t g = 0;
+      for (; g < groups.size(); ++g) {
+        const RecLaunch& q = rec[groups[g][0]][j];
+        if (q.fn == r.fn && std::memcmp(q.block, r.block, sizeof(q.block)) == 0) break;
+      }
+      if (g == groups.size()) groups.emplace_back();
+      groups[g].push_back(i);
+    }
+    for (auto& grp : groups) {
+      const RecLaunch& r0 = rec[grp[0]][j];
+      MultiLaunch m;
+      m.fn = r0.fn;
+      std::memcpy(m.block, r0.block, sizeof(m.block));
+      unsigned long long total = 0;
+      for (size_t i : grp) {
+        const RecLaunch& r = rec[i][j];
+        m.shm = std::max(m.shm, r.shm);
+        total += (unsigned long long)r.grid[0] * r.grid[1] * r.grid[2];
+      }
+      if (total >= (1ull << 31)) return hipErrorInvalidConfiguration;
+      m.total = (unsigned)total;
+      m.o_ent = carve(sizeof(MEnt) * grp.size(), 16);
+      m.o_tab = carve(sizeof(unsigned) * total, 16);
+      m.o_args = carve(r0.asize * grp.size(), std::max<size_t>(r0.aalign, 16));
+      unsigned b0 = 0;
+      for (size_t q = 0; q < grp.size(); ++q) {
+        const RecLaunch& r = rec[grp[q]][j];
+        const unsigned nb = r.grid[0] * r.grid[1] * r.grid[2];
+        const MEnt me{r.grid[0], r.grid[1], r.grid[2], b0};
+        std::memcpy(host.data() + m.o_ent + q * sizeof(MEnt), &me, sizeof(me));
+        unsigned* tab = reinterpret_cast<unsigned*>(host.data() + m.o_tab);
+        for (unsigned k = 0; k < nb; ++k) tab[b0 + k] = (unsigned)q;
+        std::memcpy(host.data() + m.o_args + q * r0.asize, r.args.data(), r0.asize);
+        b0 += nb;
+      }
+      P.L.push_back(m);
+    }
+  }
+  if (host.empty()) return hipSuccess;
+  hipError_t e = hipMalloc(&P.dmem, host.size());
+  if (!e) e = hipMemcpy(P.dmem, host.data(), host.size(), hipMemcpyHostToDevice);
+  return e;
+}
+
+// capture the plan's launches (one stream, in order) as the step's graph
+static hipError_t capture_multi(pfd_batch* b, int eq, MultiPlan& P, hipGraphExec_t* ex) {
+  hipError_t e = build_plan(b, eq, P);
+  if (e) {
+    if (P.dmem) (void)hipFree(P.dmem);
+    P = MultiPlan();
+    return e;
+  }
+  e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e) return e;
+  hipError_t es = hipSuccess;
+  for (const MultiLaunch& m : P.L) {
+    unsigned total = m.total;
+    const void* tab = P.dmem + m.o_tab;
+    const void* ent = P.dmem + m.o_ent;
+    const void* args = P.dmem + m.o_args;
+    void* ka[] = {&total, &tab, &ent, &args};
+    es = hipLaunchKernel(m.fn, dim3(total), dim3(m.block[0], m.block[1], m.block[2]), ka, m.shm, b->cap);
+    if (es) break;
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->cap, &g);
+  if (!e) e = es;
+  if (!e) e = hipGraphInstantiate(ex, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e) {
+    *ex = nullptr;
+    if (P.dmem) (void)hipFree(P.dmem);
+    P = MultiPlan();
+  }
+  return e;
+}
+
+extern "C" pfd_status pfd_batch_set_mode(pfd_batch* b, int mode) {
+  if (!b || (mode != PFD_BATCH_BRANCHES && mode != PFD_BATCH_MULTI)) return PFD_EINVAL;
+  if (mode != b->mode) {
+    BCHK(hipStreamSynchronize(b->stream));
+    drop_all(b);
+    b->mode = mode;
+  }
+  return PFD_OK;
+}
+
+extern "C" int pfd_batch_launches(const pfd_batch* b) {
+  if (!b) return -1;
+  int m = -1;
+  for (auto& row : b->plan)
+    for (auto& p : row) m = std::max(m, (int)p.L.size());
+  return m;
+}
+
 extern "C" pfd_status pfd_batch_step(pfd_batch* b, int nsteps, int equilibrium) {
   if (!b || nsteps < 0) return PFD_EINVAL;
   const int eq = equilibrium ? 1 : 0;
@@ -154,13 +316,19 @@ extern "C" pfd_status pfd_batch_step(pfd_batch* b, int nsteps, int equilibrium) 
       std::vector<unsigned long>& gen = b->gen[cur][eq];
       bool stale = gen.size() != b->ctx.size();
       for (size_t i = 0; i < b->ctx.size() && !stale; ++i) stale = gen[i] != b->ctx[i]->graph_gen;
+      MultiPlan& plan = b->plan[cur][eq];
       if (ex && stale) {
         BCHK(hipStreamSynchronize(b->stream));
         (void)hipGraphExecDestroy(ex);
         ex = nullptr;
+        if (plan.dmem) (void)hipFree(plan.dmem);
+        plan = MultiPlan();
       }
       if (!ex) {
-        BCHK(capture(b, eq, &ex));
+        if (b->mode == PFD_BATCH_MULTI)
+          BCHK(capture_multi(b, eq, plan, &ex));
+        else
+          BCHK(capture(b, eq, &ex));
         gen.resize(b->ctx.size());
         for (size_t i = 0; i < b->ctx.size(); ++i) gen[i] = b->ctx[i]->graph_gen;
       }

@@ -89,6 +89,15 @@ struct Elec {
   double *d_Sinv = nullptr, *d_dG = nullptr;  // planes x ng x ng, planes x ng
 };
 
+// one recorded kernel launch (a context stepping in record mode, for a multi-instance batch):
+// the kernel's multi-instance form, launch shape, and its packed arguments
+struct RecLaunch {
+  const void* fn = nullptr;
+  unsigned grid[3] = {1, 1, 1}, block[3] = {1, 1, 1};
+  size_t shm = 0, asize = 0, aalign = 1;
+  std::vector<unsigned char> args;
+};
+
 }  // namespace pfd
 
 struct pfd_ctx {
@@ -180,6 +189,8 @@ struct pfd_ctx {
   unsigned long graph_gen = 0;             // bumped whenever captured launches become stale
   // per-kernel-class timing (pfd_profile_enable / pfd_profile_read)
   int prof_on = 0;
+  // record mode: launches are appended here instead of being issued (nullptr: issue them)
+  std::vector<pfd::RecLaunch>* rec = nullptr;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> prof_rec;   // (class, index of the start event)

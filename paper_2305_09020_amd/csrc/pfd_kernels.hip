@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "pfd_internal.h"
+#include "pfd_launch.h"
 
 namespace pfd {
 
@@ -105,9 +106,9 @@ __device__ __forceinline__ void wdxy(const ElemLDS& s, int n, int a, int b, cons
 // its own L2.  xcd_tile maps a 2D grid's linear id to a logical tile (bx, by), bx fastest, so that
 // each XCD takes one contiguous range of logical tiles: neighbouring tiles, which share halo rows
 // or element edges, are then read through one L2.  A bijection of the grid for any size.
-__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+__device__ __forceinline__ void xcd_tile(const VGrid& vg, int& bx, int& by) {
   constexpr int NXCD = 8;
-  const int gx = gridDim.x, total = gx * gridDim.y, lin = blockIdx.x + gx * blockIdx.y;
+  const int gx = vg.g.x, total = gx * vg.g.y, lin = vg.b.x + gx * vg.b.y;
   const int q = total / NXCD, r = total - q * NXCD, x = lin % NXCD, j = lin / NXCD;
   const int lb = x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
   by = lb / gx;
@@ -115,9 +116,9 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 }
 // the same with by fastest in the logical order: the tiles of one bx (which share a streamed
 // operand block) land on one XCD
-__device__ __forceinline__ void xcd_tile_yfast(int& bx, int& by) {
+__device__ __forceinline__ void xcd_tile_yfast(const VGrid& vg, int& bx, int& by) {
   constexpr int NXCD = 8;
-  const int gy = gridDim.y, total = gridDim.x * gy, lin = blockIdx.x + gridDim.x * blockIdx.y;
+  const int gy = vg.g.y, total = vg.g.x * gy, lin = vg.b.x + vg.g.x * vg.b.y;
   const int q = total / NXCD, r = total - q * NXCD, x = lin % NXCD, j = lin / NXCD;
   const int lb = x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
   bx = lb / gy;
@@ -126,7 +127,7 @@ __device__ __forceinline__ void xcd_tile_yfast(int& bx, int& by) {
 
 #define ELEM_PROLOGUE                                                    \
   int e, pgrp;                                                           \
-  xcd_tile(e, pgrp);                                                     \
+  xcd_tile(vg, e, pgrp);                                                     \
   const int ex = e % g.nx, ey = e / g.nx;                                \
   const int n = g.n, nq = g.nq;                                          \
   const int sub = (int)threadIdx.x / nq, t = (int)threadIdx.x - sub * nq; \
@@ -199,7 +200,7 @@ __device__ __forceinline__ double dss(const Geo& g, const double* L, int pl, int
 }
 
 #define NODAL_PROLOGUE                                                   \
-  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;           \
+  const long id = (long)vg.b.x * blockDim.x + threadIdx.x;           \
   if (id >= (long)g.planes * g.Ng) return;                               \
   const int pl = (int)(id / g.Ng);                                       \
   const int node = (int)(id - (long)pl * g.Ng);                          \
@@ -273,7 +274,7 @@ __device__ __forceinline__ void rhs_out(const Geo& g, const Par& P, const Lift& 
 
 // =================================================================== stage V (eq. 54)
 // L0 = -int (eps(phi*) - eps0) grad V* . grad e   (element-local)
-__global__ void __launch_bounds__(WG) k_V_elem(Geo g, Par P, const double* phn, const double* pho,
+__device__ __forceinline__ void k_V_elem_run(const VGrid& vg, Geo g, Par P, const double* phn, const double* pho,
                                                const double* Vn, const double* Vo, double* L0) {
   ELEM_PROLOGUE
   ELEM_ARRAY(sV)
@@ -300,17 +301,19 @@ __global__ void __launch_bounds__(WG) k_V_elem(Geo g, Par P, const double* phn, 
     L0[lofs] = -(0.5 * hy * s.w[b] * wx + 0.5 * hx * s.w[a] * wy);
   }
 }
+struct k_V_elem : KDef<&k_V_elem_run, WG, 0> {};
 
 // b = (DSS(L0) - M f_V)/eps0, Dirichlet values from VD
-__global__ void k_V_rhs(Geo g, Par P, Lift L, const double* L0, const double* Mdiag, const double* fV,
+__device__ __forceinline__ void k_V_rhs_run(const VGrid& vg, Geo g, Par P, Lift L, const double* L0, const double* Mdiag, const double* fV,
                         const double* Vd, const double* Fn, const double* Fo, double* bb, double* r, double* x0) {
   NODAL_PROLOGUE
   const double v = dss(g, L0, pl, ix, iy) - Mdiag[node] * fV[id];
   rhs_out(g, P, L, Vd, Fn, Fo, id, (long)pl * g.Ng, ix, iy, v / P.eps0, bb, r, x0);
 }
+struct k_V_rhs : KDef<&k_V_rhs_run, 0, 0> {};
 
 // =================================================================== stage E (eq. 55)
-__global__ void __launch_bounds__(WG) k_E_elem(Geo g, const double* V, double* L0, double* L1) {
+__device__ __forceinline__ void k_E_elem_run(const VGrid& vg, Geo g, const double* V, double* L0, double* L1) {
   ELEM_PROLOGUE
   ELEM_ARRAY(sV)
   if (act) sV[t] = V[pofs + gi];
@@ -324,8 +327,9 @@ __global__ void __launch_bounds__(WG) k_E_elem(Geo g, const double* V, double* L
     L1[lofs] = wq * dy[0];
   }
 }
+struct k_E_elem : KDef<&k_E_elem_run, WG, 0> {};
 
-__global__ void k_E_nodal(Geo g, const double* L0, const double* L1, const double* Mdiag,
+__device__ __forceinline__ void k_E_nodal_run(const VGrid& vg, Geo g, const double* L0, const double* L1, const double* Mdiag,
                           const double* Ez, double* Ex, double* Ey, double* E2) {
   NODAL_PROLOGUE
   double m = Mdiag[node];
@@ -335,10 +339,11 @@ __global__ void k_E_nodal(Geo g, const double* L0, const double* L1, const doubl
   double ez = Ez ? Ez[id] : 0.0;
   E2[id] = ex * ex + ey * ey + ez * ez;
 }
+struct k_E_nodal : KDef<&k_E_nodal_run, 0, 0> {};
 
 // =================================================================== stage psi (eq. 56)
 // L0 = -int Q1 w + int grad Q2 . grad w ;  Q2 also written (nodal, same at shared nodes)
-__global__ void __launch_bounds__(WG) k_psi_elem(Geo g, Par P, const double* phn, const double* pho,
+__device__ __forceinline__ void k_psi_elem_run(const VGrid& vg, Geo g, Par P, const double* phn, const double* pho,
                                                  const double* uxn, const double* uxo, const double* uyn,
                                                  const double* uyo, const double* E2, const double* gsrc,
                                                  const double* uzn, const double* uzo, const double* dzphs,
@@ -385,10 +390,11 @@ __global__ void __launch_bounds__(WG) k_psi_elem(Geo g, Par P, const double* phn
     L0[lofs] = -wq * q1 + 0.5 * hy * s.w[b] * wx + 0.5 * hx * s.w[a] * wy;
   }
 }
+struct k_psi_elem : KDef<&k_psi_elem_run, WG, 0> {};
 
 // b_psi = DSS(L0) + Bo (g1 + c_psi g2) + Bs (g1 + c_psi U);  U = -g3 - Theta'(phi*)/lambda
 // also stores U (reused by the phi stage) and x0 = psi*
-__global__ void k_psi_rhs(Geo g, Par P, const double* L0, const double* bmo, const double* bmw,
+__device__ __forceinline__ void k_psi_rhs_run(const VGrid& vg, Geo g, Par P, const double* L0, const double* bmo, const double* bmw,
                           const double* g1, const double* g2, const double* g3, const double* phn,
                           const double* pho, const double* E2, const double* Fn, const double* Fo,
                           double* bb, double* U, double* Q2, double* r, double* x0, const double* bprev) {
@@ -409,9 +415,10 @@ __global__ void k_psi_rhs(Geo g, Par P, const double* L0, const double* bmo, con
     x0[id] = 0.0;
   }
 }
+struct k_psi_rhs : KDef<&k_psi_rhs_run, 0, 0> {};
 
 // =================================================================== stage phi (eq. 57)
-__global__ void k_phi_rhs(Geo g, Par P, const double* Mdiag, const double* psi, const double* bmo,
+__device__ __forceinline__ void k_phi_rhs_run(const VGrid& vg, Geo g, Par P, const double* Mdiag, const double* psi, const double* bmo,
                           const double* bmw, const double* g2, const double* U, const double* Fn,
                           const double* Fo, double* bb, double* r, double* x0, const double* bprev) {
   NODAL_PROLOGUE
@@ -426,6 +433,7 @@ __global__ void k_phi_rhs(Geo g, Par P, const double* Mdiag, const double* psi, 
     x0[id] = 0.0;
   }
 }
+struct k_phi_rhs : KDef<&k_phi_rhs_run, 0, 0> {};
 
 // optional 3D inputs / outputs of the momentum element kernel (Algorithm 2):
 // z-derivatives come from the spectral representation (nodal values, one per node)
@@ -441,7 +449,7 @@ struct Mom3 {
 // 3D (Z3): the parts multiplied by i beta_k in the per-mode forms go to LBP, LBx, LBy, and the
 //          z velocity right side to LAz (G, omega*, K are full 3-vectors there).
 template <bool Z3>
-__global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi, const double* psi,
+__device__ __forceinline__ void k_mom_elem_run(const VGrid& vg, Geo g, Par P, const double* phi, const double* psi,
                                                  const double* E2, const double* Q2,
                                                  const double* uxn, const double* uxo, const double* uyn,
                                                  const double* uyo, const double* Pn, const double* Po,
@@ -649,9 +657,11 @@ __global__ void __launch_bounds__(WG) k_mom_elem(Geo g, Par P, const double* phi
     }
   }
 }
+template <bool Z3>
+struct k_mom_elem : KDef<&k_mom_elem_run<Z3>, WG, 0> {};
 
 // b_P = DSS(L0) - rho0 gamma0/dt sum_walls int (n.w) q ;  x0 = P* (f2 on open sides)
-__global__ void k_P_rhs(Geo g, Par P, Lift L, const double* L0, const double* wx, const double* wy,
+__device__ __forceinline__ void k_P_rhs_run(const VGrid& vg, Geo g, Par P, Lift L, const double* L0, const double* wx, const double* wy,
                         const double* f2, const double* Fn, const double* Fo, double* bb, double* r, double* x0) {
   NODAL_PROLOGUE
   double v = dss(g, L0, pl, ix, iy);
@@ -661,10 +671,11 @@ __global__ void k_P_rhs(Geo g, Par P, Lift L, const double* L0, const double* wx
     if (g.side_type[sd] == PFD_WALL) v -= c * g.bm_side[sd][node] * nw[sd];
   rhs_out(g, P, L, f2, Fn, Fo, id, (long)pl * g.Ng, ix, iy, v, bb, r, x0);
 }
+struct k_P_rhs : KDef<&k_P_rhs_run, 0, 0> {};
 
 // u right side: add -(1/(nu_m rho0)) int grad P^{n+1} v to L1, L2 (and to LAz in 3D, with the
 // z-derivative dzP taken from the spectral pressure)
-__global__ void __launch_bounds__(WG) k_gradP_elem(Geo g, Par P, const double* Pnew, const double* dzP,
+__device__ __forceinline__ void k_gradP_elem_run(const VGrid& vg, Geo g, Par P, const double* Pnew, const double* dzP,
                                                    double* L1, double* L2, double* LAz) {
   ELEM_PROLOGUE
   ELEM_ARRAY(sP)
@@ -691,9 +702,10 @@ __global__ void __launch_bounds__(WG) k_gradP_elem(Geo g, Par P, const double* P
     if (dzP) LAz[lofs] = laz + c * dzp;
   }
 }
+struct k_gradP_elem : KDef<&k_gradP_elem_run, WG, 0> {};
 
 // b_u = DSS(L) + Bo f1 ; x0 = u* with w on walls (two components)
-__global__ void k_u_rhs(Geo g, Par P, Lift L, const double* L1, const double* L2, const double* bmo,
+__device__ __forceinline__ void k_u_rhs_run(const VGrid& vg, Geo g, Par P, Lift L, const double* L1, const double* L2, const double* bmo,
                         const double* f1x, const double* f1y, const double* wx, const double* wy,
                         const double* Fxn, const double* Fxo, const double* Fyn, const double* Fyo,
                         double* bx, double* by, double* rx, double* ry, double* x0x, double* x0y) {
@@ -704,23 +716,26 @@ __global__ void k_u_rhs(Geo g, Par P, Lift L, const double* L1, const double* L2
   rhs_out(g, P, L, wx, Fxn, Fxo, id, pofs, ix, iy, dss(g, L1, pl, ix, iy) + bmo[node] * f1x[id], bx, rx, x0x);
   rhs_out(g, P, Ly, wy, Fyn, Fyo, id, pofs, ix, iy, dss(g, L2, pl, ix, iy) + bmo[node] * f1y[id], by, ry, x0y);
 }
+struct k_u_rhs : KDef<&k_u_rhs_run, 0, 0> {};
 
-__global__ void k_fill(long N, double* f, double v) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_fill_run(const VGrid& vg, long N, double* f, double v) {
+  const long i = (long)vg.b.x * blockDim.x + threadIdx.x;
   if (i < N) f[i] = v;
 }
+struct k_fill : KDef<&k_fill_run, 0, 0> {};
 
 // non-finite guard on a field: sets status[0]
 // sticky non-finite flag over f (and f2 when given), one launch
-__global__ void k_check_finite(long N, const double* f, const double* f2, int* status) {
-  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_check_finite_run(const VGrid& vg, long N, const double* f, const double* f2, int* status) {
+  long i = (long)vg.b.x * blockDim.x + threadIdx.x;
   bool bad = false;
-  for (; i < N; i += (long)gridDim.x * blockDim.x) {
+  for (; i < N; i += (long)vg.g.x * blockDim.x) {
     if (!isfinite(f[i])) bad = true;
     if (f2 && !isfinite(f2[i])) bad = true;
   }
   if (bad) atomicOr(status, 1);
 }
+struct k_check_finite : KDef<&k_check_finite_run, 0, 0> {};
 
 // =================================================================== solves
 // Convergence test of the iterative refinement, taken on every FP64 residual r = b - A x the
@@ -770,11 +785,11 @@ __device__ __forceinline__ void block_sum2(double& a, double& x, double* red) {
 
 // Called by every thread of a residual work-group after its nodes were summed into
 // (r2, ax2): the work-group's partial sums
-__device__ void chk_store(const Chk& ck, double r2, double ax2) {
+__device__ void chk_store(const VGrid& vg, const Chk& ck, double r2, double ax2) {
   __shared__ double red[32];
   block_sum2(r2, ax2, red);
   if (threadIdx.x == 0) {
-    const long bid = blockIdx.x + (long)gridDim.x * blockIdx.y;
+    const long bid = vg.b.x + (long)vg.g.x * vg.b.y;
     ck.part[2 * bid] = r2;
     ck.part[2 * bid + 1] = ax2;
   }
@@ -783,7 +798,7 @@ __device__ void chk_store(const Chk& ck, double r2, double ax2) {
 // One work-group: the test of the nblk partial sums the residual kernel before it stored.
 // stat (family record): corrections, eta, max corrections, failed solves; status[1] gets bit
 // fam when the test after the last allowed correction fails.
-__global__ void __launch_bounds__(256) k_chk_decide(const double* __restrict__ part, long nblk,
+__device__ __forceinline__ void k_chk_decide_run(const VGrid& vg, const double* __restrict__ part, long nblk,
                                                     const int* __restrict__ gin, int* __restrict__ gate,
                                                     double* __restrict__ stat, int* __restrict__ status,
                                                     double tol, int it, int last, int fam) {
@@ -810,6 +825,7 @@ __global__ void __launch_bounds__(256) k_chk_decide(const double* __restrict__ p
     }
   }
 }
+struct k_chk_decide : KDef<&k_chk_decide_run, 256, 0> {};
 
 // Copies n values into LDS with U independent loads in flight per thread: value(idx) is read for
 // every idx < n (the caller clamps addresses and masks values, so there is no branch around a
@@ -838,7 +854,7 @@ __device__ __forceinline__ void stage_lds(int n, Value value, Store store) {
 // Kx[ix][ix+d] (periodic wrap in x; zero outside the band), so consecutive threads read
 // consecutive coefficients.  apply_only = 1 computes y = A x on every node.
 template <int K>
-__global__ void __launch_bounds__(WG) k_residual(int Nx, int Ny, int planes, int perx, const double* __restrict__ KxB,
+__device__ __forceinline__ void k_residual_run(const VGrid& vg, int Nx, int Ny, int planes, int perx, const double* __restrict__ KxB,
                            const double* __restrict__ Mx, const unsigned char* __restrict__ dirx,
                            const double* __restrict__ KyB, const double* __restrict__ My,
                            const unsigned char* __restrict__ diry, const double* __restrict__ shift,
@@ -846,7 +862,7 @@ __global__ void __launch_bounds__(WG) k_residual(int Nx, int Ny, int planes, int
                            int apply_only, const unsigned char* __restrict__ ebot, Chk ck) {
   if (ck.gin && *ck.gin) return;
   const long Ng = (long)Nx * Ny;
-  const long id0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long id0 = (long)vg.b.x * blockDim.x + threadIdx.x;
   double r2 = 0.0, ax2 = 0.0;
   if (id0 < planes * Ng) {
   const long id = id0;
@@ -887,8 +903,10 @@ __global__ void __launch_bounds__(WG) k_residual(int Nx, int Ny, int planes, int
     }
   }
   }
-  if (ck.part) chk_store(ck, r2, ax2);
+  if (ck.part) chk_store(vg, ck, r2, ax2);
 }
+template <int K>
+struct k_residual : KDef<&k_residual_run<K>, WG, 0> {};
 
 // LDS-tiled variant of k_residual: a work-group takes RROWS rows of one plane; the rows
 // iy0-K .. iy0+RROWS-1+K of x are staged in LDS once (coalesced), each with K halo entries on
@@ -908,7 +926,7 @@ __host__ __device__ constexpr long res_rows_lds(int K, int Nx) {
 }
 
 template <int K, class Out>
-__device__ __forceinline__ void res_rows(int Nx, int Ny, int perx, const double* __restrict__ KxB,
+__device__ __forceinline__ void res_rows(const VGrid& vg, int Nx, int Ny, int perx, const double* __restrict__ KxB,
                                          const double* __restrict__ Mx, const unsigned char* __restrict__ dirx,
                                          const double* __restrict__ KyB, const double* __restrict__ My,
                                          const unsigned char* __restrict__ diry, const double* __restrict__ shift,
@@ -920,7 +938,7 @@ __device__ __forceinline__ void res_rows(int Nx, int Ny, int perx, const double*
   double* myl = kyl + RROWS * NB;   // [RROWS] M_y
   double* dyl = myl + RROWS;        // [RROWS] Dirichlet flag of the row
   int rb, pl;
-  xcd_tile(rb, pl);
+  xcd_tile(vg, rb, pl);
   const int iy0 = rb * RROWS;
   const long Ng = (long)Nx * Ny;
   const double* xp = x + pl * Ng;
@@ -987,7 +1005,7 @@ __device__ __forceinline__ void res_rows(int Nx, int Ny, int perx, const double*
 }
 
 template <int K>
-__global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, const double* __restrict__ KxB,
+__device__ __forceinline__ void k_residual_lds_run(const VGrid& vg, int Nx, int Ny, int perx, const double* __restrict__ KxB,
                                                       const double* __restrict__ Mx,
                                                       const unsigned char* __restrict__ dirx,
                                                       const double* __restrict__ KyB, const double* __restrict__ My,
@@ -1000,10 +1018,10 @@ __global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* xs = reinterpret_cast<double*>(smem_raw);
   int rb, pl;
-  xcd_tile(rb, pl);   // the tile res_rows takes
+  xcd_tile(vg, rb, pl);   // the tile res_rows takes
   const long Ng = (long)Nx * Ny, pofs = (long)pl * Ng;
   double r2 = 0.0, x2 = 0.0;
-  res_rows<K>(Nx, Ny, perx, KxB, Mx, dirx, KyB, My, diry, shift, bb, x, apply_only, ebot, xs,
+  res_rows<K>(vg, Nx, Ny, perx, KxB, Mx, dirx, KyB, My, diry, shift, bb, x, apply_only, ebot, xs,
               [&](int, int iy, int ix, double v, double bv, double xv) {
                 r[pofs + (long)iy * Nx + ix] = v;
                 r2 += v * v;
@@ -1011,9 +1029,11 @@ __global__ void __launch_bounds__(256) k_residual_lds(int Nx, int Ny, int perx, 
               });
   if (ck.part) {
     const double an = ck.anorm[pl % ck.nplane];
-    chk_store(ck, r2, an * an * x2);
+    chk_store(vg, ck, r2, an * an * x2);
   }
 }
+template <int K>
+struct k_residual_lds : KDef<&k_residual_lds_run<K>, 256, 0> {};
 
 // Batched GEMM on the matrix cores for the fast-diagonalisation passes:
 //   C[p] (M x N) = A[p] (M x K) * B[p] (K x N), row-major, plane strides sA, sB (0: shared).
@@ -1048,7 +1068,7 @@ struct Mfma<float> {
 };
 
 template <typename T, typename TA, typename TB, int EPI>
-__global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA, const TB* __restrict__ B, long sB,
+__device__ __forceinline__ void k_gemm_run(const VGrid& vg, const TA* __restrict__ A, long sA, const TB* __restrict__ B, long sB,
                                               int M, int N, int K, T* __restrict__ C, long sC,
                                               const double* __restrict__ lr, const double* __restrict__ lc,
                                               const double* __restrict__ shift, double* __restrict__ X,
@@ -1061,7 +1081,7 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA,
   __shared__ T red[4][4][64];
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
-  const int n0 = blockIdx.x * 16, m0 = blockIdx.y * 16, pl = blockIdx.z;
+  const int n0 = vg.b.x * 16, m0 = vg.b.y * 16, pl = vg.b.z;
   const int m = m0 + r16, n = n0 + r16;
   const bool mok = m < M, nok = n < N;
   const TA* Arow = A + pl * sA + (long)(mok ? m : 0) * K;
@@ -1125,6 +1145,8 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA,
     }
   }
 }
+template <typename T, typename TA, typename TB, int EPI>
+struct k_gemm : KDef<&k_gemm_run<T, TA, TB, EPI>, 256, 0> {};
 
 // Register-blocked batched GEMM (same operands, layout and epilogues as k_gemm): one wave
 // computes a (16 TM) x (16 TN) block of C with TM*TN accumulator tiles, so each loaded A
@@ -1132,7 +1154,7 @@ __global__ void __launch_bounds__(256) k_gemm(const TA* __restrict__ A, long sA,
 // the 16-wide contraction slices w, w+SK, ... and their partial blocks are summed through LDS
 // in a fixed order.  The next slice's fragments are loaded while the current one is multiplied.
 template <typename T, typename TA, typename TB, int EPI, int TM, int TN, int SK>
-__global__ void __launch_bounds__(64 * SK) k_gemmt(const TA* __restrict__ A, long sA, const TB* __restrict__ B,
+__device__ __forceinline__ void k_gemmt_run(const VGrid& vg, const TA* __restrict__ A, long sA, const TB* __restrict__ B,
                                                    long sB, int M, int N, int K, T* __restrict__ C, long sC,
                                                    const double* __restrict__ lr, const double* __restrict__ lc,
                                                    const double* __restrict__ shift, double* __restrict__ X,
@@ -1144,7 +1166,7 @@ __global__ void __launch_bounds__(64 * SK) k_gemmt(const TA* __restrict__ A, lon
   __shared__ T red[NR][TM * TN * 4][64];
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
-  const int n0 = blockIdx.x * 16 * TN, m0 = blockIdx.y * 16 * TM, pl = blockIdx.z;
+  const int n0 = vg.b.x * 16 * TN, m0 = vg.b.y * 16 * TM, pl = vg.b.z;
   const TA* Ap = A + pl * sA;
   const TB* Bp = B + pl * sB;
   const TB* B2p = B2 ? B2 + pl * sB : nullptr;
@@ -1265,6 +1287,8 @@ __global__ void __launch_bounds__(64 * SK) k_gemmt(const TA* __restrict__ A, lon
       }
     }
 }
+template <typename T, typename TA, typename TB, int EPI, int TM, int TN, int SK>
+struct k_gemmt : KDef<&k_gemmt_run<T, TA, TB, EPI, TM, TN, SK>, 64 * SK, 0> {};
 
 // Small-operand-in-LDS batched GEMMs.  In every product of the solves and z transforms one
 // operand is a small shared matrix S (a 1D eigenvector matrix or a DFT matrix, <= 320^2) and the
@@ -1280,7 +1304,7 @@ __global__ void __launch_bounds__(64 * SK) k_gemmt(const TA* __restrict__ A, lon
 #define GEMM_CHUNK 4
 
 template <typename T, typename TA, int EPI, int W, int SK>
-__global__ void __launch_bounds__(256) k_gemm_sr(const TA* __restrict__ A, const T* __restrict__ S, int Mtot,
+__device__ __forceinline__ void k_gemm_sr_run(const VGrid& vg, const TA* __restrict__ A, const T* __restrict__ S, int Mtot,
                                                  int N, int K, T* __restrict__ C, double* __restrict__ X,
     const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
@@ -1292,7 +1316,7 @@ __global__ void __launch_bounds__(256) k_gemm_sr(const TA* __restrict__ A, const
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
   int tbx, tby;
-  xcd_tile_yfast(tbx, tby);   // row tile tbx, column block tby
+  xcd_tile_yfast(vg, tbx, tby);   // row tile tbx, column block tby
   const int n0 = tby * 16 * W;
   const int ms = w % WS, ks = w / WS;
   const int m = (tbx * WS + ms) * 16 + r16;
@@ -1392,9 +1416,11 @@ __global__ void __launch_bounds__(256) k_gemm_sr(const TA* __restrict__ A, const
     }
   }
 }
+template <typename T, typename TA, int EPI, int W, int SK>
+struct k_gemm_sr : KDef<&k_gemm_sr_run<T, TA, EPI, W, SK>, 256, 0> {};
 
 template <typename T, typename TB, int EPI, int W, int SK>
-__global__ void __launch_bounds__(256) k_gemm_sl(const T* __restrict__ S, const TB* __restrict__ B, long sB, int planes,
+__device__ __forceinline__ void k_gemm_sl_run(const VGrid& vg, const T* __restrict__ S, const TB* __restrict__ B, long sB, int planes,
                                                  int M, int N, int K, T* __restrict__ C, long sC,
                                                  const double* __restrict__ lr, const double* __restrict__ lc,
                                                  const double* __restrict__ shift, const TB* __restrict__ B2,
@@ -1409,7 +1435,7 @@ __global__ void __launch_bounds__(256) k_gemm_sl(const T* __restrict__ S, const 
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
   int tbx, tby;
-  xcd_tile_yfast(tbx, tby);   // column tile tbx, row block tby
+  xcd_tile_yfast(vg, tbx, tby);   // column tile tbx, row block tby
   const int m0 = tby * 16 * W;
   const int ms = w % WS, ks = w / WS;
   const long ctot = (long)planes * N;
@@ -1516,6 +1542,8 @@ __global__ void __launch_bounds__(256) k_gemm_sl(const T* __restrict__ S, const 
       }
     }
 }
+template <typename T, typename TB, int EPI, int W, int SK>
+struct k_gemm_sl : KDef<&k_gemm_sl_run<T, TB, EPI, W, SK>, 256, 0> {};
 
 // Configurations the autotuner chooses from.  0..7: register-blocked k_gemm / k_gemmt tiles
 // {TM, TN, SK} (entry 0 is k_gemm: 16 x 16 tile, four-wave split K); 8..15: the LDS kernels
@@ -1547,7 +1575,7 @@ static bool gemm_launch(pfd_ctx* c, int cfg, int cls, int planes, const TA* A, l
         dim3 grid((Mtot + 16 * WS - 1) / (16 * WS), (N + 16 * W - 1) / (16 * W));
 #define SR_CASE(W_, SK_)                                                                                   \
   if (W == W_ && SK == SK_)                                                                                \
-    hipLaunchKernelGGL((k_gemm_sr<T, TA, EPI, W_, SK_>), grid, dim3(256), lds, c->stream, A, (const T*)B, Mtot, N, \
+    Kern<k_gemm_sr<T, TA, EPI, W_, SK_>>::launch(c, -1, grid, dim3(256), lds, c->stream, A, (const T*)B, Mtot, N, \
                        K, C, X, c->gate);
         SR_CASE(1, 1) SR_CASE(2, 1) SR_CASE(3, 1) SR_CASE(1, 2) SR_CASE(2, 2) SR_CASE(3, 2) SR_CASE(1, 4)
         SR_CASE(2, 4)
@@ -1561,7 +1589,7 @@ static bool gemm_launch(pfd_ctx* c, int cfg, int cls, int planes, const TA* A, l
       dim3 grid((unsigned)((ctot + 16 * WS - 1) / (16 * WS)), (M + 16 * W - 1) / (16 * W));
 #define SL_CASE(W_, SK_)                                                                                   \
   if (W == W_ && SK == SK_)                                                                                \
-    hipLaunchKernelGGL((k_gemm_sl<T, TB, EPI, W_, SK_>), grid, dim3(256), lds, c->stream, (const T*)A, B, sB,     \
+    Kern<k_gemm_sl<T, TB, EPI, W_, SK_>>::launch(c, -1, grid, dim3(256), lds, c->stream, (const T*)A, B, sB,     \
                        planes, M, N, K, C, sC, lr, lc, shift, B2, cb1, cb2, c->gate);
       SL_CASE(1, 1) SL_CASE(2, 1) SL_CASE(3, 1) SL_CASE(1, 2) SL_CASE(2, 2) SL_CASE(3, 2) SL_CASE(1, 4)
       SL_CASE(2, 4)
@@ -1574,12 +1602,12 @@ static bool gemm_launch(pfd_ctx* c, int cfg, int cls, int planes, const TA* A, l
   dim3 grid((N + 16 * q.tn - 1) / (16 * q.tn), (M + 16 * q.tm - 1) / (16 * q.tm), planes);
 #define GEMMT_CASE(ID, TM_, TN_, SK_)                                                                  \
   case ID:                                                                                             \
-    hipLaunchKernelGGL((k_gemmt<T, TA, TB, EPI, TM_, TN_, SK_>), grid, dim3(64 * SK_), 0, c->stream, A, sA, B, \
+    Kern<k_gemmt<T, TA, TB, EPI, TM_, TN_, SK_>>::launch(c, -1, grid, dim3(64 * SK_), 0, c->stream, A, sA, B, \
                        sB, M, N, K, C, sC, lr, lc, shift, X, B2, cb1, cb2, c->gate);                   \
     break;
   switch (cfg) {
     case 0:
-      hipLaunchKernelGGL((k_gemm<T, TA, TB, EPI>), grid, dim3(256), 0, c->stream, A, sA, B, sB, M, N, K, C, sC, lr,
+      Kern<k_gemm<T, TA, TB, EPI>>::launch(c, -1, grid, dim3(256), 0, c->stream, A, sA, B, sB, M, N, K, C, sC, lr,
                          lc, shift, X, B2, cb1, cb2, c->gate);
       break;
     GEMMT_CASE(1, 2, 2, 1)
@@ -1621,8 +1649,8 @@ static void gemm(pfd_ctx* c, int site, int planes, const TA* A, long sA, const T
 #define FDM_LDU 17                          // LDS row pitch of u (bank spread)
 #define FDM_MAXT ((PFD_NMAX + 63) / 64)     // output tiles per wave (20 tiles over 4 waves)
 
-__device__ __forceinline__ void fdm_map(int nstrip, int planes, int& p, int& st) {
-  const int L = blockIdx.x;
+__device__ __forceinline__ void fdm_map(const VGrid& vg, int nstrip, int planes, int& p, int& st) {
+  const int L = vg.b.x;
   if ((planes & 7) == 0) {
     const int xcd = L & 7, idx = L >> 3;
     p = xcd + 8 * (idx / nstrip);
@@ -1634,7 +1662,7 @@ __device__ __forceinline__ void fdm_map(int nstrip, int planes, int& p, int& st)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_fdm1(int planes, int Ny, int Nx, long Ng, const double* __restrict__ r,
+__device__ __forceinline__ void k_fdm1_run(const VGrid& vg, int planes, int Ny, int Nx, long Ng, const double* __restrict__ r,
                                               const T* __restrict__ SxT, const T* __restrict__ SyT,
                                               const double* __restrict__ ly, const double* __restrict__ lx,
                                               const double* __restrict__ shift, T* __restrict__ t,
@@ -1644,7 +1672,7 @@ __global__ void __launch_bounds__(256) k_fdm1(int planes, int Ny, int Nx, long N
   typedef typename Mfma<T>::V V;
   const int nstrip = (Nx + 15) >> 4, mtiles = (Ny + 15) >> 4;
   int p, cs;
-  fdm_map(nstrip, planes, p, cs);
+  fdm_map(vg, nstrip, planes, p, cs);
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), r16 = lane & 15, g = lane >> 4;
   const int n = cs * 16 + r16;
   const bool nok = n < Nx;
@@ -1724,9 +1752,11 @@ __global__ void __launch_bounds__(256) k_fdm1(int planes, int Ny, int Nx, long N
     }
   }
 }
+template <typename T>
+struct k_fdm1 : KDef<&k_fdm1_run<T>, 256, 0> {};
 
 template <typename T, bool OVERWRITE>
-__global__ void __launch_bounds__(256) k_fdm2(int planes, int Ny, int Nx, long Ng, const T* __restrict__ t,
+__device__ __forceinline__ void k_fdm2_run(const VGrid& vg, int planes, int Ny, int Nx, long Ng, const T* __restrict__ t,
                                               const T* __restrict__ Sy, const T* __restrict__ Sx,
                                               double* __restrict__ x,
     const int* __restrict__ gate) {
@@ -1736,7 +1766,7 @@ __global__ void __launch_bounds__(256) k_fdm2(int planes, int Ny, int Nx, long N
   const int nstrip = (Ny + 15) >> 4, ntiles = (Nx + 15) >> 4;
   const int ldv = ntiles * 16 + 1;
   int p, rs;
-  fdm_map(nstrip, planes, p, rs);
+  fdm_map(vg, nstrip, planes, p, rs);
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), r16 = lane & 15, g = lane >> 4;
   const T* tp = t + (long)p * Ng;
   // ---- v = Sy[strip, :] t: A operand row i = rs*16 + r16 of Sy (shared by the wave's tiles)
@@ -1818,6 +1848,8 @@ __global__ void __launch_bounds__(256) k_fdm2(int planes, int Ny, int Nx, long N
     }
   }
 }
+template <typename T, bool OVERWRITE>
+struct k_fdm2 : KDef<&k_fdm2_run<T, OVERWRITE>, 256, 0> {};
 
 // Deterministic per-plane sums: part[p*PCH + blk] = sum over chunk blk of w_i f_i
 // (w = M when weighted, else 1), for planes whose shift is 0 (singular operators).
@@ -1825,11 +1857,11 @@ __global__ void __launch_bounds__(256) k_fdm2(int planes, int Ny, int Nx, long N
 //   mode 0 (gauge int_h f = 0):    f -= (sum M f)/(sum M)
 //   mode 1 (range projection):     f -= (sum f)/(sum M) * M
 #define PCH 32
-__global__ void k_plane_sums(long Ng, const double* __restrict__ Mdiag, const double* __restrict__ shift,
+__device__ __forceinline__ void k_plane_sums_run(const VGrid& vg, long Ng, const double* __restrict__ Mdiag, const double* __restrict__ shift,
                              const double* __restrict__ f, int weighted, double* __restrict__ part,
     const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
-  const int blk = blockIdx.x, pl = blockIdx.y;
+  const int blk = vg.b.x, pl = vg.b.y;
   __shared__ double sm[WG];
   double a = 0.0;
   if (shift[pl] == 0.0) {
@@ -1846,12 +1878,13 @@ __global__ void k_plane_sums(long Ng, const double* __restrict__ Mdiag, const do
   }
   if (threadIdx.x == 0) part[pl * PCH + blk] = sm[0];
 }
+struct k_plane_sums : KDef<&k_plane_sums_run, 0, 0> {};
 
-__global__ void k_plane_sub(long Ng, int planes, const double* __restrict__ Mdiag, const double* __restrict__ shift,
+__device__ __forceinline__ void k_plane_sub_run(const VGrid& vg, long Ng, int planes, const double* __restrict__ Mdiag, const double* __restrict__ shift,
                             const double* __restrict__ part, double Mtot, int mode, double* __restrict__ f,
     const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
-  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long id = (long)vg.b.x * blockDim.x + threadIdx.x;
   if (id >= planes * Ng) return;
   const int pl = (int)(id / Ng);
   if (shift[pl] != 0.0) return;
@@ -1860,15 +1893,10 @@ __global__ void k_plane_sub(long Ng, int planes, const double* __restrict__ Mdia
   const long i = id - pl * Ng;
   f[id] -= (mode == 0) ? s / Mtot : s / Mtot * Mdiag[i];
 }
+struct k_plane_sub : KDef<&k_plane_sub_run, 0, 0> {};
 
 static inline unsigned nblk(long n) { return (unsigned)((n + WG - 1) / WG); }
 
-// launch with an optional timing scope (class as in pfd_profile_read)
-#define LAUNCH(cls, ...)            \
-  do {                              \
-    ProfScope _ps(c, cls);          \
-    hipLaunchKernelGGL(__VA_ARGS__); \
-  } while (0)
 
 ProfScope::ProfScope(pfd_ctx* ctx, int k) : c(ctx), cls(k), i0(0), on(ctx && ctx->prof_on) {
   if (!on) return;
@@ -1892,9 +1920,9 @@ ProfScope::~ProfScope() {
 static void plane_fix(pfd_ctx* c, int fam, double* f, int mode) {
   Family& F = c->fam[fam];
   const long tot = (long)c->planes * c->Ng;
-  LAUNCH(PFD_PROF_OTHER, k_plane_sums, dim3(PCH, c->planes), dim3(WG), 0, c->stream, c->Ng, c->Mdiag, F.dshift, f,
+  Kern<k_plane_sums>::launch(c, PFD_PROF_OTHER, dim3(PCH, c->planes), dim3(WG), 0, c->stream, c->Ng, c->Mdiag, F.dshift, f,
                      mode == 0 ? 1 : 0, c->d_part, c->gate);
-  LAUNCH(PFD_PROF_OTHER, k_plane_sub, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Ng, c->planes, c->Mdiag, F.dshift,
+  Kern<k_plane_sub>::launch(c, PFD_PROF_OTHER, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Ng, c->planes, c->Mdiag, F.dshift,
                      c->d_part, c->Mtot, mode, f, c->gate);
 }
 
@@ -1921,11 +1949,11 @@ static long residual(pfd_ctx* c, int fam, const double* b, const double* x, doub
 #define RES_CASE(KK)                                                                                      \
   case KK:                                                                                                \
     if (tiled)                                                                                            \
-      LAUNCH(PFD_PROF_RESID, k_residual_lds<KK>, dim3((c->Ny + RROWS - 1) / RROWS, planes), dim3(256), lds,     \
+      Kern<k_residual_lds<KK>>::launch(c, PFD_PROF_RESID, dim3((c->Ny + RROWS - 1) / RROWS, planes), dim3(256), lds,     \
              c->stream, c->Nx, c->Ny, (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, \
              r, apply_only, c->lift[fam].ebot, k);                                                        \
     else                                                                                                  \
-      LAUNCH(PFD_PROF_RESID, k_residual<KK>, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, planes,    \
+      Kern<k_residual<KK>>::launch(c, PFD_PROF_RESID, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, planes,    \
              (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, r, apply_only,     \
              c->lift[fam].ebot, k);                                                                       \
     break;
@@ -2052,7 +2080,7 @@ __device__ __forceinline__ void fdm_mid_pass(const T* __restrict__ Aw, const T* 
 // row tiles, so nine waves per work-group) three work-groups then fit a CU (27 of 28 wave
 // slots), and the grid of a 128-plane solve runs in one round.
 template <typename T, int RT, int TN>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 7 : 1))) k_fdm_mid(int planes, int Ny, int Nx, long Ng, const T* __restrict__ SyTw,
+__device__ __forceinline__ void k_fdm_mid_run(const VGrid& vg, int planes, int Ny, int Nx, long Ng, const T* __restrict__ SyTw,
                                                   const T* __restrict__ Syw, const T* __restrict__ T1,
                                                   const double* __restrict__ ly, const double* __restrict__ lx,
                                                   const double* __restrict__ shift, T* __restrict__ T3, int ldo,
@@ -2067,7 +2095,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(RT ==
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = blockDim.x >> 6, nt = blockDim.x;
   const int r16 = lane & 15, g = lane >> 4;
-  const long ctot = (long)planes * Nx, c0 = (long)blockIdx.x * CW;
+  const long ctot = (long)planes * Nx, c0 = (long)vg.b.x * CW;
   T afr[MidCh<T>::v][RT][4];   // the first fragments of Sy^T are in flight while T1 is staged
   fdm_mid_load<T, RT>(SyTw, 0, MT, MT, nw, w, lane, afr);
   // stage the T1 block (coalesced along the columns), SU loads in flight per thread (column
@@ -2141,6 +2169,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(RT ==
     }
   }
 }
+template <typename T, int RT, int TN>
+struct k_fdm_mid : KDef<&k_fdm_mid_run<T, RT, TN>, 1024, RT == 1 ? 7 : 1> {};
 
 // launch of k_fdm_mid for the y-direction operator dy; false if it does not apply (LDS)
 template <typename T>
@@ -2160,7 +2190,7 @@ static bool fdm_mid_launch(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const d
   const int cls = sizeof(T) == 8 ? PFD_PROF_GEMM64 : PFD_PROF_GEMM32;
 #define MID_CASE(RT_, TN_)                                                                                   \
   if (RT == RT_ && tn == TN_)                                                                                \
-    LAUNCH(cls, (k_fdm_mid<T, RT_, TN_>), grid, block, lds, c->stream, P, Ny, Nx, c->Ng, SyTw, Syw, t1, dy.dlam, \
+    Kern<k_fdm_mid<T, RT_, TN_>>::launch(c, cls, grid, block, lds, c->stream, P, Ny, Nx, c->Ng, SyTw, Syw, t1, dy.dlam, \
            dx.dlam, shift, t3, ldo, c->gate);
   MID_CASE(1, 1) MID_CASE(1, 2)
   if constexpr (sizeof(T) == 4) {   // two row tiles per wave only where the FP32 block fits
@@ -2178,7 +2208,7 @@ static bool fdm_mid_launch(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const d
 // entries Sx[16 sl + 4 (lane / 16) + s][16 nt + lane % 16].
 // NTW: column tiles per wave, ceil(KPX / 64) (3 up to Nx = 192, 4 up to 256).
 template <int K, int NTW>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8 && NTW == 3 ? 3 : 1))) k_res_p1(int Nx, int Ny, int perx, const double* __restrict__ KxB,
+__device__ __forceinline__ void k_res_p1_run(const VGrid& vg, int Nx, int Ny, int perx, const double* __restrict__ KxB,
                                                 const double* __restrict__ Mx, const unsigned char* __restrict__ dirx,
                                                 const double* __restrict__ KyB, const double* __restrict__ My,
                                                 const unsigned char* __restrict__ diry,
@@ -2194,7 +2224,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8
   for (int idx = threadIdx.x; idx < RROWS * LDR; idx += 256) Rl[idx] = 0.0f;
   __syncthreads();   // zero fill before the residual rows land (res_rows syncs after its staging)
   double r2 = 0.0, x2 = 0.0;
-  res_rows<K>(Nx, Ny, perx, KxB, Mx, dirx, KyB, My, diry, shift, bb, x, 0, ebot, xs,
+  res_rows<K>(vg, Nx, Ny, perx, KxB, Mx, dirx, KyB, My, diry, shift, bb, x, 0, ebot, xs,
               [&](int rl, int, int ix, double v, double bv, double xv) {
                 Rl[rl * LDR + ix] = float(v);
                 r2 += v * v;
@@ -2202,9 +2232,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8
               });
   if (ck.part) {   // the test's sums leave the registers before the matrix-core phase
     int rb0, pl0;
-    xcd_tile(rb0, pl0);
+    xcd_tile(vg, rb0, pl0);
     const double an = ck.anorm[pl0 % ck.nplane];
-    chk_store(ck, r2, an * an * x2);
+    chk_store(vg, ck, r2, an * an * x2);
   }
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r16 = lane & 15, g = lane >> 4;
@@ -2253,7 +2283,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8
         for (int k = 0; k < 4; ++k) bq[q][j][k] = bn[q][j][k];
   }
   int rb, pl;
-  xcd_tile(rb, pl);   // the tile res_rows took
+  xcd_tile(vg, rb, pl);   // the tile res_rows took
   const long Ng = (long)Nx * Ny, pofs = (long)pl * Ng;
   const int iy0 = rb * RROWS;
 #pragma unroll
@@ -2268,6 +2298,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8
     }
   }
 }
+template <int K, int NTW>
+struct k_res_p1 : KDef<&k_res_p1_run<K, NTW>, 256, K <= 8 && NTW == 3 ? 3 : 1> {};
 
 // Last fast-diagonalisation pass of the refined path, x (+)= T3 Sx^T, after k_fdm_mid wrote T3
 // (FP32) with the padded row stride KPX = Nx rounded up to 16: a lane then reads each A fragment
@@ -2277,14 +2309,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8
 // past Nx are masked to zero; fragments come CH slices per prefetched chunk.  EPI 2: x += ;
 // EPI 3: x = .
 template <int EPI, int TG, int CH>
-__global__ void __launch_bounds__(256) k_p4(const float* __restrict__ T3, int Mtot, int Nx, int KPX,
+__device__ __forceinline__ void k_p4_run(const VGrid& vg, const float* __restrict__ T3, int Mtot, int Nx, int KPX,
                                             const float* __restrict__ SxFw, double* __restrict__ X,
     const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef Mfma<float>::V V;
   const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
   const int KS = KPX / 16, NT = KS, NG = (NT + TG - 1) / TG, MT = (Mtot + 15) / 16;
-  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  const int wid = __builtin_amdgcn_readfirstlane((int)(vg.b.x * 4 + (threadIdx.x >> 6)));
   const int rt = wid / NG, grp = wid - rt * NG;
   if (rt >= MT) return;   // no barrier in this kernel: a whole wave leaves
   const int m = min(16 * rt + r16, Mtot - 1);   // clamped row; rows past Mtot are not stored
@@ -2345,6 +2377,8 @@ __global__ void __launch_bounds__(256) k_p4(const float* __restrict__ T3, int Mt
     }
   }
 }
+template <int EPI, int TG, int CH>
+struct k_p4 : KDef<&k_p4_run<EPI, TG, CH>, 256, 0> {};
 
 // k_p4 over P planes (tg column tiles per wave); false where it does not apply
 // form: 1..4 column tiles per wave with two-slice chunks, 6 one tile with four-slice chunks
@@ -2358,10 +2392,10 @@ static bool p4_launch(pfd_ctx* c, const Dir1D& dx, int P, const float* t3, doubl
 #define P4_CASE(F_, TG_, CH_)                                                                                 \
   if (form == F_) {                                                                                           \
     if (overwrite)                                                                                            \
-      LAUNCH(PFD_PROF_GEMM32, (k_p4<3, TG_, CH_>), grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x, \
+      Kern<k_p4<3, TG_, CH_>>::launch(c, PFD_PROF_GEMM32, grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x, \
              c->gate);                                                                                        \
     else                                                                                                      \
-      LAUNCH(PFD_PROF_GEMM32, (k_p4<2, TG_, CH_>), grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x, \
+      Kern<k_p4<2, TG_, CH_>>::launch(c, PFD_PROF_GEMM32, grid, block, 0, c->stream, t3, (int)Mtot, Nx, KPX, dx.fSw, x, \
              c->gate);                                                                                        \
   }
   P4_CASE(1, 1, 2) P4_CASE(2, 2, 2) P4_CASE(3, 3, 2) P4_CASE(4, 4, 2) P4_CASE(6, 1, 4)
@@ -2377,7 +2411,7 @@ static bool p4_launch(pfd_ctx* c, const Dir1D& dx, int P, const float* t3, doubl
 // matrix (up to 320^2 FP32) is read from L2 once per work-group instead of once per tile.
 // EPI 0: C = acc (FP32, row stride ldc); 2: X += acc; 3: X = acc.  Needs K, N <= 32 * 16.
 template <typename TA, int EPI>
-__global__ void __launch_bounds__(1024) k_srp(const TA* __restrict__ A, int lda, int Mtot, int K, int N,
+__device__ __forceinline__ void k_srp_run(const VGrid& vg, const TA* __restrict__ A, int lda, int Mtot, int K, int N,
                                               const float* __restrict__ SB, float* __restrict__ C,
                                               double* __restrict__ X, int ldc,
     const int* __restrict__ gate) {
@@ -2407,8 +2441,8 @@ __global__ void __launch_bounds__(1024) k_srp(const TA* __restrict__ A, int lda,
       v[u] = ok ? x : 0.f;
     }
   };
-  if (blockIdx.x < MT) load_tile(blockIdx.x);
-  for (int t = blockIdx.x; t < MT; t += gridDim.x) {
+  if (vg.b.x < MT) load_tile(vg.b.x);
+  for (int t = vg.b.x; t < MT; t += vg.g.x) {
     __syncthreads();   // the matrix is staged / the previous tile's rows are read
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -2419,7 +2453,7 @@ __global__ void __launch_bounds__(1024) k_srp(const TA* __restrict__ A, int lda,
       }
     }
     __syncthreads();
-    if (t + (int)gridDim.x < MT) load_tile(t + gridDim.x);
+    if (t + (int)vg.g.x < MT) load_tile(t + vg.g.x);
     for (int nt = w; nt < NT; nt += nw) {
       // two accumulators (even and odd slices) halve the dependent chain of matrix-core ops
       V acc = V{0.f, 0.f, 0.f, 0.f}, acc1 = V{0.f, 0.f, 0.f, 0.f};
@@ -2460,6 +2494,8 @@ __global__ void __launch_bounds__(1024) k_srp(const TA* __restrict__ A, int lda,
     }
   }
 }
+template <typename TA, int EPI>
+struct k_srp : KDef<&k_srp_run<TA, EPI>, 1024, 0> {};
 
 // bytes of LDS k_srp needs for a K x N matrix; 0 where it exceeds what a work-group may have
 static size_t srp_lds(pfd_ctx* c, int K, int N) {
@@ -2478,7 +2514,7 @@ static bool srp_launch(pfd_ctx* c, int P, const TA* A, int lda, int K, int N, co
   const int Mtot = P * c->Ny, MT = (Mtot + 15) / 16, NT = (N + 15) / 16;
   const int nw = NT < 16 ? NT : 16;
   const unsigned grid = (unsigned)std::min(MT, c->num_cu);
-  LAUNCH(PFD_PROF_GEMM32, (k_srp<TA, EPI>), dim3(grid), dim3(64 * nw), lds, c->stream, A, lda, Mtot, K, N, SB, C, X,
+  Kern<k_srp<TA, EPI>>::launch(c, PFD_PROF_GEMM32, dim3(grid), dim3(64 * nw), lds, c->stream, A, lda, Mtot, K, N, SB, C, X,
          ldc, c->gate);
   return true;
 }
@@ -2498,11 +2534,11 @@ static bool res_p1_launch(pfd_ctx* c, int fam, const double* b, const double* x,
 #define RP1_CASE(KK)                                                                                         \
   case KK:                                                                                                   \
     if (three)                                                                                               \
-      LAUNCH(PFD_PROF_RESID, (k_res_p1<KK, 3>), grid, dim3(256), lds, c->stream, c->Nx, c->Ny, (int)dx.periodic, \
+      Kern<k_res_p1<KK, 3>>::launch(c, PFD_PROF_RESID, grid, dim3(256), lds, c->stream, c->Nx, c->Ny, (int)dx.periodic, \
              dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, shift, b, x, c->lift[fam].ebot,                 \
              (const float*)dx.fSTw, t1, ck);                                                                 \
     else                                                                                                     \
-      LAUNCH(PFD_PROF_RESID, (k_res_p1<KK, 4>), grid, dim3(256), lds, c->stream, c->Nx, c->Ny, (int)dx.periodic, \
+      Kern<k_res_p1<KK, 4>>::launch(c, PFD_PROF_RESID, grid, dim3(256), lds, c->stream, c->Nx, c->Ny, (int)dx.periodic, \
              dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, shift, b, x, c->lift[fam].ebot,                 \
              (const float*)dx.fSTw, t1, ck);                                                                 \
     return true;
@@ -2527,13 +2563,13 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
   T* t2 = reinterpret_cast<T*>(c->tmp2);
   if (c->fdm_variant == 1) {
     const int cls = sizeof(T) == 8 ? PFD_PROF_GEMM64 : PFD_PROF_GEMM32;
-    LAUNCH(cls, k_fdm1<T>, dim3(P * ((Nx + 15) / 16)), dim3(256), 0, c->stream, P, Ny, Nx, Ng, r, SxT, SyT,
+    Kern<k_fdm1<T>>::launch(c, cls, dim3(P * ((Nx + 15) / 16)), dim3(256), 0, c->stream, P, Ny, Nx, Ng, r, SxT, SyT,
            dy.dlam, dx.dlam, shift, t1, c->gate);
     if (overwrite)
-      LAUNCH(cls, (k_fdm2<T, true>), dim3(P * ((Ny + 15) / 16)), dim3(256), 0, c->stream, P, Ny, Nx, Ng,
+      Kern<k_fdm2<T, true>>::launch(c, cls, dim3(P * ((Ny + 15) / 16)), dim3(256), 0, c->stream, P, Ny, Nx, Ng,
              (const T*)t1, Sy, Sx, x, c->gate);
     else
-      LAUNCH(cls, (k_fdm2<T, false>), dim3(P * ((Ny + 15) / 16)), dim3(256), 0, c->stream, P, Ny, Nx, Ng,
+      Kern<k_fdm2<T, false>>::launch(c, cls, dim3(P * ((Ny + 15) / 16)), dim3(256), 0, c->stream, P, Ny, Nx, Ng,
              (const T*)t1, Sy, Sx, x, c->gate);
     return;
   }
@@ -2579,14 +2615,14 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
 // Electrode gap nodes (potential family): with Y = A_FF^{-1} r_F from the base operator,
 //   t_G = r_G - A_GF Y,  dG = S_G^{-1} t_G  (S_G^{-1} per plane, FP64, from set-up)
 // where A_GF Y at gap node (g, 0) = Mx[g] sum_{iy=1..K} Ky[0][iy] Y(g, iy).
-__global__ void k_elec_gap(int Nx, int Ny, int K, long Ng, int ng, const int* __restrict__ gap,
+__device__ __forceinline__ void k_elec_gap_run(const VGrid& vg, int Nx, int Ny, int K, long Ng, int ng, const int* __restrict__ gap,
                            const double* __restrict__ Mx, const double* __restrict__ Ky0,
                            const double* __restrict__ r, const double* __restrict__ Y,
                            const double* __restrict__ Sinv, double* __restrict__ dG,
     const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   __shared__ double t[PFD_NMAX];
-  const int pl = blockIdx.x;
+  const int pl = vg.b.x;
   const double* rp = r + pl * Ng;
   const double* Yp = Y + pl * Ng;
   const int kmax = min(K, Ny - 1);
@@ -2604,16 +2640,17 @@ __global__ void k_elec_gap(int Nx, int Ny, int K, long Ng, int ng, const int* __
     dG[(long)pl * ng + i] = acc;
   }
 }
+struct k_elec_gap : KDef<&k_elec_gap_run, 0, 0> {};
 
 // z = -A_FG dG (nonzero in the gap columns, rows 1..K), and x += Y (+ dG on the gap nodes)
-__global__ void k_elec_z(int Nx, int Ny, int K, int planes, int ng, const int* __restrict__ gapidx,
+__device__ __forceinline__ void k_elec_z_run(const VGrid& vg, int Nx, int Ny, int K, int planes, int ng, const int* __restrict__ gapidx,
                          const double* __restrict__ Mx, const double* __restrict__ Ky0,
                          const double* __restrict__ dG, const double* __restrict__ Y, double* __restrict__ z,
                          double* __restrict__ x,
     const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   const long Ng = (long)Nx * Ny;
-  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long id = (long)vg.b.x * blockDim.x + threadIdx.x;
   if (id >= planes * Ng) return;
   const int pl = (int)(id / Ng);
   const int node = (int)(id - pl * Ng);
@@ -2628,6 +2665,7 @@ __global__ void k_elec_z(int Nx, int Ny, int K, int planes, int ng, const int* _
   z[id] = zv;
   x[id] += add;
 }
+struct k_elec_z : KDef<&k_elec_z_run, 0, 0> {};
 
 // one correction of the potential family with electrode gap nodes:
 //   x += A_FF^{-1}(r_F - A_FG dG) on F,  x += dG on G
@@ -2637,9 +2675,9 @@ static void elec_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const dou
   const long tot = (long)c->planes * c->Ng;
   double* z = c->r + tot;   // scratch block of r (the potential solve uses block 0)
   fdm_correct<T>(c, dx, dy, shift, Sx, SxT, Sy, SyT, r, c->Ybuf, true);
-  LAUNCH(PFD_PROF_OTHER, k_elec_gap, dim3(c->planes), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->K, c->Ng,
+  Kern<k_elec_gap>::launch(c, PFD_PROF_OTHER, dim3(c->planes), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->K, c->Ng,
          c->elec.ng, c->elec.d_gap, dx.dM1, dy.dK0, r, c->Ybuf, c->elec.d_Sinv, c->elec.d_dG, c->gate);
-  LAUNCH(PFD_PROF_OTHER, k_elec_z, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->K, c->planes,
+  Kern<k_elec_z>::launch(c, PFD_PROF_OTHER, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, c->K, c->planes,
          c->elec.ng, c->elec.d_gapidx, dx.dM1, dy.dK0, c->elec.d_dG, c->Ybuf, z, x, c->gate);
   fdm_correct<T>(c, dx, dy, shift, Sx, SxT, Sy, SyT, z, x);
 }
@@ -2689,7 +2727,7 @@ static void refine32(pfd_ctx* c, int fam, const double* b, double* x, int p0, in
   ck.nplane = per;
   // the test of the residual just formed: its partial sums -> gate and record
   auto decide = [&](long nb, int it, int last, const int* gin) {
-    LAUNCH(PFD_PROF_OTHER, k_chk_decide, dim3(1), dim3(256), 0, c->stream, (const double*)c->d_rpart, nb, gin,
+    Kern<k_chk_decide>::launch(c, PFD_PROF_OTHER, dim3(1), dim3(256), 0, c->stream, (const double*)c->d_rpart, nb, gin,
            c->d_gate, c->d_rstat + 4 * fam, c->d_status, c->refine_tol, it, last, fam);
   };
   const int maxit = c->refine_max;
@@ -2904,12 +2942,12 @@ hipError_t autotune(pfd_ctx* c) {
       c->lds_max = v;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) == hipSuccess && v > 0)
       c->hold_ticks = (long long)v / 2;   // kHz -> ticks in 0.5 ms
-    bool ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_srp<double, 0>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max) == hipSuccess;
-    ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_srp<float, 2>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max) == hipSuccess;
-    ok = ok && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_srp<float, 3>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max) == hipSuccess;
+    // the single- and multi-instance forms of the LDS-resident pass may take all of the LDS
+    bool ok = true;
+    for (const void* f : {Kern<k_srp<double, 0>>::single(), Kern<k_srp<double, 0>>::multi(),
+                          Kern<k_srp<float, 2>>::single(), Kern<k_srp<float, 2>>::multi(),
+                          Kern<k_srp<float, 3>>::single(), Kern<k_srp<float, 3>>::multi()})
+      ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, c->lds_max) == hipSuccess;
     if (!ok) {
       (void)hipGetLastError();
       c->lds_max = std::min(c->lds_max, 64 * 1024);
@@ -3039,8 +3077,8 @@ hipError_t update_E(pfd_ctx* c) {
     ztrans(c, c->Wd, c->spec[F_V][c->cur], c->fld[F_EZ][0], nullptr, 1.0, 0.0);
     Ez = c->fld[F_EZ][0];
   }
-  LAUNCH(PFD_PROF_ELEM, k_E_elem, eg, eb, 0, c->stream, g, FLD(F_V, 0), c->Lb[0], c->Lb[1]);
-  LAUNCH(PFD_PROF_NODAL, k_E_nodal, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, c->Lb[0], c->Lb[1], c->Mdiag,
+  Kern<k_E_elem>::launch(c, PFD_PROF_ELEM, eg, eb, 0, c->stream, g, FLD(F_V, 0), c->Lb[0], c->Lb[1]);
+  Kern<k_E_nodal>::launch(c, PFD_PROF_NODAL, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, c->Lb[0], c->Lb[1], c->Mdiag,
                      Ez, c->fld[F_EX][0], c->fld[F_EY][0], c->fld[F_E2][0]);
   return hipGetLastError();
 }
@@ -3058,9 +3096,9 @@ hipError_t potential_iteration(pfd_ctx* c, const double* Vin, double* Vout) {
   Dir1D& dy = c->dirs[c->fam[PFD_FAM_V].iy];
   (void)dx;
   (void)dy;
-  LAUNCH(PFD_PROF_ELEM, k_V_elem, eg, eb, 0, c->stream, g, P, ph, ph, Vin, Vin, c->Lb[0]);
+  Kern<k_V_elem>::launch(c, PFD_PROF_ELEM, eg, eb, 0, c->stream, g, P, ph, ph, Vin, Vin, c->Lb[0]);
   const bool warm = warm_start(c, PFD_FAM_V);
-  LAUNCH(PFD_PROF_NODAL, k_V_rhs, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, P, c->lift[PFD_FAM_V], c->Lb[0],
+  Kern<k_V_rhs>::launch(c, PFD_PROF_NODAL, dim3(nblk(tot)), dim3(WG), 0, c->stream, g, P, c->lift[PFD_FAM_V], c->Lb[0],
                      c->Mdiag, c->src[PFD_SRC_FV], c->src[PFD_SRC_VD], warm ? Vin : nullptr, Vin, c->b[0], c->r,
                      Vout);
   return solve(c, PFD_FAM_V, c->b[0], Vout, 1, 0, warm ? nullptr : c->r, !warm);
@@ -3095,18 +3133,18 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
   {
     Dir1D& dx = c->dirs[c->fam[PFD_FAM_V].ix];
     Dir1D& dy = c->dirs[c->fam[PFD_FAM_V].iy];
-    LAUNCH(PFD_PROF_ELEM, k_V_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), FLD(F_V, 0), FLD(F_V, -1),
+    Kern<k_V_elem>::launch(c, PFD_PROF_ELEM, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), FLD(F_V, 0), FLD(F_V, -1),
                        c->Lb[0]);
     (void)dx;
     (void)dy;
-    LAUNCH(PFD_PROF_NODAL, k_V_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_V), c->Lb[0], c->Mdiag, S[PFD_SRC_FV],
+    Kern<k_V_rhs>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, LR(PFD_FAM_V), c->Lb[0], c->Mdiag, S[PFD_SRC_FV],
                        S[PFD_SRC_VD], H(PFD_FAM_V, F_V, 0), H(PFD_FAM_V, F_V, -1), BB(PFD_FAM_V), c->r,
                        c->fld[F_V][nw]);
     solve(c, PFD_FAM_V, BB(PFD_FAM_V), c->fld[F_V][nw], 1, 0, RR(PFD_FAM_V), !W(PFD_FAM_V));
   }
   // ---- E (eq. 55)
-  LAUNCH(PFD_PROF_ELEM, k_E_elem, eg, eb, 0, st, g, c->fld[F_V][nw], c->Lb[0], c->Lb[1]);
-  LAUNCH(PFD_PROF_NODAL, k_E_nodal, ng, nb, 0, st, g, c->Lb[0], c->Lb[1], c->Mdiag, (const double*)nullptr,
+  Kern<k_E_elem>::launch(c, PFD_PROF_ELEM, eg, eb, 0, st, g, c->fld[F_V][nw], c->Lb[0], c->Lb[1]);
+  Kern<k_E_nodal>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, c->Lb[0], c->Lb[1], c->Mdiag, (const double*)nullptr,
                      c->fld[F_EX][0], c->fld[F_EY][0], c->fld[F_E2][0]);
   // ---- psi (eq. 56)
   const double* E2 = c->fld[F_E2][0];
@@ -3115,41 +3153,41 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
   const double* uxo = equilibrium ? c->zero_buf : FLD(F_UX, -1);
   const double* uyn = equilibrium ? c->zero_buf : FLD(F_UY, 0);
   const double* uyo = equilibrium ? c->zero_buf : FLD(F_UY, -1);
-  LAUNCH(PFD_PROF_ELEM, k_psi_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), uxn, uxo, uyn, uyo, E2,
+  Kern<k_psi_elem>::launch(c, PFD_PROF_ELEM, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), uxn, uxo, uyn, uyo, E2,
                      S[PFD_SRC_G], (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, c->Lb[0]);
-  LAUNCH(PFD_PROF_NODAL, k_psi_rhs, ng, nb, 0, st, g, P, c->Lb[0], c->bm_open, c->bm_wall, S[PFD_SRC_G1],
+  Kern<k_psi_rhs>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, c->Lb[0], c->bm_open, c->bm_wall, S[PFD_SRC_G1],
                      S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), E2, H(PFD_FAM_PSI, F_PSI, 0),
                      H(PFD_FAM_PSI, F_PSI, -1), BB(PFD_FAM_PSI), c->U, c->Q2, c->r, c->fld[F_PSI][nw],
                      BP(PFD_FAM_PSI));
   solve(c, PFD_FAM_PSI, BB(PFD_FAM_PSI), c->fld[F_PSI][nw], 1, 0, RR(PFD_FAM_PSI), !W(PFD_FAM_PSI));
   // ---- phi (eq. 57)
-  LAUNCH(PFD_PROF_NODAL, k_phi_rhs, ng, nb, 0, st, g, P, c->Mdiag, c->fld[F_PSI][nw], c->bm_open, c->bm_wall,
+  Kern<k_phi_rhs>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, c->Mdiag, c->fld[F_PSI][nw], c->bm_open, c->bm_wall,
                      S[PFD_SRC_G2], c->U, H(PFD_FAM_PHI, F_PHI, 0), H(PFD_FAM_PHI, F_PHI, -1), BB(PFD_FAM_PHI),
                      c->r, c->fld[F_PHI][nw], BP(PFD_FAM_PHI));
   solve(c, PFD_FAM_PHI, BB(PFD_FAM_PHI), c->fld[F_PHI][nw], 1, 0, RR(PFD_FAM_PHI), !W(PFD_FAM_PHI));
   if (equilibrium) {
-    for (int f : {F_UX, F_UY, F_P}) LAUNCH(PFD_PROF_OTHER, k_fill, ng, nb, 0, st, tot, c->fld[f][nw], 0.0);
+    for (int f : {F_UX, F_UY, F_P}) Kern<k_fill>::launch(c, PFD_PROF_OTHER, ng, nb, 0, st, tot, c->fld[f][nw], 0.0);
   } else {
     // ---- momentum terms, P (eq. 58)
     // phi^{n-1} now holds phi^{n+1}: the momentum kernel takes Q2 (built from phi*) from the psi stage
-    LAUNCH(PFD_PROF_ELEM, k_mom_elem<false>, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
+    Kern<k_mom_elem<false>>::launch(c, PFD_PROF_ELEM, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
                        FLD(F_UX, 0), FLD(F_UX, -1), FLD(F_UY, 0), FLD(F_UY, -1), FLD(F_P, 0),
                        FLD(F_P, -1), S[PFD_SRC_FX], S[PFD_SRC_FY], c->Lb[0], c->Lb[1], c->Lb[2], Mom3{});
-    LAUNCH(PFD_PROF_NODAL, k_P_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_P), c->Lb[0], S[PFD_SRC_WX], S[PFD_SRC_WY],
+    Kern<k_P_rhs>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, LR(PFD_FAM_P), c->Lb[0], S[PFD_SRC_WX], S[PFD_SRC_WY],
                        S[PFD_SRC_F2], H(PFD_FAM_P, F_P, 0), H(PFD_FAM_P, F_P, -1), BB(PFD_FAM_P), c->r,
                        c->fld[F_P][nw]);
     solve(c, PFD_FAM_P, BB(PFD_FAM_P), c->fld[F_P][nw], 1, 0, RR(PFD_FAM_P), !W(PFD_FAM_P));
     // ---- u (eq. 59)
-    LAUNCH(PFD_PROF_ELEM, k_gradP_elem, eg, eb, 0, st, g, P, c->fld[F_P][nw], (const double*)nullptr, c->Lb[1],
+    Kern<k_gradP_elem>::launch(c, PFD_PROF_ELEM, eg, eb, 0, st, g, P, c->fld[F_P][nw], (const double*)nullptr, c->Lb[1],
            c->Lb[2], (double*)nullptr);
-    LAUNCH(PFD_PROF_NODAL, k_u_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_U), c->Lb[1], c->Lb[2], c->bm_open,
+    Kern<k_u_rhs>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, LR(PFD_FAM_U), c->Lb[1], c->Lb[2], c->bm_open,
                        S[PFD_SRC_F1X], S[PFD_SRC_F1Y], S[PFD_SRC_WX], S[PFD_SRC_WY], H(PFD_FAM_U, F_UX, 0),
                        H(PFD_FAM_U, F_UX, -1), H(PFD_FAM_U, F_UY, 0), H(PFD_FAM_U, F_UY, -1), BB(PFD_FAM_U),
                        BB(PFD_FAM_U) + tot, c->r, c->r + tot, c->fld[F_UX][nw], c->fld[F_UY][nw]);
     // both components as one stack
     solve(c, PFD_FAM_U, BB(PFD_FAM_U), c->fld[F_UX][nw], 2, 0, RR(PFD_FAM_U), !W(PFD_FAM_U));
   }
-  LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot,
+  Kern<k_check_finite>::launch(c, PFD_PROF_OTHER, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot,
          (const double*)c->fld[F_PHI][nw], equilibrium ? (const double*)nullptr : (const double*)c->fld[F_UX][nw],
          c->d_status);
   c->cur = nw;
@@ -3157,10 +3195,10 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
 }
 
 // max |a - b| and max |b| over all planes (host result), for the potential fixed point
-__global__ void k_maxdiff(long N, const double* a, const double* b, double* out) {
+__device__ __forceinline__ void k_maxdiff_run(const VGrid& vg, long N, const double* a, const double* b, double* out) {
   __shared__ double s1[WG], s2[WG];
   double m1 = 0.0, m2 = 0.0;
-  for (long i = (long)blockIdx.x * WG + threadIdx.x; i < N; i += (long)gridDim.x * WG) {
+  for (long i = (long)vg.b.x * WG + threadIdx.x; i < N; i += (long)vg.g.x * WG) {
     m1 = fmax(m1, fabs(a[i] - b[i]));
     m2 = fmax(m2, fabs(b[i]));
   }
@@ -3175,15 +3213,16 @@ __global__ void k_maxdiff(long N, const double* a, const double* b, double* out)
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[2 * blockIdx.x] = s1[0];
-    out[2 * blockIdx.x + 1] = s2[0];
+    out[2 * vg.b.x] = s1[0];
+    out[2 * vg.b.x + 1] = s2[0];
   }
 }
+struct k_maxdiff : KDef<&k_maxdiff_run, 0, 0> {};
 
 hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* out_host2) {
   const long N = (long)c->planes * c->Ng;
   const int nb = (int)std::min(512L, (long)nblk(N));
-  LAUNCH(PFD_PROF_OTHER, k_maxdiff, dim3(nb), dim3(WG), 0, c->stream, N, a, b, c->d_red);
+  Kern<k_maxdiff>::launch(c, PFD_PROF_OTHER, dim3(nb), dim3(WG), 0, c->stream, N, a, b, c->d_red);
   double h[2 * 512];
   hipMemcpyAsync(h, c->d_red, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, c->stream);
   hipError_t e = hipStreamSynchronize(c->stream);
@@ -3196,11 +3235,11 @@ hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* ou
 }
 
 // ------------------------------------------------------------------ diagnostics
-// Block partial sums per instance (blockIdx.y) of the quadrature sums behind eq. (14) and the
+// Block partial sums per instance (vg.b.y) of the quadrature sums behind eq. (14) and the
 // mass: q0 int phi, q1 int 1/2 rho |u|^2, q2 phi.(K phi) + int (d_z phi)^2, q3 int (phi^2-1)^2,
 // q4 int 1/2 eps |E|^2, q5 wall int phi (phi^2 - 3), q6 max|phi|, q7 non-finite count.
 // K phi is the x-y stiffness applied per plane (no mass shift).
-__global__ void k_stats(long Ng, long per_inst, Par P, const double* __restrict__ Mdiag,
+__device__ __forceinline__ void k_stats_run(const VGrid& vg, long Ng, long per_inst, Par P, const double* __restrict__ Mdiag,
                         const double* __restrict__ bw, const double* __restrict__ phi,
                         const double* __restrict__ ux, const double* __restrict__ uy,
                         const double* __restrict__ uz, const double* __restrict__ Ex,
@@ -3209,8 +3248,8 @@ __global__ void k_stats(long Ng, long per_inst, Par P, const double* __restrict_
                         double* __restrict__ part) {
   __shared__ double red[8][WG];
   double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const long base = (long)blockIdx.y * per_inst;
-  for (long i = (long)blockIdx.x * WG + threadIdx.x; i < per_inst; i += (long)gridDim.x * WG) {
+  const long base = (long)vg.b.y * per_inst;
+  for (long i = (long)vg.b.x * WG + threadIdx.x; i < per_inst; i += (long)vg.g.x * WG) {
     const long id = base + i;
     const long node = id % Ng;
     const double w = Mdiag[node], p = phi[id];
@@ -3239,8 +3278,9 @@ __global__ void k_stats(long Ng, long per_inst, Par P, const double* __restrict_
                                        : red[q][threadIdx.x] + red[q][threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x < 8) part[((long)blockIdx.y * gridDim.x + blockIdx.x) * 8 + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 8) part[((long)vg.b.y * vg.g.x + vg.b.x) * 8 + threadIdx.x] = red[threadIdx.x][0];
 }
+struct k_stats : KDef<&k_stats_run, 0, 0> {};
 
 hipError_t stats(pfd_ctx* c, double* out) {
   const long tot = (long)c->planes * c->Ng;
@@ -3253,7 +3293,7 @@ hipError_t stats(pfd_ctx* c, double* out) {
   double* dzphi = c->is3d ? c->r + tot : nullptr;
   residual(c, PFD_FAM_PSI, nullptr, phi, Kphi, 1, nullptr, c->zero_buf);
   if (c->is3d) ztrans(c, c->Dz, phi, dzphi, nullptr, 1.0, 0.0);
-  LAUNCH(PFD_PROF_OTHER, k_stats, dim3(nb, ninst), dim3(WG), 0, c->stream, c->Ng, per, c->par, c->Mdiag,
+  Kern<k_stats>::launch(c, PFD_PROF_OTHER, dim3(nb, ninst), dim3(WG), 0, c->stream, c->Ng, per, c->par, c->Mdiag,
          c->bm_wall, phi, c->fld[F_UX][cu], c->fld[F_UY][cu], c->is3d ? c->fld[F_UZ][cu] : nullptr,
          c->fld[F_EX][0], c->fld[F_EY][0], c->is3d ? c->fld[F_EZ][0] : nullptr, Kphi, dzphi, c->d_stats);
   std::vector<double> h((size_t)ninst * nb * 8);
@@ -3294,7 +3334,7 @@ hipError_t stats(pfd_ctx* c, double* out) {
 //   b = scale * (A + i beta_k B)   (bmode 0)   or   scale * (A + beta_k^2 B)   (bmode 1)
 //       + mc * M * Cv   (optional spectral term),
 // then the initial guess / first residual as in rhs_out (gD, Fn, Fo spectral)
-__global__ void k_spec_rhs(Geo g, Par P, Lift L, const double* A, const double* B, int bmode, double scale,
+__device__ __forceinline__ void k_spec_rhs_run(const VGrid& vg, Geo g, Par P, Lift L, const double* A, const double* B, int bmode, double scale,
                            const double* Cv, double mc, const double* Mdiag, const double* beta2,
                            const double* betad, const double* gD, const double* Fn, const double* Fo, double* bb,
                            double* r, double* x0) {
@@ -3315,18 +3355,20 @@ __global__ void k_spec_rhs(Geo g, Par P, Lift L, const double* A, const double* 
   if (Cv) v += mc * Mdiag[node] * Cv[id];
   rhs_out(g, P, L, gD, Fn, Fo, id, (long)pl * g.Ng, ix, iy, v, bb, r, x0);
 }
+struct k_spec_rhs : KDef<&k_spec_rhs_run, 0, 0> {};
 
 // V: A = DSS(L0) - M f_V,  B = M (eps(phi*) - eps0) d(V*)/dz
-__global__ void k_V_rhs3(Geo g, Par P, const double* L0, const double* Mdiag, const double* fV, const double* phn,
+__device__ __forceinline__ void k_V_rhs3_run(const VGrid& vg, Geo g, Par P, const double* L0, const double* Mdiag, const double* fV, const double* phn,
                          const double* pho, const double* dzV, double* A, double* B) {
   NODAL_PROLOGUE
   A[id] = dss(g, L0, pl, ix, iy) - Mdiag[node] * fV[id];
   const double phs = P.cs_n * phn[id] + P.cs_o * pho[id];
   B[id] = Mdiag[node] * (eps_of(P, phs) - P.eps0) * dzV[id];
 }
+struct k_V_rhs3 : KDef<&k_V_rhs3_run, 0, 0> {};
 
 // psi: A = DSS(L0) + Bo (g1 + c_psi g2) + Bs (g1 + c_psi U),  B = M Q2 ; U, Q2 kept
-__global__ void k_psi_rhs3(Geo g, Par P, const double* L0, const double* Mdiag, const double* bmo,
+__device__ __forceinline__ void k_psi_rhs3_run(const VGrid& vg, Geo g, Par P, const double* L0, const double* Mdiag, const double* bmo,
                            const double* bmw, const double* g1, const double* g2, const double* g3,
                            const double* phn, const double* pho, const double* E2, double* A, double* B,
                            double* U, double* Q2) {
@@ -3339,23 +3381,26 @@ __global__ void k_psi_rhs3(Geo g, Par P, const double* L0, const double* Mdiag, 
   A[id] = dss(g, L0, pl, ix, iy) + bmo[node] * (g1[id] + P.c_psi * g2[id]) + bmw[node] * (g1[id] + P.c_psi * u);
   B[id] = Mdiag[node] * q2;
 }
+struct k_psi_rhs3 : KDef<&k_psi_rhs3_run, 0, 0> {};
 
 // phi: boundary part Bo g2 + Bs U (the -M psi part is added in spectral space)
-__global__ void k_phi_bnd3(Geo g, const double* bmo, const double* bmw, const double* g2, const double* U,
+__device__ __forceinline__ void k_phi_bnd3_run(const VGrid& vg, Geo g, const double* bmo, const double* bmw, const double* g2, const double* U,
                            double* A) {
   NODAL_PROLOGUE
   A[id] = bmo[node] * g2[id] + bmw[node] * U[id];
 }
+struct k_phi_bnd3 : KDef<&k_phi_bnd3_run, 0, 0> {};
 
 // Phi_hat = psi_hat - c_psi phi_hat - Q2_hat, with Q2_hat = (M Q2)_hat / M (reading R-J)
-__global__ void k_Phi_hat3(Geo g, Par P, const double* psh, const double* phh, const double* BQ,
+__device__ __forceinline__ void k_Phi_hat3_run(const VGrid& vg, Geo g, Par P, const double* psh, const double* phh, const double* BQ,
                            const double* Mdiag, double* out) {
   NODAL_PROLOGUE
   out[id] = psh[id] - P.c_psi * phh[id] - BQ[id] / Mdiag[node];
 }
+struct k_Phi_hat3 : KDef<&k_Phi_hat3_run, 0, 0> {};
 
 // P: A = DSS(L0) - rho0 gamma0/dt sum_walls int (n.w) q,  B = DSS(LBP)
-__global__ void k_P_rhs3(Geo g, Par P, const double* L0, const double* LBP, const double* wx, const double* wy,
+__device__ __forceinline__ void k_P_rhs3_run(const VGrid& vg, Geo g, Par P, const double* L0, const double* LBP, const double* wx, const double* wy,
                          double* A, double* B) {
   NODAL_PROLOGUE
   double v = dss(g, L0, pl, ix, iy);
@@ -3366,9 +3411,10 @@ __global__ void k_P_rhs3(Geo g, Par P, const double* L0, const double* LBP, cons
   A[id] = v;
   B[id] = dss(g, LBP, pl, ix, iy);
 }
+struct k_P_rhs3 : KDef<&k_P_rhs3_run, 0, 0> {};
 
 // u: A_x, B_x, A_y, B_y, A_z (open-side f1 added to the A parts)
-__global__ void k_u_rhs3(Geo g, const double* L1, const double* LBx, const double* L2, const double* LBy,
+__device__ __forceinline__ void k_u_rhs3_run(const VGrid& vg, Geo g, const double* L1, const double* LBx, const double* L2, const double* LBy,
                          const double* LAz, const double* bmo, const double* f1x, const double* f1y,
                          const double* f1z, double* Ax, double* Bx, double* Ay, double* By, double* Az) {
   NODAL_PROLOGUE
@@ -3378,6 +3424,7 @@ __global__ void k_u_rhs3(Geo g, const double* L1, const double* LBx, const doubl
   By[id] = dss(g, LBy, pl, ix, iy);
   Az[id] = dss(g, LAz, pl, ix, iy) + bmo[node] * f1z[id];
 }
+struct k_u_rhs3 : KDef<&k_u_rhs3_run, 0, 0> {};
 
 // ------------------------------------------------------------------ FFT along z
 // Batched real FFT along z for a power-of-two number of planes Nz = 4..256 (the dense-DFT GEMM
@@ -3397,7 +3444,7 @@ __global__ void k_u_rhs3(Geo g, const double* L1, const double* LBx, const doubl
 // Packed layout: plane 0 = Re c_0, plane 1 = Re c_{Nz/2}, planes 2k, 2k+1 = Re, Im c_k.
 // Multiplying by i beta(k) with beta odd in k (beta(Nz-k) = -beta(k)) keeps Z = C_a + i C_b
 // consistent, so modes 2 and 3 apply it to Z directly.  One launch runs up to ZB_MAX
-// independent transforms (blockIdx.y), each with its own mode, input and output.
+// independent transforms (vg.b.y), each with its own mode, input and output.
 template <int N>
 struct ZLog2 {
   static constexpr int v = 1 + ZLog2<N / 2>::v;
@@ -3477,14 +3524,14 @@ struct ZBatch {
 };
 
 template <int LG, bool TWO>
-__global__ void __launch_bounds__(ZfftShape<LG>::T) k_zfft(ZBatch zb, long Ng, double c1, double c2,
+__device__ __forceinline__ void k_zfft_run(const VGrid& vg, ZBatch zb, long Ng, double c1, double c2,
                                                            const double* __restrict__ twr_g,
                                                            const double* __restrict__ twi_g,
                                                            const double* __restrict__ betad) {
   using S = ZfftShape<LG>;
   constexpr int NZ = S::NZ, N1 = S::N1, N2 = S::N2, P = S::P, T = S::T, RS = S::RS;
   __shared__ double lr[N1 * RS], li[N1 * RS], wr[NZ], wi[NZ];
-  const int e = blockIdx.y;
+  const int e = vg.b.y;
   const int mode = zb.mode[e];
   const double* __restrict__ in = zb.in[e];
   const double* __restrict__ in2 = zb.in2[e];
@@ -3497,7 +3544,7 @@ __global__ void __launch_bounds__(ZfftShape<LG>::T) k_zfft(ZBatch zb, long Ng, d
     wi[m] = lo ? twi_g[mm] : -twi_g[mm];
   }
   const int c = t % P, row = t / P;
-  const long n0 = (long)blockIdx.x * (2 * P);
+  const long n0 = (long)vg.b.x * (2 * P);
   const long na = n0 + c, nb = n0 + P + c;
   const bool va = na < Ng, vb = nb < Ng;
   const long ia = va ? na : 0, ib = vb ? nb : 0;   // clamped addresses, values masked after the load
@@ -3650,16 +3697,18 @@ __global__ void __launch_bounds__(ZfftShape<LG>::T) k_zfft(ZBatch zb, long Ng, d
     if (vb) out[z * Ng + nb] = xi[n1];
   }
 }
+template <int LG, bool TWO>
+struct k_zfft : KDef<&k_zfft_run<LG, TWO>, ZfftShape<LG>::T, 0> {};
 
 template <int LG>
 static void zfft_launch(pfd_ctx* c, const ZBatch& zb, int n, bool two, double c1, double c2) {
   using S = ZfftShape<LG>;
   const dim3 grid((unsigned)((c->Ng + 2 * S::P - 1) / (2 * S::P)), (unsigned)n);
   if (two)
-    LAUNCH(PFD_PROF_ZFFT, (k_zfft<LG, true>), grid, dim3(S::T), 0, c->stream, zb, c->Ng, c1, c2, c->twr, c->twi,
+    Kern<k_zfft<LG, true>>::launch(c, PFD_PROF_ZFFT, grid, dim3(S::T), 0, c->stream, zb, c->Ng, c1, c2, c->twr, c->twi,
            c->d_betad);
   else
-    LAUNCH(PFD_PROF_ZFFT, (k_zfft<LG, false>), grid, dim3(S::T), 0, c->stream, zb, c->Ng, c1, c2, c->twr, c->twi,
+    Kern<k_zfft<LG, false>>::launch(c, PFD_PROF_ZFFT, grid, dim3(S::T), 0, c->stream, zb, c->Ng, c1, c2, c->twr, c->twi,
            c->d_betad);
 }
 
@@ -3753,16 +3802,16 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
     ztrans_n(c, equilibrium ? 2 : 6, Ws, ins, dz, olds, P.cs_n, P.cs_o);
   }
   // ---- V (eq. 74)
-  LAUNCH(PFD_PROF_ELEM, k_V_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), FLD(F_V, 0), FLD(F_V, -1),
+  Kern<k_V_elem>::launch(c, PFD_PROF_ELEM, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), FLD(F_V, 0), FLD(F_V, -1),
          Lb[0]);
-  LAUNCH(PFD_PROF_NODAL, k_V_rhs3, ng, nb, 0, st, g, P, Lb[0], c->Mdiag, S[PFD_SRC_FV], FLD(F_PHI, 0),
+  Kern<k_V_rhs3>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, Lb[0], c->Mdiag, S[PFD_SRC_FV], FLD(F_PHI, 0),
          FLD(F_PHI, -1), dz[0], ph[0], ph[1]);
   const double* Wff[5] = {c->Wf, c->Wf, c->Wf, c->Wf, c->Wf};
   const double* Wfi[3] = {c->Wi, c->Wi, c->Wi};
   const double* Wid[2] = {c->Wi, c->Wd};
   const double* ph01[2] = {ph[0], ph[1]};
   ztrans_n(c, 2, Wff, ph01, sp);
-  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_V, 0), sp[0], sp[1], 0, 1.0 / P.eps0,
+  Kern<k_spec_rhs>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, LR(PFD_FAM_V, 0), sp[0], sp[1], 0, 1.0 / P.eps0,
          (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_VD], H(PFD_FAM_V, F_V, 0),
          H(PFD_FAM_V, F_V, -1), BB(PFD_FAM_V), c->r, c->spec[F_V][nw]);
   solve(c, PFD_FAM_V, BB(PFD_FAM_V), c->spec[F_V][nw], 1, 0, RR(PFD_FAM_V), !W(PFD_FAM_V));
@@ -3773,8 +3822,8 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
     ztrans_n(c, 2, Wid, ins, outs);
   }
   // ---- E (eq. 78): E_x, E_y by plane-wise projection
-  LAUNCH(PFD_PROF_ELEM, k_E_elem, eg, eb, 0, st, g, c->fld[F_V][nw], Lb[0], Lb[1]);
-  LAUNCH(PFD_PROF_NODAL, k_E_nodal, ng, nb, 0, st, g, Lb[0], Lb[1], c->Mdiag, (const double*)c->fld[F_EZ][0],
+  Kern<k_E_elem>::launch(c, PFD_PROF_ELEM, eg, eb, 0, st, g, c->fld[F_V][nw], Lb[0], Lb[1]);
+  Kern<k_E_nodal>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, Lb[0], Lb[1], c->Mdiag, (const double*)c->fld[F_EZ][0],
          c->fld[F_EX][0], c->fld[F_EY][0], c->fld[F_E2][0]);
   const double* E2 = c->fld[F_E2][0];
   // ---- psi (eq. 75)
@@ -3784,20 +3833,20 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
   const double* uyo = equilibrium ? c->zero_buf : FLD(F_UY, -1);
   const double* uzn = equilibrium ? c->zero_buf : FLD(F_UZ, 0);
   const double* uzo = equilibrium ? c->zero_buf : FLD(F_UZ, -1);
-  LAUNCH(PFD_PROF_ELEM, k_psi_elem, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), uxn, uxo, uyn, uyo, E2,
+  Kern<k_psi_elem>::launch(c, PFD_PROF_ELEM, eg, eb, 0, st, g, P, FLD(F_PHI, 0), FLD(F_PHI, -1), uxn, uxo, uyn, uyo, E2,
          S[PFD_SRC_G], uzn, uzo, (const double*)dz[1], Lb[0]);
-  LAUNCH(PFD_PROF_NODAL, k_psi_rhs3, ng, nb, 0, st, g, P, Lb[0], c->Mdiag, c->bm_open, c->bm_wall, S[PFD_SRC_G1],
+  Kern<k_psi_rhs3>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, Lb[0], c->Mdiag, c->bm_open, c->bm_wall, S[PFD_SRC_G1],
          S[PFD_SRC_G2], S[PFD_SRC_G3], FLD(F_PHI, 0), FLD(F_PHI, -1), E2, ph[0], ph[1], c->U, c->Q2);
   ztrans_n(c, 2, Wff, ph01, sp);  // sp[1] = (M Q2)_hat, kept for Phi_hat below
-  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_PSI, 0), sp[0], sp[1], 1, 1.0,
+  Kern<k_spec_rhs>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, LR(PFD_FAM_PSI, 0), sp[0], sp[1], 1, 1.0,
          (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, (const double*)nullptr,
          H(PFD_FAM_PSI, F_PSI, 0), H(PFD_FAM_PSI, F_PSI, -1), BB(PFD_FAM_PSI), c->r, c->spec[F_PSI][nw]);
   solve(c, PFD_FAM_PSI, BB(PFD_FAM_PSI), c->spec[F_PSI][nw], 1, 0, RR(PFD_FAM_PSI), !W(PFD_FAM_PSI));
   ztrans(c, c->Wi, c->spec[F_PSI][nw], c->fld[F_PSI][nw]);
   // ---- phi (eq. 76, reading R-psi)
-  LAUNCH(PFD_PROF_NODAL, k_phi_bnd3, ng, nb, 0, st, g, c->bm_open, c->bm_wall, S[PFD_SRC_G2], c->U, ph[0]);
+  Kern<k_phi_bnd3>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, c->bm_open, c->bm_wall, S[PFD_SRC_G2], c->U, ph[0]);
   ztrans(c, c->Wf, ph[0], sp[0]);
-  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_PHI, 0), sp[0], (const double*)nullptr, 0,
+  Kern<k_spec_rhs>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, LR(PFD_FAM_PHI, 0), sp[0], (const double*)nullptr, 0,
          1.0, (const double*)c->spec[F_PSI][nw], -1.0, c->Mdiag, c->d_beta2, c->d_betad, (const double*)nullptr,
          H(PFD_FAM_PHI, F_PHI, 0), H(PFD_FAM_PHI, F_PHI, -1), BB(PFD_FAM_PHI), c->r, c->spec[F_PHI][nw]);
   solve(c, PFD_FAM_PHI, BB(PFD_FAM_PHI), c->spec[F_PHI][nw], 1, 0, RR(PFD_FAM_PHI), !W(PFD_FAM_PHI));
@@ -3809,24 +3858,24 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
   }
   if (equilibrium) {
     for (int f : {F_UX, F_UY, F_UZ, F_P}) {
-      LAUNCH(PFD_PROF_OTHER, k_fill, ng, nb, 0, st, tot, c->fld[f][nw], 0.0);
-      LAUNCH(PFD_PROF_OTHER, k_fill, ng, nb, 0, st, tot, c->spec[f][nw], 0.0);
+      Kern<k_fill>::launch(c, PFD_PROF_OTHER, ng, nb, 0, st, tot, c->fld[f][nw], 0.0);
+      Kern<k_fill>::launch(c, PFD_PROF_OTHER, ng, nb, 0, st, tot, c->spec[f][nw], 0.0);
     }
   } else {
     // ---- momentum terms (eq. 49 and the G, Y, K, J, L of Sec. 3.2.2)
-    LAUNCH(PFD_PROF_NODAL, k_Phi_hat3, ng, nb, 0, st, g, P, c->spec[F_PSI][nw], c->spec[F_PHI][nw], sp[1],
+    Kern<k_Phi_hat3>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, c->spec[F_PSI][nw], c->spec[F_PHI][nw], sp[1],
            c->Mdiag, sp[2]);
     ztrans(c, c->Wd, sp[2], dz[1]);   // dz[2..5] were taken at the start of the step
     Mom3 z{FLD(F_UZ, 0), FLD(F_UZ, -1), dz[0], dz[1], dz[2], dz[3], dz[4], dz[5], S[PFD_SRC_FZ],
            Lb[3], Lb[4], Lb[5], Lb[6]};
-    LAUNCH(PFD_PROF_ELEM, k_mom_elem<true>, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
+    Kern<k_mom_elem<true>>::launch(c, PFD_PROF_ELEM, eg, eb, 0, st, g, P, c->fld[F_PHI][nw], c->fld[F_PSI][nw], E2, c->Q2,
            FLD(F_UX, 0), FLD(F_UX, -1), FLD(F_UY, 0), FLD(F_UY, -1), FLD(F_P, 0), FLD(F_P, -1), S[PFD_SRC_FX],
            S[PFD_SRC_FY], Lb[0], Lb[1], Lb[2], z);
     // ---- P (eq. 77)
-    LAUNCH(PFD_PROF_NODAL, k_P_rhs3, ng, nb, 0, st, g, P, Lb[0], Lb[3], S[PFD_SRC_WX], S[PFD_SRC_WY], ph[0],
+    Kern<k_P_rhs3>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, Lb[0], Lb[3], S[PFD_SRC_WX], S[PFD_SRC_WY], ph[0],
            ph[1]);
     ztrans_n(c, 2, Wff, ph01, sp);
-    LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_P, 0), sp[0], sp[1], 0, 1.0,
+    Kern<k_spec_rhs>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, LR(PFD_FAM_P, 0), sp[0], sp[1], 0, 1.0,
            (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_F2],
            H(PFD_FAM_P, F_P, 0), H(PFD_FAM_P, F_P, -1), BB(PFD_FAM_P), c->r, c->spec[F_P][nw]);
     solve(c, PFD_FAM_P, BB(PFD_FAM_P), c->spec[F_P][nw], 1, 0, RR(PFD_FAM_P), !W(PFD_FAM_P));
@@ -3836,9 +3885,9 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
       ztrans_n(c, 2, Wid, ins, outs);
     }
     // ---- u (eq. 78)
-    LAUNCH(PFD_PROF_ELEM, k_gradP_elem, eg, eb, 0, st, g, P, c->fld[F_P][nw], (const double*)dz[0], Lb[1], Lb[2],
+    Kern<k_gradP_elem>::launch(c, PFD_PROF_ELEM, eg, eb, 0, st, g, P, c->fld[F_P][nw], (const double*)dz[0], Lb[1], Lb[2],
            Lb[4]);
-    LAUNCH(PFD_PROF_NODAL, k_u_rhs3, ng, nb, 0, st, g, Lb[1], Lb[5], Lb[2], Lb[6], Lb[4], c->bm_open,
+    Kern<k_u_rhs3>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, Lb[1], Lb[5], Lb[2], Lb[6], Lb[4], c->bm_open,
            S[PFD_SRC_F1X], S[PFD_SRC_F1Y], S[PFD_SRC_F1Z], ph[0], ph[1], ph[2], ph[3], ph[4]);
     {
       const double* ins[5] = {ph[0], ph[1], ph[2], ph[3], ph[4]};
@@ -3849,7 +3898,7 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
     const double* Bs[3] = {sp[1], sp[3], nullptr};
     const double* As[3] = {sp[0], sp[2], sp[4]};
     for (int i = 0; i < 3; ++i)
-      LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, LR(PFD_FAM_U, i), As[i], Bs[i], 0, 1.0,
+      Kern<k_spec_rhs>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, LR(PFD_FAM_U, i), As[i], Bs[i], 0, 1.0,
              (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[ws[i]],
              H(PFD_FAM_U, uf[i], 0), H(PFD_FAM_U, uf[i], -1), BB(PFD_FAM_U) + i * tot, c->r + i * tot,
              c->spec[uf[i]][nw]);
@@ -3860,7 +3909,7 @@ hipError_t step_once_3d(pfd_ctx* c, int equilibrium) {
       ztrans_n(c, 3, Wfi, ins, outs);
     }
   }
-  LAUNCH(PFD_PROF_OTHER, k_check_finite, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot,
+  Kern<k_check_finite>::launch(c, PFD_PROF_OTHER, dim3(std::min(1024L, (long)nblk(tot))), dim3(WG), 0, st, tot,
          (const double*)c->fld[F_PHI][nw], equilibrium ? (const double*)nullptr : (const double*)c->fld[F_UX][nw],
          c->d_status);
   c->cur = nw;
@@ -3882,8 +3931,8 @@ hipError_t potential_iteration_3d(pfd_ctx* c, const double* Vin, double* Vout) {
   refresh_spectral_sources(c);
   const double* phn = FLD(F_PHI, 0);
   ztrans(c, c->Dz, Vin, dz[0]);
-  LAUNCH(PFD_PROF_ELEM, k_V_elem, eg, eb, 0, st, g, P, phn, phn, Vin, Vin, c->Lb[0]);
-  LAUNCH(PFD_PROF_NODAL, k_V_rhs3, ng, nb, 0, st, g, P, c->Lb[0], c->Mdiag, c->src[PFD_SRC_FV], phn, phn, dz[0],
+  Kern<k_V_elem>::launch(c, PFD_PROF_ELEM, eg, eb, 0, st, g, P, phn, phn, Vin, Vin, c->Lb[0]);
+  Kern<k_V_rhs3>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, c->Lb[0], c->Mdiag, c->src[PFD_SRC_FV], phn, phn, dz[0],
          ph[0], ph[1]);
   {
     const double* Wff[3] = {c->Wf, c->Wf, c->Wf};
@@ -3891,7 +3940,7 @@ hipError_t potential_iteration_3d(pfd_ctx* c, const double* Vin, double* Vout) {
     ztrans_n(c, warm ? 3 : 2, Wff, ins, sp);
   }
   double* Vh = c->spec[F_V][1 - c->cur];
-  LAUNCH(PFD_PROF_NODAL, k_spec_rhs, ng, nb, 0, st, g, P, c->lift[PFD_FAM_V], sp[0], sp[1], 0, 1.0 / P.eps0,
+  Kern<k_spec_rhs>::launch(c, PFD_PROF_NODAL, ng, nb, 0, st, g, P, c->lift[PFD_FAM_V], sp[0], sp[1], 0, 1.0 / P.eps0,
          (const double*)nullptr, 0.0, c->Mdiag, c->d_beta2, c->d_betad, c->srcS[PFD_SRC_VD],
          warm ? (const double*)sp[2] : nullptr, (const double*)sp[2], c->b[0], c->r, Vh);
   hipError_t e = solve(c, PFD_FAM_V, c->b[0], Vh, 1, 0, warm ? nullptr : c->r, !warm);

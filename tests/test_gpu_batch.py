@@ -1,5 +1,6 @@
-"""Batches of uneven instances stepped through one hipGraph per step: every instance matches
-the same context stepped on its own (same kernels), and the oracle."""
+"""Batches of uneven instances stepped through one hipGraph per step, in both forms (multi-
+instance launches and per-instance graph branches): every instance matches the same context
+stepped on its own (same kernels) bit for bit, and the oracle."""
 import math
 
 import numpy as np
@@ -53,17 +54,23 @@ def _instance(n, K, vtop, eps_ratio, precision, nz=0, tune_from=None):
 SPECS = [(2, 5, 1.0, 4.0, 0), (3, 4, 0.5, 20.0, 0), (2, 7, 2.0, 1.5, 0), (2, 5, 1.5, 10.0, 8)]
 
 
+MODES = [1, 0]   # BATCH_MULTI, BATCH_BRANCHES
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("precision", [0, 1])
-def test_batch_graph_equals_separate_steps(precision):
+def test_batch_graph_equals_separate_steps(precision, mode):
     """Four uneven instances (three 2D meshes of different order, one 3D) in one batch:
-    after each of 4 batch steps every field equals the same instance stepped alone."""
+    after each of 6 batch steps (the refined path's first two run eagerly, then both
+    time-level parities are captured and replayed) every field equals the same instance
+    stepped alone."""
     _torch()
     import paper_2305_09020_amd as pfd
     batch_ctx = [_instance(*s[:4], precision, nz=s[4])[0] for s in SPECS]
     solo_ctx = [_instance(*s[:4], precision, nz=s[4], tune_from=a)[0]   # same kernels on both sides
                 for s, a in zip(SPECS, batch_ctx)]
-    batch = pfd.Batch(batch_ctx, nlanes=3)
-    for n in range(4):
+    batch = pfd.Batch(batch_ctx, nlanes=3, mode=mode)
+    for n in range(6):
         batch.step(1)
         for c in solo_ctx:
             c.step(1)
@@ -75,8 +82,8 @@ def test_batch_graph_equals_separate_steps(precision):
 
 
 def test_batch_instance_matches_oracle():
-    """A 2D instance stepped inside a batch with two others follows the oracle (refined
-    path, 1e-8 per field)."""
+    """A 2D instance stepped inside a batch with two others (multi-instance launches) follows
+    the oracle (refined path, 1e-8 per field)."""
     _torch()
     import paper_2305_09020_amd as pfd
     ctxs, infos = zip(*[_instance(*s[:4], 1) for s in SPECS[:3]])
@@ -85,7 +92,7 @@ def test_batch_instance_matches_oracle():
     sch = Scheme(m, par, bc)
     sch.set_state(phi[0])
     sch.init_potential(dict(Vd=vd[0]))
-    for n in range(3):
+    for n in range(5):
         o = sch.step(dict(Vd=vd[0]))
         batch.step(1)
         for k in FIELDS:
@@ -96,7 +103,8 @@ def test_batch_instance_matches_oracle():
     batch.close()
 
 
-def test_batch_recaptures_after_member_changes():
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_recaptures_after_member_changes(mode):
     """A member's parameters changed between batch steps (pfd_update_params): the batch's
     graphs are recaptured (the member's graph generation changed), so the member keeps
     matching the same instance stepped alone with the same change."""
@@ -105,11 +113,11 @@ def test_batch_recaptures_after_member_changes():
     precision = 1
     batch_ctx = [_instance(*s[:4], precision, nz=s[4])[0] for s in SPECS[:3]]
     solo_ctx = [_instance(*s[:4], precision, nz=s[4], tune_from=a)[0] for s, a in zip(SPECS[:3], batch_ctx)]
-    batch = pfd.Batch(batch_ctx, nlanes=2)
+    batch = pfd.Batch(batch_ctx, nlanes=2, mode=mode)
     new = c4_param_dict(30.0)        # permittivity ratio 20 -> 30 on instance 1
     new["theta_s_deg"] = 80.0
-    for n in range(4):
-        if n == 2:
+    for n in range(6):
+        if n == 3:
             batch_ctx[1].update_params(new)
             solo_ctx[1].update_params(new)
         batch.step(1)
@@ -121,6 +129,33 @@ def test_batch_recaptures_after_member_changes():
                 assert np.array_equal(fa, fb), (n, i, k, np.max(np.abs(fa - fb)))
     # and the change took effect: instance 1 differs from a twin that kept the old parameters
     twin = _instance(*SPECS[1][:4], precision, tune_from=batch_ctx[1])[0]
-    twin.step(4)
+    twin.step(6)
     assert not np.array_equal(twin.get_field("phi"), batch_ctx[1].get_field("phi"))
     batch.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_multi_instance_launches_do_not_grow_with_instances(precision):
+    """Multi-instance form: a batch of 8 instances of one order on meshes of 2..5 elements per
+    side takes as many launches per step as a batch of 2 of them, and every member still
+    equals the same instance stepped alone."""
+    _torch()
+    import paper_2305_09020_amd as pfd
+    specs = [(2 + i % 4, 6, 0.25 * i, 2.0 + 3 * i, 0) for i in range(8)]
+    counts = []
+    for sub in (specs[:2], specs):
+        first = _instance(*sub[0][:4], precision)[0]
+        # one kernel configuration for all members (and their solo twins)
+        batch_ctx = [first] + [_instance(*s[:4], precision, tune_from=first)[0] for s in sub[1:]]
+        solo_ctx = [_instance(*s[:4], precision, tune_from=first)[0] for s in sub]
+        batch = pfd.Batch(batch_ctx)
+        for n in range(4):
+            batch.step(1)
+            for c in solo_ctx:
+                c.step(1)
+        for i, (a, b) in enumerate(zip(batch_ctx, solo_ctx)):
+            for k in FIELDS:
+                assert np.array_equal(a.get_field(k), b.get_field(k)), (len(sub), i, k)
+        counts.append(batch.launches())
+        batch.close()
+    assert counts[0] > 0 and counts[0] == counts[1], counts
