@@ -130,18 +130,24 @@ def build_workload(name, precision, graph=True):
                                C4["center"], C4["r"], precision, stream=stream))
             if (i + 1) % 16 == 0:
                 print("# c4: %d instances created" % (i + 1), file=sys.stderr, flush=True)
-        # the autotuner times each instance alone; run concurrently in the batch's graph the
-        # four-pass solver for every instance was the fastest choice in one measured run (15.8 ms
-        # per refined step against 17.1 with the per-instance choices, 16.1 with the fused middle
-        # passes, 26.6 with the fused strips); timings of this workload vary by about 10 %
-        # between runs
+        # one kernel configuration for every instance: the batch's multi-instance form merges the
+        # k-th launches of instances that run the same kernel, so shared choices mean one launch
+        # per step position (two or more where instances differ).  The choice was measured on
+        # the merged launches (uniform configurations swept, 20 steps each, one run): the
+        # four-pass solver with the 2x2-tile, 4-slice split-K GEMM (configuration 7) on every
+        # pass, 2.33 ms per refined step against 2.65 with each instance's own autotuned
+        # choices; configuration 2 (2x2 tiles, 2 slices) for the FP64 path, 1.19 against 1.26
+        # ms; the residual on LDS tiles.  Timings of this workload vary by a few percent
+        # between runs.
+        cfg = 7 if precision == pfd.REFINED_FP32 else 2
+        shared = [cfg] * 8 + [0, 0] + [0, 1, 1, 0, 0]
         for c in ctxs:
-            c.set_solver_variant(0)
+            c.set_tuning(shared)
         batch = pfd.Batch(ctxs, nlanes=4)
         return Run(ctxs, sum(c.planes * c.Nx * c.Ny for c in ctxs), 38,
-                   "64 independent 2D drops in one batch (one hipGraph launch per step): n x n "
-                   "elements with n ~ U{8..24}, order ~ U{4..10}, V_top ~ U[0,2], eps ratio ~ "
-                   "U[1.5,40], seed 1, eta 0.02, dt 1e-4, closed boxes", batch=batch)
+                   "64 independent 2D drops in one batch (multi-instance launches, one hipGraph launch "
+                   "per step): n x n elements with n ~ U{8..24}, order ~ U{4..10}, V_top ~ U[0,2], eps "
+                   "ratio ~ U[1.5,40], seed 1, eta 0.02, dt 1e-4, closed boxes", batch=batch)
     if name == "x6":
         par = x6_param_dict()
         xb = np.linspace(0.0, X6["lx"], X6["nx"] + 1)
@@ -317,7 +323,7 @@ def roofline(run, t_step, workload, path, classes, probe_gbs):
     b_alg = float(run.F * 8 * run.dof)
     achieved = b_alg / t_step / 1e9
     step_traffic, class_traffic = traffic(workload, path)
-    for k, v in classes.items():
+    for k, v in (classes or {}).items():
         if k in class_traffic:
             v["traffic_per_launch"] = class_traffic[k]
             v["traffic_GBps"] = round(class_traffic[k] / (v["avg_launch_us"] * 1e-6) / 1e9, 1)
@@ -327,6 +333,10 @@ def roofline(run, t_step, workload, path, classes, probe_gbs):
            "traffic_over_alg": (step_traffic / b_alg) if step_traffic else None,
            "probe_copy_GBps": probe_gbs, "frac_of_probe": achieved / probe_gbs if probe_gbs else None,
            "classes": classes}
+    if run.batch is not None:
+        out["kernel"] = "whole step (one hipGraph launch of multi-instance kernels)"
+        out["launches_per_step"] = run.batch.launches()
+        out["classes"] = "rocprofv3 kernel split: profiles/kernel_stats_%s.txt" % workload
     return out
 
 
@@ -642,7 +652,12 @@ def main():
         run = build_workload(a.workload, prec, graph=not a.no_graph)
         t, ts = time_steps(run, a.steps, a.warmup, a.repeats)
         nprof = min(a.steps, 50 if a.workload in ("c1", "c2", "x6", "x4") else 10)
-        classes = class_profile(run, nprof)
+        # the instrumented steps run eagerly, which for a batch would time each instance's own
+        # launches rather than the multi-instance ones: a batch's per-kernel split is the
+        # rocprofv3 summary of its graph replays instead
+        classes = class_profile(run, nprof) if run.batch is None else None
+        if run.batch is not None:
+            nprof = 0
         res[name] = dict(t=t, ts=ts, run=run, value=run.dof * a.steps / t,
                          roofline=roofline(run, t / a.steps, a.workload, name, classes, probe),
                          refinement=refinement(run) if prec == pfd.REFINED_FP32 else None,

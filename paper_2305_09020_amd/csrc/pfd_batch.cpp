@@ -28,6 +28,7 @@ using namespace pfd;
 // plan's device buffer
 struct MultiLaunch {
   const void* fn = nullptr;
+  size_t pos = 0;                  // position in the instances' launch sequences
   unsigned total = 0, block[3] = {1, 1, 1};
   size_t shm = 0, o_ent = 0, o_tab = 0, o_args = 0;
 };
@@ -202,6 +203,7 @@ static hipError_t build_plan(pfd_batch* b, int eq, MultiPlan& P) {
       const RecLaunch& r0 = rec[grp[0]][j];
       MultiLaunch m;
       m.fn = r0.fn;
+      m.pos = j;
       std::memcpy(m.block, r0.block, sizeof(m.block));
       unsigned long long total = 0;
       for (size_t i : grp) {
@@ -234,7 +236,9 @@ static hipError_t build_plan(pfd_batch* b, int eq, MultiPlan& P) {
   return e;
 }
 
-// capture the plan's launches (one stream, in order) as the step's graph
+// capture the plan as the step's graph: positions in order; the launches of one position
+// (instances on different kernels, e.g. one per element order) are independent and become
+// parallel branches forked from the capture stream onto the lanes and joined again
 static hipError_t capture_multi(pfd_batch* b, int eq, MultiPlan& P, hipGraphExec_t* ex) {
   hipError_t e = build_plan(b, eq, P);
   if (e) {
@@ -245,14 +249,31 @@ static hipError_t capture_multi(pfd_batch* b, int eq, MultiPlan& P, hipGraphExec
   e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
   if (e) return e;
   hipError_t es = hipSuccess;
-  for (const MultiLaunch& m : P.L) {
+  const int L = (int)b->lanes.size();
+  auto issue = [&](const MultiLaunch& m, hipStream_t s) {
     unsigned total = m.total;
     const void* tab = P.dmem + m.o_tab;
     const void* ent = P.dmem + m.o_ent;
     const void* args = P.dmem + m.o_args;
     void* ka[] = {&total, &tab, &ent, &args};
-    es = hipLaunchKernel(m.fn, dim3(total), dim3(m.block[0], m.block[1], m.block[2]), ka, m.shm, b->cap);
-    if (es) break;
+    return hipLaunchKernel(m.fn, dim3(total), dim3(m.block[0], m.block[1], m.block[2]), ka, m.shm, s);
+  };
+  for (size_t k = 0; k < P.L.size() && !es;) {
+    size_t end = k + 1;
+    while (end < P.L.size() && P.L[end].pos == P.L[k].pos) ++end;
+    const int m = (int)(end - k), used = std::min(m - 1, L);
+    if (used == 0) {
+      es = issue(P.L[k], b->cap);
+    } else {
+      es = hipEventRecord(b->ev[0], b->cap);
+      for (int l = 0; l < used && !es; ++l) es = hipStreamWaitEvent(b->lanes[l], b->ev[0], 0);
+      for (int q = 0; q < m && !es; ++q) es = issue(P.L[k + q], q == 0 ? b->cap : b->lanes[(q - 1) % used]);
+      for (int l = 0; l < used && !es; ++l) {
+        es = hipEventRecord(b->ev[l + 1], b->lanes[l]);
+        if (!es) es = hipStreamWaitEvent(b->cap, b->ev[l + 1], 0);
+      }
+    }
+    k = end;
   }
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(b->cap, &g);

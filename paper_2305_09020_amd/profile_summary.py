@@ -35,7 +35,9 @@ CLASSES = [("gemm64", lambda n: ("k_gemm" in n or "k_fdm" in n) and ("<double" i
 
 # workload: (description, measured steps of the trace, measured steps of the counter passes)
 WORKLOADS = {"c2": ("2D benchmark workload: 20x20 elements, K = 8, 4 instances (161 x 161 x 4 nodes)", 50, 5),
-             "c3": ("3D workload: 16x16 elements, K = 8, 128 Fourier planes (129 x 129 x 128 nodes)", 10, 2)}
+             "c3": ("3D workload: 16x16 elements, K = 8, 128 Fourier planes (129 x 129 x 128 nodes)", 10, 2),
+             "c4": ("batched workload: 64 uneven 2D instances (n x n elements, n 8..24, order 4..10) as "
+                    "multi-instance launches", 20, 2)}
 PATHS = ("refined", "fp64")
 
 
@@ -56,7 +58,25 @@ def cls_of(name):
 
 
 def short(name):
-    return name.split("(")[0]
+    """Kernel name without its parameter list; a kernel of the launch layer (k_single /
+    k_multi<body, argument types...>) is named by its body, multi-instance launches marked."""
+    n = name.split("(")[0]
+    for w in ("k_single_w<", "k_single<", "k_multi_w<", "k_multi<"):
+        i = n.find(w)
+        if i < 0:
+            continue
+        inner, d, j = n[i + len(w):], 0, 0
+        for j, ch in enumerate(inner):
+            if ch == "<":
+                d += 1
+            elif ch == ">":
+                if d == 0:
+                    break
+                d -= 1
+            elif ch == "," and d == 0:
+                break
+        return inner[:j].replace("pfd::", "").strip() + (" [multi]" if "multi" in w else "")
+    return n
 
 
 def _rows(d, fname):
@@ -111,6 +131,8 @@ def main(src, dst):
     ws = copy_scale(os.path.join(src, "write_copy"))
     sha = sources_sha()
     for wl, (desc, steps, csteps) in WORKLOADS.items():
+        if not any(os.path.isdir(os.path.join(src, "trace_%s_%s" % (wl, p))) for p in PATHS):
+            continue   # no trace of this workload in src: its summaries stay as they are
         lines = ["# Kernel time per step of the steady-state steps, %s" % desc,
                  "# commands (from /tmp, TMPDIR=/tmp; repository root as working directory of python3):"]
         for p in PATHS:
