@@ -132,15 +132,18 @@ def build_workload(name, precision, graph=True):
                 print("# c4: %d instances created" % (i + 1), file=sys.stderr, flush=True)
         # one kernel configuration for every instance: the batch's multi-instance form merges the
         # k-th launches of instances that run the same kernel, so shared choices mean one launch
-        # per step position (two or more where instances differ).  The choice was measured on
-        # the merged launches (uniform configurations swept, 20 steps each, one run): the
-        # four-pass solver with the 2x2-tile, 4-slice split-K GEMM (configuration 7) on every
-        # pass, 2.33 ms per refined step against 2.65 with each instance's own autotuned
-        # choices; configuration 2 (2x2 tiles, 2 slices) for the FP64 path, 1.19 against 1.26
-        # ms; the residual on LDS tiles.  Timings of this workload vary by a few percent
-        # between runs.
-        cfg = 7 if precision == pfd.REFINED_FP32 else 2
-        shared = [cfg] * 8 + [0, 0] + [0, 1, 1, 0, 0]
+        # per step position.  The choice was measured on the merged launches (uniform
+        # configurations swept, 20 steps each, one run): the four-pass solver with the
+        # 2x2-tile, 4-slice split-K GEMM (configuration 7) on every pass and the per-node
+        # residual with the order as a runtime argument (one kernel for all seven orders),
+        # 2.02 ms per refined step (95 launches) against 2.34 with the LDS residual (one kernel
+        # per order, 191 launches) and 2.65 with each instance's own autotuned choices;
+        # configuration 2 (2x2 tiles, 2 slices) for the FP64 path, 1.19 against 1.26 ms.
+        # Timings of this workload vary by a few percent between runs.
+        if precision == pfd.REFINED_FP32:
+            shared = [7] * 8 + [0, 0] + [0, 3, 1, 0, 0]
+        else:
+            shared = [2] * 8 + [0, 0] + [0, 1, 1, 0, 0]
         for c in ctxs:
             c.set_tuning(shared)
         batch = pfd.Batch(ctxs, nlanes=4)

@@ -291,7 +291,11 @@ pfd_status pfd_set_tuning(pfd_ctx* ctx, const int* vals, int n);
  * 2 = as 1 inside the refinement of the FP32-refined path, with the first
  * fast-diagonalisation pass (the rows times Sx) done in the same launch on
  * the matrix cores (not with solver variant 1, the electrode gap-node solve
- * or a singular operator's projection, where 1 is used).  pfd_create times
+ * or a singular operator's projection, where 1 is used), 3 = as 0 with the
+ * element order a runtime argument rather than a compile-time one: one
+ * kernel for every order, so that a multi-instance batch of instances of
+ * different orders (pfd_batch_set_mode) merges their residuals into one
+ * launch (not chosen by the autotuner).  pfd_create times
  * 0 and 1 and keeps the faster, then (refined contexts) the fused launch
  * against the separate residual and first pass.  The same sums in the same
  * order (results agree to rounding).  us[3] of pfd_get_residual_variant: us

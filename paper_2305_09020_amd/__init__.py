@@ -349,7 +349,8 @@ class Context:
 
     def set_residual_variant(self, variant):
         """0: per-node residual kernel, 1: LDS-tiled residual kernel, 2: LDS-tiled residual
-        fused with the first fast-diagonalisation pass (refined path)."""
+        fused with the first fast-diagonalisation pass (refined path), 3: per-node kernel with
+        the element order a runtime argument (one kernel for every order)."""
         _check(_lib.pfd_set_residual_variant(self.h, int(variant)), self.h)
 
     def residual_variant(self):

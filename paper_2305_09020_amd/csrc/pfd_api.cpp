@@ -954,7 +954,7 @@ extern "C" pfd_status pfd_set_tuning(pfd_ctx* c, const int* vals, int n) {
         return PFD_EINVAL;
     }
   const int* v = vals + 2 * PFD_GS_N;
-  if (v[0] < 0 || v[0] > 2 || v[1] < 0 || v[1] > 2 || v[2] < 1 || v[2] > 2 || v[3] < 0 || v[3] > 6 || v[4] < 0 ||
+  if (v[0] < 0 || v[0] > 2 || v[1] < 0 || v[1] > 3 || v[2] < 1 || v[2] > 2 || v[3] < 0 || v[3] > 6 || v[4] < 0 ||
       v[4] > 1)
     return PFD_EINVAL;
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -970,7 +970,7 @@ extern "C" pfd_status pfd_set_tuning(pfd_ctx* c, const int* vals, int n) {
 }
 
 extern "C" pfd_status pfd_set_residual_variant(pfd_ctx* c, int variant) {
-  if (!c || variant < 0 || variant > 2) return PFD_EINVAL;
+  if (!c || variant < 0 || variant > 3) return PFD_EINVAL;
   HIPCHK(hipStreamSynchronize(c->stream));
   drop_graphs(c);
   c->resid_variant = variant;

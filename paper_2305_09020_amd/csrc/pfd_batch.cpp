@@ -236,48 +236,37 @@ static hipError_t build_plan(pfd_batch* b, int eq, MultiPlan& P) {
   return e;
 }
 
-// capture the plan as the step's graph: positions in order; the launches of one position
-// (instances on different kernels, e.g. one per element order) are independent and become
-// parallel branches forked from the capture stream onto the lanes and joined again
+// the plan as the step's graph, built node by node: one kernel node per launch, each depending
+// on every node of the previous position; the launches of one position (instances on different
+// kernels, e.g. one per element order) are independent of each other
 static hipError_t capture_multi(pfd_batch* b, int eq, MultiPlan& P, hipGraphExec_t* ex) {
   hipError_t e = build_plan(b, eq, P);
-  if (e) {
-    if (P.dmem) (void)hipFree(P.dmem);
-    P = MultiPlan();
-    return e;
-  }
-  e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-  if (e) return e;
-  hipError_t es = hipSuccess;
-  const int L = (int)b->lanes.size();
-  auto issue = [&](const MultiLaunch& m, hipStream_t s) {
-    unsigned total = m.total;
-    const void* tab = P.dmem + m.o_tab;
-    const void* ent = P.dmem + m.o_ent;
-    const void* args = P.dmem + m.o_args;
-    void* ka[] = {&total, &tab, &ent, &args};
-    return hipLaunchKernel(m.fn, dim3(total), dim3(m.block[0], m.block[1], m.block[2]), ka, m.shm, s);
-  };
-  for (size_t k = 0; k < P.L.size() && !es;) {
-    size_t end = k + 1;
-    while (end < P.L.size() && P.L[end].pos == P.L[k].pos) ++end;
-    const int m = (int)(end - k), used = std::min(m - 1, L);
-    if (used == 0) {
-      es = issue(P.L[k], b->cap);
-    } else {
-      es = hipEventRecord(b->ev[0], b->cap);
-      for (int l = 0; l < used && !es; ++l) es = hipStreamWaitEvent(b->lanes[l], b->ev[0], 0);
-      for (int q = 0; q < m && !es; ++q) es = issue(P.L[k + q], q == 0 ? b->cap : b->lanes[(q - 1) % used]);
-      for (int l = 0; l < used && !es; ++l) {
-        es = hipEventRecord(b->ev[l + 1], b->lanes[l]);
-        if (!es) es = hipStreamWaitEvent(b->cap, b->ev[l + 1], 0);
-      }
-    }
-    k = end;
-  }
   hipGraph_t g = nullptr;
-  e = hipStreamEndCapture(b->cap, &g);
-  if (!e) e = es;
+  if (!e) e = hipGraphCreate(&g, 0);
+  std::vector<hipGraphNode_t> prev, cur;
+  for (size_t k = 0; k < P.L.size() && !e;) {
+    cur.clear();
+    const size_t pos = P.L[k].pos;
+    for (; k < P.L.size() && P.L[k].pos == pos && !e; ++k) {
+      const MultiLaunch& m = P.L[k];
+      unsigned total = m.total;
+      const void* tab = P.dmem + m.o_tab;
+      const void* ent = P.dmem + m.o_ent;
+      const void* args = P.dmem + m.o_args;
+      void* ka[] = {&total, &tab, &ent, &args};   // copied into the node
+      hipKernelNodeParams kp = {};
+      kp.func = const_cast<void*>(m.fn);
+      kp.gridDim = dim3(total);
+      kp.blockDim = dim3(m.block[0], m.block[1], m.block[2]);
+      kp.sharedMemBytes = (unsigned)m.shm;
+      kp.kernelParams = ka;
+      kp.extra = nullptr;
+      hipGraphNode_t node = nullptr;
+      e = hipGraphAddKernelNode(&node, g, prev.empty() ? nullptr : prev.data(), prev.size(), &kp);
+      if (!e) cur.push_back(node);
+    }
+    prev.swap(cur);
+  }
   if (!e) e = hipGraphInstantiate(ex, g, nullptr, nullptr, 0);
   if (g) (void)hipGraphDestroy(g);
   if (e) {

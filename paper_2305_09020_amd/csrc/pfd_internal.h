@@ -166,7 +166,8 @@ struct pfd_ctx {
   // (chosen by timing both at create)
   int fdm_variant = 1;
   int resid_variant = 1;                   // residual: 0 = per-node global reads, 1 = LDS tiles,
-                                           // 2 = LDS tiles fused with the first FDM pass (refined)
+                                           // 2 = LDS tiles fused with the first FDM pass (refined),
+                                           // 3 = per node with the order a runtime argument
   double resid_us[3] = {0.0, 0.0, 0.0};
   double fdm_us[3] = {0.0, 0.0, 0.0};      // autotune timings (us per correction)
   int mid_tn = 1, mid_best_tn = 1;         // column tiles per work-group of the fused middle passes

@@ -859,8 +859,9 @@ __device__ __forceinline__ void k_residual_run(const VGrid& vg, int Nx, int Ny, 
                            const double* __restrict__ KyB, const double* __restrict__ My,
                            const unsigned char* __restrict__ diry, const double* __restrict__ shift,
                            const double* __restrict__ bb, const double* __restrict__ x, double* __restrict__ r,
-                           int apply_only, const unsigned char* __restrict__ ebot, Chk ck) {
+                           int apply_only, const unsigned char* __restrict__ ebot, Chk ck, int kr) {
   if (ck.gin && *ck.gin) return;
+  const int KK = K > 0 ? K : kr;   // K = 0: the order is the runtime argument kr
   const long Ng = (long)Nx * Ny;
   const long id0 = (long)vg.b.x * blockDim.x + threadIdx.x;
   double r2 = 0.0, ax2 = 0.0;
@@ -875,17 +876,17 @@ __device__ __forceinline__ void k_residual_run(const VGrid& vg, int Nx, int Ny, 
   // zero, and with no branch around them all 4K+2 loads are issued together
   double ax = 0.0, ay = 0.0;
 #pragma unroll
-  for (int d = -K; d <= K; ++d) {
+  for (int d = -KK; d <= KK; ++d) {
     int j = ix + d;
     if (perx) j = (j < 0) ? j + Nx : (j >= Nx ? j - Nx : j);
     else j = (j < 0) ? 0 : (j >= Nx ? Nx - 1 : j);
-    ax += KxB[(long)(d + K) * Nx + ix] * xrow[j];
+    ax += KxB[(long)(d + KK) * Nx + ix] * xrow[j];
   }
 #pragma unroll
-  for (int d = -K; d <= K; ++d) {
+  for (int d = -KK; d <= KK; ++d) {
     int j = iy + d;
     j = (j < 0) ? 0 : (j >= Ny ? Ny - 1 : j);
-    ay += KyB[(long)(d + K) * Ny + iy] * xp[(long)j * Nx + ix];
+    ay += KyB[(long)(d + KK) * Ny + iy] * xp[(long)j * Nx + ix];
   }
   const double xv = xrow[ix];
   const double Av = ax * My[iy] + Mx[ix] * ay + shift[pl] * Mx[ix] * My[iy] * xv;
@@ -1944,8 +1945,14 @@ static long residual(pfd_ctx* c, int fam, const double* b, const double* x, doub
   const int planes = np > 0 ? np : c->planes;   // np: stacked components as extra planes
   const long tot = (long)planes * c->Ng;
   const size_t lds = sizeof(double) * (size_t)res_rows_lds(c->K, c->Nx);
-  const bool tiled = c->Nx <= 256 && lds <= 64 * 1024 && c->resid_variant >= 1;
+  const bool tiled = c->Nx <= 256 && lds <= 64 * 1024 && (c->resid_variant == 1 || c->resid_variant == 2);
   const Chk k = ck ? *ck : no_chk();
+  if (c->resid_variant == 3) {   // per node, the order a runtime argument: one kernel for every order
+    Kern<k_residual<0>>::launch(c, PFD_PROF_RESID, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, planes,
+                                (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, r,
+                                apply_only, c->lift[fam].ebot, k, c->K);
+    return (long)nblk(tot);
+  }
 #define RES_CASE(KK)                                                                                      \
   case KK:                                                                                                \
     if (tiled)                                                                                            \
@@ -1955,7 +1962,7 @@ static long residual(pfd_ctx* c, int fam, const double* b, const double* x, doub
     else                                                                                                  \
       Kern<k_residual<KK>>::launch(c, PFD_PROF_RESID, dim3(nblk(tot)), dim3(WG), 0, c->stream, c->Nx, c->Ny, planes,    \
              (int)dx.periodic, dx.dKb, dx.dM1, dx.ddir, dy.dKb, dy.dM1, dy.ddir, sh, b, x, r, apply_only,     \
-             c->lift[fam].ebot, k);                                                                       \
+             c->lift[fam].ebot, k, KK);                                                                   \
     break;
   switch (c->K) {
     RES_CASE(2) RES_CASE(3) RES_CASE(4) RES_CASE(5) RES_CASE(6) RES_CASE(7) RES_CASE(8) RES_CASE(9)

@@ -495,9 +495,9 @@ def test_every_gemm_tile_configuration_solves(precision):
 
 @pytest.mark.parametrize("periodic", [False, True])
 def test_residual_kernel_variants_identical(periodic):
-    """Both residual kernels (per-node; LDS-tiled rows) give the same refined solves (same
-    sums in the same order; only the compiler's fused multiply-adds may differ) and the
-    autotuner timed both."""
+    """The residual kernels (per-node; LDS-tiled rows; per-node with the order a runtime
+    argument) give the same refined solves (same sums in the same order; only the compiler's
+    fused multiply-adds may differ) and the autotuner timed the first two."""
     torch = _torch()
     m, bc, par = box_case(n=5, K=8, periodic=periodic, top=OPEN if periodic else WALL)
     ctx = gpu_context(m, par, bc, nbatch=3, precision=1)
@@ -509,12 +509,13 @@ def test_residual_kernel_variants_identical(periodic):
         b = torch.tensor(rng.standard_normal(n), device="cuda")
         g = torch.tensor(rng.standard_normal(n), device="cuda")
         out = []
-        for var in (0, 1):
+        for var in (0, 1, 3):
             ctx.set_residual_variant(var)
             x = g.clone()
             ctx.solve(fam, b, x)
             out.append(x.cpu().numpy())
         assert rel_err(out[1], out[0]) < 1e-13, (fam, rel_err(out[1], out[0]))
+        assert rel_err(out[2], out[0]) < 1e-13, (fam, rel_err(out[2], out[0]))
 
 
 @pytest.mark.parametrize("periodic,top", [(False, WALL), (True, OPEN)])
