@@ -165,3 +165,22 @@ def test_multi_instance_launches_do_not_grow_with_instances(precision):
         counts.append(batch.launches())
         batch.close()
     assert counts[0] > 0 and counts[0] == counts[1], counts
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_equilibrium_steps_equal_separate_steps(mode):
+    """Steps of the equilibrium system (Sec. 2.4) in a batch of three uneven 2D instances on the
+    refined path: every field equals the same instance stepped alone, after each of 6 steps."""
+    _torch()
+    import paper_2305_09020_amd as pfd
+    batch_ctx = [_instance(*s[:4], 1)[0] for s in SPECS[:3]]
+    solo_ctx = [_instance(*s[:4], 1, tune_from=a)[0] for s, a in zip(SPECS[:3], batch_ctx)]
+    batch = pfd.Batch(batch_ctx, mode=mode)
+    for n in range(6):
+        batch.step(1, equilibrium=True)
+        for c in solo_ctx:
+            c.step(1, True)
+        for i, (a, b) in enumerate(zip(batch_ctx, solo_ctx)):
+            for k in ("phi", "psi", "V"):
+                assert np.array_equal(a.get_field(k), b.get_field(k)), (n, i, k)
+    batch.close()
