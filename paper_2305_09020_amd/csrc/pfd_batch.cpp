@@ -291,7 +291,8 @@ extern "C" int pfd_batch_launches(const pfd_batch* b) {
   if (!b) return -1;
   int m = -1;
   for (auto& row : b->plan)
-    for (auto& p : row) m = std::max(m, (int)p.L.size());
+    for (auto& p : row)
+      if (!p.L.empty()) m = std::max(m, (int)p.L.size());
   return m;
 }
 

@@ -184,3 +184,64 @@ def test_batch_equilibrium_steps_equal_separate_steps(mode):
             for k in ("phi", "psi", "V"):
                 assert np.array_equal(a.get_field(k), b.get_field(k)), (n, i, k)
     batch.close()
+
+
+def test_batch_mode_validation():
+    """pfd_batch_set_mode takes only the two forms; the multi-instance launch count is -1 until
+    a multi-instance graph has been captured (refined: from the third step on)."""
+    _torch()
+    import paper_2305_09020_amd as pfd
+    ctx = _instance(*SPECS[0][:4], 1)[0]
+    batch = pfd.Batch([ctx], mode=pfd.BATCH_BRANCHES)
+    batch.step(3)
+    assert batch.launches() == -1
+    with pytest.raises(pfd.PfdError):
+        batch.set_mode(2)
+    batch.set_mode(pfd.BATCH_MULTI)
+    batch.step(2)
+    assert batch.launches() > 0
+    batch.close()
+
+
+def _electrode_instance(n, K, volt, precision, tune_from=None):
+    """x-periodic box, open top, one electrode segment [0.25, 0.5] on the bottom wall at volt
+    (the potential solve takes the gap-node correction), a drop sitting on the bottom."""
+    par = Params(**{**c4_param_dict(8.0), "theta_s_deg": 75.0})
+    xb = np.linspace(0.0, 1.0, n + 1)
+    m = Mesh2D(xb, xb, K, periodic_x=True)
+    bc = BCs(side={BOTTOM: WALL, TOP: OPEN}, electrodes=[(0.25, 0.5)])
+    ctx = gpu_context(m, par, bc, precision=precision)
+    if tune_from is not None:
+        _pin(ctx, tune_from)
+    X, Y = m.X.ravel(), m.Y.ravel()
+    phi = drop_field(X, Y, (0.5, 0.0), 0.3, par.eta)
+    vd = np.where(np.isclose(Y, 0.0) & (X >= 0.25 - 1e-12) & (X <= 0.5 + 1e-12), volt, 0.0)
+    shape = (1, m.Ny, m.Nx)
+    ctx.set_field("phi", phi.reshape(shape))
+    ctx.set_sources({"Vd": vd.reshape(shape)})
+    ctx.init_potential(tol=1e-12, max_iter=5000)
+    return ctx
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_with_electrode_instances(mode):
+    """Two electrode instances (gap-node potential solve; n = 4 and 8 elements per side) and
+    a closed box in one batch, refined path: every field equals the same instance stepped
+    alone after each of 6 steps."""
+    _torch()
+    import paper_2305_09020_amd as pfd
+    batch_ctx = [_electrode_instance(4, 6, 1.0, 1), _electrode_instance(8, 5, 0.5, 1),
+                 _instance(*SPECS[1][:4], 1)[0]]
+    solo_ctx = [_electrode_instance(4, 6, 1.0, 1, tune_from=batch_ctx[0]),
+                _electrode_instance(8, 5, 0.5, 1, tune_from=batch_ctx[1]),
+                _instance(*SPECS[1][:4], 1, tune_from=batch_ctx[2])[0]]
+    batch = pfd.Batch(batch_ctx, mode=mode)
+    for n in range(6):
+        batch.step(1)
+        for c in solo_ctx:
+            c.step(1)
+        for i, (a, b) in enumerate(zip(batch_ctx, solo_ctx)):
+            for k in FIELDS:
+                fa, fb = a.get_field(k), b.get_field(k)
+                assert np.array_equal(fa, fb), (n, i, k, np.max(np.abs(fa - fb)))
+    batch.close()
