@@ -245,3 +245,25 @@ def test_batch_with_electrode_instances(mode):
                 fa, fb = a.get_field(k), b.get_field(k)
                 assert np.array_equal(fa, fb), (n, i, k, np.max(np.abs(fa - fb)))
     batch.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_of_3d_instances_with_different_plane_counts(mode):
+    """Two 3D instances of different Fourier plane counts (8 and 16: different z-transform
+    kernels) and one 2D instance in one batch, refined path: every field equals the same
+    instance stepped alone after each of 6 steps."""
+    _torch()
+    import paper_2305_09020_amd as pfd
+    specs = [(2, 5, 1.5, 10.0, 8), (2, 4, 0.5, 3.0, 16), (3, 4, 0.5, 20.0, 0)]
+    batch_ctx = [_instance(*s[:4], 1, nz=s[4])[0] for s in specs]
+    solo_ctx = [_instance(*s[:4], 1, nz=s[4], tune_from=a)[0] for s, a in zip(specs, batch_ctx)]
+    batch = pfd.Batch(batch_ctx, mode=mode)
+    for n in range(6):
+        batch.step(1)
+        for c in solo_ctx:
+            c.step(1)
+        for i, (a, b) in enumerate(zip(batch_ctx, solo_ctx)):
+            for k in FIELDS:
+                fa, fb = a.get_field(k), b.get_field(k)
+                assert np.array_equal(fa, fb), (n, i, k, np.max(np.abs(fa - fb)))
+    batch.close()
