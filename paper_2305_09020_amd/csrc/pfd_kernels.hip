@@ -275,7 +275,7 @@ __device__ __forceinline__ void rhs_out(const Geo& g, const Par& P, const Lift& 
 // =================================================================== stage V (eq. 54)
 // L0 = -int (eps(phi*) - eps0) grad V* . grad e   (element-local)
 __device__ __forceinline__ void k_V_elem_run(const VGrid& vg, Geo g, Par P, const double* phn, const double* pho,
-                                               const double* Vn, const double* Vo, double* L0) {
+                                             const double* Vn, const double* Vo, double* L0) {
   ELEM_PROLOGUE
   ELEM_ARRAY(sV)
   ELEM_ARRAY(sgx)
@@ -304,8 +304,9 @@ __device__ __forceinline__ void k_V_elem_run(const VGrid& vg, Geo g, Par P, cons
 struct k_V_elem : KDef<&k_V_elem_run, WG, 0> {};
 
 // b = (DSS(L0) - M f_V)/eps0, Dirichlet values from VD
-__device__ __forceinline__ void k_V_rhs_run(const VGrid& vg, Geo g, Par P, Lift L, const double* L0, const double* Mdiag, const double* fV,
-                        const double* Vd, const double* Fn, const double* Fo, double* bb, double* r, double* x0) {
+__device__ __forceinline__ void k_V_rhs_run(const VGrid& vg, Geo g, Par P, Lift L, const double* L0,
+                                            const double* Mdiag, const double* fV, const double* Vd, const double* Fn,
+                                            const double* Fo, double* bb, double* r, double* x0) {
   NODAL_PROLOGUE
   const double v = dss(g, L0, pl, ix, iy) - Mdiag[node] * fV[id];
   rhs_out(g, P, L, Vd, Fn, Fo, id, (long)pl * g.Ng, ix, iy, v / P.eps0, bb, r, x0);
@@ -329,8 +330,9 @@ __device__ __forceinline__ void k_E_elem_run(const VGrid& vg, Geo g, const doubl
 }
 struct k_E_elem : KDef<&k_E_elem_run, WG, 0> {};
 
-__device__ __forceinline__ void k_E_nodal_run(const VGrid& vg, Geo g, const double* L0, const double* L1, const double* Mdiag,
-                          const double* Ez, double* Ex, double* Ey, double* E2) {
+__device__ __forceinline__ void k_E_nodal_run(const VGrid& vg, Geo g, const double* L0, const double* L1,
+                                              const double* Mdiag, const double* Ez, double* Ex, double* Ey,
+                                              double* E2) {
   NODAL_PROLOGUE
   double m = Mdiag[node];
   double ex = dss(g, L0, pl, ix, iy) / m, ey = dss(g, L1, pl, ix, iy) / m;
@@ -344,10 +346,10 @@ struct k_E_nodal : KDef<&k_E_nodal_run, 0, 0> {};
 // =================================================================== stage psi (eq. 56)
 // L0 = -int Q1 w + int grad Q2 . grad w ;  Q2 also written (nodal, same at shared nodes)
 __device__ __forceinline__ void k_psi_elem_run(const VGrid& vg, Geo g, Par P, const double* phn, const double* pho,
-                                                 const double* uxn, const double* uxo, const double* uyn,
-                                                 const double* uyo, const double* E2, const double* gsrc,
-                                                 const double* uzn, const double* uzo, const double* dzphs,
-                                                 double* L0) {
+                                               const double* uxn, const double* uxo, const double* uyn,
+                                               const double* uyo, const double* E2, const double* gsrc,
+                                               const double* uzn, const double* uzo, const double* dzphs,
+                                               double* L0) {
   ELEM_PROLOGUE
   ELEM_ARRAY(sph)
   ELEM_ARRAY(sQ2)
@@ -394,10 +396,11 @@ struct k_psi_elem : KDef<&k_psi_elem_run, WG, 0> {};
 
 // b_psi = DSS(L0) + Bo (g1 + c_psi g2) + Bs (g1 + c_psi U);  U = -g3 - Theta'(phi*)/lambda
 // also stores U (reused by the phi stage) and x0 = psi*
-__device__ __forceinline__ void k_psi_rhs_run(const VGrid& vg, Geo g, Par P, const double* L0, const double* bmo, const double* bmw,
-                          const double* g1, const double* g2, const double* g3, const double* phn,
-                          const double* pho, const double* E2, const double* Fn, const double* Fo,
-                          double* bb, double* U, double* Q2, double* r, double* x0, const double* bprev) {
+__device__ __forceinline__ void k_psi_rhs_run(const VGrid& vg, Geo g, Par P, const double* L0, const double* bmo,
+                                              const double* bmw, const double* g1, const double* g2, const double* g3,
+                                              const double* phn, const double* pho, const double* E2,
+                                              const double* Fn, const double* Fo, double* bb, double* U, double* Q2,
+                                              double* r, double* x0, const double* bprev) {
   NODAL_PROLOGUE
   double phs = P.cs_n * phn[id] + P.cs_o * pho[id];
   double u = -g3[id] - thp_of(P, phs);
@@ -418,9 +421,10 @@ __device__ __forceinline__ void k_psi_rhs_run(const VGrid& vg, Geo g, Par P, con
 struct k_psi_rhs : KDef<&k_psi_rhs_run, 0, 0> {};
 
 // =================================================================== stage phi (eq. 57)
-__device__ __forceinline__ void k_phi_rhs_run(const VGrid& vg, Geo g, Par P, const double* Mdiag, const double* psi, const double* bmo,
-                          const double* bmw, const double* g2, const double* U, const double* Fn,
-                          const double* Fo, double* bb, double* r, double* x0, const double* bprev) {
+__device__ __forceinline__ void k_phi_rhs_run(const VGrid& vg, Geo g, Par P, const double* Mdiag, const double* psi,
+                                              const double* bmo, const double* bmw, const double* g2, const double* U,
+                                              const double* Fn, const double* Fo, double* bb, double* r, double* x0,
+                                              const double* bprev) {
   NODAL_PROLOGUE
   const double v = -Mdiag[node] * psi[id] + bmo[node] * g2[id] + bmw[node] * U[id];
   const double bo = bprev ? bb[id] : 0.0;   // recycled first residual (as rhs_out)
@@ -450,11 +454,10 @@ struct Mom3 {
 //          z velocity right side to LAz (G, omega*, K are full 3-vectors there).
 template <bool Z3>
 __device__ __forceinline__ void k_mom_elem_run(const VGrid& vg, Geo g, Par P, const double* phi, const double* psi,
-                                                 const double* E2, const double* Q2,
-                                                 const double* uxn, const double* uxo, const double* uyn,
-                                                 const double* uyo, const double* Pn, const double* Po,
-                                                 const double* fx, const double* fy, double* L0,
-                                                 double* L1, double* L2, Mom3 z) {
+                                               const double* E2, const double* Q2, const double* uxn,
+                                               const double* uxo, const double* uyn, const double* uyo,
+                                               const double* Pn, const double* Po, const double* fx, const double* fy,
+                                               double* L0, double* L1, double* L2, Mom3 z) {
   ELEM_PROLOGUE
   ELEM_ARRAY(sph)
   ELEM_ARRAY(sPhi)
@@ -661,8 +664,9 @@ template <bool Z3>
 struct k_mom_elem : KDef<&k_mom_elem_run<Z3>, WG, 0> {};
 
 // b_P = DSS(L0) - rho0 gamma0/dt sum_walls int (n.w) q ;  x0 = P* (f2 on open sides)
-__device__ __forceinline__ void k_P_rhs_run(const VGrid& vg, Geo g, Par P, Lift L, const double* L0, const double* wx, const double* wy,
-                        const double* f2, const double* Fn, const double* Fo, double* bb, double* r, double* x0) {
+__device__ __forceinline__ void k_P_rhs_run(const VGrid& vg, Geo g, Par P, Lift L, const double* L0, const double* wx,
+                                            const double* wy, const double* f2, const double* Fn, const double* Fo,
+                                            double* bb, double* r, double* x0) {
   NODAL_PROLOGUE
   double v = dss(g, L0, pl, ix, iy);
   const double c = P.rho0 * P.gamma0 / P.dt;
@@ -676,7 +680,7 @@ struct k_P_rhs : KDef<&k_P_rhs_run, 0, 0> {};
 // u right side: add -(1/(nu_m rho0)) int grad P^{n+1} v to L1, L2 (and to LAz in 3D, with the
 // z-derivative dzP taken from the spectral pressure)
 __device__ __forceinline__ void k_gradP_elem_run(const VGrid& vg, Geo g, Par P, const double* Pnew, const double* dzP,
-                                                   double* L1, double* L2, double* LAz) {
+                                                 double* L1, double* L2, double* LAz) {
   ELEM_PROLOGUE
   ELEM_ARRAY(sP)
   // the element-local sums this kernel adds to (and the 3D z-derivative) are requested before
@@ -705,10 +709,11 @@ __device__ __forceinline__ void k_gradP_elem_run(const VGrid& vg, Geo g, Par P, 
 struct k_gradP_elem : KDef<&k_gradP_elem_run, WG, 0> {};
 
 // b_u = DSS(L) + Bo f1 ; x0 = u* with w on walls (two components)
-__device__ __forceinline__ void k_u_rhs_run(const VGrid& vg, Geo g, Par P, Lift L, const double* L1, const double* L2, const double* bmo,
-                        const double* f1x, const double* f1y, const double* wx, const double* wy,
-                        const double* Fxn, const double* Fxo, const double* Fyn, const double* Fyo,
-                        double* bx, double* by, double* rx, double* ry, double* x0x, double* x0y) {
+__device__ __forceinline__ void k_u_rhs_run(const VGrid& vg, Geo g, Par P, Lift L, const double* L1, const double* L2,
+                                            const double* bmo, const double* f1x, const double* f1y, const double* wx,
+                                            const double* wy, const double* Fxn, const double* Fxo, const double* Fyn,
+                                            const double* Fyo, double* bx, double* by, double* rx, double* ry,
+                                            double* x0x, double* x0y) {
   NODAL_PROLOGUE
   const long pofs = (long)pl * g.Ng;
   Lift Ly = L;   // the y component's history follows the x component's (contiguous blocks)
@@ -726,7 +731,8 @@ struct k_fill : KDef<&k_fill_run, 0, 0> {};
 
 // non-finite guard on a field: sets status[0]
 // sticky non-finite flag over f (and f2 when given), one launch
-__device__ __forceinline__ void k_check_finite_run(const VGrid& vg, long N, const double* f, const double* f2, int* status) {
+__device__ __forceinline__ void k_check_finite_run(const VGrid& vg, long N, const double* f, const double* f2,
+                                                   int* status) {
   long i = (long)vg.b.x * blockDim.x + threadIdx.x;
   bool bad = false;
   for (; i < N; i += (long)vg.g.x * blockDim.x) {
@@ -799,9 +805,9 @@ __device__ void chk_store(const VGrid& vg, const Chk& ck, double r2, double ax2)
 // stat (family record): corrections, eta, max corrections, failed solves; status[1] gets bit
 // fam when the test after the last allowed correction fails.
 __device__ __forceinline__ void k_chk_decide_run(const VGrid& vg, const double* __restrict__ part, long nblk,
-                                                    const int* __restrict__ gin, int* __restrict__ gate,
-                                                    double* __restrict__ stat, int* __restrict__ status,
-                                                    double tol, int it, int last, int fam) {
+                                                 const int* __restrict__ gin, int* __restrict__ gate,
+                                                 double* __restrict__ stat, int* __restrict__ status, double tol,
+                                                 int it, int last, int fam) {
   if (gin && *gin) return;
   __shared__ double red[32];
   double R = 0.0, X = 0.0;
@@ -854,12 +860,13 @@ __device__ __forceinline__ void stage_lds(int n, Value value, Store store) {
 // Kx[ix][ix+d] (periodic wrap in x; zero outside the band), so consecutive threads read
 // consecutive coefficients.  apply_only = 1 computes y = A x on every node.
 template <int K>
-__device__ __forceinline__ void k_residual_run(const VGrid& vg, int Nx, int Ny, int planes, int perx, const double* __restrict__ KxB,
-                           const double* __restrict__ Mx, const unsigned char* __restrict__ dirx,
-                           const double* __restrict__ KyB, const double* __restrict__ My,
-                           const unsigned char* __restrict__ diry, const double* __restrict__ shift,
-                           const double* __restrict__ bb, const double* __restrict__ x, double* __restrict__ r,
-                           int apply_only, const unsigned char* __restrict__ ebot, Chk ck, int kr) {
+__device__ __forceinline__ void k_residual_run(const VGrid& vg, int Nx, int Ny, int planes, int perx,
+                                               const double* __restrict__ KxB, const double* __restrict__ Mx,
+                                               const unsigned char* __restrict__ dirx, const double* __restrict__ KyB,
+                                               const double* __restrict__ My, const unsigned char* __restrict__ diry,
+                                               const double* __restrict__ shift, const double* __restrict__ bb,
+                                               const double* __restrict__ x, double* __restrict__ r, int apply_only,
+                                               const unsigned char* __restrict__ ebot, Chk ck, int kr) {
   if (ck.gin && *ck.gin) return;
   const int KK = K > 0 ? K : kr;   // K = 0: the order is the runtime argument kr
   const long Ng = (long)Nx * Ny;
@@ -1006,15 +1013,14 @@ __device__ __forceinline__ void res_rows(const VGrid& vg, int Nx, int Ny, int pe
 }
 
 template <int K>
-__device__ __forceinline__ void k_residual_lds_run(const VGrid& vg, int Nx, int Ny, int perx, const double* __restrict__ KxB,
-                                                      const double* __restrict__ Mx,
-                                                      const unsigned char* __restrict__ dirx,
-                                                      const double* __restrict__ KyB, const double* __restrict__ My,
-                                                      const unsigned char* __restrict__ diry,
-                                                      const double* __restrict__ shift, const double* __restrict__ bb,
-                                                      const double* __restrict__ x, double* __restrict__ r,
-                                                      int apply_only, const unsigned char* __restrict__ ebot,
-                                                      Chk ck) {
+__device__ __forceinline__ void k_residual_lds_run(const VGrid& vg, int Nx, int Ny, int perx,
+                                                   const double* __restrict__ KxB, const double* __restrict__ Mx,
+                                                   const unsigned char* __restrict__ dirx,
+                                                   const double* __restrict__ KyB, const double* __restrict__ My,
+                                                   const unsigned char* __restrict__ diry,
+                                                   const double* __restrict__ shift, const double* __restrict__ bb,
+                                                   const double* __restrict__ x, double* __restrict__ r,
+                                                   int apply_only, const unsigned char* __restrict__ ebot, Chk ck) {
   if (ck.gin && *ck.gin) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* xs = reinterpret_cast<double*>(smem_raw);
@@ -1069,12 +1075,12 @@ struct Mfma<float> {
 };
 
 template <typename T, typename TA, typename TB, int EPI>
-__device__ __forceinline__ void k_gemm_run(const VGrid& vg, const TA* __restrict__ A, long sA, const TB* __restrict__ B, long sB,
-                                              int M, int N, int K, T* __restrict__ C, long sC,
-                                              const double* __restrict__ lr, const double* __restrict__ lc,
-                                              const double* __restrict__ shift, double* __restrict__ X,
-                                              const TB* __restrict__ B2, double cb1, double cb2,
-    const int* __restrict__ gate) {
+__device__ __forceinline__ void k_gemm_run(const VGrid& vg, const TA* __restrict__ A, long sA,
+                                           const TB* __restrict__ B, long sB, int M, int N, int K, T* __restrict__ C,
+                                           long sC, const double* __restrict__ lr, const double* __restrict__ lc,
+                                           const double* __restrict__ shift, double* __restrict__ X,
+                                           const TB* __restrict__ B2, double cb1, double cb2,
+                                           const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   // B2 != nullptr: the right operand is cb1 B + cb2 B2 (e.g. the BDF extrapolation of a field)
   // four waves split K: wave w takes the 16-wide slices w, w+4, w+8, ... of the contraction,
@@ -1155,12 +1161,12 @@ struct k_gemm : KDef<&k_gemm_run<T, TA, TB, EPI>, 256, 0> {};
 // the 16-wide contraction slices w, w+SK, ... and their partial blocks are summed through LDS
 // in a fixed order.  The next slice's fragments are loaded while the current one is multiplied.
 template <typename T, typename TA, typename TB, int EPI, int TM, int TN, int SK>
-__device__ __forceinline__ void k_gemmt_run(const VGrid& vg, const TA* __restrict__ A, long sA, const TB* __restrict__ B,
-                                                   long sB, int M, int N, int K, T* __restrict__ C, long sC,
-                                                   const double* __restrict__ lr, const double* __restrict__ lc,
-                                                   const double* __restrict__ shift, double* __restrict__ X,
-                                                   const TB* __restrict__ B2, double cb1, double cb2,
-    const int* __restrict__ gate) {
+__device__ __forceinline__ void k_gemmt_run(const VGrid& vg, const TA* __restrict__ A, long sA,
+                                            const TB* __restrict__ B, long sB, int M, int N, int K, T* __restrict__ C,
+                                            long sC, const double* __restrict__ lr, const double* __restrict__ lc,
+                                            const double* __restrict__ shift, double* __restrict__ X,
+                                            const TB* __restrict__ B2, double cb1, double cb2,
+                                            const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef typename Mfma<T>::V V;
   constexpr int NR = SK > 1 ? SK - 1 : 1;
@@ -1305,9 +1311,9 @@ struct k_gemmt : KDef<&k_gemmt_run<T, TA, TB, EPI, TM, TN, SK>, 64 * SK, 0> {};
 #define GEMM_CHUNK 4
 
 template <typename T, typename TA, int EPI, int W, int SK>
-__device__ __forceinline__ void k_gemm_sr_run(const VGrid& vg, const TA* __restrict__ A, const T* __restrict__ S, int Mtot,
-                                                 int N, int K, T* __restrict__ C, double* __restrict__ X,
-    const int* __restrict__ gate) {
+__device__ __forceinline__ void k_gemm_sr_run(const VGrid& vg, const TA* __restrict__ A, const T* __restrict__ S,
+                                              int Mtot, int N, int K, T* __restrict__ C, double* __restrict__ X,
+                                              const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef typename Mfma<T>::V V;
   constexpr int WS = 4 / SK, NP = 16 * W + 4;
@@ -1421,12 +1427,11 @@ template <typename T, typename TA, int EPI, int W, int SK>
 struct k_gemm_sr : KDef<&k_gemm_sr_run<T, TA, EPI, W, SK>, 256, 0> {};
 
 template <typename T, typename TB, int EPI, int W, int SK>
-__device__ __forceinline__ void k_gemm_sl_run(const VGrid& vg, const T* __restrict__ S, const TB* __restrict__ B, long sB, int planes,
-                                                 int M, int N, int K, T* __restrict__ C, long sC,
-                                                 const double* __restrict__ lr, const double* __restrict__ lc,
-                                                 const double* __restrict__ shift, const TB* __restrict__ B2,
-                                                 double cb1, double cb2,
-    const int* __restrict__ gate) {
+__device__ __forceinline__ void k_gemm_sl_run(const VGrid& vg, const T* __restrict__ S, const TB* __restrict__ B,
+                                              long sB, int planes, int M, int N, int K, T* __restrict__ C, long sC,
+                                              const double* __restrict__ lr, const double* __restrict__ lc,
+                                              const double* __restrict__ shift, const TB* __restrict__ B2, double cb1,
+                                              double cb2, const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef typename Mfma<T>::V V;
   constexpr int WS = 4 / SK, MP = 16 * W + 4;
@@ -1663,11 +1668,11 @@ __device__ __forceinline__ void fdm_map(const VGrid& vg, int nstrip, int planes,
 }
 
 template <typename T>
-__device__ __forceinline__ void k_fdm1_run(const VGrid& vg, int planes, int Ny, int Nx, long Ng, const double* __restrict__ r,
-                                              const T* __restrict__ SxT, const T* __restrict__ SyT,
-                                              const double* __restrict__ ly, const double* __restrict__ lx,
-                                              const double* __restrict__ shift, T* __restrict__ t,
-    const int* __restrict__ gate) {
+__device__ __forceinline__ void k_fdm1_run(const VGrid& vg, int planes, int Ny, int Nx, long Ng,
+                                           const double* __restrict__ r, const T* __restrict__ SxT,
+                                           const T* __restrict__ SyT, const double* __restrict__ ly,
+                                           const double* __restrict__ lx, const double* __restrict__ shift,
+                                           T* __restrict__ t, const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   __shared__ T u[PFD_NMAX * FDM_LDU];
   typedef typename Mfma<T>::V V;
@@ -1757,10 +1762,10 @@ template <typename T>
 struct k_fdm1 : KDef<&k_fdm1_run<T>, 256, 0> {};
 
 template <typename T, bool OVERWRITE>
-__device__ __forceinline__ void k_fdm2_run(const VGrid& vg, int planes, int Ny, int Nx, long Ng, const T* __restrict__ t,
-                                              const T* __restrict__ Sy, const T* __restrict__ Sx,
-                                              double* __restrict__ x,
-    const int* __restrict__ gate) {
+__device__ __forceinline__ void k_fdm2_run(const VGrid& vg, int planes, int Ny, int Nx, long Ng,
+                                           const T* __restrict__ t, const T* __restrict__ Sy,
+                                           const T* __restrict__ Sx, double* __restrict__ x,
+                                           const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   __shared__ T v[16 * (PFD_NMAX + 1)];
   typedef typename Mfma<T>::V V;
@@ -1858,9 +1863,10 @@ struct k_fdm2 : KDef<&k_fdm2_run<T, OVERWRITE>, 256, 0> {};
 //   mode 0 (gauge int_h f = 0):    f -= (sum M f)/(sum M)
 //   mode 1 (range projection):     f -= (sum f)/(sum M) * M
 #define PCH 32
-__device__ __forceinline__ void k_plane_sums_run(const VGrid& vg, long Ng, const double* __restrict__ Mdiag, const double* __restrict__ shift,
-                             const double* __restrict__ f, int weighted, double* __restrict__ part,
-    const int* __restrict__ gate) {
+__device__ __forceinline__ void k_plane_sums_run(const VGrid& vg, long Ng, const double* __restrict__ Mdiag,
+                                                 const double* __restrict__ shift, const double* __restrict__ f,
+                                                 int weighted, double* __restrict__ part,
+                                                 const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   const int blk = vg.b.x, pl = vg.b.y;
   __shared__ double sm[WG];
@@ -1881,9 +1887,10 @@ __device__ __forceinline__ void k_plane_sums_run(const VGrid& vg, long Ng, const
 }
 struct k_plane_sums : KDef<&k_plane_sums_run, 0, 0> {};
 
-__device__ __forceinline__ void k_plane_sub_run(const VGrid& vg, long Ng, int planes, const double* __restrict__ Mdiag, const double* __restrict__ shift,
-                            const double* __restrict__ part, double Mtot, int mode, double* __restrict__ f,
-    const int* __restrict__ gate) {
+__device__ __forceinline__ void k_plane_sub_run(const VGrid& vg, long Ng, int planes,
+                                                const double* __restrict__ Mdiag, const double* __restrict__ shift,
+                                                const double* __restrict__ part, double Mtot, int mode,
+                                                double* __restrict__ f, const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   const long id = (long)vg.b.x * blockDim.x + threadIdx.x;
   if (id >= planes * Ng) return;
@@ -2087,11 +2094,11 @@ __device__ __forceinline__ void fdm_mid_pass(const T* __restrict__ Aw, const T* 
 // row tiles, so nine waves per work-group) three work-groups then fit a CU (27 of 28 wave
 // slots), and the grid of a 128-plane solve runs in one round.
 template <typename T, int RT, int TN>
-__device__ __forceinline__ void k_fdm_mid_run(const VGrid& vg, int planes, int Ny, int Nx, long Ng, const T* __restrict__ SyTw,
-                                                  const T* __restrict__ Syw, const T* __restrict__ T1,
-                                                  const double* __restrict__ ly, const double* __restrict__ lx,
-                                                  const double* __restrict__ shift, T* __restrict__ T3, int ldo,
-    const int* __restrict__ gate) {
+__device__ __forceinline__ void k_fdm_mid_run(const VGrid& vg, int planes, int Ny, int Nx, long Ng,
+                                              const T* __restrict__ SyTw, const T* __restrict__ Syw,
+                                              const T* __restrict__ T1, const double* __restrict__ ly,
+                                              const double* __restrict__ lx, const double* __restrict__ shift,
+                                              T* __restrict__ T3, int ldo, const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef typename Mfma<T>::V V;
   constexpr int CW = 16 * TN, LDC = FDM_MID_LDC(CW);
@@ -2215,13 +2222,13 @@ static bool fdm_mid_launch(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const d
 // entries Sx[16 sl + 4 (lane / 16) + s][16 nt + lane % 16].
 // NTW: column tiles per wave, ceil(KPX / 64) (3 up to Nx = 192, 4 up to 256).
 template <int K, int NTW>
-__device__ __forceinline__ void k_res_p1_run(const VGrid& vg, int Nx, int Ny, int perx, const double* __restrict__ KxB,
-                                                const double* __restrict__ Mx, const unsigned char* __restrict__ dirx,
-                                                const double* __restrict__ KyB, const double* __restrict__ My,
-                                                const unsigned char* __restrict__ diry,
-                                                const double* __restrict__ shift, const double* __restrict__ bb,
-                                                const double* __restrict__ x, const unsigned char* __restrict__ ebot,
-                                                const float* __restrict__ SxB, float* __restrict__ T1, Chk ck) {
+__device__ __forceinline__ void k_res_p1_run(const VGrid& vg, int Nx, int Ny, int perx,
+                                             const double* __restrict__ KxB, const double* __restrict__ Mx,
+                                             const unsigned char* __restrict__ dirx, const double* __restrict__ KyB,
+                                             const double* __restrict__ My, const unsigned char* __restrict__ diry,
+                                             const double* __restrict__ shift, const double* __restrict__ bb,
+                                             const double* __restrict__ x, const unsigned char* __restrict__ ebot,
+                                             const float* __restrict__ SxB, float* __restrict__ T1, Chk ck) {
   if (ck.gin && *ck.gin) return;
   typedef Mfma<float>::V V;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -2317,8 +2324,8 @@ struct k_res_p1 : KDef<&k_res_p1_run<K, NTW>, 256, K <= 8 && NTW == 3 ? 3 : 1> {
 // EPI 3: x = .
 template <int EPI, int TG, int CH>
 __device__ __forceinline__ void k_p4_run(const VGrid& vg, const float* __restrict__ T3, int Mtot, int Nx, int KPX,
-                                            const float* __restrict__ SxFw, double* __restrict__ X,
-    const int* __restrict__ gate) {
+                                         const float* __restrict__ SxFw, double* __restrict__ X,
+                                         const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef Mfma<float>::V V;
   const int lane = threadIdx.x & 63, r16 = lane & 15, g = lane >> 4;
@@ -2419,9 +2426,8 @@ static bool p4_launch(pfd_ctx* c, const Dir1D& dx, int P, const float* t3, doubl
 // EPI 0: C = acc (FP32, row stride ldc); 2: X += acc; 3: X = acc.  Needs K, N <= 32 * 16.
 template <typename TA, int EPI>
 __device__ __forceinline__ void k_srp_run(const VGrid& vg, const TA* __restrict__ A, int lda, int Mtot, int K, int N,
-                                              const float* __restrict__ SB, float* __restrict__ C,
-                                              double* __restrict__ X, int ldc,
-    const int* __restrict__ gate) {
+                                          const float* __restrict__ SB, float* __restrict__ C, double* __restrict__ X,
+                                          int ldc, const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   typedef Mfma<float>::V V;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -2622,11 +2628,11 @@ static void fdm_correct(pfd_ctx* c, const Dir1D& dx, const Dir1D& dy, const doub
 // Electrode gap nodes (potential family): with Y = A_FF^{-1} r_F from the base operator,
 //   t_G = r_G - A_GF Y,  dG = S_G^{-1} t_G  (S_G^{-1} per plane, FP64, from set-up)
 // where A_GF Y at gap node (g, 0) = Mx[g] sum_{iy=1..K} Ky[0][iy] Y(g, iy).
-__device__ __forceinline__ void k_elec_gap_run(const VGrid& vg, int Nx, int Ny, int K, long Ng, int ng, const int* __restrict__ gap,
-                           const double* __restrict__ Mx, const double* __restrict__ Ky0,
-                           const double* __restrict__ r, const double* __restrict__ Y,
-                           const double* __restrict__ Sinv, double* __restrict__ dG,
-    const int* __restrict__ gate) {
+__device__ __forceinline__ void k_elec_gap_run(const VGrid& vg, int Nx, int Ny, int K, long Ng, int ng,
+                                               const int* __restrict__ gap, const double* __restrict__ Mx,
+                                               const double* __restrict__ Ky0, const double* __restrict__ r,
+                                               const double* __restrict__ Y, const double* __restrict__ Sinv,
+                                               double* __restrict__ dG, const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   __shared__ double t[PFD_NMAX];
   const int pl = vg.b.x;
@@ -2650,11 +2656,11 @@ __device__ __forceinline__ void k_elec_gap_run(const VGrid& vg, int Nx, int Ny, 
 struct k_elec_gap : KDef<&k_elec_gap_run, 0, 0> {};
 
 // z = -A_FG dG (nonzero in the gap columns, rows 1..K), and x += Y (+ dG on the gap nodes)
-__device__ __forceinline__ void k_elec_z_run(const VGrid& vg, int Nx, int Ny, int K, int planes, int ng, const int* __restrict__ gapidx,
-                         const double* __restrict__ Mx, const double* __restrict__ Ky0,
-                         const double* __restrict__ dG, const double* __restrict__ Y, double* __restrict__ z,
-                         double* __restrict__ x,
-    const int* __restrict__ gate) {
+__device__ __forceinline__ void k_elec_z_run(const VGrid& vg, int Nx, int Ny, int K, int planes, int ng,
+                                             const int* __restrict__ gapidx, const double* __restrict__ Mx,
+                                             const double* __restrict__ Ky0, const double* __restrict__ dG,
+                                             const double* __restrict__ Y, double* __restrict__ z,
+                                             double* __restrict__ x, const int* __restrict__ gate) {
   if (gate && *gate) return;   // the refinement has converged: nothing left to do
   const long Ng = (long)Nx * Ny;
   const long id = (long)vg.b.x * blockDim.x + threadIdx.x;
@@ -3202,7 +3208,8 @@ hipError_t step_once(pfd_ctx* c, int equilibrium) {
 }
 
 // max |a - b| and max |b| over all planes (host result), for the potential fixed point
-__device__ __forceinline__ void k_maxdiff_run(const VGrid& vg, long N, const double* a, const double* b, double* out) {
+__device__ __forceinline__ void k_maxdiff_run(const VGrid& vg, long N, const double* a, const double* b,
+                                              double* out) {
   __shared__ double s1[WG], s2[WG];
   double m1 = 0.0, m2 = 0.0;
   for (long i = (long)vg.b.x * WG + threadIdx.x; i < N; i += (long)vg.g.x * WG) {
@@ -3246,13 +3253,13 @@ hipError_t max_abs_diff(pfd_ctx* c, const double* a, const double* b, double* ou
 // mass: q0 int phi, q1 int 1/2 rho |u|^2, q2 phi.(K phi) + int (d_z phi)^2, q3 int (phi^2-1)^2,
 // q4 int 1/2 eps |E|^2, q5 wall int phi (phi^2 - 3), q6 max|phi|, q7 non-finite count.
 // K phi is the x-y stiffness applied per plane (no mass shift).
-__device__ __forceinline__ void k_stats_run(const VGrid& vg, long Ng, long per_inst, Par P, const double* __restrict__ Mdiag,
-                        const double* __restrict__ bw, const double* __restrict__ phi,
-                        const double* __restrict__ ux, const double* __restrict__ uy,
-                        const double* __restrict__ uz, const double* __restrict__ Ex,
-                        const double* __restrict__ Ey, const double* __restrict__ Ez,
-                        const double* __restrict__ Kphi, const double* __restrict__ dzphi,
-                        double* __restrict__ part) {
+__device__ __forceinline__ void k_stats_run(const VGrid& vg, long Ng, long per_inst, Par P,
+                                            const double* __restrict__ Mdiag, const double* __restrict__ bw,
+                                            const double* __restrict__ phi, const double* __restrict__ ux,
+                                            const double* __restrict__ uy, const double* __restrict__ uz,
+                                            const double* __restrict__ Ex, const double* __restrict__ Ey,
+                                            const double* __restrict__ Ez, const double* __restrict__ Kphi,
+                                            const double* __restrict__ dzphi, double* __restrict__ part) {
   __shared__ double red[8][WG];
   double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const long base = (long)vg.b.y * per_inst;
@@ -3341,10 +3348,11 @@ hipError_t stats(pfd_ctx* c, double* out) {
 //   b = scale * (A + i beta_k B)   (bmode 0)   or   scale * (A + beta_k^2 B)   (bmode 1)
 //       + mc * M * Cv   (optional spectral term),
 // then the initial guess / first residual as in rhs_out (gD, Fn, Fo spectral)
-__device__ __forceinline__ void k_spec_rhs_run(const VGrid& vg, Geo g, Par P, Lift L, const double* A, const double* B, int bmode, double scale,
-                           const double* Cv, double mc, const double* Mdiag, const double* beta2,
-                           const double* betad, const double* gD, const double* Fn, const double* Fo, double* bb,
-                           double* r, double* x0) {
+__device__ __forceinline__ void k_spec_rhs_run(const VGrid& vg, Geo g, Par P, Lift L, const double* A,
+                                               const double* B, int bmode, double scale, const double* Cv, double mc,
+                                               const double* Mdiag, const double* beta2, const double* betad,
+                                               const double* gD, const double* Fn, const double* Fo, double* bb,
+                                               double* r, double* x0) {
   NODAL_PROLOGUE
   double v = A[id];
   if (B) {
@@ -3365,8 +3373,9 @@ __device__ __forceinline__ void k_spec_rhs_run(const VGrid& vg, Geo g, Par P, Li
 struct k_spec_rhs : KDef<&k_spec_rhs_run, 0, 0> {};
 
 // V: A = DSS(L0) - M f_V,  B = M (eps(phi*) - eps0) d(V*)/dz
-__device__ __forceinline__ void k_V_rhs3_run(const VGrid& vg, Geo g, Par P, const double* L0, const double* Mdiag, const double* fV, const double* phn,
-                         const double* pho, const double* dzV, double* A, double* B) {
+__device__ __forceinline__ void k_V_rhs3_run(const VGrid& vg, Geo g, Par P, const double* L0, const double* Mdiag,
+                                             const double* fV, const double* phn, const double* pho,
+                                             const double* dzV, double* A, double* B) {
   NODAL_PROLOGUE
   A[id] = dss(g, L0, pl, ix, iy) - Mdiag[node] * fV[id];
   const double phs = P.cs_n * phn[id] + P.cs_o * pho[id];
@@ -3375,10 +3384,11 @@ __device__ __forceinline__ void k_V_rhs3_run(const VGrid& vg, Geo g, Par P, cons
 struct k_V_rhs3 : KDef<&k_V_rhs3_run, 0, 0> {};
 
 // psi: A = DSS(L0) + Bo (g1 + c_psi g2) + Bs (g1 + c_psi U),  B = M Q2 ; U, Q2 kept
-__device__ __forceinline__ void k_psi_rhs3_run(const VGrid& vg, Geo g, Par P, const double* L0, const double* Mdiag, const double* bmo,
-                           const double* bmw, const double* g1, const double* g2, const double* g3,
-                           const double* phn, const double* pho, const double* E2, double* A, double* B,
-                           double* U, double* Q2) {
+__device__ __forceinline__ void k_psi_rhs3_run(const VGrid& vg, Geo g, Par P, const double* L0, const double* Mdiag,
+                                               const double* bmo, const double* bmw, const double* g1,
+                                               const double* g2, const double* g3, const double* phn,
+                                               const double* pho, const double* E2, double* A, double* B, double* U,
+                                               double* Q2) {
   NODAL_PROLOGUE
   const double phs = P.cs_n * phn[id] + P.cs_o * pho[id];
   const double u = -g3[id] - thp_of(P, phs);
@@ -3391,24 +3401,24 @@ __device__ __forceinline__ void k_psi_rhs3_run(const VGrid& vg, Geo g, Par P, co
 struct k_psi_rhs3 : KDef<&k_psi_rhs3_run, 0, 0> {};
 
 // phi: boundary part Bo g2 + Bs U (the -M psi part is added in spectral space)
-__device__ __forceinline__ void k_phi_bnd3_run(const VGrid& vg, Geo g, const double* bmo, const double* bmw, const double* g2, const double* U,
-                           double* A) {
+__device__ __forceinline__ void k_phi_bnd3_run(const VGrid& vg, Geo g, const double* bmo, const double* bmw,
+                                               const double* g2, const double* U, double* A) {
   NODAL_PROLOGUE
   A[id] = bmo[node] * g2[id] + bmw[node] * U[id];
 }
 struct k_phi_bnd3 : KDef<&k_phi_bnd3_run, 0, 0> {};
 
 // Phi_hat = psi_hat - c_psi phi_hat - Q2_hat, with Q2_hat = (M Q2)_hat / M (reading R-J)
-__device__ __forceinline__ void k_Phi_hat3_run(const VGrid& vg, Geo g, Par P, const double* psh, const double* phh, const double* BQ,
-                           const double* Mdiag, double* out) {
+__device__ __forceinline__ void k_Phi_hat3_run(const VGrid& vg, Geo g, Par P, const double* psh, const double* phh,
+                                               const double* BQ, const double* Mdiag, double* out) {
   NODAL_PROLOGUE
   out[id] = psh[id] - P.c_psi * phh[id] - BQ[id] / Mdiag[node];
 }
 struct k_Phi_hat3 : KDef<&k_Phi_hat3_run, 0, 0> {};
 
 // P: A = DSS(L0) - rho0 gamma0/dt sum_walls int (n.w) q,  B = DSS(LBP)
-__device__ __forceinline__ void k_P_rhs3_run(const VGrid& vg, Geo g, Par P, const double* L0, const double* LBP, const double* wx, const double* wy,
-                         double* A, double* B) {
+__device__ __forceinline__ void k_P_rhs3_run(const VGrid& vg, Geo g, Par P, const double* L0, const double* LBP,
+                                             const double* wx, const double* wy, double* A, double* B) {
   NODAL_PROLOGUE
   double v = dss(g, L0, pl, ix, iy);
   const double c = P.rho0 * P.gamma0 / P.dt;
@@ -3421,9 +3431,11 @@ __device__ __forceinline__ void k_P_rhs3_run(const VGrid& vg, Geo g, Par P, cons
 struct k_P_rhs3 : KDef<&k_P_rhs3_run, 0, 0> {};
 
 // u: A_x, B_x, A_y, B_y, A_z (open-side f1 added to the A parts)
-__device__ __forceinline__ void k_u_rhs3_run(const VGrid& vg, Geo g, const double* L1, const double* LBx, const double* L2, const double* LBy,
-                         const double* LAz, const double* bmo, const double* f1x, const double* f1y,
-                         const double* f1z, double* Ax, double* Bx, double* Ay, double* By, double* Az) {
+__device__ __forceinline__ void k_u_rhs3_run(const VGrid& vg, Geo g, const double* L1, const double* LBx,
+                                             const double* L2, const double* LBy, const double* LAz,
+                                             const double* bmo, const double* f1x, const double* f1y,
+                                             const double* f1z, double* Ax, double* Bx, double* Ay, double* By,
+                                             double* Az) {
   NODAL_PROLOGUE
   Ax[id] = dss(g, L1, pl, ix, iy) + bmo[node] * f1x[id];
   Bx[id] = dss(g, LBx, pl, ix, iy);
@@ -3532,9 +3544,8 @@ struct ZBatch {
 
 template <int LG, bool TWO>
 __device__ __forceinline__ void k_zfft_run(const VGrid& vg, ZBatch zb, long Ng, double c1, double c2,
-                                                           const double* __restrict__ twr_g,
-                                                           const double* __restrict__ twi_g,
-                                                           const double* __restrict__ betad) {
+                                           const double* __restrict__ twr_g, const double* __restrict__ twi_g,
+                                           const double* __restrict__ betad) {
   using S = ZfftShape<LG>;
   constexpr int NZ = S::NZ, N1 = S::N1, N2 = S::N2, P = S::P, T = S::T, RS = S::RS;
   __shared__ double lr[N1 * RS], li[N1 * RS], wr[NZ], wi[NZ];
