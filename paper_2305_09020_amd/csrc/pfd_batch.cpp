@@ -6,9 +6,10 @@
 //  * multi-instance launches: every instance's step is recorded (its launches, in order, with
 //    their packed arguments), and the k-th launches of all instances that run the same kernel
 //    with the same work-group shape become one launch of that kernel's multi-instance form,
-//    whose work-groups are the concatenation of the instances' grids.  A step is then about as
-//    many launches as one instance's step (times the number of distinct kernel templates at a
-//    position, e.g. one per element order), whatever the number of instances.
+//    whose work-groups are the concatenation of the instances' grids; the step's graph is built
+//    node by node from these launches.  A step is then about as many launches as one
+//    instance's step (times the number of distinct kernels at a position, e.g. one per element
+//    order for order-specialised kernels), whatever the number of instances.
 // Instances keep their own workspaces, autotuned kernels and state in both forms; the batch
 // only orders and groups their launches.
 #include <hip/hip_runtime.h>
@@ -239,7 +240,7 @@ static hipError_t build_plan(pfd_batch* b, int eq, MultiPlan& P) {
 // the plan as the step's graph, built node by node: one kernel node per launch, each depending
 // on every node of the previous position; the launches of one position (instances on different
 // kernels, e.g. one per element order) are independent of each other
-static hipError_t capture_multi(pfd_batch* b, int eq, MultiPlan& P, hipGraphExec_t* ex) {
+static hipError_t build_multi_graph(pfd_batch* b, int eq, MultiPlan& P, hipGraphExec_t* ex) {
   hipError_t e = build_plan(b, eq, P);
   hipGraph_t g = nullptr;
   if (!e) e = hipGraphCreate(&g, 0);
@@ -337,7 +338,7 @@ extern "C" pfd_status pfd_batch_step(pfd_batch* b, int nsteps, int equilibrium) 
       }
       if (!ex) {
         if (b->mode == PFD_BATCH_MULTI)
-          BCHK(capture_multi(b, eq, plan, &ex));
+          BCHK(build_multi_graph(b, eq, plan, &ex));
         else
           BCHK(capture(b, eq, &ex));
         gen.resize(b->ctx.size());
