@@ -46,6 +46,7 @@ from synth import (C1, C2, C3, C4, C5, X6, c1_param_dict, c2_param_dict, c3_para
 
 VTOP = (0.0, 0.5, 1.0, 2.0)
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"gemm32": 157.3, "gemm64": 78.6}   # MI355X dense FP32 / FP64 matrix peaks
 FAMILIES = ("V", "psi", "phi", "P", "u")
 
 
@@ -341,6 +342,50 @@ def roofline(run, t_step, workload, path, classes, probe_gbs):
         out["launches_per_step"] = run.batch.launches()
         out["classes"] = "rocprofv3 kernel split: profiles/kernel_stats_%s.txt" % workload
     return out
+
+
+def fdm_mfma(run, classes, refine, gemm_probe):
+    """Matrix-core rate of the fast-diagonalisation passes, a kernel figure beside the step's
+    HBM roofline: the dense flops of the corrections one step executes, 4 Ny Nx (Nx + Ny) per
+    plane and correction (two passes along each axis), over the time per step of the GEMM
+    classes (instrumented steps).  Corrections per family come from the refinement record of
+    the last step (one per plane on the FP64 path and on the FP64 rung); where the residual
+    kernel carries the first pass (residual variant 2) that pass's flops of every correction
+    after a residual are left out, as its time is in the residual class.  The classes also hold
+    the z transform's DFT GEMM of a plane count that is not a power of two (its flops are not
+    counted).  None for batches."""
+    if not classes or run.batch is not None:
+        return None
+    c = run.ctx
+    Nx, Ny, planes = c.Nx, c.Ny, c.planes
+    per = 4.0 * Ny * Nx * (Nx + Ny)
+    p1 = 2.0 * Ny * Nx * Nx
+    fams = ("V", "psi", "phi") if run.equilibrium else FAMILIES
+    comps = {"u": 3 if c.planes_are_z else 2}
+    fused = refine is not None and c.residual_variant()[0] == 2
+    flops = {"gemm32": 0.0, "gemm64": 0.0}
+    for f in fams:
+        k = comps.get(f, 1)
+        if refine is None:
+            flops["gemm64"] += k * planes * per
+            continue
+        r = refine[f]
+        n64 = r["fp64_planes"]
+        corr = r["last_corrections"]
+        flops["gemm64"] += k * n64 * per
+        flops["gemm32"] += k * (planes - n64) * (corr * per - (max(corr - 1, 0) * p1 if fused else 0.0))
+    out = {}
+    for cls, fl in flops.items():
+        v = classes.get(cls)
+        if not fl or not v:
+            continue
+        us = v["avg_launch_us"] * v["launches_per_step"]
+        tf = fl / (us * 1e-6) / 1e12
+        probe = gemm_probe.get("fp32" if cls == "gemm32" else "fp64") if gemm_probe else None
+        out[cls] = {"flops_per_step": fl, "us_per_step": round(us, 2), "achieved_TFLOPs": round(tf, 3),
+                    "peak_TFLOPs": MFMA_PEAK_TFLOPS[cls], "frac": tf / MFMA_PEAK_TFLOPS[cls],
+                    "frac_of_probe": tf / probe if probe else None}
+    return out or None
 
 
 def refinement(run):
@@ -661,9 +706,11 @@ def main():
         classes = class_profile(run, nprof) if run.batch is None else None
         if run.batch is not None:
             nprof = 0
+        refine = refinement(run) if prec == pfd.REFINED_FP32 else None
+        rl = roofline(run, t / a.steps, a.workload, name, classes, probe)
+        rl["fdm_mfma"] = fdm_mfma(run, classes, refine, gemm_probe)
         res[name] = dict(t=t, ts=ts, run=run, value=run.dof * a.steps / t,
-                         roofline=roofline(run, t / a.steps, a.workload, name, classes, probe),
-                         refinement=refinement(run) if prec == pfd.REFINED_FP32 else None,
+                         roofline=rl, refinement=refine,
                          nsteps=a.warmup + a.repeats * a.steps + nprof)
         print("# %-7s %.3f ms/step  %.4e DOF-steps/s  (repeats: %s ms/step)"
               % (name, 1e3 * t / a.steps, run.dof * a.steps / t,
