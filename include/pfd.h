@@ -336,18 +336,20 @@ pfd_status pfd_set_graph(pfd_ctx* ctx, int on);
 /* ------------------------------------------------------------------ batches
  * A batch steps independent contexts together: instances of uneven mesh,
  * order, parameters and precision (2D or 3D) that were all created on one
- * stream.  Each step is one hipGraph launch, captured on first use per parity
- * of the time level and step kind, in one of two forms (pfd_batch_set_mode):
+ * stream.  Each step is one hipGraph launch, made on first use per parity of
+ * the time level and step kind, in one of two forms (pfd_batch_set_mode):
  *  PFD_BATCH_MULTI (default): multi-instance launches.  One step of every
  *    instance is recorded; the k-th launches of all instances that run the
  *    same kernel with the same work-group shape become one launch whose
  *    work-groups are the concatenation of the instances' grids (each
  *    instance keeps its own grid, arguments and buffers).  A step is as many
- *    launches as one instance's step times the number of distinct kernel
- *    templates at a position (e.g. element orders), independent of the
+ *    launches as one instance's step times the number of distinct kernels at
+ *    a position (e.g. one per element order for order-specialised kernels;
+ *    residual variant 3 takes the order at run time), independent of the
  *    number of instances; results equal those of the instances stepped alone
  *    bit for bit.  The plan's tables and argument packs (about 4 bytes per
- *    work-group of a step, plus the arguments) are allocated at capture.
+ *    work-group of a step, plus the arguments) are allocated when the
+ *    graph is made.
  *  PFD_BATCH_BRANCHES: every instance's own launches as parallel graph
  *    branches (spread over nlanes capture streams, 1..16, default 4 when
  *    nlanes < 1).
